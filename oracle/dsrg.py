@@ -1,0 +1,182 @@
+"""DSRG-MRPT3 unrelaxed energy, step by step (oracle; FP64, spin-orbital, dense).
+
+Each function follows one passage of the paper; the commutators go through the
+generic engine in ``gno`` (no hand-derived working equations).  Sizes up to the
+"small" workload (120 spin orbitals) run in seconds to a minute.
+
+Readings of the paper used here (each also listed in the design notes):
+* Only the semicanonical energies, the factorised integrals and the reference
+  densities are given, so the inter-block Fock elements f^(1) are zero and the
+  first-order Hamiltonian H^(1) is the normal-ordered two-body operator.
+* Only correlation energies are returned (E0 is not an input); the energy is the
+  unrelaxed one of Eq. E_unrelaxed.
+* The regulariser R_s(D) = (1 - exp(-s D^2)) / D takes its limit 0 at D = 0.
+* Internal (all-active) amplitudes are zero at both orders (Sec. II.A).
+* "1,2" keeps scalar, one- and two-body parts of every commutator (Sec. II.A).
+"""
+from __future__ import annotations
+
+import dataclasses
+from typing import Optional
+
+import numpy as np
+
+from paper_1701_02011_amd.synth import Problem
+
+from . import gno
+from .spaces import Spaces, build_densities, so_energies, so_integrals
+
+
+def regulariser(s: float, D: np.ndarray) -> np.ndarray:
+    """R_s(D) = (1 - exp(-s D^2)) / D  (Eqs. T1_1st, T2_1st), FP64.
+
+    Written as -expm1(-s D^2)/D to keep the relative error at the FP64 level for
+    small s D^2; its limit at D = 0 is 0 (reading of the paper).  s = inf gives 1/D.
+    """
+    D = np.asarray(D, dtype=np.float64)
+    out = np.zeros_like(D)
+    nz = D != 0.0
+    if np.isinf(s):
+        out[nz] = 1.0 / D[nz]
+        return out
+    out[nz] = -np.expm1(-s * D[nz] ** 2) / D[nz]
+    return out
+
+
+def source_factor(s: float, D: np.ndarray) -> np.ndarray:
+    """exp(-s D^2) (Sec. III, the expressions for the non-diagonal H~(1))."""
+    if np.isinf(s):
+        return np.where(np.asarray(D) == 0.0, 1.0, 0.0)
+    return np.exp(-s * np.asarray(D, dtype=np.float64) ** 2)
+
+
+@dataclasses.dataclass
+class Result:
+    e2: float
+    e3: float
+    e3_a: float          # <[H~(1), T(2)]>
+    e3_b: float          # <[H~(2)_{1,2}, T(1)]>
+    sp: Spaces
+    eps: np.ndarray      # spin-orbital energies
+    t1_1: np.ndarray     # first-order singles  [2N][2N]  (t[a, i])
+    t2_1: np.ndarray     # first-order doubles  [2N]^4   (t[a, b, i, j])
+    o1_1: np.ndarray     # [H~(1), A(1)]_{1,2} one-body block  [P][H]
+    o1_2: np.ndarray     # two-body block [P][P][H][H] (C-convention)
+    z1_1: np.ndarray
+    z1_2: np.ndarray
+    t1_2: np.ndarray     # second-order singles
+    t2_2: np.ndarray     # second-order doubles
+    h2_1: np.ndarray     # H~(2)_{1,2} one-body [P][H]
+    h2_2: np.ndarray     # H~(2)_{1,2} two-body [P][P][H][H]
+
+
+def _internal_mask(sp: Spaces):
+    """mask[a, b, i, j] (over G) that keeps excitation amplitudes: a,b in P, i,j in H,
+    not all four active."""
+    n = 2 * sp.N
+    inP = np.zeros(n, bool)
+    inP[sp.P] = True
+    inH = np.zeros(n, bool)
+    inH[sp.H] = True
+    inA = np.zeros(n, bool)
+    inA[sp.A] = True
+    m2 = (inP[:, None, None, None] & inP[None, :, None, None]
+          & inH[None, None, :, None] & inH[None, None, None, :])
+    allA = (inA[:, None, None, None] & inA[None, :, None, None]
+            & inA[None, None, :, None] & inA[None, None, None, :])
+    m1 = inP[:, None] & inH[None, :] & ~(inA[:, None] & inA[None, :])
+    return m1, m2 & ~allA
+
+
+def denominators(eps):
+    """D1[a, i] = e_i - e_a and D2[a, b, i, j] = e_i + e_j - e_a - e_b (Eq. T2_1st)."""
+    D1 = eps[None, :] - eps[:, None]
+    D2 = (eps[None, None, :, None] + eps[None, None, None, :]
+          - eps[:, None, None, None] - eps[None, :, None, None])
+    return D1, D2
+
+
+def amplitudes(sp: Spaces, eps, gamma, s, f_exc, v_exc, m1, m2):
+    """Amplitudes from their driving terms (Eqs. T1_1st, T2_1st; T1_2nd, T2_2nd):
+        t[a,b,i,j] = v[a,b,i,j] R_s(D^ij_ab)
+        t[a,i]     = [f[a,i] + sum_{u,x in A} (e_x - e_u) t[a,x,i,u] gamma[x,u]] R_s(D^i_a)
+    Internal amplitudes are zero."""
+    D1, D2 = denominators(eps)
+    t2 = np.where(m2, v_exc * regulariser(s, D2), 0.0)
+    A = sp.A
+    Dux = eps[None, A] - eps[A, None]                    # [u, x] = e_x - e_u
+    coup = np.zeros_like(D1)
+    # sum_{ux} (e_x - e_u) t[a, x, i, u] gamma[x, u]
+    coup[:, :] = np.einsum("axiu,ux,xu->ai", t2[:, A, :, A], Dux, gamma[A, A], optimize=True)
+    t1 = np.where(m1, (f_exc + coup) * regulariser(s, D1), 0.0)
+    return t1, t2
+
+
+def anti_hermitian(t1, t2):
+    """A = T - T+ as a GNO operator in C-convention (one- and two-body tensors)."""
+    return t1 - t1.T, t2 - t2.transpose(2, 3, 0, 1)
+
+
+def run(prob: Problem, keep_full: bool = False) -> Result:
+    """E^(2) and E^(3) of the unrelaxed DSRG-MRPT3 (Eqs. E(2), E(3), E_unrelaxed)."""
+    sp = Spaces(prob.n_core, prob.n_active, prob.n_virtual)
+    s = prob.s
+    n = 2 * sp.N
+    G, H, P = sp.G, sp.H, sp.P
+    # step a0: densities and cumulants
+    dens = build_densities(sp, prob.gamma1, prob.gamma2, prob.gamma3)
+    eps = so_energies(sp, prob.eps)
+    # step a1: antisymmetrised integrals from the factorised tensor (Eq. int_fact)
+    v = so_integrals(sp, prob.B)
+    m1, m2 = _internal_mask(sp)
+    # step a2: first-order amplitudes (Eqs. T1_1st, T2_1st); f^(1) = 0
+    t1, t2 = amplitudes(sp, eps, dens.gamma, s, np.zeros((n, n)), v, m1, m2)
+    a1_1, a1_2 = anti_hermitian(t1, t2)
+    A1 = gno.to_plain(0.0, a1_1, a1_2)
+    F0 = (0.0, np.diag(eps), None)
+    # Y1 = [H^(0), A^(1)] (exact, one- and two-body); H~(1) = 2 H^(1) + Y1 (Eq. Hbar_1st)
+    _, y1_1p, y1_2p = gno.commutator(F0, A1, dens, want1=(G, G), want2=(G, G, G, G))
+    y1_1 = y1_1p
+    y1_2 = gno.c_from_plain2(y1_2p)
+    del y1_2p
+    ht1_1 = y1_1
+    ht1_2 = 2.0 * v + y1_2
+    Ht1 = gno.to_plain(0.0, ht1_1, ht1_2)
+    T1 = gno.to_plain(0.0, t1, t2)
+    # step a3: E^(2) = <[H~(1), T(1)]>  (Eq. E(2))
+    e2, _, _ = gno.commutator(Ht1, T1, dens, want0=True)
+    # steps a4-a5: O1 = [H~(1), A(1)]_{1,2}, excitation blocks (Eq. Hbar_2nd)
+    _, o1_1, o1_2p = gno.commutator(Ht1, A1, dens, want1=(P, H), want2=(P, P, H, H))
+    o1_2 = gno.c_from_plain2(o1_2p)
+    # step a6: Z1 = [Y1, A(1)]_{1,2}
+    Y1 = gno.to_plain(0.0, y1_1, y1_2)
+    _, z1_1, z1_2p = gno.commutator(Y1, A1, dens, want1=(P, H), want2=(P, P, H, H))
+    z1_2 = gno.c_from_plain2(z1_2p)
+    # second-order amplitudes from the non-diagonal part of 1/2 O1 (Eqs. T1_2nd, T2_2nd)
+    f2 = np.zeros((n, n))
+    f2[P, H] = 0.5 * o1_1
+    v2 = np.zeros((n,) * 4)
+    v2[P, P, H, H] = 0.5 * o1_2
+    u1, u2 = amplitudes(sp, eps, dens.gamma, s, f2, v2, m1, m2)
+    del v2
+    # step a7: H~(2)_{1,2} = [H^(0), A(2)] + 1/2 O1 - 1/6 Z1 (Eq. Hbar_2nd and the definition
+    # of H~(2)); only its excitation block and the adjoint enter <[H~(2), T(1)]>
+    a2_1, a2_2 = anti_hermitian(u1, u2)
+    A2 = gno.to_plain(0.0, a2_1, a2_2)
+    _, w1, w2p = gno.commutator(F0, A2, dens, want1=(P, H), want2=(P, P, H, H))
+    h2_1 = w1 + 0.5 * o1_1 - z1_1 / 6.0
+    h2_2 = gno.c_from_plain2(w2p) + 0.5 * o1_2 - z1_2 / 6.0
+    X1 = np.zeros((n, n))
+    X1[P, H] = h2_1
+    X1[H, P] = h2_1.T
+    X2 = np.zeros((n,) * 4)
+    X2[P, P, H, H] = h2_2
+    X2[H, H, P, P] = h2_2.transpose(2, 3, 0, 1)
+    Ht2 = gno.to_plain(0.0, X1, X2)
+    del X2
+    T2 = gno.to_plain(0.0, u1, u2)
+    # E^(3) = <[H~(1), T(2)]> + <[H~(2)_{1,2}, T(1)]>  (Eq. E(3))
+    e3a, _, _ = gno.commutator(Ht1, T2, dens, want0=True)
+    e3b, _, _ = gno.commutator(Ht2, T1, dens, want0=True)
+    return Result(float(e2), float(e3a + e3b), float(e3a), float(e3b), sp, eps,
+                  t1, t2, o1_1, o1_2, z1_1, z1_2, u1, u2, h2_1, h2_2)

@@ -1,0 +1,299 @@
+"""Seeded synthetic inputs for the DSRG-MRPT3 hot path.
+
+This module only *draws* inputs; it holds none of the method's arithmetic.
+It is shared by the FP64 oracle, the tests and the benchmark, so that both
+sides of every parity check see bit-identical inputs.
+
+What is drawn (all FP64, spatial orbitals ordered [core | active | virtual]):
+
+* ``eps``   -- semicanonical orbital energies, one sorted uniform draw per block
+  (the zeroth-order Hamiltonian is the diagonal of the Fock operator in each
+  block, Sec. II.B, Eq. F0th).
+* ``B``     -- the three-index factorised integrals B^Q_pq, symmetric in pq,
+  i.i.d. N(0, 0.1^2) on the upper triangle, so (pq|rs) = sum_Q B^Q_pq B^Q_rs
+  (Sec. III, Eq. int_fact).
+* ``ci``    -- a random normalised CAS(n,n) vector over all determinants with
+  n_alpha = ceil(n/2), n_beta = floor(n/2) electrons in the n active orbitals
+  (Sec. II.A, Eq. mref).  The reference is core^2 x CAS x virtual^0.
+* ``gamma1``, ``gamma2``, ``gamma3`` -- the active-space 1-, 2- and 3-body
+  reduced density matrices of that vector in the spin-block layout the library
+  takes as input (see include/dsrg.h).  The paper poses the reference only
+  through its densities (Sec. I: any reference whose one-, two- and three-body
+  cumulants are available can be used); building them from a CI vector is part
+  of making the input, not of the method.
+
+Fock-space conventions used for the RDMs: the 2*nA active spin orbitals are
+bits 0..nA-1 (alpha) and nA..2nA-1 (beta); a creation operator on bit k picks up
+the sign (-1)^(number of occupied bits below k).  A determinant with the
+alpha string S_a and beta string S_b is the product of creators in ascending bit
+order acting on the vacuum.
+
+Spin-block layout of the densities (spatial indices u,v,w,x,y,z in [0,nA)):
+
+* gamma1[s][u][v]            = <a+_{u s} a_{v s}>,                 s in (alpha, beta)
+* gamma2[b][u][v][x][y]      = <a+_{u s1} a+_{v s2} a_{y s2} a_{x s1}>, b in (aa, ab, bb)
+* gamma3[b][u][v][w][x][y][z]= <a+_{u s1} a+_{v s2} a+_{w s3} a_{z s3} a_{y s2} a_{x s1}>,
+                               b in (aaa, aab, abb, bbb)
+"""
+from __future__ import annotations
+
+import dataclasses
+import itertools
+import math
+from typing import List, Optional, Sequence
+
+import numpy as np
+
+__all__ = [
+    "Problem",
+    "CONFIGS",
+    "make_problem",
+    "make_config",
+    "make_batch_config",
+    "random_ci",
+    "active_rdms",
+    "fock_rdms",
+    "det_strings",
+]
+
+
+@dataclasses.dataclass
+class Problem:
+    """One DSRG-MRPT3 problem in the layout of the C ABI (all arrays FP64, C order)."""
+
+    n_core: int
+    n_active: int
+    n_virtual: int
+    n_aux: int
+    eps: np.ndarray              # [N]
+    B: np.ndarray                # [M][N][N]
+    gamma1: Optional[np.ndarray]  # [2][nA][nA]
+    gamma2: Optional[np.ndarray]  # [3][nA]*4
+    gamma3: Optional[np.ndarray]  # [4][nA]*6
+    s: float
+    ci: Optional[np.ndarray] = None   # [n_alpha_strings][n_beta_strings]
+    n_alpha: int = 0                  # active alpha electrons
+    n_beta: int = 0                   # active beta electrons
+    name: str = ""
+
+    @property
+    def N(self) -> int:
+        return self.n_core + self.n_active + self.n_virtual
+
+    @property
+    def n_hole(self) -> int:
+        return self.n_core + self.n_active
+
+    @property
+    def n_particle(self) -> int:
+        return self.n_active + self.n_virtual
+
+    def with_s(self, s: float) -> "Problem":
+        return dataclasses.replace(self, s=float(s))
+
+    def scaled(self, kappa: float) -> "Problem":
+        """Same problem with B -> kappa * B (two-electron integrals scale by kappa^2)."""
+        return dataclasses.replace(self, B=self.B * kappa)
+
+
+# ---------------------------------------------------------------------------
+# Fock-space helpers for the active space (input generation only)
+# ---------------------------------------------------------------------------
+
+def det_strings(n_orb: int, n_el: int) -> List[tuple]:
+    """All occupation strings of n_el electrons in n_orb orbitals, lexicographic order."""
+    return list(itertools.combinations(range(n_orb), n_el))
+
+
+def _popcount_below(states: np.ndarray, k: int) -> np.ndarray:
+    mask = np.uint64((1 << k) - 1)
+    x = states & mask
+    # vectorised popcount
+    cnt = np.zeros(states.shape, dtype=np.int64)
+    while np.any(x):
+        cnt += (x & np.uint64(1)).astype(np.int64)
+        x = x >> np.uint64(1)
+    return cnt
+
+
+class _Fock:
+    """Dense Fock-space vectors over n_so spin orbitals (n_so <= 20)."""
+
+    def __init__(self, n_so: int):
+        if n_so > 20:
+            raise ValueError("active Fock space limited to 20 spin orbitals")
+        self.n_so = n_so
+        self.dim = 1 << n_so
+        self.states = np.arange(self.dim, dtype=np.uint64)
+        self._sign = []
+        for k in range(n_so):
+            par = _popcount_below(self.states, k) & 1
+            self._sign.append(np.where(par == 1, -1.0, 1.0))
+
+    def annihilate(self, k: int, vec: np.ndarray) -> np.ndarray:
+        """a_k acting on one or many vectors (last axis = Fock index)."""
+        bit = np.uint64(1 << k)
+        occ = (self.states & bit) != 0
+        src = self.states[occ]
+        dst = (src ^ bit).astype(np.int64)
+        out = np.zeros_like(vec)
+        out[..., dst] = vec[..., src.astype(np.int64)] * self._sign[k][occ]
+        return out
+
+
+def _ci_to_fock(ci: np.ndarray, n_orb: int, n_alpha: int, n_beta: int,
+                fock: _Fock, alpha_offset: int, beta_offset: int) -> np.ndarray:
+    a_str = det_strings(n_orb, n_alpha)
+    b_str = det_strings(n_orb, n_beta)
+    vec = np.zeros(fock.dim)
+    for ia, sa in enumerate(a_str):
+        ma = sum(1 << (alpha_offset + o) for o in sa)
+        for ib, sb in enumerate(b_str):
+            mb = sum(1 << (beta_offset + o) for o in sb)
+            vec[ma | mb] = ci[ia, ib]
+    return vec
+
+
+def fock_rdms(vec: np.ndarray, fock: _Fock, order: int) -> np.ndarray:
+    """Spin-orbital RDM of the given order from a Fock-space vector.
+
+    Returns G with G[p1..pk, q1..qk] = <a+_p1 ... a+_pk a_qk ... a_q1>, computed as the
+    Gram matrix of the k-fold annihilated vectors and expanded by antisymmetry.
+    """
+    n = fock.n_so
+    tuples = list(itertools.combinations(range(n), order))
+    # w_T = a_{t_k} ... a_{t_1} |psi>  for T = (t_1 < ... < t_k)
+    W = np.empty((len(tuples), fock.dim))
+    for idx, T in enumerate(tuples):
+        w = vec
+        for t in T:          # apply a_{t_1} first, then a_{t_2}, ...
+            w = fock.annihilate(t, w)
+        W[idx] = w
+    # <w_P | w_Q> = <psi| a+_{p1} .. a+_{pk} a_{qk} .. a_{q1} |psi>
+    gram = W @ W.T
+    G = np.zeros((n,) * (2 * order))
+    perms = list(itertools.permutations(range(order)))
+    signs = []
+    for pm in perms:
+        inv = sum(1 for i in range(order) for j in range(i + 1, order) if pm[i] > pm[j])
+        signs.append(-1.0 if inv % 2 else 1.0)
+    tup = np.array(tuples, dtype=np.int64)           # [T][k]
+    for pu, su in zip(perms, signs):
+        up = tup[:, list(pu)]
+        for pl, sl in zip(perms, signs):
+            lo = tup[:, list(pl)]
+            idx_up = tuple(up[:, i][:, None] for i in range(order))
+            idx_lo = tuple(lo[:, i][None, :] for i in range(order))
+            G[idx_up + idx_lo] = su * sl * gram
+    return G
+
+
+def random_ci(rng: np.random.Generator, n_orb: int, n_alpha: int, n_beta: int) -> np.ndarray:
+    """i.i.d. N(0,1) coefficients over (alpha string x beta string), L2-normalised."""
+    na = math.comb(n_orb, n_alpha)
+    nb = math.comb(n_orb, n_beta)
+    c = rng.standard_normal(na * nb).reshape(na, nb)
+    return c / np.linalg.norm(c)
+
+
+def active_rdms(ci: np.ndarray, n_orb: int, n_alpha: int, n_beta: int):
+    """gamma1 [2][n]^2, gamma2 [3][n]^4, gamma3 [4][n]^6 of a CAS vector (spin-block layout)."""
+    n = n_orb
+    fock = _Fock(2 * n)
+    vec = _ci_to_fock(ci, n, n_alpha, n_beta, fock, 0, n)
+    g1 = fock_rdms(vec, fock, 1)
+    g2 = fock_rdms(vec, fock, 2)
+    g3 = fock_rdms(vec, fock, 3) if n > 0 else None
+    A, Bb = slice(0, n), slice(n, 2 * n)
+    gamma1 = np.stack([g1[A, A], g1[Bb, Bb]])
+    gamma2 = np.stack([g2[A, A, A, A], g2[A, Bb, A, Bb], g2[Bb, Bb, Bb, Bb]])
+    gamma3 = np.stack([
+        g3[A, A, A, A, A, A],
+        g3[A, A, Bb, A, A, Bb],
+        g3[A, Bb, Bb, A, Bb, Bb],
+        g3[Bb, Bb, Bb, Bb, Bb, Bb],
+    ])
+    return (np.ascontiguousarray(gamma1), np.ascontiguousarray(gamma2),
+            np.ascontiguousarray(gamma3))
+
+
+# ---------------------------------------------------------------------------
+# Problem generation
+# ---------------------------------------------------------------------------
+
+def _draw_B(rng: np.random.Generator, M: int, N: int, sigma: float = 0.1) -> np.ndarray:
+    iu = np.triu_indices(N)
+    vals = rng.standard_normal(M * len(iu[0])) * sigma
+    B = np.zeros((M, N, N))
+    vals = vals.reshape(M, len(iu[0]))
+    B[:, iu[0], iu[1]] = vals
+    B[:, iu[1], iu[0]] = vals
+    return B
+
+
+def make_problem(n_core: int, n_active: int, n_virtual: int, n_aux: int, seed: int,
+                 s: float = 0.5, gap: float = 1.0, name: str = "",
+                 with_gamma3: bool = True) -> Problem:
+    """Draw one problem.
+
+    Draw order (part of the contract so both sides reproduce it): core energies,
+    active energies, virtual energies, B, CI vector.  ``gap`` in (0, 1] scales the
+    inner edges of the energy windows toward zero to mimic a stretched bond:
+    core U(-2, -0.5 gap), active U(-0.3 gap, 0.3 gap), virtual U(0.2 gap, 3).
+    """
+    rng = np.random.default_rng(seed)
+    N = n_core + n_active + n_virtual
+    ec = np.sort(rng.uniform(-2.0, -0.5 * gap, n_core))
+    ea = np.sort(rng.uniform(-0.3 * gap, 0.3 * gap, n_active))
+    ev = np.sort(rng.uniform(0.2 * gap, 3.0, n_virtual))
+    eps = np.concatenate([ec, ea, ev])
+    B = _draw_B(rng, n_aux, N)
+    n_alpha = (n_active + 1) // 2
+    n_beta = n_active // 2
+    if n_active > 0:
+        ci = random_ci(rng, n_active, n_alpha, n_beta)
+        g1, g2, g3 = active_rdms(ci, n_active, n_alpha, n_beta)
+        if not with_gamma3:
+            g3 = None
+    else:
+        ci, g1, g2, g3 = None, None, None, None
+    return Problem(n_core, n_active, n_virtual, n_aux, eps, B, g1, g2, g3, float(s),
+                   ci=ci, n_alpha=n_alpha, n_beta=n_beta, name=name)
+
+
+# The five workloads: shapes from the paper's CAS(2,2), CAS(6,6) and CAS(8,8)
+# references, s = 0.5 and 1.0, dissociation curves, and the ~100-electron regime.
+CONFIGS = {
+    "tiny":   dict(n_core=2, n_active=2, n_virtual=10, n_aux=40, seed=101, s=0.5),
+    "small":  dict(n_core=5, n_active=6, n_virtual=49, n_aux=200, seed=202, s=0.5),
+    "medium": dict(n_core=20, n_active=8, n_virtual=300, n_aux=1200, seed=303, s=0.5),
+    "large":  dict(n_core=43, n_active=2, n_virtual=185, n_aux=920, seed=505, s=0.5),
+}
+SMALL_S_VALUES = (0.1, 0.5, 1.0)
+
+
+def make_config(name: str, s: Optional[float] = None) -> Problem:
+    kw = dict(CONFIGS[name])
+    if s is not None:
+        kw["s"] = s
+    return make_problem(name=name, **kw)
+
+
+def make_batch_config(n_geom: int = 64, base_seed: int = 4000, s: float = 0.5,
+                      first: int = 0) -> List[Problem]:
+    """Uneven geometries along a synthetic dissociation curve.
+
+    Geometry k draws its sizes first (core U{5..15}, active U{4..8}, virtual
+    U{80..400}), then uses naux = 4 N and gap factor 1 - 0.8 k/63.
+    """
+    probs = []
+    for k in range(first, first + n_geom):
+        rng = np.random.default_rng(base_seed + k)
+        nc = int(rng.integers(5, 16))
+        na = int(rng.integers(4, 9))
+        nv = int(rng.integers(80, 401))
+        N = nc + na + nv
+        gap = 1.0 - 0.8 * k / 63.0
+        probs.append(make_problem(nc, na, nv, 4 * N, seed=base_seed + 10000 + k, s=s,
+                                  gap=gap, name=f"curve{k}"))
+    return probs
