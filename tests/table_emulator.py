@@ -1,0 +1,199 @@
+"""NumPy executor of the library's contraction table (tests only).
+
+Parses ``paper_1701_02011_amd/csrc/dsrg_terms.inc`` exactly as the C++ library does and
+runs the same sequence of steps on spin-blocked spatial arrays, so the table and the
+step order can be checked against the oracle on the CPU.  It is not an oracle: the
+expected values always come from ``oracle/``.
+"""
+import os
+import re
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+INC = os.path.join(ROOT, "paper_1701_02011_amd", "csrc", "dsrg_terms.inc")
+STORAGE = {"T1": "PH", "T2": "PPHH", "E1": "PH", "E2": "PPHH", "Y1": "PH", "Y2": "PPHH",
+           "L2": "AAAA", "L3": "AAAAAA", "gA": "AA", "eA": "AA", "O1": "PH", "O2": "PPHH"}
+
+
+def load_table(path=INC):
+    text = open(path).read()
+    lines = [ln for ln in re.findall(r'^\s*"(.*)\\n"\s*$', text, flags=re.M) if ln]
+    uses, cur = {}, None
+    for ln in lines:
+        tag = ln[0]
+        if tag == "U":
+            _, name, n = ln.split()
+            cur = uses.setdefault(name, [])
+        elif tag == "P":
+            head, spc, res = [x.strip() for x in ln[1:].split("|")]
+            toks = head.split()
+            facs = []
+            for t in toks[1:]:
+                tb, lets = t.split(":")
+                tn, blk = tb.split(".")
+                facs.append((tn, "" if blk == "-" else blk, lets))
+            sp = dict(x.split("=") for x in spc.split())
+            cur.append([facs, sp, "" if res == "-" else res, []])
+        elif tag == "S":
+            _, coef, tgt = ln.split()
+            tb, lets = tgt.split(":")
+            tn, blk = tb.split(".")
+            cur[-1][3].append((float(coef), tn, "" if blk == "-" else blk,
+                               "" if lets == "-" else lets))
+    return uses
+
+
+class Dims:
+    def __init__(self, nC, nA, nV):
+        self.nC, self.nA, self.nV = nC, nA, nV
+        self.off = {"C": 0, "A": nC, "V": nC + nA, "H": 0, "P": nC, "G": 0}
+        self.len = {"C": nC, "A": nA, "V": nV, "H": nC + nA, "P": nA + nV, "G": nC + nA + nV}
+
+    def rng(self, ls, ax):
+        o = self.off[ls] - self.off[ax]
+        return slice(o, o + self.len[ls])
+
+
+def run_use(prods, d, B, tens, outs):
+    E = 0.0
+    for facs, sp, res, scat in prods:
+        if any(d.len[sp[l]] == 0 for l in sp):
+            continue
+        ops, specs = [], []
+        for tn, blk, ls in facs:
+            if tn == "J":
+                R = [slice(d.off[sp[l]], d.off[sp[l]] + d.len[sp[l]]) for l in ls]
+                ops.append(np.einsum("Qpr,Qqs->prqs", B[:, R[0], R[1]], B[:, R[2], R[3]]))
+            else:
+                ops.append(tens[tn][blk][tuple(d.rng(sp[l], ax) for l, ax in zip(ls, STORAGE[tn]))])
+            specs.append(ls)
+        val = np.einsum(",".join(specs) + "->" + res, *ops, optimize="greedy")
+        for coef, ot, ob, ol in scat:
+            if ot == "E":
+                E += coef * float(val)
+            else:
+                perm = [res.index(l) for l in ol]
+                arr = outs[ot][ob]
+                arr[tuple(d.rng(sp[l], ax) for l, ax in zip(ol, STORAGE[ot]))] += coef * np.transpose(val, perm)
+    return E
+
+
+def regulariser(s, D):
+    out = np.zeros_like(D)
+    nz = D != 0
+    out[nz] = -np.expm1(-s * D[nz] ** 2) / D[nz]
+    return out
+
+
+def cumulant_blocks(nA, g1, g2, g3):
+    """lambda2 / lambda3 spin blocks from the input RDM blocks, by the spin-orbital
+    route the library takes (expand, subtract antisymmetrised products, take blocks)."""
+    import itertools
+
+    def par(p):
+        return -1 if sum(1 for i in range(len(p)) for j in range(i + 1, len(p)) if p[i] > p[j]) % 2 else 1
+    n2 = 2 * nA
+    a, b = slice(0, nA), slice(nA, n2)
+    sl = (a, b)
+    G1 = np.zeros((n2, n2)); G1[a, a] = g1[0]; G1[b, b] = g1[1]
+
+    def fill(rank, canon):
+        T = np.zeros((n2,) * (2 * rank))
+        for up in itertools.product((0, 1), repeat=rank):
+            for lo in itertools.product((0, 1), repeat=rank):
+                if sorted(up) != sorted(lo):
+                    continue
+                pu = sorted(range(rank), key=lambda i: (up[i], i))
+                pl = sorted(range(rank), key=lambda i: (lo[i], i))
+                axes = [pu.index(k) for k in range(rank)] + [rank + pl.index(k) for k in range(rank)]
+                idx = tuple(sl[up[k]] for k in range(rank)) + tuple(sl[lo[k]] for k in range(rank))
+                T[idx] = par(pu) * par(pl) * np.transpose(canon[sum(up)], axes)
+        return T
+    G2 = fill(2, dict(enumerate(g2)))
+    L2 = G2 - np.einsum("pr,qs->pqrs", G1, G1) + np.einsum("ps,qr->pqrs", G1, G1)
+    L3 = np.zeros((n2,) * 6)
+    if g3 is not None:
+        G3 = fill(3, dict(enumerate(g3)))
+        det = 0.0
+        for pm in itertools.permutations(range(3)):
+            det = det + par(pm) * np.einsum("p%s,q%s,r%s->pqrstu" % tuple("stu"[i] for i in pm), G1, G1, G1)
+        gl = 0.0
+        up, lo = "pqr", "stu"
+        for i in range(3):
+            for j in range(3):
+                gl = gl + (-1) ** (i + j) * np.einsum("%s%s,%s%s->pqrstu" % (
+                    up[i], lo[j], up[:i] + up[i + 1:], lo[:j] + lo[j + 1:]), G1, L2)
+        L3 = G3 - det - gl
+    L2b = {"aa": L2[a, a, a, a], "ab": L2[a, b, a, b], "bb": L2[b, b, b, b]}
+    L3b = {"aaa": L3[a, a, a, a, a, a], "aab": L3[a, a, b, a, a, b],
+           "abb": L3[a, b, b, a, b, b], "bbb": L3[b, b, b, b, b, b]}
+    return L2b, L3b
+
+
+def pipeline(p, uses=None):
+    """E^(2), E^(3) and intermediates by the library's sequence of steps."""
+    uses = uses or load_table()
+    nC, nA, nV = p.n_core, p.n_active, p.n_virtual
+    d = Dims(nC, nA, nV)
+    nH, nP = nC + nA, nA + nV
+    s, eps, B = p.s, p.eps, p.B
+    if nA > 0:
+        L2, L3 = cumulant_blocks(nA, p.gamma1, p.gamma2, p.gamma3)
+        gA = {"a": p.gamma1[0], "b": p.gamma1[1]}
+    else:
+        L2 = {k: np.zeros((0,) * 4) for k in ("aa", "ab", "bb")}
+        L3 = {k: np.zeros((0,) * 6) for k in ("aaa", "aab", "abb", "bbb")}
+        gA = {k: np.zeros((0, 0)) for k in "ab"}
+    eA = {k: np.eye(nA) - v for k, v in gA.items()}
+    eP, eH = eps[nC:], eps[:nH]
+    D2 = eH[None, None, :, None] + eH[None, None, None, :] - eP[:, None, None, None] - eP[None, :, None, None]
+    D1 = eH[None, :] - eP[:, None]
+    aP = np.arange(nP) < nA
+    aH = np.arange(nH) >= nC
+    int2 = aP[:, None, None, None] & aP[None, :, None, None] & aH[None, None, :, None] & aH[None, None, None, :]
+    int1 = aP[:, None] & aH[None, :]
+    J = np.einsum("Qai,Qbj->aibj", B[:, nC:, :nH], B[:, nC:, :nH])       # (ai|bj)
+    vab = J.transpose(0, 2, 1, 3)
+    v = {"ab": vab, "aa": vab - vab.transpose(0, 1, 3, 2)}
+    v["bb"] = v["aa"]
+    R2, R1 = regulariser(s, D2), regulariser(s, D1)
+    e2f, e1f = np.exp(-s * D2 ** 2), np.exp(-s * D1 ** 2)
+    Dux = eps[nC:nH][None, :] - eps[nC:nH][:, None]
+
+    def amps(f1, v2):
+        t2 = {k: np.where(int2, 0.0, v2[k] * R2) for k in ("aa", "ab", "bb")}
+        ca = (np.einsum("axiu,ux,xu->ai", t2["aa"][:, :nA, :, nC:], Dux, gA["a"])
+              + np.einsum("axiu,ux,xu->ai", t2["ab"][:, :nA, :, nC:], Dux, gA["b"]))
+        cb = (np.einsum("axiu,ux,xu->ai", t2["bb"][:, :nA, :, nC:], Dux, gA["b"])
+              + np.einsum("xaui,ux,xu->ai", t2["ab"][:nA, :, nC:, :], Dux, gA["a"]))
+        coup = {"a": ca, "b": cb}
+        t1 = {k: np.where(int1, 0.0, (f1[k] + coup[k]) * R1) for k in "ab"}
+        return t1, t2, coup
+
+    z1 = {k: np.zeros((nP, nH)) for k in "ab"}
+    t1, t2, coup = amps(z1, v)
+    Y2 = {k: -D2 * t2[k] for k in t2}
+    Y1 = {k: np.where(int1, 0.0, coup[k] * e1f) for k in "ab"}
+    E2t = {k: np.where(int2, 2 * v[k], 2 * v[k] + Y2[k]) for k in v}
+    tens = dict(T1=t1, T2=t2, E1=Y1, E2=E2t, Y1=Y1, Y2=Y2, L2=L2, L3=L3, gA=gA, eA=eA)
+    e2 = run_use(uses["C0"], d, B, tens, None)
+
+    def zeros():
+        return {"O1": {k: np.zeros((nP, nH)) for k in "ab"},
+                "O2": {k: np.zeros((nP, nP, nH, nH)) for k in ("aa", "ab", "bb")}}
+    W, Z = zeros(), zeros()
+    run_use(uses["W"], d, B, tens, W)
+    run_use(uses["Z"], d, B, tens, Z)
+    O1 = {k: 2 * W["O1"][k] + Z["O1"][k] for k in "ab"}
+    O2 = {k: 2 * W["O2"][k] + Z["O2"][k] for k in ("aa", "ab", "bb")}
+    f2 = {k: 0.5 * O1[k] for k in "ab"}
+    v2 = {k: 0.5 * O2[k] for k in O2}
+    u1, u2, coup2 = amps(f2, v2)
+    H2 = {k: np.where(int2, 0.5 * O2[k] - Z["O2"][k] / 6, v2[k] * e2f - Z["O2"][k] / 6) for k in O2}
+    H1 = {k: np.where(int1, 0.5 * O1[k] - Z["O1"][k] / 6,
+                      (f2[k] + coup2[k]) * e1f - Z["O1"][k] / 6) for k in "ab"}
+    e3a = run_use(uses["C0"], d, B, dict(tens, T1=u1, T2=u2), None)
+    e3b = run_use(uses["C0"], d, B, dict(tens, E1=H1, E2=H2), None)
+    return dict(e2=e2, e3=e3a + e3b, e3a=e3a, e3b=e3b, t1=t1, t2=t2, u1=u1, u2=u2,
+                O1=O1, O2=O2, Z=Z, H1=H1, H2=H2)
