@@ -1,0 +1,130 @@
+/*
+ * dsrg.h -- C ABI of the DSRG-MRPT3 hot path on one AMD Instinct MI355X (gfx950).
+ *
+ * The library evaluates the unrelaxed second- and third-order correlation energies of
+ * the driven similarity renormalization group multireference perturbation theory
+ * (Li & Evangelista, arXiv:1701.02011):
+ *   E(2) = <Psi0|[H~(1), T(1)]|Psi0>                                 (Sec. II.B, Eq. E(2))
+ *   E(3) = <Psi0|[H~(1), T(2)]|Psi0> + <Psi0|[H~(2)_{1,2}, T(1)]|Psi0> (Sec. II.B, Eq. E(3))
+ * with first- and second-order amplitudes from the DSRG-regularised expressions
+ * (Eqs. T1_1st, T2_1st, T1_2nd, T2_2nd), commutators truncated to one- and two-body
+ * operators under the Mukherjee-Kutzelnigg generalised normal ordering (Sec. II.A), and
+ * two-electron integrals from a factorised three-index tensor (Sec. III, Eq. int_fact).
+ *
+ * Conventions
+ *   - Spatial orbitals are ordered [core | active | virtual]; N = nC + nA + nV.
+ *   - Orbitals are restricted (one spatial set for alpha and beta); the reference may
+ *     have different alpha and beta densities.
+ *   - The orbitals are semicanonical: eps are the diagonal elements of the core, active
+ *     and virtual blocks of the generalised Fock matrix (Sec. II.B, Eq. F0th), and the
+ *     inter-block Fock elements are taken as zero.
+ *   - The returned energies are correlation energies (the reference energy E0 is not an
+ *     input) of the unrelaxed series (Eq. E_unrelaxed).
+ *   - All arrays are FP64, C (row-major) order.
+ *
+ * Thread safety: calls may run concurrently from different host threads on different
+ * streams; each call allocates and frees its own device workspace.
+ */
+#ifndef DSRG_H
+#define DSRG_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+/* return codes */
+#define DSRG_OK 0
+#define DSRG_E_ARG (-1)         /* NULL pointer, negative size, n_aux < 1, s <= 0 or NaN */
+#define DSRG_E_NONFINITE (-2)   /* NaN or Inf in eps, B or the densities */
+#define DSRG_E_OOM (-3)         /* device allocation failed or workspace_cap too small */
+#define DSRG_E_HIP (-4)         /* HIP runtime error (message in dsrg_last_error) */
+#define DSRG_E_UNSUPPORTED (-5) /* option not built (e.g. a precision other than FP64) */
+
+/* options.flags */
+#define DSRG_F_DEVICE_PTRS 1    /* every array pointer in dsrg_problem is a device pointer */
+#define DSRG_F_PROFILE 2        /* bracket every contraction launch with HIP events and report
+                                   per-role device time in dsrg_result.role_* (adds overhead) */
+
+typedef struct {
+  int32_t n_core, n_active, n_virtual, n_aux;
+  /* [N] semicanonical orbital energies (E_h) */
+  const double* eps;
+  /* [n_aux][N][N], symmetric in the last two indices: (pq|rs) = sum_Q B[Q][p][q] B[Q][r][s] */
+  const double* B;
+  /* [2][nA][nA]: gamma1[s][u][v] = <a+_{u s} a_{v s}>, s = alpha, beta.  Unused if nA == 0. */
+  const double* gamma1;
+  /* [3][nA][nA][nA][nA], blocks aa, ab, bb: gamma2[b][u][v][x][y] = <a+_u a+_v a_y a_x> with
+     spins (s1, s2) on (u, x) and (v, y). */
+  const double* gamma2;
+  /* [4][nA]^6, blocks aaa, aab, abb, bbb: gamma3[b][u][v][w][x][y][z] =
+     <a+_u a+_v a+_w a_z a_y a_x>, spins (s1, s2, s3) on (u,x), (v,y), (w,z).
+     NULL sets the three-body cumulant to zero (an approximation; never used for parity). */
+  const double* gamma3;
+  /* flow parameter s (E_h^-2), > 0; +INFINITY selects the unregularised limit 1/D */
+  double s;
+} dsrg_problem;
+
+typedef struct {
+  int32_t flags;          /* DSRG_F_* */
+  int32_t precision;      /* 0 = FP64 (the only precision built) */
+  int64_t workspace_cap;  /* bytes of device workspace for batched integral blocks; 0 = 8 GiB */
+  void* stream;           /* hipStream_t to run on, or NULL for the null stream; caller owns it */
+} dsrg_options;
+
+typedef struct {
+  double e2;              /* E(2) (E_h) */
+  double e3;              /* E(3) = e3_a + e3_b (E_h) */
+  double e3_a;            /* <[H~(1), T(2)]> */
+  double e3_b;            /* <[H~(2)_{1,2}, T(1)]> */
+  double t_seconds[8];    /* device time: [0] densities+integrals, [1] first order, [2] E(2),
+                             [3] [V,A] (ladders, rings), [4] [Y,A], [5] second order + E(3),
+                             [6] unused, [7] whole call */
+  double gett_flops;      /* floating-point operations issued by the contraction kernels */
+  double ladder_flops;    /* of which the (PP|PP) particle-particle ladder (Sec. III) */
+  double ladder_seconds;  /* device time of the ladder contractions (GETT launches only) */
+  int32_t ladder_batch;   /* virtual batch size used for the (PP|PP) integrals */
+  int32_t n_launch;       /* kernel launches issued */
+  /* with DSRG_F_PROFILE: contraction launches by role [0] table products, [1] (PP|PP)
+     ladder products, [2] Coulomb-block builds from B: device seconds, flops, launches */
+  double role_seconds[3];
+  double role_flops[3];
+  int32_t role_launches[3];
+} dsrg_result;
+
+/* Optional host outputs of intermediates (each pointer may be NULL).  Shapes use
+   nH = nC + nA and nP = nA + nV; excitation order [P][H] and [P][P][H][H] (C-convention
+   coefficient of {a+_a a_i} and 1/4 {a+_a a+_b a_j a_i}). */
+typedef struct {
+  double* t1;   /* [2][nP][nH]       first-order singles, spins a, b */
+  double* t2;   /* [3][nP][nP][nH][nH] first-order doubles, blocks aa, ab, bb */
+  double* w1;   /* [2][nP][nH]       excitation block of [V, A(1)]_{1,2} */
+  double* w2;   /* [3][nP][nP][nH][nH] */
+  double* z1;   /* [2][nP][nH]       excitation block of [[H(0), A(1)], A(1)]_{1,2} */
+  double* z2;   /* [3][nP][nP][nH][nH] */
+  double* u1;   /* [2][nP][nH]       second-order singles */
+  double* u2;   /* [3][nP][nP][nH][nH] second-order doubles */
+} dsrg_intermediates;
+
+/* E(2) only (Eq. E(2)); out->e3* are set to 0.  Returns DSRG_OK or a DSRG_E_* code; on
+   error *out is left untouched.  The caller owns all buffers; inputs are only read. */
+int dsrg_pt2_energy(const dsrg_problem* prob, const dsrg_options* opt, dsrg_result* out);
+
+/* E(2) and E(3) (Eqs. E(2), E(3)).  Same conventions as dsrg_pt2_energy. */
+int dsrg_pt3_energy(const dsrg_problem* prob, const dsrg_options* opt, dsrg_result* out);
+
+/* As dsrg_pt3_energy, and copies the requested intermediates to host memory. */
+int dsrg_pt3_energy_ex(const dsrg_problem* prob, const dsrg_options* opt, dsrg_result* out,
+                       const dsrg_intermediates* inter);
+
+/* Message of the last failing call on this host thread ("" if none). */
+const char* dsrg_last_error(void);
+
+/* Library version: major * 10000 + minor * 100 + patch. */
+int dsrg_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* DSRG_H */

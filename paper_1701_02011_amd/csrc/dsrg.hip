@@ -1,0 +1,1108 @@
+// DSRG-MRPT3 hot path on one MI355X: C ABI, contraction-table executor and pipeline.
+//
+// The steps follow Sec. II.B of the paper: first-order amplitudes (Eqs. T1_1st, T2_1st),
+// E(2) = <[H~(1), T(1)]>, O1 = [H~(1), A(1)]_{1,2} with H~(1) = 2 V + Y and
+// Y = [H(0), A(1)] (so O1 = 2 [V, A(1)] + [Y, A(1)]), second-order amplitudes from the
+// non-diagonal part of O1/2 (Eqs. T1_2nd, T2_2nd), H~(2)_{1,2} = [H(0), A(2)] + O1/2 - [Y, A(1)]/6
+// and E(3) = <[H~(1), T(2)]> + <[H~(2)_{1,2}, T(1)]>.  The commutator terms come from the
+// generated table in dsrg_terms.inc; every contraction in it runs on the GETT kernel.
+#include "../../include/dsrg.h"
+#include "kernels.h"
+
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <cstdio>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <sstream>
+#include <stdexcept>
+#include <string>
+#include <vector>
+
+#include "dsrg_terms.inc"
+
+namespace dsrg {
+
+static thread_local std::string g_last_error;
+
+struct Error : std::runtime_error {
+  int code;
+  Error(int c, const std::string& m) : std::runtime_error(m), code(c) {}
+};
+
+#define HIPCHECK(x)                                                                          \
+  do {                                                                                       \
+    hipError_t e_ = (x);                                                                     \
+    if (e_ != hipSuccess) {                                                                  \
+      if (e_ == hipErrorOutOfMemory) throw Error(DSRG_E_OOM, std::string(#x) + ": out of memory"); \
+      throw Error(DSRG_E_HIP, std::string(#x) + ": " + hipGetErrorString(e_));               \
+    }                                                                                        \
+  } while (0)
+
+// ---------------------------------------------------------------------------
+// Orbital spaces: C, A, V, H = C+A, P = A+V, G; contiguous in [C|A|V] order
+// ---------------------------------------------------------------------------
+struct Dims {
+  int nC, nA, nV;
+  int off(char s) const {
+    switch (s) {
+      case 'C': case 'H': case 'G': return 0;
+      case 'A': case 'P': return nC;
+      case 'V': return nC + nA;
+    }
+    throw Error(DSRG_E_ARG, "bad space");
+  }
+  int len(char s) const {
+    switch (s) {
+      case 'C': return nC;
+      case 'A': return nA;
+      case 'V': return nV;
+      case 'H': return nC + nA;
+      case 'P': return nA + nV;
+      case 'G': return nC + nA + nV;
+    }
+    throw Error(DSRG_E_ARG, "bad space");
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Contraction table
+// ---------------------------------------------------------------------------
+struct TFactor {
+  std::string tensor, block, letters;
+};
+struct TScatter {
+  double coef;
+  std::string tensor, block, letters;
+};
+struct TProduct {
+  std::vector<TFactor> f;
+  std::map<char, char> space;
+  std::string res;
+  std::vector<TScatter> s;
+};
+using Use = std::vector<TProduct>;
+
+static std::map<std::string, Use>& table() {
+  static std::map<std::string, Use> t;
+  static std::once_flag once;
+  std::call_once(once, [] {
+    std::istringstream in(kDsrgTermTable);
+    std::string line;
+    Use* cur = nullptr;
+    while (std::getline(in, line)) {
+      if (line.empty()) continue;
+      std::istringstream ls(line);
+      std::string tag;
+      ls >> tag;
+      if (tag == "U") {
+        std::string name;
+        ls >> name;
+        cur = &t[name];
+      } else if (tag == "P") {
+        TProduct p;
+        int nf;
+        ls >> nf;
+        for (int i = 0; i < nf; ++i) {
+          std::string tok;
+          ls >> tok;
+          size_t dot = tok.find('.'), col = tok.find(':');
+          TFactor f{tok.substr(0, dot), tok.substr(dot + 1, col - dot - 1), tok.substr(col + 1)};
+          if (f.block == "-") f.block = "";
+          p.f.push_back(f);
+        }
+        std::string bar;
+        ls >> bar;  // '|'
+        std::string tok;
+        while (ls >> tok && tok != "|") p.space[tok[0]] = tok[2];
+        ls >> p.res;
+        if (p.res == "-") p.res = "";
+        cur->push_back(p);
+      } else if (tag == "S") {
+        TScatter s;
+        std::string tgt;
+        ls >> s.coef >> tgt;
+        size_t dot = tgt.find('.'), col = tgt.find(':');
+        s.tensor = tgt.substr(0, dot);
+        s.block = tgt.substr(dot + 1, col - dot - 1);
+        s.letters = tgt.substr(col + 1);
+        if (s.block == "-") s.block = "";
+        if (s.letters == "-") s.letters = "";
+        cur->back().s.push_back(s);
+      }
+    }
+  });
+  return t;
+}
+
+static const char* storage_axes(const std::string& t) {
+  if (t == "T1" || t == "E1" || t == "Y1" || t == "O1") return "PH";
+  if (t == "T2" || t == "E2" || t == "Y2" || t == "O2") return "PPHH";
+  if (t == "L2") return "AAAA";
+  if (t == "L3") return "AAAAAA";
+  if (t == "gA" || t == "eA") return "AA";
+  throw Error(DSRG_E_ARG, "unknown tensor " + t);
+}
+
+// ---------------------------------------------------------------------------
+// Device memory: call-scoped allocations
+// ---------------------------------------------------------------------------
+struct Pool {
+  hipStream_t st;
+  std::vector<void*> bufs;
+  size_t bytes = 0;
+  explicit Pool(hipStream_t s) : st(s) {}
+  double* alloc(size_t n) {
+    if (n == 0) n = 1;
+    void* p = nullptr;
+    hipError_t e = hipMalloc(&p, n * sizeof(double));
+    if (e != hipSuccess) {
+      (void)hipGetLastError();
+      throw Error(DSRG_E_OOM, "device allocation of " + std::to_string(n * 8) + " bytes failed");
+    }
+    bufs.push_back(p);
+    bytes += n * 8;
+    return (double*)p;
+  }
+  void release(double* p) {
+    for (auto& b : bufs)
+      if (b == p) {
+        (void)hipFree(b);
+        b = nullptr;
+      }
+  }
+  ~Pool() {
+    (void)hipStreamSynchronize(st);
+    for (void* p : bufs)
+      if (p) (void)hipFree(p);
+  }
+};
+
+// A strided view of a stored tensor with one letter per axis.
+struct Opnd {
+  const double* p;
+  std::string letters;
+  std::vector<long long> stride;
+  long long lim = 0;   // elements addressable from p (allocation end)
+};
+
+struct TensorRef {
+  double* p;
+  std::string axes;               // storage spaces per axis
+  std::vector<long long> stride;  // element strides per axis
+  long long lim = 0;              // elements addressable from p
+};
+
+// Host-side bounds check of a strided view before any launch that reads or writes it.
+static void check_view(const char* what, long long lim, const std::vector<long long>& stride,
+                       const std::vector<int>& len) {
+  long long hi = 0;
+  for (size_t k = 0; k < stride.size(); ++k) {
+    if (len[k] <= 0) return;
+    if (stride[k] < 0) throw Error(DSRG_E_HIP, std::string("internal: negative stride in ") + what);
+    hi += (long long)(len[k] - 1) * stride[k];
+  }
+  if (hi >= lim)
+    throw Error(DSRG_E_HIP, std::string("internal: view of ") + what + " addresses past its allocation");
+}
+
+// ---------------------------------------------------------------------------
+// Executor
+// ---------------------------------------------------------------------------
+struct Exec {
+  Dims d;
+  hipStream_t st;
+  Pool& pool;
+  const double* B;   // [M][N][N] device
+  int M;
+  std::map<std::string, TensorRef> tensors;   // "T2.aa" -> view
+  std::map<std::string, double*> jblocks;     // "HPHP" -> [X1][X2][X3][X4]
+  double* partial = nullptr;
+  long long ws_cap;
+  double gett_flops = 0, ladder_flops = 0, ladder_ms = 0;
+  int ladder_batch = 0, n_launch = 0;
+
+  Exec(Dims d_, hipStream_t s, Pool& p, const double* B_, int M_, long long cap, bool prof)
+      : d(d_), st(s), pool(p), B(B_), M(M_), ws_cap(cap), profile(prof) {
+    partial = pool.alloc(dot_partials());
+  }
+
+  // every contraction launch goes through here; with profiling, HIP events bracket it
+  bool profile;
+  int role_now = kRoleGeneric;
+  struct Rec {
+    hipEvent_t a, b;
+    int role;
+    double flops;
+  };
+  std::vector<Rec> recs;
+  void gett(const GettDesc& g, const double* A, const double* Bp, double* C, int role) {
+    double fl = 2.0 * g.M * (double)g.N * g.K;
+    Rec r{nullptr, nullptr, role, fl};
+    if (profile) {
+      HIPCHECK(hipEventCreate(&r.a));
+      HIPCHECK(hipEventCreate(&r.b));
+      HIPCHECK(hipEventRecord(r.a, st));
+    }
+    launch_gett(g, A, Bp, C, st, role);
+    if (profile) {
+      HIPCHECK(hipEventRecord(r.b, st));
+      recs.push_back(r);
+    }
+    gett_flops += fl;
+    if (role == kRoleLadder) ladder_flops_products += fl;
+    ++n_launch;
+  }
+  double ladder_flops_products = 0;
+  // per-role totals of profiled launches: seconds, launches, flops
+  double role_sec[3] = {0, 0, 0}, role_flops[3] = {0, 0, 0};
+  int role_n[3] = {0, 0, 0};
+  void collect_profile() {
+    for (auto& r : recs) {
+      float ms = 0;
+      HIPCHECK(hipEventElapsedTime(&ms, r.a, r.b));
+      role_sec[r.role] += ms * 1e-3;
+      role_flops[r.role] += r.flops;
+      role_n[r.role] += 1;
+      (void)hipEventDestroy(r.a);
+      (void)hipEventDestroy(r.b);
+    }
+    recs.clear();
+  }
+  ~Exec() {
+    for (auto& r : recs) {
+      (void)hipEventDestroy(r.a);
+      (void)hipEventDestroy(r.b);
+    }
+  }
+
+  void set(const std::string& name, double* p, const char* axes) {
+    TensorRef t{p, axes, {}};
+    int r = (int)strlen(axes);
+    t.stride.assign(r, 1);
+    for (int k = r - 2; k >= 0; --k) t.stride[k] = t.stride[k + 1] * d.len(axes[k + 1]);
+    t.lim = t.stride[0] * d.len(axes[0]);
+    tensors[name] = t;
+  }
+  void set_view(const std::string& name, double* p, const char* axes, std::vector<long long> stride,
+                long long lim) {
+    tensors[name] = TensorRef{p, axes, stride, lim};
+  }
+
+  // ---- Coulomb blocks J(X1 X2 | X3 X4)[p][q][r][s] = sum_Q B[Q][p][q] B[Q][r][s] ----
+  void build_j(char s1, char s2, char s3, char s4, int off1, int n1, double* out) {
+    int N = d.nC + d.nA + d.nV;
+    GettDesc g;
+    g.nm = 2; g.nn = 2; g.nk = 1;
+    g.md[0] = n1; g.md[1] = d.len(s2);
+    g.nd[0] = d.len(s3); g.nd[1] = d.len(s4);
+    g.kd[0] = M;
+    g.M = g.md[0] * g.md[1];
+    g.N = g.nd[0] * g.nd[1];
+    g.K = M;
+    const double* A0 = B + (long long)(d.off(s1) + off1) * N + d.off(s2);
+    const double* B0 = B + (long long)d.off(s3) * N + d.off(s4);
+    g.am[0] = N; g.am[1] = 1; g.ak[0] = (long long)N * N;
+    g.bk[0] = (long long)N * N; g.bn[0] = N; g.bn[1] = 1;
+    g.cm[0] = (long long)g.md[1] * g.N; g.cm[1] = g.N;
+    g.cn[0] = g.nd[1]; g.cn[1] = 1;
+    g.a_kfast = 0; g.b_kfast = 0;
+    g.alpha = 1.0; g.beta = 0;
+    long long nB = (long long)M * N * N;
+    check_view("B (first pair)", nB - (A0 - B), {g.am[0], g.am[1], g.ak[0]}, {g.md[0], g.md[1], M});
+    check_view("B (second pair)", nB - (B0 - B), {g.bn[0], g.bn[1], g.bk[0]}, {g.nd[0], g.nd[1], M});
+    gett(g, A0, B0, out, kRoleIntegrals);
+  }
+  double* jblock(const std::string& key) {
+    auto it = jblocks.find(key);
+    if (it != jblocks.end()) return it->second;
+    size_t n = (size_t)d.len(key[0]) * d.len(key[1]) * d.len(key[2]) * d.len(key[3]);
+    double* p = pool.alloc(n);
+    build_j(key[0], key[1], key[2], key[3], 0, d.len(key[0]), p);
+    jblocks[key] = p;
+    return p;
+  }
+
+  static char promote(char s) { return (s == 'C' || s == 'A' || s == 'H') ? 'H' : 'P'; }
+
+  // Canonical chemist order of a J factor: H before P inside each pair, then pairs HH < HP < PP.
+  static void canon_j(const std::string& L, const std::map<char, char>& sp, std::string& letters,
+                      std::string& key) {
+    std::string l = L;
+    auto pr = [&](char c) { return promote(sp.at(c)); };
+    if (pr(l[0]) == 'P' && pr(l[1]) == 'H') std::swap(l[0], l[1]);
+    if (pr(l[2]) == 'P' && pr(l[3]) == 'H') std::swap(l[2], l[3]);
+    auto rank = [&](char a, char b) { return (pr(a) == 'P') + (pr(b) == 'P'); };
+    if (rank(l[0], l[1]) > rank(l[2], l[3])) l = l.substr(2, 2) + l.substr(0, 2);
+    letters = l;
+    key = std::string() + pr(l[0]) + pr(l[1]) + pr(l[2]) + pr(l[3]);
+  }
+
+  // ---- letter ranges (with an optional batched letter) ----
+  struct LetterRange {
+    std::map<char, int> off, len;   // offset inside the letter's own space, length
+  };
+
+  Opnd factor_view(const TFactor& f, const std::map<char, char>& sp, const LetterRange& lr,
+                   const double* jbatch, char batch_letter) {
+    Opnd o;
+    if (f.tensor == "J") {
+      std::string L, key;
+      canon_j(f.letters, sp, L, key);
+      const double* base;
+      std::vector<int> dims(4);
+      std::vector<int> extra(4, 0);
+      if (key == "PPPP") {
+        base = jbatch;
+        if (!jbatch || L[0] != batch_letter) throw Error(DSRG_E_HIP, "internal: unbatched (PP|PP) block");
+        dims[0] = lr.len.at(L[0]);
+        for (int k = 1; k < 4; ++k) dims[k] = d.len('P');
+      } else {
+        base = jblock(key);
+        for (int k = 0; k < 4; ++k) dims[k] = d.len(key[k]);
+      }
+      std::vector<long long> stride(4, 1);
+      for (int k = 2; k >= 0; --k) stride[k] = stride[k + 1] * dims[k + 1];
+      long long off = 0;
+      for (int k = 0; k < 4; ++k) {
+        char l = L[k];
+        int pos = d.off(sp.at(l)) - d.off(key[k]) + lr.off.at(l);
+        if (key == "PPPP" && k == 0) pos = 0;   // the batch buffer starts at the batch
+        off += pos * stride[k];
+      }
+      o.p = base + off;
+      o.letters = L;
+      o.stride = stride;
+      o.lim = (long long)dims[0] * stride[0] - off;
+      return o;
+    }
+    std::string name = f.tensor + "." + f.block;
+    auto it = tensors.find(name);
+    if (it == tensors.end()) throw Error(DSRG_E_HIP, "internal: tensor " + name + " not bound");
+    const TensorRef& t = it->second;
+    long long off = 0;
+    for (size_t k = 0; k < f.letters.size(); ++k) {
+      char l = f.letters[k];
+      off += (long long)(d.off(sp.at(l)) - d.off(t.axes[k]) + lr.off.at(l)) * t.stride[k];
+    }
+    o.p = t.p + off;
+    o.letters = f.letters;
+    o.stride = t.stride;
+    o.lim = t.lim - off;
+    return o;
+  }
+
+  // contract two operands; result either a new contiguous temp or (final) the target
+  Opnd contract(const Opnd& a, const Opnd& b, const LetterRange& lr, std::vector<double*>& temps) {
+    std::string ml, nl, kl;
+    std::vector<long long> am, ak, bk, bn;
+    for (size_t i = 0; i < a.letters.size(); ++i) {
+      char l = a.letters[i];
+      size_t j = b.letters.find(l);
+      if (j == std::string::npos) { ml += l; am.push_back(a.stride[i]); }
+      else { kl += l; ak.push_back(a.stride[i]); bk.push_back(b.stride[j]); }
+    }
+    for (size_t j = 0; j < b.letters.size(); ++j)
+      if (a.letters.find(b.letters[j]) == std::string::npos) { nl += b.letters[j]; bn.push_back(b.stride[j]); }
+    GettDesc g;
+    g.nm = (int)ml.size(); g.nn = (int)nl.size(); g.nk = (int)kl.size();
+    if (g.nm > kMaxComp || g.nn > kMaxComp || g.nk > kMaxComp) throw Error(DSRG_E_HIP, "internal: rank");
+    long long Mx = 1, Nx = 1, Kx = 1;
+    for (int i = 0; i < g.nm; ++i) { g.md[i] = lr.len.at(ml[i]); g.am[i] = am[i]; Mx *= g.md[i]; }
+    for (int i = 0; i < g.nn; ++i) { g.nd[i] = lr.len.at(nl[i]); g.bn[i] = bn[i]; Nx *= g.nd[i]; }
+    for (int i = 0; i < g.nk; ++i) { g.kd[i] = lr.len.at(kl[i]); g.ak[i] = ak[i]; g.bk[i] = bk[i]; Kx *= g.kd[i]; }
+    if (Mx >= (1LL << 31) || Nx >= (1LL << 31) || Kx >= (1LL << 31))
+      throw Error(DSRG_E_UNSUPPORTED, "contraction dimension exceeds 2^31");
+    g.M = (int)Mx; g.N = (int)Nx; g.K = (int)Kx;
+    check_operand("contraction A", a, lr);
+    check_operand("contraction B", b, lr);
+    Opnd r;
+    r.letters = ml + nl;
+    size_t n = (size_t)Mx * Nx;
+    double* out = pool_temp(n, temps);
+    r.lim = (long long)n;
+    r.p = out;
+    r.stride.assign(r.letters.size(), 1);
+    for (int k = (int)r.letters.size() - 2; k >= 0; --k) r.stride[k] = r.stride[k + 1] * lr.len.at(r.letters[k + 1]);
+    for (int i = 0; i < g.nm; ++i) g.cm[i] = r.stride[i];
+    for (int i = 0; i < g.nn; ++i) g.cn[i] = r.stride[g.nm + i];
+    set_load_order(g);
+    g.alpha = 1.0; g.beta = 0;
+    gett(g, a.p, b.p, out, role_now);
+    return r;
+  }
+
+  void check_operand(const char* what, const Opnd& o, const LetterRange& lr) {
+    std::vector<int> len;
+    for (char c : o.letters) len.push_back(lr.len.at(c));
+    check_view(what, o.lim, o.stride, len);
+  }
+
+  static void set_load_order(GettDesc& g) {
+    auto mn = [](const long long* s, int n) {
+      long long m = (1LL << 62);
+      for (int i = 0; i < n; ++i) m = std::min(m, s[i] < 0 ? -s[i] : s[i]);
+      return m;
+    };
+    g.a_kfast = mn(g.ak, g.nk) < mn(g.am, g.nm);
+    g.b_kfast = mn(g.bk, g.nk) < mn(g.bn, g.nn);
+  }
+
+  // temporaries: grow-only arena reused across products (single stream, so reuse is
+  // ordered after every earlier use)
+  std::vector<std::pair<double*, size_t>> free_tmp;
+  double* pool_temp(size_t n, std::vector<double*>& temps) {
+    size_t best = free_tmp.size();
+    for (size_t i = 0; i < free_tmp.size(); ++i)
+      if (free_tmp[i].second >= n && (best == free_tmp.size() || free_tmp[i].second < free_tmp[best].second))
+        best = i;
+    double* p;
+    size_t sz;
+    if (best < free_tmp.size()) {
+      p = free_tmp[best].first;
+      sz = free_tmp[best].second;
+      free_tmp.erase(free_tmp.begin() + best);
+    } else {
+      p = pool.alloc(n);
+      sz = n;
+    }
+    temps.push_back(p);
+    tmp_size[p] = sz;
+    return p;
+  }
+  std::map<double*, size_t> tmp_size;
+  void release_temps(std::vector<double*>& temps) {
+    for (double* t : temps) free_tmp.push_back({t, tmp_size[t]});
+    temps.clear();
+  }
+
+  // Execute one product; outputs by name ("O1.a" -> TensorRef) or scalar slots.
+  void run_product(const TProduct& P, const LetterRange& lr, const double* jbatch, char batch_letter,
+                   std::map<std::string, TensorRef>& outs, double* slot, double& slot_coef,
+                   double flops_scale_ladder) {
+    for (auto& kv : lr.len)
+      if (kv.second == 0) return;
+    std::vector<Opnd> ops;
+    for (auto& f : P.f) ops.push_back(factor_view(f, P.space, lr, jbatch, batch_letter));
+    std::vector<double*> temps;
+    double f0 = gett_flops;
+    // direct path: two factors, one scatter into a tensor output
+    if (ops.size() == 2 && P.s.size() == 1 && !P.res.empty()) {
+      const TScatter& s = P.s[0];
+      const TensorRef& o = outs.at(s.tensor + "." + s.block);
+      contract_into(ops[0], ops[1], lr, P.space, s, o);
+      if (flops_scale_ladder > 0) ladder_flops += gett_flops - f0;
+      return;
+    }
+    while (ops.size() > 2 || (ops.size() == 2 && !P.res.empty())) {
+      if (ops.size() == 1) break;
+      size_t bi = 0, bj = 1;
+      double best = 1e300;
+      for (size_t i = 0; i < ops.size(); ++i)
+        for (size_t j = i + 1; j < ops.size(); ++j) {
+          std::string u = ops[i].letters;
+          for (char c : ops[j].letters)
+            if (u.find(c) == std::string::npos) u += c;
+          double c = 1;
+          for (char l : u) c *= lr.len.at(l);
+          if (c < best) { best = c; bi = i; bj = j; }
+        }
+      Opnd r = contract(ops[bi], ops[bj], lr, temps);
+      ops.erase(ops.begin() + bj);
+      ops[bi] = r;
+    }
+    if (P.res.empty()) {
+      // final scalar: dot product of the last two operands
+      if (ops.size() != 2) throw Error(DSRG_E_HIP, "internal: scalar product shape");
+      const Opnd& a = ops[0];
+      const Opnd& b = ops[1];
+      DotDesc dd;
+      dd.nk = (int)a.letters.size();
+      dd.K = 1;
+      for (int i = 0; i < dd.nk; ++i) {
+        char l = a.letters[i];
+        size_t j = b.letters.find(l);
+        dd.kd[i] = lr.len.at(l);
+        dd.as[i] = a.stride[i];
+        dd.bs[i] = b.stride[j];
+        dd.K *= dd.kd[i];
+      }
+      check_operand("dot A", a, lr);
+      check_operand("dot B", b, lr);
+      launch_dot(dd, a.p, b.p, partial, slot, st);
+      n_launch += 2;
+      gett_flops += 2.0 * dd.K;
+      double c = 0;
+      for (auto& s : P.s) c += s.coef;
+      slot_coef = c;
+    } else {
+      const Opnd& r = ops[0];
+      for (auto& s : P.s) {
+        const TensorRef& o = outs.at(s.tensor + "." + s.block);
+        ScatterDesc sd;
+        sd.rank = (int)s.letters.size();
+        sd.n = 1;
+        long long ooff = 0;
+        for (int k = 0; k < sd.rank; ++k) {
+          char l = s.letters[k];
+          sd.d[k] = lr.len.at(l);
+          sd.ss[k] = r.stride[r.letters.find(l)];
+          sd.so[k] = o.stride[k];
+          ooff += (long long)(d.off(P.space.at(l)) - d.off(o.axes[k]) + lr.off.at(l)) * o.stride[k];
+          sd.n *= sd.d[k];
+        }
+        sd.coef = s.coef;
+        check_operand("scatter source", r, lr);
+        {
+          std::vector<long long> so(sd.so, sd.so + sd.rank);
+          std::vector<int> len(sd.d, sd.d + sd.rank);
+          check_view("scatter target", o.lim - ooff, so, len);
+        }
+        launch_scatter(sd, r.p, o.p + ooff, st);
+        ++n_launch;
+      }
+    }
+    release_temps(temps);
+    if (flops_scale_ladder > 0) ladder_flops += gett_flops - f0;
+  }
+
+  void contract_into(const Opnd& a, const Opnd& b, const LetterRange& lr,
+                     const std::map<char, char>& sp, const TScatter& s, const TensorRef& o) {
+    std::string ml, nl, kl;
+    GettDesc g;
+    long long ooff = 0;
+    std::map<char, long long> ostr;
+    for (size_t k = 0; k < s.letters.size(); ++k) {
+      char l = s.letters[k];
+      ostr[l] = o.stride[k];
+      ooff += (long long)(d.off(sp.at(l)) - d.off(o.axes[k]) + lr.off.at(l)) * o.stride[k];
+    }
+    for (size_t i = 0; i < a.letters.size(); ++i) {
+      char l = a.letters[i];
+      size_t j = b.letters.find(l);
+      if (j == std::string::npos) {
+        g.md[g.nm] = lr.len.at(l); g.am[g.nm] = a.stride[i]; g.cm[g.nm] = ostr.at(l); ++g.nm;
+      } else {
+        g.kd[g.nk] = lr.len.at(l); g.ak[g.nk] = a.stride[i]; g.bk[g.nk] = b.stride[j]; ++g.nk;
+      }
+    }
+    for (size_t j = 0; j < b.letters.size(); ++j) {
+      char l = b.letters[j];
+      if (a.letters.find(l) == std::string::npos) {
+        g.nd[g.nn] = lr.len.at(l); g.bn[g.nn] = b.stride[j]; g.cn[g.nn] = ostr.at(l); ++g.nn;
+      }
+    }
+    long long Mx = 1, Nx = 1, Kx = 1;
+    for (int i = 0; i < g.nm; ++i) Mx *= g.md[i];
+    for (int i = 0; i < g.nn; ++i) Nx *= g.nd[i];
+    for (int i = 0; i < g.nk; ++i) Kx *= g.kd[i];
+    if (Mx >= (1LL << 31) || Nx >= (1LL << 31) || Kx >= (1LL << 31))
+      throw Error(DSRG_E_UNSUPPORTED, "contraction dimension exceeds 2^31");
+    g.M = (int)Mx; g.N = (int)Nx; g.K = (int)Kx;
+    set_load_order(g);
+    g.alpha = s.coef;
+    g.beta = 1;
+    check_operand("contraction A", a, lr);
+    check_operand("contraction B", b, lr);
+    {
+      std::vector<long long> cs;
+      std::vector<int> len;
+      for (int i = 0; i < g.nm; ++i) { cs.push_back(g.cm[i]); len.push_back(g.md[i]); }
+      for (int i = 0; i < g.nn; ++i) { cs.push_back(g.cn[i]); len.push_back(g.nd[i]); }
+      check_view("contraction target", o.lim - ooff, cs, len);
+    }
+    gett(g, a.p, b.p, o.p + ooff, role_now);
+  }
+
+  static bool is_pppp(const TProduct& P, std::string* jl) {
+    for (auto& f : P.f)
+      if (f.tensor == "J") {
+        std::string L, key;
+        canon_j(f.letters, P.space, L, key);
+        if (key == "PPPP") {
+          if (jl) *jl = L;
+          return true;
+        }
+      }
+    return false;
+  }
+
+  LetterRange full_range(const TProduct& P) const {
+    LetterRange lr;
+    for (auto& kv : P.space) {
+      lr.off[kv.first] = 0;
+      lr.len[kv.first] = d.len(kv.second);
+    }
+    return lr;
+  }
+
+  // Run a use of the table.  Scalar products write vals[i]/coefs[i] for a final weighted sum.
+  void run_use(const Use& U, std::map<std::string, TensorRef>& outs, double* vals,
+               std::vector<double>& coefs) {
+    // products with the (PP|PP) block, grouped by the block's letters
+    std::map<std::string, std::vector<const TProduct*>> pppp;
+    int slot = 0;
+    for (auto& P : U) {
+      std::string jl;
+      if (is_pppp(P, &jl)) {
+        // batch letter: a free letter of the block; rotate it to the first position
+        std::string key = jl;
+        for (auto& kv : P.space) key += std::string(1, kv.first) + kv.second;
+        pppp[key].push_back(&P);
+        continue;
+      }
+      double c = 0;
+      run_product(P, full_range(P), nullptr, 0, outs, vals ? vals + slot : nullptr, c, 0);
+      if (P.res.empty()) {
+        coefs.push_back(c);
+        ++slot;
+      }
+    }
+    for (auto& grp : pppp) {
+      const TProduct& P0 = *grp.second[0];
+      std::string L, key;
+      for (auto& f : P0.f)
+        if (f.tensor == "J") canon_j(f.letters, P0.space, L, key);
+      // the first letter of the canonical block must be free in every product of the group
+      char bl = 0;
+      for (int k = 0; k < 4 && !bl; ++k) {
+        bool free_all = true;
+        for (auto* P : grp.second)
+          if (P->res.find(L[k]) == std::string::npos) free_all = false;
+        if (free_all) bl = L[k];
+      }
+      if (!bl) throw Error(DSRG_E_HIP, "internal: no free letter to batch the (PP|PP) block");
+      int nP = d.len('P');
+      int lbl = d.len(P0.space.at(bl));
+      long long per = (long long)nP * nP * nP;
+      long long nb = std::max(1LL, std::min<long long>(lbl, ws_cap / (8 * per)));
+      ladder_batch = (int)nb;
+      // products are written with the batch letter first in the J factor: rotate letters
+      double* jb = pool.alloc((size_t)(nb * per));
+      hipEvent_t e0, e1;
+      HIPCHECK(hipEventCreate(&e0));
+      HIPCHECK(hipEventCreate(&e1));
+      HIPCHECK(hipEventRecord(e0, st));
+      for (int b0 = 0; b0 < lbl; b0 += (int)nb) {
+        int n1 = (int)std::min<long long>(nb, lbl - b0);
+        // J(P P | P P) batch with the first index in [b0, b0+n1) of the batch letter's space
+        int off1 = d.off(P0.space.at(bl)) - d.off('P') + b0;
+        double fb = gett_flops;
+        build_j('P', 'P', 'P', 'P', off1, n1, jb);
+        for (auto* P : grp.second) {
+          TProduct Q = *P;
+          for (auto& f : Q.f)
+            if (f.tensor == "J") f.letters = rotate_first(f.letters, bl, Q.space);
+          LetterRange lr = full_range(Q);
+          lr.off[bl] = b0;
+          lr.len[bl] = n1;
+          double c = 0;
+          role_now = kRoleLadder;
+          run_product(Q, lr, jb, bl, outs, nullptr, c, 0.0);
+          role_now = kRoleGeneric;
+        }
+        ladder_flops += gett_flops - fb;  // integral batch build plus the ladder products
+      }
+      HIPCHECK(hipEventRecord(e1, st));
+      HIPCHECK(hipEventSynchronize(e1));
+      float ms = 0;
+      HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
+      ladder_ms += ms;
+      (void)hipEventDestroy(e0);
+      (void)hipEventDestroy(e1);
+      pool.release(jb);
+    }
+  }
+
+  // Rewrite J(l1 l2|l3 l4) so that letter bl comes first (symmetries of real (pr|qs)).
+  static std::string rotate_first(const std::string& L0, char bl, const std::map<char, char>& sp) {
+    std::string L, key;
+    canon_j(L0, sp, L, key);
+    if (L[0] == bl) return L;
+    if (L[1] == bl) return std::string() + L[1] + L[0] + L[2] + L[3];
+    if (L[2] == bl) return std::string() + L[2] + L[3] + L[0] + L[1];
+    return std::string() + L[3] + L[2] + L[0] + L[1];
+  }
+};
+
+// ---------------------------------------------------------------------------
+// Pipeline
+// ---------------------------------------------------------------------------
+static bool finite_host(const double* p, size_t n) {
+  for (size_t i = 0; i < n; ++i)
+    if (!std::isfinite(p[i])) return false;
+  return true;
+}
+
+__global__ void count_nonfinite_kernel(const double* __restrict__ p, long long n, int* __restrict__ bad) {
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += 256LL * gridDim.x)
+    if (!isfinite(p[i])) atomicAdd(bad, 1);
+}
+
+static int run(const dsrg_problem* P, const dsrg_options* O, dsrg_result* R,
+               const dsrg_intermediates* I, bool pt3) {
+  if (!P || !R) throw Error(DSRG_E_ARG, "null problem or result");
+  const int nC = P->n_core, nA = P->n_active, nV = P->n_virtual, M = P->n_aux;
+  if (nC < 0 || nA < 0 || nV < 0) throw Error(DSRG_E_ARG, "negative orbital count");
+  if (M < 1) throw Error(DSRG_E_ARG, "n_aux must be >= 1");
+  if (nC + nA + nV < 1) throw Error(DSRG_E_ARG, "no orbitals");
+  if (!(P->s > 0.0)) throw Error(DSRG_E_ARG, "s must be > 0");
+  if (!P->eps || !P->B) throw Error(DSRG_E_ARG, "null eps or B");
+  if (nA > 0 && (!P->gamma1 || !P->gamma2)) throw Error(DSRG_E_ARG, "null gamma1/gamma2 with nA > 0");
+  if (nA > 8) throw Error(DSRG_E_UNSUPPORTED, "active spaces above 8 orbitals are not built");
+  if (O && O->precision != 0) throw Error(DSRG_E_UNSUPPORTED, "only FP64 is built");
+  const bool devptr = O && (O->flags & DSRG_F_DEVICE_PTRS);
+  const int N = nC + nA + nV, nH = nC + nA, nP = nA + nV;
+  const long long nB = (long long)M * N * N;
+  const long long g1n = 2LL * nA * nA, g2n = 3LL * nA * nA * nA * nA,
+                  g3n = 4LL * nA * nA * nA * nA * nA * nA;
+  const bool has_g3 = nA > 0 && P->gamma3;
+  if (!devptr) {
+    if (!finite_host(P->eps, N) || !finite_host(P->B, nB) ||
+        (nA > 0 && (!finite_host(P->gamma1, g1n) || !finite_host(P->gamma2, g2n))) ||
+        (has_g3 && !finite_host(P->gamma3, g3n)))
+      throw Error(DSRG_E_NONFINITE, "non-finite value in eps, B or the densities");
+  }
+  hipStream_t st = (O && O->stream) ? (hipStream_t)O->stream : (hipStream_t)0;
+  long long cap = (O && O->workspace_cap > 0) ? O->workspace_cap : (8LL << 30);
+  Dims d{nC, nA, nV};
+  Pool pool(st);
+
+  hipEvent_t ev[8];
+  for (auto& e : ev) HIPCHECK(hipEventCreate(&e));
+  struct EvGuard {
+    hipEvent_t* e;
+    ~EvGuard() { for (int i = 0; i < 8; ++i) (void)hipEventDestroy(e[i]); }
+  } evg{ev};
+  HIPCHECK(hipEventRecord(ev[0], st));
+
+  // inputs on the device
+  const double *eps, *B, *g1 = nullptr, *g2 = nullptr, *g3 = nullptr;
+  if (devptr) {
+    eps = P->eps; B = P->B; g1 = P->gamma1; g2 = P->gamma2; g3 = has_g3 ? P->gamma3 : nullptr;
+    int* bad;
+    HIPCHECK(hipMalloc(&bad, sizeof(int)));
+    HIPCHECK(hipMemsetAsync(bad, 0, sizeof(int), st));
+    auto chk = [&](const double* p, long long n) {
+      if (!p || n == 0) return;
+      long long blocks = std::min<long long>((n + 255) / 256, 4096);
+      hipLaunchKernelGGL(count_nonfinite_kernel, dim3((unsigned)blocks), dim3(256), 0, st, p, n, bad);
+    };
+    chk(eps, N); chk(B, nB);
+    if (nA > 0) { chk(g1, g1n); chk(g2, g2n); }
+    if (g3) chk(g3, g3n);
+    int hbad = 0;
+    HIPCHECK(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHECK(hipStreamSynchronize(st));
+    (void)hipFree(bad);
+    if (hbad) throw Error(DSRG_E_NONFINITE, "non-finite value in eps, B or the densities");
+  } else {
+    auto up = [&](const double* h, long long n) -> const double* {
+      double* p = pool.alloc(n);
+      HIPCHECK(hipMemcpyAsync(p, h, n * sizeof(double), hipMemcpyHostToDevice, st));
+      return p;
+    };
+    eps = up(P->eps, N);
+    B = up(P->B, nB);
+    if (nA > 0) { g1 = up(P->gamma1, g1n); g2 = up(P->gamma2, g2n); }
+    if (has_g3) g3 = up(P->gamma3, g3n);
+  }
+
+  Exec X(d, st, pool, B, M, cap, O && (O->flags & DSRG_F_PROFILE));
+  // step a0: spin-orbital densities and cumulants over the active space
+  const int n2 = 2 * nA;
+  double *G1 = nullptr, *G2 = nullptr, *G3 = nullptr, *L2 = nullptr, *L3 = nullptr, *eta = nullptr;
+  if (nA > 0) {
+    G1 = pool.alloc((size_t)n2 * n2);
+    G2 = pool.alloc((size_t)n2 * n2 * n2 * n2);
+    L2 = pool.alloc((size_t)n2 * n2 * n2 * n2);
+    eta = pool.alloc((size_t)n2 * n2);
+    L3 = pool.alloc((size_t)n2 * n2 * n2 * n2 * n2 * n2);
+    launch_expand_rdm(nA, 1, g1, G1, st);
+    launch_expand_rdm(nA, 2, g2, G2, st);
+    if (g3) {
+      G3 = pool.alloc((size_t)n2 * n2 * n2 * n2 * n2 * n2);
+      launch_expand_rdm(nA, 3, g3, G3, st);
+      launch_cumulants(nA, G1, G2, G3, L2, L3, eta, st);
+      pool.release(G3);
+    } else {
+      launch_cumulants(nA, G1, G2, nullptr, L2, nullptr, eta, st);
+      launch_fill(L3, (long long)n2 * n2 * n2 * n2 * n2 * n2, 0.0, st);
+    }
+    pool.release(G2);
+    // spin-block views of the spin-orbital arrays
+    long long s1 = 1, s2 = n2, s3 = (long long)n2 * n2, s4 = s3 * n2, s5 = s4 * n2, s6 = s5 * n2;
+    X.set_view("gA.a", G1, "AA", {s2, s1}, s3);
+    X.set_view("gA.b", G1 + nA * s2 + nA, "AA", {s2, s1}, s3 - nA * s2 - nA);
+    X.set_view("eA.a", eta, "AA", {s2, s1}, s3);
+    X.set_view("eA.b", eta + nA * s2 + nA, "AA", {s2, s1}, s3 - nA * s2 - nA);
+    std::vector<long long> st4{s4, s3, s2, s1}, st6{s6, s5, s4, s3, s2, s1};
+    auto off = [&](std::vector<int> spins, std::vector<long long>& strd) {
+      long long o = 0;
+      for (size_t k = 0; k < spins.size(); ++k) o += spins[k] * nA * strd[k];
+      return o;
+    };
+    X.set_view("L2.aa", L2 + off({0, 0, 0, 0}, st4), "AAAA", st4, s5 - off({0, 0, 0, 0}, st4));
+    X.set_view("L2.ab", L2 + off({0, 1, 0, 1}, st4), "AAAA", st4, s5 - off({0, 1, 0, 1}, st4));
+    X.set_view("L2.bb", L2 + off({1, 1, 1, 1}, st4), "AAAA", st4, s5 - off({1, 1, 1, 1}, st4));
+    X.set_view("L3.aaa", L3 + off({0, 0, 0, 0, 0, 0}, st6), "AAAAAA", st6, s6 * n2 - off({0, 0, 0, 0, 0, 0}, st6));
+    X.set_view("L3.aab", L3 + off({0, 0, 1, 0, 0, 1}, st6), "AAAAAA", st6, s6 * n2 - off({0, 0, 1, 0, 0, 1}, st6));
+    X.set_view("L3.abb", L3 + off({0, 1, 1, 0, 1, 1}, st6), "AAAAAA", st6, s6 * n2 - off({0, 1, 1, 0, 1, 1}, st6));
+    X.set_view("L3.bbb", L3 + off({1, 1, 1, 1, 1, 1}, st6), "AAAAAA", st6, s6 * n2 - off({1, 1, 1, 1, 1, 1}, st6));
+  }
+  // Coulomb blocks used by the first-order amplitudes
+  double* Jhphp = X.jblock("HPHP");
+  HIPCHECK(hipEventRecord(ev[1], st));
+
+  // step a2: first-order amplitudes, Y = [H(0), A(1)] and H~(1) (excitation blocks)
+  const size_t n4 = (size_t)nP * nP * nH * nH, n1 = (size_t)nP * nH;
+  AmpDims ad{nC, nA, nV};
+  double* T2aa = pool.alloc(n4); double* T2ab = pool.alloc(n4);
+  double* Y2aa = pool.alloc(n4); double* Y2ab = pool.alloc(n4);
+  double* E2aa = pool.alloc(n4); double* E2ab = pool.alloc(n4);
+  launch_first_order_doubles(ad, Jhphp, eps, P->s, T2aa, T2ab, Y2aa, Y2ab, E2aa, E2ab, st);
+  double* T1a = pool.alloc(n1); double* T1b = pool.alloc(n1);
+  double* Y1a = pool.alloc(n1); double* Y1b = pool.alloc(n1);
+  // gamma1 input blocks [2][nA][nA] are read directly by the singles kernel
+  const double* g1c = nA > 0 ? g1 : nullptr;
+  launch_singles(ad, T2aa, T2ab, T2aa, g1c, g1c ? g1c + nA * nA : nullptr, eps, P->s, nullptr,
+                 nullptr, T1a, T1b, Y1a, Y1b, st);
+  auto bind_first = [&]() {
+    X.set("T1.a", T1a, "PH"); X.set("T1.b", T1b, "PH");
+    X.set("T2.aa", T2aa, "PPHH"); X.set("T2.ab", T2ab, "PPHH"); X.set("T2.bb", T2aa, "PPHH");
+  };
+  auto bind_h1 = [&]() {
+    X.set("E1.a", Y1a, "PH"); X.set("E1.b", Y1b, "PH");
+    X.set("E2.aa", E2aa, "PPHH"); X.set("E2.ab", E2ab, "PPHH"); X.set("E2.bb", E2aa, "PPHH");
+  };
+  bind_first();
+  bind_h1();
+  X.set("Y1.a", Y1a, "PH"); X.set("Y1.b", Y1b, "PH");
+  X.set("Y2.aa", Y2aa, "PPHH"); X.set("Y2.ab", Y2ab, "PPHH"); X.set("Y2.bb", Y2aa, "PPHH");
+  HIPCHECK(hipEventRecord(ev[2], st));
+
+  auto& T = table();
+  const Use& C0 = T.at("C0");
+  size_t nslot = C0.size();
+  double* vals = pool.alloc(nslot + 4);
+  double* coefd = pool.alloc(nslot);
+  double* energies = pool.alloc(4);
+  launch_fill(energies, 4, 0.0, st);
+  std::vector<double> coefs;
+  std::map<std::string, TensorRef> none;
+  auto scalar = [&](double* outp) {
+    coefs.clear();
+    launch_fill(vals, (long long)nslot, 0.0, st);
+    X.run_use(C0, none, vals, coefs);
+    HIPCHECK(hipMemcpyAsync(coefd, coefs.data(), coefs.size() * 8, hipMemcpyHostToDevice, st));
+    HIPCHECK(hipStreamSynchronize(st));   // coefs is a host buffer reused below
+    launch_weighted_sum((int)coefs.size(), vals, coefd, outp, st);
+  };
+  // step a3: E(2) = <[H~(1), T(1)]>
+  scalar(energies + 0);
+  HIPCHECK(hipEventRecord(ev[3], st));
+
+  double* W1a = nullptr;
+  if (pt3) {
+    // steps a4-a5: W = [V, A(1)]_{1,2}, excitation block
+    W1a = pool.alloc(2 * n1);
+    double* W2 = pool.alloc(3 * n4);
+    launch_fill(W1a, 2 * n1, 0.0, st);
+    launch_fill(W2, 3 * n4, 0.0, st);
+    std::map<std::string, TensorRef> wout;
+    auto bind_out = [&](std::map<std::string, TensorRef>& o, double* p1, double* p2) {
+      auto mk = [&](double* p, const char* ax) {
+        TensorRef t{p, ax, {}};
+        int r = (int)strlen(ax);
+        t.stride.assign(r, 1);
+        for (int k = r - 2; k >= 0; --k) t.stride[k] = t.stride[k + 1] * d.len(ax[k + 1]);
+        t.lim = t.stride[0] * d.len(ax[0]);
+        return t;
+      };
+      o["O1.a"] = mk(p1, "PH"); o["O1.b"] = mk(p1 + n1, "PH");
+      o["O2.aa"] = mk(p2, "PPHH"); o["O2.ab"] = mk(p2 + n4, "PPHH"); o["O2.bb"] = mk(p2 + 2 * n4, "PPHH");
+    };
+    bind_out(wout, W1a, W2);
+    std::vector<double> dummy;
+    X.run_use(T.at("W"), wout, nullptr, dummy);
+    HIPCHECK(hipEventRecord(ev[4], st));
+    // step a6: Z = [Y, A(1)]_{1,2}
+    double* Z1 = pool.alloc(2 * n1);
+    double* Z2 = pool.alloc(3 * n4);
+    launch_fill(Z1, 2 * n1, 0.0, st);
+    launch_fill(Z2, 3 * n4, 0.0, st);
+    std::map<std::string, TensorRef> zout;
+    bind_out(zout, Z1, Z2);
+    X.run_use(T.at("Z"), zout, nullptr, dummy);
+    HIPCHECK(hipEventRecord(ev[5], st));
+    // second-order amplitudes and H~(2)_{1,2}
+    double* U2 = pool.alloc(3 * n4);
+    double* H2 = pool.alloc(3 * n4);
+    for (int b = 0; b < 3; ++b)
+      launch_second_order_doubles(ad, W2 + b * n4, Z2 + b * n4, eps, P->s, U2 + b * n4, H2 + b * n4, st);
+    double* f2 = pool.alloc(2 * n1);
+    launch_combine_f2((int)(2 * n1), W1a, Z1, f2, st);
+    double* U1 = pool.alloc(2 * n1);
+    double* S2 = pool.alloc(2 * n1);
+    launch_singles(ad, U2, U2 + n4, U2 + 2 * n4, g1c, g1c ? g1c + nA * nA : nullptr, eps, P->s, f2,
+                   f2 + n1, U1, U1 + n1, S2, S2 + n1, st);
+    double* H1 = pool.alloc(2 * n1);
+    for (int sidx = 0; sidx < 2; ++sidx)
+      launch_second_order_h1(ad, W1a + sidx * n1, Z1 + sidx * n1, S2 + sidx * n1, H1 + sidx * n1, st);
+    // E(3)_a = <[H~(1), T(2)]>
+    X.set("T1.a", U1, "PH"); X.set("T1.b", U1 + n1, "PH");
+    X.set("T2.aa", U2, "PPHH"); X.set("T2.ab", U2 + n4, "PPHH"); X.set("T2.bb", U2 + 2 * n4, "PPHH");
+    scalar(energies + 1);
+    // E(3)_b = <[H~(2)_{1,2}, T(1)]>
+    bind_first();
+    X.set("E1.a", H1, "PH"); X.set("E1.b", H1 + n1, "PH");
+    X.set("E2.aa", H2, "PPHH"); X.set("E2.ab", H2 + n4, "PPHH"); X.set("E2.bb", H2 + 2 * n4, "PPHH");
+    scalar(energies + 2);
+    HIPCHECK(hipEventRecord(ev[6], st));
+    if (I) {
+      auto cp = [&](double* h, const double* dptr, size_t n) {
+        if (h) HIPCHECK(hipMemcpyAsync(h, dptr, n * 8, hipMemcpyDeviceToHost, st));
+      };
+      cp(I->w1, W1a, 2 * n1); cp(I->w2, W2, 3 * n4);
+      cp(I->z1, Z1, 2 * n1); cp(I->z2, Z2, 3 * n4);
+      cp(I->u1, U1, 2 * n1); cp(I->u2, U2, 3 * n4);
+    }
+  } else {
+    for (int k = 4; k < 7; ++k) HIPCHECK(hipEventRecord(ev[k], st));
+  }
+  if (I) {
+    if (I->t1) {
+      HIPCHECK(hipMemcpyAsync(I->t1, T1a, n1 * 8, hipMemcpyDeviceToHost, st));
+      HIPCHECK(hipMemcpyAsync(I->t1 + n1, T1b, n1 * 8, hipMemcpyDeviceToHost, st));
+    }
+    if (I->t2) {
+      HIPCHECK(hipMemcpyAsync(I->t2, T2aa, n4 * 8, hipMemcpyDeviceToHost, st));
+      HIPCHECK(hipMemcpyAsync(I->t2 + n4, T2ab, n4 * 8, hipMemcpyDeviceToHost, st));
+      HIPCHECK(hipMemcpyAsync(I->t2 + 2 * n4, T2aa, n4 * 8, hipMemcpyDeviceToHost, st));
+    }
+  }
+  HIPCHECK(hipEventRecord(ev[7], st));
+  double e[4] = {0, 0, 0, 0};
+  HIPCHECK(hipMemcpyAsync(e, energies, 4 * 8, hipMemcpyDeviceToHost, st));
+  HIPCHECK(hipStreamSynchronize(st));
+  HIPCHECK(hipGetLastError());
+  dsrg_result r;
+  memset(&r, 0, sizeof(r));
+  r.e2 = e[0];
+  r.e3_a = pt3 ? e[1] : 0.0;
+  r.e3_b = pt3 ? e[2] : 0.0;
+  r.e3 = r.e3_a + r.e3_b;
+  float ms;
+  for (int k = 0; k < 6; ++k) {
+    HIPCHECK(hipEventElapsedTime(&ms, ev[k], ev[k + 1]));
+    r.t_seconds[k] = ms * 1e-3;
+  }
+  HIPCHECK(hipEventElapsedTime(&ms, ev[0], ev[7]));
+  r.t_seconds[7] = ms * 1e-3;
+  if (X.profile) X.collect_profile();
+  for (int k = 0; k < 3; ++k) {
+    r.role_seconds[k] = X.role_sec[k];
+    r.role_flops[k] = X.role_flops[k];
+    r.role_launches[k] = X.role_n[k];
+  }
+  r.gett_flops = X.gett_flops;
+  r.ladder_flops = X.ladder_flops;
+  r.ladder_seconds = X.ladder_ms * 1e-3;
+  r.ladder_batch = X.ladder_batch;
+  r.n_launch = X.n_launch;
+  *R = r;
+  return DSRG_OK;
+}
+
+template <class F>
+static int guarded(F&& f) {
+  try {
+    int rc = f();
+    g_last_error.clear();
+    return rc;
+  } catch (const Error& e) {
+    g_last_error = e.what();
+    return e.code;
+  } catch (const std::exception& e) {
+    g_last_error = e.what();
+    return DSRG_E_HIP;
+  }
+}
+
+}  // namespace dsrg
+
+extern "C" {
+
+int dsrg_pt2_energy(const dsrg_problem* prob, const dsrg_options* opt, dsrg_result* out) {
+  return dsrg::guarded([&] { return dsrg::run(prob, opt, out, nullptr, false); });
+}
+
+int dsrg_pt3_energy(const dsrg_problem* prob, const dsrg_options* opt, dsrg_result* out) {
+  return dsrg::guarded([&] { return dsrg::run(prob, opt, out, nullptr, true); });
+}
+
+int dsrg_pt3_energy_ex(const dsrg_problem* prob, const dsrg_options* opt, dsrg_result* out,
+                       const dsrg_intermediates* inter) {
+  return dsrg::guarded([&] { return dsrg::run(prob, opt, out, inter, true); });
+}
+
+const char* dsrg_last_error(void) { return dsrg::g_last_error.c_str(); }
+
+int dsrg_version(void) { return 100; }
+
+}  // extern "C"
+
+extern "C" int dsrg_test_gett(int nm, const int* md, const long long* am, const long long* cm,
+                              int nn, const int* nd, const long long* bn, const long long* cn,
+                              int nk, const int* kd, const long long* ak, const long long* bk,
+                              const double* A, long long na, const double* B, long long nb,
+                              double* C, long long nc, double alpha, int beta) {
+  using namespace dsrg;
+  return guarded([&] {
+    if (nm < 0 || nn < 0 || nk < 0 || nm > kMaxComp || nn > kMaxComp || nk > kMaxComp)
+      throw Error(DSRG_E_ARG, "component count out of range");
+    if (!A || !B || !C || na <= 0 || nb <= 0 || nc <= 0) throw Error(DSRG_E_ARG, "null or empty array");
+    GettDesc g;
+    g.nm = nm; g.nn = nn; g.nk = nk;
+    long long M = 1, N = 1, K = 1, amax = 0, bmax = 0, cmax = 0;
+    for (int i = 0; i < nm; ++i) {
+      if (md[i] < 1) throw Error(DSRG_E_ARG, "extent < 1");
+      g.md[i] = md[i]; g.am[i] = am[i]; g.cm[i] = cm[i]; M *= md[i];
+      amax += (md[i] - 1) * std::abs(am[i]); cmax += (md[i] - 1) * std::abs(cm[i]);
+    }
+    for (int i = 0; i < nn; ++i) {
+      if (nd[i] < 1) throw Error(DSRG_E_ARG, "extent < 1");
+      g.nd[i] = nd[i]; g.bn[i] = bn[i]; g.cn[i] = cn[i]; N *= nd[i];
+      bmax += (nd[i] - 1) * std::abs(bn[i]); cmax += (nd[i] - 1) * std::abs(cn[i]);
+    }
+    for (int i = 0; i < nk; ++i) {
+      if (kd[i] < 1) throw Error(DSRG_E_ARG, "extent < 1");
+      g.kd[i] = kd[i]; g.ak[i] = ak[i]; g.bk[i] = bk[i]; K *= kd[i];
+      amax += (kd[i] - 1) * std::abs(ak[i]); bmax += (kd[i] - 1) * std::abs(bk[i]);
+    }
+    for (int i = 0; i < nm; ++i) if (am[i] < 0 || cm[i] < 0) throw Error(DSRG_E_ARG, "negative stride");
+    for (int i = 0; i < nn; ++i) if (bn[i] < 0 || cn[i] < 0) throw Error(DSRG_E_ARG, "negative stride");
+    for (int i = 0; i < nk; ++i) if (ak[i] < 0 || bk[i] < 0) throw Error(DSRG_E_ARG, "negative stride");
+    if (amax >= na || bmax >= nb || cmax >= nc) throw Error(DSRG_E_ARG, "strides address past the arrays");
+    if (M >= (1LL << 31) || N >= (1LL << 31) || K >= (1LL << 31)) throw Error(DSRG_E_ARG, "too large");
+    g.M = (int)M; g.N = (int)N; g.K = (int)K;
+    Exec::set_load_order(g);
+    g.alpha = alpha; g.beta = beta ? 1 : 0;
+    double *dA, *dB, *dC;
+    HIPCHECK(hipMalloc(&dA, na * 8));
+    HIPCHECK(hipMalloc(&dB, nb * 8));
+    HIPCHECK(hipMalloc(&dC, nc * 8));
+    HIPCHECK(hipMemcpy(dA, A, na * 8, hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(dB, B, nb * 8, hipMemcpyHostToDevice));
+    HIPCHECK(hipMemcpy(dC, C, nc * 8, hipMemcpyHostToDevice));
+    launch_gett(g, dA, dB, dC, 0);
+    HIPCHECK(hipGetLastError());
+    HIPCHECK(hipMemcpy(C, dC, nc * 8, hipMemcpyDeviceToHost));
+    (void)hipFree(dA); (void)hipFree(dB); (void)hipFree(dC);
+    return DSRG_OK;
+  });
+}

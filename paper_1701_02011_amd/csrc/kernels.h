@@ -1,0 +1,88 @@
+// Device kernels of the DSRG-MRPT3 hot path (gfx950).  Internal interface between the
+// executor (dsrg.hip) and the kernels (kernels.hip); not part of the C ABI.
+#pragma once
+#include <hip/hip_runtime.h>
+#include <cstdint>
+
+namespace dsrg {
+
+constexpr int kMaxComp = 6;   // index components per group (M, N or K)
+
+// A strided tensor contraction C[m][n] (+)= alpha * sum_k A[m][k] B[k][n], where m, n and
+// k are multi-indices (row-major composition of up to kMaxComp components) and every
+// operand addresses its elements through its own per-component strides.
+struct GettDesc {
+  int M = 1, N = 1, K = 1;
+  int nm = 0, nn = 0, nk = 0;
+  int md[kMaxComp] = {}, nd[kMaxComp] = {}, kd[kMaxComp] = {};
+  long long am[kMaxComp] = {}, ak[kMaxComp] = {};
+  long long bk[kMaxComp] = {}, bn[kMaxComp] = {};
+  long long cm[kMaxComp] = {}, cn[kMaxComp] = {};
+  double alpha = 1.0;
+  int beta = 0;        // 0: C = alpha AB, 1: C += alpha AB
+  int a_kfast = 1;     // A tile loads walk k fastest (else m fastest)
+  int b_kfast = 0;     // B tile loads walk k fastest (else n fastest)
+};
+
+// sum_k A[k] B[k] over a strided multi-index k (deterministic two-pass reduction).
+struct DotDesc {
+  long long K = 0;
+  int nk = 0;
+  int kd[2 * kMaxComp] = {};
+  long long as[2 * kMaxComp] = {}, bs[2 * kMaxComp] = {};
+};
+
+// out[o] += coef * src[s] over a strided multi-index (rank <= 6).
+struct ScatterDesc {
+  long long n = 0;
+  int rank = 0;
+  int d[kMaxComp] = {};
+  long long ss[kMaxComp] = {}, so[kMaxComp] = {};
+  double coef = 1.0;
+};
+
+// Launch roles (same kernel, distinct symbols): contraction-table products, the (PP|PP)
+// particle-particle ladder products, and Coulomb-block builds from the DF tensor.
+constexpr int kRoleGeneric = 0, kRoleLadder = 1, kRoleIntegrals = 2;
+void launch_gett(const GettDesc& g, const double* A, const double* B, double* C, hipStream_t st,
+                 int role = kRoleGeneric);
+// partial: scratch of at least dot_partials() doubles; writes the sum into out[0]
+int dot_partials();
+void launch_dot(const DotDesc& d, const double* A, const double* B, double* partial, double* out,
+                hipStream_t st);
+void launch_scatter(const ScatterDesc& d, const double* src, double* out, hipStream_t st);
+
+// Spin-orbital active densities [2nA]^k from the spin-block inputs, and cumulants.
+void launch_expand_rdm(int nA, int rank, const double* blocks, double* so, hipStream_t st);
+void launch_cumulants(int nA, const double* G1, const double* G2, const double* G3, double* L2,
+                      double* L3, double* eta, hipStream_t st);
+
+// First-order doubles from the Coulomb block J(HP|HP)[i][a][j][b] = (ai|bj):
+// t = v R_s(D), Y = -D t, E = 2 v + Y (E = 2 v on internal elements), blocks aa (=bb) and ab.
+struct AmpDims {
+  int nC, nA, nV;
+};
+void launch_first_order_doubles(AmpDims d, const double* Jhphp, const double* eps, double s,
+                                double* T2aa, double* T2ab, double* Y2aa, double* Y2ab,
+                                double* E2aa, double* E2ab, hipStream_t st);
+// Singles: coup_s[a,i] = sum_{ux} (e_x - e_u) (t_ss[a,x,i,u] g_s[x,u] + t_{s s'}..[..] g_s'[x,u]);
+// t1 = (f + coup) R_s(D), and the non-diagonal one-body source (f + coup) exp(-s D^2).
+// f may be null (zero).  For a null g1 (nA = 0) coup = 0.
+void launch_singles(AmpDims d, const double* T2aa, const double* T2ab, const double* T2bb,
+                    const double* g1a, const double* g1b, const double* eps, double s,
+                    const double* fa, const double* fb, double* t1a, double* t1b, double* srca,
+                    double* srcb, hipStream_t st);
+// Second-order doubles and the H~(2) two-body excitation block:
+// O = 2 W + Z; u = (O/2) R_s(D) (0 on internal), H = (O/2) exp(-s D^2) - Z/6 (O/2 - Z/6 internal).
+void launch_second_order_doubles(AmpDims d, const double* W, const double* Z, const double* eps,
+                                 double s, double* U, double* H, hipStream_t st);
+// One-body counterpart: f2 = (2 W1 + Z1)/2; H1 = src - Z1/6 (f2 - Z1/6 on internal elements),
+// where src = (f2 + coup2) exp(-s D^2) comes from launch_singles.
+void launch_second_order_h1(AmpDims d, const double* W1, const double* Z1, const double* src,
+                            double* H1, hipStream_t st);
+void launch_combine_f2(int n, const double* W1, const double* Z1, double* f2, hipStream_t st);
+// out = sum_i coef[i] * vals[i] (fixed order)
+void launch_weighted_sum(int n, const double* vals, const double* coef, double* out, hipStream_t st);
+void launch_fill(double* p, long long n, double v, hipStream_t st);
+
+}  // namespace dsrg

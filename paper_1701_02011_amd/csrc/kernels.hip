@@ -1,0 +1,519 @@
+// Device kernels of the DSRG-MRPT3 hot path for CDNA4 (gfx950), FP64.
+#include "kernels.h"
+
+#include <cmath>
+#include <cstdio>
+
+namespace dsrg {
+
+typedef double double4_t __attribute__((ext_vector_type(4)));
+
+// ---------------------------------------------------------------------------
+// Strided multi-index helpers
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ long long decode(int idx, int n, const int* d, const long long* s) {
+  long long off = 0;
+#pragma unroll
+  for (int c = kMaxComp - 1; c >= 0; --c) {
+    if (c < n) {
+      int q = idx / d[c];
+      int r = idx - q * d[c];
+      off += (long long)r * s[c];
+      idx = q;
+    }
+  }
+  return off;
+}
+
+// ---------------------------------------------------------------------------
+// GETT: 64x64 output tile per workgroup of 256 threads (4 waves, 2x2), each wave a
+// 32x32 sub-tile made of 2x2 v_mfma_f64_16x16x4 tiles; K staged through LDS in steps
+// of 16.  Operand layout of the 16x16x4 FP64 MFMA (checked on gfx950 by the kernel unit
+// tests): lane l holds A[l%16][l/16] and B[l/16][l%16]; accumulator element r of lane l
+// is D[l/16 + 4 r][l%16].
+// ---------------------------------------------------------------------------
+constexpr int BM = 64, BN = 64, BK = 16;
+constexpr int LDA = BM + 1, LDB = BN + 1;
+
+template <int kRole>
+__global__ __launch_bounds__(256) void gett_f64_kernel(GettDesc g, const double* __restrict__ A,
+                                                       const double* __restrict__ B,
+                                                       double* __restrict__ C) {
+  __shared__ double As[BK * LDA];
+  __shared__ double Bs[BK * LDB];
+  const int tid = threadIdx.x;
+  const int lane = tid & 63;
+  const int wave = tid >> 6;
+  const int tile_m = blockIdx.x * BM;
+  const int tile_n = blockIdx.y * BN;
+
+  // fixed per-thread load slots: 4 elements of each tile
+  long long aoff_m[4], boff_n[4];
+  int a_mm[4], a_kk[4], b_nn[4], b_kk[4];
+  bool a_ok[4], b_ok[4];
+#pragma unroll
+  for (int i = 0; i < 4; ++i) {
+    int e = tid + 256 * i;
+    if (g.a_kfast) { a_kk[i] = e % BK; a_mm[i] = e / BK; }
+    else           { a_mm[i] = e % BM; a_kk[i] = e / BM; }
+    if (g.b_kfast) { b_kk[i] = e % BK; b_nn[i] = e / BK; }
+    else           { b_nn[i] = e % BN; b_kk[i] = e / BN; }
+    int m = tile_m + a_mm[i];
+    int n = tile_n + b_nn[i];
+    a_ok[i] = m < g.M;
+    b_ok[i] = n < g.N;
+    aoff_m[i] = a_ok[i] ? decode(m, g.nm, g.md, g.am) : 0;
+    boff_n[i] = b_ok[i] ? decode(n, g.nn, g.nd, g.bn) : 0;
+  }
+
+  double4_t acc[2][2];
+#pragma unroll
+  for (int a = 0; a < 2; ++a)
+#pragma unroll
+    for (int b = 0; b < 2; ++b) acc[a][b] = (double4_t){0.0, 0.0, 0.0, 0.0};
+
+  const int wm = (wave & 1) * 32;
+  const int wn = (wave >> 1) * 32;
+  const int li = lane & 15;
+  const int lk = lane >> 4;
+
+  for (int k0 = 0; k0 < g.K; k0 += BK) {
+#pragma unroll
+    for (int i = 0; i < 4; ++i) {
+      int k = k0 + a_kk[i];
+      double v = 0.0;
+      if (a_ok[i] && k < g.K) v = A[aoff_m[i] + decode(k, g.nk, g.kd, g.ak)];
+      As[a_kk[i] * LDA + a_mm[i]] = v;
+      int kb = k0 + b_kk[i];
+      double w = 0.0;
+      if (b_ok[i] && kb < g.K) w = B[boff_n[i] + decode(kb, g.nk, g.kd, g.bk)];
+      Bs[b_kk[i] * LDB + b_nn[i]] = w;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < BK; kk += 4) {
+      double av[2], bv[2];
+#pragma unroll
+      for (int t = 0; t < 2; ++t) {
+        av[t] = As[(kk + lk) * LDA + wm + t * 16 + li];
+        bv[t] = Bs[(kk + lk) * LDB + wn + t * 16 + li];
+      }
+#pragma unroll
+      for (int a = 0; a < 2; ++a)
+#pragma unroll
+        for (int b = 0; b < 2; ++b)
+          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+    }
+    __syncthreads();
+  }
+
+#pragma unroll
+  for (int a = 0; a < 2; ++a) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+      int m = tile_m + wm + a * 16 + lk + 4 * r;
+      if (m >= g.M) continue;
+      long long cmo = decode(m, g.nm, g.md, g.cm);
+#pragma unroll
+      for (int b = 0; b < 2; ++b) {
+        int n = tile_n + wn + b * 16 + li;
+        if (n >= g.N) continue;
+        long long o = cmo + decode(n, g.nn, g.nd, g.cn);
+        double v = g.alpha * acc[a][b][r];
+        if (g.beta) v += C[o];
+        C[o] = v;
+      }
+    }
+  }
+}
+
+void launch_gett(const GettDesc& g, const double* A, const double* B, double* C, hipStream_t st,
+                 int role) {
+  if (g.M <= 0 || g.N <= 0) return;
+  dim3 grid((g.M + BM - 1) / BM, (g.N + BN - 1) / BN);
+  // the role only selects a distinct kernel symbol so profiles can tell the launches apart
+  if (role == kRoleLadder)
+    hipLaunchKernelGGL(gett_f64_kernel<kRoleLadder>, grid, dim3(256), 0, st, g, A, B, C);
+  else if (role == kRoleIntegrals)
+    hipLaunchKernelGGL(gett_f64_kernel<kRoleIntegrals>, grid, dim3(256), 0, st, g, A, B, C);
+  else
+    hipLaunchKernelGGL(gett_f64_kernel<kRoleGeneric>, grid, dim3(256), 0, st, g, A, B, C);
+}
+
+// ---------------------------------------------------------------------------
+// Deterministic dot product over a strided multi-index
+// ---------------------------------------------------------------------------
+constexpr int kDotBlocks = 512;
+int dot_partials() { return kDotBlocks; }
+
+__device__ __forceinline__ void decode2(long long idx, int n, const int* d, const long long* sa,
+                                        const long long* sb, long long& oa, long long& ob) {
+  oa = 0;
+  ob = 0;
+  for (int c = n - 1; c >= 0; --c) {
+    long long q = idx / d[c];
+    long long r = idx - q * d[c];
+    oa += r * sa[c];
+    ob += r * sb[c];
+    idx = q;
+  }
+}
+
+__global__ __launch_bounds__(256) void dot_kernel(DotDesc d, const double* __restrict__ A,
+                                                  const double* __restrict__ B,
+                                                  double* __restrict__ partial) {
+  __shared__ double red[256];
+  double sum = 0.0;
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < d.K; i += 256LL * gridDim.x) {
+    long long oa, ob;
+    decode2(i, d.nk, d.kd, d.as, d.bs, oa, ob);
+    sum += A[oa] * B[ob];
+  }
+  red[threadIdx.x] = sum;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[blockIdx.x] = red[0];
+}
+
+__global__ __launch_bounds__(256) void sum_partials_kernel(const double* __restrict__ partial, int n,
+                                                           double* __restrict__ out) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) s += partial[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[0] = red[0];
+}
+
+void launch_dot(const DotDesc& d, const double* A, const double* B, double* partial, double* out,
+                hipStream_t st) {
+  hipLaunchKernelGGL(dot_kernel, dim3(kDotBlocks), dim3(256), 0, st, d, A, B, partial);
+  hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, st, partial, kDotBlocks, out);
+}
+
+// ---------------------------------------------------------------------------
+// Scatter-add with permutation
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void scatter_kernel(ScatterDesc d, const double* __restrict__ src,
+                                                      double* __restrict__ out) {
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < d.n; i += 256LL * gridDim.x) {
+    long long os, oo;
+    decode2(i, d.rank, d.d, d.ss, d.so, os, oo);
+    out[oo] += d.coef * src[os];
+  }
+}
+
+void launch_scatter(const ScatterDesc& d, const double* src, double* out, hipStream_t st) {
+  if (d.n <= 0) return;
+  long long blocks = (d.n + 255) / 256;
+  if (blocks > 8192) blocks = 8192;
+  hipLaunchKernelGGL(scatter_kernel, dim3((unsigned)blocks), dim3(256), 0, st, d, src, out);
+}
+
+// ---------------------------------------------------------------------------
+// Reference densities: spin blocks -> spin-orbital tensors over the 2 nA active spin
+// orbitals [alpha | beta]; other spin patterns follow from the canonical (alpha-first)
+// block by permuting upper and lower indices with the parity sign.
+// ---------------------------------------------------------------------------
+__global__ void expand_rdm_kernel(int nA, int rank, const double* __restrict__ blocks,
+                                  double* __restrict__ so, long long total) {
+  long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (i >= total) return;
+  const int n2 = 2 * nA;
+  int idx[6];
+  long long t = i;
+  for (int c = 2 * rank - 1; c >= 0; --c) {
+    idx[c] = (int)(t % n2);
+    t /= n2;
+  }
+  int spin[6], sp[6];
+  int nbu = 0, nbl = 0;
+  for (int c = 0; c < 2 * rank; ++c) {
+    spin[c] = idx[c] >= nA;
+    sp[c] = idx[c] - spin[c] * nA;
+  }
+  for (int c = 0; c < rank; ++c) { nbu += spin[c]; nbl += spin[rank + c]; }
+  if (nbu != nbl) { so[i] = 0.0; return; }
+  // stable sort of upper and lower slots by spin; parity of each permutation
+  int pu[3], pl[3], k = 0, par = 0;
+  for (int s = 0; s < 2; ++s)
+    for (int c = 0; c < rank; ++c)
+      if (spin[c] == s) pu[k++] = c;
+  k = 0;
+  for (int s = 0; s < 2; ++s)
+    for (int c = 0; c < rank; ++c)
+      if (spin[rank + c] == s) pl[k++] = c;
+  for (int a = 0; a < rank; ++a)
+    for (int b = a + 1; b < rank; ++b) {
+      par += pu[a] > pu[b];
+      par += pl[a] > pl[b];
+    }
+  long long bsz = 1;
+  for (int c = 0; c < 2 * rank; ++c) bsz *= nA;
+  long long off = 0;
+  for (int c = 0; c < rank; ++c) off = off * nA + sp[pu[c]];
+  for (int c = 0; c < rank; ++c) off = off * nA + sp[rank + pl[c]];
+  double v = blocks[nbu * bsz + off];
+  so[i] = (par & 1) ? -v : v;
+}
+
+void launch_expand_rdm(int nA, int rank, const double* blocks, double* so, hipStream_t st) {
+  long long total = 1;
+  for (int c = 0; c < 2 * rank; ++c) total *= 2 * nA;
+  if (total == 0) return;
+  hipLaunchKernelGGL(expand_rdm_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, nA,
+                     rank, blocks, so, total);
+}
+
+// lambda2[p,q,r,s] = G2 - (g_pr g_qs - g_ps g_qr);  C-convention over spin orbitals.
+__global__ void cumulant2_kernel(int n, const double* __restrict__ G1, const double* __restrict__ G2,
+                                 double* __restrict__ L2) {
+  long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  long long total = (long long)n * n * n * n;
+  if (i >= total) return;
+  int s = i % n, r = (i / n) % n, q = (i / n / n) % n, p = i / n / n / n;
+  L2[i] = G2[i] - (G1[p * n + r] * G1[q * n + s] - G1[p * n + s] * G1[q * n + r]);
+}
+
+// lambda3 = G3 - det(g g g) - sum_{ij} (-1)^(i+j) g[P_i, S_j] lambda2[P\i, S\j]
+__global__ void cumulant3_kernel(int n, const double* __restrict__ G1, const double* __restrict__ L2,
+                                 const double* __restrict__ G3, double* __restrict__ L3) {
+  long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  long long total = (long long)n * n * n * n * n * n;
+  if (i >= total) return;
+  int idx[6];
+  long long t = i;
+  for (int c = 5; c >= 0; --c) { idx[c] = (int)(t % n); t /= n; }
+  const int* P = idx;
+  const int* S = idx + 3;
+  auto g = [&](int a, int b) { return G1[a * n + b]; };
+  // determinant part
+  double det = g(P[0], S[0]) * (g(P[1], S[1]) * g(P[2], S[2]) - g(P[1], S[2]) * g(P[2], S[1]))
+             - g(P[0], S[1]) * (g(P[1], S[0]) * g(P[2], S[2]) - g(P[1], S[2]) * g(P[2], S[0]))
+             + g(P[0], S[2]) * (g(P[1], S[0]) * g(P[2], S[1]) - g(P[1], S[1]) * g(P[2], S[0]));
+  double gl = 0.0;
+  for (int a = 0; a < 3; ++a) {
+    int u0 = P[(a + 1) % 3 < (a + 2) % 3 ? (a + 1) % 3 : (a + 2) % 3];
+    int u1 = P[(a + 1) % 3 < (a + 2) % 3 ? (a + 2) % 3 : (a + 1) % 3];
+    for (int b = 0; b < 3; ++b) {
+      int l0 = S[(b + 1) % 3 < (b + 2) % 3 ? (b + 1) % 3 : (b + 2) % 3];
+      int l1 = S[(b + 1) % 3 < (b + 2) % 3 ? (b + 2) % 3 : (b + 1) % 3];
+      double sgn = ((a + b) & 1) ? -1.0 : 1.0;
+      gl += sgn * g(P[a], S[b]) * L2[((long long)(u0 * n + u1) * n + l0) * n + l1];
+    }
+  }
+  L3[i] = G3[i] - det - gl;
+}
+
+__global__ void eta_kernel(int n, const double* __restrict__ G1, double* __restrict__ eta) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n * n) return;
+  eta[i] = ((i / n) == (i % n) ? 1.0 : 0.0) - G1[i];
+}
+
+void launch_cumulants(int nA, const double* G1, const double* G2, const double* G3, double* L2,
+                      double* L3, double* eta, hipStream_t st) {
+  int n = 2 * nA;
+  if (n == 0) return;
+  long long t2 = (long long)n * n * n * n;
+  hipLaunchKernelGGL(cumulant2_kernel, dim3((unsigned)((t2 + 255) / 256)), dim3(256), 0, st, n, G1,
+                     G2, L2);
+  if (G3 && L3) {
+    long long t3 = t2 * n * n;
+    hipLaunchKernelGGL(cumulant3_kernel, dim3((unsigned)((t3 + 255) / 256)), dim3(256), 0, st, n, G1,
+                       L2, G3, L3);
+  }
+  hipLaunchKernelGGL(eta_kernel, dim3((n * n + 255) / 256), dim3(256), 0, st, n, G1, eta);
+}
+
+// ---------------------------------------------------------------------------
+// Regulariser and source factor (FP64 throughout)
+// R_s(D) = (1 - exp(-s D^2)) / D, evaluated as -expm1(-s D^2) / D; R_s(0) = 0.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ double regulariser(double s, double D) {
+  if (D == 0.0) return 0.0;
+  if (isinf(s)) return 1.0 / D;
+  return -expm1(-s * D * D) / D;
+}
+__device__ __forceinline__ double source_factor(double s, double D) {
+  if (isinf(s)) return D == 0.0 ? 1.0 : 0.0;
+  return exp(-s * D * D);
+}
+
+__global__ void first_order_doubles_kernel(AmpDims d, const double* __restrict__ J,
+                                           const double* __restrict__ eps, double s,
+                                           double* __restrict__ Taa, double* __restrict__ Tab,
+                                           double* __restrict__ Yaa, double* __restrict__ Yab,
+                                           double* __restrict__ Eaa, double* __restrict__ Eab) {
+  const int nH = d.nC + d.nA, nP = d.nA + d.nV;
+  long long total = (long long)nP * nP * nH * nH;
+  long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  int j = idx % nH, i = (idx / nH) % nH, b = (idx / nH / nH) % nP, a = idx / nH / nH / nP;
+  // J(HP|HP)[i][a][j][b] = (ia|jb) = (ai|bj)
+  double vab = J[(((long long)i * nP + a) * nH + j) * nP + b];
+  double vx = J[(((long long)j * nP + a) * nH + i) * nP + b];  // (aj|bi)
+  double vaa = vab - vx;
+  bool internal = a < d.nA && b < d.nA && i >= d.nC && j >= d.nC;
+  double D = eps[i] + eps[j] - eps[d.nC + a] - eps[d.nC + b];
+  double R = regulariser(s, D);
+  double tab = internal ? 0.0 : vab * R, taa = internal ? 0.0 : vaa * R;
+  Tab[idx] = tab;
+  Taa[idx] = taa;
+  Yab[idx] = -D * tab;
+  Yaa[idx] = -D * taa;
+  Eab[idx] = 2.0 * vab - D * tab;
+  Eaa[idx] = 2.0 * vaa - D * taa;
+}
+
+void launch_first_order_doubles(AmpDims d, const double* J, const double* eps, double s,
+                                double* T2aa, double* T2ab, double* Y2aa, double* Y2ab,
+                                double* E2aa, double* E2ab, hipStream_t st) {
+  long long nH = d.nC + d.nA, nP = d.nA + d.nV;
+  long long total = nP * nP * nH * nH;
+  if (total == 0) return;
+  hipLaunchKernelGGL(first_order_doubles_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0,
+                     st, d, J, eps, s, T2aa, T2ab, Y2aa, Y2ab, E2aa, E2ab);
+}
+
+// coup_a[a,i] = sum_ux (e_x - e_u)(t_aa[a,x,i,u] g_a[x,u] + t_ab[a,x,i,u] g_b[x,u])
+// coup_b[a,i] = sum_ux (e_x - e_u)(t_bb[a,x,i,u] g_b[x,u] + t_ab[x,a,u,i] g_a[x,u])
+__global__ void singles_kernel(AmpDims d, const double* __restrict__ Taa, const double* __restrict__ Tab,
+                               const double* __restrict__ Tbb, const double* __restrict__ ga,
+                               const double* __restrict__ gb, const double* __restrict__ eps, double s,
+                               const double* __restrict__ fa, const double* __restrict__ fb,
+                               double* __restrict__ t1a, double* __restrict__ t1b,
+                               double* __restrict__ srca, double* __restrict__ srcb) {
+  const int nH = d.nC + d.nA, nP = d.nA + d.nV, nA = d.nA, nC = d.nC;
+  int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= 2 * nP * nH) return;
+  int spin = idx / (nP * nH);
+  int e = idx - spin * nP * nH;
+  int a = e / nH, i = e % nH;
+  double c = 0.0;
+  const long long sH = 1, sH2 = nH, sP = (long long)nH * nH, sP2 = (long long)nP * nH * nH;
+  for (int u = 0; u < nA; ++u) {
+    for (int x = 0; x < nA; ++x) {
+      double D = eps[nC + x] - eps[nC + u];
+      // t[a, x, i, u]: a (P), x (P, active at offset 0), i (H), u (H, active at offset nC)
+      long long o_axiu = a * sP2 + x * sP + i * sH2 + (nC + u) * sH;
+      if (spin == 0) {
+        c += D * (Taa[o_axiu] * ga[x * nA + u] + Tab[o_axiu] * gb[x * nA + u]);
+      } else {
+        long long o_xaui = x * sP2 + a * sP + (nC + u) * sH2 + i * sH;
+        c += D * (Tbb[o_axiu] * gb[x * nA + u] + Tab[o_xaui] * ga[x * nA + u]);
+      }
+    }
+  }
+  double f = 0.0;
+  const double* fp = spin ? fb : fa;
+  if (fp) f = fp[e];
+  bool internal = a < nA && i >= nC;
+  double D1 = eps[i] - eps[nC + a];
+  double* t1 = spin ? t1b : t1a;
+  double* src = spin ? srcb : srca;
+  t1[e] = internal ? 0.0 : (f + c) * regulariser(s, D1);
+  if (src) src[e] = internal ? 0.0 : (f + c) * source_factor(s, D1);
+}
+
+void launch_singles(AmpDims d, const double* T2aa, const double* T2ab, const double* T2bb,
+                    const double* g1a, const double* g1b, const double* eps, double s,
+                    const double* fa, const double* fb, double* t1a, double* t1b, double* srca,
+                    double* srcb, hipStream_t st) {
+  int nH = d.nC + d.nA, nP = d.nA + d.nV;
+  int total = 2 * nP * nH;
+  if (total == 0) return;
+  hipLaunchKernelGGL(singles_kernel, dim3((total + 255) / 256), dim3(256), 0, st, d, T2aa, T2ab, T2bb,
+                     g1a, g1b, eps, s, fa, fb, t1a, t1b, srca, srcb);
+}
+
+__global__ void second_order_doubles_kernel(AmpDims d, const double* __restrict__ W,
+                                            const double* __restrict__ Z,
+                                            const double* __restrict__ eps, double s,
+                                            double* __restrict__ U, double* __restrict__ H) {
+  const int nH = d.nC + d.nA, nP = d.nA + d.nV;
+  long long total = (long long)nP * nP * nH * nH;
+  long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  if (idx >= total) return;
+  int j = idx % nH, i = (idx / nH) % nH, b = (idx / nH / nH) % nP, a = idx / nH / nH / nP;
+  bool internal = a < d.nA && b < d.nA && i >= d.nC && j >= d.nC;
+  double D = eps[i] + eps[j] - eps[d.nC + a] - eps[d.nC + b];
+  double z = Z[idx];
+  double v2 = W[idx] + 0.5 * z;  // (2 W + Z) / 2
+  U[idx] = internal ? 0.0 : v2 * regulariser(s, D);
+  H[idx] = (internal ? v2 : v2 * source_factor(s, D)) - z / 6.0;
+}
+
+void launch_second_order_doubles(AmpDims d, const double* W, const double* Z, const double* eps,
+                                 double s, double* U, double* H, hipStream_t st) {
+  long long nH = d.nC + d.nA, nP = d.nA + d.nV;
+  long long total = nP * nP * nH * nH;
+  if (total == 0) return;
+  hipLaunchKernelGGL(second_order_doubles_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0,
+                     st, d, W, Z, eps, s, U, H);
+}
+
+__global__ void combine_f2_kernel(int n, const double* __restrict__ W1, const double* __restrict__ Z1,
+                                  double* __restrict__ f2) {
+  int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) f2[i] = W1[i] + 0.5 * Z1[i];
+}
+
+void launch_combine_f2(int n, const double* W1, const double* Z1, double* f2, hipStream_t st) {
+  if (n == 0) return;
+  hipLaunchKernelGGL(combine_f2_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, W1, Z1, f2);
+}
+
+__global__ void second_order_h1_kernel(AmpDims d, const double* __restrict__ W1,
+                                       const double* __restrict__ Z1,
+                                       const double* __restrict__ src, double* __restrict__ H1) {
+  const int nH = d.nC + d.nA, nP = d.nA + d.nV;
+  int e = blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= nP * nH) return;
+  int a = e / nH, i = e % nH;
+  bool internal = a < d.nA && i >= d.nC;
+  double z = Z1[e];
+  double f2 = W1[e] + 0.5 * z;
+  H1[e] = (internal ? f2 : src[e]) - z / 6.0;
+}
+
+void launch_second_order_h1(AmpDims d, const double* W1, const double* Z1, const double* src,
+                            double* H1, hipStream_t st) {
+  int n = (d.nA + d.nV) * (d.nC + d.nA);
+  if (n == 0) return;
+  hipLaunchKernelGGL(second_order_h1_kernel, dim3((n + 255) / 256), dim3(256), 0, st, d, W1, Z1, src,
+                     H1);
+}
+
+__global__ void weighted_sum_kernel(int n, const double* __restrict__ vals,
+                                    const double* __restrict__ coef, double* __restrict__ out) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    double s = 0.0;
+    for (int i = 0; i < n; ++i) s += coef[i] * vals[i];
+    out[0] = s;
+  }
+}
+
+void launch_weighted_sum(int n, const double* vals, const double* coef, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(weighted_sum_kernel, dim3(1), dim3(64), 0, st, n, vals, coef, out);
+}
+
+__global__ void fill_kernel(double* __restrict__ p, long long n, double v) {
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += 256LL * gridDim.x) p[i] = v;
+}
+
+void launch_fill(double* p, long long n, double v, hipStream_t st) {
+  if (n <= 0) return;
+  long long blocks = (n + 255) / 256;
+  if (blocks > 16384) blocks = 16384;
+  hipLaunchKernelGGL(fill_kernel, dim3((unsigned)blocks), dim3(256), 0, st, p, n, v);
+}
+
+}  // namespace dsrg

@@ -162,6 +162,8 @@ def fock_rdms(vec: np.ndarray, fock: _Fock, order: int) -> np.ndarray:
     """
     n = fock.n_so
     tuples = list(itertools.combinations(range(n), order))
+    if not tuples:                      # fewer spin orbitals than the order: zero density
+        return np.zeros((n,) * (2 * order))
     # w_T = a_{t_k} ... a_{t_1} |psi>  for T = (t_1 < ... < t_k)
     W = np.empty((len(tuples), fock.dim))
     for idx, T in enumerate(tuples):

@@ -1,0 +1,53 @@
+"""Write oracle energies for workloads too slow to run inside a test.
+
+Calls only ``oracle/`` (and the shared input generator).  Usage:
+    python tests/golden/make_golden.py small
+Writes tests/golden/<name>_s<s>.json with E(2), E(3) and its two parts.
+"""
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.dirname(os.path.dirname(os.path.abspath(__file__))))
+sys.path.insert(0, ROOT)
+
+from paper_1701_02011_amd.synth import make_config, SMALL_S_VALUES  # noqa: E402
+from oracle import dsrg  # noqa: E402
+
+sys.path.insert(0, os.path.join(ROOT, "tests"))
+from blocks import oracle_blocks  # noqa: E402  (index mapping only)
+import numpy as np  # noqa: E402
+
+
+def samples(r, p, n=400, seed=12345):
+    """Seeded random elements of each intermediate, in the library's spin-block layout."""
+    rng = np.random.default_rng(seed)
+    out = {}
+    for k, arr in oracle_blocks(r, p).items():
+        flat = rng.choice(arr.size, size=min(n, arr.size), replace=False)
+        idx = np.array(np.unravel_index(flat, arr.shape)).T
+        out[k] = dict(index=idx.tolist(), value=arr[tuple(idx.T)].tolist(),
+                      scale=float(np.abs(arr).max()))
+    return out
+
+
+def main(name):
+    svals = SMALL_S_VALUES if name == "small" else (None,)
+    for s in svals:
+        p = make_config(name, s=s)
+        t = time.time()
+        r = dsrg.run(p)
+        out = dict(workload=name, s=p.s, n_core=p.n_core, n_active=p.n_active,
+                   n_virtual=p.n_virtual, n_aux=p.n_aux, e2=r.e2, e3=r.e3, e3_a=r.e3_a,
+                   e3_b=r.e3_b, oracle_seconds=time.time() - t,
+                   source="oracle/dsrg.py (FP64, spin-orbital, MK-GNO commutator engine)",
+                   samples=samples(r, p))
+        path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "%s_s%g.json" % (name, p.s))
+        with open(path, "w") as f:
+            json.dump(out, f, indent=1)
+        print(path, out["e2"], out["e3"], "%.0fs" % out["oracle_seconds"], flush=True)
+
+
+if __name__ == "__main__":
+    main(sys.argv[1] if len(sys.argv) > 1 else "small")

@@ -1,0 +1,103 @@
+"""C ABI checks that need no GPU: the library loads, exports every declared symbol, and
+rejects bad arguments with the documented codes before touching the device."""
+import ctypes
+import glob
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+
+from paper_1701_02011_amd import _lib
+from paper_1701_02011_amd.synth import make_problem
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+@pytest.fixture(scope="session")
+def lib():
+    if not os.path.exists(_lib.LIB_PATH):
+        from paper_1701_02011_amd import _build
+        _build.build()
+    return _lib.load()
+
+
+def declared_functions():
+    names = set()
+    for h in glob.glob(os.path.join(ROOT, "include", "*.h")):
+        text = open(h).read()
+        text = re.sub(r"/\*.*?\*/", "", text, flags=re.S)
+        for m in re.finditer(r"\b(dsrg_\w+)\s*\(", text):
+            names.add(m.group(1))
+    return sorted(names)
+
+
+def test_exports_every_declared_symbol(lib):
+    names = declared_functions()
+    assert "dsrg_pt2_energy" in names and "dsrg_pt3_energy" in names
+    for n in names:
+        assert hasattr(lib, n), n
+    assert lib.dsrg_version() >= 100
+
+
+def _call(p, mutate=None, opt=None):
+    keep = []
+    st, fl = _lib._problem_struct(p, keep)
+    if mutate:
+        mutate(st)
+    r = _lib.Result()
+    r.e2 = 12345.0
+    o = opt or _lib.Options(fl, 0, 0, None)
+    rc = _lib.load().dsrg_pt3_energy(ctypes.byref(st), ctypes.byref(o), ctypes.byref(r))
+    return rc, r
+
+
+@pytest.mark.parametrize("mut,code", [
+    (lambda s: setattr(s, "n_core", -1), _lib.DSRG_E_ARG),
+    (lambda s: setattr(s, "n_aux", 0), _lib.DSRG_E_ARG),
+    (lambda s: setattr(s, "s", 0.0), _lib.DSRG_E_ARG),
+    (lambda s: setattr(s, "s", -1.0), _lib.DSRG_E_ARG),
+    (lambda s: setattr(s, "s", float("nan")), _lib.DSRG_E_ARG),
+    (lambda s: setattr(s, "B", None), _lib.DSRG_E_ARG),
+    (lambda s: setattr(s, "gamma1", None), _lib.DSRG_E_ARG),
+])
+def test_bad_arguments(lib, mut, code):
+    p = make_problem(1, 2, 3, 6, seed=1)
+    rc, r = _call(p, mut)
+    assert rc == code
+    assert r.e2 == 12345.0               # output untouched
+    assert len(lib.dsrg_last_error()) > 0
+
+
+def test_non_finite_input(lib):
+    p = make_problem(1, 2, 3, 6, seed=1)
+    p.B[2, 1, 3] = np.nan
+    rc, r = _call(p)
+    assert rc == _lib.DSRG_E_NONFINITE and r.e2 == 12345.0
+    p = make_problem(1, 2, 3, 6, seed=1)
+    p.gamma2[1, 0, 0, 0, 0] = np.inf
+    rc, _ = _call(p)
+    assert rc == _lib.DSRG_E_NONFINITE
+
+
+def test_unsupported_options(lib):
+    p = make_problem(1, 2, 3, 6, seed=1)
+    rc, _ = _call(p, opt=_lib.Options(0, 1, 0, None))
+    assert rc == _lib.DSRG_E_UNSUPPORTED
+    p = make_problem(0, 9, 1, 4, seed=1, with_gamma3=False)
+    rc, _ = _call(p)
+    assert rc == _lib.DSRG_E_UNSUPPORTED
+
+
+def test_null_problem(lib):
+    r = _lib.Result()
+    rc = lib.dsrg_pt3_energy(None, None, ctypes.byref(r))
+    assert rc == _lib.DSRG_E_ARG
+
+
+def test_test_gett_validates_strides(lib):
+    A = np.zeros(4); B = np.zeros(4); C = np.zeros(4)
+    with pytest.raises(_lib.DsrgError) as e:
+        _lib.test_gett(A, B, C, m=[(3, 2, 1)], n=[(2, 1, 1)], k=[(2, 1, 2)])
+    assert e.value.code == _lib.DSRG_E_ARG

@@ -1,0 +1,163 @@
+"""GPU parity tests: the HIP path through the C ABI against the FP64 oracle.
+
+Tolerances: the spec bar for the FP64 path is |dE| <= 1e-7 E_h (read as
+1e-7 * max(1, |E|) for the synthetic magnitudes).  The checks below are
+far tighter (1e-10 relative on energies, 1e-11 relative to the tensor's largest element
+on intermediates) because both sides compute in FP64 and differ only in summation order.
+"""
+import json
+import os
+import sys
+
+import numpy as np
+import pytest
+
+from paper_1701_02011_amd import _lib
+from paper_1701_02011_amd.synth import make_problem, make_config, SMALL_S_VALUES
+from oracle import dsrg
+
+from blocks import oracle_blocks
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+def _close(x, ref, rel=1e-10):
+    return abs(x - ref) <= rel * max(1.0, abs(ref))
+
+
+# ---------------------------------------------------------------------------
+# contraction kernel
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("case", ["gemm", "ragged", "strided", "multi", "vec", "accum"])
+def test_gett_kernel(case):
+    say("gett case", case)
+    rng = np.random.default_rng(hash(case) % 1000)
+    if case == "gemm":
+        M, N, K = 128, 64, 48
+        A = rng.standard_normal((M, K)); B = rng.standard_normal((K, N)); C = np.zeros((M, N))
+        out = _lib.test_gett(A, B, C, m=[(M, K, N)], n=[(N, 1, 1)], k=[(K, 1, N)])
+        ref = A @ B
+    elif case == "ragged":
+        M, N, K = 77, 45, 19
+        A = rng.standard_normal((M, K)); B = rng.standard_normal((K, N)); C = np.zeros((M, N))
+        out = _lib.test_gett(A, B, C, m=[(M, K, N)], n=[(N, 1, 1)], k=[(K, 1, N)])
+        ref = A @ B
+    elif case == "strided":
+        # C[i,j] = sum_k A[k,i] B[j,k]  (both operands transposed)
+        M, N, K = 70, 66, 35
+        A = rng.standard_normal((K, M)); B = rng.standard_normal((N, K)); C = np.zeros((M, N))
+        out = _lib.test_gett(A, B, C, m=[(M, 1, N)], n=[(N, K, 1)], k=[(K, M, 1)])
+        ref = A.T @ B.T
+    elif case == "multi":
+        # O[a,b,i,j] = sum_{c,d} X[a,c,b,d] T[c,d,i,j]  with ragged extents
+        a, b, c, d, i, j = 9, 7, 5, 6, 4, 3
+        X = rng.standard_normal((a, c, b, d)); T = rng.standard_normal((c, d, i, j))
+        C = np.zeros((a, b, i, j))
+        out = _lib.test_gett(X, T, C,
+                             m=[(a, c * b * d, b * i * j), (b, d, i * j)],
+                             n=[(i, j, j), (j, 1, 1)],
+                             k=[(c, b * d, d * i * j), (d, 1, i * j)])
+        ref = np.einsum("acbd,cdij->abij", X, T)
+    elif case == "vec":
+        K = 1000
+        A = rng.standard_normal(K); B = rng.standard_normal(K); C = np.zeros(1)
+        out = _lib.test_gett(A, B, C, m=[], n=[], k=[(K, 1, 1)])
+        ref = np.array([A @ B])
+    else:
+        M, N, K = 65, 130, 17
+        A = rng.standard_normal((M, K)); B = rng.standard_normal((K, N)); C = rng.standard_normal((M, N))
+        out = _lib.test_gett(A, B, C, m=[(M, K, N)], n=[(N, 1, 1)], k=[(K, 1, N)],
+                             alpha=-0.5, beta=1)
+        ref = C - 0.5 * (A @ B)
+    np.testing.assert_allclose(out.reshape(ref.shape), ref, rtol=1e-13, atol=1e-12)
+
+
+# ---------------------------------------------------------------------------
+# energies and intermediates against the oracle
+# ---------------------------------------------------------------------------
+@pytest.mark.parametrize("shape,seed,s", [((1, 2, 3, 10), 11, 0.5), ((1, 3, 2, 8), 7, 0.6),
+                                          ((2, 2, 4, 9), 5, 1.3), ((2, 0, 4, 9), 17, 0.4),
+                                          ((0, 3, 3, 7), 19, 0.8), ((3, 1, 5, 12), 23, 0.5)])
+def test_micro_energies(shape, seed, s):
+    p = make_problem(*shape, seed=seed, s=s)
+    say("micro", shape, seed, s)
+    g = _lib.dsrg_pt3_energy(p)
+    r = dsrg.run(p)
+    assert _close(g["e2"], r.e2), (g["e2"], r.e2)
+    assert _close(g["e3_a"], r.e3_a), (g["e3_a"], r.e3_a)
+    assert _close(g["e3_b"], r.e3_b), (g["e3_b"], r.e3_b)
+    g2 = _lib.dsrg_pt2_energy(p)
+    assert g2["e2"] == g["e2"] and g2["e3"] == 0.0
+
+
+def test_tiny_intermediates_elementwise():
+    p = make_config("tiny")
+    say("tiny intermediates")
+    g = _lib.dsrg_pt3_energy_ex(p)
+    r = dsrg.run(p)
+    ref = oracle_blocks(r, p)
+    for k in ("t1", "t2", "w1", "w2", "z1", "z2", "u1", "u2"):
+        scale = max(1.0, np.abs(ref[k]).max())
+        err = np.abs(g[k] - ref[k]).max()
+        assert err <= 1e-11 * scale, (k, err, scale)
+    assert _close(g["e2"], r.e2) and _close(g["e3"], r.e3)
+
+
+@pytest.mark.parametrize("s", SMALL_S_VALUES)
+def test_small_against_golden(s):
+    path = os.path.join(GOLDEN, "small_s%g.json" % s)
+    gold = json.load(open(path))
+    p = make_config("small", s=s)
+    say("small s=%g" % s)
+    g = _lib.dsrg_pt3_energy(p)
+    assert _close(g["e2"], gold["e2"]), (g["e2"], gold["e2"])
+    assert _close(g["e3_a"], gold["e3_a"]), (g["e3_a"], gold["e3_a"])
+    assert _close(g["e3_b"], gold["e3_b"]), (g["e3_b"], gold["e3_b"])
+    samples = gold.get("samples")
+    assert samples, "golden file has no sampled intermediates"
+    gi = _lib.dsrg_pt3_energy_ex(p)
+    for key, samp in samples.items():
+        idx = tuple(np.array(samp["index"]).T)
+        vals = np.array(samp["value"])
+        scale = max(1.0, samp["scale"])
+        assert np.abs(gi[key][idx] - vals).max() <= 1e-11 * scale, key
+
+
+def test_device_pointers_and_determinism():
+    import torch
+    p = make_config("tiny")
+    say("device pointers")
+    h = _lib.dsrg_pt3_energy(p)
+    d = _lib.to_device(p)
+    g1 = _lib.dsrg_pt3_energy(d)
+    g2 = _lib.dsrg_pt3_energy(d)
+    torch.cuda.synchronize()
+    assert g1["e2"] == h["e2"] and g1["e3"] == h["e3"]
+    assert g1["e2"] == g2["e2"] and g1["e3"] == g2["e3"]
+
+
+def test_small_batched_pppp_matches_unbatched():
+    """The (PP|PP) integrals in several virtual batches give the same energies."""
+    p = make_config("small")
+    say("small batched")
+    a = _lib.dsrg_pt3_energy(p)
+    nP = p.n_active + p.n_virtual
+    b = _lib.dsrg_pt3_energy(p, workspace_cap=7 * nP ** 3 * 8)
+    assert b["ladder_batch"] == 7
+    assert _close(b["e2"], a["e2"], 1e-13) and _close(b["e3"], a["e3"], 1e-13)
+
+
+def test_nonfinite_device_input():
+    import torch
+    p = make_problem(1, 2, 3, 6, seed=1)
+    d = _lib.to_device(p)
+    d["B"][0, 1, 1] = float("nan")
+    with pytest.raises(_lib.DsrgError) as e:
+        _lib.dsrg_pt3_energy(d)
+    assert e.value.code == _lib.DSRG_E_NONFINITE
