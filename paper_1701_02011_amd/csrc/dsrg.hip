@@ -15,6 +15,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstring>
+#include <cstdlib>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -229,6 +230,22 @@ struct Exec {
   Exec(Dims d_, hipStream_t s, Pool& p, const double* B_, int M_, long long cap, bool prof)
       : d(d_), st(s), pool(p), B(B_), M(M_), ws_cap(cap), profile(prof) {
     partial = pool.alloc(dot_partials());
+    splitk_ws = pool.alloc((size_t)splitk_elems);
+  }
+  // split-K partial tiles for contractions with few output tiles
+  long long splitk_elems = 1LL << 23;
+  double* splitk_ws = nullptr;
+  // k -> offset tables of the contraction kernel; launches on one stream reuse the buffer
+  // in order, so a table is never overwritten while an earlier launch still reads it
+  long long* ktab = nullptr;
+  long long ktab_cap = 0;
+  long long* ktab_for(long long K) {
+    if (2 * K > ktab_cap) {
+      long long n = std::max(2 * K, 1LL << 20);
+      ktab = (long long*)pool.alloc((size_t)n);
+      ktab_cap = n;
+    }
+    return ktab;
   }
 
   // every contraction launch goes through here; with profiling, HIP events bracket it
@@ -238,17 +255,20 @@ struct Exec {
     hipEvent_t a, b;
     int role;
     double flops;
+    int M, N, K, nm, nn, nk;
+    int product;
   };
+  int cur_product = -1;
   std::vector<Rec> recs;
   void gett(const GettDesc& g, const double* A, const double* Bp, double* C, int role) {
     double fl = 2.0 * g.M * (double)g.N * g.K;
-    Rec r{nullptr, nullptr, role, fl};
+    Rec r{nullptr, nullptr, role, fl, g.M, g.N, g.K, g.nm, g.nn, g.nk, cur_product};
     if (profile) {
       HIPCHECK(hipEventCreate(&r.a));
       HIPCHECK(hipEventCreate(&r.b));
       HIPCHECK(hipEventRecord(r.a, st));
     }
-    launch_gett(g, A, Bp, C, st, role);
+    launch_gett(g, A, Bp, C, st, role, splitk_ws, splitk_elems, ktab_for(g.K));
     if (profile) {
       HIPCHECK(hipEventRecord(r.b, st));
       recs.push_back(r);
@@ -262,15 +282,22 @@ struct Exec {
   double role_sec[3] = {0, 0, 0}, role_flops[3] = {0, 0, 0};
   int role_n[3] = {0, 0, 0};
   void collect_profile() {
+    // optional per-launch dump (shape and device time) for tuning
+    const char* dump = getenv("DSRG_PROFILE_DUMP");
+    FILE* fd = dump ? fopen(dump, "a") : nullptr;
     for (auto& r : recs) {
       float ms = 0;
       HIPCHECK(hipEventElapsedTime(&ms, r.a, r.b));
+      if (fd)
+        fprintf(fd, "%d,%d,%d,%d,%d,%d,%d,%d,%.6f\n", r.product, r.role, r.M, r.N, r.K, r.nm, r.nn,
+                r.nk, ms);
       role_sec[r.role] += ms * 1e-3;
       role_flops[r.role] += r.flops;
       role_n[r.role] += 1;
       (void)hipEventDestroy(r.a);
       (void)hipEventDestroy(r.b);
     }
+    if (fd) fclose(fd);
     recs.clear();
   }
   ~Exec() {
@@ -641,12 +668,16 @@ struct Exec {
   }
 
   // Run a use of the table.  Scalar products write vals[i]/coefs[i] for a final weighted sum.
+  int use_id = 0;
   void run_use(const Use& U, std::map<std::string, TensorRef>& outs, double* vals,
                std::vector<double>& coefs) {
     // products with the (PP|PP) block, grouped by the block's letters
     std::map<std::string, std::vector<const TProduct*>> pppp;
     int slot = 0;
+    int pidx = -1;
     for (auto& P : U) {
+      ++pidx;
+      cur_product = use_id * 10000 + pidx;
       std::string jl;
       if (is_pppp(P, &jl)) {
         // batch letter: a free letter of the block; rotate it to the first position
@@ -897,6 +928,7 @@ static int run(const dsrg_problem* P, const dsrg_options* O, dsrg_result* R,
   auto scalar = [&](double* outp) {
     coefs.clear();
     launch_fill(vals, (long long)nslot, 0.0, st);
+    X.use_id = 0;
     X.run_use(C0, none, vals, coefs);
     HIPCHECK(hipMemcpyAsync(coefd, coefs.data(), coefs.size() * 8, hipMemcpyHostToDevice, st));
     HIPCHECK(hipStreamSynchronize(st));   // coefs is a host buffer reused below
@@ -928,6 +960,7 @@ static int run(const dsrg_problem* P, const dsrg_options* O, dsrg_result* R,
     };
     bind_out(wout, W1a, W2);
     std::vector<double> dummy;
+    X.use_id = 1;
     X.run_use(T.at("W"), wout, nullptr, dummy);
     HIPCHECK(hipEventRecord(ev[4], st));
     // step a6: Z = [Y, A(1)]_{1,2}
@@ -937,6 +970,7 @@ static int run(const dsrg_problem* P, const dsrg_options* O, dsrg_result* R,
     launch_fill(Z2, 3 * n4, 0.0, st);
     std::map<std::string, TensorRef> zout;
     bind_out(zout, Z1, Z2);
+    X.use_id = 2;
     X.run_use(T.at("Z"), zout, nullptr, dummy);
     HIPCHECK(hipEventRecord(ev[5], st));
     // second-order amplitudes and H~(2)_{1,2}
@@ -1099,8 +1133,17 @@ extern "C" int dsrg_test_gett(int nm, const int* md, const long long* am, const 
     HIPCHECK(hipMemcpy(dA, A, na * 8, hipMemcpyHostToDevice));
     HIPCHECK(hipMemcpy(dB, B, nb * 8, hipMemcpyHostToDevice));
     HIPCHECK(hipMemcpy(dC, C, nc * 8, hipMemcpyHostToDevice));
-    launch_gett(g, dA, dB, dC, 0);
+    // with a workspace, shapes with few output tiles and a long k range use split-K
+    const long long ws_elems = 1LL << 22;
+    double* ws;
+    HIPCHECK(hipMalloc(&ws, ws_elems * 8));
+    long long* tab;
+    HIPCHECK(hipMalloc(&tab, 2 * K * sizeof(long long)));
+    launch_gett(g, dA, dB, dC, 0, kRoleGeneric, ws, ws_elems, tab);
     HIPCHECK(hipGetLastError());
+    HIPCHECK(hipDeviceSynchronize());
+    (void)hipFree(ws);
+    (void)hipFree(tab);
     HIPCHECK(hipMemcpy(C, dC, nc * 8, hipMemcpyDeviceToHost));
     (void)hipFree(dA); (void)hipFree(dB); (void)hipFree(dC);
     return DSRG_OK;

@@ -22,6 +22,9 @@ struct GettDesc {
   int beta = 0;        // 0: C = alpha AB, 1: C += alpha AB
   int a_kfast = 1;     // A tile loads walk k fastest (else m fastest)
   int b_kfast = 0;     // B tile loads walk k fastest (else n fastest)
+  int kchunk = 0;      // set by launch_gett: k range per split
+  double* part = nullptr;  // set by launch_gett: split-K partial tiles [split][M][N]
+  const long long* ktab = nullptr;  // set by launch_gett: k -> offset tables [2][K]
 };
 
 // sum_k A[k] B[k] over a strided multi-index k (deterministic two-pass reduction).
@@ -44,8 +47,12 @@ struct ScatterDesc {
 // Launch roles (same kernel, distinct symbols): contraction-table products, the (PP|PP)
 // particle-particle ladder products, and Coulomb-block builds from the DF tensor.
 constexpr int kRoleGeneric = 0, kRoleLadder = 1, kRoleIntegrals = 2;
+// ws (ws_elems doubles) enables split-K for launches with few output tiles and a long
+// k range: partial tiles go to ws and a fixed-order reduction writes C (deterministic).
+// ktab: scratch of 2 K int64 for the k -> offset tables of A and B (required).
 void launch_gett(const GettDesc& g, const double* A, const double* B, double* C, hipStream_t st,
-                 int role = kRoleGeneric);
+                 int role, double* ws, long long ws_elems, long long* ktab);
+int gett_splits(const GettDesc& g, long long ws_elems);
 // partial: scratch of at least dot_partials() doubles; writes the sum into out[0]
 int dot_partials();
 void launch_dot(const DotDesc& d, const double* A, const double* B, double* partial, double* out,

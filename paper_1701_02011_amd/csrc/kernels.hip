@@ -1,6 +1,7 @@
 // Device kernels of the DSRG-MRPT3 hot path for CDNA4 (gfx950), FP64.
 #include "kernels.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstdio>
 
@@ -26,96 +27,141 @@ __device__ __forceinline__ long long decode(int idx, int n, const int* d, const 
 }
 
 // ---------------------------------------------------------------------------
-// GETT: 64x64 output tile per workgroup of 256 threads (4 waves, 2x2), each wave a
-// 32x32 sub-tile made of 2x2 v_mfma_f64_16x16x4 tiles; K staged through LDS in steps
-// of 16.  Operand layout of the 16x16x4 FP64 MFMA (checked on gfx950 by the kernel unit
-// tests): lane l holds A[l%16][l/16] and B[l/16][l%16]; accumulator element r of lane l
-// is D[l/16 + 4 r][l%16].
+// GETT: a workgroup of 256 threads (4 waves, 2x2) computes a BM x BN output tile; each
+// wave owns a (16 WM) x (16 WN) sub-tile made of WM x WN v_mfma_f64_16x16x4 tiles.
+// K is staged through LDS in steps of BK = 16 with two buffers: the next step's global
+// loads are issued into registers before the current step's MFMAs and stored to the
+// other buffer afterwards (one barrier per step).
+// Operand layout of the 16x16x4 FP64 MFMA (checked on gfx950 by the kernel unit tests):
+// lane l holds A[l%16][l/16] and B[l/16][l%16]; accumulator element r of lane l is
+// D[l/16 + 4 r][l%16].
 // ---------------------------------------------------------------------------
-constexpr int BM = 64, BN = 64, BK = 16;
-constexpr int LDA = BM + 1, LDB = BN + 1;
+constexpr int BK = 16;
 
-template <int kRole>
+template <int kRole, int WM, int WN>
 __global__ __launch_bounds__(256) void gett_f64_kernel(GettDesc g, const double* __restrict__ A,
                                                        const double* __restrict__ B,
                                                        double* __restrict__ C) {
-  __shared__ double As[BK * LDA];
-  __shared__ double Bs[BK * LDB];
+  constexpr int BM = 32 * WM, BN = 32 * WN;
+  constexpr int LDA = BM + 2, LDB = BN + 2;
+  constexpr int NA = BM * BK / 256, NB = BN * BK / 256;   // loads per thread per step
+  __shared__ double As[2][BK * LDA];
+  __shared__ double Bs[2][BK * LDB];
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
   const int tile_m = blockIdx.x * BM;
   const int tile_n = blockIdx.y * BN;
+  // split-K: workgroup z sums k in [k_lo, k_hi) and then writes a partial tile
+  const int k_lo = blockIdx.z * g.kchunk;
+  const int k_hi = min(g.K, k_lo + g.kchunk);
 
-  // fixed per-thread load slots: 4 elements of each tile
-  long long aoff_m[4], boff_n[4];
-  int a_mm[4], a_kk[4], b_nn[4], b_kk[4];
-  bool a_ok[4], b_ok[4];
+  // fixed per-thread load slots
+  long long aoff_m[NA], boff_n[NB];
+  int a_mm[NA], a_kk[NA], b_nn[NB], b_kk[NB];
+  bool a_ok[NA], b_ok[NB];
 #pragma unroll
-  for (int i = 0; i < 4; ++i) {
+  for (int i = 0; i < NA; ++i) {
     int e = tid + 256 * i;
     if (g.a_kfast) { a_kk[i] = e % BK; a_mm[i] = e / BK; }
     else           { a_mm[i] = e % BM; a_kk[i] = e / BM; }
+    int m = tile_m + a_mm[i];
+    a_ok[i] = m < g.M;
+    aoff_m[i] = a_ok[i] ? decode(m, g.nm, g.md, g.am) : 0;
+  }
+#pragma unroll
+  for (int i = 0; i < NB; ++i) {
+    int e = tid + 256 * i;
     if (g.b_kfast) { b_kk[i] = e % BK; b_nn[i] = e / BK; }
     else           { b_nn[i] = e % BN; b_kk[i] = e / BN; }
-    int m = tile_m + a_mm[i];
     int n = tile_n + b_nn[i];
-    a_ok[i] = m < g.M;
     b_ok[i] = n < g.N;
-    aoff_m[i] = a_ok[i] ? decode(m, g.nm, g.md, g.am) : 0;
     boff_n[i] = b_ok[i] ? decode(n, g.nn, g.nd, g.bn) : 0;
   }
-
-  double4_t acc[2][2];
+  double ra[NA], rb[NB];
+  // k -> element offset tables (filled by kofs_kernel before this launch)
+  const long long* __restrict__ ta = g.ktab;
+  const long long* __restrict__ tb = g.ktab + g.K;
+  // branch-free loads in two phases (all k offsets, then all elements) so the memory
+  // requests of one step are in flight together; out-of-range slots read a valid element
+  // (row 0 / last k of the range) and are zeroed by a select
+  auto fetch = [&](int k0) {
+    long long oa[NA], ob[NB];
 #pragma unroll
-  for (int a = 0; a < 2; ++a)
+    for (int i = 0; i < NA; ++i) oa[i] = __builtin_nontemporal_load(&ta[min(k0 + a_kk[i], k_hi - 1)]);
 #pragma unroll
-    for (int b = 0; b < 2; ++b) acc[a][b] = (double4_t){0.0, 0.0, 0.0, 0.0};
+    for (int i = 0; i < NB; ++i) ob[i] = __builtin_nontemporal_load(&tb[min(k0 + b_kk[i], k_hi - 1)]);
+#pragma unroll
+    for (int i = 0; i < NA; ++i) ra[i] = A[aoff_m[i] + oa[i]];
+#pragma unroll
+    for (int i = 0; i < NB; ++i) rb[i] = B[boff_n[i] + ob[i]];
+  };
+  // the zeroing select sits here, after the step's MFMAs, so the loads overlap them
+  auto stash = [&](int buf, int k0) {
+#pragma unroll
+    for (int i = 0; i < NA; ++i)
+      As[buf][a_kk[i] * LDA + a_mm[i]] = (a_ok[i] && k0 + a_kk[i] < k_hi) ? ra[i] : 0.0;
+#pragma unroll
+    for (int i = 0; i < NB; ++i)
+      Bs[buf][b_kk[i] * LDB + b_nn[i]] = (b_ok[i] && k0 + b_kk[i] < k_hi) ? rb[i] : 0.0;
+  };
 
-  const int wm = (wave & 1) * 32;
-  const int wn = (wave >> 1) * 32;
+  double4_t acc[WM][WN];
+#pragma unroll
+  for (int a = 0; a < WM; ++a)
+#pragma unroll
+    for (int b = 0; b < WN; ++b) acc[a][b] = (double4_t){0.0, 0.0, 0.0, 0.0};
+
+  const int wm = (wave & 1) * (16 * WM);
+  const int wn = (wave >> 1) * (16 * WN);
   const int li = lane & 15;
   const int lk = lane >> 4;
 
-  for (int k0 = 0; k0 < g.K; k0 += BK) {
-#pragma unroll
-    for (int i = 0; i < 4; ++i) {
-      int k = k0 + a_kk[i];
-      double v = 0.0;
-      if (a_ok[i] && k < g.K) v = A[aoff_m[i] + decode(k, g.nk, g.kd, g.ak)];
-      As[a_kk[i] * LDA + a_mm[i]] = v;
-      int kb = k0 + b_kk[i];
-      double w = 0.0;
-      if (b_ok[i] && kb < g.K) w = B[boff_n[i] + decode(kb, g.nk, g.kd, g.bk)];
-      Bs[b_kk[i] * LDB + b_nn[i]] = w;
-    }
-    __syncthreads();
+  int buf = 0;
+  if (k_lo < k_hi) {
+    fetch(k_lo);
+    stash(0, k_lo);
+  }
+  __syncthreads();
+  for (int k0 = k_lo; k0 < k_hi; k0 += BK) {
+    const bool more = k0 + BK < k_hi;
+    if (more) fetch(k0 + BK);
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
-      double av[2], bv[2];
+      double av[WM], bv[WN];
 #pragma unroll
-      for (int t = 0; t < 2; ++t) {
-        av[t] = As[(kk + lk) * LDA + wm + t * 16 + li];
-        bv[t] = Bs[(kk + lk) * LDB + wn + t * 16 + li];
-      }
+      for (int t = 0; t < WM; ++t) av[t] = As[buf][(kk + lk) * LDA + wm + t * 16 + li];
 #pragma unroll
-      for (int a = 0; a < 2; ++a)
+      for (int t = 0; t < WN; ++t) bv[t] = Bs[buf][(kk + lk) * LDB + wn + t * 16 + li];
 #pragma unroll
-        for (int b = 0; b < 2; ++b)
+      for (int a = 0; a < WM; ++a)
+#pragma unroll
+        for (int b = 0; b < WN; ++b)
           acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
     }
+    if (more) stash(buf ^ 1, k0 + BK);
     __syncthreads();
+    buf ^= 1;
   }
 
 #pragma unroll
-  for (int a = 0; a < 2; ++a) {
+  for (int a = 0; a < WM; ++a) {
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
       int m = tile_m + wm + a * 16 + lk + 4 * r;
       if (m >= g.M) continue;
+      if (g.part) {
+        double* prow = g.part + ((long long)blockIdx.z * g.M + m) * g.N;
+#pragma unroll
+        for (int b = 0; b < WN; ++b) {
+          int n = tile_n + wn + b * 16 + li;
+          if (n < g.N) prow[n] = acc[a][b][r];
+        }
+        continue;
+      }
       long long cmo = decode(m, g.nm, g.md, g.cm);
 #pragma unroll
-      for (int b = 0; b < 2; ++b) {
+      for (int b = 0; b < WN; ++b) {
         int n = tile_n + wn + b * 16 + li;
         if (n >= g.N) continue;
         long long o = cmo + decode(n, g.nn, g.nd, g.cn);
@@ -127,17 +173,89 @@ __global__ __launch_bounds__(256) void gett_f64_kernel(GettDesc g, const double*
   }
 }
 
-void launch_gett(const GettDesc& g, const double* A, const double* B, double* C, hipStream_t st,
-                 int role) {
-  if (g.M <= 0 || g.N <= 0) return;
-  dim3 grid((g.M + BM - 1) / BM, (g.N + BN - 1) / BN);
+// k -> offset tables of both operands: tab[k] (A) and tab[K + k] (B)
+__global__ __launch_bounds__(256) void kofs_kernel(GettDesc g, long long* __restrict__ tab) {
+  for (int k = blockIdx.x * 256 + threadIdx.x; k < g.K; k += 256 * gridDim.x) {
+    tab[k] = decode(k, g.nk, g.kd, g.ak);
+    tab[g.K + k] = decode(k, g.nk, g.kd, g.bk);
+  }
+}
+
+// C[m][n] = alpha * sum_z part[z][m][n] (+ C) in a fixed order of z
+__global__ __launch_bounds__(256) void splitk_reduce_kernel(GettDesc g, const double* __restrict__ part,
+                                                            int nsplit, double* __restrict__ C) {
+  long long total = (long long)g.M * g.N;
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < total; i += 256LL * gridDim.x) {
+    int m = (int)(i / g.N), n = (int)(i - (long long)m * g.N);
+    double s = 0.0;
+    for (int z = 0; z < nsplit; ++z) s += part[(long long)z * total + i];
+    long long o = decode(m, g.nm, g.md, g.cm) + decode(n, g.nn, g.nd, g.cn);
+    double v = g.alpha * s;
+    if (g.beta) v += C[o];
+    C[o] = v;
+  }
+}
+
+// Large tiles (128 x 128) when they still give enough workgroups, else 64 x 64.
+static bool big_tiles(const GettDesc& g) {
+  long long t128 = (long long)((g.M + 127) / 128) * ((g.N + 127) / 128);
+  return g.M >= 128 && g.N >= 128 && t128 >= 256;
+}
+
+int gett_splits(const GettDesc& g, long long ws_elems) {
+  const int bm = big_tiles(g) ? 128 : 64, bn = bm;
+  long long tiles = (long long)((g.M + bm - 1) / bm) * ((g.N + bn - 1) / bn);
+  if (tiles >= 512 || g.K < 512) return 1;
+  long long s = std::min<long long>((g.K + 255) / 256, (2048 + tiles - 1) / tiles);
+  long long cap = ws_elems / std::max<long long>(1, (long long)g.M * g.N);
+  s = std::min(s, cap);
+  return (int)std::max<long long>(1, s);
+}
+
+template <int kRole>
+static void launch_role(const GettDesc& g, bool big, dim3 grid, const double* A, const double* B,
+                        double* C, hipStream_t st) {
+  if (big)
+    hipLaunchKernelGGL((gett_f64_kernel<kRole, 4, 4>), grid, dim3(256), 0, st, g, A, B, C);
+  else
+    hipLaunchKernelGGL((gett_f64_kernel<kRole, 2, 2>), grid, dim3(256), 0, st, g, A, B, C);
+}
+
+void launch_gett(const GettDesc& g0, const double* A, const double* B, double* C, hipStream_t st,
+                 int role, double* ws, long long ws_elems, long long* ktab) {
+  if (g0.M <= 0 || g0.N <= 0) return;
+  GettDesc g = g0;
+  g.ktab = ktab;
+  {
+    long long blocks = std::min<long long>((g.K + 255) / 256, 1024);
+    hipLaunchKernelGGL(kofs_kernel, dim3((unsigned)std::max<long long>(1, blocks)), dim3(256), 0, st,
+                       g, ktab);
+  }
+  const bool big = big_tiles(g);
+  const int bm = big ? 128 : 64, bn = bm;
+  int ns = ws ? gett_splits(g, ws_elems) : 1;
+  g.part = nullptr;
+  g.kchunk = g.K;
+  if (ns > 1) {
+    int chunk = (g.K + ns - 1) / ns;
+    chunk = (chunk + BK - 1) / BK * BK;
+    ns = (g.K + chunk - 1) / chunk;
+    g.kchunk = chunk;
+    g.part = ws;
+  }
+  dim3 grid((g.M + bm - 1) / bm, (g.N + bn - 1) / bn, ns);
   // the role only selects a distinct kernel symbol so profiles can tell the launches apart
   if (role == kRoleLadder)
-    hipLaunchKernelGGL(gett_f64_kernel<kRoleLadder>, grid, dim3(256), 0, st, g, A, B, C);
+    launch_role<kRoleLadder>(g, big, grid, A, B, C, st);
   else if (role == kRoleIntegrals)
-    hipLaunchKernelGGL(gett_f64_kernel<kRoleIntegrals>, grid, dim3(256), 0, st, g, A, B, C);
+    launch_role<kRoleIntegrals>(g, big, grid, A, B, C, st);
   else
-    hipLaunchKernelGGL(gett_f64_kernel<kRoleGeneric>, grid, dim3(256), 0, st, g, A, B, C);
+    launch_role<kRoleGeneric>(g, big, grid, A, B, C, st);
+  if (ns > 1) {
+    long long total = (long long)g.M * g.N;
+    long long blocks = std::min<long long>((total + 255) / 256, 4096);
+    hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)blocks), dim3(256), 0, st, g, ws, ns, C);
+  }
 }
 
 // ---------------------------------------------------------------------------

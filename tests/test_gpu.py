@@ -34,7 +34,7 @@ def _close(x, ref, rel=1e-10):
 # ---------------------------------------------------------------------------
 # contraction kernel
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("case", ["gemm", "ragged", "strided", "multi", "vec", "accum"])
+@pytest.mark.parametrize("case", ["gemm", "ragged", "strided", "multi", "vec", "accum", "splitk"])
 def test_gett_kernel(case):
     say("gett case", case)
     rng = np.random.default_rng(hash(case) % 1000)
@@ -69,6 +69,15 @@ def test_gett_kernel(case):
         A = rng.standard_normal(K); B = rng.standard_normal(K); C = np.zeros(1)
         out = _lib.test_gett(A, B, C, m=[], n=[], k=[(K, 1, 1)])
         ref = np.array([A @ B])
+    elif case == "splitk":
+        # few output tiles, long k range over a 3-component multi-index: split-K path
+        M, N, k1, k2, k3 = 20, 37, 31, 29, 23
+        A = rng.standard_normal((M, k1, k2, k3)); B = rng.standard_normal((k3, k1, k2, N))
+        C = rng.standard_normal((M, N))
+        out = _lib.test_gett(A, B, C, m=[(M, k1 * k2 * k3, N)], n=[(N, 1, 1)],
+                             k=[(k1, k2 * k3, k2 * N), (k2, k3, N), (k3, 1, k1 * k2 * N)],
+                             alpha=0.75, beta=1)
+        ref = C + 0.75 * np.einsum("mabc,cabn->mn", A, B)
     else:
         M, N, K = 65, 130, 17
         A = rng.standard_normal((M, K)); B = rng.standard_normal((K, N)); C = rng.standard_normal((M, N))
