@@ -46,6 +46,11 @@ extern "C" {
 #define DSRG_F_DEVICE_PTRS 1    /* every array pointer in dsrg_problem is a device pointer */
 #define DSRG_F_PROFILE 2        /* bracket every contraction launch with HIP events and report
                                    per-role device time in dsrg_result.role_* (adds overhead) */
+#define DSRG_F_NO_GROUPING 4    /* one launch per contraction.  By default the independent
+                                   contractions of each commutator run as grouped launches (one
+                                   per dependency level) whenever their temporaries fit in half of
+                                   workspace_cap; results agree to rounding either way, and each
+                                   mode is deterministic. */
 
 typedef struct {
   int32_t n_core, n_active, n_virtual, n_aux;

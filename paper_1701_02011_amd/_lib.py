@@ -23,6 +23,7 @@ DSRG_E_HIP = -4
 DSRG_E_UNSUPPORTED = -5
 DSRG_F_DEVICE_PTRS = 1
 DSRG_F_PROFILE = 2
+DSRG_F_NO_GROUPING = 4
 
 _dp = ctypes.POINTER(ctypes.c_double)
 
@@ -161,30 +162,39 @@ def _stream_of(p, stream):
     return None
 
 
-def dsrg_pt2_energy(p, stream=None, workspace_cap=0):
+def _flags(fl, profile=False, grouping=True):
+    if profile:
+        fl |= DSRG_F_PROFILE
+    if not grouping:
+        fl |= DSRG_F_NO_GROUPING
+    return fl
+
+
+def dsrg_pt2_energy(p, stream=None, workspace_cap=0, grouping=True):
     keep = []
     st, fl = _problem_struct(p, keep)
+    fl = _flags(fl, grouping=grouping)
     r = Result()
     _check(load().dsrg_pt2_energy(ctypes.byref(st), ctypes.byref(
         _options(fl, _stream_of(p, stream), workspace_cap)), ctypes.byref(r)))
     return _result_dict(r)
 
 
-def dsrg_pt3_energy(p, stream=None, workspace_cap=0, profile=False):
+def dsrg_pt3_energy(p, stream=None, workspace_cap=0, profile=False, grouping=True):
     keep = []
     st, fl = _problem_struct(p, keep)
-    if profile:
-        fl |= DSRG_F_PROFILE
+    fl = _flags(fl, profile, grouping)
     r = Result()
     _check(load().dsrg_pt3_energy(ctypes.byref(st), ctypes.byref(
         _options(fl, _stream_of(p, stream), workspace_cap)), ctypes.byref(r)))
     return _result_dict(r)
 
 
-def dsrg_pt3_energy_ex(p, stream=None, workspace_cap=0):
+def dsrg_pt3_energy_ex(p, stream=None, workspace_cap=0, grouping=True):
     """E(2), E(3) and the intermediates as numpy arrays (spin blocks, excitation order)."""
     keep = []
     st, fl = _problem_struct(p, keep)
+    fl = _flags(fl, grouping=grouping)
     nC, nA, nV = st.n_core, st.n_active, st.n_virtual
     nH, nP = nC + nA, nA + nV
     bufs = {k: np.zeros((2, nP, nH)) for k in ("t1", "w1", "z1", "u1")}

@@ -16,6 +16,7 @@
 #include <cstdio>
 #include <cstring>
 #include <cstdlib>
+#include <deque>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -189,6 +190,7 @@ struct Opnd {
   std::string letters;
   std::vector<long long> stride;
   long long lim = 0;   // elements addressable from p (allocation end)
+  long long toff = -1; // grouped planning: offset in the temporary arena (p unset)
 };
 
 struct TensorRef {
@@ -423,10 +425,15 @@ struct Exec {
     return o;
   }
 
-  // contract two operands; result either a new contiguous temp or (final) the target
-  Opnd contract(const Opnd& a, const Opnd& b, const LetterRange& lr, std::vector<double*>& temps) {
-    std::string ml, nl, kl;
+  // Descriptor of C[m][n] = sum_k a[m, k] b[k, n] for two operands: the free letters of a
+  // (in a's order) form m, those of b form n, the shared letters form k.  C strides are left
+  // to the caller.
+  GettDesc pair_desc(const Opnd& a, const Opnd& b, const LetterRange& lr, std::string& ml,
+                     std::string& nl) {
+    std::string kl;
     std::vector<long long> am, ak, bk, bn;
+    ml.clear();
+    nl.clear();
     for (size_t i = 0; i < a.letters.size(); ++i) {
       char l = a.letters[i];
       size_t j = b.letters.find(l);
@@ -447,20 +454,49 @@ struct Exec {
     g.M = (int)Mx; g.N = (int)Nx; g.K = (int)Kx;
     check_operand("contraction A", a, lr);
     check_operand("contraction B", b, lr);
+    return g;
+  }
+
+  // Contiguous result operand with letters ml + nl; sets the C strides of g.
+  Opnd result_operand(GettDesc& g, const std::string& ml, const std::string& nl, const LetterRange& lr) {
     Opnd r;
     r.letters = ml + nl;
-    size_t n = (size_t)Mx * Nx;
-    double* out = pool_temp(n, temps);
-    r.lim = (long long)n;
-    r.p = out;
+    r.lim = (long long)g.M * g.N;
     r.stride.assign(r.letters.size(), 1);
     for (int k = (int)r.letters.size() - 2; k >= 0; --k) r.stride[k] = r.stride[k + 1] * lr.len.at(r.letters[k + 1]);
     for (int i = 0; i < g.nm; ++i) g.cm[i] = r.stride[i];
     for (int i = 0; i < g.nn; ++i) g.cn[i] = r.stride[g.nm + i];
     set_load_order(g);
-    g.alpha = 1.0; g.beta = 0;
+    g.alpha = 1.0;
+    g.beta = 0;
+    return r;
+  }
+
+  // contract two operands into a new contiguous temporary
+  Opnd contract(const Opnd& a, const Opnd& b, const LetterRange& lr, std::vector<double*>& temps) {
+    std::string ml, nl;
+    GettDesc g = pair_desc(a, b, lr, ml, nl);
+    Opnd r = result_operand(g, ml, nl, lr);
+    double* out = pool_temp((size_t)r.lim, temps);
+    r.p = out;
     gett(g, a.p, b.p, out, role_now);
     return r;
+  }
+
+  // Greedy pairwise order: the pair whose combined letters span the fewest elements.
+  static std::pair<size_t, size_t> pick_pair(const std::vector<Opnd>& ops, const LetterRange& lr) {
+    size_t bi = 0, bj = 1;
+    double best = 1e300;
+    for (size_t i = 0; i < ops.size(); ++i)
+      for (size_t j = i + 1; j < ops.size(); ++j) {
+        std::string u = ops[i].letters;
+        for (char c : ops[j].letters)
+          if (u.find(c) == std::string::npos) u += c;
+        double c = 1;
+        for (char l : u) c *= lr.len.at(l);
+        if (c < best) { best = c; bi = i; bj = j; }
+      }
+    return {bi, bj};
   }
 
   void check_operand(const char* what, const Opnd& o, const LetterRange& lr) {
@@ -526,18 +562,7 @@ struct Exec {
       return;
     }
     while (ops.size() > 2 || (ops.size() == 2 && !P.res.empty())) {
-      if (ops.size() == 1) break;
-      size_t bi = 0, bj = 1;
-      double best = 1e300;
-      for (size_t i = 0; i < ops.size(); ++i)
-        for (size_t j = i + 1; j < ops.size(); ++j) {
-          std::string u = ops[i].letters;
-          for (char c : ops[j].letters)
-            if (u.find(c) == std::string::npos) u += c;
-          double c = 1;
-          for (char l : u) c *= lr.len.at(l);
-          if (c < best) { best = c; bi = i; bj = j; }
-        }
+      auto [bi, bj] = pick_pair(ops, lr);
       Opnd r = contract(ops[bi], ops[bj], lr, temps);
       ops.erase(ops.begin() + bj);
       ops[bi] = r;
@@ -667,25 +692,324 @@ struct Exec {
     return lr;
   }
 
-  // Run a use of the table.  Scalar products write vals[i]/coefs[i] for a final weighted sum.
-  int use_id = 0;
-  void run_use(const Use& U, std::map<std::string, TensorRef>& outs, double* vals,
-               std::vector<double>& coefs) {
-    // products with the (PP|PP) block, grouped by the block's letters
-    std::map<std::string, std::vector<const TProduct*>> pppp;
-    int slot = 0;
-    int pidx = -1;
-    for (auto& P : U) {
-      ++pidx;
-      cur_product = use_id * 10000 + pidx;
-      std::string jl;
-      if (is_pppp(P, &jl)) {
-        // batch letter: a free letter of the block; rotate it to the first position
-        std::string key = jl;
-        for (auto& kv : P.space) key += std::string(1, kv.first) + kv.second;
-        pppp[key].push_back(&P);
-        continue;
+  // Host copies behind asynchronous uploads; they live until the call has synchronised.
+  std::deque<std::vector<char>> hold;
+  template <class T>
+  T* upload(const std::vector<T>& v) {
+    if (v.empty()) return nullptr;
+    size_t bytes = v.size() * sizeof(T);
+    double* dp = pool.alloc((bytes + 7) / 8);
+    hold.emplace_back((const char*)v.data(), (const char*)v.data() + bytes);
+    HIPCHECK(hipMemcpyAsync(dp, hold.back().data(), bytes, hipMemcpyHostToDevice, st));
+    return (T*)dp;
+  }
+
+  // A grouped launch, bracketed by events when profiling.
+  template <class F>
+  void group_launch(double flops, F&& launch) {
+    Rec r{nullptr, nullptr, kRoleGeneric, flops, 0, 0, 0, 0, 0, 0, -2};
+    if (profile) {
+      HIPCHECK(hipEventCreate(&r.a));
+      HIPCHECK(hipEventCreate(&r.b));
+      HIPCHECK(hipEventRecord(r.a, st));
+    }
+    launch();
+    if (profile) {
+      HIPCHECK(hipEventRecord(r.b, st));
+      recs.push_back(r);
+    }
+    gett_flops += flops;
+    ++n_launch;
+  }
+
+  // Sub-spaces of an output axis covered by a letter's space: bit 0 is the lower part of
+  // the axis (A of P, C of H), bit 1 the upper part (V of P, A of H).
+  static unsigned covers(char axis, char letter_space) {
+    if (axis == 'P') {
+      if (letter_space == 'P') return 3;
+      if (letter_space == 'A') return 1;
+      if (letter_space == 'V') return 2;
+    } else if (axis == 'H') {
+      if (letter_space == 'H') return 3;
+      if (letter_space == 'C') return 1;
+      if (letter_space == 'A') return 2;
+    }
+    throw Error(DSRG_E_HIP, "internal: output axis/letter space pair");
+  }
+
+  static DotDesc dot_desc(const Opnd& a, const Opnd& b, const LetterRange& lr) {
+    DotDesc dd;
+    dd.nk = (int)a.letters.size();
+    if (dd.nk > 2 * kMaxComp || a.letters.size() != b.letters.size())
+      throw Error(DSRG_E_HIP, "internal: scalar product shape");
+    dd.K = 1;
+    for (int i = 0; i < dd.nk; ++i) {
+      char l = a.letters[i];
+      size_t j = b.letters.find(l);
+      if (j == std::string::npos) throw Error(DSRG_E_HIP, "internal: scalar product letters");
+      dd.kd[i] = lr.len.at(l);
+      dd.as[i] = a.stride[i];
+      dd.bs[i] = b.stride[j];
+      dd.K *= dd.kd[i];
+    }
+    return dd;
+  }
+
+  // Grouped execution of the products of one use: every pairwise contraction writes its
+  // own temporary, contractions at the same depth of their product's chain run in one
+  // launch, scalar products end in one grouped dot launch and tensor products in one
+  // gather per output tensor (fixed entry order, so the sums are deterministic).  Returns
+  // false, having launched nothing, when the temporaries would exceed group_cap bytes.
+  bool run_grouped(const std::vector<std::pair<int, const TProduct*>>& prods,
+                   std::map<std::string, TensorRef>& outs, double* scalar_out) {
+    struct Fix {
+      long long a, b, c;   // arena offsets of A, B, C (-1: not a temporary)
+    };
+    std::vector<std::vector<GroupItem>> lev;
+    std::vector<std::vector<Fix>> levfix;
+    std::vector<DotItem> dots;
+    std::vector<std::pair<long long, long long>> dfix;
+    std::vector<double> dcoef;
+    struct GEnt {
+      GatherEntry e;
+      long long sfix;
+      unsigned mask;   // classes this entry contributes to
+    };
+    std::map<std::string, std::vector<GEnt>> gents;
+    long long arena = 0;
+    auto take = [&](long long n) {
+      long long o = arena;
+      arena += (n + 31) / 32 * 32;
+      return o;
+    };
+    for (auto& pp : prods) {
+      const TProduct& P = *pp.second;
+      LetterRange lr = full_range(P);
+      bool empty = false;
+      for (auto& kv : lr.len)
+        if (kv.second == 0) empty = true;
+      if (empty) continue;
+      std::vector<Opnd> ops;
+      for (auto& f : P.f) ops.push_back(factor_view(f, P.space, lr, nullptr, 0));
+      size_t level = 0;
+      while (ops.size() > 2 || (ops.size() == 2 && !P.res.empty())) {
+        auto [bi, bj] = pick_pair(ops, lr);
+        std::string ml, nl;
+        GettDesc g = pair_desc(ops[bi], ops[bj], lr, ml, nl);
+        Opnd r = result_operand(g, ml, nl, lr);
+        r.toff = take(r.lim);
+        if (lev.size() <= level) {
+          lev.resize(level + 1);
+          levfix.resize(level + 1);
+        }
+        GroupItem it;
+        it.g = g;
+        it.A = ops[bi].p;
+        it.B = ops[bj].p;
+        lev[level].push_back(it);
+        levfix[level].push_back({ops[bi].toff, ops[bj].toff, r.toff});
+        ops.erase(ops.begin() + bj);
+        ops[bi] = r;
+        ++level;
       }
+      if (P.res.empty()) {
+        if (ops.size() != 2) throw Error(DSRG_E_HIP, "internal: scalar product shape");
+        check_operand("dot A", ops[0], lr);
+        check_operand("dot B", ops[1], lr);
+        DotItem di;
+        di.d = dot_desc(ops[0], ops[1], lr);
+        di.A = ops[0].p;
+        di.B = ops[1].p;
+        di.nblk = (int)std::max<long long>(1, std::min<long long>(64, (di.d.K + 4095) / 4096));
+        dots.push_back(di);
+        dfix.push_back({ops[0].toff, ops[1].toff});
+        double c = 0;
+        for (auto& sc : P.s) c += sc.coef;
+        dcoef.push_back(c);
+      } else {
+        const Opnd& r = ops[0];
+        check_operand("gather source", r, lr);
+        for (auto& sc : P.s) {
+          std::string name = sc.tensor + "." + sc.block;
+          const TensorRef& o = outs.at(name);
+          const int rank = (int)sc.letters.size();
+          if (rank > 4 || rank != (int)o.axes.size()) throw Error(DSRG_E_HIP, "internal: gather rank");
+          GEnt ge;
+          ge.e.src = r.p;
+          ge.sfix = r.toff;
+          ge.e.coef = sc.coef;
+          unsigned allowed[4] = {1, 1, 1, 1};
+          long long base = 0;
+          for (int k = 0; k < rank; ++k) {
+            char l = sc.letters[k];
+            size_t pos = r.letters.find(l);
+            if (pos == std::string::npos) throw Error(DSRG_E_HIP, "internal: gather letter");
+            char ls = P.space.at(l);
+            ge.e.ss[k] = r.stride[pos];
+            base -= (long long)(d.off(ls) - d.off(o.axes[k])) * r.stride[pos];
+            allowed[k] = covers(o.axes[k], ls);
+          }
+          ge.e.base = base;
+          ge.mask = 0;
+          for (int c = 0; c < (1 << rank); ++c) {
+            bool ok = true;
+            for (int k = 0; k < rank; ++k) ok = ok && ((allowed[k] >> ((c >> k) & 1)) & 1);
+            if (ok) ge.mask |= 1u << c;
+          }
+          gents[name].push_back(ge);
+        }
+      }
+    }
+
+    // split-K for items with few tiles and a long k range; k tables; budget check
+    long long part_elems = 0, ksum = 0;
+    std::vector<std::vector<long long>> poff(lev.size());
+    for (size_t L = 0; L < lev.size(); ++L) {
+      for (auto& it : lev[L]) {
+        GettDesc& g = it.g;
+        it.tiles_m = (g.M + kGroupTile - 1) / kGroupTile;
+        it.tiles_n = (g.N + kGroupTile - 1) / kGroupTile;
+        long long tiles = (long long)it.tiles_m * it.tiles_n;
+        int ns = 1;
+        if (g.K >= 1024 && tiles < 64) {
+          long long want = std::min<long long>((g.K + 255) / 256, std::max<long long>(1, 256 / tiles));
+          int chunk = (int)((g.K + want - 1) / want);
+          chunk = (chunk + kGettBK - 1) / kGettBK * kGettBK;
+          ns = (g.K + chunk - 1) / chunk;
+          g.kchunk = chunk;
+        } else {
+          g.kchunk = g.K;
+        }
+        it.splits = ns;
+        poff[L].push_back(ns > 1 ? part_elems : -1);
+        if (ns > 1) part_elems += (long long)ns * g.M * g.N;
+        ksum += g.K;
+      }
+    }
+    long long bytes = 8 * (arena + part_elems + 2 * ksum);
+    if (bytes > group_cap) return false;
+
+    double* tbase = arena > 0 ? pool.alloc((size_t)arena) : nullptr;
+    double* pbase = part_elems > 0 ? pool.alloc((size_t)part_elems) : nullptr;
+    long long* kbase = ksum > 0 ? (long long*)pool.alloc((size_t)(2 * ksum)) : nullptr;
+    auto at = [&](long long off, const double* p) -> const double* { return off >= 0 ? tbase + off : p; };
+
+    // flatten the levels (longest tiles first inside a level) and patch the addresses
+    std::vector<GroupItem> items;
+    std::vector<int> split_idx;
+    struct LevelRange {
+      int i0, n, tiles, s0, ns;
+      long long red;
+      double flops;
+    };
+    std::vector<LevelRange> ranges;
+    long long kpos = 0;   // k-table prefix in the flattened order (the k-table launch searches it)
+    for (size_t L = 0; L < lev.size(); ++L) {
+      std::vector<int> order(lev[L].size());
+      for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+      std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
+        return lev[L][x].g.kchunk > lev[L][y].g.kchunk;
+      });
+      LevelRange R{(int)items.size(), (int)order.size(), 0, (int)split_idx.size(), 0, 0, 0.0};
+      for (int oi : order) {
+        GroupItem it = lev[L][oi];
+        const Fix& fx = levfix[L][oi];
+        it.A = at(fx.a, it.A);
+        it.B = at(fx.b, it.B);
+        it.C = tbase + fx.c;
+        it.kofs0 = kpos;
+        kpos += it.g.K;
+        it.g.ktab = kbase + 2 * it.kofs0;
+        it.g.part = it.splits > 1 ? pbase + poff[L][oi] : nullptr;
+        it.tile0 = R.tiles;
+        long long t = (long long)it.tiles_m * it.tiles_n * it.splits;
+        if (R.tiles + t >= (1LL << 31)) throw Error(DSRG_E_UNSUPPORTED, "grouped launch too large");
+        R.tiles += (int)t;
+        if (it.splits > 1) {
+          it.red0 = R.red;
+          R.red += (long long)it.g.M * it.g.N;
+          split_idx.push_back((int)items.size() - R.i0);
+          ++R.ns;
+        }
+        R.flops += 2.0 * it.g.M * (double)it.g.N * it.g.K;
+        items.push_back(it);
+      }
+      ranges.push_back(R);
+    }
+    GroupItem* d_items = upload(items);
+    int* d_split = upload(split_idx);
+    if (!items.empty()) group_launch(0.0, [&] { launch_group_kofs(d_items, (int)items.size(), ksum, st); });
+    for (auto& R : ranges) {
+      group_launch(R.flops, [&] { launch_gett_group(d_items + R.i0, R.n, R.tiles, st); });
+      if (R.ns > 0)
+        group_launch(0.0, [&] { launch_group_reduce(d_items + R.i0, d_split + R.s0, R.ns, R.red, st); });
+    }
+
+    if (scalar_out) {
+      int blocks = 0;
+      std::vector<double> bcoef;
+      for (size_t i = 0; i < dots.size(); ++i) {
+        dots[i].A = at(dfix[i].first, dots[i].A);
+        dots[i].B = at(dfix[i].second, dots[i].B);
+        dots[i].blk0 = blocks;
+        blocks += dots[i].nblk;
+        for (int b = 0; b < dots[i].nblk; ++b) bcoef.push_back(dcoef[i]);
+      }
+      if (blocks == 0) {
+        launch_fill(scalar_out, 1, 0.0, st);
+        ++n_launch;
+      } else {
+        double* part = pool.alloc((size_t)blocks);
+        DotItem* d_dots = upload(dots);
+        double* d_coef = upload(bcoef);
+        double fl = 0;
+        for (auto& di : dots) fl += 2.0 * di.d.K;
+        group_launch(fl, [&] { launch_dot_group(d_dots, (int)dots.size(), blocks, part, st); });
+        launch_weighted_sum(blocks, part, d_coef, scalar_out, st);
+        ++n_launch;
+      }
+    } else if (!dots.empty()) {
+      throw Error(DSRG_E_HIP, "internal: scalar products in a tensor use");
+    }
+
+    for (auto& kv : gents) {
+      const TensorRef& o = outs.at(kv.first);
+      GatherDesc gd;
+      gd.rank = (int)o.axes.size();
+      std::vector<GatherEntry> ent;
+      for (int k = 0; k < gd.rank; ++k) {
+        gd.dim[k] = d.len(o.axes[k]);
+        gd.split[k] = o.axes[k] == 'P' ? d.nA : d.nC;
+        if (o.stride[k] != (k + 1 < gd.rank ? o.stride[k + 1] * d.len(o.axes[k + 1]) : 1))
+          throw Error(DSRG_E_HIP, "internal: gather output must be contiguous");
+      }
+      for (int c = 0; c < (1 << gd.rank); ++c) {
+        gd.cls[c] = (int)ent.size();
+        for (auto& ge : kv.second)
+          if ((ge.mask >> c) & 1) {
+            GatherEntry e = ge.e;
+            e.src = at(ge.sfix, e.src);
+            ent.push_back(e);
+          }
+      }
+      gd.cls[1 << gd.rank] = (int)ent.size();
+      GatherEntry* d_ent = upload(ent);
+      launch_gather(gd, d_ent, o.p, st);
+      ++n_launch;
+    }
+    return true;
+  }
+
+  // One launch per contraction, temporaries reused from a free list.
+  void run_serial(const std::vector<std::pair<int, const TProduct*>>& prods,
+                  std::map<std::string, TensorRef>& outs, double* scalar_out) {
+    std::vector<double> coefs;
+    double* vals = scalar_out ? pool.alloc(prods.size() + 1) : nullptr;
+    if (vals) launch_fill(vals, (long long)prods.size() + 1, 0.0, st);
+    int slot = 0;
+    for (auto& pp : prods) {
+      cur_product = use_id * 10000 + pp.first;
+      const TProduct& P = *pp.second;
       double c = 0;
       run_product(P, full_range(P), nullptr, 0, outs, vals ? vals + slot : nullptr, c, 0);
       if (P.res.empty()) {
@@ -693,6 +1017,40 @@ struct Exec {
         ++slot;
       }
     }
+    if (scalar_out) {
+      if (coefs.empty()) {
+        launch_fill(scalar_out, 1, 0.0, st);
+      } else {
+        double* coefd = upload(coefs);
+        launch_weighted_sum((int)coefs.size(), vals, coefd, scalar_out, st);
+      }
+      ++n_launch;
+    }
+  }
+
+  // Run a use of the table into tensor outputs, or (scalar uses) into *scalar_out.
+  int use_id = 0;
+  bool grouped = true;
+  long long group_cap = 0;   // bytes of temporaries one grouped use may hold
+  void run_use(const Use& U, std::map<std::string, TensorRef>& outs, double* scalar_out) {
+    // products with the (PP|PP) block, grouped by the block's letters
+    std::map<std::string, std::vector<const TProduct*>> pppp;
+    std::vector<std::pair<int, const TProduct*>> plain;
+    int pidx = -1;
+    for (auto& P : U) {
+      ++pidx;
+      std::string jl;
+      if (is_pppp(P, &jl)) {
+        if (scalar_out) throw Error(DSRG_E_HIP, "internal: (PP|PP) block in a scalar use");
+        // batch letter: a free letter of the block; rotate it to the first position
+        std::string key = jl;
+        for (auto& kv : P.space) key += std::string(1, kv.first) + kv.second;
+        pppp[key].push_back(&P);
+        continue;
+      }
+      plain.push_back({pidx, &P});
+    }
+    if (!(grouped && run_grouped(plain, outs, scalar_out))) run_serial(plain, outs, scalar_out);
     for (auto& grp : pppp) {
       const TProduct& P0 = *grp.second[0];
       std::string L, key;
@@ -844,6 +1202,8 @@ static int run(const dsrg_problem* P, const dsrg_options* O, dsrg_result* R,
   }
 
   Exec X(d, st, pool, B, M, cap, O && (O->flags & DSRG_F_PROFILE));
+  X.grouped = !(O && (O->flags & DSRG_F_NO_GROUPING));
+  X.group_cap = cap / 2;
   // step a0: spin-orbital densities and cumulants over the active space
   const int n2 = 2 * nA;
   double *G1 = nullptr, *G2 = nullptr, *G3 = nullptr, *L2 = nullptr, *L3 = nullptr, *eta = nullptr;
@@ -918,21 +1278,12 @@ static int run(const dsrg_problem* P, const dsrg_options* O, dsrg_result* R,
 
   auto& T = table();
   const Use& C0 = T.at("C0");
-  size_t nslot = C0.size();
-  double* vals = pool.alloc(nslot + 4);
-  double* coefd = pool.alloc(nslot);
   double* energies = pool.alloc(4);
   launch_fill(energies, 4, 0.0, st);
-  std::vector<double> coefs;
   std::map<std::string, TensorRef> none;
   auto scalar = [&](double* outp) {
-    coefs.clear();
-    launch_fill(vals, (long long)nslot, 0.0, st);
     X.use_id = 0;
-    X.run_use(C0, none, vals, coefs);
-    HIPCHECK(hipMemcpyAsync(coefd, coefs.data(), coefs.size() * 8, hipMemcpyHostToDevice, st));
-    HIPCHECK(hipStreamSynchronize(st));   // coefs is a host buffer reused below
-    launch_weighted_sum((int)coefs.size(), vals, coefd, outp, st);
+    X.run_use(C0, none, outp);
   };
   // step a3: E(2) = <[H~(1), T(1)]>
   scalar(energies + 0);
@@ -959,9 +1310,8 @@ static int run(const dsrg_problem* P, const dsrg_options* O, dsrg_result* R,
       o["O2.aa"] = mk(p2, "PPHH"); o["O2.ab"] = mk(p2 + n4, "PPHH"); o["O2.bb"] = mk(p2 + 2 * n4, "PPHH");
     };
     bind_out(wout, W1a, W2);
-    std::vector<double> dummy;
     X.use_id = 1;
-    X.run_use(T.at("W"), wout, nullptr, dummy);
+    X.run_use(T.at("W"), wout, nullptr);
     HIPCHECK(hipEventRecord(ev[4], st));
     // step a6: Z = [Y, A(1)]_{1,2}
     double* Z1 = pool.alloc(2 * n1);
@@ -971,7 +1321,7 @@ static int run(const dsrg_problem* P, const dsrg_options* O, dsrg_result* R,
     std::map<std::string, TensorRef> zout;
     bind_out(zout, Z1, Z2);
     X.use_id = 2;
-    X.run_use(T.at("Z"), zout, nullptr, dummy);
+    X.run_use(T.at("Z"), zout, nullptr);
     HIPCHECK(hipEventRecord(ev[5], st));
     // second-order amplitudes and H~(2)_{1,2}
     double* U2 = pool.alloc(3 * n4);

@@ -7,6 +7,7 @@
 namespace dsrg {
 
 constexpr int kMaxComp = 6;   // index components per group (M, N or K)
+constexpr int kGettBK = 16;   // k step of the contraction kernel (split-K chunks are multiples)
 
 // A strided tensor contraction C[m][n] (+)= alpha * sum_k A[m][k] B[k][n], where m, n and
 // k are multi-indices (row-major composition of up to kMaxComp components) and every
@@ -53,6 +54,55 @@ constexpr int kRoleGeneric = 0, kRoleLadder = 1, kRoleIntegrals = 2;
 void launch_gett(const GettDesc& g, const double* A, const double* B, double* C, hipStream_t st,
                  int role, double* ws, long long ws_elems, long long* ktab);
 int gett_splits(const GettDesc& g, long long ws_elems);
+// ---- grouped execution: independent contractions of one dependency level per launch ----
+// Item i owns workgroups [tile0, tile0 + tiles_m * tiles_n * splits) of a grouped launch,
+// each a 64 x 64 output tile of one k chunk (g.kchunk).  With splits > 1 the partial tiles
+// go to g.part ([splits][M][N]) and launch_group_reduce writes C.  g.ktab points at this
+// item's k tables (2 K entries), filled by launch_group_kofs from kofs0 (prefix of K).
+constexpr int kGroupWM = 2, kGroupWN = 2, kGroupTile = 32 * kGroupWM;
+struct GroupItem {
+  GettDesc g;
+  const double* A = nullptr;
+  const double* B = nullptr;
+  double* C = nullptr;
+  int tiles_m = 0, tiles_n = 0, splits = 1;
+  int tile0 = 0;          // first workgroup of this item
+  long long kofs0 = 0;    // prefix of K over the items of the k-table launch
+  long long red0 = 0;     // prefix of M N over the split items of the reduction launch
+};
+void launch_group_kofs(const GroupItem* items, int n, long long ksum, hipStream_t st);
+void launch_gett_group(const GroupItem* items, int n, int tiles, hipStream_t st);
+// split_idx: indices of the items with splits > 1, in increasing red0
+void launch_group_reduce(const GroupItem* items, const int* split_idx, int nsplit, long long total,
+                         hipStream_t st);
+
+// Grouped dot products: workgroups [blk0, blk0 + nblk) of the launch sum item i; one
+// partial per workgroup.
+struct DotItem {
+  DotDesc d;
+  const double* A = nullptr;
+  const double* B = nullptr;
+  int blk0 = 0, nblk = 1;
+};
+void launch_dot_group(const DotItem* items, int n, int blocks, double* partial, hipStream_t st);
+
+// out[x] += sum over the entries of x's class of coef * src[base + sum_k x_k ss[k]], where
+// x is a row-major multi-index over dim[0..rank) and the class has bit k set when
+// x_k >= split[k].  Entries of class c are [cls[c], cls[c + 1]).
+struct GatherEntry {
+  const double* src = nullptr;
+  long long base = 0;
+  long long ss[4] = {};
+  double coef = 0;
+};
+struct GatherDesc {
+  int rank = 0;
+  int dim[4] = {1, 1, 1, 1};
+  int split[4] = {};
+  int cls[17] = {};
+};
+void launch_gather(const GatherDesc& g, const GatherEntry* entries, double* out, hipStream_t st);
+
 // partial: scratch of at least dot_partials() doubles; writes the sum into out[0]
 int dot_partials();
 void launch_dot(const DotDesc& d, const double* A, const double* B, double* partial, double* out,

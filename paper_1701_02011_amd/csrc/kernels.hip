@@ -36,24 +36,31 @@ __device__ __forceinline__ long long decode(int idx, int n, const int* d, const 
 // lane l holds A[l%16][l/16] and B[l/16][l%16]; accumulator element r of lane l is
 // D[l/16 + 4 r][l%16].
 // ---------------------------------------------------------------------------
-constexpr int BK = 16;
+constexpr int BK = kGettBK;
 
-template <int kRole, int WM, int WN>
-__global__ __launch_bounds__(256) void gett_f64_kernel(GettDesc g, const double* __restrict__ A,
-                                                       const double* __restrict__ B,
-                                                       double* __restrict__ C) {
+template <int WM, int WN>
+struct TileLds {
+  static constexpr int BM = 32 * WM, BN = 32 * WN;
+  static constexpr int LDA = BM + 2, LDB = BN + 2;
+  double As[2][BK * LDA];
+  double Bs[2][BK * LDB];
+};
+
+// One BM x BN output tile at (tile_m, tile_n) for k chunk kz of the contraction g.
+template <int WM, int WN>
+__device__ __forceinline__ void gett_tile(const GettDesc& g, const double* __restrict__ A,
+                                          const double* __restrict__ B, double* __restrict__ C,
+                                          int tile_m, int tile_n, int kz, TileLds<WM, WN>& lds) {
   constexpr int BM = 32 * WM, BN = 32 * WN;
   constexpr int LDA = BM + 2, LDB = BN + 2;
   constexpr int NA = BM * BK / 256, NB = BN * BK / 256;   // loads per thread per step
-  __shared__ double As[2][BK * LDA];
-  __shared__ double Bs[2][BK * LDB];
+  auto& As = lds.As;
+  auto& Bs = lds.Bs;
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  const int tile_m = blockIdx.x * BM;
-  const int tile_n = blockIdx.y * BN;
-  // split-K: workgroup z sums k in [k_lo, k_hi) and then writes a partial tile
-  const int k_lo = blockIdx.z * g.kchunk;
+  // split-K: chunk kz sums k in [k_lo, k_hi) and then writes a partial tile
+  const int k_lo = kz * g.kchunk;
   const int k_hi = min(g.K, k_lo + g.kchunk);
 
   // fixed per-thread load slots
@@ -151,7 +158,7 @@ __global__ __launch_bounds__(256) void gett_f64_kernel(GettDesc g, const double*
       int m = tile_m + wm + a * 16 + lk + 4 * r;
       if (m >= g.M) continue;
       if (g.part) {
-        double* prow = g.part + ((long long)blockIdx.z * g.M + m) * g.N;
+        double* prow = g.part + ((long long)kz * g.M + m) * g.N;
 #pragma unroll
         for (int b = 0; b < WN; ++b) {
           int n = tile_n + wn + b * 16 + li;
@@ -171,6 +178,14 @@ __global__ __launch_bounds__(256) void gett_f64_kernel(GettDesc g, const double*
       }
     }
   }
+}
+
+template <int kRole, int WM, int WN>
+__global__ __launch_bounds__(256) void gett_f64_kernel(GettDesc g, const double* __restrict__ A,
+                                                       const double* __restrict__ B,
+                                                       double* __restrict__ C) {
+  __shared__ TileLds<WM, WN> lds;
+  gett_tile<WM, WN>(g, A, B, C, blockIdx.x * (32 * WM), blockIdx.y * (32 * WN), blockIdx.z, lds);
 }
 
 // k -> offset tables of both operands: tab[k] (A) and tab[K + k] (B)
@@ -256,6 +271,182 @@ void launch_gett(const GettDesc& g0, const double* A, const double* B, double* C
     long long blocks = std::min<long long>((total + 255) / 256, 4096);
     hipLaunchKernelGGL(splitk_reduce_kernel, dim3((unsigned)blocks), dim3(256), 0, st, g, ws, ns, C);
   }
+}
+
+// ---------------------------------------------------------------------------
+// Grouped contractions: independent GETTs of one dependency level in a single launch.
+// Workgroup b finds its item by binary search over the items' first workgroups; items
+// never share an output element, so the launch is race-free and its result does not
+// depend on scheduling.
+// ---------------------------------------------------------------------------
+__device__ __forceinline__ int find_item_int(const GroupItem* __restrict__ items, int n, int b) {
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (items[mid].tile0 <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  return lo;
+}
+
+template <int WM, int WN>
+__global__ __launch_bounds__(256) void gett_group_kernel(const GroupItem* __restrict__ items, int n) {
+  __shared__ TileLds<WM, WN> lds;
+  const int b = blockIdx.x;
+  const GroupItem& it = items[find_item_int(items, n, b)];
+  const int t = b - it.tile0;
+  const int per = it.tiles_m * it.tiles_n;
+  const int kz = t / per;
+  const int r = t - kz * per;
+  const int tm = r / it.tiles_n;
+  const int tn = r - tm * it.tiles_n;
+  gett_tile<WM, WN>(it.g, it.A, it.B, it.C, tm * (32 * WM), tn * (32 * WN), kz, lds);
+}
+
+// k -> offset tables of every item: the item owning global k slot q is found by binary
+// search over kofs0 (prefix sums of K)
+__global__ __launch_bounds__(256) void group_kofs_kernel(const GroupItem* __restrict__ items, int n,
+                                                         long long ksum) {
+  for (long long q = blockIdx.x * 256LL + threadIdx.x; q < ksum; q += 256LL * gridDim.x) {
+    int lo = 0, hi = n - 1;
+    while (lo < hi) {
+      int mid = (lo + hi + 1) >> 1;
+      if (items[mid].kofs0 <= q) lo = mid;
+      else hi = mid - 1;
+    }
+    const GettDesc& g = items[lo].g;
+    const int k = (int)(q - items[lo].kofs0);
+    long long* tab = const_cast<long long*>(g.ktab);
+    tab[k] = decode(k, g.nk, g.kd, g.ak);
+    tab[g.K + k] = decode(k, g.nk, g.kd, g.bk);
+  }
+}
+
+// split-K items: C = alpha * sum_z part[z] (+ C), fixed order of z
+__global__ __launch_bounds__(256) void group_reduce_kernel(const GroupItem* __restrict__ items,
+                                                           const int* __restrict__ idx, int nsplit,
+                                                           long long total) {
+  for (long long q = blockIdx.x * 256LL + threadIdx.x; q < total; q += 256LL * gridDim.x) {
+    int lo = 0, hi = nsplit - 1;
+    while (lo < hi) {
+      int mid = (lo + hi + 1) >> 1;
+      if (items[idx[mid]].red0 <= q) lo = mid;
+      else hi = mid - 1;
+    }
+    const GroupItem& it = items[idx[lo]];
+    const GettDesc& g = it.g;
+    const long long i = q - it.red0;
+    const long long mn = (long long)g.M * g.N;
+    const int m = (int)(i / g.N), nn = (int)(i - (long long)m * g.N);
+    double s = 0.0;
+    for (int z = 0; z < it.splits; ++z) s += g.part[(long long)z * mn + i];
+    const long long o = decode(m, g.nm, g.md, g.cm) + decode(nn, g.nn, g.nd, g.cn);
+    double v = g.alpha * s;
+    if (g.beta) v += it.C[o];
+    it.C[o] = v;
+  }
+}
+
+void launch_group_kofs(const GroupItem* items, int n, long long ksum, hipStream_t st) {
+  if (n <= 0 || ksum <= 0) return;
+  long long blocks = std::min<long long>((ksum + 255) / 256, 4096);
+  hipLaunchKernelGGL(group_kofs_kernel, dim3((unsigned)blocks), dim3(256), 0, st, items, n, ksum);
+}
+
+void launch_gett_group(const GroupItem* items, int n, int tiles, hipStream_t st) {
+  if (n <= 0 || tiles <= 0) return;
+  hipLaunchKernelGGL((gett_group_kernel<kGroupWM, kGroupWN>), dim3((unsigned)tiles), dim3(256), 0,
+                     st, items, n);
+}
+
+void launch_group_reduce(const GroupItem* items, const int* split_idx, int nsplit, long long total,
+                         hipStream_t st) {
+  if (nsplit <= 0 || total <= 0) return;
+  long long blocks = std::min<long long>((total + 255) / 256, 4096);
+  hipLaunchKernelGGL(group_reduce_kernel, dim3((unsigned)blocks), dim3(256), 0, st, items, split_idx,
+                     nsplit, total);
+}
+
+// ---------------------------------------------------------------------------
+// Grouped dot products: block b of the launch adds its share of item i's sum into
+// partial[b]; the final weighted sum reads the partials in a fixed order.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void dot_group_kernel(const DotItem* __restrict__ items, int n,
+                                                        double* __restrict__ partial) {
+  __shared__ double red[256];
+  const int b = blockIdx.x;
+  int lo = 0, hi = n - 1;
+  while (lo < hi) {
+    int mid = (lo + hi + 1) >> 1;
+    if (items[mid].blk0 <= b) lo = mid;
+    else hi = mid - 1;
+  }
+  const DotItem& it = items[lo];
+  const int j = b - it.blk0;
+  double sum = 0.0;
+  for (long long i = j * 256LL + threadIdx.x; i < it.d.K; i += 256LL * it.nblk) {
+    long long oa = 0, ob = 0;
+    long long idx = i;
+    for (int c = it.d.nk - 1; c >= 0; --c) {
+      long long q = idx / it.d.kd[c];
+      long long r = idx - q * it.d.kd[c];
+      oa += r * it.d.as[c];
+      ob += r * it.d.bs[c];
+      idx = q;
+    }
+    sum += it.A[oa] * it.B[ob];
+  }
+  red[threadIdx.x] = sum;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) partial[b] = red[0];
+}
+
+void launch_dot_group(const DotItem* items, int n, int blocks, double* partial, hipStream_t st) {
+  if (n <= 0 || blocks <= 0) return;
+  hipLaunchKernelGGL(dot_group_kernel, dim3((unsigned)blocks), dim3(256), 0, st, items, n, partial);
+}
+
+// ---------------------------------------------------------------------------
+// Gather-accumulate into a contiguous output: element x (multi-index) belongs to the
+// class given by which sub-space each index falls in; every entry of that class adds
+// coef * src[base + sum_k x_k ss_k], in entry order.
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void gather_kernel(GatherDesc g, const GatherEntry* __restrict__ ent,
+                                                     double* __restrict__ out, long long total) {
+  for (long long e = blockIdx.x * 256LL + threadIdx.x; e < total; e += 256LL * gridDim.x) {
+    int x[4] = {0, 0, 0, 0};
+    long long idx = e;
+    int cls = 0;
+#pragma unroll
+    for (int k = 3; k >= 0; --k) {
+      if (k < g.rank) {
+        long long q = idx / g.dim[k];
+        x[k] = (int)(idx - q * g.dim[k]);
+        idx = q;
+        cls |= (x[k] >= g.split[k]) << k;
+      }
+    }
+    double acc = 0.0;
+    for (int i = g.cls[cls]; i < g.cls[cls + 1]; ++i) {
+      const GatherEntry& en = ent[i];
+      long long o = en.base + (long long)x[0] * en.ss[0] + (long long)x[1] * en.ss[1] +
+                    (long long)x[2] * en.ss[2] + (long long)x[3] * en.ss[3];
+      acc += en.coef * en.src[o];
+    }
+    if (g.cls[cls + 1] > g.cls[cls]) out[e] += acc;
+  }
+}
+
+void launch_gather(const GatherDesc& g, const GatherEntry* entries, double* out, hipStream_t st) {
+  long long total = 1;
+  for (int k = 0; k < g.rank; ++k) total *= g.dim[k];
+  if (total <= 0 || g.cls[1 << g.rank] == 0) return;
+  long long blocks = std::min<long long>((total + 255) / 256, 8192);
+  hipLaunchKernelGGL(gather_kernel, dim3((unsigned)blocks), dim3(256), 0, st, g, entries, out, total);
 }
 
 // ---------------------------------------------------------------------------
@@ -610,17 +801,24 @@ void launch_second_order_h1(AmpDims d, const double* W1, const double* Z1, const
                      H1);
 }
 
-__global__ void weighted_sum_kernel(int n, const double* __restrict__ vals,
-                                    const double* __restrict__ coef, double* __restrict__ out) {
-  if (threadIdx.x == 0 && blockIdx.x == 0) {
-    double s = 0.0;
-    for (int i = 0; i < n; ++i) s += coef[i] * vals[i];
-    out[0] = s;
+// one workgroup; thread t sums elements t, t + 256, ... and a fixed tree combines them
+__global__ __launch_bounds__(256) void weighted_sum_kernel(int n, const double* __restrict__ vals,
+                                                           const double* __restrict__ coef,
+                                                           double* __restrict__ out) {
+  __shared__ double red[256];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < n; i += 256) s += coef[i] * vals[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
   }
+  if (threadIdx.x == 0) out[0] = red[0];
 }
 
 void launch_weighted_sum(int n, const double* vals, const double* coef, double* out, hipStream_t st) {
-  hipLaunchKernelGGL(weighted_sum_kernel, dim3(1), dim3(64), 0, st, n, vals, coef, out);
+  hipLaunchKernelGGL(weighted_sum_kernel, dim3(1), dim3(256), 0, st, n, vals, coef, out);
 }
 
 __global__ void fill_kernel(double* __restrict__ p, long long n, double v) {

@@ -155,11 +155,34 @@ def test_small_batched_pppp_matches_unbatched():
     """The (PP|PP) integrals in several virtual batches give the same energies."""
     p = make_config("small")
     say("small batched")
-    a = _lib.dsrg_pt3_energy(p)
+    a = _lib.dsrg_pt3_energy(p, grouping=False)
     nP = p.n_active + p.n_virtual
-    b = _lib.dsrg_pt3_energy(p, workspace_cap=7 * nP ** 3 * 8)
+    b = _lib.dsrg_pt3_energy(p, workspace_cap=7 * nP ** 3 * 8, grouping=False)
     assert b["ladder_batch"] == 7
     assert _close(b["e2"], a["e2"], 1e-13) and _close(b["e3"], a["e3"], 1e-13)
+
+
+@pytest.mark.parametrize("name", ["micro", "nocore", "tiny", "small"])
+def test_grouped_matches_per_launch(name):
+    """Grouped launches (default) and one launch per contraction: same intermediates and
+    energies up to summation order; both deterministic."""
+    if name == "micro":
+        p = make_problem(2, 2, 4, 9, seed=5, s=1.3)
+    elif name == "nocore":
+        p = make_problem(0, 3, 3, 7, seed=19, s=0.8)
+    else:
+        p = make_config(name)
+    say("grouped vs per-launch", name)
+    a = _lib.dsrg_pt3_energy_ex(p, grouping=False)
+    b = _lib.dsrg_pt3_energy_ex(p)
+    for k in ("t1", "t2", "w1", "w2", "z1", "z2", "u1", "u2"):
+        scale = max(1.0, np.abs(a[k]).max())
+        assert np.abs(a[k] - b[k]).max() <= 1e-12 * scale, k
+    for k in ("e2", "e3_a", "e3_b"):
+        assert _close(b[k], a[k], 1e-12), (k, a[k], b[k])
+    c = _lib.dsrg_pt3_energy(p)
+    assert c["e2"] == b["e2"] and c["e3"] == b["e3"]
+    assert c["n_launch"] < a["n_launch"]
 
 
 def test_nonfinite_device_input():
