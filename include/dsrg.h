@@ -22,8 +22,16 @@
  *     input) of the unrelaxed series (Eq. E_unrelaxed).
  *   - All arrays are FP64, C (row-major) order.
  *
+ * Execution: the first call of a shape (device, nC, nA, nV, n_aux, gamma3 given or not,
+ * E(2) or E(3), grouping, workspace_cap) runs the pipeline and records it as a plan: its
+ * device buffers plus a HIP graph of every launch.  Later calls of that shape copy their
+ * inputs into the plan's buffers and launch the graph on the caller's stream; the result
+ * is bitwise the same as the recording run's would be for the same inputs.  At most 4
+ * plans (16 GiB) are kept, least recently used first out; dsrg_release_cache() frees them.
+ * Calls with DSRG_F_PROFILE, DSRG_F_NO_PLAN_CACHE or intermediates run without a plan.
+ *
  * Thread safety: calls may run concurrently from different host threads on different
- * streams; each call allocates and frees its own device workspace.
+ * streams.  A call that finds the plan of its shape in use by another call runs without one.
  */
 #ifndef DSRG_H
 #define DSRG_H
@@ -51,6 +59,7 @@ extern "C" {
                                    per dependency level) whenever their temporaries fit in half of
                                    workspace_cap; results agree to rounding either way, and each
                                    mode is deterministic. */
+#define DSRG_F_NO_PLAN_CACHE 8  /* neither use nor record a cached plan (see Execution above) */
 
 typedef struct {
   int32_t n_core, n_active, n_virtual, n_aux;
@@ -85,10 +94,11 @@ typedef struct {
   double e3_b;            /* <[H~(2)_{1,2}, T(1)]> */
   double t_seconds[8];    /* device time: [0] densities+integrals, [1] first order, [2] E(2),
                              [3] [V,A] (ladders, rings), [4] [Y,A], [5] second order + E(3),
-                             [6] unused, [7] whole call */
+                             [6] unused, [7] whole pipeline.  A call that replays a plan
+                             fills [7] only. */
   double gett_flops;      /* floating-point operations issued by the contraction kernels */
   double ladder_flops;    /* of which the (PP|PP) particle-particle ladder (Sec. III) */
-  double ladder_seconds;  /* device time of the ladder contractions (GETT launches only) */
+  double ladder_seconds;  /* with DSRG_F_PROFILE: device time of the (PP|PP) ladder groups */
   int32_t ladder_batch;   /* virtual batch size used for the (PP|PP) integrals */
   int32_t n_launch;       /* kernel launches issued */
   /* with DSRG_F_PROFILE: contraction launches by role [0] table products, [1] (PP|PP)
@@ -96,6 +106,9 @@ typedef struct {
   double role_seconds[3];
   double role_flops[3];
   int32_t role_launches[3];
+  int32_t plan;           /* 0: ran without a plan, 1: ran and recorded a plan, 2: replayed one */
+  int32_t grouped_uses;   /* commutator evaluations run as grouped launches (the others ran
+                             one launch per contraction) */
 } dsrg_result;
 
 /* Optional host outputs of intermediates (each pointer may be NULL).  Shapes use
@@ -128,6 +141,10 @@ const char* dsrg_last_error(void);
 
 /* Library version: major * 10000 + minor * 100 + patch. */
 int dsrg_version(void);
+
+/* Free the cached plans (device buffers and graphs) that no call is using.  Returns
+   DSRG_OK. */
+int dsrg_release_cache(void);
 
 #ifdef __cplusplus
 }

@@ -117,8 +117,13 @@ def anti_hermitian(t1, t2):
     return t1 - t1.T, t2 - t2.transpose(2, 3, 0, 1)
 
 
-def run(prob: Problem, keep_full: bool = False) -> Result:
-    """E^(2) and E^(3) of the unrelaxed DSRG-MRPT3 (Eqs. E(2), E(3), E_unrelaxed)."""
+def run(prob: Problem, keep_full: bool = False, through: str = "e3") -> Result:
+    """E^(2) and E^(3) of the unrelaxed DSRG-MRPT3 (Eqs. E(2), E(3), E_unrelaxed).
+
+    through="e2" stops after E^(2) (steps a0-a3); the third-order fields are then NaN/None.
+    """
+    if through not in ("e2", "e3"):
+        raise ValueError("through must be 'e2' or 'e3'")
     sp = Spaces(prob.n_core, prob.n_active, prob.n_virtual)
     s = prob.s
     n = 2 * sp.N
@@ -145,6 +150,10 @@ def run(prob: Problem, keep_full: bool = False) -> Result:
     T1 = gno.to_plain(0.0, t1, t2)
     # step a3: E^(2) = <[H~(1), T(1)]>  (Eq. E(2))
     e2, _, _ = gno.commutator(Ht1, T1, dens, want0=True)
+    if through == "e2":
+        nan = float("nan")
+        return Result(float(e2), nan, nan, nan, sp, eps, t1, t2, None, None, None, None,
+                      None, None, None, None)
     # steps a4-a5: O1 = [H~(1), A(1)]_{1,2}, excitation blocks (Eq. Hbar_2nd)
     _, o1_1, o1_2p = gno.commutator(Ht1, A1, dens, want1=(P, H), want2=(P, P, H, H))
     o1_2 = gno.c_from_plain2(o1_2p)

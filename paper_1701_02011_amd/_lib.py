@@ -24,6 +24,7 @@ DSRG_E_UNSUPPORTED = -5
 DSRG_F_DEVICE_PTRS = 1
 DSRG_F_PROFILE = 2
 DSRG_F_NO_GROUPING = 4
+DSRG_F_NO_PLAN_CACHE = 8
 
 _dp = ctypes.POINTER(ctypes.c_double)
 
@@ -46,7 +47,8 @@ class Result(ctypes.Structure):
                 ("gett_flops", ctypes.c_double), ("ladder_flops", ctypes.c_double),
                 ("ladder_seconds", ctypes.c_double), ("ladder_batch", ctypes.c_int32),
                 ("n_launch", ctypes.c_int32), ("role_seconds", ctypes.c_double * 3),
-                ("role_flops", ctypes.c_double * 3), ("role_launches", ctypes.c_int32 * 3)]
+                ("role_flops", ctypes.c_double * 3), ("role_launches", ctypes.c_int32 * 3),
+                ("plan", ctypes.c_int32), ("grouped_uses", ctypes.c_int32)]
 
 
 class Intermediates(ctypes.Structure):
@@ -84,6 +86,7 @@ def load() -> ctypes.CDLL:
         lib.dsrg_pt3_energy_ex.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(Options),
                                            ctypes.POINTER(Result), ctypes.POINTER(Intermediates)]
         lib.dsrg_pt3_energy_ex.restype = ctypes.c_int
+        lib.dsrg_release_cache.restype = ctypes.c_int
         lib.dsrg_last_error.restype = ctypes.c_char_p
         lib.dsrg_version.restype = ctypes.c_int
         ip = ctypes.POINTER(ctypes.c_int)
@@ -150,7 +153,8 @@ def _result_dict(r: Result):
                 gett_flops=r.gett_flops, ladder_flops=r.ladder_flops,
                 ladder_seconds=r.ladder_seconds, ladder_batch=r.ladder_batch,
                 n_launch=r.n_launch, role_seconds=list(r.role_seconds),
-                role_flops=list(r.role_flops), role_launches=list(r.role_launches))
+                role_flops=list(r.role_flops), role_launches=list(r.role_launches), plan=r.plan,
+                grouped_uses=r.grouped_uses)
 
 
 def _stream_of(p, stream):
@@ -162,28 +166,35 @@ def _stream_of(p, stream):
     return None
 
 
-def _flags(fl, profile=False, grouping=True):
+def _flags(fl, profile=False, grouping=True, cache=True):
     if profile:
         fl |= DSRG_F_PROFILE
     if not grouping:
         fl |= DSRG_F_NO_GROUPING
+    if not cache:
+        fl |= DSRG_F_NO_PLAN_CACHE
     return fl
 
 
-def dsrg_pt2_energy(p, stream=None, workspace_cap=0, grouping=True):
+def release_cache():
+    """Free the library's cached plans (device buffers and graphs)."""
+    _check(load().dsrg_release_cache())
+
+
+def dsrg_pt2_energy(p, stream=None, workspace_cap=0, grouping=True, cache=True):
     keep = []
     st, fl = _problem_struct(p, keep)
-    fl = _flags(fl, grouping=grouping)
+    fl = _flags(fl, grouping=grouping, cache=cache)
     r = Result()
     _check(load().dsrg_pt2_energy(ctypes.byref(st), ctypes.byref(
         _options(fl, _stream_of(p, stream), workspace_cap)), ctypes.byref(r)))
     return _result_dict(r)
 
 
-def dsrg_pt3_energy(p, stream=None, workspace_cap=0, profile=False, grouping=True):
+def dsrg_pt3_energy(p, stream=None, workspace_cap=0, profile=False, grouping=True, cache=True):
     keep = []
     st, fl = _problem_struct(p, keep)
-    fl = _flags(fl, profile, grouping)
+    fl = _flags(fl, profile, grouping, cache)
     r = Result()
     _check(load().dsrg_pt3_energy(ctypes.byref(st), ctypes.byref(
         _options(fl, _stream_of(p, stream), workspace_cap)), ctypes.byref(r)))

@@ -17,6 +17,7 @@
 #include <cstring>
 #include <cstdlib>
 #include <deque>
+#include <functional>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -151,13 +152,19 @@ static const char* storage_axes(const std::string& t) {
 }
 
 // ---------------------------------------------------------------------------
-// Device memory: call-scoped allocations
+// Device memory.  A call-scoped pool frees its buffers when the call ends; a plan-owned
+// pool (keep = true) never frees before the plan is destroyed, because a captured graph
+// addresses every buffer of the pipeline.
 // ---------------------------------------------------------------------------
 struct Pool {
-  hipStream_t st;
+  hipStream_t st;     // synchronised before freeing while sync_before_free is set
+  bool keep;
+  bool sync_before_free = true;
   std::vector<void*> bufs;
   size_t bytes = 0;
-  explicit Pool(hipStream_t s) : st(s) {}
+  explicit Pool(hipStream_t s, bool keep_ = false) : st(s), keep(keep_) {}
+  Pool(const Pool&) = delete;
+  Pool& operator=(const Pool&) = delete;
   double* alloc(size_t n) {
     if (n == 0) n = 1;
     void* p = nullptr;
@@ -171,6 +178,7 @@ struct Pool {
     return (double*)p;
   }
   void release(double* p) {
+    if (keep) return;
     for (auto& b : bufs)
       if (b == p) {
         (void)hipFree(b);
@@ -178,9 +186,21 @@ struct Pool {
       }
   }
   ~Pool() {
-    (void)hipStreamSynchronize(st);
+    if (sync_before_free) (void)hipStreamSynchronize(st);
     for (void* p : bufs)
       if (p) (void)hipFree(p);
+  }
+};
+
+// Device operations of the pipeline: each runs at once on the call's stream and, while a
+// plan is being built, is also kept (by value) for capture into a HIP graph.
+using DevOp = std::function<void(hipStream_t)>;
+struct OpLog {
+  hipStream_t st;
+  std::vector<DevOp>* rec = nullptr;
+  void operator()(DevOp f) {
+    f(st);
+    if (rec) rec->push_back(std::move(f));
   }
 };
 
@@ -220,6 +240,7 @@ struct Exec {
   Dims d;
   hipStream_t st;
   Pool& pool;
+  OpLog& op;
   const double* B;   // [M][N][N] device
   int M;
   std::map<std::string, TensorRef> tensors;   // "T2.aa" -> view
@@ -229,8 +250,8 @@ struct Exec {
   double gett_flops = 0, ladder_flops = 0, ladder_ms = 0;
   int ladder_batch = 0, n_launch = 0;
 
-  Exec(Dims d_, hipStream_t s, Pool& p, const double* B_, int M_, long long cap, bool prof)
-      : d(d_), st(s), pool(p), B(B_), M(M_), ws_cap(cap), profile(prof) {
+  Exec(Dims d_, hipStream_t s, Pool& p, OpLog& o, const double* B_, int M_, long long cap, bool prof)
+      : d(d_), st(s), pool(p), op(o), B(B_), M(M_), ws_cap(cap), profile(prof) {
     partial = pool.alloc(dot_partials());
     splitk_ws = pool.alloc((size_t)splitk_elems);
   }
@@ -270,7 +291,10 @@ struct Exec {
       HIPCHECK(hipEventCreate(&r.b));
       HIPCHECK(hipEventRecord(r.a, st));
     }
-    launch_gett(g, A, Bp, C, st, role, splitk_ws, splitk_elems, ktab_for(g.K));
+    long long* kt = ktab_for(g.K);
+    double* ws = splitk_ws;
+    long long wse = splitk_elems;
+    op([g, A, Bp, C, role, ws, wse, kt](hipStream_t s) { launch_gett(g, A, Bp, C, s, role, ws, wse, kt); });
     if (profile) {
       HIPCHECK(hipEventRecord(r.b, st));
       recs.push_back(r);
@@ -585,7 +609,11 @@ struct Exec {
       }
       check_operand("dot A", a, lr);
       check_operand("dot B", b, lr);
-      launch_dot(dd, a.p, b.p, partial, slot, st);
+      {
+        const double *pa = a.p, *pb = b.p;
+        double* part = partial;
+        op([dd, pa, pb, part, slot](hipStream_t s) { launch_dot(dd, pa, pb, part, slot, s); });
+      }
       n_launch += 2;
       gett_flops += 2.0 * dd.K;
       double c = 0;
@@ -614,7 +642,11 @@ struct Exec {
           std::vector<int> len(sd.d, sd.d + sd.rank);
           check_view("scatter target", o.lim - ooff, so, len);
         }
-        launch_scatter(sd, r.p, o.p + ooff, st);
+        {
+          const double* src = r.p;
+          double* dst = o.p + ooff;
+          op([sd, src, dst](hipStream_t s) { launch_scatter(sd, src, dst, s); });
+        }
         ++n_launch;
       }
     }
@@ -705,16 +737,18 @@ struct Exec {
   }
 
   // A grouped launch, bracketed by events when profiling.
-  template <class F>
-  void group_launch(double flops, F&& launch) {
+  // A grouped launch.  With profiling, the contraction launches (timed = true) are
+  // bracketed by events and counted under the generic role; helper launches are not.
+  void group_launch(double flops, DevOp launch, bool timed = false) {
     Rec r{nullptr, nullptr, kRoleGeneric, flops, 0, 0, 0, 0, 0, 0, -2};
-    if (profile) {
+    timed = timed && profile;
+    if (timed) {
       HIPCHECK(hipEventCreate(&r.a));
       HIPCHECK(hipEventCreate(&r.b));
       HIPCHECK(hipEventRecord(r.a, st));
     }
-    launch();
-    if (profile) {
+    op(std::move(launch));
+    if (timed) {
       HIPCHECK(hipEventRecord(r.b, st));
       recs.push_back(r);
     }
@@ -938,11 +972,16 @@ struct Exec {
     }
     GroupItem* d_items = upload(items);
     int* d_split = upload(split_idx);
-    if (!items.empty()) group_launch(0.0, [&] { launch_group_kofs(d_items, (int)items.size(), ksum, st); });
+    if (!items.empty()) {
+      const int n = (int)items.size();
+      group_launch(0.0, [d_items, n, ksum](hipStream_t s) { launch_group_kofs(d_items, n, ksum, s); });
+    }
     for (auto& R : ranges) {
-      group_launch(R.flops, [&] { launch_gett_group(d_items + R.i0, R.n, R.tiles, st); });
+      const GroupItem* it = d_items + R.i0;
+      const int* sp = d_split + R.s0;
+      group_launch(R.flops, [it, R](hipStream_t s) { launch_gett_group(it, R.n, R.tiles, s); }, true);
       if (R.ns > 0)
-        group_launch(0.0, [&] { launch_group_reduce(d_items + R.i0, d_split + R.s0, R.ns, R.red, st); });
+        group_launch(0.0, [it, sp, R](hipStream_t s) { launch_group_reduce(it, sp, R.ns, R.red, s); });
     }
 
     if (scalar_out) {
@@ -956,7 +995,7 @@ struct Exec {
         for (int b = 0; b < dots[i].nblk; ++b) bcoef.push_back(dcoef[i]);
       }
       if (blocks == 0) {
-        launch_fill(scalar_out, 1, 0.0, st);
+        op([scalar_out](hipStream_t s) { launch_fill(scalar_out, 1, 0.0, s); });
         ++n_launch;
       } else {
         double* part = pool.alloc((size_t)blocks);
@@ -964,8 +1003,13 @@ struct Exec {
         double* d_coef = upload(bcoef);
         double fl = 0;
         for (auto& di : dots) fl += 2.0 * di.d.K;
-        group_launch(fl, [&] { launch_dot_group(d_dots, (int)dots.size(), blocks, part, st); });
-        launch_weighted_sum(blocks, part, d_coef, scalar_out, st);
+        const int nd = (int)dots.size();
+        group_launch(fl, [d_dots, nd, blocks, part](hipStream_t s) {
+          launch_dot_group(d_dots, nd, blocks, part, s);
+        });
+        op([blocks, part, d_coef, scalar_out](hipStream_t s) {
+          launch_weighted_sum(blocks, part, d_coef, scalar_out, s);
+        });
         ++n_launch;
       }
     } else if (!dots.empty()) {
@@ -994,7 +1038,8 @@ struct Exec {
       }
       gd.cls[1 << gd.rank] = (int)ent.size();
       GatherEntry* d_ent = upload(ent);
-      launch_gather(gd, d_ent, o.p, st);
+      double* dst = o.p;
+      op([gd, d_ent, dst](hipStream_t s) { launch_gather(gd, d_ent, dst, s); });
       ++n_launch;
     }
     return true;
@@ -1005,7 +1050,10 @@ struct Exec {
                   std::map<std::string, TensorRef>& outs, double* scalar_out) {
     std::vector<double> coefs;
     double* vals = scalar_out ? pool.alloc(prods.size() + 1) : nullptr;
-    if (vals) launch_fill(vals, (long long)prods.size() + 1, 0.0, st);
+    if (vals) {
+      const long long nv = (long long)prods.size() + 1;
+      op([vals, nv](hipStream_t s) { launch_fill(vals, nv, 0.0, s); });
+    }
     int slot = 0;
     for (auto& pp : prods) {
       cur_product = use_id * 10000 + pp.first;
@@ -1019,10 +1067,11 @@ struct Exec {
     }
     if (scalar_out) {
       if (coefs.empty()) {
-        launch_fill(scalar_out, 1, 0.0, st);
+        op([scalar_out](hipStream_t s) { launch_fill(scalar_out, 1, 0.0, s); });
       } else {
         double* coefd = upload(coefs);
-        launch_weighted_sum((int)coefs.size(), vals, coefd, scalar_out, st);
+        const int nc = (int)coefs.size();
+        op([nc, vals, coefd, scalar_out](hipStream_t s) { launch_weighted_sum(nc, vals, coefd, scalar_out, s); });
       }
       ++n_launch;
     }
@@ -1030,6 +1079,7 @@ struct Exec {
 
   // Run a use of the table into tensor outputs, or (scalar uses) into *scalar_out.
   int use_id = 0;
+  int grouped_uses = 0;
   bool grouped = true;
   long long group_cap = 0;   // bytes of temporaries one grouped use may hold
   void run_use(const Use& U, std::map<std::string, TensorRef>& outs, double* scalar_out) {
@@ -1050,7 +1100,8 @@ struct Exec {
       }
       plain.push_back({pidx, &P});
     }
-    if (!(grouped && run_grouped(plain, outs, scalar_out))) run_serial(plain, outs, scalar_out);
+    if (grouped && run_grouped(plain, outs, scalar_out)) ++grouped_uses;
+    else run_serial(plain, outs, scalar_out);
     for (auto& grp : pppp) {
       const TProduct& P0 = *grp.second[0];
       std::string L, key;
@@ -1071,11 +1122,13 @@ struct Exec {
       long long nb = std::max(1LL, std::min<long long>(lbl, ws_cap / (8 * per)));
       ladder_batch = (int)nb;
       // products are written with the batch letter first in the J factor: rotate letters
-      double* jb = pool.alloc((size_t)(nb * per));
-      hipEvent_t e0, e1;
-      HIPCHECK(hipEventCreate(&e0));
-      HIPCHECK(hipEventCreate(&e1));
-      HIPCHECK(hipEventRecord(e0, st));
+      double* jb = jbatch_buffer(nb * per);
+      hipEvent_t e0 = nullptr, e1 = nullptr;
+      if (profile) {
+        HIPCHECK(hipEventCreate(&e0));
+        HIPCHECK(hipEventCreate(&e1));
+        HIPCHECK(hipEventRecord(e0, st));
+      }
       for (int b0 = 0; b0 < lbl; b0 += (int)nb) {
         int n1 = (int)std::min<long long>(nb, lbl - b0);
         // J(P P | P P) batch with the first index in [b0, b0+n1) of the batch letter's space
@@ -1096,15 +1149,29 @@ struct Exec {
         }
         ladder_flops += gett_flops - fb;  // integral batch build plus the ladder products
       }
-      HIPCHECK(hipEventRecord(e1, st));
-      HIPCHECK(hipEventSynchronize(e1));
-      float ms = 0;
-      HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
-      ladder_ms += ms;
-      (void)hipEventDestroy(e0);
-      (void)hipEventDestroy(e1);
-      pool.release(jb);
+      if (profile) {
+        HIPCHECK(hipEventRecord(e1, st));
+        HIPCHECK(hipEventSynchronize(e1));
+        float ms = 0;
+        HIPCHECK(hipEventElapsedTime(&ms, e0, e1));
+        ladder_ms += ms;
+        (void)hipEventDestroy(e0);
+        (void)hipEventDestroy(e1);
+      }
     }
+  }
+
+  // (PP|PP) batch buffer, shared by the ladder groups of the call (stream order makes the
+  // reuse safe)
+  double* jb_buf = nullptr;
+  long long jb_cap = 0;
+  double* jbatch_buffer(long long n) {
+    if (n > jb_cap) {
+      if (jb_buf) pool.release(jb_buf);
+      jb_buf = pool.alloc((size_t)n);
+      jb_cap = n;
+    }
+    return jb_buf;
   }
 
   // Rewrite J(l1 l2|l3 l4) so that letter bl comes first (symmetries of real (pr|qs)).
@@ -1132,97 +1199,108 @@ __global__ void count_nonfinite_kernel(const double* __restrict__ p, long long n
     if (!isfinite(p[i])) atomicAdd(bad, 1);
 }
 
-static int run(const dsrg_problem* P, const dsrg_options* O, dsrg_result* R,
-               const dsrg_intermediates* I, bool pt3) {
-  if (!P || !R) throw Error(DSRG_E_ARG, "null problem or result");
-  const int nC = P->n_core, nA = P->n_active, nV = P->n_virtual, M = P->n_aux;
-  if (nC < 0 || nA < 0 || nV < 0) throw Error(DSRG_E_ARG, "negative orbital count");
-  if (M < 1) throw Error(DSRG_E_ARG, "n_aux must be >= 1");
-  if (nC + nA + nV < 1) throw Error(DSRG_E_ARG, "no orbitals");
-  if (!(P->s > 0.0)) throw Error(DSRG_E_ARG, "s must be > 0");
-  if (!P->eps || !P->B) throw Error(DSRG_E_ARG, "null eps or B");
-  if (nA > 0 && (!P->gamma1 || !P->gamma2)) throw Error(DSRG_E_ARG, "null gamma1/gamma2 with nA > 0");
-  if (nA > 8) throw Error(DSRG_E_UNSUPPORTED, "active spaces above 8 orbitals are not built");
-  if (O && O->precision != 0) throw Error(DSRG_E_UNSUPPORTED, "only FP64 is built");
-  const bool devptr = O && (O->flags & DSRG_F_DEVICE_PTRS);
-  const int N = nC + nA + nV, nH = nC + nA, nP = nA + nV;
-  const long long nB = (long long)M * N * N;
-  const long long g1n = 2LL * nA * nA, g2n = 3LL * nA * nA * nA * nA,
-                  g3n = 4LL * nA * nA * nA * nA * nA * nA;
-  const bool has_g3 = nA > 0 && P->gamma3;
-  if (!devptr) {
-    if (!finite_host(P->eps, N) || !finite_host(P->B, nB) ||
-        (nA > 0 && (!finite_host(P->gamma1, g1n) || !finite_host(P->gamma2, g2n))) ||
-        (has_g3 && !finite_host(P->gamma3, g3n)))
-      throw Error(DSRG_E_NONFINITE, "non-finite value in eps, B or the densities");
+// Shape of a call and the device copies of its inputs.  The pipeline reads only these
+// copies (and s from device memory), so a graph captured once serves every later call of
+// the same shape, whatever the input values, s and input pointers.
+struct Shape {
+  int nC, nA, nV, M;
+  bool has_g3, pt3;
+  long long N, nB, g1n, g2n, g3n;
+};
+
+struct Inputs {
+  double *eps = nullptr, *B = nullptr, *g1 = nullptr, *g2 = nullptr, *g3 = nullptr;
+  double* s = nullptr;         // [1]
+  double* energies = nullptr;  // [4]: E(2), E(3)_a, E(3)_b, unused
+  int* bad = nullptr;          // non-finite counter for device inputs
+};
+
+static Inputs alloc_inputs(Pool& pool, const Shape& sh) {
+  Inputs in;
+  in.eps = pool.alloc((size_t)sh.N);
+  in.B = pool.alloc((size_t)sh.nB);
+  if (sh.nA > 0) {
+    in.g1 = pool.alloc((size_t)sh.g1n);
+    in.g2 = pool.alloc((size_t)sh.g2n);
   }
-  hipStream_t st = (O && O->stream) ? (hipStream_t)O->stream : (hipStream_t)0;
-  long long cap = (O && O->workspace_cap > 0) ? O->workspace_cap : (8LL << 30);
-  Dims d{nC, nA, nV};
-  Pool pool(st);
+  if (sh.has_g3) in.g3 = pool.alloc((size_t)sh.g3n);
+  in.s = pool.alloc(1);
+  in.energies = pool.alloc(4);
+  in.bad = (int*)pool.alloc(1);
+  return in;
+}
 
-  hipEvent_t ev[8];
-  for (auto& e : ev) HIPCHECK(hipEventCreate(&e));
-  struct EvGuard {
-    hipEvent_t* e;
-    ~EvGuard() { for (int i = 0; i < 8; ++i) (void)hipEventDestroy(e[i]); }
-  } evg{ev};
-  HIPCHECK(hipEventRecord(ev[0], st));
-
-  // inputs on the device
-  const double *eps, *B, *g1 = nullptr, *g2 = nullptr, *g3 = nullptr;
-  if (devptr) {
-    eps = P->eps; B = P->B; g1 = P->gamma1; g2 = P->gamma2; g3 = has_g3 ? P->gamma3 : nullptr;
-    int* bad;
-    HIPCHECK(hipMalloc(&bad, sizeof(int)));
-    HIPCHECK(hipMemsetAsync(bad, 0, sizeof(int), st));
-    auto chk = [&](const double* p, long long n) {
-      if (!p || n == 0) return;
-      long long blocks = std::min<long long>((n + 255) / 256, 4096);
-      hipLaunchKernelGGL(count_nonfinite_kernel, dim3((unsigned)blocks), dim3(256), 0, st, p, n, bad);
-    };
-    chk(eps, N); chk(B, nB);
-    if (nA > 0) { chk(g1, g1n); chk(g2, g2n); }
-    if (g3) chk(g3, g3n);
-    int hbad = 0;
-    HIPCHECK(hipMemcpyAsync(&hbad, bad, sizeof(int), hipMemcpyDeviceToHost, st));
-    HIPCHECK(hipStreamSynchronize(st));
-    (void)hipFree(bad);
-    if (hbad) throw Error(DSRG_E_NONFINITE, "non-finite value in eps, B or the densities");
-  } else {
-    auto up = [&](const double* h, long long n) -> const double* {
-      double* p = pool.alloc(n);
-      HIPCHECK(hipMemcpyAsync(p, h, n * sizeof(double), hipMemcpyHostToDevice, st));
-      return p;
-    };
-    eps = up(P->eps, N);
-    B = up(P->B, nB);
-    if (nA > 0) { g1 = up(P->gamma1, g1n); g2 = up(P->gamma2, g2n); }
-    if (has_g3) g3 = up(P->gamma3, g3n);
+// Copy the inputs into the device buffers (host or device sources) and s from s_host,
+// which must stay valid until the stream is synchronised.  Device inputs are checked for
+// non-finite values on the copies (one synchronisation).
+static void load_inputs(const dsrg_problem* P, bool devptr, const Shape& sh, const Inputs& in,
+                        const double* s_host, hipStream_t st) {
+  const hipMemcpyKind kind = devptr ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
+  auto cp = [&](double* dst, const double* src, long long n) {
+    if (n > 0) HIPCHECK(hipMemcpyAsync(dst, src, n * sizeof(double), kind, st));
+  };
+  cp(in.eps, P->eps, sh.N);
+  cp(in.B, P->B, sh.nB);
+  if (sh.nA > 0) {
+    cp(in.g1, P->gamma1, sh.g1n);
+    cp(in.g2, P->gamma2, sh.g2n);
   }
+  if (sh.has_g3) cp(in.g3, P->gamma3, sh.g3n);
+  HIPCHECK(hipMemcpyAsync(in.s, s_host, sizeof(double), hipMemcpyHostToDevice, st));
+  if (!devptr) return;
+  HIPCHECK(hipMemsetAsync(in.bad, 0, sizeof(int), st));
+  auto chk = [&](const double* p, long long n) {
+    if (!p || n == 0) return;
+    long long blocks = std::min<long long>((n + 255) / 256, 4096);
+    hipLaunchKernelGGL(count_nonfinite_kernel, dim3((unsigned)blocks), dim3(256), 0, st, p, n, in.bad);
+  };
+  chk(in.eps, sh.N);
+  chk(in.B, sh.nB);
+  if (sh.nA > 0) {
+    chk(in.g1, sh.g1n);
+    chk(in.g2, sh.g2n);
+  }
+  if (sh.has_g3) chk(in.g3, sh.g3n);
+  int hbad = 0;
+  HIPCHECK(hipMemcpyAsync(&hbad, in.bad, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHECK(hipStreamSynchronize(st));
+  if (hbad) throw Error(DSRG_E_NONFINITE, "non-finite value in eps, B or the densities");
+}
 
-  Exec X(d, st, pool, B, M, cap, O && (O->flags & DSRG_F_PROFILE));
-  X.grouped = !(O && (O->flags & DSRG_F_NO_GROUPING));
-  X.group_cap = cap / 2;
+// Device buffers of the intermediates a caller may ask for.
+struct BodyOut {
+  double *T1a = nullptr, *T1b = nullptr, *T2aa = nullptr, *T2ab = nullptr;
+  double *W1 = nullptr, *W2 = nullptr, *Z1 = nullptr, *Z2 = nullptr, *U1 = nullptr, *U2 = nullptr;
+};
+
+// The pipeline: every device operation goes through op (and so into a plan being built);
+// ev[1..6] mark the stages on st.
+static BodyOut body(Exec& X, OpLog& op, Pool& pool, const Shape& sh, const Inputs& in, hipEvent_t* ev,
+                    hipStream_t st) {
+  const int nC = sh.nC, nA = sh.nA, nV = sh.nV;
+  const int nH = nC + nA, nP = nA + nV;
+  const Dims d{nC, nA, nV};
+  const double *eps = in.eps, *g1 = in.g1, *g2 = in.g2, *g3 = in.g3, *sdev = in.s;
+  BodyOut bo;
   // step a0: spin-orbital densities and cumulants over the active space
   const int n2 = 2 * nA;
-  double *G1 = nullptr, *G2 = nullptr, *G3 = nullptr, *L2 = nullptr, *L3 = nullptr, *eta = nullptr;
   if (nA > 0) {
-    G1 = pool.alloc((size_t)n2 * n2);
-    G2 = pool.alloc((size_t)n2 * n2 * n2 * n2);
-    L2 = pool.alloc((size_t)n2 * n2 * n2 * n2);
-    eta = pool.alloc((size_t)n2 * n2);
-    L3 = pool.alloc((size_t)n2 * n2 * n2 * n2 * n2 * n2);
-    launch_expand_rdm(nA, 1, g1, G1, st);
-    launch_expand_rdm(nA, 2, g2, G2, st);
+    const long long e2n = (long long)n2 * n2, e4n = e2n * e2n, e6n = e4n * e2n;
+    double* G1 = pool.alloc((size_t)e2n);
+    double* G2 = pool.alloc((size_t)e4n);
+    double* L2 = pool.alloc((size_t)e4n);
+    double* eta = pool.alloc((size_t)e2n);
+    double* L3 = pool.alloc((size_t)e6n);
+    op([nA, g1, G1](hipStream_t s) { launch_expand_rdm(nA, 1, g1, G1, s); });
+    op([nA, g2, G2](hipStream_t s) { launch_expand_rdm(nA, 2, g2, G2, s); });
     if (g3) {
-      G3 = pool.alloc((size_t)n2 * n2 * n2 * n2 * n2 * n2);
-      launch_expand_rdm(nA, 3, g3, G3, st);
-      launch_cumulants(nA, G1, G2, G3, L2, L3, eta, st);
+      double* G3 = pool.alloc((size_t)e6n);
+      op([nA, g3, G3](hipStream_t s) { launch_expand_rdm(nA, 3, g3, G3, s); });
+      op([nA, G1, G2, G3, L2, L3, eta](hipStream_t s) { launch_cumulants(nA, G1, G2, G3, L2, L3, eta, s); });
       pool.release(G3);
     } else {
-      launch_cumulants(nA, G1, G2, nullptr, L2, nullptr, eta, st);
-      launch_fill(L3, (long long)n2 * n2 * n2 * n2 * n2 * n2, 0.0, st);
+      op([nA, G1, G2, L2, eta](hipStream_t s) { launch_cumulants(nA, G1, G2, nullptr, L2, nullptr, eta, s); });
+      op([L3, e6n](hipStream_t s) { launch_fill(L3, e6n, 0.0, s); });
     }
     pool.release(G2);
     // spin-block views of the spin-orbital arrays
@@ -1251,35 +1329,37 @@ static int run(const dsrg_problem* P, const dsrg_options* O, dsrg_result* R,
 
   // step a2: first-order amplitudes, Y = [H(0), A(1)] and H~(1) (excitation blocks)
   const size_t n4 = (size_t)nP * nP * nH * nH, n1 = (size_t)nP * nH;
-  AmpDims ad{nC, nA, nV};
+  const AmpDims ad{nC, nA, nV};
   double* T2aa = pool.alloc(n4); double* T2ab = pool.alloc(n4);
   double* Y2aa = pool.alloc(n4); double* Y2ab = pool.alloc(n4);
   double* E2aa = pool.alloc(n4); double* E2ab = pool.alloc(n4);
-  launch_first_order_doubles(ad, Jhphp, eps, P->s, T2aa, T2ab, Y2aa, Y2ab, E2aa, E2ab, st);
+  op([=](hipStream_t s) {
+    launch_first_order_doubles(ad, Jhphp, eps, sdev, T2aa, T2ab, Y2aa, Y2ab, E2aa, E2ab, s);
+  });
   double* T1a = pool.alloc(n1); double* T1b = pool.alloc(n1);
   double* Y1a = pool.alloc(n1); double* Y1b = pool.alloc(n1);
   // gamma1 input blocks [2][nA][nA] are read directly by the singles kernel
-  const double* g1c = nA > 0 ? g1 : nullptr;
-  launch_singles(ad, T2aa, T2ab, T2aa, g1c, g1c ? g1c + nA * nA : nullptr, eps, P->s, nullptr,
-                 nullptr, T1a, T1b, Y1a, Y1b, st);
+  const double* g1a = nA > 0 ? g1 : nullptr;
+  const double* g1b = nA > 0 ? g1 + nA * nA : nullptr;
+  op([=](hipStream_t s) {
+    launch_singles(ad, T2aa, T2ab, T2aa, g1a, g1b, eps, sdev, nullptr, nullptr, T1a, T1b, Y1a, Y1b, s);
+  });
   auto bind_first = [&]() {
     X.set("T1.a", T1a, "PH"); X.set("T1.b", T1b, "PH");
     X.set("T2.aa", T2aa, "PPHH"); X.set("T2.ab", T2ab, "PPHH"); X.set("T2.bb", T2aa, "PPHH");
   };
-  auto bind_h1 = [&]() {
-    X.set("E1.a", Y1a, "PH"); X.set("E1.b", Y1b, "PH");
-    X.set("E2.aa", E2aa, "PPHH"); X.set("E2.ab", E2ab, "PPHH"); X.set("E2.bb", E2aa, "PPHH");
-  };
   bind_first();
-  bind_h1();
+  X.set("E1.a", Y1a, "PH"); X.set("E1.b", Y1b, "PH");
+  X.set("E2.aa", E2aa, "PPHH"); X.set("E2.ab", E2ab, "PPHH"); X.set("E2.bb", E2aa, "PPHH");
   X.set("Y1.a", Y1a, "PH"); X.set("Y1.b", Y1b, "PH");
   X.set("Y2.aa", Y2aa, "PPHH"); X.set("Y2.ab", Y2ab, "PPHH"); X.set("Y2.bb", Y2aa, "PPHH");
+  bo.T1a = T1a; bo.T1b = T1b; bo.T2aa = T2aa; bo.T2ab = T2ab;
   HIPCHECK(hipEventRecord(ev[2], st));
 
   auto& T = table();
   const Use& C0 = T.at("C0");
-  double* energies = pool.alloc(4);
-  launch_fill(energies, 4, 0.0, st);
+  double* energies = in.energies;
+  op([energies](hipStream_t s) { launch_fill(energies, 4, 0.0, s); });
   std::map<std::string, TensorRef> none;
   auto scalar = [&](double* outp) {
     X.use_id = 0;
@@ -1288,98 +1368,310 @@ static int run(const dsrg_problem* P, const dsrg_options* O, dsrg_result* R,
   // step a3: E(2) = <[H~(1), T(1)]>
   scalar(energies + 0);
   HIPCHECK(hipEventRecord(ev[3], st));
-
-  double* W1a = nullptr;
-  if (pt3) {
-    // steps a4-a5: W = [V, A(1)]_{1,2}, excitation block
-    W1a = pool.alloc(2 * n1);
-    double* W2 = pool.alloc(3 * n4);
-    launch_fill(W1a, 2 * n1, 0.0, st);
-    launch_fill(W2, 3 * n4, 0.0, st);
-    std::map<std::string, TensorRef> wout;
-    auto bind_out = [&](std::map<std::string, TensorRef>& o, double* p1, double* p2) {
-      auto mk = [&](double* p, const char* ax) {
-        TensorRef t{p, ax, {}};
-        int r = (int)strlen(ax);
-        t.stride.assign(r, 1);
-        for (int k = r - 2; k >= 0; --k) t.stride[k] = t.stride[k + 1] * d.len(ax[k + 1]);
-        t.lim = t.stride[0] * d.len(ax[0]);
-        return t;
-      };
-      o["O1.a"] = mk(p1, "PH"); o["O1.b"] = mk(p1 + n1, "PH");
-      o["O2.aa"] = mk(p2, "PPHH"); o["O2.ab"] = mk(p2 + n4, "PPHH"); o["O2.bb"] = mk(p2 + 2 * n4, "PPHH");
-    };
-    bind_out(wout, W1a, W2);
-    X.use_id = 1;
-    X.run_use(T.at("W"), wout, nullptr);
-    HIPCHECK(hipEventRecord(ev[4], st));
-    // step a6: Z = [Y, A(1)]_{1,2}
-    double* Z1 = pool.alloc(2 * n1);
-    double* Z2 = pool.alloc(3 * n4);
-    launch_fill(Z1, 2 * n1, 0.0, st);
-    launch_fill(Z2, 3 * n4, 0.0, st);
-    std::map<std::string, TensorRef> zout;
-    bind_out(zout, Z1, Z2);
-    X.use_id = 2;
-    X.run_use(T.at("Z"), zout, nullptr);
-    HIPCHECK(hipEventRecord(ev[5], st));
-    // second-order amplitudes and H~(2)_{1,2}
-    double* U2 = pool.alloc(3 * n4);
-    double* H2 = pool.alloc(3 * n4);
-    for (int b = 0; b < 3; ++b)
-      launch_second_order_doubles(ad, W2 + b * n4, Z2 + b * n4, eps, P->s, U2 + b * n4, H2 + b * n4, st);
-    double* f2 = pool.alloc(2 * n1);
-    launch_combine_f2((int)(2 * n1), W1a, Z1, f2, st);
-    double* U1 = pool.alloc(2 * n1);
-    double* S2 = pool.alloc(2 * n1);
-    launch_singles(ad, U2, U2 + n4, U2 + 2 * n4, g1c, g1c ? g1c + nA * nA : nullptr, eps, P->s, f2,
-                   f2 + n1, U1, U1 + n1, S2, S2 + n1, st);
-    double* H1 = pool.alloc(2 * n1);
-    for (int sidx = 0; sidx < 2; ++sidx)
-      launch_second_order_h1(ad, W1a + sidx * n1, Z1 + sidx * n1, S2 + sidx * n1, H1 + sidx * n1, st);
-    // E(3)_a = <[H~(1), T(2)]>
-    X.set("T1.a", U1, "PH"); X.set("T1.b", U1 + n1, "PH");
-    X.set("T2.aa", U2, "PPHH"); X.set("T2.ab", U2 + n4, "PPHH"); X.set("T2.bb", U2 + 2 * n4, "PPHH");
-    scalar(energies + 1);
-    // E(3)_b = <[H~(2)_{1,2}, T(1)]>
-    bind_first();
-    X.set("E1.a", H1, "PH"); X.set("E1.b", H1 + n1, "PH");
-    X.set("E2.aa", H2, "PPHH"); X.set("E2.ab", H2 + n4, "PPHH"); X.set("E2.bb", H2 + 2 * n4, "PPHH");
-    scalar(energies + 2);
-    HIPCHECK(hipEventRecord(ev[6], st));
-    if (I) {
-      auto cp = [&](double* h, const double* dptr, size_t n) {
-        if (h) HIPCHECK(hipMemcpyAsync(h, dptr, n * 8, hipMemcpyDeviceToHost, st));
-      };
-      cp(I->w1, W1a, 2 * n1); cp(I->w2, W2, 3 * n4);
-      cp(I->z1, Z1, 2 * n1); cp(I->z2, Z2, 3 * n4);
-      cp(I->u1, U1, 2 * n1); cp(I->u2, U2, 3 * n4);
-    }
-  } else {
+  if (!sh.pt3) {
     for (int k = 4; k < 7; ++k) HIPCHECK(hipEventRecord(ev[k], st));
+    return bo;
   }
+
+  // steps a4-a5: W = [V, A(1)]_{1,2}, excitation block
+  double* W1 = pool.alloc(2 * n1);
+  double* W2 = pool.alloc(3 * n4);
+  op([W1, W2, n1, n4](hipStream_t s) {
+    launch_fill(W1, 2 * n1, 0.0, s);
+    launch_fill(W2, 3 * n4, 0.0, s);
+  });
+  auto bind_out = [&](std::map<std::string, TensorRef>& o, double* p1, double* p2) {
+    auto mk = [&](double* p, const char* ax) {
+      TensorRef t{p, ax, {}};
+      int r = (int)strlen(ax);
+      t.stride.assign(r, 1);
+      for (int k = r - 2; k >= 0; --k) t.stride[k] = t.stride[k + 1] * d.len(ax[k + 1]);
+      t.lim = t.stride[0] * d.len(ax[0]);
+      return t;
+    };
+    o["O1.a"] = mk(p1, "PH"); o["O1.b"] = mk(p1 + n1, "PH");
+    o["O2.aa"] = mk(p2, "PPHH"); o["O2.ab"] = mk(p2 + n4, "PPHH"); o["O2.bb"] = mk(p2 + 2 * n4, "PPHH");
+  };
+  std::map<std::string, TensorRef> wout;
+  bind_out(wout, W1, W2);
+  X.use_id = 1;
+  X.run_use(T.at("W"), wout, nullptr);
+  HIPCHECK(hipEventRecord(ev[4], st));
+  // step a6: Z = [Y, A(1)]_{1,2}
+  double* Z1 = pool.alloc(2 * n1);
+  double* Z2 = pool.alloc(3 * n4);
+  op([Z1, Z2, n1, n4](hipStream_t s) {
+    launch_fill(Z1, 2 * n1, 0.0, s);
+    launch_fill(Z2, 3 * n4, 0.0, s);
+  });
+  std::map<std::string, TensorRef> zout;
+  bind_out(zout, Z1, Z2);
+  X.use_id = 2;
+  X.run_use(T.at("Z"), zout, nullptr);
+  HIPCHECK(hipEventRecord(ev[5], st));
+  // second-order amplitudes and H~(2)_{1,2}
+  double* U2 = pool.alloc(3 * n4);
+  double* H2 = pool.alloc(3 * n4);
+  double* f2 = pool.alloc(2 * n1);
+  double* U1 = pool.alloc(2 * n1);
+  double* S2 = pool.alloc(2 * n1);
+  double* H1 = pool.alloc(2 * n1);
+  op([=](hipStream_t s) {
+    for (int b = 0; b < 3; ++b)
+      launch_second_order_doubles(ad, W2 + b * n4, Z2 + b * n4, eps, sdev, U2 + b * n4, H2 + b * n4, s);
+    launch_combine_f2((int)(2 * n1), W1, Z1, f2, s);
+    launch_singles(ad, U2, U2 + n4, U2 + 2 * n4, g1a, g1b, eps, sdev, f2, f2 + n1, U1, U1 + n1, S2,
+                   S2 + n1, s);
+    for (int sidx = 0; sidx < 2; ++sidx)
+      launch_second_order_h1(ad, W1 + sidx * n1, Z1 + sidx * n1, S2 + sidx * n1, H1 + sidx * n1, s);
+  });
+  // E(3)_a = <[H~(1), T(2)]>
+  X.set("T1.a", U1, "PH"); X.set("T1.b", U1 + n1, "PH");
+  X.set("T2.aa", U2, "PPHH"); X.set("T2.ab", U2 + n4, "PPHH"); X.set("T2.bb", U2 + 2 * n4, "PPHH");
+  scalar(energies + 1);
+  // E(3)_b = <[H~(2)_{1,2}, T(1)]>
+  bind_first();
+  X.set("E1.a", H1, "PH"); X.set("E1.b", H1 + n1, "PH");
+  X.set("E2.aa", H2, "PPHH"); X.set("E2.ab", H2 + n4, "PPHH"); X.set("E2.bb", H2 + 2 * n4, "PPHH");
+  scalar(energies + 2);
+  HIPCHECK(hipEventRecord(ev[6], st));
+  bo.W1 = W1; bo.W2 = W2; bo.Z1 = Z1; bo.Z2 = Z2; bo.U1 = U1; bo.U2 = U2;
+  return bo;
+}
+
+// ---------------------------------------------------------------------------
+// Plans: the pipeline of one shape, recorded while it first runs and captured into a HIP
+// graph; later calls of the same shape copy their inputs and launch the graph.
+// ---------------------------------------------------------------------------
+struct Plan {
+  std::string key;
+  int device = 0;
+  std::unique_ptr<Pool> pool;
+  Inputs in;
+  hipStream_t cap = nullptr;
+  hipGraph_t graph = nullptr;
+  hipGraphExec_t exec = nullptr;
+  double* pinned = nullptr;   // host [8]: s at [0], energies at [4..8)
+  bool busy = false;
+  unsigned long long stamp = 0;
+  double gett_flops = 0, ladder_flops = 0;
+  int ladder_batch = 0, n_launch = 0, grouped_uses = 0;
+  ~Plan() {
+    int cur = 0;
+    (void)hipGetDevice(&cur);
+    (void)hipSetDevice(device);
+    if (exec) (void)hipGraphExecDestroy(exec);
+    if (graph) (void)hipGraphDestroy(graph);
+    if (cap) (void)hipStreamDestroy(cap);
+    if (pinned) (void)hipHostFree(pinned);
+    pool.reset();
+    (void)hipSetDevice(cur);
+  }
+};
+
+constexpr int kMaxPlans = 4;
+constexpr size_t kMaxPlanBytes = 16ULL << 30;
+static std::mutex g_plan_mu;
+// never destroyed: freeing device memory during static destruction can outlive the runtime
+static std::vector<std::unique_ptr<Plan>>& plans() {
+  static auto* v = new std::vector<std::unique_ptr<Plan>>();
+  return *v;
+}
+static unsigned long long g_plan_clock = 0;
+
+static void capture(Plan& pl, std::vector<DevOp>& ops) {
+  HIPCHECK(hipStreamCreateWithFlags(&pl.cap, hipStreamNonBlocking));
+  HIPCHECK(hipStreamBeginCapture(pl.cap, hipStreamCaptureModeRelaxed));
+  hipGraph_t g = nullptr;
+  try {
+    for (auto& f : ops) f(pl.cap);
+    HIPCHECK(hipGetLastError());
+  } catch (...) {
+    if (hipStreamEndCapture(pl.cap, &g) == hipSuccess && g) (void)hipGraphDestroy(g);
+    (void)hipGetLastError();
+    throw;
+  }
+  HIPCHECK(hipStreamEndCapture(pl.cap, &g));
+  pl.graph = g;
+  HIPCHECK(hipGraphInstantiate(&pl.exec, pl.graph, nullptr, nullptr, 0));
+}
+
+// Insert a new plan, dropping the least recently used idle plans beyond the limits.
+static bool keep_plan(std::unique_ptr<Plan> fresh) {
+  std::lock_guard<std::mutex> lk(g_plan_mu);
+  auto& v = plans();
+  v.push_back(std::move(fresh));
+  auto over = [&] {
+    size_t bytes = 0;
+    for (auto& p : v) bytes += p->pool->bytes;
+    return (int)v.size() > kMaxPlans || bytes > kMaxPlanBytes;
+  };
+  while (over()) {
+    int victim = -1;
+    for (int i = 0; i + 1 < (int)v.size(); ++i)
+      if (!v[i]->busy && (victim < 0 || v[i]->stamp < v[victim]->stamp)) victim = i;
+    if (victim < 0) {
+      v.pop_back();   // the new plan (idle) does not fit beside busy ones
+      return false;
+    }
+    v.erase(v.begin() + victim);
+  }
+  return true;
+}
+
+static void fill_result(dsrg_result* R, const double* e, bool pt3) {
+  R->e2 = e[0];
+  R->e3_a = pt3 ? e[1] : 0.0;
+  R->e3_b = pt3 ? e[2] : 0.0;
+  R->e3 = R->e3_a + R->e3_b;
+}
+
+static int run(const dsrg_problem* P, const dsrg_options* O, dsrg_result* R,
+               const dsrg_intermediates* I, bool pt3) {
+  if (!P || !R) throw Error(DSRG_E_ARG, "null problem or result");
+  const int nC = P->n_core, nA = P->n_active, nV = P->n_virtual, M = P->n_aux;
+  if (nC < 0 || nA < 0 || nV < 0) throw Error(DSRG_E_ARG, "negative orbital count");
+  if (M < 1) throw Error(DSRG_E_ARG, "n_aux must be >= 1");
+  if (nC + nA + nV < 1) throw Error(DSRG_E_ARG, "no orbitals");
+  if (!(P->s > 0.0)) throw Error(DSRG_E_ARG, "s must be > 0");
+  if (!P->eps || !P->B) throw Error(DSRG_E_ARG, "null eps or B");
+  if (nA > 0 && (!P->gamma1 || !P->gamma2)) throw Error(DSRG_E_ARG, "null gamma1/gamma2 with nA > 0");
+  if (nA > 8) throw Error(DSRG_E_UNSUPPORTED, "active spaces above 8 orbitals are not built");
+  if (O && O->precision != 0) throw Error(DSRG_E_UNSUPPORTED, "only FP64 is built");
+  const int flags = O ? O->flags : 0;
+  const bool devptr = flags & DSRG_F_DEVICE_PTRS;
+  const bool profile = flags & DSRG_F_PROFILE;
+  Shape sh;
+  sh.nC = nC; sh.nA = nA; sh.nV = nV; sh.M = M;
+  sh.N = nC + nA + nV;
+  sh.nB = (long long)M * sh.N * sh.N;
+  sh.g1n = 2LL * nA * nA;
+  sh.g2n = 3LL * nA * nA * nA * nA;
+  sh.g3n = 4LL * nA * nA * nA * nA * nA * nA;
+  sh.has_g3 = nA > 0 && P->gamma3;
+  sh.pt3 = pt3;
+  if (!devptr) {
+    if (!finite_host(P->eps, sh.N) || !finite_host(P->B, sh.nB) ||
+        (nA > 0 && (!finite_host(P->gamma1, sh.g1n) || !finite_host(P->gamma2, sh.g2n))) ||
+        (sh.has_g3 && !finite_host(P->gamma3, sh.g3n)))
+      throw Error(DSRG_E_NONFINITE, "non-finite value in eps, B or the densities");
+  }
+  hipStream_t st = (O && O->stream) ? (hipStream_t)O->stream : (hipStream_t)0;
+  const long long cap = (O && O->workspace_cap > 0) ? O->workspace_cap : (8LL << 30);
+  const bool grouped = !(flags & DSRG_F_NO_GROUPING);
+  const bool cacheable = !profile && !I && !(flags & DSRG_F_NO_PLAN_CACHE);
+
+  int dev = 0;
+  HIPCHECK(hipGetDevice(&dev));
+  char kbuf[160];
+  snprintf(kbuf, sizeof(kbuf), "%d:%d:%d:%d:%d:%d:%d:%d:%lld", dev, nC, nA, nV, M, (int)sh.has_g3,
+           (int)pt3, (int)grouped, cap);
+  const std::string key(kbuf);
+  Plan* plan = nullptr;
+  std::unique_ptr<Plan> fresh;
+  if (cacheable) {
+    std::lock_guard<std::mutex> lk(g_plan_mu);
+    bool seen = false;
+    for (auto& p : plans())
+      if (p->key == key) {
+        seen = true;
+        if (!p->busy) {
+          plan = p.get();
+          plan->busy = true;
+          plan->stamp = ++g_plan_clock;
+          break;
+        }
+      }
+    // a plan of this shape in use by another thread: run without one
+    if (!seen) {
+      fresh = std::make_unique<Plan>();
+      fresh->key = key;
+      fresh->device = dev;
+      fresh->stamp = ++g_plan_clock;
+    }
+  }
+
+  hipEvent_t ev[8];
+  for (auto& e : ev) HIPCHECK(hipEventCreate(&e));
+  struct EvGuard {
+    hipEvent_t* e;
+    ~EvGuard() { for (int i = 0; i < 8; ++i) (void)hipEventDestroy(e[i]); }
+  } evg{ev};
+  dsrg_result r;
+  memset(&r, 0, sizeof(r));
+
+  if (plan) {
+    struct Release {
+      Plan* p;
+      ~Release() {
+        std::lock_guard<std::mutex> lk(g_plan_mu);
+        p->busy = false;
+      }
+    } rel{plan};
+    plan->pinned[0] = P->s;
+    load_inputs(P, devptr, sh, plan->in, plan->pinned, st);
+    HIPCHECK(hipEventRecord(ev[0], st));
+    HIPCHECK(hipGraphLaunch(plan->exec, st));
+    HIPCHECK(hipEventRecord(ev[7], st));
+    HIPCHECK(hipMemcpyAsync(plan->pinned + 4, plan->in.energies, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHECK(hipStreamSynchronize(st));
+    HIPCHECK(hipGetLastError());
+    fill_result(&r, plan->pinned + 4, pt3);
+    float ms = 0;
+    HIPCHECK(hipEventElapsedTime(&ms, ev[0], ev[7]));
+    r.t_seconds[7] = ms * 1e-3;
+    r.gett_flops = plan->gett_flops;
+    r.ladder_flops = plan->ladder_flops;
+    r.ladder_batch = plan->ladder_batch;
+    r.n_launch = plan->n_launch;
+    r.grouped_uses = plan->grouped_uses;
+    r.plan = 2;
+    *R = r;
+    return DSRG_OK;
+  }
+
+  std::unique_ptr<Pool> local;
+  Pool* pool;
+  const double* s_src = &P->s;   // lives until the synchronisation below
+  if (fresh) {
+    fresh->pool = std::make_unique<Pool>(st, true);
+    pool = fresh->pool.get();
+    HIPCHECK(hipHostMalloc((void**)&fresh->pinned, 8 * sizeof(double), hipHostMallocDefault));
+    fresh->pinned[0] = P->s;
+    s_src = fresh->pinned;
+  } else {
+    local = std::make_unique<Pool>(st);
+    pool = local.get();
+  }
+  Inputs in = alloc_inputs(*pool, sh);
+  load_inputs(P, devptr, sh, in, s_src, st);
+  std::vector<DevOp> ops;
+  OpLog op{st, fresh ? &ops : nullptr};
+  Exec X(Dims{nC, nA, nV}, st, *pool, op, in.B, M, cap, profile);
+  X.grouped = grouped;
+  X.group_cap = cap / 2;
+  HIPCHECK(hipEventRecord(ev[0], st));
+  BodyOut bo = body(X, op, *pool, sh, in, ev, st);
   if (I) {
-    if (I->t1) {
-      HIPCHECK(hipMemcpyAsync(I->t1, T1a, n1 * 8, hipMemcpyDeviceToHost, st));
-      HIPCHECK(hipMemcpyAsync(I->t1 + n1, T1b, n1 * 8, hipMemcpyDeviceToHost, st));
-    }
-    if (I->t2) {
-      HIPCHECK(hipMemcpyAsync(I->t2, T2aa, n4 * 8, hipMemcpyDeviceToHost, st));
-      HIPCHECK(hipMemcpyAsync(I->t2 + n4, T2ab, n4 * 8, hipMemcpyDeviceToHost, st));
-      HIPCHECK(hipMemcpyAsync(I->t2 + 2 * n4, T2aa, n4 * 8, hipMemcpyDeviceToHost, st));
-    }
+    const size_t nH = nC + nA, nP = nA + nV, n1 = nP * nH, n4 = nP * nP * nH * nH;
+    auto cp = [&](double* h, const double* dptr, size_t n) {
+      if (h && dptr) HIPCHECK(hipMemcpyAsync(h, dptr, n * 8, hipMemcpyDeviceToHost, st));
+    };
+    cp(I->t1, bo.T1a, n1);
+    cp(I->t1 ? I->t1 + n1 : nullptr, bo.T1b, n1);
+    cp(I->t2, bo.T2aa, n4);
+    cp(I->t2 ? I->t2 + n4 : nullptr, bo.T2ab, n4);
+    cp(I->t2 ? I->t2 + 2 * n4 : nullptr, bo.T2aa, n4);
+    cp(I->w1, bo.W1, 2 * n1); cp(I->w2, bo.W2, 3 * n4);
+    cp(I->z1, bo.Z1, 2 * n1); cp(I->z2, bo.Z2, 3 * n4);
+    cp(I->u1, bo.U1, 2 * n1); cp(I->u2, bo.U2, 3 * n4);
   }
   HIPCHECK(hipEventRecord(ev[7], st));
   double e[4] = {0, 0, 0, 0};
-  HIPCHECK(hipMemcpyAsync(e, energies, 4 * 8, hipMemcpyDeviceToHost, st));
+  HIPCHECK(hipMemcpyAsync(e, in.energies, 4 * 8, hipMemcpyDeviceToHost, st));
   HIPCHECK(hipStreamSynchronize(st));
   HIPCHECK(hipGetLastError());
-  dsrg_result r;
-  memset(&r, 0, sizeof(r));
-  r.e2 = e[0];
-  r.e3_a = pt3 ? e[1] : 0.0;
-  r.e3_b = pt3 ? e[2] : 0.0;
-  r.e3 = r.e3_a + r.e3_b;
+  fill_result(&r, e, pt3);
   float ms;
   for (int k = 0; k < 6; ++k) {
     HIPCHECK(hipEventElapsedTime(&ms, ev[k], ev[k + 1]));
@@ -1398,7 +1690,26 @@ static int run(const dsrg_problem* P, const dsrg_options* O, dsrg_result* R,
   r.ladder_seconds = X.ladder_ms * 1e-3;
   r.ladder_batch = X.ladder_batch;
   r.n_launch = X.n_launch;
+  r.grouped_uses = X.grouped_uses;
   *R = r;
+
+  if (fresh && pool->bytes <= kMaxPlanBytes) {
+    // capture the recorded pipeline; a failure only means later calls run without a plan
+    fresh->in = in;
+    fresh->gett_flops = X.gett_flops;
+    fresh->ladder_flops = X.ladder_flops;
+    fresh->ladder_batch = X.ladder_batch;
+    fresh->n_launch = X.n_launch;
+    fresh->grouped_uses = X.grouped_uses;
+    try {
+      capture(*fresh, ops);
+      // from here on every use of the plan ends with a synchronisation of its caller's stream
+      fresh->pool->sync_before_free = false;
+      if (keep_plan(std::move(fresh))) R->plan = 1;
+    } catch (const Error&) {
+      (void)hipGetLastError();
+    }
+  }
   return DSRG_OK;
 }
 
@@ -1437,6 +1748,16 @@ int dsrg_pt3_energy_ex(const dsrg_problem* prob, const dsrg_options* opt, dsrg_r
 const char* dsrg_last_error(void) { return dsrg::g_last_error.c_str(); }
 
 int dsrg_version(void) { return 100; }
+
+int dsrg_release_cache(void) {
+  return dsrg::guarded([&] {
+    std::lock_guard<std::mutex> lk(dsrg::g_plan_mu);
+    auto& v = dsrg::plans();
+    for (size_t i = v.size(); i-- > 0;)
+      if (!v[i]->busy) v.erase(v.begin() + i);
+    return DSRG_OK;
+  });
+}
 
 }  // extern "C"
 

@@ -114,25 +114,27 @@ void launch_expand_rdm(int nA, int rank, const double* blocks, double* so, hipSt
 void launch_cumulants(int nA, const double* G1, const double* G2, const double* G3, double* L2,
                       double* L3, double* eta, hipStream_t st);
 
+// The flow parameter s is read from device memory (s points at one double), so a captured
+// launch sequence serves every s.
 // First-order doubles from the Coulomb block J(HP|HP)[i][a][j][b] = (ai|bj):
 // t = v R_s(D), Y = -D t, E = 2 v + Y (E = 2 v on internal elements), blocks aa (=bb) and ab.
 struct AmpDims {
   int nC, nA, nV;
 };
-void launch_first_order_doubles(AmpDims d, const double* Jhphp, const double* eps, double s,
+void launch_first_order_doubles(AmpDims d, const double* Jhphp, const double* eps, const double* s,
                                 double* T2aa, double* T2ab, double* Y2aa, double* Y2ab,
                                 double* E2aa, double* E2ab, hipStream_t st);
 // Singles: coup_s[a,i] = sum_{ux} (e_x - e_u) (t_ss[a,x,i,u] g_s[x,u] + t_{s s'}..[..] g_s'[x,u]);
 // t1 = (f + coup) R_s(D), and the non-diagonal one-body source (f + coup) exp(-s D^2).
 // f may be null (zero).  For a null g1 (nA = 0) coup = 0.
 void launch_singles(AmpDims d, const double* T2aa, const double* T2ab, const double* T2bb,
-                    const double* g1a, const double* g1b, const double* eps, double s,
+                    const double* g1a, const double* g1b, const double* eps, const double* s,
                     const double* fa, const double* fb, double* t1a, double* t1b, double* srca,
                     double* srcb, hipStream_t st);
 // Second-order doubles and the H~(2) two-body excitation block:
 // O = 2 W + Z; u = (O/2) R_s(D) (0 on internal), H = (O/2) exp(-s D^2) - Z/6 (O/2 - Z/6 internal).
 void launch_second_order_doubles(AmpDims d, const double* W, const double* Z, const double* eps,
-                                 double s, double* U, double* H, hipStream_t st);
+                                 const double* s, double* U, double* H, hipStream_t st);
 // One-body counterpart: f2 = (2 W1 + Z1)/2; H1 = src - Z1/6 (f2 - Z1/6 on internal elements),
 // where src = (f2 + coup2) exp(-s D^2) comes from launch_singles.
 void launch_second_order_h1(AmpDims d, const double* W1, const double* Z1, const double* src,

@@ -657,10 +657,11 @@ __device__ __forceinline__ double source_factor(double s, double D) {
 }
 
 __global__ void first_order_doubles_kernel(AmpDims d, const double* __restrict__ J,
-                                           const double* __restrict__ eps, double s,
+                                           const double* __restrict__ eps, const double* __restrict__ sp,
                                            double* __restrict__ Taa, double* __restrict__ Tab,
                                            double* __restrict__ Yaa, double* __restrict__ Yab,
                                            double* __restrict__ Eaa, double* __restrict__ Eab) {
+  const double s = *sp;
   const int nH = d.nC + d.nA, nP = d.nA + d.nV;
   long long total = (long long)nP * nP * nH * nH;
   long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x;
@@ -682,7 +683,7 @@ __global__ void first_order_doubles_kernel(AmpDims d, const double* __restrict__
   Eaa[idx] = 2.0 * vaa - D * taa;
 }
 
-void launch_first_order_doubles(AmpDims d, const double* J, const double* eps, double s,
+void launch_first_order_doubles(AmpDims d, const double* J, const double* eps, const double* s,
                                 double* T2aa, double* T2ab, double* Y2aa, double* Y2ab,
                                 double* E2aa, double* E2ab, hipStream_t st) {
   long long nH = d.nC + d.nA, nP = d.nA + d.nV;
@@ -696,10 +697,11 @@ void launch_first_order_doubles(AmpDims d, const double* J, const double* eps, d
 // coup_b[a,i] = sum_ux (e_x - e_u)(t_bb[a,x,i,u] g_b[x,u] + t_ab[x,a,u,i] g_a[x,u])
 __global__ void singles_kernel(AmpDims d, const double* __restrict__ Taa, const double* __restrict__ Tab,
                                const double* __restrict__ Tbb, const double* __restrict__ ga,
-                               const double* __restrict__ gb, const double* __restrict__ eps, double s,
+                               const double* __restrict__ gb, const double* __restrict__ eps, const double* __restrict__ sp,
                                const double* __restrict__ fa, const double* __restrict__ fb,
                                double* __restrict__ t1a, double* __restrict__ t1b,
                                double* __restrict__ srca, double* __restrict__ srcb) {
+  const double s = *sp;
   const int nH = d.nC + d.nA, nP = d.nA + d.nV, nA = d.nA, nC = d.nC;
   int idx = blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= 2 * nP * nH) return;
@@ -733,7 +735,7 @@ __global__ void singles_kernel(AmpDims d, const double* __restrict__ Taa, const 
 }
 
 void launch_singles(AmpDims d, const double* T2aa, const double* T2ab, const double* T2bb,
-                    const double* g1a, const double* g1b, const double* eps, double s,
+                    const double* g1a, const double* g1b, const double* eps, const double* s,
                     const double* fa, const double* fb, double* t1a, double* t1b, double* srca,
                     double* srcb, hipStream_t st) {
   int nH = d.nC + d.nA, nP = d.nA + d.nV;
@@ -745,8 +747,9 @@ void launch_singles(AmpDims d, const double* T2aa, const double* T2ab, const dou
 
 __global__ void second_order_doubles_kernel(AmpDims d, const double* __restrict__ W,
                                             const double* __restrict__ Z,
-                                            const double* __restrict__ eps, double s,
+                                            const double* __restrict__ eps, const double* __restrict__ sp,
                                             double* __restrict__ U, double* __restrict__ H) {
+  const double s = *sp;
   const int nH = d.nC + d.nA, nP = d.nA + d.nV;
   long long total = (long long)nP * nP * nH * nH;
   long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x;
@@ -761,7 +764,7 @@ __global__ void second_order_doubles_kernel(AmpDims d, const double* __restrict_
 }
 
 void launch_second_order_doubles(AmpDims d, const double* W, const double* Z, const double* eps,
-                                 double s, double* U, double* H, hipStream_t st) {
+                                 const double* s, double* U, double* H, hipStream_t st) {
   long long nH = d.nC + d.nA, nP = d.nA + d.nV;
   long long total = nP * nP * nH * nH;
   if (total == 0) return;

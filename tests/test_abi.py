@@ -39,6 +39,7 @@ def test_exports_every_declared_symbol(lib):
     for n in names:
         assert hasattr(lib, n), n
     assert lib.dsrg_version() >= 100
+    assert lib.dsrg_release_cache() == 0
 
 
 def _call(p, mutate=None, opt=None):

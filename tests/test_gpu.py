@@ -185,6 +185,43 @@ def test_grouped_matches_per_launch(name):
     assert c["n_launch"] < a["n_launch"]
 
 
+def test_plan_replay_matches_eager():
+    """First call of a shape records a plan (a HIP graph of the pipeline); later calls copy
+    their inputs and replay it.  Every replay, with eager work and synchronisations between
+    replays, equals the eager result bitwise; new values, s and device inputs of the same
+    shape go through the same plan and still match the oracle."""
+    import torch
+    _lib.release_cache()
+    p = make_config("tiny")
+    say("plan replay: tiny")
+    eager = _lib.dsrg_pt3_energy(p, cache=False)
+    assert eager["plan"] == 0
+    first = _lib.dsrg_pt3_energy(p)
+    assert first["plan"] == 1
+    assert first["e2"] == eager["e2"] and first["e3"] == eager["e3"]
+    for k in range(4):
+        x = torch.randn(4096, device="cuda")
+        assert torch.isfinite((x * x).sum()).item()
+        _lib.dsrg_pt3_energy(p, cache=False, grouping=False)
+        torch.cuda.synchronize()
+        rep = _lib.dsrg_pt3_energy(p)
+        assert rep["plan"] == 2, k
+        assert rep["e2"] == eager["e2"] and rep["e3"] == eager["e3"], k
+    q = make_problem(2, 2, 10, 40, seed=999, s=1.1)
+    g = _lib.dsrg_pt3_energy(q)
+    assert g["plan"] == 2
+    r = dsrg.run(q)
+    assert _close(g["e2"], r.e2) and _close(g["e3"], r.e3), (g, r.e2, r.e3)
+    gd = _lib.dsrg_pt3_energy(_lib.to_device(q))
+    assert gd["plan"] == 2 and gd["e2"] == g["e2"] and gd["e3"] == g["e3"]
+    g2 = _lib.dsrg_pt2_energy(q)
+    assert g2["e2"] == g["e2"] and g2["e3"] == 0.0
+    _lib.release_cache()
+    again = _lib.dsrg_pt3_energy(p)
+    assert again["plan"] == 1 and again["e3"] == eager["e3"]
+    _lib.release_cache()
+
+
 def test_nonfinite_device_input():
     import torch
     p = make_problem(1, 2, 3, 6, seed=1)
