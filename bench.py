@@ -113,15 +113,14 @@ def main():
     # the kernels run on; the timed loop above replays the recorded graph instead
     prof = [_lib.dsrg_pt3_energy(d, profile=True) for d in dev]
     torch.cuda.synchronize()
-    grouped = all(r["grouped_uses"] > 0 for r in prof)
-    names = ["gett_group_kernel<2, 2> (grouped table contractions)" if grouped else
-             "gett_f64_kernel<0, *, *> (table contractions)",
+    names = ["gett_f64_kernel<0, *, *> (table contractions, one launch each)",
              "gett_f64_kernel<1, *, *> ((PP|PP) ladder contractions)",
-             "gett_f64_kernel<2, *, *> (Coulomb-block builds B.B)"]
-    sec = [sum(r["role_seconds"][k] for r in prof) for k in range(3)]
-    nl = [sum(r["role_launches"][k] for r in prof) for k in range(3)]
-    fl = [sum(r["role_flops"][k] for r in prof) for k in range(3)]
-    dom = max(range(3), key=lambda k: sec[k])
+             "gett_f64_kernel<2, *, *> (Coulomb-block builds B.B)",
+             "gett_group_kernel<2, 2> (grouped table contractions)"]
+    sec = [sum(r["role_seconds"][k] for r in prof) for k in range(4)]
+    nl = [sum(r["role_launches"][k] for r in prof) for k in range(4)]
+    fl = [sum(r["role_flops"][k] for r in prof) for k in range(4)]
+    dom = max(range(4), key=lambda k: sec[k])
     if dom == 1:
         # algorithmic: unique pairs for the same-spin ladders (the kernel sums all pairs)
         nH = probs[0].n_core + probs[0].n_active

@@ -101,11 +101,12 @@ typedef struct {
   double ladder_seconds;  /* with DSRG_F_PROFILE: device time of the (PP|PP) ladder groups */
   int32_t ladder_batch;   /* virtual batch size used for the (PP|PP) integrals */
   int32_t n_launch;       /* kernel launches issued */
-  /* with DSRG_F_PROFILE: contraction launches by role [0] table products, [1] (PP|PP)
-     ladder products, [2] Coulomb-block builds from B: device seconds, flops, launches */
-  double role_seconds[3];
-  double role_flops[3];
-  int32_t role_launches[3];
+  /* with DSRG_F_PROFILE: contraction launches by role [0] table products one launch each,
+     [1] (PP|PP) ladder products, [2] Coulomb-block builds from B, [3] grouped launches of
+     table products: device seconds, flops, launches */
+  double role_seconds[4];
+  double role_flops[4];
+  int32_t role_launches[4];
   int32_t plan;           /* 0: ran without a plan, 1: ran and recorded a plan, 2: replayed one */
   int32_t grouped_uses;   /* commutator evaluations run as grouped launches (the others ran
                              one launch per contraction) */

@@ -10,6 +10,9 @@ LIB = os.path.join(HERE, "libdsrg.so")
 SOURCES = ["dsrg.hip", "kernels.hip"]
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
+         # MFMA accumulators in ordinary VGPRs: with the AGPR form the compiler copied every
+         # accumulator AGPR -> VGPR -> AGPR on each k step of the contraction loops
+         "-mllvm", "-amdgpu-mfma-vgpr-form",
          "-Wno-unused-command-line-argument", "-I" + os.path.join(ROOT, "include")]
 
 

@@ -46,8 +46,8 @@ class Result(ctypes.Structure):
                 ("e3_b", ctypes.c_double), ("t_seconds", ctypes.c_double * 8),
                 ("gett_flops", ctypes.c_double), ("ladder_flops", ctypes.c_double),
                 ("ladder_seconds", ctypes.c_double), ("ladder_batch", ctypes.c_int32),
-                ("n_launch", ctypes.c_int32), ("role_seconds", ctypes.c_double * 3),
-                ("role_flops", ctypes.c_double * 3), ("role_launches", ctypes.c_int32 * 3),
+                ("n_launch", ctypes.c_int32), ("role_seconds", ctypes.c_double * 4),
+                ("role_flops", ctypes.c_double * 4), ("role_launches", ctypes.c_int32 * 4),
                 ("plan", ctypes.c_int32), ("grouped_uses", ctypes.c_int32)]
 
 

@@ -253,22 +253,19 @@ struct Exec {
   Exec(Dims d_, hipStream_t s, Pool& p, OpLog& o, const double* B_, int M_, long long cap, bool prof)
       : d(d_), st(s), pool(p), op(o), B(B_), M(M_), ws_cap(cap), profile(prof) {
     partial = pool.alloc(dot_partials());
-    splitk_ws = pool.alloc((size_t)splitk_elems);
   }
-  // split-K partial tiles for contractions with few output tiles
-  long long splitk_elems = 1LL << 23;
+  // split-K partial tiles, grown on demand up to kSplitCap doubles; launches on one stream
+  // use the buffer in order, and a replaced buffer stays allocated until the call ends
+  static constexpr long long kSplitCap = 1LL << 27;
+  long long splitk_elems = 0;
   double* splitk_ws = nullptr;
-  // k -> offset tables of the contraction kernel; launches on one stream reuse the buffer
-  // in order, so a table is never overwritten while an earlier launch still reads it
-  long long* ktab = nullptr;
-  long long ktab_cap = 0;
-  long long* ktab_for(long long K) {
-    if (2 * K > ktab_cap) {
-      long long n = std::max(2 * K, 1LL << 20);
-      ktab = (long long*)pool.alloc((size_t)n);
-      ktab_cap = n;
+  double* splitk_buffer(long long n) {
+    if (n <= 0) return nullptr;
+    if (n > splitk_elems) {
+      splitk_ws = pool.alloc((size_t)n);
+      splitk_elems = n;
     }
-    return ktab;
+    return splitk_ws;
   }
 
   // every contraction launch goes through here; with profiling, HIP events bracket it
@@ -283,7 +280,51 @@ struct Exec {
   };
   int cur_product = -1;
   std::vector<Rec> recs;
-  void gett(const GettDesc& g, const double* A, const double* Bp, double* C, int role) {
+  // Packed copies of operands that the contraction kernel would read without unit stride
+  // along its fast load direction: [m][k] for A, [n][k] for B with the kernel's inner k
+  // last, so both load with k fastest.  Only when the other free dimension is large
+  // enough for the copy to cost a small fraction of the contraction.
+  static constexpr long long kPackMin = 64, kPackCap = 1LL << 28;
+  double* pack_buf[2] = {nullptr, nullptr};
+  long long pack_elems[2] = {0, 0};
+  static bool unit_fast(bool kfast, int nfree, const long long* free_stride, long long k_inner) {
+    if (kfast) return std::llabs(k_inner) == 1;
+    return nfree > 0 && std::llabs(free_stride[nfree - 1]) == 1;
+  }
+  const double* pack_operand(int which, GettDesc& g, const double* src) {
+    const bool isA = which == 0;
+    const int nf = isA ? g.nm : g.nn;
+    const int* fd = isA ? g.md : g.nd;
+    long long* fs = isA ? g.am : g.bn;
+    long long* ks = isA ? g.ak : g.bk;
+    const long long n = (long long)(isA ? g.M : g.N) * g.K;
+    PackDesc pd;
+    pd.n = n;
+    pd.rank = nf + g.nk;
+    for (int i = 0; i < nf; ++i) { pd.d[i] = fd[i]; pd.ss[i] = fs[i]; }
+    for (int j = 0; j < g.nk; ++j) { pd.d[nf + j] = g.kd[j]; pd.ss[nf + j] = ks[j]; }
+    if (n > pack_elems[which]) {
+      pack_buf[which] = pool.alloc((size_t)n);
+      pack_elems[which] = n;
+    }
+    double* dst = pack_buf[which];
+    op([pd, src, dst](hipStream_t s) { launch_pack(pd, src, dst, s); });
+    ++n_launch;
+    long long st = 1;
+    for (int j = g.nk - 1; j >= 0; --j) { ks[j] = st; st *= g.kd[j]; }
+    for (int i = nf - 1; i >= 0; --i) { fs[i] = st; st *= fd[i]; }
+    return dst;
+  }
+
+  void gett(const GettDesc& g0, const double* A, const double* Bp, double* C, int role) {
+    GettDesc g = g0;
+    const bool pa = !unit_fast(g.a_kfast, g.nm, g.am, g.ak[g.nk - 1]) && g.N >= kPackMin &&
+                    (long long)g.M * g.K <= kPackCap;
+    const bool pb = !unit_fast(g.b_kfast, g.nn, g.bn, g.bk[g.nk - 1]) && g.M >= kPackMin &&
+                    (long long)g.N * g.K <= kPackCap;
+    if (pa) A = pack_operand(0, g, A);
+    if (pb) Bp = pack_operand(1, g, Bp);
+    if (pa || pb) gett_prepare(g);
     double fl = 2.0 * g.M * (double)g.N * g.K;
     Rec r{nullptr, nullptr, role, fl, g.M, g.N, g.K, g.nm, g.nn, g.nk, cur_product};
     if (profile) {
@@ -291,10 +332,10 @@ struct Exec {
       HIPCHECK(hipEventCreate(&r.b));
       HIPCHECK(hipEventRecord(r.a, st));
     }
-    long long* kt = ktab_for(g.K);
-    double* ws = splitk_ws;
-    long long wse = splitk_elems;
-    op([g, A, Bp, C, role, ws, wse, kt](hipStream_t s) { launch_gett(g, A, Bp, C, s, role, ws, wse, kt); });
+    const int ns = gett_splits(g, kSplitCap);
+    const long long wse = ns > 1 ? (long long)ns * g.M * g.N : 0;
+    double* ws = splitk_buffer(wse);
+    op([g, A, Bp, C, role, ws, wse](hipStream_t s) { launch_gett(g, A, Bp, C, s, role, ws, wse); });
     if (profile) {
       HIPCHECK(hipEventRecord(r.b, st));
       recs.push_back(r);
@@ -305,8 +346,8 @@ struct Exec {
   }
   double ladder_flops_products = 0;
   // per-role totals of profiled launches: seconds, launches, flops
-  double role_sec[3] = {0, 0, 0}, role_flops[3] = {0, 0, 0};
-  int role_n[3] = {0, 0, 0};
+  double role_sec[kRoles] = {}, role_flops[kRoles] = {};
+  int role_n[kRoles] = {};
   void collect_profile() {
     // optional per-launch dump (shape and device time) for tuning
     const char* dump = getenv("DSRG_PROFILE_DUMP");
@@ -363,8 +404,8 @@ struct Exec {
     g.bk[0] = (long long)N * N; g.bn[0] = N; g.bn[1] = 1;
     g.cm[0] = (long long)g.md[1] * g.N; g.cm[1] = g.N;
     g.cn[0] = g.nd[1]; g.cn[1] = 1;
-    g.a_kfast = 0; g.b_kfast = 0;
     g.alpha = 1.0; g.beta = 0;
+    gett_prepare(g);
     long long nB = (long long)M * N * N;
     check_view("B (first pair)", nB - (A0 - B), {g.am[0], g.am[1], g.ak[0]}, {g.md[0], g.md[1], M});
     check_view("B (second pair)", nB - (B0 - B), {g.bn[0], g.bn[1], g.bk[0]}, {g.nd[0], g.nd[1], M});
@@ -478,19 +519,29 @@ struct Exec {
     g.M = (int)Mx; g.N = (int)Nx; g.K = (int)Kx;
     check_operand("contraction A", a, lr);
     check_operand("contraction B", b, lr);
+    gett_prepare(g);
     return g;
   }
 
-  // Contiguous result operand with letters ml + nl; sets the C strides of g.
-  Opnd result_operand(GettDesc& g, const std::string& ml, const std::string& nl, const LetterRange& lr) {
+  // Contiguous result operand with letters ml + nl, laid out row-major in the order of
+  // `layout` (default: ml + nl); sets the C strides of g.
+  Opnd result_operand(GettDesc& g, const std::string& ml, const std::string& nl, const LetterRange& lr,
+                      const std::string& layout = "") {
     Opnd r;
     r.letters = ml + nl;
     r.lim = (long long)g.M * g.N;
+    const std::string lay = layout.empty() ? r.letters : layout;
+    if (lay.size() != r.letters.size()) throw Error(DSRG_E_HIP, "internal: result layout");
     r.stride.assign(r.letters.size(), 1);
-    for (int k = (int)r.letters.size() - 2; k >= 0; --k) r.stride[k] = r.stride[k + 1] * lr.len.at(r.letters[k + 1]);
+    long long st = 1;
+    for (int k = (int)lay.size() - 1; k >= 0; --k) {
+      size_t pos = r.letters.find(lay[k]);
+      if (pos == std::string::npos) throw Error(DSRG_E_HIP, "internal: result layout letter");
+      r.stride[pos] = st;
+      st *= lr.len.at(lay[k]);
+    }
     for (int i = 0; i < g.nm; ++i) g.cm[i] = r.stride[i];
     for (int i = 0; i < g.nn; ++i) g.cn[i] = r.stride[g.nm + i];
-    set_load_order(g);
     g.alpha = 1.0;
     g.beta = 0;
     return r;
@@ -529,15 +580,6 @@ struct Exec {
     check_view(what, o.lim, o.stride, len);
   }
 
-  static void set_load_order(GettDesc& g) {
-    auto mn = [](const long long* s, int n) {
-      long long m = (1LL << 62);
-      for (int i = 0; i < n; ++i) m = std::min(m, s[i] < 0 ? -s[i] : s[i]);
-      return m;
-    };
-    g.a_kfast = mn(g.ak, g.nk) < mn(g.am, g.nm);
-    g.b_kfast = mn(g.bk, g.nk) < mn(g.bn, g.nn);
-  }
 
   // temporaries: grow-only arena reused across products (single stream, so reuse is
   // ordered after every earlier use)
@@ -687,7 +729,7 @@ struct Exec {
     if (Mx >= (1LL << 31) || Nx >= (1LL << 31) || Kx >= (1LL << 31))
       throw Error(DSRG_E_UNSUPPORTED, "contraction dimension exceeds 2^31");
     g.M = (int)Mx; g.N = (int)Nx; g.K = (int)Kx;
-    set_load_order(g);
+    gett_prepare(g);
     g.alpha = s.coef;
     g.beta = 1;
     check_operand("contraction A", a, lr);
@@ -738,10 +780,14 @@ struct Exec {
 
   // A grouped launch, bracketed by events when profiling.
   // A grouped launch.  With profiling, the contraction launches (timed = true) are
-  // bracketed by events and counted under the generic role; helper launches are not.
-  void group_launch(double flops, DevOp launch, bool timed = false) {
-    Rec r{nullptr, nullptr, kRoleGeneric, flops, 0, 0, 0, 0, 0, 0, -2};
+  // bracketed by events and counted under the grouped role (items in M, workgroups in N of
+  // the profile record); helper launches are not.
+  void group_launch(double flops, DevOp launch, bool timed = false, int items = 0, int tiles = 0) {
+    Rec r{nullptr, nullptr, kRoleGrouped, flops, 0, 0, 0, 0, 0, 0, -2};
     timed = timed && profile;
+    r.M = items;
+    r.N = tiles;
+    r.product = use_id * 10000 + 9000 + group_level++;
     if (timed) {
       HIPCHECK(hipEventCreate(&r.a));
       HIPCHECK(hipEventCreate(&r.b));
@@ -830,7 +876,10 @@ struct Exec {
         auto [bi, bj] = pick_pair(ops, lr);
         std::string ml, nl;
         GettDesc g = pair_desc(ops[bi], ops[bj], lr, ml, nl);
-        Opnd r = result_operand(g, ml, nl, lr);
+        // the final result of a tensor product is laid out like its first output, so the
+        // gather reads that entry with unit stride
+        const bool last = ops.size() == 2 && !P.res.empty();
+        Opnd r = result_operand(g, ml, nl, lr, last ? P.s[0].letters : std::string());
         r.toff = take(r.lim);
         if (lev.size() <= level) {
           lev.resize(level + 1);
@@ -895,37 +944,45 @@ struct Exec {
       }
     }
 
-    // split-K for items with few tiles and a long k range; k tables; budget check
-    long long part_elems = 0, ksum = 0;
+    // split-K for items with few tiles and a long k range; budget check
+    long long part_elems = 0;
     std::vector<std::vector<long long>> poff(lev.size());
     for (size_t L = 0; L < lev.size(); ++L) {
       for (auto& it : lev[L]) {
         GettDesc& g = it.g;
-        it.tiles_m = (g.M + kGroupTile - 1) / kGroupTile;
-        it.tiles_n = (g.N + kGroupTile - 1) / kGroupTile;
+        // tile shape with the least padded work (ties: the first, square one)
+        long long bestw = -1;
+        for (int sh = 0; sh < kGroupShapes; ++sh) {
+          const long long tm = (g.M + kGroupTiles[sh][0] - 1) / kGroupTiles[sh][0];
+          const long long tn = (g.N + kGroupTiles[sh][1] - 1) / kGroupTiles[sh][1];
+          const long long w = tm * kGroupTiles[sh][0] * tn * kGroupTiles[sh][1];
+          if (bestw < 0 || w < bestw) {
+            bestw = w;
+            it.shape = sh;
+            it.tiles_m = (int)tm;
+            it.tiles_n = (int)tn;
+          }
+        }
         long long tiles = (long long)it.tiles_m * it.tiles_n;
         int ns = 1;
-        if (g.K >= 1024 && tiles < 64) {
-          long long want = std::min<long long>((g.K + 255) / 256, std::max<long long>(1, 256 / tiles));
-          int chunk = (int)((g.K + want - 1) / want);
-          chunk = (chunk + kGettBK - 1) / kGettBK * kGettBK;
-          ns = (g.K + chunk - 1) / chunk;
+        if (g.steps >= 64 && tiles < 64) {
+          long long want = std::min<long long>((g.steps + 15) / 16, std::max<long long>(1, 256 / tiles));
+          long long chunk = (g.steps + want - 1) / want;
+          ns = (int)((g.steps + chunk - 1) / chunk);
           g.kchunk = chunk;
         } else {
-          g.kchunk = g.K;
+          g.kchunk = g.steps;
         }
         it.splits = ns;
         poff[L].push_back(ns > 1 ? part_elems : -1);
         if (ns > 1) part_elems += (long long)ns * g.M * g.N;
-        ksum += g.K;
       }
     }
-    long long bytes = 8 * (arena + part_elems + 2 * ksum);
+    long long bytes = 8 * (arena + part_elems);
     if (bytes > group_cap) return false;
 
     double* tbase = arena > 0 ? pool.alloc((size_t)arena) : nullptr;
     double* pbase = part_elems > 0 ? pool.alloc((size_t)part_elems) : nullptr;
-    long long* kbase = ksum > 0 ? (long long*)pool.alloc((size_t)(2 * ksum)) : nullptr;
     auto at = [&](long long off, const double* p) -> const double* { return off >= 0 ? tbase + off : p; };
 
     // flatten the levels (longest tiles first inside a level) and patch the addresses
@@ -937,7 +994,6 @@ struct Exec {
       double flops;
     };
     std::vector<LevelRange> ranges;
-    long long kpos = 0;   // k-table prefix in the flattened order (the k-table launch searches it)
     for (size_t L = 0; L < lev.size(); ++L) {
       std::vector<int> order(lev[L].size());
       for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
@@ -951,9 +1007,6 @@ struct Exec {
         it.A = at(fx.a, it.A);
         it.B = at(fx.b, it.B);
         it.C = tbase + fx.c;
-        it.kofs0 = kpos;
-        kpos += it.g.K;
-        it.g.ktab = kbase + 2 * it.kofs0;
         it.g.part = it.splits > 1 ? pbase + poff[L][oi] : nullptr;
         it.tile0 = R.tiles;
         long long t = (long long)it.tiles_m * it.tiles_n * it.splits;
@@ -970,16 +1023,25 @@ struct Exec {
       }
       ranges.push_back(R);
     }
+    if (const char* path = getenv("DSRG_GROUP_DUMP")) {
+      // planning record for tuning: use, level, M, N, K, splits, k chunk
+      if (FILE* f = fopen(path, "a")) {
+        for (size_t L = 0; L < ranges.size(); ++L)
+          for (int i = 0; i < ranges[L].n; ++i) {
+            const GroupItem& it = items[ranges[L].i0 + i];
+            fprintf(f, "%d,%d,%d,%d,%d,%d,%lld\n", use_id, (int)L, it.g.M, it.g.N, it.g.K, it.splits,
+                    it.g.kchunk);
+          }
+        fclose(f);
+      }
+    }
     GroupItem* d_items = upload(items);
     int* d_split = upload(split_idx);
-    if (!items.empty()) {
-      const int n = (int)items.size();
-      group_launch(0.0, [d_items, n, ksum](hipStream_t s) { launch_group_kofs(d_items, n, ksum, s); });
-    }
     for (auto& R : ranges) {
       const GroupItem* it = d_items + R.i0;
       const int* sp = d_split + R.s0;
-      group_launch(R.flops, [it, R](hipStream_t s) { launch_gett_group(it, R.n, R.tiles, s); }, true);
+      group_launch(R.flops, [it, R](hipStream_t s) { launch_gett_group(it, R.n, R.tiles, s); }, true,
+                   R.n, R.tiles);
       if (R.ns > 0)
         group_launch(0.0, [it, sp, R](hipStream_t s) { launch_group_reduce(it, sp, R.ns, R.red, s); });
     }
@@ -1079,6 +1141,7 @@ struct Exec {
 
   // Run a use of the table into tensor outputs, or (scalar uses) into *scalar_out.
   int use_id = 0;
+  int group_level = 0;
   int grouped_uses = 0;
   bool grouped = true;
   long long group_cap = 0;   // bytes of temporaries one grouped use may hold
@@ -1680,7 +1743,7 @@ static int run(const dsrg_problem* P, const dsrg_options* O, dsrg_result* R,
   HIPCHECK(hipEventElapsedTime(&ms, ev[0], ev[7]));
   r.t_seconds[7] = ms * 1e-3;
   if (X.profile) X.collect_profile();
-  for (int k = 0; k < 3; ++k) {
+  for (int k = 0; k < kRoles; ++k) {
     r.role_seconds[k] = X.role_sec[k];
     r.role_flops[k] = X.role_flops[k];
     r.role_launches[k] = X.role_n[k];
@@ -1795,7 +1858,7 @@ extern "C" int dsrg_test_gett(int nm, const int* md, const long long* am, const 
     if (amax >= na || bmax >= nb || cmax >= nc) throw Error(DSRG_E_ARG, "strides address past the arrays");
     if (M >= (1LL << 31) || N >= (1LL << 31) || K >= (1LL << 31)) throw Error(DSRG_E_ARG, "too large");
     g.M = (int)M; g.N = (int)N; g.K = (int)K;
-    Exec::set_load_order(g);
+    gett_prepare(g);
     g.alpha = alpha; g.beta = beta ? 1 : 0;
     double *dA, *dB, *dC;
     HIPCHECK(hipMalloc(&dA, na * 8));
@@ -1808,13 +1871,10 @@ extern "C" int dsrg_test_gett(int nm, const int* md, const long long* am, const 
     const long long ws_elems = 1LL << 22;
     double* ws;
     HIPCHECK(hipMalloc(&ws, ws_elems * 8));
-    long long* tab;
-    HIPCHECK(hipMalloc(&tab, 2 * K * sizeof(long long)));
-    launch_gett(g, dA, dB, dC, 0, kRoleGeneric, ws, ws_elems, tab);
+    launch_gett(g, dA, dB, dC, 0, kRoleGeneric, ws, ws_elems);
     HIPCHECK(hipGetLastError());
     HIPCHECK(hipDeviceSynchronize());
     (void)hipFree(ws);
-    (void)hipFree(tab);
     HIPCHECK(hipMemcpy(C, dC, nc * 8, hipMemcpyDeviceToHost));
     (void)hipFree(dA); (void)hipFree(dB); (void)hipFree(dC);
     return DSRG_OK;

@@ -12,6 +12,12 @@ constexpr int kGettBK = 16;   // k step of the contraction kernel (split-K chunk
 // A strided tensor contraction C[m][n] (+)= alpha * sum_k A[m][k] B[k][n], where m, n and
 // k are multi-indices (row-major composition of up to kMaxComp components) and every
 // operand addresses its elements through its own per-component strides.
+//
+// The kernel walks k in steps of kGettBK consecutive values of the last k component (the
+// "inner" one, zero-padded to a multiple of kGettBK), so inside a step both operands are
+// affine in k; the other ("outer") k components advance between steps.  gett_prepare
+// merges k components that are contiguous in both operands, picks the inner component and
+// the load order; it must run before a launch.
 struct GettDesc {
   int M = 1, N = 1, K = 1;
   int nm = 0, nn = 0, nk = 0;
@@ -23,10 +29,12 @@ struct GettDesc {
   int beta = 0;        // 0: C = alpha AB, 1: C += alpha AB
   int a_kfast = 1;     // A tile loads walk k fastest (else m fastest)
   int b_kfast = 0;     // B tile loads walk k fastest (else n fastest)
-  int kchunk = 0;      // set by launch_gett: k range per split
-  double* part = nullptr;  // set by launch_gett: split-K partial tiles [split][M][N]
-  const long long* ktab = nullptr;  // set by launch_gett: k -> offset tables [2][K]
+  int ksteps = 1;      // k steps per value of the outer k components
+  long long steps = 1;   // total k steps: K / kd[nk - 1] * ksteps
+  long long kchunk = 1;  // k steps per split (split-K), set by the launcher
+  double* part = nullptr;  // split-K partial tiles [split][M][N], set by the launcher
 };
+void gett_prepare(GettDesc& g);
 
 // sum_k A[k] B[k] over a strided multi-index k (deterministic two-pass reduction).
 struct DotDesc {
@@ -46,31 +54,33 @@ struct ScatterDesc {
 };
 
 // Launch roles (same kernel, distinct symbols): contraction-table products, the (PP|PP)
-// particle-particle ladder products, and Coulomb-block builds from the DF tensor.
-constexpr int kRoleGeneric = 0, kRoleLadder = 1, kRoleIntegrals = 2;
-// ws (ws_elems doubles) enables split-K for launches with few output tiles and a long
-// k range: partial tiles go to ws and a fixed-order reduction writes C (deterministic).
-// ktab: scratch of 2 K int64 for the k -> offset tables of A and B (required).
+// particle-particle ladder products, and Coulomb-block builds from the DF tensor.  Role 3
+// counts the grouped launches of table products (gett_group_kernel) in profiles.
+constexpr int kRoleGeneric = 0, kRoleLadder = 1, kRoleIntegrals = 2, kRoleGrouped = 3;
+constexpr int kRoles = 4;
+// g must have been through gett_prepare.  ws (ws_elems doubles) enables split-K for
+// launches with few output tiles and a long k range: partial tiles go to ws and a
+// fixed-order reduction writes C (deterministic).
 void launch_gett(const GettDesc& g, const double* A, const double* B, double* C, hipStream_t st,
-                 int role, double* ws, long long ws_elems, long long* ktab);
+                 int role, double* ws, long long ws_elems);
 int gett_splits(const GettDesc& g, long long ws_elems);
 // ---- grouped execution: independent contractions of one dependency level per launch ----
 // Item i owns workgroups [tile0, tile0 + tiles_m * tiles_n * splits) of a grouped launch,
-// each a 64 x 64 output tile of one k chunk (g.kchunk).  With splits > 1 the partial tiles
-// go to g.part ([splits][M][N]) and launch_group_reduce writes C.  g.ktab points at this
-// item's k tables (2 K entries), filled by launch_group_kofs from kofs0 (prefix of K).
-constexpr int kGroupWM = 2, kGroupWN = 2, kGroupTile = 32 * kGroupWM;
+// each an output tile of shape kGroupTiles[shape] and one chunk of k steps (g.kchunk).
+// With splits > 1 the partial tiles go to g.part ([splits][M][N]) and launch_group_reduce
+// writes C.
+constexpr int kGroupShapes = 3;
+constexpr int kGroupTiles[kGroupShapes][2] = {{64, 64}, {16, 128}, {128, 16}};
 struct GroupItem {
   GettDesc g;
   const double* A = nullptr;
   const double* B = nullptr;
   double* C = nullptr;
+  int shape = 0;
   int tiles_m = 0, tiles_n = 0, splits = 1;
   int tile0 = 0;          // first workgroup of this item
-  long long kofs0 = 0;    // prefix of K over the items of the k-table launch
   long long red0 = 0;     // prefix of M N over the split items of the reduction launch
 };
-void launch_group_kofs(const GroupItem* items, int n, long long ksum, hipStream_t st);
 void launch_gett_group(const GroupItem* items, int n, int tiles, hipStream_t st);
 // split_idx: indices of the items with splits > 1, in increasing red0
 void launch_group_reduce(const GroupItem* items, const int* split_idx, int nsplit, long long total,
@@ -108,6 +118,16 @@ int dot_partials();
 void launch_dot(const DotDesc& d, const double* A, const double* B, double* partial, double* out,
                 hipStream_t st);
 void launch_scatter(const ScatterDesc& d, const double* src, double* out, hipStream_t st);
+
+// dst[e] = src[sum_c idx_c(e) ss[c]] with e row-major over d[0..rank) (a packed copy of a
+// strided view, rank <= 2 kMaxComp).
+struct PackDesc {
+  long long n = 0;
+  int rank = 0;
+  int d[2 * kMaxComp] = {};
+  long long ss[2 * kMaxComp] = {};
+};
+void launch_pack(const PackDesc& d, const double* src, double* dst, hipStream_t st);
 
 // Spin-orbital active densities [2nA]^k from the spin-block inputs, and cumulants.
 void launch_expand_rdm(int nA, int rank, const double* blocks, double* so, hipStream_t st);

@@ -4,6 +4,7 @@
 #include <algorithm>
 #include <cmath>
 #include <cstdio>
+#include <cstdlib>
 
 namespace dsrg {
 
@@ -29,29 +30,34 @@ __device__ __forceinline__ long long decode(int idx, int n, const int* d, const 
 // ---------------------------------------------------------------------------
 // GETT: a workgroup of 256 threads (4 waves, 2x2) computes a BM x BN output tile; each
 // wave owns a (16 WM) x (16 WN) sub-tile made of WM x WN v_mfma_f64_16x16x4 tiles.
-// K is staged through LDS in steps of BK = 16 with two buffers: the next step's global
-// loads are issued into registers before the current step's MFMAs and stored to the
-// other buffer afterwards (one barrier per step).
+// k advances in steps of BK = 16 values of the inner k component (zero-padded past its
+// extent); the outer k components advance between steps, their base offsets carried in
+// uniform registers, so a step's loads are plain base + per-thread-constant addresses.
+// Steps are staged through LDS with two buffers: the next step's global loads are issued
+// into registers before the current step's MFMAs and stored to the other buffer
+// afterwards (one barrier per step).
 // Operand layout of the 16x16x4 FP64 MFMA (checked on gfx950 by the kernel unit tests):
 // lane l holds A[l%16][l/16] and B[l/16][l%16]; accumulator element r of lane l is
 // D[l/16 + 4 r][l%16].
 // ---------------------------------------------------------------------------
 constexpr int BK = kGettBK;
 
-template <int WM, int WN>
+// Tile of WGM x (4 / WGM) waves, each wave WM x WN MFMA blocks of 16 x 16.
+template <int WM, int WN, int WGM>
 struct TileLds {
-  static constexpr int BM = 32 * WM, BN = 32 * WN;
+  static constexpr int BM = 16 * WM * WGM, BN = 16 * WN * (4 / WGM);
   static constexpr int LDA = BM + 2, LDB = BN + 2;
   double As[2][BK * LDA];
   double Bs[2][BK * LDB];
 };
 
-// One BM x BN output tile at (tile_m, tile_n) for k chunk kz of the contraction g.
-template <int WM, int WN>
+// One BM x BN output tile at (tile_m, tile_n) for chunk kz of the k steps of g.
+template <int WM, int WN, int WGM = 2>
 __device__ __forceinline__ void gett_tile(const GettDesc& g, const double* __restrict__ A,
                                           const double* __restrict__ B, double* __restrict__ C,
-                                          int tile_m, int tile_n, int kz, TileLds<WM, WN>& lds) {
-  constexpr int BM = 32 * WM, BN = 32 * WN;
+                                          int tile_m, int tile_n, int kz, TileLds<WM, WN, WGM>& lds) {
+  constexpr int BM = TileLds<WM, WN, WGM>::BM, BN = TileLds<WM, WN, WGM>::BN;
+  static_assert(BM * BK % 256 == 0 && BN * BK % 256 == 0 && 256 % BM == 0 || BM >= 256, "tile");
   constexpr int LDA = BM + 2, LDB = BN + 2;
   constexpr int NA = BM * BK / 256, NB = BN * BK / 256;   // loads per thread per step
   auto& As = lds.As;
@@ -59,58 +65,101 @@ __device__ __forceinline__ void gett_tile(const GettDesc& g, const double* __res
   const int tid = threadIdx.x;
   const int lane = tid & 63;
   const int wave = tid >> 6;
-  // split-K: chunk kz sums k in [k_lo, k_hi) and then writes a partial tile
-  const int k_lo = kz * g.kchunk;
-  const int k_hi = min(g.K, k_lo + g.kchunk);
+  const int nk = g.nk;
+  const int kin = g.kd[nk - 1];
+  const long long a_in = g.ak[nk - 1], b_in = g.bk[nk - 1];
+  const int ksteps = g.ksteps;
+  const long long s_lo = (long long)kz * g.kchunk;
+  const long long s_hi = min(g.steps, s_lo + g.kchunk);
+  const bool akf = g.a_kfast, bkf = g.b_kfast;
 
-  // fixed per-thread load slots
-  long long aoff_m[NA], boff_n[NB];
-  int a_mm[NA], a_kk[NA], b_nn[NB], b_kk[NB];
-  bool a_ok[NA], b_ok[NB];
+  // load slots: slot i of this thread covers (row, k) of the A tile and (k, col) of B;
+  // with k fastest the k of every slot is the same, else the row (column) is
+  auto a_k = [&](int i) { return akf ? (tid & (BK - 1)) : tid / BM + (256 / BM) * i; };
+  auto a_m = [&](int i) { return akf ? (tid / BK) + (256 / BK) * i : (tid & (BM - 1)); };
+  auto b_k = [&](int i) { return bkf ? (tid & (BK - 1)) : tid / BN + (256 / BN) * i; };
+  auto b_n = [&](int i) { return bkf ? (tid / BK) + (256 / BK) * i : (tid & (BN - 1)); };
+  long long aoff[NA], boff[NB];
 #pragma unroll
   for (int i = 0; i < NA; ++i) {
-    int e = tid + 256 * i;
-    if (g.a_kfast) { a_kk[i] = e % BK; a_mm[i] = e / BK; }
-    else           { a_mm[i] = e % BM; a_kk[i] = e / BM; }
-    int m = tile_m + a_mm[i];
-    a_ok[i] = m < g.M;
-    aoff_m[i] = a_ok[i] ? decode(m, g.nm, g.md, g.am) : 0;
+    const int m = tile_m + a_m(i);
+    aoff[i] = m < g.M ? decode(m, g.nm, g.md, g.am) + a_k(i) * a_in : 0;
   }
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
-    int e = tid + 256 * i;
-    if (g.b_kfast) { b_kk[i] = e % BK; b_nn[i] = e / BK; }
-    else           { b_nn[i] = e % BN; b_kk[i] = e / BN; }
-    int n = tile_n + b_nn[i];
-    b_ok[i] = n < g.N;
-    boff_n[i] = b_ok[i] ? decode(n, g.nn, g.nd, g.bn) : 0;
+    const int n = tile_n + b_n(i);
+    boff[i] = n < g.N ? decode(n, g.nn, g.nd, g.bn) + b_k(i) * b_in : 0;
   }
-  double ra[NA], rb[NB];
-  // k -> element offset tables (filled by kofs_kernel before this launch)
-  const long long* __restrict__ ta = g.ktab;
-  const long long* __restrict__ tb = g.ktab + g.K;
-  // branch-free loads in two phases (all k offsets, then all elements) so the memory
-  // requests of one step are in flight together; out-of-range slots read a valid element
-  // (row 0 / last k of the range) and are zeroed by a select
-  auto fetch = [&](int k0) {
-    long long oa[NA], ob[NB];
+
+  // uniform k state: inner step c, outer counters and the outer base offsets
+  int c;
+  int cnt[kMaxComp];
+  long long abo = 0, bbo = 0;
+  {
+    long long o = s_lo / ksteps;
+    c = (int)(s_lo - o * ksteps);
 #pragma unroll
-    for (int i = 0; i < NA; ++i) oa[i] = __builtin_nontemporal_load(&ta[min(k0 + a_kk[i], k_hi - 1)]);
+    for (int j = kMaxComp - 2; j >= 0; --j) {
+      cnt[j] = 0;
+      if (j <= nk - 2) {
+        const long long q = o / g.kd[j];
+        cnt[j] = (int)(o - q * g.kd[j]);
+        o = q;
+        abo += cnt[j] * g.ak[j];
+        bbo += cnt[j] * g.bk[j];
+      }
+    }
+  }
+  auto advance = [&]() {
+    if (++c < ksteps) return;
+    c = 0;
+    bool carry = true;
 #pragma unroll
-    for (int i = 0; i < NB; ++i) ob[i] = __builtin_nontemporal_load(&tb[min(k0 + b_kk[i], k_hi - 1)]);
-#pragma unroll
-    for (int i = 0; i < NA; ++i) ra[i] = A[aoff_m[i] + oa[i]];
-#pragma unroll
-    for (int i = 0; i < NB; ++i) rb[i] = B[boff_n[i] + ob[i]];
+    for (int j = kMaxComp - 2; j >= 0; --j) {
+      if (carry && j <= nk - 2) {
+        ++cnt[j];
+        abo += g.ak[j];
+        bbo += g.bk[j];
+        if (cnt[j] < g.kd[j]) {
+          carry = false;
+        } else {
+          cnt[j] = 0;
+          abo -= g.kd[j] * g.ak[j];
+          bbo -= g.kd[j] * g.bk[j];
+        }
+      }
+    }
   };
-  // the zeroing select sits here, after the step's MFMAs, so the loads overlap them
-  auto stash = [&](int buf, int k0) {
+
+  double ra[NA], rb[NB];
+  // loads of the step (c): out-of-range slots read the step's first element (valid) and
+  // are zeroed by the select in stash, which runs after the MFMAs so the loads overlap them
+  auto fetch = [&]() {
+    const int k0 = c * BK;
+    const long long ab = abo + k0 * a_in, bb = bbo + k0 * b_in;
 #pragma unroll
-    for (int i = 0; i < NA; ++i)
-      As[buf][a_kk[i] * LDA + a_mm[i]] = (a_ok[i] && k0 + a_kk[i] < k_hi) ? ra[i] : 0.0;
+    for (int i = 0; i < NA; ++i) {
+      const bool ok = k0 + a_k(i) < kin;
+      ra[i] = A[ab + (ok ? aoff[i] : 0)];
+    }
 #pragma unroll
-    for (int i = 0; i < NB; ++i)
-      Bs[buf][b_kk[i] * LDB + b_nn[i]] = (b_ok[i] && k0 + b_kk[i] < k_hi) ? rb[i] : 0.0;
+    for (int i = 0; i < NB; ++i) {
+      const bool ok = k0 + b_k(i) < kin;
+      rb[i] = B[bb + (ok ? boff[i] : 0)];
+    }
+  };
+  auto stash = [&](int buf) {
+    const int k0 = c * BK;
+#pragma unroll
+    for (int i = 0; i < NA; ++i) {
+      const bool ok = k0 + a_k(i) < kin && tile_m + a_m(i) < g.M;
+      As[buf][a_k(i) * LDA + a_m(i)] = ok ? ra[i] : 0.0;
+    }
+#pragma unroll
+    for (int i = 0; i < NB; ++i) {
+      const bool ok = k0 + b_k(i) < kin && tile_n + b_n(i) < g.N;
+      Bs[buf][b_k(i) * LDB + b_n(i)] = ok ? rb[i] : 0.0;
+    }
   };
 
   double4_t acc[WM][WN];
@@ -119,20 +168,23 @@ __device__ __forceinline__ void gett_tile(const GettDesc& g, const double* __res
 #pragma unroll
     for (int b = 0; b < WN; ++b) acc[a][b] = (double4_t){0.0, 0.0, 0.0, 0.0};
 
-  const int wm = (wave & 1) * (16 * WM);
-  const int wn = (wave >> 1) * (16 * WN);
+  const int wm = (wave % WGM) * (16 * WM);
+  const int wn = (wave / WGM) * (16 * WN);
   const int li = lane & 15;
   const int lk = lane >> 4;
 
   int buf = 0;
-  if (k_lo < k_hi) {
-    fetch(k_lo);
-    stash(0, k_lo);
+  if (s_lo < s_hi) {
+    fetch();
+    stash(0);
   }
   __syncthreads();
-  for (int k0 = k_lo; k0 < k_hi; k0 += BK) {
-    const bool more = k0 + BK < k_hi;
-    if (more) fetch(k0 + BK);
+  for (long long s = s_lo; s < s_hi; ++s) {
+    const bool more = s + 1 < s_hi;
+    if (more) {
+      advance();
+      fetch();
+    }
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
       double av[WM], bv[WN];
@@ -146,7 +198,7 @@ __device__ __forceinline__ void gett_tile(const GettDesc& g, const double* __res
         for (int b = 0; b < WN; ++b)
           acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
     }
-    if (more) stash(buf ^ 1, k0 + BK);
+    if (more) stash(buf ^ 1);
     __syncthreads();
     buf ^= 1;
   }
@@ -184,16 +236,8 @@ template <int kRole, int WM, int WN>
 __global__ __launch_bounds__(256) void gett_f64_kernel(GettDesc g, const double* __restrict__ A,
                                                        const double* __restrict__ B,
                                                        double* __restrict__ C) {
-  __shared__ TileLds<WM, WN> lds;
-  gett_tile<WM, WN>(g, A, B, C, blockIdx.x * (32 * WM), blockIdx.y * (32 * WN), blockIdx.z, lds);
-}
-
-// k -> offset tables of both operands: tab[k] (A) and tab[K + k] (B)
-__global__ __launch_bounds__(256) void kofs_kernel(GettDesc g, long long* __restrict__ tab) {
-  for (int k = blockIdx.x * 256 + threadIdx.x; k < g.K; k += 256 * gridDim.x) {
-    tab[k] = decode(k, g.nk, g.kd, g.ak);
-    tab[g.K + k] = decode(k, g.nk, g.kd, g.bk);
-  }
+  __shared__ TileLds<WM, WN, 2> lds;
+  gett_tile<WM, WN, 2>(g, A, B, C, blockIdx.x * (32 * WM), blockIdx.y * (32 * WN), blockIdx.z, lds);
 }
 
 // C[m][n] = alpha * sum_z part[z][m][n] (+ C) in a fixed order of z
@@ -211,20 +255,93 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(GettDesc g, const do
   }
 }
 
+// Merge k components that are contiguous in both operands (the outer one's strides are
+// the inner one's times its extent), then move to the last place the inner component:
+// first the one that lets most operands load coalesced (unit k stride, or a unit stride of
+// the operand's innermost free index), then the one whose padding to whole steps wastes
+// least, then the larger.
+void gett_prepare(GettDesc& g) {
+  if (g.nk == 0) {
+    g.nk = 1;
+    g.kd[0] = 1;
+    g.ak[0] = 0;
+    g.bk[0] = 0;
+  }
+  for (bool merged = true; merged && g.nk > 1;) {
+    merged = false;
+    for (int i = 0; i < g.nk && !merged; ++i)
+      for (int j = 0; j < g.nk && !merged; ++j) {
+        if (i == j) continue;
+        if (g.ak[i] == (long long)g.kd[j] * g.ak[j] && g.bk[i] == (long long)g.kd[j] * g.bk[j]) {
+          // i is the outer of the pair: (i, j) -> one component with j's strides
+          g.kd[j] *= g.kd[i];
+          for (int t = i; t + 1 < g.nk; ++t) {
+            g.kd[t] = g.kd[t + 1];
+            g.ak[t] = g.ak[t + 1];
+            g.bk[t] = g.bk[t + 1];
+          }
+          --g.nk;
+          merged = true;
+        }
+      }
+  }
+  auto waste = [&](int j) { return (double)((g.kd[j] + BK - 1) / BK * BK) / g.kd[j]; };
+  const bool am1 = g.nm > 0 && std::llabs(g.am[g.nm - 1]) == 1;
+  const bool bn1 = g.nn > 0 && std::llabs(g.bn[g.nn - 1]) == 1;
+  auto coalesced = [&](int j) {
+    return (int)(am1 || std::llabs(g.ak[j]) == 1) + (int)(bn1 || std::llabs(g.bk[j]) == 1);
+  };
+  int best = g.nk - 1;
+  for (int j = 0; j < g.nk; ++j) {
+    const int cj = coalesced(j), cb = coalesced(best);
+    const double wj = waste(j), wb = waste(best);
+    if (cj > cb || (cj == cb && (wj < wb - 1e-12 || (wj <= wb + 1e-12 && g.kd[j] > g.kd[best]))))
+      best = j;
+  }
+  std::swap(g.kd[best], g.kd[g.nk - 1]);
+  std::swap(g.ak[best], g.ak[g.nk - 1]);
+  std::swap(g.bk[best], g.bk[g.nk - 1]);
+  const int kin = g.kd[g.nk - 1];
+  g.ksteps = (kin + BK - 1) / BK;
+  g.steps = (long long)(g.K / kin) * g.ksteps;
+  g.kchunk = g.steps;
+  g.part = nullptr;
+  const long long ai = std::llabs(g.ak[g.nk - 1]), bi = std::llabs(g.bk[g.nk - 1]);
+  g.a_kfast = g.nm == 0 || ai < std::llabs(g.am[g.nm - 1]);
+  g.b_kfast = g.nn == 0 || bi < std::llabs(g.bn[g.nn - 1]);
+}
+
 // Large tiles (128 x 128) when they still give enough workgroups, else 64 x 64.
 static bool big_tiles(const GettDesc& g) {
   long long t128 = (long long)((g.M + 127) / 128) * ((g.N + 127) / 128);
   return g.M >= 128 && g.N >= 128 && t128 >= 256;
 }
 
+// Split-K factor: the number of k chunks that fills the resident workgroup slots in the
+// most nearly whole rounds (256 CUs; two 128 x 128 or four 64 x 64 workgroups per CU fit
+// the registers), keeping at least 16 k steps per chunk and the partial tiles within
+// ws_elems.  A larger split must gain at least 5 % of utilisation.
 int gett_splits(const GettDesc& g, long long ws_elems) {
-  const int bm = big_tiles(g) ? 128 : 64, bn = bm;
-  long long tiles = (long long)((g.M + bm - 1) / bm) * ((g.N + bn - 1) / bn);
-  if (tiles >= 512 || g.K < 512) return 1;
-  long long s = std::min<long long>((g.K + 255) / 256, (2048 + tiles - 1) / tiles);
-  long long cap = ws_elems / std::max<long long>(1, (long long)g.M * g.N);
-  s = std::min(s, cap);
-  return (int)std::max<long long>(1, s);
+  const bool big = big_tiles(g);
+  const int bm = big ? 128 : 64, bn = bm;
+  const long long slots = 256LL * (big ? 2 : 4);
+  const long long tiles = (long long)((g.M + bm - 1) / bm) * ((g.N + bn - 1) / bn);
+  const long long mn = std::max<long long>(1, (long long)g.M * g.N);
+  const long long smax = std::min<long long>({g.steps / 16, ws_elems / mn, 4096});
+  auto util = [&](long long s) {
+    const long long w = tiles * s;
+    return (double)w / (double)(slots * ((w + slots - 1) / slots));
+  };
+  long long best = 1;
+  double ub = util(1);
+  for (long long s = 2; s <= smax && tiles * (s - 1) < 8 * slots; ++s) {
+    const double u = util(s);
+    if (u > ub + 0.05) {
+      best = s;
+      ub = u;
+    }
+  }
+  return (int)best;
 }
 
 template <int kRole>
@@ -237,24 +354,17 @@ static void launch_role(const GettDesc& g, bool big, dim3 grid, const double* A,
 }
 
 void launch_gett(const GettDesc& g0, const double* A, const double* B, double* C, hipStream_t st,
-                 int role, double* ws, long long ws_elems, long long* ktab) {
+                 int role, double* ws, long long ws_elems) {
   if (g0.M <= 0 || g0.N <= 0) return;
   GettDesc g = g0;
-  g.ktab = ktab;
-  {
-    long long blocks = std::min<long long>((g.K + 255) / 256, 1024);
-    hipLaunchKernelGGL(kofs_kernel, dim3((unsigned)std::max<long long>(1, blocks)), dim3(256), 0, st,
-                       g, ktab);
-  }
   const bool big = big_tiles(g);
   const int bm = big ? 128 : 64, bn = bm;
   int ns = ws ? gett_splits(g, ws_elems) : 1;
   g.part = nullptr;
-  g.kchunk = g.K;
+  g.kchunk = g.steps;
   if (ns > 1) {
-    int chunk = (g.K + ns - 1) / ns;
-    chunk = (chunk + BK - 1) / BK * BK;
-    ns = (g.K + chunk - 1) / chunk;
+    long long chunk = (g.steps + ns - 1) / ns;
+    ns = (int)((g.steps + chunk - 1) / chunk);
     g.kchunk = chunk;
     g.part = ws;
   }
@@ -289,9 +399,21 @@ __device__ __forceinline__ int find_item_int(const GroupItem* __restrict__ items
   return lo;
 }
 
-template <int WM, int WN>
+// Tile shapes of grouped items (kGroupTiles): 64 x 64, 16 x 128 and 128 x 16; the item's
+// shape is uniform in its workgroups, so the switch does not diverge.
+using GroupLds0 = TileLds<2, 2, 2>;
+using GroupLds1 = TileLds<1, 2, 1>;
+using GroupLds2 = TileLds<2, 1, 4>;
+static_assert(GroupLds0::BM == 64 && GroupLds0::BN == 64, "group tile 0");
+static_assert(GroupLds1::BM == 16 && GroupLds1::BN == 128, "group tile 1");
+static_assert(GroupLds2::BM == 128 && GroupLds2::BN == 16, "group tile 2");
+
 __global__ __launch_bounds__(256) void gett_group_kernel(const GroupItem* __restrict__ items, int n) {
-  __shared__ TileLds<WM, WN> lds;
+  __shared__ union {
+    GroupLds0 t0;
+    GroupLds1 t1;
+    GroupLds2 t2;
+  } lds;
   const int b = blockIdx.x;
   const GroupItem& it = items[find_item_int(items, n, b)];
   const int t = b - it.tile0;
@@ -300,25 +422,15 @@ __global__ __launch_bounds__(256) void gett_group_kernel(const GroupItem* __rest
   const int r = t - kz * per;
   const int tm = r / it.tiles_n;
   const int tn = r - tm * it.tiles_n;
-  gett_tile<WM, WN>(it.g, it.A, it.B, it.C, tm * (32 * WM), tn * (32 * WN), kz, lds);
-}
-
-// k -> offset tables of every item: the item owning global k slot q is found by binary
-// search over kofs0 (prefix sums of K)
-__global__ __launch_bounds__(256) void group_kofs_kernel(const GroupItem* __restrict__ items, int n,
-                                                         long long ksum) {
-  for (long long q = blockIdx.x * 256LL + threadIdx.x; q < ksum; q += 256LL * gridDim.x) {
-    int lo = 0, hi = n - 1;
-    while (lo < hi) {
-      int mid = (lo + hi + 1) >> 1;
-      if (items[mid].kofs0 <= q) lo = mid;
-      else hi = mid - 1;
-    }
-    const GettDesc& g = items[lo].g;
-    const int k = (int)(q - items[lo].kofs0);
-    long long* tab = const_cast<long long*>(g.ktab);
-    tab[k] = decode(k, g.nk, g.kd, g.ak);
-    tab[g.K + k] = decode(k, g.nk, g.kd, g.bk);
+  switch (it.shape) {
+    case 1:
+      gett_tile<1, 2, 1>(it.g, it.A, it.B, it.C, tm * GroupLds1::BM, tn * GroupLds1::BN, kz, lds.t1);
+      break;
+    case 2:
+      gett_tile<2, 1, 4>(it.g, it.A, it.B, it.C, tm * GroupLds2::BM, tn * GroupLds2::BN, kz, lds.t2);
+      break;
+    default:
+      gett_tile<2, 2, 2>(it.g, it.A, it.B, it.C, tm * GroupLds0::BM, tn * GroupLds0::BN, kz, lds.t0);
   }
 }
 
@@ -347,16 +459,9 @@ __global__ __launch_bounds__(256) void group_reduce_kernel(const GroupItem* __re
   }
 }
 
-void launch_group_kofs(const GroupItem* items, int n, long long ksum, hipStream_t st) {
-  if (n <= 0 || ksum <= 0) return;
-  long long blocks = std::min<long long>((ksum + 255) / 256, 4096);
-  hipLaunchKernelGGL(group_kofs_kernel, dim3((unsigned)blocks), dim3(256), 0, st, items, n, ksum);
-}
-
 void launch_gett_group(const GroupItem* items, int n, int tiles, hipStream_t st) {
   if (n <= 0 || tiles <= 0) return;
-  hipLaunchKernelGGL((gett_group_kernel<kGroupWM, kGroupWN>), dim3((unsigned)tiles), dim3(256), 0,
-                     st, items, n);
+  hipLaunchKernelGGL(gett_group_kernel, dim3((unsigned)tiles), dim3(256), 0, st, items, n);
 }
 
 void launch_group_reduce(const GroupItem* items, const int* split_idx, int nsplit, long long total,
@@ -505,6 +610,28 @@ void launch_dot(const DotDesc& d, const double* A, const double* B, double* part
                 hipStream_t st) {
   hipLaunchKernelGGL(dot_kernel, dim3(kDotBlocks), dim3(256), 0, st, d, A, B, partial);
   hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, st, partial, kDotBlocks, out);
+}
+
+// ---------------------------------------------------------------------------
+// Packed copy of a strided view
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void pack_kernel(PackDesc d, const double* __restrict__ src,
+                                                   double* __restrict__ dst) {
+  for (long long e = blockIdx.x * 256LL + threadIdx.x; e < d.n; e += 256LL * gridDim.x) {
+    long long idx = e, off = 0;
+    for (int c = d.rank - 1; c >= 0; --c) {
+      const long long q = idx / d.d[c];
+      off += (idx - q * d.d[c]) * d.ss[c];
+      idx = q;
+    }
+    dst[e] = src[off];
+  }
+}
+
+void launch_pack(const PackDesc& d, const double* src, double* dst, hipStream_t st) {
+  if (d.n <= 0) return;
+  const long long blocks = std::min<long long>((d.n + 255) / 256, 16384);
+  hipLaunchKernelGGL(pack_kernel, dim3((unsigned)blocks), dim3(256), 0, st, d, src, dst);
 }
 
 // ---------------------------------------------------------------------------
