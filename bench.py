@@ -42,8 +42,9 @@ def ladder_algorithmic_flops(p, M):
 
 
 # Ratio of the oracle's time for a whole small-workload energy to its time through E(2)
-# (steps a0-a3), measured once with the same oracle on an 8-core host: 233 s / 58 s.
-ORACLE_FULL_OVER_E2 = 4.0
+# (steps a0-a3), measured once with the same oracle on an 8-core host (OpenBLAS 0.3.29,
+# 8 threads, nothing else running): 204.7 s / 53.2 s.
+ORACLE_FULL_OVER_E2 = 3.85
 
 
 def blas_threads():
@@ -70,7 +71,7 @@ def cpu_baseline(workload):
                 sample="oracle/dsrg.py run(through='e2') on the %s problem with s=%g (steps a0-a3: "
                        "densities, integrals, first-order amplitudes, [H0,A1], E(2)) took %.1f s; "
                        "scaled by %.1f, the oracle's full-energy/through-E(2) time ratio measured "
-                       "on an 8-core host (233 s / 58 s), to %.0f s per energy"
+                       "on an 8-core host (204.7 s / 53.2 s), to %.0f s per energy"
                        % (workload, p.s, dt, ORACLE_FULL_OVER_E2, per_energy))
 
 
@@ -159,6 +160,8 @@ def main():
         "energies": [dict(s=p.s, e2=r["e2"], e3=r["e3"]) for p, r in zip(probs, res)],
         "parity": parity,
         "plan": [r["plan"] for r in res],
+        "contraction_flops_per_energy": res[0]["gett_flops"],
+        "launches_per_energy": res[0]["n_launch"],
     }
     if not args.no_cpu_baseline:
         if args.workload in ("tiny", "small"):
