@@ -21,6 +21,7 @@ ROOT = os.path.dirname(os.path.abspath(__file__))
 sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6      # MI355X dense FP64 (matrix = vector)
+PEAK_FP32_TFLOPS = 157.3     # MI355X dense FP32 MFMA
 METRIC = "DSRG-MRPT3 energies/sec and MFMA TFLOP/s vs peak at |ΔE|≤1e-6 Eh"
 
 
@@ -82,6 +83,8 @@ def main():
     ap.add_argument("--warmup", type=int, default=2)
     ap.add_argument("--workload", default="small", choices=["tiny", "small", "medium", "large"])
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"],
+                    help="fp32: FP32 products in the contractions (FP64 sums and reductions)")
     args = ap.parse_args()
     if args.gpus != 1:
         sys.stderr.write("bench.py: this build runs on exactly one GPU; --gpus %d is not "
@@ -95,8 +98,10 @@ def main():
     dev = [_lib.to_device(p) for p in probs]
     torch.cuda.synchronize()
 
+    prec = 1 if args.precision == "fp32" else 0
+
     def step():
-        return [_lib.dsrg_pt3_energy(d) for d in dev]
+        return [_lib.dsrg_pt3_energy(d, precision=prec) for d in dev]
 
     for _ in range(args.warmup):
         step()
@@ -112,7 +117,7 @@ def main():
     # roofline of the dominant contraction kernel: HIP events bracket every contraction
     # launch (grouped or single) in a profiled pass over the same problems, on the stream
     # the kernels run on; the timed loop above replays the recorded graph instead
-    prof = [_lib.dsrg_pt3_energy(d, profile=True) for d in dev]
+    prof = [_lib.dsrg_pt3_energy(d, profile=True, precision=prec) for d in dev]
     torch.cuda.synchronize()
     names = ["gett_f64_kernel<0, *, *> (table contractions, one launch each)",
              "gett_f64_kernel<1, *, *> ((PP|PP) ladder contractions)",
@@ -132,8 +137,12 @@ def main():
         alg = fl[dom]
     avg_s = sec[dom] / max(1, nl[dom])
     achieved = alg / sec[dom] / 1e12 if sec[dom] > 0 else 0.0
-    roofline = dict(bound="mfma", achieved=achieved, peak=PEAK_FP64_TFLOPS, unit="TFLOP/s",
-                    frac=achieved / PEAK_FP64_TFLOPS, traffic=None, kernel=names[dom],
+    peak = PEAK_FP32_TFLOPS if prec else PEAK_FP64_TFLOPS
+    if prec:
+        names = [n.replace("f64", "f32").replace("gett_group_kernel<2, 2>", "gett_group_kernel<true>")
+                 for n in names]
+    roofline = dict(bound="mfma", achieved=achieved, peak=peak, unit="TFLOP/s",
+                    frac=achieved / peak, traffic=None, kernel=names[dom],
                     launches_per_energy=nl[dom] / len(dev), avg_launch_us=1e6 * avg_s,
                     alg_flops_per_launch=alg / max(1, nl[dom]),
                     issued_tflops=fl[dom] / sec[dom] / 1e12 if sec[dom] > 0 else 0.0)
@@ -150,7 +159,8 @@ def main():
     out = {
         "metric": METRIC, "value": energies / dt, "unit": "energies/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
-        "higher_is_better": True, "scaling": "weak", "vs_baseline": None, "dtype": "f64",
+        "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
+        "dtype": "f64" if not prec else "f64 (FP32 products)",
         "data": "synthetic",
         "config": {"workload": args.workload,
                    "problems": [dict(n_core=p.n_core, n_active=p.n_active, n_virtual=p.n_virtual,

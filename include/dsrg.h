@@ -48,7 +48,15 @@ extern "C" {
 #define DSRG_E_NONFINITE (-2)   /* NaN or Inf in eps, B or the densities */
 #define DSRG_E_OOM (-3)         /* device allocation failed or workspace_cap too small */
 #define DSRG_E_HIP (-4)         /* HIP runtime error (message in dsrg_last_error) */
-#define DSRG_E_UNSUPPORTED (-5) /* option not built (e.g. a precision other than FP64) */
+#define DSRG_E_UNSUPPORTED (-5) /* option not built (unknown precision, nA > 8) */
+
+/* options.precision */
+#define DSRG_PRECISION_FP64 0   /* every step in FP64 */
+#define DSRG_PRECISION_FP32 1   /* the tensor contractions (integral builds, ladders, table products)
+                                   multiply FP32-rounded operands on FP32 MFMA, sum in FP32 over at
+                                   most 1024 k values and accumulate those partial sums in FP64;
+                                   tensors stay FP64 in memory; denominators, the regulariser and
+                                   every energy reduction stay FP64 */
 
 /* options.flags */
 #define DSRG_F_DEVICE_PTRS 1    /* every array pointer in dsrg_problem is a device pointer */
@@ -82,7 +90,7 @@ typedef struct {
 
 typedef struct {
   int32_t flags;          /* DSRG_F_* */
-  int32_t precision;      /* 0 = FP64 (the only precision built) */
+  int32_t precision;      /* DSRG_PRECISION_FP64 (0) or DSRG_PRECISION_FP32 (1) */
   int64_t workspace_cap;  /* bytes of device workspace for batched integral blocks; 0 = 8 GiB */
   void* stream;           /* hipStream_t to run on, or NULL for the null stream; caller owns it */
 } dsrg_options;

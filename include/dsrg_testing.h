@@ -1,13 +1,15 @@
 /*
  * dsrg_testing.h -- test entry points of libdsrg (not needed by applications).
  *
- * dsrg_test_gett runs the library's strided FP64 contraction kernel once on host arrays:
+ * dsrg_test_gett runs the library's strided contraction kernel once on host arrays:
  *   C[m][n] = alpha * sum_k A[m][k] B[k][n] + (beta ? C[m][n] : 0)
  * where m, n, k are multi-indices with nm, nn, nk (<= 6) components of extents md, nd,
  * kd (row-major composition), and each operand addresses element (m, k), (k, n), (m, n)
  * through its own per-component strides (am, ak), (bk, bn), (cm, cn) in elements.
  * na, nb, nc are the host array lengths (elements), which must cover every addressed
  * element.  The caller owns every buffer; C is read (beta != 0) and overwritten.
+ * precision selects the kernel: DSRG_PRECISION_FP64 or DSRG_PRECISION_FP32 (FP32 products,
+ * FP64 accumulation between k chunks; see dsrg.h).
  * Returns DSRG_OK or a DSRG_E_* code (message in dsrg_last_error).
  */
 #ifndef DSRG_TESTING_H
@@ -20,7 +22,7 @@ int dsrg_test_gett(int nm, const int* md, const long long* am, const long long* 
                    int nn, const int* nd, const long long* bn, const long long* cn,
                    int nk, const int* kd, const long long* ak, const long long* bk,
                    const double* A, long long na, const double* B, long long nb,
-                   double* C, long long nc, double alpha, int beta);
+                   double* C, long long nc, double alpha, int beta, int precision);
 #ifdef __cplusplus
 }
 #endif

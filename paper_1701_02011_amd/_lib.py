@@ -25,6 +25,8 @@ DSRG_F_DEVICE_PTRS = 1
 DSRG_F_PROFILE = 2
 DSRG_F_NO_GROUPING = 4
 DSRG_F_NO_PLAN_CACHE = 8
+DSRG_PRECISION_FP64 = 0
+DSRG_PRECISION_FP32 = 1
 
 _dp = ctypes.POINTER(ctypes.c_double)
 
@@ -94,7 +96,7 @@ def load() -> ctypes.CDLL:
         lib.dsrg_test_gett.argtypes = [ctypes.c_int, ip, lp, lp, ctypes.c_int, ip, lp, lp,
                                        ctypes.c_int, ip, lp, lp, _dp, ctypes.c_longlong, _dp,
                                        ctypes.c_longlong, _dp, ctypes.c_longlong, ctypes.c_double,
-                                       ctypes.c_int]
+                                       ctypes.c_int, ctypes.c_int]
         lib.dsrg_test_gett.restype = ctypes.c_int
         _lib = lib
     return _lib
@@ -134,8 +136,8 @@ def _problem_struct(p, keep):
     return st, 0
 
 
-def _options(flags, stream=None, workspace_cap=0):
-    return Options(flags, 0, int(workspace_cap), stream)
+def _options(flags, stream=None, workspace_cap=0, precision=DSRG_PRECISION_FP64):
+    return Options(flags, int(precision), int(workspace_cap), stream)
 
 
 def to_device(p, device="cuda:0"):
@@ -181,27 +183,28 @@ def release_cache():
     _check(load().dsrg_release_cache())
 
 
-def dsrg_pt2_energy(p, stream=None, workspace_cap=0, grouping=True, cache=True):
+def dsrg_pt2_energy(p, stream=None, workspace_cap=0, grouping=True, cache=True, precision=0):
     keep = []
     st, fl = _problem_struct(p, keep)
     fl = _flags(fl, grouping=grouping, cache=cache)
     r = Result()
     _check(load().dsrg_pt2_energy(ctypes.byref(st), ctypes.byref(
-        _options(fl, _stream_of(p, stream), workspace_cap)), ctypes.byref(r)))
+        _options(fl, _stream_of(p, stream), workspace_cap, precision)), ctypes.byref(r)))
     return _result_dict(r)
 
 
-def dsrg_pt3_energy(p, stream=None, workspace_cap=0, profile=False, grouping=True, cache=True):
+def dsrg_pt3_energy(p, stream=None, workspace_cap=0, profile=False, grouping=True, cache=True,
+                    precision=0):
     keep = []
     st, fl = _problem_struct(p, keep)
     fl = _flags(fl, profile, grouping, cache)
     r = Result()
     _check(load().dsrg_pt3_energy(ctypes.byref(st), ctypes.byref(
-        _options(fl, _stream_of(p, stream), workspace_cap)), ctypes.byref(r)))
+        _options(fl, _stream_of(p, stream), workspace_cap, precision)), ctypes.byref(r)))
     return _result_dict(r)
 
 
-def dsrg_pt3_energy_ex(p, stream=None, workspace_cap=0, grouping=True):
+def dsrg_pt3_energy_ex(p, stream=None, workspace_cap=0, grouping=True, precision=0):
     """E(2), E(3) and the intermediates as numpy arrays (spin blocks, excitation order)."""
     keep = []
     st, fl = _problem_struct(p, keep)
@@ -213,13 +216,14 @@ def dsrg_pt3_energy_ex(p, stream=None, workspace_cap=0, grouping=True):
     inter = Intermediates(**{k: v.ctypes.data for k, v in bufs.items()})
     r = Result()
     _check(load().dsrg_pt3_energy_ex(ctypes.byref(st), ctypes.byref(
-        _options(fl, _stream_of(p, stream), workspace_cap)), ctypes.byref(r), ctypes.byref(inter)))
+        _options(fl, _stream_of(p, stream), workspace_cap, precision)), ctypes.byref(r),
+        ctypes.byref(inter)))
     out = _result_dict(r)
     out.update(bufs)
     return out
 
 
-def test_gett(A, B, C, m, n, k, alpha=1.0, beta=0):
+def test_gett(A, B, C, m, n, k, alpha=1.0, beta=0, precision=0):
     """Run the contraction kernel once.  m, n, k: lists of (extent, strideA-or-B, strideC)
     triples: m -> (extent, A stride, C stride), n -> (extent, B stride, C stride),
     k -> (extent, A stride, B stride)."""
@@ -232,6 +236,7 @@ def test_gett(A, B, C, m, n, k, alpha=1.0, beta=0):
                                len(n), I([x[0] for x in n]), L([x[1] for x in n]), L([x[2] for x in n]),
                                len(k), I([x[0] for x in k]), L([x[1] for x in k]), L([x[2] for x in k]),
                                A.ctypes.data_as(_dp), A.size, B.ctypes.data_as(_dp), B.size,
-                               C.ctypes.data_as(_dp), C.size, float(alpha), int(beta))
+                               C.ctypes.data_as(_dp), C.size, float(alpha), int(beta),
+                               int(precision))
     _check(rc)
     return C

@@ -7,6 +7,7 @@
 // and E(3) = <[H~(1), T(2)]> + <[H~(2)_{1,2}, T(1)]>.  The commutator terms come from the
 // generated table in dsrg_terms.inc; every contraction in it runs on the GETT kernel.
 #include "../../include/dsrg.h"
+#include "../../include/dsrg_testing.h"
 #include "kernels.h"
 
 #include <hip/hip_runtime.h>
@@ -335,7 +336,8 @@ struct Exec {
     const int ns = gett_splits(g, kSplitCap);
     const long long wse = ns > 1 ? (long long)ns * g.M * g.N : 0;
     double* ws = splitk_buffer(wse);
-    op([g, A, Bp, C, role, ws, wse](hipStream_t s) { launch_gett(g, A, Bp, C, s, role, ws, wse); });
+    const bool lo = f32;
+    op([g, A, Bp, C, role, ws, wse, lo](hipStream_t s) { launch_gett(g, A, Bp, C, s, role, ws, wse, lo); });
     if (profile) {
       HIPCHECK(hipEventRecord(r.b, st));
       recs.push_back(r);
@@ -950,15 +952,26 @@ struct Exec {
     for (size_t L = 0; L < lev.size(); ++L) {
       for (auto& it : lev[L]) {
         GettDesc& g = it.g;
-        // tile shape with the least padded work (ties: the first, square one)
+        // tile shape with the least padded work (ties: the first, square one); 128 x 128
+        // when it pads at most 10 % more than the best small shape (four times the work
+        // per loaded element) and the k range is long (short ones ran slower that way)
         long long bestw = -1;
         for (int sh = 0; sh < kGroupShapes; ++sh) {
+          if (sh == kGroupBigShape) continue;
           const long long tm = (g.M + kGroupTiles[sh][0] - 1) / kGroupTiles[sh][0];
           const long long tn = (g.N + kGroupTiles[sh][1] - 1) / kGroupTiles[sh][1];
           const long long w = tm * kGroupTiles[sh][0] * tn * kGroupTiles[sh][1];
           if (bestw < 0 || w < bestw) {
             bestw = w;
             it.shape = sh;
+            it.tiles_m = (int)tm;
+            it.tiles_n = (int)tn;
+          }
+        }
+        if (g.M >= 128 && g.N >= 128 && g.steps >= 128) {
+          const long long tm = (g.M + 127) / 128, tn = (g.N + 127) / 128;
+          if (tm * tn * 128 * 128 * 10 <= bestw * 11) {
+            it.shape = kGroupBigShape;
             it.tiles_m = (int)tm;
             it.tiles_n = (int)tn;
           }
@@ -992,15 +1005,19 @@ struct Exec {
       int i0, n, tiles, s0, ns;
       long long red;
       double flops;
+      bool big;
     };
     std::vector<LevelRange> ranges;
-    for (size_t L = 0; L < lev.size(); ++L) {
-      std::vector<int> order(lev[L].size());
-      for (size_t i = 0; i < order.size(); ++i) order[i] = (int)i;
+    for (size_t L = 0; L < lev.size(); ++L)
+     for (int big = 1; big >= 0; --big) {
+      std::vector<int> order;
+      for (size_t i = 0; i < lev[L].size(); ++i)
+        if ((lev[L][i].shape == kGroupBigShape) == (big == 1)) order.push_back((int)i);
+      if (order.empty()) continue;
       std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
         return lev[L][x].g.kchunk > lev[L][y].g.kchunk;
       });
-      LevelRange R{(int)items.size(), (int)order.size(), 0, (int)split_idx.size(), 0, 0, 0.0};
+      LevelRange R{(int)items.size(), (int)order.size(), 0, (int)split_idx.size(), 0, 0, 0.0, big == 1};
       for (int oi : order) {
         GroupItem it = lev[L][oi];
         const Fix& fx = levfix[L][oi];
@@ -1022,15 +1039,15 @@ struct Exec {
         items.push_back(it);
       }
       ranges.push_back(R);
-    }
+     }
     if (const char* path = getenv("DSRG_GROUP_DUMP")) {
       // planning record for tuning: use, level, M, N, K, splits, k chunk
       if (FILE* f = fopen(path, "a")) {
         for (size_t L = 0; L < ranges.size(); ++L)
           for (int i = 0; i < ranges[L].n; ++i) {
             const GroupItem& it = items[ranges[L].i0 + i];
-            fprintf(f, "%d,%d,%d,%d,%d,%d,%lld\n", use_id, (int)L, it.g.M, it.g.N, it.g.K, it.splits,
-                    it.g.kchunk);
+            fprintf(f, "%d,%d,%d,%d,%d,%d,%lld,%d\n", use_id, (int)L, it.g.M, it.g.N, it.g.K, it.splits,
+                    it.g.kchunk, it.shape);
           }
         fclose(f);
       }
@@ -1040,8 +1057,9 @@ struct Exec {
     for (auto& R : ranges) {
       const GroupItem* it = d_items + R.i0;
       const int* sp = d_split + R.s0;
-      group_launch(R.flops, [it, R](hipStream_t s) { launch_gett_group(it, R.n, R.tiles, s); }, true,
-                   R.n, R.tiles);
+      const bool lo = f32;
+      group_launch(R.flops, [it, R, lo](hipStream_t s) { launch_gett_group(it, R.n, R.tiles, R.big, lo, s); },
+                   true, R.n, R.tiles);
       if (R.ns > 0)
         group_launch(0.0, [it, sp, R](hipStream_t s) { launch_group_reduce(it, sp, R.ns, R.red, s); });
     }
@@ -1141,6 +1159,7 @@ struct Exec {
 
   // Run a use of the table into tensor outputs, or (scalar uses) into *scalar_out.
   int use_id = 0;
+  bool f32 = false;   // FP32 products in every contraction
   int group_level = 0;
   int grouped_uses = 0;
   bool grouped = true;
@@ -1600,7 +1619,9 @@ static int run(const dsrg_problem* P, const dsrg_options* O, dsrg_result* R,
   if (!P->eps || !P->B) throw Error(DSRG_E_ARG, "null eps or B");
   if (nA > 0 && (!P->gamma1 || !P->gamma2)) throw Error(DSRG_E_ARG, "null gamma1/gamma2 with nA > 0");
   if (nA > 8) throw Error(DSRG_E_UNSUPPORTED, "active spaces above 8 orbitals are not built");
-  if (O && O->precision != 0) throw Error(DSRG_E_UNSUPPORTED, "only FP64 is built");
+  if (O && O->precision != DSRG_PRECISION_FP64 && O->precision != DSRG_PRECISION_FP32)
+    throw Error(DSRG_E_UNSUPPORTED, "unknown precision");
+  const bool f32 = O && O->precision == DSRG_PRECISION_FP32;
   const int flags = O ? O->flags : 0;
   const bool devptr = flags & DSRG_F_DEVICE_PTRS;
   const bool profile = flags & DSRG_F_PROFILE;
@@ -1627,8 +1648,8 @@ static int run(const dsrg_problem* P, const dsrg_options* O, dsrg_result* R,
   int dev = 0;
   HIPCHECK(hipGetDevice(&dev));
   char kbuf[160];
-  snprintf(kbuf, sizeof(kbuf), "%d:%d:%d:%d:%d:%d:%d:%d:%lld", dev, nC, nA, nV, M, (int)sh.has_g3,
-           (int)pt3, (int)grouped, cap);
+  snprintf(kbuf, sizeof(kbuf), "%d:%d:%d:%d:%d:%d:%d:%d:%d:%lld", dev, nC, nA, nV, M, (int)sh.has_g3,
+           (int)pt3, (int)grouped, (int)f32, cap);
   const std::string key(kbuf);
   Plan* plan = nullptr;
   std::unique_ptr<Plan> fresh;
@@ -1713,6 +1734,7 @@ static int run(const dsrg_problem* P, const dsrg_options* O, dsrg_result* R,
   Exec X(Dims{nC, nA, nV}, st, *pool, op, in.B, M, cap, profile);
   X.grouped = grouped;
   X.group_cap = cap / 2;
+  X.f32 = f32;
   HIPCHECK(hipEventRecord(ev[0], st));
   BodyOut bo = body(X, op, *pool, sh, in, ev, st);
   if (I) {
@@ -1828,12 +1850,14 @@ extern "C" int dsrg_test_gett(int nm, const int* md, const long long* am, const 
                               int nn, const int* nd, const long long* bn, const long long* cn,
                               int nk, const int* kd, const long long* ak, const long long* bk,
                               const double* A, long long na, const double* B, long long nb,
-                              double* C, long long nc, double alpha, int beta) {
+                              double* C, long long nc, double alpha, int beta, int precision) {
   using namespace dsrg;
   return guarded([&] {
     if (nm < 0 || nn < 0 || nk < 0 || nm > kMaxComp || nn > kMaxComp || nk > kMaxComp)
       throw Error(DSRG_E_ARG, "component count out of range");
     if (!A || !B || !C || na <= 0 || nb <= 0 || nc <= 0) throw Error(DSRG_E_ARG, "null or empty array");
+    if (precision != DSRG_PRECISION_FP64 && precision != DSRG_PRECISION_FP32)
+      throw Error(DSRG_E_UNSUPPORTED, "unknown precision");
     GettDesc g;
     g.nm = nm; g.nn = nn; g.nk = nk;
     long long M = 1, N = 1, K = 1, amax = 0, bmax = 0, cmax = 0;
@@ -1871,7 +1895,7 @@ extern "C" int dsrg_test_gett(int nm, const int* md, const long long* am, const 
     const long long ws_elems = 1LL << 22;
     double* ws;
     HIPCHECK(hipMalloc(&ws, ws_elems * 8));
-    launch_gett(g, dA, dB, dC, 0, kRoleGeneric, ws, ws_elems);
+    launch_gett(g, dA, dB, dC, 0, kRoleGeneric, ws, ws_elems, precision == DSRG_PRECISION_FP32);
     HIPCHECK(hipGetLastError());
     HIPCHECK(hipDeviceSynchronize());
     (void)hipFree(ws);

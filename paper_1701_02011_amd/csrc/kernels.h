@@ -61,16 +61,20 @@ constexpr int kRoles = 4;
 // g must have been through gett_prepare.  ws (ws_elems doubles) enables split-K for
 // launches with few output tiles and a long k range: partial tiles go to ws and a
 // fixed-order reduction writes C (deterministic).
+// f32: FP32 products (operands rounded to FP32 in LDS, FP32 MFMA, sums flushed into the
+// FP64 output every kF32FlushSteps k steps); else FP64 throughout.
 void launch_gett(const GettDesc& g, const double* A, const double* B, double* C, hipStream_t st,
-                 int role, double* ws, long long ws_elems);
+                 int role, double* ws, long long ws_elems, bool f32 = false);
 int gett_splits(const GettDesc& g, long long ws_elems);
 // ---- grouped execution: independent contractions of one dependency level per launch ----
 // Item i owns workgroups [tile0, tile0 + tiles_m * tiles_n * splits) of a grouped launch,
 // each an output tile of shape kGroupTiles[shape] and one chunk of k steps (g.kchunk).
 // With splits > 1 the partial tiles go to g.part ([splits][M][N]) and launch_group_reduce
 // writes C.
-constexpr int kGroupShapes = 3;
-constexpr int kGroupTiles[kGroupShapes][2] = {{64, 64}, {16, 128}, {128, 16}};
+// Shapes 0-2 run in gett_group_kernel, shape 3 (128 x 128, for large items) in a launch of
+// its own (launch_gett_group with big = true), since its register count halves occupancy.
+constexpr int kGroupShapes = 4, kGroupBigShape = 3;
+constexpr int kGroupTiles[kGroupShapes][2] = {{64, 64}, {16, 128}, {128, 16}, {128, 128}};
 struct GroupItem {
   GettDesc g;
   const double* A = nullptr;
@@ -81,7 +85,7 @@ struct GroupItem {
   int tile0 = 0;          // first workgroup of this item
   long long red0 = 0;     // prefix of M N over the split items of the reduction launch
 };
-void launch_gett_group(const GroupItem* items, int n, int tiles, hipStream_t st);
+void launch_gett_group(const GroupItem* items, int n, int tiles, bool big, bool f32, hipStream_t st);
 // split_idx: indices of the items with splits > 1, in increasing red0
 void launch_group_reduce(const GroupItem* items, const int* split_idx, int nsplit, long long total,
                          hipStream_t st);

@@ -42,21 +42,54 @@ __device__ __forceinline__ long long decode(int idx, int n, const int* d, const 
 // ---------------------------------------------------------------------------
 constexpr int BK = kGettBK;
 
-// Tile of WGM x (4 / WGM) waves, each wave WM x WN MFMA blocks of 16 x 16.
-template <int WM, int WN, int WGM>
+// Tile of WGM x (4 / WGM) waves, each wave WM x WN MFMA blocks of 16 x 16; T is the
+// element type staged in LDS (double, or float for the FP32-product precision).
+template <int WM, int WN, int WGM, class T = double>
 struct TileLds {
   static constexpr int BM = 16 * WM * WGM, BN = 16 * WN * (4 / WGM);
   static constexpr int LDA = BM + 2, LDB = BN + 2;
-  double As[2][BK * LDA];
-  double Bs[2][BK * LDB];
+  T As[2][BK * LDA];
+  T Bs[2][BK * LDB];
 };
 
+// MFMA blocks of the two precisions.  FP64: v_mfma_f64_16x16x4f64, accumulator element r
+// of lane l is D[l/16 + 4 r][l%16].  FP32 products: v_mfma_f32_16x16x4f32 (operands
+// rounded to FP32, products accumulated in FP32 for at most kF32FlushSteps k steps, then
+// added into the FP64 output); accumulator element r of lane l is D[4 (l/16) + r][l%16].
+typedef float float4_t __attribute__((ext_vector_type(4)));
+template <bool kF32>
+struct Mfma;
+template <>
+struct Mfma<false> {
+  using T = double;
+  using Acc = double4_t;
+  static __device__ __forceinline__ Acc zero() { return (Acc){0.0, 0.0, 0.0, 0.0}; }
+  static __device__ __forceinline__ Acc fma(T a, T b, Acc c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lk, int r) { return lk + 4 * r; }
+};
+template <>
+struct Mfma<true> {
+  using T = float;
+  using Acc = float4_t;
+  static __device__ __forceinline__ Acc zero() { return (Acc){0.f, 0.f, 0.f, 0.f}; }
+  static __device__ __forceinline__ Acc fma(T a, T b, Acc c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+  }
+  static __device__ __forceinline__ int row(int lk, int r) { return 4 * lk + r; }
+};
+constexpr int kF32FlushSteps = 64;
+
 // One BM x BN output tile at (tile_m, tile_n) for chunk kz of the k steps of g.
-template <int WM, int WN, int WGM = 2>
+template <int WM, int WN, int WGM = 2, bool kF32 = false>
 __device__ __forceinline__ void gett_tile(const GettDesc& g, const double* __restrict__ A,
                                           const double* __restrict__ B, double* __restrict__ C,
-                                          int tile_m, int tile_n, int kz, TileLds<WM, WN, WGM>& lds) {
-  constexpr int BM = TileLds<WM, WN, WGM>::BM, BN = TileLds<WM, WN, WGM>::BN;
+                                          int tile_m, int tile_n, int kz,
+                                          TileLds<WM, WN, WGM, typename Mfma<kF32>::T>& lds) {
+  using MF = Mfma<kF32>;
+  using T = typename MF::T;
+  constexpr int BM = TileLds<WM, WN, WGM, T>::BM, BN = TileLds<WM, WN, WGM, T>::BN;
   static_assert(BM * BK % 256 == 0 && BN * BK % 256 == 0 && 256 % BM == 0 || BM >= 256, "tile");
   constexpr int LDA = BM + 2, LDB = BN + 2;
   constexpr int NA = BM * BK / 256, NB = BN * BK / 256;   // loads per thread per step
@@ -153,25 +186,61 @@ __device__ __forceinline__ void gett_tile(const GettDesc& g, const double* __res
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
       const bool ok = k0 + a_k(i) < kin && tile_m + a_m(i) < g.M;
-      As[buf][a_k(i) * LDA + a_m(i)] = ok ? ra[i] : 0.0;
+      As[buf][a_k(i) * LDA + a_m(i)] = ok ? (T)ra[i] : (T)0;
     }
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
       const bool ok = k0 + b_k(i) < kin && tile_n + b_n(i) < g.N;
-      Bs[buf][b_k(i) * LDB + b_n(i)] = ok ? rb[i] : 0.0;
+      Bs[buf][b_k(i) * LDB + b_n(i)] = ok ? (T)rb[i] : (T)0;
     }
   };
 
-  double4_t acc[WM][WN];
+  typename MF::Acc acc[WM][WN];
 #pragma unroll
   for (int a = 0; a < WM; ++a)
 #pragma unroll
-    for (int b = 0; b < WN; ++b) acc[a][b] = (double4_t){0.0, 0.0, 0.0, 0.0};
+    for (int b = 0; b < WN; ++b) acc[a][b] = MF::zero();
 
   const int wm = (wave % WGM) * (16 * WM);
   const int wn = (wave / WGM) * (16 * WN);
   const int li = lane & 15;
   const int lk = lane >> 4;
+
+  // write the accumulators: the first write of a tile follows beta (split-K partial tiles
+  // are written plain), later writes (FP32 products only) add to what is there
+  auto flush = [&](bool first) {
+    // an opaque copy of the tile origin keeps the compiler from hoisting the output
+    // offsets of every row and column out of the k loop (they would stay live in VGPRs)
+    int tm0 = tile_m, tn0 = tile_n;
+    asm volatile("" : "+v"(tm0), "+v"(tn0));
+#pragma unroll
+    for (int a = 0; a < WM; ++a) {
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        int m = tm0 + wm + a * 16 + MF::row(lk, r);
+        if (m >= g.M) continue;
+        if (g.part) {
+          double* prow = g.part + ((long long)kz * g.M + m) * g.N;
+#pragma unroll
+          for (int b = 0; b < WN; ++b) {
+            int n = tn0 + wn + b * 16 + li;
+            if (n < g.N) prow[n] = first ? (double)acc[a][b][r] : prow[n] + (double)acc[a][b][r];
+          }
+          continue;
+        }
+        long long cmo = decode(m, g.nm, g.md, g.cm);
+#pragma unroll
+        for (int b = 0; b < WN; ++b) {
+          int n = tn0 + wn + b * 16 + li;
+          if (n >= g.N) continue;
+          long long o = cmo + decode(n, g.nn, g.nd, g.cn);
+          double v = g.alpha * (double)acc[a][b][r];
+          if (g.beta || !first) v += C[o];
+          C[o] = v;
+        }
+      }
+    }
+  };
 
   int buf = 0;
   if (s_lo < s_hi) {
@@ -179,6 +248,8 @@ __device__ __forceinline__ void gett_tile(const GettDesc& g, const double* __res
     stash(0);
   }
   __syncthreads();
+  bool first = true;
+  int since = 0;
   for (long long s = s_lo; s < s_hi; ++s) {
     const bool more = s + 1 < s_hi;
     if (more) {
@@ -187,7 +258,7 @@ __device__ __forceinline__ void gett_tile(const GettDesc& g, const double* __res
     }
 #pragma unroll
     for (int kk = 0; kk < BK; kk += 4) {
-      double av[WM], bv[WN];
+      T av[WM], bv[WN];
 #pragma unroll
       for (int t = 0; t < WM; ++t) av[t] = As[buf][(kk + lk) * LDA + wm + t * 16 + li];
 #pragma unroll
@@ -195,49 +266,39 @@ __device__ __forceinline__ void gett_tile(const GettDesc& g, const double* __res
 #pragma unroll
       for (int a = 0; a < WM; ++a)
 #pragma unroll
-        for (int b = 0; b < WN; ++b)
-          acc[a][b] = __builtin_amdgcn_mfma_f64_16x16x4f64(av[a], bv[b], acc[a][b], 0, 0, 0);
+        for (int b = 0; b < WN; ++b) acc[a][b] = MF::fma(av[a], bv[b], acc[a][b]);
+    }
+    if (kF32 && more && ++since == kF32FlushSteps) {
+      flush(first);
+      first = false;
+      since = 0;
+#pragma unroll
+      for (int a = 0; a < WM; ++a)
+#pragma unroll
+        for (int b = 0; b < WN; ++b) acc[a][b] = MF::zero();
     }
     if (more) stash(buf ^ 1);
     __syncthreads();
     buf ^= 1;
   }
-
-#pragma unroll
-  for (int a = 0; a < WM; ++a) {
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-      int m = tile_m + wm + a * 16 + lk + 4 * r;
-      if (m >= g.M) continue;
-      if (g.part) {
-        double* prow = g.part + ((long long)kz * g.M + m) * g.N;
-#pragma unroll
-        for (int b = 0; b < WN; ++b) {
-          int n = tile_n + wn + b * 16 + li;
-          if (n < g.N) prow[n] = acc[a][b][r];
-        }
-        continue;
-      }
-      long long cmo = decode(m, g.nm, g.md, g.cm);
-#pragma unroll
-      for (int b = 0; b < WN; ++b) {
-        int n = tile_n + wn + b * 16 + li;
-        if (n >= g.N) continue;
-        long long o = cmo + decode(n, g.nn, g.nd, g.cn);
-        double v = g.alpha * acc[a][b][r];
-        if (g.beta) v += C[o];
-        C[o] = v;
-      }
-    }
-  }
+  flush(first);
 }
 
 template <int kRole, int WM, int WN>
 __global__ __launch_bounds__(256) void gett_f64_kernel(GettDesc g, const double* __restrict__ A,
                                                        const double* __restrict__ B,
                                                        double* __restrict__ C) {
-  __shared__ TileLds<WM, WN, 2> lds;
-  gett_tile<WM, WN, 2>(g, A, B, C, blockIdx.x * (32 * WM), blockIdx.y * (32 * WN), blockIdx.z, lds);
+  __shared__ TileLds<WM, WN, 2, double> lds;
+  gett_tile<WM, WN, 2, false>(g, A, B, C, blockIdx.x * (32 * WM), blockIdx.y * (32 * WN), blockIdx.z, lds);
+}
+
+// FP64 operands and output, FP32 products (DSRG_PRECISION_FP32)
+template <int kRole, int WM, int WN>
+__global__ __launch_bounds__(256) void gett_f32_kernel(GettDesc g, const double* __restrict__ A,
+                                                       const double* __restrict__ B,
+                                                       double* __restrict__ C) {
+  __shared__ TileLds<WM, WN, 2, float> lds;
+  gett_tile<WM, WN, 2, true>(g, A, B, C, blockIdx.x * (32 * WM), blockIdx.y * (32 * WN), blockIdx.z, lds);
 }
 
 // C[m][n] = alpha * sum_z part[z][m][n] (+ C) in a fixed order of z
@@ -345,16 +406,23 @@ int gett_splits(const GettDesc& g, long long ws_elems) {
 }
 
 template <int kRole>
-static void launch_role(const GettDesc& g, bool big, dim3 grid, const double* A, const double* B,
-                        double* C, hipStream_t st) {
-  if (big)
-    hipLaunchKernelGGL((gett_f64_kernel<kRole, 4, 4>), grid, dim3(256), 0, st, g, A, B, C);
-  else
-    hipLaunchKernelGGL((gett_f64_kernel<kRole, 2, 2>), grid, dim3(256), 0, st, g, A, B, C);
+static void launch_role(const GettDesc& g, bool big, bool f32, dim3 grid, const double* A,
+                        const double* B, double* C, hipStream_t st) {
+  if (f32) {
+    if (big)
+      hipLaunchKernelGGL((gett_f32_kernel<kRole, 4, 4>), grid, dim3(256), 0, st, g, A, B, C);
+    else
+      hipLaunchKernelGGL((gett_f32_kernel<kRole, 2, 2>), grid, dim3(256), 0, st, g, A, B, C);
+  } else {
+    if (big)
+      hipLaunchKernelGGL((gett_f64_kernel<kRole, 4, 4>), grid, dim3(256), 0, st, g, A, B, C);
+    else
+      hipLaunchKernelGGL((gett_f64_kernel<kRole, 2, 2>), grid, dim3(256), 0, st, g, A, B, C);
+  }
 }
 
 void launch_gett(const GettDesc& g0, const double* A, const double* B, double* C, hipStream_t st,
-                 int role, double* ws, long long ws_elems) {
+                 int role, double* ws, long long ws_elems, bool f32) {
   if (g0.M <= 0 || g0.N <= 0) return;
   GettDesc g = g0;
   const bool big = big_tiles(g);
@@ -371,11 +439,11 @@ void launch_gett(const GettDesc& g0, const double* A, const double* B, double* C
   dim3 grid((g.M + bm - 1) / bm, (g.N + bn - 1) / bn, ns);
   // the role only selects a distinct kernel symbol so profiles can tell the launches apart
   if (role == kRoleLadder)
-    launch_role<kRoleLadder>(g, big, grid, A, B, C, st);
+    launch_role<kRoleLadder>(g, big, f32, grid, A, B, C, st);
   else if (role == kRoleIntegrals)
-    launch_role<kRoleIntegrals>(g, big, grid, A, B, C, st);
+    launch_role<kRoleIntegrals>(g, big, f32, grid, A, B, C, st);
   else
-    launch_role<kRoleGeneric>(g, big, grid, A, B, C, st);
+    launch_role<kRoleGeneric>(g, big, f32, grid, A, B, C, st);
   if (ns > 1) {
     long long total = (long long)g.M * g.N;
     long long blocks = std::min<long long>((total + 255) / 256, 4096);
@@ -401,14 +469,15 @@ __device__ __forceinline__ int find_item_int(const GroupItem* __restrict__ items
 
 // Tile shapes of grouped items (kGroupTiles): 64 x 64, 16 x 128 and 128 x 16; the item's
 // shape is uniform in its workgroups, so the switch does not diverge.
-using GroupLds0 = TileLds<2, 2, 2>;
-using GroupLds1 = TileLds<1, 2, 1>;
-using GroupLds2 = TileLds<2, 1, 4>;
-static_assert(GroupLds0::BM == 64 && GroupLds0::BN == 64, "group tile 0");
-static_assert(GroupLds1::BM == 16 && GroupLds1::BN == 128, "group tile 1");
-static_assert(GroupLds2::BM == 128 && GroupLds2::BN == 16, "group tile 2");
-
+template <bool kF32>
 __global__ __launch_bounds__(256) void gett_group_kernel(const GroupItem* __restrict__ items, int n) {
+  using T = typename Mfma<kF32>::T;
+  using GroupLds0 = TileLds<2, 2, 2, T>;
+  using GroupLds1 = TileLds<1, 2, 1, T>;
+  using GroupLds2 = TileLds<2, 1, 4, T>;
+  static_assert(GroupLds0::BM == 64 && GroupLds0::BN == 64, "group tile 0");
+  static_assert(GroupLds1::BM == 16 && GroupLds1::BN == 128, "group tile 1");
+  static_assert(GroupLds2::BM == 128 && GroupLds2::BN == 16, "group tile 2");
   __shared__ union {
     GroupLds0 t0;
     GroupLds1 t1;
@@ -424,14 +493,30 @@ __global__ __launch_bounds__(256) void gett_group_kernel(const GroupItem* __rest
   const int tn = r - tm * it.tiles_n;
   switch (it.shape) {
     case 1:
-      gett_tile<1, 2, 1>(it.g, it.A, it.B, it.C, tm * GroupLds1::BM, tn * GroupLds1::BN, kz, lds.t1);
+      gett_tile<1, 2, 1, kF32>(it.g, it.A, it.B, it.C, tm * GroupLds1::BM, tn * GroupLds1::BN, kz, lds.t1);
       break;
     case 2:
-      gett_tile<2, 1, 4>(it.g, it.A, it.B, it.C, tm * GroupLds2::BM, tn * GroupLds2::BN, kz, lds.t2);
+      gett_tile<2, 1, 4, kF32>(it.g, it.A, it.B, it.C, tm * GroupLds2::BM, tn * GroupLds2::BN, kz, lds.t2);
       break;
     default:
-      gett_tile<2, 2, 2>(it.g, it.A, it.B, it.C, tm * GroupLds0::BM, tn * GroupLds0::BN, kz, lds.t0);
+      gett_tile<2, 2, 2, kF32>(it.g, it.A, it.B, it.C, tm * GroupLds0::BM, tn * GroupLds0::BN, kz, lds.t0);
   }
+}
+
+// items of the big shape (128 x 128)
+template <bool kF32>
+__global__ __launch_bounds__(256) void gett_group_big_kernel(const GroupItem* __restrict__ items, int n) {
+  using Lds = TileLds<4, 4, 2, typename Mfma<kF32>::T>;
+  __shared__ Lds lds;
+  const int b = blockIdx.x;
+  const GroupItem& it = items[find_item_int(items, n, b)];
+  const int t = b - it.tile0;
+  const int per = it.tiles_m * it.tiles_n;
+  const int kz = t / per;
+  const int r = t - kz * per;
+  const int tm = r / it.tiles_n;
+  const int tn = r - tm * it.tiles_n;
+  gett_tile<4, 4, 2, kF32>(it.g, it.A, it.B, it.C, tm * Lds::BM, tn * Lds::BN, kz, lds);
 }
 
 // split-K items: C = alpha * sum_z part[z] (+ C), fixed order of z
@@ -459,9 +544,17 @@ __global__ __launch_bounds__(256) void group_reduce_kernel(const GroupItem* __re
   }
 }
 
-void launch_gett_group(const GroupItem* items, int n, int tiles, hipStream_t st) {
+void launch_gett_group(const GroupItem* items, int n, int tiles, bool big, bool f32, hipStream_t st) {
   if (n <= 0 || tiles <= 0) return;
-  hipLaunchKernelGGL(gett_group_kernel, dim3((unsigned)tiles), dim3(256), 0, st, items, n);
+  const dim3 grid((unsigned)tiles), block(256);
+  if (big && f32)
+    hipLaunchKernelGGL(gett_group_big_kernel<true>, grid, block, 0, st, items, n);
+  else if (big)
+    hipLaunchKernelGGL(gett_group_big_kernel<false>, grid, block, 0, st, items, n);
+  else if (f32)
+    hipLaunchKernelGGL(gett_group_kernel<true>, grid, block, 0, st, items, n);
+  else
+    hipLaunchKernelGGL(gett_group_kernel<false>, grid, block, 0, st, items, n);
 }
 
 void launch_group_reduce(const GroupItem* items, const int* split_idx, int nsplit, long long total,
@@ -520,9 +613,15 @@ void launch_dot_group(const DotItem* items, int n, int blocks, double* partial, 
 // class given by which sub-space each index falls in; every entry of that class adds
 // coef * src[base + sum_k x_k ss_k], in entry order.
 // ---------------------------------------------------------------------------
+// tpe consecutive lanes share one output element: lane j of the group sums entries j,
+// j + tpe, ... of the element's class, and a fixed butterfly over the group adds the
+// partial sums (deterministic for a given tpe).  Small outputs with long entry lists use
+// wide groups, large outputs one lane per element.
 __global__ __launch_bounds__(256) void gather_kernel(GatherDesc g, const GatherEntry* __restrict__ ent,
-                                                     double* __restrict__ out, long long total) {
-  for (long long e = blockIdx.x * 256LL + threadIdx.x; e < total; e += 256LL * gridDim.x) {
+                                                     double* __restrict__ out, long long total, int tpe) {
+  const long long gt = blockIdx.x * 256LL + threadIdx.x;
+  const int sub = (int)(gt % tpe);
+  for (long long e = gt / tpe; e < total; e += 256LL * gridDim.x / tpe) {
     int x[4] = {0, 0, 0, 0};
     long long idx = e;
     int cls = 0;
@@ -536,13 +635,14 @@ __global__ __launch_bounds__(256) void gather_kernel(GatherDesc g, const GatherE
       }
     }
     double acc = 0.0;
-    for (int i = g.cls[cls]; i < g.cls[cls + 1]; ++i) {
+    for (int i = g.cls[cls] + sub; i < g.cls[cls + 1]; i += tpe) {
       const GatherEntry& en = ent[i];
       long long o = en.base + (long long)x[0] * en.ss[0] + (long long)x[1] * en.ss[1] +
                     (long long)x[2] * en.ss[2] + (long long)x[3] * en.ss[3];
       acc += en.coef * en.src[o];
     }
-    if (g.cls[cls + 1] > g.cls[cls]) out[e] += acc;
+    for (int w = tpe >> 1; w > 0; w >>= 1) acc += __shfl_xor(acc, w, 64);
+    if (sub == 0 && g.cls[cls + 1] > g.cls[cls]) out[e] += acc;
   }
 }
 
@@ -550,8 +650,12 @@ void launch_gather(const GatherDesc& g, const GatherEntry* entries, double* out,
   long long total = 1;
   for (int k = 0; k < g.rank; ++k) total *= g.dim[k];
   if (total <= 0 || g.cls[1 << g.rank] == 0) return;
-  long long blocks = std::min<long long>((total + 255) / 256, 8192);
-  hipLaunchKernelGGL(gather_kernel, dim3((unsigned)blocks), dim3(256), 0, st, g, entries, out, total);
+  // lanes per element: enough threads to fill the chip (>= 2^18), at most a wave
+  int tpe = 1;
+  while (tpe < 64 && total * tpe < (1LL << 18)) tpe <<= 1;
+  long long threads = total * tpe;
+  long long blocks = std::min<long long>((threads + 255) / 256, 8192);
+  hipLaunchKernelGGL(gather_kernel, dim3((unsigned)blocks), dim3(256), 0, st, g, entries, out, total, tpe);
 }
 
 // ---------------------------------------------------------------------------

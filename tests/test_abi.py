@@ -84,8 +84,9 @@ def test_non_finite_input(lib):
 
 def test_unsupported_options(lib):
     p = make_problem(1, 2, 3, 6, seed=1)
-    rc, _ = _call(p, opt=_lib.Options(0, 1, 0, None))
-    assert rc == _lib.DSRG_E_UNSUPPORTED
+    for precision in (2, -1, 7):
+        rc, _ = _call(p, opt=_lib.Options(0, precision, 0, None))
+        assert rc == _lib.DSRG_E_UNSUPPORTED
     p = make_problem(0, 9, 1, 4, seed=1, with_gamma3=False)
     rc, _ = _call(p)
     assert rc == _lib.DSRG_E_UNSUPPORTED
@@ -102,3 +103,7 @@ def test_test_gett_validates_strides(lib):
     with pytest.raises(_lib.DsrgError) as e:
         _lib.test_gett(A, B, C, m=[(3, 2, 1)], n=[(2, 1, 1)], k=[(2, 1, 2)])
     assert e.value.code == _lib.DSRG_E_ARG
+    A = np.zeros(4); B = np.zeros(4); C = np.zeros(4)
+    with pytest.raises(_lib.DsrgError) as e:
+        _lib.test_gett(A, B, C, m=[(2, 1, 1)], n=[(2, 1, 2)], k=[(2, 2, 1)], precision=5)
+    assert e.value.code == _lib.DSRG_E_UNSUPPORTED

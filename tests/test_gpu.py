@@ -34,57 +34,78 @@ def _close(x, ref, rel=1e-10):
 # ---------------------------------------------------------------------------
 # contraction kernel
 # ---------------------------------------------------------------------------
-@pytest.mark.parametrize("case", ["gemm", "ragged", "strided", "multi", "vec", "accum", "splitk"])
-def test_gett_kernel(case):
-    say("gett case", case)
+GETT_CASES = ["gemm", "ragged", "strided", "multi", "vec", "accum", "splitk", "longk"]
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("case", GETT_CASES)
+def test_gett_kernel(case, precision):
+    say("gett case", case, "precision", precision)
     rng = np.random.default_rng(hash(case) % 1000)
+    gett = lambda *a, **k: _lib.test_gett(*a, precision=precision, **k)
     if case == "gemm":
         M, N, K = 128, 64, 48
         A = rng.standard_normal((M, K)); B = rng.standard_normal((K, N)); C = np.zeros((M, N))
-        out = _lib.test_gett(A, B, C, m=[(M, K, N)], n=[(N, 1, 1)], k=[(K, 1, N)])
+        out = gett(A, B, C, m=[(M, K, N)], n=[(N, 1, 1)], k=[(K, 1, N)])
         ref = A @ B
     elif case == "ragged":
         M, N, K = 77, 45, 19
         A = rng.standard_normal((M, K)); B = rng.standard_normal((K, N)); C = np.zeros((M, N))
-        out = _lib.test_gett(A, B, C, m=[(M, K, N)], n=[(N, 1, 1)], k=[(K, 1, N)])
+        out = gett(A, B, C, m=[(M, K, N)], n=[(N, 1, 1)], k=[(K, 1, N)])
         ref = A @ B
     elif case == "strided":
         # C[i,j] = sum_k A[k,i] B[j,k]  (both operands transposed)
         M, N, K = 70, 66, 35
         A = rng.standard_normal((K, M)); B = rng.standard_normal((N, K)); C = np.zeros((M, N))
-        out = _lib.test_gett(A, B, C, m=[(M, 1, N)], n=[(N, K, 1)], k=[(K, M, 1)])
+        out = gett(A, B, C, m=[(M, 1, N)], n=[(N, K, 1)], k=[(K, M, 1)])
         ref = A.T @ B.T
     elif case == "multi":
         # O[a,b,i,j] = sum_{c,d} X[a,c,b,d] T[c,d,i,j]  with ragged extents
         a, b, c, d, i, j = 9, 7, 5, 6, 4, 3
-        X = rng.standard_normal((a, c, b, d)); T = rng.standard_normal((c, d, i, j))
+        A = rng.standard_normal((a, c, b, d)); B = rng.standard_normal((c, d, i, j))
         C = np.zeros((a, b, i, j))
-        out = _lib.test_gett(X, T, C,
-                             m=[(a, c * b * d, b * i * j), (b, d, i * j)],
-                             n=[(i, j, j), (j, 1, 1)],
-                             k=[(c, b * d, d * i * j), (d, 1, i * j)])
-        ref = np.einsum("acbd,cdij->abij", X, T)
+        out = gett(A, B, C,
+                   m=[(a, c * b * d, b * i * j), (b, d, i * j)],
+                   n=[(i, j, j), (j, 1, 1)],
+                   k=[(c, b * d, d * i * j), (d, 1, i * j)])
+        ref = np.einsum("acbd,cdij->abij", A, B)
+        K = c * d
     elif case == "vec":
         K = 1000
         A = rng.standard_normal(K); B = rng.standard_normal(K); C = np.zeros(1)
-        out = _lib.test_gett(A, B, C, m=[], n=[], k=[(K, 1, 1)])
+        out = gett(A, B, C, m=[], n=[], k=[(K, 1, 1)])
         ref = np.array([A @ B])
     elif case == "splitk":
         # few output tiles, long k range over a 3-component multi-index: split-K path
         M, N, k1, k2, k3 = 20, 37, 31, 29, 23
         A = rng.standard_normal((M, k1, k2, k3)); B = rng.standard_normal((k3, k1, k2, N))
         C = rng.standard_normal((M, N))
-        out = _lib.test_gett(A, B, C, m=[(M, k1 * k2 * k3, N)], n=[(N, 1, 1)],
-                             k=[(k1, k2 * k3, k2 * N), (k2, k3, N), (k3, 1, k1 * k2 * N)],
-                             alpha=0.75, beta=1)
+        out = gett(A, B, C, m=[(M, k1 * k2 * k3, N)], n=[(N, 1, 1)],
+                   k=[(k1, k2 * k3, k2 * N), (k2, k3, N), (k3, 1, k1 * k2 * N)],
+                   alpha=0.75, beta=1)
         ref = C + 0.75 * np.einsum("mabc,cabn->mn", A, B)
+        K = k1 * k2 * k3
+    elif case == "longk":
+        # k longer than two FP32 flush chunks (64 steps of 16), ragged, accumulate
+        M, N, K = 70, 90, 64 * 16 * 2 + 37
+        A = rng.standard_normal((M, K)); B = rng.standard_normal((K, N)); C = rng.standard_normal((M, N))
+        out = gett(A, B, C, m=[(M, K, N)], n=[(N, 1, 1)], k=[(K, 1, N)], alpha=1.5, beta=1)
+        ref = C + 1.5 * (A @ B)
     else:
         M, N, K = 65, 130, 17
         A = rng.standard_normal((M, K)); B = rng.standard_normal((K, N)); C = rng.standard_normal((M, N))
-        out = _lib.test_gett(A, B, C, m=[(M, K, N)], n=[(N, 1, 1)], k=[(K, 1, N)],
-                             alpha=-0.5, beta=1)
+        out = gett(A, B, C, m=[(M, K, N)], n=[(N, 1, 1)], k=[(K, 1, N)], alpha=-0.5, beta=1)
         ref = C - 0.5 * (A @ B)
-    np.testing.assert_allclose(out.reshape(ref.shape), ref, rtol=1e-13, atol=1e-12)
+    out = out.reshape(ref.shape)
+    if precision == 0:
+        np.testing.assert_allclose(out, ref, rtol=1e-13, atol=1e-12)
+        return
+    # FP32 products: operands rounded to FP32 (relative 2^-24 each) and FP32 sums over at
+    # most 1024 terms before FP64 accumulation; a worst-case bound per element
+    bound = 4 * 2.0 ** -24 * (K + 64) * np.abs(A).max() * np.abs(B).max() * 1.5
+    err = np.abs(out - ref).max()
+    assert err <= bound, (err, bound)
+    assert err > 0.0   # the FP32 kernel really ran
 
 
 # ---------------------------------------------------------------------------
@@ -220,6 +241,30 @@ def test_plan_replay_matches_eager():
     again = _lib.dsrg_pt3_energy(p)
     assert again["plan"] == 1 and again["e3"] == eager["e3"]
     _lib.release_cache()
+
+
+@pytest.mark.parametrize("name", ["micro", "tiny", "small"])
+def test_fp32_products_meet_mixed_bar(name):
+    """DSRG_PRECISION_FP32 (FP32 products in every contraction, FP64 sums, denominators and
+    reductions): |dE| <= 1e-6 max(1, |E|) against the FP64 oracle, the bar for the mixed
+    path.  Also differs from the FP64 path (the FP32 kernels ran)."""
+    if name == "small":
+        cases = []
+        for s_ in SMALL_S_VALUES:
+            gold = json.load(open(os.path.join(GOLDEN, "small_s%g.json" % s_)))
+            cases.append((make_config("small", s=s_), gold["e2"], gold["e3"]))
+    else:
+        p = make_problem(2, 2, 4, 9, seed=5, s=1.3) if name == "micro" else make_config(name)
+        r = dsrg.run(p)
+        cases = [(p, r.e2, r.e3)]
+    for p, e2, e3 in cases:
+        say("fp32 products", name, p.s)
+        g = _lib.dsrg_pt3_energy(p, precision=1)
+        g64 = _lib.dsrg_pt3_energy(p)
+        for k, ref in (("e2", e2), ("e3", e3)):
+            err = abs(g[k] - ref)
+            assert err <= 1e-6 * max(1.0, abs(ref)), (k, g[k], ref, err)
+        assert g["e3"] != g64["e3"]
 
 
 def test_nonfinite_device_input():
