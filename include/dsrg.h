@@ -141,6 +141,14 @@ int dsrg_pt2_energy(const dsrg_problem* prob, const dsrg_options* opt, dsrg_resu
 /* E(2) and E(3) (Eqs. E(2), E(3)).  Same conventions as dsrg_pt2_energy. */
 int dsrg_pt3_energy(const dsrg_problem* prob, const dsrg_options* opt, dsrg_result* out);
 
+/* E(2) and E(3) of n independent problems (e.g. geometries along a dissociation curve),
+   one after another on one stream; problems of equal shape share one plan.  outs[k] and
+   status[k] receive item k's result and return code; an item that fails (bad arguments,
+   non-finite input) is skipped and leaves outs[k] untouched.  Returns DSRG_OK if at least
+   one item succeeded, else the first item's code (DSRG_E_ARG for n < 1 or null arrays). */
+int dsrg_pt3_energy_batch(const dsrg_problem* probs, int32_t n, const dsrg_options* opt,
+                          dsrg_result* outs, int32_t* status);
+
 /* As dsrg_pt3_energy, and copies the requested intermediates to host memory. */
 int dsrg_pt3_energy_ex(const dsrg_problem* prob, const dsrg_options* opt, dsrg_result* out,
                        const dsrg_intermediates* inter);

@@ -89,6 +89,10 @@ def load() -> ctypes.CDLL:
                                            ctypes.POINTER(Result), ctypes.POINTER(Intermediates)]
         lib.dsrg_pt3_energy_ex.restype = ctypes.c_int
         lib.dsrg_release_cache.restype = ctypes.c_int
+        lib.dsrg_pt3_energy_batch.argtypes = [ctypes.POINTER(Problem), ctypes.c_int32,
+                                              ctypes.POINTER(Options), ctypes.POINTER(Result),
+                                              ctypes.POINTER(ctypes.c_int32)]
+        lib.dsrg_pt3_energy_batch.restype = ctypes.c_int
         lib.dsrg_last_error.restype = ctypes.c_char_p
         lib.dsrg_version.restype = ctypes.c_int
         ip = ctypes.POINTER(ctypes.c_int)
@@ -202,6 +206,32 @@ def dsrg_pt3_energy(p, stream=None, workspace_cap=0, profile=False, grouping=Tru
     _check(load().dsrg_pt3_energy(ctypes.byref(st), ctypes.byref(
         _options(fl, _stream_of(p, stream), workspace_cap, precision)), ctypes.byref(r)))
     return _result_dict(r)
+
+
+def dsrg_pt3_energy_batch(problems, stream=None, workspace_cap=0, precision=0, grouping=True,
+                          cache=True):
+    """E(2), E(3) of several problems in one call: (list of result dicts or None, codes).
+    All problems must be host problems or all device dicts."""
+    keep = []
+    structs, flags = [], set()
+    for p in problems:
+        st, fl = _problem_struct(p, keep)
+        structs.append(st)
+        flags.add(fl)
+    if len(flags) > 1:
+        raise ValueError("mix of host and device problems")
+    n = len(structs)
+    arr = (Problem * n)(*structs)
+    res = (Result * n)()
+    status = (ctypes.c_int32 * n)()
+    fl = _flags(flags.pop() if flags else 0, grouping=grouping, cache=cache)
+    st0 = _stream_of(problems[0], stream) if problems else None
+    rc = load().dsrg_pt3_energy_batch(arr, n, ctypes.byref(_options(fl, st0, workspace_cap, precision)),
+                                      res, status)
+    codes = list(status)
+    if rc != DSRG_OK and not any(c == DSRG_OK for c in codes):
+        _check(rc)
+    return [(_result_dict(res[k]) if codes[k] == DSRG_OK else None) for k in range(n)], codes
 
 
 def dsrg_pt3_energy_ex(p, stream=None, workspace_cap=0, grouping=True, precision=0):

@@ -1825,6 +1825,22 @@ int dsrg_pt3_energy(const dsrg_problem* prob, const dsrg_options* opt, dsrg_resu
   return dsrg::guarded([&] { return dsrg::run(prob, opt, out, nullptr, true); });
 }
 
+int dsrg_pt3_energy_batch(const dsrg_problem* probs, int32_t n, const dsrg_options* opt,
+                          dsrg_result* outs, int32_t* status) {
+  if (!probs || !outs || !status || n < 1) {
+    dsrg::g_last_error = "null arrays or n < 1";
+    return DSRG_E_ARG;
+  }
+  int first_error = DSRG_OK;
+  bool any_ok = false;
+  for (int32_t k = 0; k < n; ++k) {
+    status[k] = dsrg::guarded([&] { return dsrg::run(probs + k, opt, outs + k, nullptr, true); });
+    if (status[k] == DSRG_OK) any_ok = true;
+    else if (first_error == DSRG_OK) first_error = status[k];
+  }
+  return any_ok ? DSRG_OK : first_error;
+}
+
 int dsrg_pt3_energy_ex(const dsrg_problem* prob, const dsrg_options* opt, dsrg_result* out,
                        const dsrg_intermediates* inter) {
   return dsrg::guarded([&] { return dsrg::run(prob, opt, out, inter, true); });

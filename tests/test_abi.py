@@ -98,6 +98,22 @@ def test_null_problem(lib):
     assert rc == _lib.DSRG_E_ARG
 
 
+def test_batch_rejects_bad_items_without_gpu(lib):
+    """Every item fails validation on the host: the call returns the first item's code."""
+    p = make_problem(1, 2, 3, 6, seed=1)
+    keep = []
+    st, fl = _lib._problem_struct(p, keep)
+    st.n_aux = 0
+    st2, _ = _lib._problem_struct(p, keep)
+    st2.s = -1.0
+    arr = (_lib.Problem * 2)(st, st2)
+    res = (_lib.Result * 2)()
+    status = (ctypes.c_int32 * 2)()
+    rc = lib.dsrg_pt3_energy_batch(arr, 2, None, res, status)
+    assert rc == _lib.DSRG_E_ARG and list(status) == [_lib.DSRG_E_ARG, _lib.DSRG_E_ARG]
+    assert lib.dsrg_pt3_energy_batch(arr, 0, None, res, status) == _lib.DSRG_E_ARG
+
+
 def test_test_gett_validates_strides(lib):
     A = np.zeros(4); B = np.zeros(4); C = np.zeros(4)
     with pytest.raises(_lib.DsrgError) as e:

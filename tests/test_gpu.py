@@ -267,6 +267,32 @@ def test_fp32_products_meet_mixed_bar(name):
         assert g["e3"] != g64["e3"]
 
 
+def test_batch_of_uneven_problems():
+    """dsrg_pt3_energy_batch: uneven problems (two of the same shape), one invalid item
+    (skipped with its code), each result equal to its single call."""
+    probs = [make_problem(2, 2, 4, 9, seed=5, s=1.3), make_problem(1, 3, 2, 8, seed=7, s=0.6),
+             make_problem(2, 2, 4, 9, seed=6, s=0.4), make_problem(1, 2, 3, 10, seed=11, s=0.5)]
+    bad = make_problem(1, 2, 3, 10, seed=11, s=0.5)
+    bad.B = bad.B.copy()
+    bad.B[0, 0, 0] = np.nan
+    probs.insert(2, bad)
+    say("batch of", len(probs))
+    res, codes = _lib.dsrg_pt3_energy_batch(probs)
+    assert codes[2] == _lib.DSRG_E_NONFINITE and res[2] is None
+    for k, p in enumerate(probs):
+        if k == 2:
+            continue
+        assert codes[k] == _lib.DSRG_OK
+        single = _lib.dsrg_pt3_energy(p)
+        assert res[k]["e2"] == single["e2"] and res[k]["e3"] == single["e3"], k
+        r = dsrg.run(p)
+        assert _close(res[k]["e3"], r.e3) and _close(res[k]["e2"], r.e2)
+    d = [_lib.to_device(p) for k, p in enumerate(probs) if k != 2]
+    dres, dcodes = _lib.dsrg_pt3_energy_batch(d)
+    assert all(c == _lib.DSRG_OK for c in dcodes)
+    assert [x["e3"] for x in dres] == [res[k]["e3"] for k in range(len(probs)) if k != 2]
+
+
 def test_nonfinite_device_input():
     import torch
     p = make_problem(1, 2, 3, 6, seed=1)
