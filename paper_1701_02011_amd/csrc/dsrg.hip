@@ -1125,6 +1125,44 @@ struct Exec {
     return true;
   }
 
+  // Products that a use too large to group as a whole still groups: temporaries of the
+  // whole chain and the largest contraction below these bounds.
+  static constexpr double kSmallProductBytes = 64.0 * (1 << 20), kSmallProductFlops = 2e10;
+  // Elements of the temporaries of a product's contraction chain and its largest
+  // contraction's flops (the same greedy order as the executors).
+  void product_cost(const TProduct& P, double& temp, double& flops) {
+    temp = 0;
+    flops = 0;
+    LetterRange lr = full_range(P);
+    for (auto& kv : lr.len)
+      if (kv.second == 0) return;
+    std::vector<Opnd> ops;
+    for (auto& f : P.f) ops.push_back(factor_view(f, P.space, lr, nullptr, 0));
+    while (ops.size() > 2 || (ops.size() == 2 && !P.res.empty())) {
+      auto [bi, bj] = pick_pair(ops, lr);
+      std::string u = ops[bi].letters;
+      for (char c : ops[bj].letters)
+        if (u.find(c) == std::string::npos) u += c;
+      double all = 1, res = 1;
+      std::string rl;
+      for (char c : u) {
+        all *= lr.len.at(c);
+        const bool shared = ops[bi].letters.find(c) != std::string::npos &&
+                            ops[bj].letters.find(c) != std::string::npos;
+        if (!shared) {
+          res *= lr.len.at(c);
+          rl += c;
+        }
+      }
+      temp += res;
+      flops = std::max(flops, 2.0 * all);
+      Opnd r;
+      r.letters = rl;
+      ops.erase(ops.begin() + bj);
+      ops[bi] = r;
+    }
+  }
+
   // One launch per contraction, temporaries reused from a free list.
   void run_serial(const std::vector<std::pair<int, const TProduct*>>& prods,
                   std::map<std::string, TensorRef>& outs, double* scalar_out) {
@@ -1182,8 +1220,44 @@ struct Exec {
       }
       plain.push_back({pidx, &P});
     }
-    if (grouped && run_grouped(plain, outs, scalar_out)) ++grouped_uses;
-    else run_serial(plain, outs, scalar_out);
+    if (grouped && run_grouped(plain, outs, scalar_out)) {
+      ++grouped_uses;
+    } else if (grouped) {
+      // too large to group as a whole: the small products run grouped in waves whose
+      // temporaries fit, the others one launch each; scalar uses sum the waves' partial
+      // values in a fixed order
+      std::vector<std::pair<int, const TProduct*>> large;
+      std::vector<std::vector<std::pair<int, const TProduct*>>> waves(1);
+      double wave_bytes = 0;
+      for (auto& pp : plain) {
+        double temp = 0, flops = 0;
+        product_cost(*pp.second, temp, flops);
+        if (temp * 8 > kSmallProductBytes || flops > kSmallProductFlops) {
+          large.push_back(pp);
+          continue;
+        }
+        if (!waves.back().empty() && wave_bytes + temp * 8 > 0.75 * group_cap) {
+          waves.emplace_back();
+          wave_bytes = 0;
+        }
+        waves.back().push_back(pp);
+        wave_bytes += temp * 8;
+      }
+      const int nw = (int)waves.size();
+      double* part = scalar_out ? pool.alloc(nw + 1) : nullptr;
+      for (int w = 0; w < nw; ++w) {
+        double* pw = part ? part + w : nullptr;
+        if (run_grouped(waves[w], outs, pw)) ++grouped_uses;
+        else run_serial(waves[w], outs, pw);
+      }
+      run_serial(large, outs, part ? part + nw : nullptr);
+      if (scalar_out) {
+        double* ones = upload(std::vector<double>(nw + 1, 1.0));
+        op([nw, part, ones, scalar_out](hipStream_t s) { launch_weighted_sum(nw + 1, part, ones, scalar_out, s); });
+      }
+    } else {
+      run_serial(plain, outs, scalar_out);
+    }
     for (auto& grp : pppp) {
       const TProduct& P0 = *grp.second[0];
       std::string L, key;

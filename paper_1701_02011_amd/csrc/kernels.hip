@@ -284,12 +284,47 @@ __device__ __forceinline__ void gett_tile(const GettDesc& g, const double* __res
   flush(first);
 }
 
+// Workgroups are dispatched to the 8 XCDs round-robin by their id; this bijection gives
+// XCD x a contiguous range of logical tiles, so the tiles that share operand panels share
+// one XCD's L2 instead of being spread over all eight.
+constexpr int kXcds = 8;
+__device__ __forceinline__ int xcd_tile(int b, int total) {
+  const int q = total / kXcds, r = total - q * kXcds;
+  const int x = b % kXcds, j = b / kXcds;
+  return x * q + min(x, r) + j;
+}
+
+// Grouped launches order their tiles longest first; a contiguous range per XCD would load
+// XCD 0 with the longest ones.  Within each window of kXcds * 8 workgroups XCD x takes 8
+// consecutive tiles instead (the tail past the last whole window keeps its order).
+__device__ __forceinline__ int xcd_tile_windowed(int b, int total) {
+  constexpr int c = 8, W = kXcds * c;
+  const int full = total / W * W;
+  if (b >= full) return b;
+  const int base = b / W * W, o = b - base;
+  return base + (o % kXcds) * c + o / kXcds;
+}
+
+// Logical tile L of a (gx, gy, gz) grid, consecutive L walking m tiles first.
+template <int WM, int WN, bool kF32>
+__device__ __forceinline__ void gett_grid_tile(const GettDesc& g, const double* __restrict__ A,
+                                               const double* __restrict__ B, double* __restrict__ C,
+                                               TileLds<WM, WN, 2, typename Mfma<kF32>::T>& lds) {
+  const int gx = gridDim.x, gy = gridDim.y;
+  const int total = gx * gy * gridDim.z;
+  const int b = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+  const int L = xcd_tile(b, total);
+  const int tm = L % gx, rest = L / gx;
+  const int tn = rest % gy, kz = rest / gy;
+  gett_tile<WM, WN, 2, kF32>(g, A, B, C, tm * (32 * WM), tn * (32 * WN), kz, lds);
+}
+
 template <int kRole, int WM, int WN>
 __global__ __launch_bounds__(256) void gett_f64_kernel(GettDesc g, const double* __restrict__ A,
                                                        const double* __restrict__ B,
                                                        double* __restrict__ C) {
   __shared__ TileLds<WM, WN, 2, double> lds;
-  gett_tile<WM, WN, 2, false>(g, A, B, C, blockIdx.x * (32 * WM), blockIdx.y * (32 * WN), blockIdx.z, lds);
+  gett_grid_tile<WM, WN, false>(g, A, B, C, lds);
 }
 
 // FP64 operands and output, FP32 products (DSRG_PRECISION_FP32)
@@ -298,7 +333,7 @@ __global__ __launch_bounds__(256) void gett_f32_kernel(GettDesc g, const double*
                                                        const double* __restrict__ B,
                                                        double* __restrict__ C) {
   __shared__ TileLds<WM, WN, 2, float> lds;
-  gett_tile<WM, WN, 2, true>(g, A, B, C, blockIdx.x * (32 * WM), blockIdx.y * (32 * WN), blockIdx.z, lds);
+  gett_grid_tile<WM, WN, true>(g, A, B, C, lds);
 }
 
 // C[m][n] = alpha * sum_z part[z][m][n] (+ C) in a fixed order of z
@@ -483,7 +518,7 @@ __global__ __launch_bounds__(256) void gett_group_kernel(const GroupItem* __rest
     GroupLds1 t1;
     GroupLds2 t2;
   } lds;
-  const int b = blockIdx.x;
+  const int b = xcd_tile_windowed(blockIdx.x, gridDim.x);
   const GroupItem& it = items[find_item_int(items, n, b)];
   const int t = b - it.tile0;
   const int per = it.tiles_m * it.tiles_n;
@@ -508,7 +543,7 @@ template <bool kF32>
 __global__ __launch_bounds__(256) void gett_group_big_kernel(const GroupItem* __restrict__ items, int n) {
   using Lds = TileLds<4, 4, 2, typename Mfma<kF32>::T>;
   __shared__ Lds lds;
-  const int b = blockIdx.x;
+  const int b = xcd_tile_windowed(blockIdx.x, gridDim.x);
   const GroupItem& it = items[find_item_int(items, n, b)];
   const int t = b - it.tile0;
   const int per = it.tiles_m * it.tiles_n;

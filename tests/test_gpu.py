@@ -206,6 +206,24 @@ def test_grouped_matches_per_launch(name):
     assert c["n_launch"] < a["n_launch"]
 
 
+def test_medium_partly_grouped_matches_per_launch():
+    """At the medium size a commutator's temporaries exceed the grouping budget: its small
+    products run grouped in waves and the large ones one launch each.  Same energies as one
+    launch per contraction, to summation order; deterministic."""
+    p = make_config("medium")
+    d = _lib.to_device(p)
+    say("medium: partly grouped vs per-launch")
+    a = _lib.dsrg_pt3_energy(d, grouping=False, cache=False)
+    b = _lib.dsrg_pt3_energy(d, cache=False)
+    c = _lib.dsrg_pt3_energy(d, cache=False)
+    # E(2), both E(3) parts and the two commutators each ran (at least partly) grouped
+    assert b["grouped_uses"] >= 5 and a["grouped_uses"] == 0
+    assert b["n_launch"] < a["n_launch"] / 2, (b["n_launch"], a["n_launch"])
+    for k in ("e2", "e3_a", "e3_b"):
+        assert _close(b[k], a[k], 1e-12), (k, a[k], b[k])
+    assert c["e3"] == b["e3"] and c["e2"] == b["e2"]
+
+
 def test_plan_replay_matches_eager():
     """First call of a shape records a plan (a HIP graph of the pipeline); later calls copy
     their inputs and replay it.  Every replay, with eager work and synchronisations between
