@@ -52,6 +52,26 @@ def ladder_algorithmic_flops(p, M):
 ORACLE_FULL_OVER_E2 = 3.85
 
 
+def measured_traffic(kernel, workload, precision):
+    """HBM bytes per launch of the kernel from the committed rocprofv3 counter summaries
+    (FETCH_SIZE and WRITE_SIZE, scaled by a copy of known size), or None when no summary
+    covers this kernel and workload or the kernel source changed since it was taken."""
+    import glob
+    import hashlib
+    src = os.path.join(ROOT, "paper_1701_02011_amd", "csrc", "kernels.hip")
+    digest = hashlib.sha256(open(src, "rb").read()).hexdigest()
+    for path in glob.glob(os.path.join(ROOT, "profiles", "*_hbm_traffic.txt")):
+        kv = {}
+        for line in open(path):
+            if ": " in line and not line.startswith(" "):
+                k, v = line.rstrip("\n").split(": ", 1)
+                kv[k] = v
+        if (kv.get("kernel") == kernel and kv.get("workload") == workload and
+                kv.get("precision") == precision and kv.get("kernels_hip_sha256") == digest):
+            return float(kv["traffic_bytes_per_launch"])
+    return None
+
+
 def blas_threads():
     try:
         from threadpoolctl import threadpool_info
@@ -131,7 +151,7 @@ def main():
     names = ["gett_f64_kernel<0, *, *> (table contractions, one launch each)",
              "gett_f64_kernel<1, *, *> ((PP|PP) ladder contractions)",
              "gett_f64_kernel<2, *, *> (Coulomb-block builds B.B)",
-             "gett_group_kernel<2, 2> (grouped table contractions)"]
+             "gett_group_kernel<false> (grouped table contractions)"]
     sec = [sum(r["role_seconds"][k] for r in prof) for k in range(4)]
     nl = [sum(r["role_launches"][k] for r in prof) for k in range(4)]
     fl = [sum(r["role_flops"][k] for r in prof) for k in range(4)]
@@ -150,10 +170,11 @@ def main():
     achieved = alg / sec[dom] / 1e12 if sec[dom] > 0 else 0.0
     peak = PEAK_FP32_TFLOPS if prec else PEAK_FP64_TFLOPS
     if prec:
-        names = [n.replace("f64", "f32").replace("gett_group_kernel<2, 2>", "gett_group_kernel<true>")
+        names = [n.replace("f64", "f32").replace("gett_group_kernel<false>", "gett_group_kernel<true>")
                  for n in names]
     roofline = dict(bound="mfma", achieved=achieved, peak=peak, unit="TFLOP/s",
-                    frac=achieved / peak, traffic=None, kernel=names[dom],
+                    frac=achieved / peak, traffic=measured_traffic(names[dom], args.workload, args.precision),
+                    kernel=names[dom],
                     launches_per_energy=nl[dom] / len(dev), avg_launch_us=1e6 * avg_s,
                     alg_flops_per_launch=alg / max(1, nl[dom]),
                     issued_tflops=fl[dom] / sec[dom] / 1e12 if sec[dom] > 0 else 0.0)
