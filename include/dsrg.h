@@ -149,6 +149,17 @@ int dsrg_pt3_energy(const dsrg_problem* prob, const dsrg_options* opt, dsrg_resu
 int dsrg_pt3_energy_batch(const dsrg_problem* probs, int32_t n, const dsrg_options* opt,
                           dsrg_result* outs, int32_t* status);
 
+/* E(2), E(3) and a core-pair decomposition of E(3).  E(3) = <[H~(1), T(2)]> +
+   <[H~(2)_{1,2}, T(1)]> is linear in the amplitudes of its two commutators (Eq. E(3));
+   e3_pairs[k] is its value with those amplitudes restricted to the doubles whose two hole
+   indices are the spatial core orbitals i and j (any spins, both orders), for the pairs
+   i <= j in row-major order of the upper triangle (k = 0 .. nC(nC+1)/2 - 1); *e3_rest =
+   E(3) - sum_k e3_pairs[k] (singles and doubles with an active hole index).  The
+   decomposition is a reading: the paper defines none.  e3_pairs may be NULL if n_core is
+   0; runs without a plan. */
+int dsrg_pt3_pair_energies(const dsrg_problem* prob, const dsrg_options* opt, dsrg_result* out,
+                           double* e3_pairs, double* e3_rest);
+
 /* As dsrg_pt3_energy, and copies the requested intermediates to host memory. */
 int dsrg_pt3_energy_ex(const dsrg_problem* prob, const dsrg_options* opt, dsrg_result* out,
                        const dsrg_intermediates* inter);

@@ -68,6 +68,7 @@ class Result:
     t2_2: np.ndarray     # second-order doubles
     h2_1: np.ndarray     # H~(2)_{1,2} one-body [P][H]
     h2_2: np.ndarray     # H~(2)_{1,2} two-body [P][P][H][H]
+    ops: Optional[dict] = None   # with keep_ops: the operators of the two E(3) scalars
 
 
 def _internal_mask(sp: Spaces):
@@ -117,10 +118,11 @@ def anti_hermitian(t1, t2):
     return t1 - t1.T, t2 - t2.transpose(2, 3, 0, 1)
 
 
-def run(prob: Problem, keep_full: bool = False, through: str = "e3") -> Result:
+def run(prob: Problem, keep_ops: bool = False, through: str = "e3") -> Result:
     """E^(2) and E^(3) of the unrelaxed DSRG-MRPT3 (Eqs. E(2), E(3), E_unrelaxed).
 
     through="e2" stops after E^(2) (steps a0-a3); the third-order fields are then NaN/None.
+    keep_ops=True keeps H~(1), H~(2)_{1,2}, the densities and both orders' amplitudes.
     """
     if through not in ("e2", "e3"):
         raise ValueError("through must be 'e2' or 'e3'")
@@ -187,5 +189,44 @@ def run(prob: Problem, keep_full: bool = False, through: str = "e3") -> Result:
     # E^(3) = <[H~(1), T(2)]> + <[H~(2)_{1,2}, T(1)]>  (Eq. E(3))
     e3a, _, _ = gno.commutator(Ht1, T2, dens, want0=True)
     e3b, _, _ = gno.commutator(Ht2, T1, dens, want0=True)
+    ops = dict(Ht1=Ht1, Ht2=Ht2, dens=dens) if keep_ops else None
     return Result(float(e2), float(e3a + e3b), float(e3a), float(e3b), sp, eps,
-                  t1, t2, o1_1, o1_2, z1_1, z1_2, u1, u2, h2_1, h2_2)
+                  t1, t2, o1_1, o1_2, z1_1, z1_2, u1, u2, h2_1, h2_2, ops)
+
+
+def pair_energies(prob: Problem):
+    """Core-pair decomposition of E^(3) (a reading: the paper defines none).
+
+    E^(3) = <[H~(1), T(2)]> + <[H~(2)_{1,2}, T(1)]> is linear in the amplitudes of its
+    two commutators (Eq. E(3)).  e_ij (spatial core orbitals i <= j) is the value with
+    those amplitudes restricted to the doubles whose two hole indices are the core
+    orbitals i and j (any spins, both orders); `rest` uses the complement (singles and
+    doubles with an active hole).  Returns ({(i, j): e_ij}, rest, result); the parts add
+    up to E^(3).
+    """
+    r = run(prob, keep_ops=True)
+    sp, ops = r.sp, r.ops
+    spatial, _ = sp.so_index()
+    n = 2 * sp.N
+    core = np.zeros(n, bool)
+    core[sp.C] = True
+    both_core = core[:, None] & core[None, :]
+
+    def e3_with(mask1, mask2):
+        u1 = np.where(mask1, r.t1_2, 0.0)
+        u2 = r.t2_2 * mask2[None, None, :, :]
+        t1 = np.where(mask1, r.t1_1, 0.0)
+        t2 = r.t2_1 * mask2[None, None, :, :]
+        a, _, _ = gno.commutator(ops["Ht1"], gno.to_plain(0.0, u1, u2), ops["dens"], want0=True)
+        b, _, _ = gno.commutator(ops["Ht2"], gno.to_plain(0.0, t1, t2), ops["dens"], want0=True)
+        return float(a + b)
+
+    no_singles = np.zeros((n, n), bool)
+    pairs = {}
+    for i in range(sp.nC):
+        for j in range(i, sp.nC):
+            pq = np.sort(np.stack(np.broadcast_arrays(spatial[:, None], spatial[None, :])), axis=0)
+            mask = both_core & (pq[0] == i) & (pq[1] == j)
+            pairs[(i, j)] = e3_with(no_singles, mask)
+    rest = e3_with(np.ones((n, n), bool), ~both_core)
+    return pairs, rest, r

@@ -89,6 +89,9 @@ def load() -> ctypes.CDLL:
                                            ctypes.POINTER(Result), ctypes.POINTER(Intermediates)]
         lib.dsrg_pt3_energy_ex.restype = ctypes.c_int
         lib.dsrg_release_cache.restype = ctypes.c_int
+        lib.dsrg_pt3_pair_energies.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(Options),
+                                               ctypes.POINTER(Result), _dp, _dp]
+        lib.dsrg_pt3_pair_energies.restype = ctypes.c_int
         lib.dsrg_pt3_energy_batch.argtypes = [ctypes.POINTER(Problem), ctypes.c_int32,
                                               ctypes.POINTER(Options), ctypes.POINTER(Result),
                                               ctypes.POINTER(ctypes.c_int32)]
@@ -232,6 +235,25 @@ def dsrg_pt3_energy_batch(problems, stream=None, workspace_cap=0, precision=0, g
     if rc != DSRG_OK and not any(c == DSRG_OK for c in codes):
         _check(rc)
     return [(_result_dict(res[k]) if codes[k] == DSRG_OK else None) for k in range(n)], codes
+
+
+def dsrg_pt3_pair_energies(p, stream=None, workspace_cap=0, precision=0, grouping=True):
+    """E(2), E(3) and the core-pair decomposition of E(3): the result dict gains
+    'pairs' {(i, j): e_ij} for core orbitals i <= j and 'rest'."""
+    keep = []
+    st, fl = _problem_struct(p, keep)
+    nC = int(st.n_core)
+    buf = np.zeros(max(1, nC * (nC + 1) // 2))
+    rest = np.zeros(1)
+    r = Result()
+    _check(load().dsrg_pt3_pair_energies(ctypes.byref(st), ctypes.byref(
+        _options(_flags(fl, grouping=grouping), _stream_of(p, stream), workspace_cap, precision)),
+        ctypes.byref(r), buf.ctypes.data_as(_dp), rest.ctypes.data_as(_dp)))
+    out = _result_dict(r)
+    keys = [(i, j) for i in range(nC) for j in range(i, nC)]
+    out["pairs"] = {k: float(buf[n]) for n, k in enumerate(keys)}
+    out["rest"] = float(rest[0])
+    return out
 
 
 def dsrg_pt3_energy_ex(p, stream=None, workspace_cap=0, grouping=True, precision=0):

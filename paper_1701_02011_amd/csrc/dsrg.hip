@@ -143,6 +143,45 @@ static std::map<std::string, Use>& table() {
   return t;
 }
 
+// Gradient of the scalar use C0 with respect to its doubles factor, restricted to core
+// holes: E(3) is linear in the amplitudes of its final commutators, so each C0 product
+// with a doubles factor T2[a,b,i,j] becomes the product of its other factors with the free
+// letters a,b,i,j (each of them appears in exactly one other factor), scattered into
+// G2.<block>; the hole letters run over the core only.  sum_ab G2[a,b,i,j] T2[a,b,i,j]
+// is then the contribution of the core pair's amplitudes.  Products with a singles
+// factor, or whose doubles factor has an active-only hole letter, belong to the rest.
+static const Use& pair_use() {
+  static Use u;
+  static std::once_flag once;
+  std::call_once(once, [] {
+    for (const TProduct& P : table().at("C0")) {
+      int t2 = -1, t1 = -1;
+      for (size_t k = 0; k < P.f.size(); ++k) {
+        if (P.f[k].tensor == "T2") t2 = (int)k;
+        if (P.f[k].tensor == "T1") t1 = (int)k;
+      }
+      if (t1 >= 0 || t2 < 0) continue;
+      const TFactor T = P.f[t2];   // storage [P][P][H][H]
+      TProduct Q = P;
+      bool active_hole = false;
+      for (int k = 2; k < 4; ++k) {
+        char& sp = Q.space.at(T.letters[k]);
+        if (sp == 'A') active_hole = true;
+        sp = 'C';
+      }
+      if (active_hole) continue;
+      Q.f.erase(Q.f.begin() + t2);
+      double coef = 0;
+      for (auto& sc : P.s) coef += sc.coef;
+      Q.res = T.letters;
+      Q.s.clear();
+      Q.s.push_back(TScatter{coef, "G2", T.block, T.letters});
+      u.push_back(Q);
+    }
+  });
+  return u;
+}
+
 static const char* storage_axes(const std::string& t) {
   if (t == "T1" || t == "E1" || t == "Y1" || t == "O1") return "PH";
   if (t == "T2" || t == "E2" || t == "Y2" || t == "O2") return "PPHH";
@@ -1427,12 +1466,13 @@ static void load_inputs(const dsrg_problem* P, bool devptr, const Shape& sh, con
 struct BodyOut {
   double *T1a = nullptr, *T1b = nullptr, *T2aa = nullptr, *T2ab = nullptr;
   double *W1 = nullptr, *W2 = nullptr, *Z1 = nullptr, *Z2 = nullptr, *U1 = nullptr, *U2 = nullptr;
+  double* pairs = nullptr;   // [nC (nC + 1) / 2 + 1]: core-pair parts of E(3), then the rest
 };
 
 // The pipeline: every device operation goes through op (and so into a plan being built);
 // ev[1..6] mark the stages on st.
 static BodyOut body(Exec& X, OpLog& op, Pool& pool, const Shape& sh, const Inputs& in, hipEvent_t* ev,
-                    hipStream_t st) {
+                    hipStream_t st, bool want_pairs = false) {
   const int nC = sh.nC, nA = sh.nA, nV = sh.nV;
   const int nH = nC + nA, nP = nA + nV;
   const Dims d{nC, nA, nV};
@@ -1585,11 +1625,42 @@ static BodyOut body(Exec& X, OpLog& op, Pool& pool, const Shape& sh, const Input
   X.set("T1.a", U1, "PH"); X.set("T1.b", U1 + n1, "PH");
   X.set("T2.aa", U2, "PPHH"); X.set("T2.ab", U2 + n4, "PPHH"); X.set("T2.bb", U2 + 2 * n4, "PPHH");
   scalar(energies + 1);
+  // core-pair matrix P2[i][j] of E(3): gradient of each scalar with respect to its doubles
+  // amplitudes on the core-core block, dotted with those amplitudes
+  std::map<std::string, TensorRef> gout;
+  double *G2 = nullptr, *P2 = nullptr;
+  auto pair_part = [&](const double* Taa, const double* Tab, const double* Tbb) {
+    op([G2, n4](hipStream_t s) { launch_fill(G2, 3 * (long long)n4, 0.0, s); });
+    X.run_use(pair_use(), gout, nullptr);
+    op([ad, G2, Taa, Tab, Tbb, P2](hipStream_t s) { launch_pair_dot(ad, G2, Taa, Tab, Tbb, P2, s); });
+  };
+  if (want_pairs) {
+    G2 = pool.alloc(3 * n4);
+    P2 = pool.alloc((size_t)std::max(1, nC * nC));
+    const long long np2 = (long long)nC * nC;
+    op([P2, np2](hipStream_t s) { launch_fill(P2, np2, 0.0, s); });
+    auto mk = [&](double* p) {
+      TensorRef t{p, "PPHH", {(long long)nP * nH * nH, (long long)nH * nH, nH, 1}, (long long)n4};
+      return t;
+    };
+    gout["G2.aa"] = mk(G2);
+    gout["G2.ab"] = mk(G2 + n4);
+    gout["G2.bb"] = mk(G2 + 2 * n4);
+    X.use_id = 3;
+    pair_part(U2, U2 + n4, U2 + 2 * n4);
+  }
   // E(3)_b = <[H~(2)_{1,2}, T(1)]>
   bind_first();
   X.set("E1.a", H1, "PH"); X.set("E1.b", H1 + n1, "PH");
   X.set("E2.aa", H2, "PPHH"); X.set("E2.ab", H2 + n4, "PPHH"); X.set("E2.bb", H2 + 2 * n4, "PPHH");
   scalar(energies + 2);
+  if (want_pairs) {
+    X.use_id = 4;
+    pair_part(T2aa, T2ab, T2aa);
+    bo.pairs = pool.alloc((size_t)nC * (nC + 1) / 2 + 1);
+    double* pairs = bo.pairs;
+    op([nC, P2, energies, pairs](hipStream_t s) { launch_pair_fold(nC, P2, energies, pairs, s); });
+  }
   HIPCHECK(hipEventRecord(ev[6], st));
   bo.W1 = W1; bo.W2 = W2; bo.Z1 = Z1; bo.Z2 = Z2; bo.U1 = U1; bo.U2 = U2;
   return bo;
@@ -1683,7 +1754,8 @@ static void fill_result(dsrg_result* R, const double* e, bool pt3) {
 }
 
 static int run(const dsrg_problem* P, const dsrg_options* O, dsrg_result* R,
-               const dsrg_intermediates* I, bool pt3) {
+               const dsrg_intermediates* I, bool pt3, double* e3_pairs = nullptr,
+               double* e3_rest = nullptr) {
   if (!P || !R) throw Error(DSRG_E_ARG, "null problem or result");
   const int nC = P->n_core, nA = P->n_active, nV = P->n_virtual, M = P->n_aux;
   if (nC < 0 || nA < 0 || nV < 0) throw Error(DSRG_E_ARG, "negative orbital count");
@@ -1717,7 +1789,9 @@ static int run(const dsrg_problem* P, const dsrg_options* O, dsrg_result* R,
   hipStream_t st = (O && O->stream) ? (hipStream_t)O->stream : (hipStream_t)0;
   const long long cap = (O && O->workspace_cap > 0) ? O->workspace_cap : (8LL << 30);
   const bool grouped = !(flags & DSRG_F_NO_GROUPING);
-  const bool cacheable = !profile && !I && !(flags & DSRG_F_NO_PLAN_CACHE);
+  const bool want_pairs = e3_rest != nullptr;
+  if (want_pairs && nC > 0 && !e3_pairs) throw Error(DSRG_E_ARG, "null e3_pairs with n_core > 0");
+  const bool cacheable = !profile && !I && !want_pairs && !(flags & DSRG_F_NO_PLAN_CACHE);
 
   int dev = 0;
   HIPCHECK(hipGetDevice(&dev));
@@ -1810,7 +1884,13 @@ static int run(const dsrg_problem* P, const dsrg_options* O, dsrg_result* R,
   X.group_cap = cap / 2;
   X.f32 = f32;
   HIPCHECK(hipEventRecord(ev[0], st));
-  BodyOut bo = body(X, op, *pool, sh, in, ev, st);
+  BodyOut bo = body(X, op, *pool, sh, in, ev, st, want_pairs);
+  std::vector<double> pair_host;
+  if (want_pairs) {
+    const size_t np = (size_t)nC * (nC + 1) / 2 + 1;
+    pair_host.resize(np);
+    HIPCHECK(hipMemcpyAsync(pair_host.data(), bo.pairs, np * sizeof(double), hipMemcpyDeviceToHost, st));
+  }
   if (I) {
     const size_t nH = nC + nA, nP = nA + nV, n1 = nP * nH, n4 = nP * nP * nH * nH;
     auto cp = [&](double* h, const double* dptr, size_t n) {
@@ -1851,6 +1931,11 @@ static int run(const dsrg_problem* P, const dsrg_options* O, dsrg_result* R,
   r.n_launch = X.n_launch;
   r.grouped_uses = X.grouped_uses;
   *R = r;
+  if (want_pairs) {
+    const size_t np = (size_t)nC * (nC + 1) / 2;
+    if (np) memcpy(e3_pairs, pair_host.data(), np * sizeof(double));
+    *e3_rest = pair_host[np];
+  }
 
   if (fresh && pool->bytes <= kMaxPlanBytes) {
     // capture the recorded pipeline; a failure only means later calls run without a plan
@@ -1913,6 +1998,14 @@ int dsrg_pt3_energy_batch(const dsrg_problem* probs, int32_t n, const dsrg_optio
     else if (first_error == DSRG_OK) first_error = status[k];
   }
   return any_ok ? DSRG_OK : first_error;
+}
+
+int dsrg_pt3_pair_energies(const dsrg_problem* prob, const dsrg_options* opt, dsrg_result* out,
+                           double* e3_pairs, double* e3_rest) {
+  return dsrg::guarded([&] {
+    if (!e3_rest) throw dsrg::Error(DSRG_E_ARG, "null e3_rest");
+    return dsrg::run(prob, opt, out, nullptr, true, e3_pairs, e3_rest);
+  });
 }
 
 int dsrg_pt3_energy_ex(const dsrg_problem* prob, const dsrg_options* opt, dsrg_result* out,

@@ -164,6 +164,14 @@ void launch_second_order_doubles(AmpDims d, const double* W, const double* Z, co
 void launch_second_order_h1(AmpDims d, const double* W1, const double* Z1, const double* src,
                             double* H1, hipStream_t st);
 void launch_combine_f2(int n, const double* W1, const double* Z1, double* f2, hipStream_t st);
+// P2[i][j] += sum over the blocks aa, ab, bb and a, b in P of G2[blk][a][b][i][j] T[blk][a][b][i][j]
+// for core i, j (G2 and T are [P][P][H][H] per block; P2 is [nC][nC]); fixed-order sums.
+void launch_pair_dot(AmpDims d, const double* G2, const double* Taa, const double* Tab,
+                     const double* Tbb, double* P2, hipStream_t st);
+// Core pairs i <= j (row-major over the upper triangle): out[k] = P2[i][j] + P2[j][i]
+// (P2[i][i] on the diagonal); out[npairs] = energies[1] + energies[2] - sum_k out[k] in
+// a fixed order.
+void launch_pair_fold(int nC, const double* P2, const double* energies, double* out, hipStream_t st);
 // out = sum_i coef[i] * vals[i] (fixed order)
 void launch_weighted_sum(int n, const double* vals, const double* coef, double* out, hipStream_t st);
 void launch_fill(double* p, long long n, double v, hipStream_t st);

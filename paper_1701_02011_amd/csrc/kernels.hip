@@ -1070,6 +1070,70 @@ void launch_second_order_h1(AmpDims d, const double* W1, const double* Z1, const
                      H1);
 }
 
+__global__ __launch_bounds__(256) void pair_dot_kernel(AmpDims d, const double* __restrict__ G2,
+                                                       const double* __restrict__ Taa,
+                                                       const double* __restrict__ Tab,
+                                                       const double* __restrict__ Tbb,
+                                                       double* __restrict__ P2) {
+  __shared__ double red[256];
+  const int nH = d.nC + d.nA, nP = d.nA + d.nV;
+  const int i = blockIdx.x / d.nC, j = blockIdx.x - i * d.nC;
+  const long long n4 = (long long)nP * nP * nH * nH;
+  const long long nab = (long long)nP * nP;
+  double part = 0.0;
+  for (long long e = threadIdx.x; e < 3 * nab; e += 256) {
+    const int blk = (int)(e / nab);
+    const long long ab = e - blk * nab;
+    const long long o = (ab * nH + i) * nH + j;
+    const double* T = blk == 0 ? Taa : (blk == 1 ? Tab : Tbb);
+    part += G2[blk * n4 + o] * T[o];
+  }
+  red[threadIdx.x] = part;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) P2[i * d.nC + j] += red[0];
+}
+
+void launch_pair_dot(AmpDims d, const double* G2, const double* Taa, const double* Tab,
+                     const double* Tbb, double* P2, hipStream_t st) {
+  if (d.nC <= 0 || d.nA + d.nV <= 0) return;
+  hipLaunchKernelGGL(pair_dot_kernel, dim3((unsigned)(d.nC * d.nC)), dim3(256), 0, st, d, G2, Taa, Tab,
+                     Tbb, P2);
+}
+
+__global__ __launch_bounds__(256) void pair_fold_kernel(int nC, const double* __restrict__ P2,
+                                                        const double* __restrict__ energies,
+                                                        double* __restrict__ out) {
+  __shared__ double red[256];
+  const int np = nC * (nC + 1) / 2;
+  double part = 0.0;
+  for (int k = threadIdx.x; k < np; k += 256) {
+    int i = 0, rem = k;
+    while (rem >= nC - i) {
+      rem -= nC - i;
+      ++i;
+    }
+    const int j = i + rem;
+    const double v = i == j ? P2[i * nC + i] : P2[i * nC + j] + P2[j * nC + i];
+    out[k] = v;
+    part += v;
+  }
+  red[threadIdx.x] = part;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) out[np] = (energies[1] + energies[2]) - red[0];
+}
+
+void launch_pair_fold(int nC, const double* P2, const double* energies, double* out, hipStream_t st) {
+  hipLaunchKernelGGL(pair_fold_kernel, dim3(1), dim3(256), 0, st, nC, P2, energies, out);
+}
+
 // one workgroup; thread t sums elements t, t + 256, ... and a fixed tree combines them
 __global__ __launch_bounds__(256) void weighted_sum_kernel(int n, const double* __restrict__ vals,
                                                            const double* __restrict__ coef,

@@ -1,8 +1,10 @@
 """Write oracle energies for workloads too slow to run inside a test.
 
 Calls only ``oracle/`` (and the shared input generator).  Usage:
-    python tests/golden/make_golden.py small
-Writes tests/golden/<name>_s<s>.json with E(2), E(3) and its two parts.
+    python tests/golden/make_golden.py small          # energies and sampled intermediates
+    python tests/golden/make_golden.py small-pairs    # core-pair parts of E(3), s = 0.5
+Writes tests/golden/<name>_s<s>.json with E(2), E(3) and its two parts, or
+tests/golden/small_pairs_s0.5.json with the core-pair decomposition of E(3).
 """
 import json
 import os
@@ -49,5 +51,23 @@ def main(name):
         print(path, out["e2"], out["e3"], "%.0fs" % out["oracle_seconds"], flush=True)
 
 
+def main_pairs():
+    p = make_config("small", s=0.5)
+    t = time.time()
+    pairs, rest, r = dsrg.pair_energies(p)
+    out = dict(workload="small", s=p.s, e3=r.e3, rest=rest,
+               pairs=[[i, j, v] for (i, j), v in sorted(pairs.items())],
+               oracle_seconds=time.time() - t,
+               source="oracle/dsrg.py pair_energies (FP64, spin-orbital, MK-GNO engine)")
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "small_pairs_s0.5.json")
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+    print(path, len(pairs), rest, "%.0fs" % out["oracle_seconds"], flush=True)
+
+
 if __name__ == "__main__":
-    main(sys.argv[1] if len(sys.argv) > 1 else "small")
+    arg = sys.argv[1] if len(sys.argv) > 1 else "small"
+    if arg == "small-pairs":
+        main_pairs()
+    else:
+        main(arg)

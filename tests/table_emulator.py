@@ -13,7 +13,29 @@ import numpy as np
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 INC = os.path.join(ROOT, "paper_1701_02011_amd", "csrc", "dsrg_terms.inc")
 STORAGE = {"T1": "PH", "T2": "PPHH", "E1": "PH", "E2": "PPHH", "Y1": "PH", "Y2": "PPHH",
-           "L2": "AAAA", "L3": "AAAAAA", "gA": "AA", "eA": "AA", "O1": "PH", "O2": "PPHH"}
+           "L2": "AAAA", "L3": "AAAAAA", "gA": "AA", "eA": "AA", "O1": "PH", "O2": "PPHH",
+           "G2": "PPHH"}
+
+
+def pair_use(c0):
+    """The library's derived use for the core-pair decomposition of E(3): every C0
+    product with a doubles factor, that factor removed, its letters free (holes on the
+    core only), scattered into G2.<block> with the product's scalar coefficient."""
+    out = []
+    for facs, sp, res, scat in c0:
+        names = [f[0] for f in facs]
+        if "T1" in names or "T2" not in names:
+            continue
+        k = names.index("T2")
+        tn, blk, ls = facs[k]
+        if any(sp[l] == "A" for l in ls[2:]):
+            continue
+        sp2 = dict(sp)
+        for l in ls[2:]:
+            sp2[l] = "C"
+        coef = sum(c for c, *_ in scat)
+        out.append([facs[:k] + facs[k + 1:], sp2, ls, [(coef, "G2", blk, ls)]])
+    return out
 
 
 def load_table(path=INC):
@@ -195,5 +217,18 @@ def pipeline(p, uses=None):
                       (f2[k] + coup2[k]) * e1f - Z["O1"][k] / 6) for k in "ab"}
     e3a = run_use(uses["C0"], d, B, dict(tens, T1=u1, T2=u2), None)
     e3b = run_use(uses["C0"], d, B, dict(tens, E1=H1, E2=H2), None)
+    # core-pair decomposition: gradient of each E(3) scalar with respect to its doubles
+    pu = pair_use(uses["C0"])
+    P2 = np.zeros((nC, nC))
+    for tn, tt in ((dict(tens, T1=u1, T2=u2), u2), (dict(tens, E1=H1, E2=H2), t2)):
+        G = {"G2": {k: np.zeros((nP, nP, nH, nH)) for k in ("aa", "ab", "bb")}}
+        run_use(pu, d, B, tn, G)
+        for k in ("aa", "ab", "bb"):
+            P2 += np.einsum("abij,abij->ij", G["G2"][k][:, :, :nC, :nC], tt[k][:, :, :nC, :nC])
+    pairs = {}
+    for i in range(nC):
+        for j in range(i, nC):
+            pairs[(i, j)] = P2[i, i] if i == j else P2[i, j] + P2[j, i]
     return dict(e2=e2, e3=e3a + e3b, e3a=e3a, e3b=e3b, t1=t1, t2=t2, u1=u1, u2=u2,
-                O1=O1, O2=O2, Z=Z, H1=H1, H2=H2)
+                O1=O1, O2=O2, Z=Z, H1=H1, H2=H2, pairs=pairs,
+                pair_rest=e3a + e3b - sum(pairs.values()))

@@ -311,6 +311,25 @@ def test_batch_of_uneven_problems():
     assert [x["e3"] for x in dres] == [res[k]["e3"] for k in range(len(probs)) if k != 2]
 
 
+@pytest.mark.parametrize("shape,seed,s", [((2, 2, 10, 40), 101, 0.5), ((3, 1, 5, 12), 23, 0.5),
+                                          ((2, 0, 4, 9), 17, 0.4), ((0, 3, 3, 7), 19, 0.8)])
+def test_pair_energies_against_oracle(shape, seed, s):
+    """dsrg_pt3_pair_energies: every core-pair part of E(3) and the rest against the
+    oracle's decomposition (amplitudes of the final commutators restricted per pair)."""
+    p = make_problem(*shape, seed=seed, s=s)
+    say("pair energies", shape, seed, s)
+    g = _lib.dsrg_pt3_pair_energies(p)
+    pairs, rest, r = dsrg.pair_energies(p)
+    assert _close(g["e3"], r.e3) and _close(g["e2"], r.e2)
+    scale = max([1.0, abs(r.e3)] + [abs(v) for v in pairs.values()])
+    assert set(g["pairs"]) == set(pairs)
+    for k, v in pairs.items():
+        assert abs(g["pairs"][k] - v) <= 1e-11 * scale, (k, g["pairs"][k], v)
+    assert abs(g["rest"] - rest) <= 1e-11 * scale
+    plain = _lib.dsrg_pt3_energy(p)
+    assert plain["e3"] == g["e3"]
+
+
 def test_nonfinite_device_input():
     import torch
     p = make_problem(1, 2, 3, 6, seed=1)

@@ -7,6 +7,8 @@ own formulas for the expected side.
 import itertools
 import math
 
+import dataclasses
+
 import numpy as np
 import pytest
 
@@ -434,3 +436,29 @@ def test_spin_flip_and_orbital_permutation_invariance():
                  p.B[:, perm][:, :, perm], p.gamma1, p.gamma2, p.gamma3, p.s)
     r2 = dsrg.run(q2)
     assert abs(r2.e2 - r.e2) < 1e-13 and abs(r2.e3 - r.e3) < 1e-13
+
+
+def test_pair_energies_partition_e3():
+    """The core-pair parts of E(3) and the rest add up to E(3) (the amplitudes of the two
+    final commutators are split into disjoint parts, Eq. E(3) is linear in them)."""
+    p = _micro(3, 1, 3, 10, seed=29)
+    pairs, rest, r = dsrg.pair_energies(p)
+    assert len(pairs) == 6
+    total = sum(pairs.values()) + rest
+    assert abs(total - r.e3) <= 1e-12 * max(1.0, abs(r.e3))
+    assert all(v != 0.0 for v in pairs.values())
+
+
+def test_pair_energies_follow_core_permutation():
+    """Relabelling the core orbitals relabels the pairs: e'_{pi(i) pi(j)} = e_{ij}."""
+    p = _micro(3, 1, 3, 10, seed=31)
+    perm = np.array([2, 0, 1])               # new core orbital k is old orbital perm[k]
+    N = p.N
+    full = np.concatenate([perm, np.arange(3, N)])
+    q = dataclasses.replace(p, eps=p.eps[full], B=p.B[:, full][:, :, full])
+    a, rest_a, _ = dsrg.pair_energies(p)
+    b, rest_b, _ = dsrg.pair_energies(q)
+    assert abs(rest_a - rest_b) <= 1e-12 * max(1.0, abs(rest_a))
+    for (i, j), v in b.items():
+        key = tuple(sorted((int(perm[i]), int(perm[j]))))
+        assert abs(v - a[key]) <= 1e-12 * max(1.0, abs(v)), ((i, j), key)

@@ -99,3 +99,17 @@ def test_table_pipeline_tiny_config():
     r = dsrg.run(p)
     assert abs(e["e2"] - r.e2) < 1e-12 * max(1.0, abs(r.e2))
     assert abs(e["e3"] - r.e3) < 1e-12 * max(1.0, abs(r.e3))
+
+
+@pytest.mark.parametrize("shape,seed,s", [((2, 2, 10, 40), 101, 0.5), ((3, 1, 5, 12), 23, 0.5),
+                                          ((2, 2, 4, 9), 5, 1.3), ((2, 0, 4, 9), 17, 0.4)])
+def test_pair_use_matches_oracle(shape, seed, s):
+    """The library's derived pair use (C0 products differentiated by their doubles
+    factor, core holes only), run by the emulator, gives the oracle's core-pair parts."""
+    p = make_problem(*shape, seed=seed, s=s)
+    e = pipeline(p)
+    pairs, rest, r = dsrg.pair_energies(p)
+    scale = max(1.0, max(abs(v) for v in pairs.values()))
+    for k, v in pairs.items():
+        assert abs(e["pairs"][k] - v) <= 1e-12 * scale, k
+    assert abs(e["pair_rest"] - rest) <= 1e-12 * max(1.0, abs(rest))
