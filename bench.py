@@ -22,6 +22,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6      # MI355X dense FP64 (matrix = vector)
 PEAK_FP32_TFLOPS = 157.3     # MI355X dense FP32 MFMA
+PEAK_HBM_GBS = 8000.0        # MI355X HBM3E
 METRIC = "DSRG-MRPT3 energies/sec and MFMA TFLOP/s vs peak at |ΔE|≤1e-6 Eh"
 
 
@@ -167,14 +168,26 @@ def main():
     else:
         alg = fl[dom]
     avg_s = sec[dom] / max(1, nl[dom])
+    by = [sum(r["role_bytes"][k] for r in prof) for k in range(4)]
+    # the binding roofline of the dominant role: MFMA if its arithmetic intensity (flops per
+    # algorithmic byte) is above the ridge point peak / 8 TB/s, else HBM
+    peak_flops = (PEAK_FP32_TFLOPS if prec else PEAK_FP64_TFLOPS) * 1e12
+    intensity = fl[dom] / by[dom] if by[dom] > 0 else float("inf")
+    hbm_bound = intensity < peak_flops / (PEAK_HBM_GBS * 1e9)
     achieved = alg / sec[dom] / 1e12 if sec[dom] > 0 else 0.0
     peak = PEAK_FP32_TFLOPS if prec else PEAK_FP64_TFLOPS
     if prec:
         names = [n.replace("f64", "f32").replace("gett_group_kernel<false>", "gett_group_kernel<true>")
                  for n in names]
-    roofline = dict(bound="mfma", achieved=achieved, peak=peak, unit="TFLOP/s",
+    bound, unit = "mfma", "TFLOP/s"
+    if hbm_bound:
+        bound, unit, peak = "hbm", "GB/s", PEAK_HBM_GBS
+        achieved = by[dom] / sec[dom] / 1e9
+    roofline = dict(bound=bound, achieved=achieved, peak=peak, unit=unit,
                     frac=achieved / peak, traffic=measured_traffic(names[dom], args.workload, args.precision),
-                    kernel=names[dom],
+                    kernel=names[dom], arithmetic_intensity=intensity,
+                    mfma_tflops=alg / sec[dom] / 1e12 if sec[dom] > 0 else 0.0,
+                    alg_bytes_per_launch=by[dom] / max(1, nl[dom]),
                     launches_per_energy=nl[dom] / len(dev), avg_launch_us=1e6 * avg_s,
                     alg_flops_per_launch=alg / max(1, nl[dom]),
                     issued_tflops=fl[dom] / sec[dom] / 1e12 if sec[dom] > 0 else 0.0)

@@ -118,6 +118,9 @@ typedef struct {
   int32_t plan;           /* 0: ran without a plan, 1: ran and recorded a plan, 2: replayed one */
   int32_t grouped_uses;   /* commutator evaluations run as grouped launches (the others ran
                              one launch per contraction) */
+  double role_bytes[4];   /* with DSRG_F_PROFILE: algorithmic bytes of the role_* launches, each
+                             operand view read once and the result written once (read too when
+                             accumulated) */
 } dsrg_result;
 
 /* Optional host outputs of intermediates (each pointer may be NULL).  Shapes use

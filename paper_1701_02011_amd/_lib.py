@@ -50,7 +50,8 @@ class Result(ctypes.Structure):
                 ("ladder_seconds", ctypes.c_double), ("ladder_batch", ctypes.c_int32),
                 ("n_launch", ctypes.c_int32), ("role_seconds", ctypes.c_double * 4),
                 ("role_flops", ctypes.c_double * 4), ("role_launches", ctypes.c_int32 * 4),
-                ("plan", ctypes.c_int32), ("grouped_uses", ctypes.c_int32)]
+                ("plan", ctypes.c_int32), ("grouped_uses", ctypes.c_int32),
+                ("role_bytes", ctypes.c_double * 4)]
 
 
 class Intermediates(ctypes.Structure):
@@ -163,7 +164,7 @@ def _result_dict(r: Result):
                 ladder_seconds=r.ladder_seconds, ladder_batch=r.ladder_batch,
                 n_launch=r.n_launch, role_seconds=list(r.role_seconds),
                 role_flops=list(r.role_flops), role_launches=list(r.role_launches), plan=r.plan,
-                grouped_uses=r.grouped_uses)
+                grouped_uses=r.grouped_uses, role_bytes=list(r.role_bytes))
 
 
 def _stream_of(p, stream):
@@ -256,15 +257,21 @@ def dsrg_pt3_pair_energies(p, stream=None, workspace_cap=0, precision=0, groupin
     return out
 
 
-def dsrg_pt3_energy_ex(p, stream=None, workspace_cap=0, grouping=True, precision=0):
-    """E(2), E(3) and the intermediates as numpy arrays (spin blocks, excitation order)."""
+INTERMEDIATES = ("t1", "t2", "w1", "w2", "z1", "z2", "u1", "u2")
+
+
+def dsrg_pt3_energy_ex(p, stream=None, workspace_cap=0, grouping=True, precision=0,
+                       keys=INTERMEDIATES):
+    """E(2), E(3) and the requested intermediates as numpy arrays (spin blocks, excitation
+    order)."""
     keep = []
     st, fl = _problem_struct(p, keep)
     fl = _flags(fl, grouping=grouping)
     nC, nA, nV = st.n_core, st.n_active, st.n_virtual
     nH, nP = nC + nA, nA + nV
-    bufs = {k: np.zeros((2, nP, nH)) for k in ("t1", "w1", "z1", "u1")}
-    bufs.update({k: np.zeros((3, nP, nP, nH, nH)) for k in ("t2", "w2", "z2", "u2")})
+    bufs = {}
+    for k in keys:
+        bufs[k] = np.zeros((2, nP, nH)) if k.endswith("1") else np.zeros((3, nP, nP, nH, nH))
     inter = Intermediates(**{k: v.ctypes.data for k, v in bufs.items()})
     r = Result()
     _check(load().dsrg_pt3_energy_ex(ctypes.byref(st), ctypes.byref(

@@ -317,6 +317,7 @@ struct Exec {
     double flops;
     int M, N, K, nm, nn, nk;
     int product;
+    double bytes = 0;   // algorithmic bytes: operands read once, result written once
   };
   int cur_product = -1;
   std::vector<Rec> recs;
@@ -367,6 +368,7 @@ struct Exec {
     if (pa || pb) gett_prepare(g);
     double fl = 2.0 * g.M * (double)g.N * g.K;
     Rec r{nullptr, nullptr, role, fl, g.M, g.N, g.K, g.nm, g.nn, g.nk, cur_product};
+    r.bytes = 8.0 * ((double)g.M * g.K + (double)g.K * g.N + (double)g.M * g.N * (g.beta ? 2 : 1));
     if (profile) {
       HIPCHECK(hipEventCreate(&r.a));
       HIPCHECK(hipEventCreate(&r.b));
@@ -387,7 +389,7 @@ struct Exec {
   }
   double ladder_flops_products = 0;
   // per-role totals of profiled launches: seconds, launches, flops
-  double role_sec[kRoles] = {}, role_flops[kRoles] = {};
+  double role_sec[kRoles] = {}, role_flops[kRoles] = {}, role_bytes[kRoles] = {};
   int role_n[kRoles] = {};
   void collect_profile() {
     // optional per-launch dump (shape and device time) for tuning
@@ -401,6 +403,7 @@ struct Exec {
                 r.nk, ms);
       role_sec[r.role] += ms * 1e-3;
       role_flops[r.role] += r.flops;
+      role_bytes[r.role] += r.bytes;
       role_n[r.role] += 1;
       (void)hipEventDestroy(r.a);
       (void)hipEventDestroy(r.b);
@@ -823,8 +826,10 @@ struct Exec {
   // A grouped launch.  With profiling, the contraction launches (timed = true) are
   // bracketed by events and counted under the grouped role (items in M, workgroups in N of
   // the profile record); helper launches are not.
-  void group_launch(double flops, DevOp launch, bool timed = false, int items = 0, int tiles = 0) {
+  void group_launch(double flops, DevOp launch, bool timed = false, int items = 0, int tiles = 0,
+                    double bytes = 0) {
     Rec r{nullptr, nullptr, kRoleGrouped, flops, 0, 0, 0, 0, 0, 0, -2};
+    r.bytes = bytes;
     timed = timed && profile;
     r.M = items;
     r.N = tiles;
@@ -1045,6 +1050,7 @@ struct Exec {
       long long red;
       double flops;
       bool big;
+      double bytes;
     };
     std::vector<LevelRange> ranges;
     for (size_t L = 0; L < lev.size(); ++L)
@@ -1056,7 +1062,7 @@ struct Exec {
       std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
         return lev[L][x].g.kchunk > lev[L][y].g.kchunk;
       });
-      LevelRange R{(int)items.size(), (int)order.size(), 0, (int)split_idx.size(), 0, 0, 0.0, big == 1};
+      LevelRange R{(int)items.size(), (int)order.size(), 0, (int)split_idx.size(), 0, 0, 0.0, big == 1, 0.0};
       for (int oi : order) {
         GroupItem it = lev[L][oi];
         const Fix& fx = levfix[L][oi];
@@ -1075,6 +1081,7 @@ struct Exec {
           ++R.ns;
         }
         R.flops += 2.0 * it.g.M * (double)it.g.N * it.g.K;
+        R.bytes += 8.0 * ((double)it.g.M * it.g.K + (double)it.g.K * it.g.N + (double)it.g.M * it.g.N);
         items.push_back(it);
       }
       ranges.push_back(R);
@@ -1098,7 +1105,7 @@ struct Exec {
       const int* sp = d_split + R.s0;
       const bool lo = f32;
       group_launch(R.flops, [it, R, lo](hipStream_t s) { launch_gett_group(it, R.n, R.tiles, R.big, lo, s); },
-                   true, R.n, R.tiles);
+                   true, R.n, R.tiles, R.bytes);
       if (R.ns > 0)
         group_launch(0.0, [it, sp, R](hipStream_t s) { launch_group_reduce(it, sp, R.ns, R.red, s); });
     }
@@ -1922,6 +1929,7 @@ static int run(const dsrg_problem* P, const dsrg_options* O, dsrg_result* R,
   for (int k = 0; k < kRoles; ++k) {
     r.role_seconds[k] = X.role_sec[k];
     r.role_flops[k] = X.role_flops[k];
+    r.role_bytes[k] = X.role_bytes[k];
     r.role_launches[k] = X.role_n[k];
   }
   r.gett_flops = X.gett_flops;

@@ -330,6 +330,53 @@ def test_pair_energies_against_oracle(shape, seed, s):
     assert plain["e3"] == g["e3"]
 
 
+def test_small_pair_energies_against_golden():
+    """Core-pair parts of E(3) at the small workload (s = 0.5) against stored oracle values."""
+    gold = json.load(open(os.path.join(GOLDEN, "small_pairs_s0.5.json")))
+    p = make_config("small", s=0.5)
+    say("small pair energies")
+    g = _lib.dsrg_pt3_pair_energies(p)
+    scale = max([1.0, abs(gold["e3"])] + [abs(v) for _, _, v in gold["pairs"]])
+    for i, j, v in gold["pairs"]:
+        assert abs(g["pairs"][(i, j)] - v) <= 1e-11 * scale, (i, j, g["pairs"][(i, j)], v)
+    assert abs(g["rest"] - gold["rest"]) <= 1e-11 * scale
+
+
+@pytest.mark.parametrize("precision", [0, 1])
+def test_medium_homogeneity(precision):
+    """Full medium size (nC=20, nA=8, nV=300, naux=1200), the bench's launch configuration:
+    B -> 2B multiplies every two-electron integral by 4, so E(2) -> 16 E(2) and
+    E(3) -> 64 E(3); powers of two scale every rounding step, so FP64 is exact bitwise and
+    FP32 products too."""
+    p = make_config("medium")
+    say("medium homogeneity, precision", precision)
+    a = _lib.dsrg_pt3_energy(_lib.to_device(p), precision=precision, cache=False)
+    b = _lib.dsrg_pt3_energy(_lib.to_device(p.scaled(2.0)), precision=precision, cache=False)
+    assert b["e2"] == 16.0 * a["e2"] and b["e3"] == 64.0 * a["e3"], (a, b)
+
+
+def test_medium_sampled_first_order_amplitudes():
+    """Full medium size: sampled elements of the alpha-beta first-order doubles against
+    t = (ai|bj) R_s(e_i + e_j - e_a - e_b) evaluated one by one with the oracle's regulariser
+    (Eq. T2_1st) and the factorised integrals (Eq. int_fact)."""
+    p = make_config("medium")
+    say("medium sampled amplitudes")
+    g = _lib.dsrg_pt3_energy_ex(_lib.to_device(p), keys=("t2",))
+    nC, nA, nV = p.n_core, p.n_active, p.n_virtual
+    nH, nP = nC + nA, nA + nV
+    rng = np.random.default_rng(77)
+    a = rng.integers(0, nP, 300); b = rng.integers(0, nP, 300)
+    i = rng.integers(0, nH, 300); j = rng.integers(0, nH, 300)
+    vab = np.einsum("qk,qk->k", p.B[:, nC + a, i], p.B[:, nC + b, j])
+    D = p.eps[i] + p.eps[j] - p.eps[nC + a] - p.eps[nC + b]
+    internal = (a < nA) & (b < nA) & (i >= nC) & (j >= nC)
+    ref = np.where(internal, 0.0, vab * dsrg.regulariser(p.s, D))
+    got = g["t2"][1, a, b, i, j]
+    scale = np.abs(ref).max()
+    assert np.abs(got - ref).max() <= 1e-12 * scale
+    assert abs(g["e3"] - _lib.dsrg_pt3_energy(_lib.to_device(p))["e3"]) <= 1e-12 * abs(g["e3"])
+
+
 def test_nonfinite_device_input():
     import torch
     p = make_problem(1, 2, 3, 6, seed=1)
