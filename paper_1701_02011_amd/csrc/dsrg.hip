@@ -449,10 +449,10 @@ struct Exec {
     g.cm[0] = (long long)g.md[1] * g.N; g.cm[1] = g.N;
     g.cn[0] = g.nd[1]; g.cn[1] = 1;
     g.alpha = 1.0; g.beta = 0;
-    gett_prepare(g);
     long long nB = (long long)M * N * N;
     check_view("B (first pair)", nB - (A0 - B), {g.am[0], g.am[1], g.ak[0]}, {g.md[0], g.md[1], M});
     check_view("B (second pair)", nB - (B0 - B), {g.bn[0], g.bn[1], g.bk[0]}, {g.nd[0], g.nd[1], M});
+    gett_prepare(g);   // may merge components: the checks above use the unmerged ones
     gett(g, A0, B0, out, kRoleIntegrals);
   }
   double* jblock(const std::string& key) {
@@ -536,7 +536,7 @@ struct Exec {
 
   // Descriptor of C[m][n] = sum_k a[m, k] b[k, n] for two operands: the free letters of a
   // (in a's order) form m, those of b form n, the shared letters form k.  C strides are left
-  // to the caller.
+  // to the caller, which then runs gett_prepare.
   GettDesc pair_desc(const Opnd& a, const Opnd& b, const LetterRange& lr, std::string& ml,
                      std::string& nl) {
     std::string kl;
@@ -563,7 +563,6 @@ struct Exec {
     g.M = (int)Mx; g.N = (int)Nx; g.K = (int)Kx;
     check_operand("contraction A", a, lr);
     check_operand("contraction B", b, lr);
-    gett_prepare(g);
     return g;
   }
 
@@ -588,6 +587,14 @@ struct Exec {
     for (int i = 0; i < g.nn; ++i) g.cn[i] = r.stride[g.nm + i];
     g.alpha = 1.0;
     g.beta = 0;
+    gett_prepare(g);   // after the C strides: it merges free components of A/B and C
+    {
+      std::vector<long long> cs;
+      std::vector<int> len;
+      for (int i = 0; i < g.nm; ++i) { cs.push_back(g.cm[i]); len.push_back(g.md[i]); }
+      for (int i = 0; i < g.nn; ++i) { cs.push_back(g.cn[i]); len.push_back(g.nd[i]); }
+      check_view("contraction result", r.lim, cs, len);
+    }
     return r;
   }
 
@@ -1098,14 +1105,29 @@ struct Exec {
         fclose(f);
       }
     }
+    // tile -> item map of every launch (one load per workgroup instead of a search)
+    std::vector<int> tile_item;
+    std::vector<long long> map0;
+    for (auto& R : ranges) {
+      map0.push_back((long long)tile_item.size());
+      for (int i = 0; i < R.n; ++i) {
+        const GroupItem& it = items[R.i0 + i];
+        const int t = it.tiles_m * it.tiles_n * it.splits;
+        for (int k = 0; k < t; ++k) tile_item.push_back(i);
+      }
+    }
     GroupItem* d_items = upload(items);
     int* d_split = upload(split_idx);
-    for (auto& R : ranges) {
+    int* d_map = upload(tile_item);
+    for (size_t ri = 0; ri < ranges.size(); ++ri) {
+      const LevelRange& R = ranges[ri];
       const GroupItem* it = d_items + R.i0;
       const int* sp = d_split + R.s0;
+      const int* tm = d_map + map0[ri];
       const bool lo = f32;
-      group_launch(R.flops, [it, R, lo](hipStream_t s) { launch_gett_group(it, R.n, R.tiles, R.big, lo, s); },
-                   true, R.n, R.tiles, R.bytes);
+      group_launch(R.flops, [it, tm, R, lo](hipStream_t s) {
+        launch_gett_group(it, tm, R.n, R.tiles, R.big, lo, s);
+      }, true, R.n, R.tiles, R.bytes);
       if (R.ns > 0)
         group_launch(0.0, [it, sp, R](hipStream_t s) { launch_group_reduce(it, sp, R.ns, R.red, s); });
     }

@@ -67,7 +67,7 @@ void launch_gett(const GettDesc& g, const double* A, const double* B, double* C,
                  int role, double* ws, long long ws_elems, bool f32 = false);
 int gett_splits(const GettDesc& g, long long ws_elems);
 // ---- grouped execution: independent contractions of one dependency level per launch ----
-// Item i owns workgroups [tile0, tile0 + tiles_m * tiles_n * splits) of a grouped launch,
+// Item i owns workgroup tiles [tile0, tile0 + tiles_m * tiles_n * splits) of a grouped launch,
 // each an output tile of shape kGroupTiles[shape] and one chunk of k steps (g.kchunk).
 // With splits > 1 the partial tiles go to g.part ([splits][M][N]) and launch_group_reduce
 // writes C.
@@ -85,7 +85,9 @@ struct GroupItem {
   int tile0 = 0;          // first workgroup of this item
   long long red0 = 0;     // prefix of M N over the split items of the reduction launch
 };
-void launch_gett_group(const GroupItem* items, int n, int tiles, bool big, bool f32, hipStream_t st);
+// tile_item[b] (b < tiles): index of the item that owns workgroup tile b of the launch.
+void launch_gett_group(const GroupItem* items, const int* tile_item, int n, int tiles, bool big,
+                       bool f32, hipStream_t st);
 // split_idx: indices of the items with splits > 1, in increasing red0
 void launch_group_reduce(const GroupItem* items, const int* split_idx, int nsplit, long long total,
                          hipStream_t st);

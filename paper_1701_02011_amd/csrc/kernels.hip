@@ -13,10 +13,12 @@ typedef double double4_t __attribute__((ext_vector_type(4)));
 // ---------------------------------------------------------------------------
 // Strided multi-index helpers
 // ---------------------------------------------------------------------------
+// Offset of the row-major multi-index idx over components d[0..n) with strides s.  The
+// outermost component takes what is left of idx (idx < prod d), so it needs no division.
 __device__ __forceinline__ long long decode(int idx, int n, const int* d, const long long* s) {
   long long off = 0;
 #pragma unroll
-  for (int c = kMaxComp - 1; c >= 0; --c) {
+  for (int c = kMaxComp - 1; c >= 1; --c) {
     if (c < n) {
       int q = idx / d[c];
       int r = idx - q * d[c];
@@ -24,6 +26,7 @@ __device__ __forceinline__ long long decode(int idx, int n, const int* d, const 
       idx = q;
     }
   }
+  if (n > 0) off += (long long)idx * s[0];
   return off;
 }
 
@@ -356,7 +359,31 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(GettDesc g, const do
 // first the one that lets most operands load coalesced (unit k stride, or a unit stride of
 // the operand's innermost free index), then the one whose padding to whole steps wastes
 // least, then the larger.
+// Merge free components that are contiguous in both the operand and C: outer i, inner j
+// with s_op[i] == d[j] s_op[j] and s_c[i] == d[j] s_c[j] become one component (fewer
+// divisions in every index decode).
+static void merge_free(int& n, int* d, long long* so, long long* sc) {
+  for (bool merged = true; merged && n > 1;) {
+    merged = false;
+    for (int i = 0; i + 1 < n && !merged; ++i) {
+      const int j = i + 1;
+      if (so[i] == (long long)d[j] * so[j] && sc[i] == (long long)d[j] * sc[j]) {
+        d[j] *= d[i];
+        for (int t = i; t + 1 < n; ++t) {
+          d[t] = d[t + 1];
+          so[t] = so[t + 1];
+          sc[t] = sc[t + 1];
+        }
+        --n;
+        merged = true;
+      }
+    }
+  }
+}
+
 void gett_prepare(GettDesc& g) {
+  merge_free(g.nm, g.md, g.am, g.cm);
+  merge_free(g.nn, g.nd, g.bn, g.cn);
   if (g.nk == 0) {
     g.nk = 1;
     g.kd[0] = 1;
@@ -492,20 +519,9 @@ void launch_gett(const GettDesc& g0, const double* A, const double* B, double* C
 // never share an output element, so the launch is race-free and its result does not
 // depend on scheduling.
 // ---------------------------------------------------------------------------
-__device__ __forceinline__ int find_item_int(const GroupItem* __restrict__ items, int n, int b) {
-  int lo = 0, hi = n - 1;
-  while (lo < hi) {
-    int mid = (lo + hi + 1) >> 1;
-    if (items[mid].tile0 <= b) lo = mid;
-    else hi = mid - 1;
-  }
-  return lo;
-}
-
-// Tile shapes of grouped items (kGroupTiles): 64 x 64, 16 x 128 and 128 x 16; the item's
-// shape is uniform in its workgroups, so the switch does not diverge.
 template <bool kF32>
-__global__ __launch_bounds__(256) void gett_group_kernel(const GroupItem* __restrict__ items, int n) {
+__global__ __launch_bounds__(256) void gett_group_kernel(const GroupItem* __restrict__ items,
+                                                         const int* __restrict__ tile_item) {
   using T = typename Mfma<kF32>::T;
   using GroupLds0 = TileLds<2, 2, 2, T>;
   using GroupLds1 = TileLds<1, 2, 1, T>;
@@ -519,7 +535,7 @@ __global__ __launch_bounds__(256) void gett_group_kernel(const GroupItem* __rest
     GroupLds2 t2;
   } lds;
   const int b = xcd_tile_windowed(blockIdx.x, gridDim.x);
-  const GroupItem& it = items[find_item_int(items, n, b)];
+  const GroupItem& it = items[tile_item[b]];
   const int t = b - it.tile0;
   const int per = it.tiles_m * it.tiles_n;
   const int kz = t / per;
@@ -540,11 +556,12 @@ __global__ __launch_bounds__(256) void gett_group_kernel(const GroupItem* __rest
 
 // items of the big shape (128 x 128)
 template <bool kF32>
-__global__ __launch_bounds__(256) void gett_group_big_kernel(const GroupItem* __restrict__ items, int n) {
+__global__ __launch_bounds__(256) void gett_group_big_kernel(const GroupItem* __restrict__ items,
+                                                             const int* __restrict__ tile_item) {
   using Lds = TileLds<4, 4, 2, typename Mfma<kF32>::T>;
   __shared__ Lds lds;
   const int b = xcd_tile_windowed(blockIdx.x, gridDim.x);
-  const GroupItem& it = items[find_item_int(items, n, b)];
+  const GroupItem& it = items[tile_item[b]];
   const int t = b - it.tile0;
   const int per = it.tiles_m * it.tiles_n;
   const int kz = t / per;
@@ -579,17 +596,18 @@ __global__ __launch_bounds__(256) void group_reduce_kernel(const GroupItem* __re
   }
 }
 
-void launch_gett_group(const GroupItem* items, int n, int tiles, bool big, bool f32, hipStream_t st) {
+void launch_gett_group(const GroupItem* items, const int* tile_item, int n, int tiles, bool big,
+                       bool f32, hipStream_t st) {
   if (n <= 0 || tiles <= 0) return;
   const dim3 grid((unsigned)tiles), block(256);
   if (big && f32)
-    hipLaunchKernelGGL(gett_group_big_kernel<true>, grid, block, 0, st, items, n);
+    hipLaunchKernelGGL(gett_group_big_kernel<true>, grid, block, 0, st, items, tile_item);
   else if (big)
-    hipLaunchKernelGGL(gett_group_big_kernel<false>, grid, block, 0, st, items, n);
+    hipLaunchKernelGGL(gett_group_big_kernel<false>, grid, block, 0, st, items, tile_item);
   else if (f32)
-    hipLaunchKernelGGL(gett_group_kernel<true>, grid, block, 0, st, items, n);
+    hipLaunchKernelGGL(gett_group_kernel<true>, grid, block, 0, st, items, tile_item);
   else
-    hipLaunchKernelGGL(gett_group_kernel<false>, grid, block, 0, st, items, n);
+    hipLaunchKernelGGL(gett_group_kernel<false>, grid, block, 0, st, items, tile_item);
 }
 
 void launch_group_reduce(const GroupItem* items, const int* split_idx, int nsplit, long long total,
