@@ -68,6 +68,12 @@ extern "C" {
                                    workspace_cap; results agree to rounding either way, and each
                                    mode is deterministic. */
 #define DSRG_F_NO_PLAN_CACHE 8  /* neither use nor record a cached plan (see Execution above) */
+#define DSRG_F_FULL_LADDER 16   /* contract the same-spin (PP|PP) ladder over every ordered pair of
+                                   particle and hole indices.  By default it runs on the unique
+                                   pairs p<q, r<s, i<j of the antisymmetric amplitudes (about an
+                                   eighth of the work), and the two same-spin blocks share one
+                                   contraction when their amplitudes are the same array; results
+                                   agree to rounding either way. */
 
 typedef struct {
   int32_t n_core, n_active, n_virtual, n_aux;

@@ -25,6 +25,7 @@ DSRG_F_DEVICE_PTRS = 1
 DSRG_F_PROFILE = 2
 DSRG_F_NO_GROUPING = 4
 DSRG_F_NO_PLAN_CACHE = 8
+DSRG_F_FULL_LADDER = 16
 DSRG_PRECISION_FP64 = 0
 DSRG_PRECISION_FP32 = 1
 
@@ -176,7 +177,9 @@ def _stream_of(p, stream):
     return None
 
 
-def _flags(fl, profile=False, grouping=True, cache=True):
+def _flags(fl, profile=False, grouping=True, cache=True, unique_ladder=True):
+    if not unique_ladder:
+        fl |= DSRG_F_FULL_LADDER
     if profile:
         fl |= DSRG_F_PROFILE
     if not grouping:
@@ -202,10 +205,10 @@ def dsrg_pt2_energy(p, stream=None, workspace_cap=0, grouping=True, cache=True, 
 
 
 def dsrg_pt3_energy(p, stream=None, workspace_cap=0, profile=False, grouping=True, cache=True,
-                    precision=0):
+                    precision=0, unique_ladder=True):
     keep = []
     st, fl = _problem_struct(p, keep)
-    fl = _flags(fl, profile, grouping, cache)
+    fl = _flags(fl, profile, grouping, cache, unique_ladder)
     r = Result()
     _check(load().dsrg_pt3_energy(ctypes.byref(st), ctypes.byref(
         _options(fl, _stream_of(p, stream), workspace_cap, precision)), ctypes.byref(r)))
@@ -261,12 +264,12 @@ INTERMEDIATES = ("t1", "t2", "w1", "w2", "z1", "z2", "u1", "u2")
 
 
 def dsrg_pt3_energy_ex(p, stream=None, workspace_cap=0, grouping=True, precision=0,
-                       keys=INTERMEDIATES):
+                       keys=INTERMEDIATES, unique_ladder=True):
     """E(2), E(3) and the requested intermediates as numpy arrays (spin blocks, excitation
     order)."""
     keep = []
     st, fl = _problem_struct(p, keep)
-    fl = _flags(fl, grouping=grouping)
+    fl = _flags(fl, grouping=grouping, unique_ladder=unique_ladder)
     nC, nA, nV = st.n_core, st.n_active, st.n_virtual
     nH, nP = nC + nA, nA + nV
     bufs = {}

@@ -1263,6 +1263,50 @@ struct Exec {
     }
   }
 
+  // A same-spin ladder product O[o] += coef (R0 R1|R2 R3) T[t], R the block letters with the
+  // batch letter R0 first, R0 and R2 free, R1 and R3 summed, every block letter over the
+  // whole particle space and T a same-spin doubles tensor, antisymmetric in its particle pair
+  // and in its hole pair.  The product is then c X[o] with
+  // X[p,q,I,J] = sum_{x,y} (px|qy) T[x,y,I,J], itself antisymmetric in (p,q) and in (I,J)
+  // for the real, pair-symmetric integrals, and the sign c collects the letter orders.
+  bool unique_ladder = true;
+  bool pair_ladder(const TProduct& P, char bl, const std::map<std::string, TensorRef>& outs,
+                   const double*& Tp, double*& Op, double& c) const {
+    if (!unique_ladder || P.f.size() != 2 || P.s.size() != 1) return false;
+    const TFactor* J = nullptr;
+    const TFactor* T = nullptr;
+    for (auto& f : P.f) {
+      if (f.tensor == "J") J = &f;
+      else T = &f;
+    }
+    if (!J || !T || T->tensor != "T2" || (T->block != "aa" && T->block != "bb")) return false;
+    for (char l : J->letters)
+      if (P.space.at(l) != 'P') return false;
+    const std::string R = rotate_first(J->letters, bl, P.space);
+    const std::string& t = T->letters;
+    const TScatter& S = P.s[0];
+    const std::string& o = S.letters;
+    auto has = [](const std::string& str, char l) { return str.find(l) != std::string::npos; };
+    if (R[0] != bl || !has(P.res, R[0]) || !has(P.res, R[2]) || has(P.res, R[1]) || has(P.res, R[3]))
+      return false;
+    if (t.size() != 4 || o.size() != 4) return false;
+    if (!((t[0] == R[1] && t[1] == R[3]) || (t[0] == R[3] && t[1] == R[1]))) return false;
+    if (P.space.at(t[2]) != 'H' || P.space.at(t[3]) != 'H') return false;
+    if (!((o[0] == R[0] && o[1] == R[2]) || (o[0] == R[2] && o[1] == R[0]))) return false;
+    if (!((o[2] == t[2] && o[3] == t[3]) || (o[2] == t[3] && o[3] == t[2]))) return false;
+    auto ti = tensors.find(T->tensor + "." + T->block);
+    auto oi = outs.find(S.tensor + "." + S.block);
+    if (ti == tensors.end() || oi == outs.end()) return false;
+    const long long nP = d.len('P'), nH = d.len('H');
+    const std::vector<long long> dense{nP * nH * nH, nH * nH, nH, 1};
+    for (const TensorRef* r : {&ti->second, &oi->second})
+      if (r->axes != "PPHH" || r->stride != dense || r->lim < nP * nP * nH * nH) return false;
+    Tp = ti->second.p;
+    Op = oi->second.p;
+    c = S.coef * (t[0] == R[1] ? 1 : -1) * (o[0] == R[0] ? 1 : -1) * (o[2] == t[2] ? 1 : -1);
+    return true;
+  }
+
   // Run a use of the table into tensor outputs, or (scalar uses) into *scalar_out.
   int use_id = 0;
   bool f32 = false;   // FP32 products in every contraction
@@ -1345,6 +1389,64 @@ struct Exec {
       long long per = (long long)nP * nP * nP;
       long long nb = std::max(1LL, std::min<long long>(lbl, ws_cap / (8 * per)));
       ladder_batch = (int)nb;
+      // same-spin products on unique pairs, one contraction per distinct doubles tensor
+      std::vector<const TProduct*> full;
+      std::vector<const double*> tri_t;
+      std::vector<std::vector<std::pair<double*, double>>> tri_o;
+      for (auto* P : grp.second) {
+        const double* Tt;
+        double* Ot;
+        double c;
+        if (pair_ladder(*P, bl, outs, Tt, Ot, c)) {
+          size_t k = std::find(tri_t.begin(), tri_t.end(), Tt) - tri_t.begin();
+          if (k == tri_t.size()) {
+            tri_t.push_back(Tt);
+            tri_o.emplace_back();
+          }
+          tri_o[k].push_back({Ot, c});
+        } else {
+          full.push_back(P);
+        }
+      }
+      const int nH = d.len('H');
+      const int kp = nP * (nP - 1) / 2, np = nH * (nH - 1) / 2;
+      std::vector<IntPair> rows_all;      // (p, q), p < q, p-major
+      std::vector<long long> row_start;   // first row of each p
+      IntPair *rowtab = nullptr, *ktab = nullptr, *ntab = nullptr;
+      std::vector<double*> tpk;           // packed doubles [np][kp] per distinct tensor
+      double *Vp = nullptr, *Xp = nullptr;
+      if (!tri_t.empty() && kp > 0 && np > 0) {
+        if (P0.space.at(bl) != 'P') throw Error(DSRG_E_HIP, "internal: ladder batch letter outside P");
+        std::vector<IntPair> kt, nt;
+        for (int x = 0; x < nP; ++x)
+          for (int y = x + 1; y < nP; ++y) kt.push_back({x, y});
+        for (int i = 0; i < nH; ++i)
+          for (int j = i + 1; j < nH; ++j) nt.push_back({i, j});
+        for (int p = 0; p < nP; ++p) {
+          row_start.push_back((long long)rows_all.size());
+          for (int q = p + 1; q < nP; ++q) rows_all.push_back({p, q});
+        }
+        row_start.push_back((long long)rows_all.size());
+        rowtab = upload(rows_all);
+        ktab = upload(kt);
+        ntab = upload(nt);
+        long long max_rows = 0;
+        for (int b0 = 0; b0 < nP; b0 += (int)nb) {
+          int b1 = (int)std::min<long long>(nP, b0 + nb);
+          max_rows = std::max(max_rows, row_start[b1] - row_start[b0]);
+        }
+        Vp = pool.alloc((size_t)std::max(1LL, max_rows * kp));
+        Xp = pool.alloc((size_t)std::max(1LL, max_rows * np));
+        for (const double* Tt : tri_t) {
+          double* tp = pool.alloc((size_t)kp * np);
+          const int nPl = nP;
+          op([Tt, nPl, nH, ktab, kp, ntab, np, tp](hipStream_t s) {
+            launch_ladder_pack_t(Tt, nPl, nH, ktab, kp, ntab, np, tp, s);
+          });
+          ++n_launch;
+          tpk.push_back(tp);
+        }
+      }
       // products are written with the batch letter first in the J factor: rotate letters
       double* jb = jbatch_buffer(nb * per);
       hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -1359,7 +1461,42 @@ struct Exec {
         int off1 = d.off(P0.space.at(bl)) - d.off('P') + b0;
         double fb = gett_flops;
         build_j('P', 'P', 'P', 'P', off1, n1, jb);
-        for (auto* P : grp.second) {
+        if (rowtab) {
+          const long long r0 = row_start[b0], nr = row_start[b0 + n1] - r0;
+          const IntPair* rt = rowtab + r0;
+          const int rows = (int)nr;
+          const int nPl = nP;
+          if (rows > 0) {
+            op([jb, nPl, b0, rt, rows, ktab, kp, Vp](hipStream_t s) {
+              launch_ladder_pack_v(jb, nPl, b0, rt, rows, ktab, kp, Vp, s);
+            });
+            ++n_launch;
+            role_now = kRoleLadder;
+            for (size_t k = 0; k < tri_t.size(); ++k) {
+              // Xp[row][n] = sum_k Vp[row][k] Tp[n][k]
+              GettDesc g;
+              g.nm = 1; g.nn = 1; g.nk = 1;
+              g.md[0] = rows; g.nd[0] = np; g.kd[0] = kp;
+              g.M = rows; g.N = np; g.K = kp;
+              g.am[0] = kp; g.ak[0] = 1;
+              g.bn[0] = kp; g.bk[0] = 1;
+              g.cm[0] = np; g.cn[0] = 1;
+              g.alpha = 1.0; g.beta = 0;
+              gett_prepare(g);
+              gett(g, Vp, tpk[k], Xp, kRoleLadder);
+              for (auto& oc : tri_o[k]) {
+                double* Ot = oc.first;
+                const double c = oc.second;
+                op([Xp, rows, np, rt, ntab, nPl, nH, c, Ot](hipStream_t s) {
+                  launch_ladder_unpack(Xp, rows, np, rt, ntab, nPl, nH, c, Ot, s);
+                });
+                ++n_launch;
+              }
+            }
+            role_now = kRoleGeneric;
+          }
+        }
+        for (auto* P : full) {
           TProduct Q = *P;
           for (auto& f : Q.f)
             if (f.tensor == "J") f.letters = rotate_first(f.letters, bl, Q.space);
@@ -1818,6 +1955,7 @@ static int run(const dsrg_problem* P, const dsrg_options* O, dsrg_result* R,
   hipStream_t st = (O && O->stream) ? (hipStream_t)O->stream : (hipStream_t)0;
   const long long cap = (O && O->workspace_cap > 0) ? O->workspace_cap : (8LL << 30);
   const bool grouped = !(flags & DSRG_F_NO_GROUPING);
+  const bool unique_ladder = !(flags & DSRG_F_FULL_LADDER);
   const bool want_pairs = e3_rest != nullptr;
   if (want_pairs && nC > 0 && !e3_pairs) throw Error(DSRG_E_ARG, "null e3_pairs with n_core > 0");
   const bool cacheable = !profile && !I && !want_pairs && !(flags & DSRG_F_NO_PLAN_CACHE);
@@ -1825,8 +1963,8 @@ static int run(const dsrg_problem* P, const dsrg_options* O, dsrg_result* R,
   int dev = 0;
   HIPCHECK(hipGetDevice(&dev));
   char kbuf[160];
-  snprintf(kbuf, sizeof(kbuf), "%d:%d:%d:%d:%d:%d:%d:%d:%d:%lld", dev, nC, nA, nV, M, (int)sh.has_g3,
-           (int)pt3, (int)grouped, (int)f32, cap);
+  snprintf(kbuf, sizeof(kbuf), "%d:%d:%d:%d:%d:%d:%d:%d:%d:%d:%lld", dev, nC, nA, nV, M, (int)sh.has_g3,
+           (int)pt3, (int)grouped, (int)unique_ladder, (int)f32, cap);
   const std::string key(kbuf);
   Plan* plan = nullptr;
   std::unique_ptr<Plan> fresh;
@@ -1910,6 +2048,7 @@ static int run(const dsrg_problem* P, const dsrg_options* O, dsrg_result* R,
   OpLog op{st, fresh ? &ops : nullptr};
   Exec X(Dims{nC, nA, nV}, st, *pool, op, in.B, M, cap, profile);
   X.grouped = grouped;
+  X.unique_ladder = unique_ladder;
   X.group_cap = cap / 2;
   X.f32 = f32;
   HIPCHECK(hipEventRecord(ev[0], st));

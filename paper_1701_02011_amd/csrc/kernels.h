@@ -135,6 +135,25 @@ struct PackDesc {
 };
 void launch_pack(const PackDesc& d, const double* src, double* dst, hipStream_t st);
 
+// ---- same-spin (PP|PP) ladder on unique pairs ----
+// X[p,q,I,J] = sum_{x<y} V[pq, xy] T[x,y,I,J] with V[pq, xy] = (px|qy) - (py|qx), for p < q
+// and I < J (T antisymmetric in its particle pair and in its hole pair), from a batch of
+// Coulomb integrals jb[p - b0][x][q][y] = (p x|q y).  Rows are pairs (p, q) = rowtab[row].
+struct IntPair {
+  int a, b;
+};
+// Vp[row][k] = jb[p - b0][x][q][y] - jb[p - b0][y][q][x], (p, q) = rowtab[row], (x, y) = ktab[k]
+void launch_ladder_pack_v(const double* jb, int nP, int b0, const IntPair* rowtab, int rows,
+                          const IntPair* ktab, int kp, double* Vp, hipStream_t st);
+// Tp[n][k] = T[x][y][I][J] (T is [P][P][H][H]), (x, y) = ktab[k], (I, J) = ntab[n]
+void launch_ladder_pack_t(const double* T, int nP, int nH, const IntPair* ktab, int kp,
+                          const IntPair* ntab, int np, double* Tp, hipStream_t st);
+// O[p][q][I][J] += c X, O[q][p][I][J] -= c X, O[p][q][J][I] -= c X, O[q][p][J][I] += c X
+// for X = Xp[row][n], (p, q) = rowtab[row], (I, J) = ntab[n]; O is [P][P][H][H].  The four
+// elements of distinct (row, n) are distinct, so one thread owns each.
+void launch_ladder_unpack(const double* Xp, int rows, int np, const IntPair* rowtab,
+                          const IntPair* ntab, int nP, int nH, double c, double* O, hipStream_t st);
+
 // Spin-orbital active densities [2nA]^k from the spin-block inputs, and cumulants.
 void launch_expand_rdm(int nA, int rank, const double* blocks, double* so, hipStream_t st);
 void launch_cumulants(int nA, const double* G1, const double* G2, const double* G3, double* L2,

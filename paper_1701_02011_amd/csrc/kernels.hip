@@ -792,6 +792,78 @@ void launch_pack(const PackDesc& d, const double* src, double* dst, hipStream_t 
 }
 
 // ---------------------------------------------------------------------------
+// Same-spin ladder on unique pairs: packing of the antisymmetrised integrals and of the
+// amplitudes, and the antisymmetric fill of the result
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void ladder_pack_v_kernel(const double* __restrict__ jb, int nP, int b0,
+                                                            const IntPair* __restrict__ rowtab, int rows,
+                                                            const IntPair* __restrict__ ktab, int kp,
+                                                            double* __restrict__ Vp) {
+  const long long total = (long long)rows * kp;
+  const long long n2 = (long long)nP * nP, n3 = n2 * nP;
+  for (long long e = blockIdx.x * 256LL + threadIdx.x; e < total; e += 256LL * gridDim.x) {
+    const int row = (int)(e / kp), k = (int)(e - (long long)row * kp);
+    const IntPair pq = rowtab[row], xy = ktab[k];
+    const long long base = (pq.a - b0) * n3 + (long long)pq.b * nP;
+    Vp[e] = jb[base + xy.a * n2 + xy.b] - jb[base + xy.b * n2 + xy.a];
+  }
+}
+
+__global__ __launch_bounds__(256) void ladder_pack_t_kernel(const double* __restrict__ T, int nP, int nH,
+                                                            const IntPair* __restrict__ ktab, int kp,
+                                                            const IntPair* __restrict__ ntab, int np,
+                                                            double* __restrict__ Tp) {
+  const long long total = (long long)kp * np;
+  for (long long e = blockIdx.x * 256LL + threadIdx.x; e < total; e += 256LL * gridDim.x) {
+    const int n = (int)(e / kp), k = (int)(e - (long long)n * kp);
+    const IntPair xy = ktab[k], ij = ntab[n];
+    Tp[e] = T[(((long long)xy.a * nP + xy.b) * nH + ij.a) * nH + ij.b];
+  }
+}
+
+__global__ __launch_bounds__(256) void ladder_unpack_kernel(const double* __restrict__ Xp, int rows, int np,
+                                                            const IntPair* __restrict__ rowtab,
+                                                            const IntPair* __restrict__ ntab, int nP,
+                                                            int nH, double c, double* __restrict__ O) {
+  const long long total = (long long)rows * np;
+  for (long long e = blockIdx.x * 256LL + threadIdx.x; e < total; e += 256LL * gridDim.x) {
+    const int row = (int)(e / np), n = (int)(e - (long long)row * np);
+    const IntPair pq = rowtab[row], ij = ntab[n];
+    const long long p = pq.a, q = pq.b;
+    const double v = c * Xp[e];
+    O[((p * nP + q) * nH + ij.a) * nH + ij.b] += v;
+    O[((q * nP + p) * nH + ij.a) * nH + ij.b] -= v;
+    O[((p * nP + q) * nH + ij.b) * nH + ij.a] -= v;
+    O[((q * nP + p) * nH + ij.b) * nH + ij.a] += v;
+  }
+}
+
+static unsigned grid_for(long long n) {
+  return (unsigned)std::max<long long>(1, std::min<long long>((n + 255) / 256, 16384));
+}
+
+void launch_ladder_pack_v(const double* jb, int nP, int b0, const IntPair* rowtab, int rows,
+                          const IntPair* ktab, int kp, double* Vp, hipStream_t st) {
+  if (rows <= 0 || kp <= 0) return;
+  hipLaunchKernelGGL(ladder_pack_v_kernel, dim3(grid_for((long long)rows * kp)), dim3(256), 0, st, jb, nP, b0,
+                     rowtab, rows, ktab, kp, Vp);
+}
+
+void launch_ladder_pack_t(const double* T, int nP, int nH, const IntPair* ktab, int kp,
+                          const IntPair* ntab, int np, double* Tp, hipStream_t st) {
+  if (kp <= 0 || np <= 0) return;
+  hipLaunchKernelGGL(ladder_pack_t_kernel, dim3(grid_for((long long)kp * np)), dim3(256), 0, st, T, nP, nH,
+                     ktab, kp, ntab, np, Tp);
+}
+
+void launch_ladder_unpack(const double* Xp, int rows, int np, const IntPair* rowtab,
+                          const IntPair* ntab, int nP, int nH, double c, double* O, hipStream_t st) {
+  if (rows <= 0 || np <= 0) return;
+  hipLaunchKernelGGL(ladder_unpack_kernel, dim3(grid_for((long long)rows * np)), dim3(256), 0, st, Xp, rows,
+                     np, rowtab, ntab, nP, nH, c, O);
+}
+
+// ---------------------------------------------------------------------------
 // Scatter-add with permutation
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void scatter_kernel(ScatterDesc d, const double* __restrict__ src,

@@ -113,7 +113,8 @@ def test_gett_kernel(case, precision):
 # ---------------------------------------------------------------------------
 @pytest.mark.parametrize("shape,seed,s", [((1, 2, 3, 10), 11, 0.5), ((1, 3, 2, 8), 7, 0.6),
                                           ((2, 2, 4, 9), 5, 1.3), ((2, 0, 4, 9), 17, 0.4),
-                                          ((0, 3, 3, 7), 19, 0.8), ((3, 1, 5, 12), 23, 0.5)])
+                                          ((0, 3, 3, 7), 19, 0.8), ((3, 1, 5, 12), 23, 0.5),
+                                          ((1, 0, 4, 9), 29, 0.7)])
 def test_micro_energies(shape, seed, s):
     p = make_problem(*shape, seed=seed, s=s)
     say("micro", shape, seed, s)
@@ -181,6 +182,36 @@ def test_small_batched_pppp_matches_unbatched():
     b = _lib.dsrg_pt3_energy(p, workspace_cap=7 * nP ** 3 * 8, grouping=False)
     assert b["ladder_batch"] == 7
     assert _close(b["e2"], a["e2"], 1e-13) and _close(b["e3"], a["e3"], 1e-13)
+
+
+@pytest.mark.parametrize("name", ["micro", "onehole", "tiny", "small"])
+def test_unique_pair_ladder_matches_full(name):
+    """The same-spin (PP|PP) ladder on unique index pairs (default) and over every ordered
+    pair give the same intermediates and energies to summation order; also with the
+    integral block in ragged batches."""
+    if name == "micro":
+        p = make_problem(2, 2, 4, 9, seed=5, s=1.3)
+    elif name == "onehole":
+        p = make_problem(1, 0, 4, 9, seed=29, s=0.7)
+    else:
+        p = make_config(name)
+    say("unique-pair vs full ladder", name)
+    a = _lib.dsrg_pt3_energy_ex(p, unique_ladder=False)
+    b = _lib.dsrg_pt3_energy_ex(p)
+    for k in ("w2", "u2"):
+        scale = max(1.0, np.abs(a[k]).max())
+        assert np.abs(a[k] - b[k]).max() <= 1e-12 * scale, k
+    # the same-spin blocks stay antisymmetric
+    for blk in (0, 2):
+        w = b["w2"][blk]
+        assert np.abs(w + w.transpose(1, 0, 2, 3)).max() <= 1e-12 * max(1.0, np.abs(w).max())
+    for k in ("e2", "e3_a", "e3_b"):
+        assert _close(b[k], a[k], 1e-12), (k, a[k], b[k])
+    if name == "small":
+        nP = p.n_active + p.n_virtual
+        c = _lib.dsrg_pt3_energy(p, workspace_cap=7 * nP ** 3 * 8, grouping=False)
+        assert c["ladder_batch"] == 7
+        assert _close(c["e2"], b["e2"], 1e-12) and _close(c["e3"], b["e3"], 1e-12)
 
 
 @pytest.mark.parametrize("name", ["micro", "nocore", "tiny", "small"])
