@@ -37,16 +37,6 @@ def workload_problems(name, geometries=4):
     return [make_config(name)]
 
 
-def ladder_algorithmic_flops(p, M):
-    """Algorithmic flops of the particle-particle ladder row (Sec. III, Eq. scaling_problem):
-    building (PP|PP) from B (2 M nP^4) and contracting it with the three spin blocks of the
-    doubles on unique pairs (2 nH^2 nP^4 for ab, 2 C(nH,2) C(nP,2)^2 each for aa and bb)."""
-    nH = p.n_core + p.n_active
-    nP = p.n_active + p.n_virtual
-    c = lambda n: n * (n - 1) / 2
-    return 2.0 * M * nP ** 4 + 2.0 * nH ** 2 * nP ** 4 + 2 * 2.0 * c(nH) * c(nP) ** 2
-
-
 # Ratio of the oracle's time for a whole small-workload energy to its time through E(2)
 # (steps a0-a3), measured once with the same oracle on an 8-core host (OpenBLAS 0.3.29,
 # 8 threads, nothing else running): 204.7 s / 53.2 s.
@@ -157,16 +147,9 @@ def main():
     nl = [sum(r["role_launches"][k] for r in prof) for k in range(4)]
     fl = [sum(r["role_flops"][k] for r in prof) for k in range(4)]
     dom = max(range(4), key=lambda k: sec[k])
-    if dom == 1:
-        # algorithmic: unique pairs for the same-spin ladders (the kernel sums all pairs)
-        c = lambda n: n * (n - 1) / 2
-        alg = 0.0
-        for p in probs:
-            nH = p.n_core + p.n_active
-            nP = p.n_active + p.n_virtual
-            alg += 2.0 * nH ** 2 * nP ** 4 + 4.0 * c(nH) * c(nP) ** 2
-    else:
-        alg = fl[dom]
+    # every role issues its algorithmic flops: the same-spin ladders contract unique index
+    # pairs only, and the two same-spin blocks share one contraction (equal amplitudes)
+    alg = fl[dom]
     avg_s = sec[dom] / max(1, nl[dom])
     by = [sum(r["role_bytes"][k] for r in prof) for k in range(4)]
     # the binding roofline of the dominant role: MFMA if its arithmetic intensity (flops per
@@ -215,6 +198,9 @@ def main():
         "energies": [dict(s=p.s, e2=r["e2"], e3=r["e3"]) for p, r in zip(probs, res)],
         "parity": parity,
         "plan": [r["plan"] for r in res],
+        # device time, launches and issued TFLOP of each contraction role in the profiled pass
+        "roles": {n: dict(seconds=sec[k], launches=nl[k], tflop=fl[k] / 1e12)
+                  for k, n in enumerate(["table", "ladder", "integrals", "grouped"])},
         "contraction_flops_per_energy": res[0]["gett_flops"],
         "launches_per_energy": res[0]["n_launch"],
     }

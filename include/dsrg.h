@@ -68,12 +68,15 @@ extern "C" {
                                    workspace_cap; results agree to rounding either way, and each
                                    mode is deterministic. */
 #define DSRG_F_NO_PLAN_CACHE 8  /* neither use nor record a cached plan (see Execution above) */
-#define DSRG_F_FULL_LADDER 16   /* contract the same-spin (PP|PP) ladder over every ordered pair of
-                                   particle and hole indices.  By default it runs on the unique
-                                   pairs p<q, r<s, i<j of the antisymmetric amplitudes (about an
-                                   eighth of the work), and the two same-spin blocks share one
-                                   contraction when their amplitudes are the same array; results
-                                   agree to rounding either way. */
+#define DSRG_F_FULL_LADDER 16   /* contract the (PP|PP) ladder over every ordered pair of particle
+                                   and hole indices.  By default it runs on unique pairs: p<q,
+                                   r<s, i<j for the antisymmetric same-spin amplitudes (the two
+                                   same-spin blocks share one contraction when their amplitudes
+                                   are the same array), p<=q, r<=s, i<=j for the parts of the
+                                   opposite-spin amplitudes symmetric and antisymmetric in the
+                                   particle pair, with integral batches of the rows q>=p only
+                                   (about a quarter of the ladder and half of the integral work);
+                                   results agree to rounding either way. */
 
 typedef struct {
   int32_t n_core, n_active, n_virtual, n_aux;
@@ -97,7 +100,8 @@ typedef struct {
 typedef struct {
   int32_t flags;          /* DSRG_F_* */
   int32_t precision;      /* DSRG_PRECISION_FP64 (0) or DSRG_PRECISION_FP32 (1) */
-  int64_t workspace_cap;  /* bytes of device workspace for batched integral blocks; 0 = 8 GiB */
+  int64_t workspace_cap;  /* bytes of device workspace for the batched (PP|PP) integrals and their
+                             packed pair rows; 0 = 8 GiB */
   void* stream;           /* hipStream_t to run on, or NULL for the null stream; caller owns it */
 } dsrg_options;
 

@@ -258,6 +258,9 @@ struct TensorRef {
   std::string axes;               // storage spaces per axis
   std::vector<long long> stride;  // element strides per axis
   long long lim = 0;              // elements addressable from p
+  // known symmetry of a [P][P][H][H] doubles tensor: 1 antisymmetric in the particle pair
+  // and in the hole pair; 2 T[x][y][i][j] = T[y][x][j][i]; 0 none assumed
+  int sym = 0;
 };
 
 // Host-side bounds check of a strided view before any launch that reads or writes it.
@@ -418,8 +421,9 @@ struct Exec {
     }
   }
 
-  void set(const std::string& name, double* p, const char* axes) {
+  void set(const std::string& name, double* p, const char* axes, int sym = 0) {
     TensorRef t{p, axes, {}};
+    t.sym = sym;
     int r = (int)strlen(axes);
     t.stride.assign(r, 1);
     for (int k = r - 2; k >= 0; --k) t.stride[k] = t.stride[k + 1] * d.len(axes[k + 1]);
@@ -432,18 +436,21 @@ struct Exec {
   }
 
   // ---- Coulomb blocks J(X1 X2 | X3 X4)[p][q][r][s] = sum_Q B[Q][p][q] B[Q][r][s] ----
-  void build_j(char s1, char s2, char s3, char s4, int off1, int n1, double* out) {
+  // (optionally the first index in [off1, off1 + n1) and the third in [off3, off3 + n3) of
+  // their spaces)
+  void build_j(char s1, char s2, char s3, char s4, int off1, int n1, double* out, int off3 = 0,
+               int n3 = -1) {
     int N = d.nC + d.nA + d.nV;
     GettDesc g;
     g.nm = 2; g.nn = 2; g.nk = 1;
     g.md[0] = n1; g.md[1] = d.len(s2);
-    g.nd[0] = d.len(s3); g.nd[1] = d.len(s4);
+    g.nd[0] = n3 < 0 ? d.len(s3) : n3; g.nd[1] = d.len(s4);
     g.kd[0] = M;
     g.M = g.md[0] * g.md[1];
     g.N = g.nd[0] * g.nd[1];
     g.K = M;
     const double* A0 = B + (long long)(d.off(s1) + off1) * N + d.off(s2);
-    const double* B0 = B + (long long)d.off(s3) * N + d.off(s4);
+    const double* B0 = B + (long long)(d.off(s3) + off3) * N + d.off(s4);
     g.am[0] = N; g.am[1] = 1; g.ak[0] = (long long)N * N;
     g.bk[0] = (long long)N * N; g.bn[0] = N; g.bn[1] = 1;
     g.cm[0] = (long long)g.md[1] * g.N; g.cm[1] = g.N;
@@ -1263,48 +1270,153 @@ struct Exec {
     }
   }
 
-  // A same-spin ladder product O[o] += coef (R0 R1|R2 R3) T[t], R the block letters with the
-  // batch letter R0 first, R0 and R2 free, R1 and R3 summed, every block letter over the
-  // whole particle space and T a same-spin doubles tensor, antisymmetric in its particle pair
-  // and in its hole pair.  The product is then c X[o] with
-  // X[p,q,I,J] = sum_{x,y} (px|qy) T[x,y,I,J], itself antisymmetric in (p,q) and in (I,J)
-  // for the real, pair-symmetric integrals, and the sign c collects the letter orders.
+  // Ladder products O[o] += coef (R0 R1|R2 R3) T[t] that run on unique index pairs, R the
+  // block letters with the batch letter R0 first, R0 and R2 free, R1 and R3 summed, every
+  // block letter over the whole particle space, both hole letters over the whole hole space.
+  // With X[p,q,I,J] = sum_{x,y} (px|qy) T[x,y,I,J] for the real, pair-symmetric integrals:
+  //  1: T a same-spin doubles tensor, antisymmetric in its particle pair and in its hole pair:
+  //     X is antisymmetric in (p,q) and in (I,J), and the product is c X[o], the sign c
+  //     collecting the letter orders;
+  //  2: T the opposite-spin doubles, T[x,y,I,J] = T[y,x,J,I], in the order T[R1,R3,h,h'] and
+  //     O[R0,R2,h,h']: the product is coef X, whose parts of even and odd particle-pair
+  //     symmetry are also of even and odd hole-pair symmetry.
+  // 0: any other product.
   bool unique_ladder = true;
-  bool pair_ladder(const TProduct& P, char bl, const std::map<std::string, TensorRef>& outs,
-                   const double*& Tp, double*& Op, double& c) const {
-    if (!unique_ladder || P.f.size() != 2 || P.s.size() != 1) return false;
+  struct LadderTarget {
+    double* O;
+    double c;
+  };
+  int pair_ladder(const TProduct& P, char bl, const std::map<std::string, TensorRef>& outs,
+                  const double*& Tp, std::vector<LadderTarget>& tg) const {
+    tg.clear();
+    if (!unique_ladder || P.f.size() != 2 || P.s.empty()) return 0;
     const TFactor* J = nullptr;
     const TFactor* T = nullptr;
     for (auto& f : P.f) {
       if (f.tensor == "J") J = &f;
       else T = &f;
     }
-    if (!J || !T || T->tensor != "T2" || (T->block != "aa" && T->block != "bb")) return false;
+    if (!J || !T || T->tensor != "T2") return 0;
+    const int kind = (T->block == "aa" || T->block == "bb") ? 1 : T->block == "ab" ? 2 : 0;
+    if (!kind) return 0;
     for (char l : J->letters)
-      if (P.space.at(l) != 'P') return false;
+      if (P.space.at(l) != 'P') return 0;
     const std::string R = rotate_first(J->letters, bl, P.space);
     const std::string& t = T->letters;
-    const TScatter& S = P.s[0];
-    const std::string& o = S.letters;
     auto has = [](const std::string& str, char l) { return str.find(l) != std::string::npos; };
     if (R[0] != bl || !has(P.res, R[0]) || !has(P.res, R[2]) || has(P.res, R[1]) || has(P.res, R[3]))
-      return false;
-    if (t.size() != 4 || o.size() != 4) return false;
-    if (!((t[0] == R[1] && t[1] == R[3]) || (t[0] == R[3] && t[1] == R[1]))) return false;
-    if (P.space.at(t[2]) != 'H' || P.space.at(t[3]) != 'H') return false;
-    if (!((o[0] == R[0] && o[1] == R[2]) || (o[0] == R[2] && o[1] == R[0]))) return false;
-    if (!((o[2] == t[2] && o[3] == t[3]) || (o[2] == t[3] && o[3] == t[2]))) return false;
+      return 0;
+    if (t.size() != 4) return 0;
+    if (P.space.at(t[2]) != 'H' || P.space.at(t[3]) != 'H') return 0;
+    if (kind == 1 && !((t[0] == R[1] && t[1] == R[3]) || (t[0] == R[3] && t[1] == R[1]))) return 0;
+    if (kind == 2 && (t[0] != R[1] || t[1] != R[3])) return 0;
     auto ti = tensors.find(T->tensor + "." + T->block);
-    auto oi = outs.find(S.tensor + "." + S.block);
-    if (ti == tensors.end() || oi == outs.end()) return false;
+    if (ti == tensors.end() || ti->second.sym != kind) return 0;
     const long long nP = d.len('P'), nH = d.len('H');
     const std::vector<long long> dense{nP * nH * nH, nH * nH, nH, 1};
-    for (const TensorRef* r : {&ti->second, &oi->second})
-      if (r->axes != "PPHH" || r->stride != dense || r->lim < nP * nP * nH * nH) return false;
+    auto dense_ok = [&](const TensorRef& r) {
+      return r.axes == "PPHH" && r.stride == dense && r.lim >= nP * nP * nH * nH;
+    };
+    if (!dense_ok(ti->second)) return 0;
+    for (const TScatter& S : P.s) {
+      const std::string& o = S.letters;
+      if (o.size() != 4) return 0;
+      if (kind == 1) {
+        if (!((o[0] == R[0] && o[1] == R[2]) || (o[0] == R[2] && o[1] == R[0]))) return 0;
+        if (!((o[2] == t[2] && o[3] == t[3]) || (o[2] == t[3] && o[3] == t[2]))) return 0;
+      } else if (o[0] != R[0] || o[1] != R[2] || o[2] != t[2] || o[3] != t[3]) {
+        return 0;
+      }
+      auto oi = outs.find(S.tensor + "." + S.block);
+      if (oi == outs.end() || !dense_ok(oi->second)) return 0;
+      double c = S.coef;
+      if (kind == 1) c *= (t[0] == R[1] ? 1 : -1) * (o[0] == R[0] ? 1 : -1) * (o[2] == t[2] ? 1 : -1);
+      tg.push_back({oi->second.p, c});
+    }
     Tp = ti->second.p;
-    Op = oi->second.p;
-    c = S.coef * (t[0] == R[1] ? 1 : -1) * (o[0] == R[0] ? 1 : -1) * (o[2] == t[2] ? 1 : -1);
-    return true;
+    return kind;
+  }
+
+  // Signature of the value of a product: its factors' data (a bound tensor view, or the
+  // Coulomb integrals) with letters in a canonical order under the factor's symmetries, the
+  // letters' spaces and the result's letter order.  The product is sign times the value of
+  // the canonical form.  Products of one signature compute the same result, so one
+  // contraction serves all of their scatters.  Empty: no signature (unbound factor).
+  bool merge_products = true;
+  std::string product_signature(const TProduct& P, int& sign) const {
+    sign = 1;
+    std::vector<std::string> fs;
+    for (auto& f : P.f) {
+      std::string L = f.letters;
+      std::string key;
+      if (f.tensor == "J") {
+        // (ab|cd) = (ba|cd) = (ab|dc) = (cd|ab) for real orbitals
+        if (L.size() != 4) return "";
+        std::string a = L.substr(0, 2), b = L.substr(2, 2);
+        if (a[1] < a[0]) std::swap(a[0], a[1]);
+        if (b[1] < b[0]) std::swap(b[0], b[1]);
+        if (b < a) std::swap(a, b);
+        key = "J:" + a + b;
+      } else {
+        auto it = tensors.find(f.tensor + "." + f.block);
+        if (it == tensors.end()) return "";
+        const TensorRef& t = it->second;
+        if (t.sym && L.size() == 4) {
+          // sym 2: T[x][y][i][j] = T[y][x][j][i]; sym 1: antisymmetric in each pair
+          const std::string forms[4] = {L, std::string{L[1], L[0], L[2], L[3]},
+                                        std::string{L[0], L[1], L[3], L[2]},
+                                        std::string{L[1], L[0], L[3], L[2]}};
+          const int signs[4] = {1, -1, -1, 1};
+          std::string best = L;
+          int bs = 1;
+          for (int k = 1; k < 4; ++k) {
+            if (t.sym == 2 && k != 3) continue;
+            if (forms[k] < best) {
+              best = forms[k];
+              bs = t.sym == 1 ? signs[k] : 1;
+            }
+          }
+          L = best;
+          sign *= bs;
+        }
+        char buf[48];
+        snprintf(buf, sizeof(buf), "%p:", (const void*)t.p);
+        key = std::string(buf) + t.axes;
+        for (long long x : t.stride) key += ":" + std::to_string(x);
+        key += ":" + L;
+      }
+      fs.push_back(key);
+    }
+    std::sort(fs.begin(), fs.end());
+    std::string sig;
+    for (auto& x : fs) sig += x + "|";
+    for (auto& kv : P.space) {
+      sig += kv.first;
+      sig += kv.second;
+    }
+    return sig + "|" + P.res;
+  }
+  // The products of a use with those of equal signature merged into the first of them.
+  Use merged_use(const Use& U) const {
+    Use out;
+    std::map<std::string, std::pair<size_t, int>> seen;
+    for (auto& P : U) {
+      int sign = 1;
+      std::string sig = merge_products ? product_signature(P, sign) : std::string();
+      auto it = sig.empty() ? seen.end() : seen.find(sig);
+      if (it == seen.end()) {
+        if (!sig.empty()) seen[sig] = {out.size(), sign};
+        out.push_back(P);
+        continue;
+      }
+      TProduct& Q = out[it->second.first];
+      const double rel = (double)(sign * it->second.second);
+      for (TScatter sc : P.s) {
+        sc.coef *= rel;
+        Q.s.push_back(sc);
+      }
+    }
+    return out;
   }
 
   // Run a use of the table into tensor outputs, or (scalar uses) into *scalar_out.
@@ -1314,7 +1426,8 @@ struct Exec {
   int grouped_uses = 0;
   bool grouped = true;
   long long group_cap = 0;   // bytes of temporaries one grouped use may hold
-  void run_use(const Use& U, std::map<std::string, TensorRef>& outs, double* scalar_out) {
+  void run_use(const Use& U0, std::map<std::string, TensorRef>& outs, double* scalar_out) {
+    const Use U = merged_use(U0);
     // products with the (PP|PP) block, grouped by the block's letters
     std::map<std::string, std::vector<const TProduct*>> pppp;
     std::vector<std::pair<int, const TProduct*>> plain;
@@ -1384,69 +1497,115 @@ struct Exec {
         if (free_all) bl = L[k];
       }
       if (!bl) throw Error(DSRG_E_HIP, "internal: no free letter to batch the (PP|PP) block");
-      int nP = d.len('P');
-      int lbl = d.len(P0.space.at(bl));
-      long long per = (long long)nP * nP * nP;
-      long long nb = std::max(1LL, std::min<long long>(lbl, ws_cap / (8 * per)));
-      ladder_batch = (int)nb;
-      // same-spin products on unique pairs, one contraction per distinct doubles tensor
+      const int nP = d.len('P'), nH = d.len('H');
+      const int lbl = d.len(P0.space.at(bl));
+      // products on unique index pairs, one contraction per distinct amplitude array and part
       std::vector<const TProduct*> full;
-      std::vector<const double*> tri_t;
-      std::vector<std::vector<std::pair<double*, double>>> tri_o;
+      std::vector<const double*> pt[3];
+      std::vector<std::vector<LadderTarget>> po[3];
+      std::vector<LadderTarget> tg;
       for (auto* P : grp.second) {
-        const double* Tt;
-        double* Ot;
-        double c;
-        if (pair_ladder(*P, bl, outs, Tt, Ot, c)) {
-          size_t k = std::find(tri_t.begin(), tri_t.end(), Tt) - tri_t.begin();
-          if (k == tri_t.size()) {
-            tri_t.push_back(Tt);
-            tri_o.emplace_back();
-          }
-          tri_o[k].push_back({Ot, c});
-        } else {
+        const double* Tt = nullptr;
+        const int kind = (nP > 0 && nH > 0) ? pair_ladder(*P, bl, outs, Tt, tg) : 0;
+        if (!kind) {
           full.push_back(P);
+          continue;
         }
+        size_t k = std::find(pt[kind].begin(), pt[kind].end(), Tt) - pt[kind].begin();
+        if (k == pt[kind].size()) {
+          pt[kind].push_back(Tt);
+          po[kind].emplace_back();
+        }
+        po[kind][k].insert(po[kind][k].end(), tg.begin(), tg.end());
       }
-      const int nH = d.len('H');
-      const int kp = nP * (nP - 1) / 2, np = nH * (nH - 1) / 2;
-      std::vector<IntPair> rows_all;      // (p, q), p < q, p-major
-      std::vector<long long> row_start;   // first row of each p
-      IntPair *rowtab = nullptr, *ktab = nullptr, *ntab = nullptr;
-      std::vector<double*> tpk;           // packed doubles [np][kp] per distinct tensor
-      double *Vp = nullptr, *Xp = nullptr;
-      if (!tri_t.empty() && kp > 0 && np > 0) {
+      const bool pairs = !pt[1].empty() || !pt[2].empty();
+      const bool sym = !pt[2].empty();
+      // with every product on unique pairs the batch holds the rows q >= b0 only
+      const bool tri_build = pairs && full.empty();
+      const long long kp = (long long)nP * (nP - 1) / 2, kp1 = kp + nP;
+      const long long np = (long long)nH * (nH - 1) / 2, np1 = np + nH;
+      // doubles per value of the batch letter: integral rows plus packed rows
+      const long long per = (long long)nP * nP * nP;
+      const long long per_all = per + (pairs ? (long long)nP * (kp + (sym ? kp1 : 0)) : 0);
+      long long nb = std::max(1LL, std::min<long long>(lbl, ws_cap / (8 * per_all)));
+      ladder_batch = (int)nb;
+      // pair tables: strict pairs (m = own index) and pairs a <= b (m = strict index or -1),
+      // p-major row lists with the first row of each p
+      auto pairs_of = [](int n, bool diag, std::vector<LadderPair>& v, std::vector<long long>* start) {
+        int m = 0;
+        for (int a = 0; a < n; ++a) {
+          if (start) start->push_back((long long)v.size());
+          for (int b = diag ? a : a + 1; b < n; ++b) v.push_back({a, b, b > a ? m++ : -1});
+        }
+        if (start) start->push_back((long long)v.size());
+      };
+      std::vector<long long> rs0, rs1;
+      LadderPair *rows0 = nullptr, *rows1 = nullptr, *kt0 = nullptr, *kt1 = nullptr, *nt0 = nullptr,
+                 *nt1 = nullptr;
+      std::vector<double*> tpk[3], tmk;   // packed amplitudes per distinct array (T-: tmk)
+      double *Va = nullptr, *Vs = nullptr, *Xa = nullptr, *Xs = nullptr;
+      auto pack_t = [&](const double* Tt, const LadderPair* kt, long long k, const LadderPair* nt, long long n,
+                        int mode) {
+        double* tp = pool.alloc((size_t)std::max(1LL, k * n));
+        const int nPl = nP, nHl = nH, ki = (int)k, ni = (int)n;
+        op([Tt, nPl, nHl, kt, ki, nt, ni, mode, tp](hipStream_t s) {
+          launch_ladder_pack_t(Tt, nPl, nHl, kt, ki, nt, ni, mode, tp, s);
+        });
+        ++n_launch;
+        return tp;
+      };
+      if (pairs) {
         if (P0.space.at(bl) != 'P') throw Error(DSRG_E_HIP, "internal: ladder batch letter outside P");
-        std::vector<IntPair> kt, nt;
-        for (int x = 0; x < nP; ++x)
-          for (int y = x + 1; y < nP; ++y) kt.push_back({x, y});
-        for (int i = 0; i < nH; ++i)
-          for (int j = i + 1; j < nH; ++j) nt.push_back({i, j});
-        for (int p = 0; p < nP; ++p) {
-          row_start.push_back((long long)rows_all.size());
-          for (int q = p + 1; q < nP; ++q) rows_all.push_back({p, q});
+        if (kp1 >= (1LL << 31) || (long long)nb * nP * std::max(nP, nH) >= (1LL << 31))
+          throw Error(DSRG_E_UNSUPPORTED, "ladder pair contraction dimension exceeds 2^31");
+        std::vector<LadderPair> r0, r1, k0, k1, n0, n1v;
+        pairs_of(nP, false, r0, &rs0);
+        pairs_of(nP, false, k0, nullptr);
+        pairs_of(nH, false, n0, nullptr);
+        rows0 = upload(r0);
+        kt0 = upload(k0);
+        nt0 = upload(n0);
+        if (sym) {
+          pairs_of(nP, true, r1, &rs1);
+          pairs_of(nP, true, k1, nullptr);
+          pairs_of(nH, true, n1v, nullptr);
+          rows1 = upload(r1);
+          kt1 = upload(k1);
+          nt1 = upload(n1v);
         }
-        row_start.push_back((long long)rows_all.size());
-        rowtab = upload(rows_all);
-        ktab = upload(kt);
-        ntab = upload(nt);
-        long long max_rows = 0;
+        long long mr0 = 0, mr1 = 0;
         for (int b0 = 0; b0 < nP; b0 += (int)nb) {
-          int b1 = (int)std::min<long long>(nP, b0 + nb);
-          max_rows = std::max(max_rows, row_start[b1] - row_start[b0]);
+          const int b1 = (int)std::min<long long>(nP, b0 + nb);
+          mr0 = std::max(mr0, rs0[b1] - rs0[b0]);
+          if (sym) mr1 = std::max(mr1, rs1[b1] - rs1[b0]);
         }
-        Vp = pool.alloc((size_t)std::max(1LL, max_rows * kp));
-        Xp = pool.alloc((size_t)std::max(1LL, max_rows * np));
-        for (const double* Tt : tri_t) {
-          double* tp = pool.alloc((size_t)kp * np);
-          const int nPl = nP;
-          op([Tt, nPl, nH, ktab, kp, ntab, np, tp](hipStream_t s) {
-            launch_ladder_pack_t(Tt, nPl, nH, ktab, kp, ntab, np, tp, s);
-          });
-          ++n_launch;
-          tpk.push_back(tp);
+        Va = pool.alloc((size_t)std::max(1LL, mr0 * kp));
+        Xa = pool.alloc((size_t)std::max(1LL, mr0 * np));
+        if (sym) {
+          Vs = pool.alloc((size_t)std::max(1LL, mr1 * kp1));
+          Xs = pool.alloc((size_t)std::max(1LL, mr1 * np1));
+        }
+        if (kp > 0 && np > 0)
+          for (const double* Tt : pt[1]) tpk[1].push_back(pack_t(Tt, kt0, kp, nt0, np, 0));
+        for (const double* Tt : pt[2]) {
+          tpk[2].push_back(pack_t(Tt, kt1, kp1, nt1, np1, 1));
+          tmk.push_back(kp > 0 && np > 0 ? pack_t(Tt, kt0, kp, nt0, np, 2) : nullptr);
         }
       }
+      // C[row][n] = sum_k A[row][k] B[n][k]
+      auto pair_gemm = [&](const double* A, const double* Bm, double* C, long long rows, long long n,
+                           long long k) {
+        GettDesc g;
+        g.nm = 1; g.nn = 1; g.nk = 1;
+        g.md[0] = (int)rows; g.nd[0] = (int)n; g.kd[0] = (int)k;
+        g.M = (int)rows; g.N = (int)n; g.K = (int)k;
+        g.am[0] = k; g.ak[0] = 1;
+        g.bn[0] = k; g.bk[0] = 1;
+        g.cm[0] = n; g.cn[0] = 1;
+        g.alpha = 1.0; g.beta = 0;
+        gett_prepare(g);
+        gett(g, A, Bm, C, kRoleLadder);
+      };
       // products are written with the batch letter first in the J factor: rotate letters
       double* jb = jbatch_buffer(nb * per);
       hipEvent_t e0 = nullptr, e1 = nullptr;
@@ -1458,43 +1617,58 @@ struct Exec {
       for (int b0 = 0; b0 < lbl; b0 += (int)nb) {
         int n1 = (int)std::min<long long>(nb, lbl - b0);
         // J(P P | P P) batch with the first index in [b0, b0+n1) of the batch letter's space
+        // and the third in [qoff, nP)
         int off1 = d.off(P0.space.at(bl)) - d.off('P') + b0;
+        const int qoff = tri_build ? b0 : 0, nq = nP - qoff;
         double fb = gett_flops;
-        build_j('P', 'P', 'P', 'P', off1, n1, jb);
-        if (rowtab) {
-          const long long r0 = row_start[b0], nr = row_start[b0 + n1] - r0;
-          const IntPair* rt = rowtab + r0;
-          const int rows = (int)nr;
-          const int nPl = nP;
-          if (rows > 0) {
-            op([jb, nPl, b0, rt, rows, ktab, kp, Vp](hipStream_t s) {
-              launch_ladder_pack_v(jb, nPl, b0, rt, rows, ktab, kp, Vp, s);
+        build_j('P', 'P', 'P', 'P', off1, n1, jb, qoff, nq);
+        if (pairs) {
+          const long long r0 = rs0[b0], na = rs0[b0 + n1] - r0;
+          const long long s0 = sym ? rs1[b0] : 0, ns = sym ? rs1[b0 + n1] - s0 : 0;
+          const LadderPair* ra = rows0 + r0;
+          const LadderPair* rsy = sym ? rows1 + s0 : nullptr;
+          const int nPl = nP, nHl = nH, nai = (int)na, nsi = (int)ns, kpi = (int)kp, kp1i = (int)kp1;
+          const int npi = (int)np, np1i = (int)np1, m0 = (int)r0;
+          const bool anti_part = na > 0 && kp > 0 && np > 0;
+          if (anti_part) {
+            op([jb, nPl, b0, qoff, nq, ra, nai, kt0, kpi, Va](hipStream_t s) {
+              launch_ladder_pack_v(jb, nPl, b0, qoff, nq, ra, nai, kt0, kpi, 0, Va, s);
             });
             ++n_launch;
-            role_now = kRoleLadder;
-            for (size_t k = 0; k < tri_t.size(); ++k) {
-              // Xp[row][n] = sum_k Vp[row][k] Tp[n][k]
-              GettDesc g;
-              g.nm = 1; g.nn = 1; g.nk = 1;
-              g.md[0] = rows; g.nd[0] = np; g.kd[0] = kp;
-              g.M = rows; g.N = np; g.K = kp;
-              g.am[0] = kp; g.ak[0] = 1;
-              g.bn[0] = kp; g.bk[0] = 1;
-              g.cm[0] = np; g.cn[0] = 1;
-              g.alpha = 1.0; g.beta = 0;
-              gett_prepare(g);
-              gett(g, Vp, tpk[k], Xp, kRoleLadder);
-              for (auto& oc : tri_o[k]) {
-                double* Ot = oc.first;
-                const double c = oc.second;
-                op([Xp, rows, np, rt, ntab, nPl, nH, c, Ot](hipStream_t s) {
-                  launch_ladder_unpack(Xp, rows, np, rt, ntab, nPl, nH, c, Ot, s);
+          }
+          if (ns > 0) {
+            op([jb, nPl, b0, qoff, nq, rsy, nsi, kt1, kp1i, Vs](hipStream_t s) {
+              launch_ladder_pack_v(jb, nPl, b0, qoff, nq, rsy, nsi, kt1, kp1i, 1, Vs, s);
+            });
+            ++n_launch;
+          }
+          role_now = kRoleLadder;
+          if (anti_part)
+            for (size_t k = 0; k < pt[1].size(); ++k) {
+              pair_gemm(Va, tpk[1][k], Xa, na, np, kp);
+              for (auto& tg : po[1][k]) {
+                double* Ot = tg.O;
+                const double c = tg.c;
+                op([Xa, nai, npi, ra, nt0, nPl, nHl, c, Ot](hipStream_t s) {
+                  launch_ladder_unpack_anti(Xa, nai, npi, ra, nt0, nPl, nHl, c, Ot, s);
                 });
                 ++n_launch;
               }
             }
-            role_now = kRoleGeneric;
-          }
+          if (ns > 0)
+            for (size_t k = 0; k < pt[2].size(); ++k) {
+              if (anti_part) pair_gemm(Va, tmk[k], Xa, na, np, kp);
+              pair_gemm(Vs, tpk[2][k], Xs, ns, np1, kp1);
+              for (auto& tg : po[2][k]) {
+                double* Ot = tg.O;
+                const double c = tg.c;
+                op([Xs, Xa, nsi, np1i, npi, m0, rsy, nt1, nPl, nHl, c, Ot](hipStream_t s) {
+                  launch_ladder_unpack_sym(Xs, Xa, nsi, np1i, npi, m0, rsy, nt1, nPl, nHl, c, Ot, s);
+                });
+                ++n_launch;
+              }
+            }
+          role_now = kRoleGeneric;
         }
         for (auto* P : full) {
           TProduct Q = *P;
@@ -1708,7 +1882,9 @@ static BodyOut body(Exec& X, OpLog& op, Pool& pool, const Shape& sh, const Input
   });
   auto bind_first = [&]() {
     X.set("T1.a", T1a, "PH"); X.set("T1.b", T1b, "PH");
-    X.set("T2.aa", T2aa, "PPHH"); X.set("T2.ab", T2ab, "PPHH"); X.set("T2.bb", T2aa, "PPHH");
+    // first-order doubles: regularised integrals, so the same-spin blocks are antisymmetric
+    // and the opposite-spin block is symmetric under the exchange of both pairs
+    X.set("T2.aa", T2aa, "PPHH", 1); X.set("T2.ab", T2ab, "PPHH", 2); X.set("T2.bb", T2aa, "PPHH", 1);
   };
   bind_first();
   X.set("E1.a", Y1a, "PH"); X.set("E1.b", Y1b, "PH");
@@ -1789,7 +1965,7 @@ static BodyOut body(Exec& X, OpLog& op, Pool& pool, const Shape& sh, const Input
   });
   // E(3)_a = <[H~(1), T(2)]>
   X.set("T1.a", U1, "PH"); X.set("T1.b", U1 + n1, "PH");
-  X.set("T2.aa", U2, "PPHH"); X.set("T2.ab", U2 + n4, "PPHH"); X.set("T2.bb", U2 + 2 * n4, "PPHH");
+  X.set("T2.aa", U2, "PPHH", 1); X.set("T2.ab", U2 + n4, "PPHH"); X.set("T2.bb", U2 + 2 * n4, "PPHH", 1);
   scalar(energies + 1);
   // core-pair matrix P2[i][j] of E(3): gradient of each scalar with respect to its doubles
   // amplitudes on the core-core block, dotted with those amplitudes

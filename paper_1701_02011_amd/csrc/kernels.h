@@ -135,24 +135,37 @@ struct PackDesc {
 };
 void launch_pack(const PackDesc& d, const double* src, double* dst, hipStream_t st);
 
-// ---- same-spin (PP|PP) ladder on unique pairs ----
-// X[p,q,I,J] = sum_{x<y} V[pq, xy] T[x,y,I,J] with V[pq, xy] = (px|qy) - (py|qx), for p < q
-// and I < J (T antisymmetric in its particle pair and in its hole pair), from a batch of
-// Coulomb integrals jb[p - b0][x][q][y] = (p x|q y).  Rows are pairs (p, q) = rowtab[row].
-struct IntPair {
-  int a, b;
+// ---- (PP|PP) ladder on unique index pairs ----
+// A batch of Coulomb integrals holds jb[p - b0][x][q - qoff][y] = (p x|q y) for p in the
+// batch, q in [qoff, qoff + nq) and x, y over the particle space.  A pair table entry is a
+// pair (a, b) of indices and m, the position of (a, b) among the strict pairs a < b of the
+// same table order (-1 when a == b).
+struct LadderPair {
+  int a, b, m;
 };
-// Vp[row][k] = jb[p - b0][x][q][y] - jb[p - b0][y][q][x], (p, q) = rowtab[row], (x, y) = ktab[k]
-void launch_ladder_pack_v(const double* jb, int nP, int b0, const IntPair* rowtab, int rows,
-                          const IntPair* ktab, int kp, double* Vp, hipStream_t st);
-// Tp[n][k] = T[x][y][I][J] (T is [P][P][H][H]), (x, y) = ktab[k], (I, J) = ntab[n]
-void launch_ladder_pack_t(const double* T, int nP, int nH, const IntPair* ktab, int kp,
-                          const IntPair* ntab, int np, double* Tp, hipStream_t st);
-// O[p][q][I][J] += c X, O[q][p][I][J] -= c X, O[p][q][J][I] -= c X, O[q][p][J][I] += c X
-// for X = Xp[row][n], (p, q) = rowtab[row], (I, J) = ntab[n]; O is [P][P][H][H].  The four
-// elements of distinct (row, n) are distinct, so one thread owns each.
-void launch_ladder_unpack(const double* Xp, int rows, int np, const IntPair* rowtab,
-                          const IntPair* ntab, int nP, int nH, double c, double* O, hipStream_t st);
+// Vp[row][k] = (p x|q y) - (p y|q x)              (sym = 0: strict pairs x < y)
+// Vp[row][k] = ((p x|q y) + (p y|q x)) w_xy      (sym = 1: pairs x <= y, w = 1/2 on x == y)
+// with (p, q) = rowtab[row], (x, y) = ktab[k]; every q of the rows lies in [qoff, qoff + nq)
+void launch_ladder_pack_v(const double* jb, int nP, int b0, int qoff, int nq, const LadderPair* rowtab,
+                          int rows, const LadderPair* ktab, int kp, int sym, double* Vp, hipStream_t st);
+// Tp[n][k] from T [P][P][H][H], (x, y) = ktab[k], (I, J) = ntab[n]:
+// mode 0: T[x][y][I][J];  mode 1: (T[x][y][I][J] + T[y][x][I][J]) / 2;
+// mode 2: (T[x][y][I][J] - T[y][x][I][J]) / 2
+void launch_ladder_pack_t(const double* T, int nP, int nH, const LadderPair* ktab, int kp,
+                          const LadderPair* ntab, int np, int mode, double* Tp, hipStream_t st);
+// Antisymmetric fill, X = Xp[row][n] over strict pairs (p, q) = rowtab[row], (I, J) = ntab[n]:
+// O[p][q][I][J] += c X, O[q][p][I][J] -= c X, O[p][q][J][I] -= c X, O[q][p][J][I] += c X.
+// O is [P][P][H][H]; the four elements of distinct (row, n) are distinct.
+void launch_ladder_unpack_anti(const double* Xp, int rows, int np, const LadderPair* rowtab,
+                               const LadderPair* ntab, int nP, int nH, double c, double* O,
+                               hipStream_t st);
+// Fill from a symmetric part S = Xs[row][n] over pairs p <= q, I <= J (tables rowtab, ntab)
+// and an antisymmetric part A = Xa[rowtab[row].m - m0][ntab[n].m] (0 on a diagonal):
+// O[p][q][I][J] += c (S + A), O[p][q][J][I] += c (S - A), O[q][p][I][J] += c (S - A),
+// O[q][p][J][I] += c (S + A), each image once when p == q or I == J.  npa: row length of Xa.
+void launch_ladder_unpack_sym(const double* Xs, const double* Xa, int rows, int np, int npa, int m0,
+                              const LadderPair* rowtab, const LadderPair* ntab, int nP, int nH, double c,
+                              double* O, hipStream_t st);
 
 // Spin-orbital active densities [2nA]^k from the spin-block inputs, and cumulants.
 void launch_expand_rdm(int nA, int rank, const double* blocks, double* so, hipStream_t st);

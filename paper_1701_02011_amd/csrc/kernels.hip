@@ -796,39 +796,49 @@ void launch_pack(const PackDesc& d, const double* src, double* dst, hipStream_t 
 // amplitudes, and the antisymmetric fill of the result
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void ladder_pack_v_kernel(const double* __restrict__ jb, int nP, int b0,
-                                                            const IntPair* __restrict__ rowtab, int rows,
-                                                            const IntPair* __restrict__ ktab, int kp,
+                                                            int qoff, int nq,
+                                                            const LadderPair* __restrict__ rowtab, int rows,
+                                                            const LadderPair* __restrict__ ktab, int kp, int sym,
                                                             double* __restrict__ Vp) {
   const long long total = (long long)rows * kp;
-  const long long n2 = (long long)nP * nP, n3 = n2 * nP;
+  const long long sq = nP, sx = (long long)nq * nP, sp = sx * nP;
   for (long long e = blockIdx.x * 256LL + threadIdx.x; e < total; e += 256LL * gridDim.x) {
     const int row = (int)(e / kp), k = (int)(e - (long long)row * kp);
-    const IntPair pq = rowtab[row], xy = ktab[k];
-    const long long base = (pq.a - b0) * n3 + (long long)pq.b * nP;
-    Vp[e] = jb[base + xy.a * n2 + xy.b] - jb[base + xy.b * n2 + xy.a];
+    const LadderPair pq = rowtab[row], xy = ktab[k];
+    const long long base = (pq.a - b0) * sp + (long long)(pq.b - qoff) * sq;
+    const double u = jb[base + xy.a * sx + xy.b], w = jb[base + xy.b * sx + xy.a];
+    Vp[e] = sym ? (xy.a == xy.b ? u : u + w) : u - w;
   }
 }
 
 __global__ __launch_bounds__(256) void ladder_pack_t_kernel(const double* __restrict__ T, int nP, int nH,
-                                                            const IntPair* __restrict__ ktab, int kp,
-                                                            const IntPair* __restrict__ ntab, int np,
-                                                            double* __restrict__ Tp) {
+                                                            const LadderPair* __restrict__ ktab, int kp,
+                                                            const LadderPair* __restrict__ ntab, int np,
+                                                            int mode, double* __restrict__ Tp) {
   const long long total = (long long)kp * np;
+  const long long hh = (long long)nH * nH;
   for (long long e = blockIdx.x * 256LL + threadIdx.x; e < total; e += 256LL * gridDim.x) {
     const int n = (int)(e / kp), k = (int)(e - (long long)n * kp);
-    const IntPair xy = ktab[k], ij = ntab[n];
-    Tp[e] = T[(((long long)xy.a * nP + xy.b) * nH + ij.a) * nH + ij.b];
+    const LadderPair xy = ktab[k], ij = ntab[n];
+    const long long h = (long long)ij.a * nH + ij.b;
+    const double u = T[((long long)xy.a * nP + xy.b) * hh + h];
+    if (mode == 0) {
+      Tp[e] = u;
+    } else {
+      const double w = T[((long long)xy.b * nP + xy.a) * hh + h];
+      Tp[e] = mode == 1 ? 0.5 * (u + w) : 0.5 * (u - w);
+    }
   }
 }
 
-__global__ __launch_bounds__(256) void ladder_unpack_kernel(const double* __restrict__ Xp, int rows, int np,
-                                                            const IntPair* __restrict__ rowtab,
-                                                            const IntPair* __restrict__ ntab, int nP,
-                                                            int nH, double c, double* __restrict__ O) {
+__global__ __launch_bounds__(256) void ladder_unpack_anti_kernel(const double* __restrict__ Xp, int rows, int np,
+                                                                 const LadderPair* __restrict__ rowtab,
+                                                                 const LadderPair* __restrict__ ntab, int nP,
+                                                                 int nH, double c, double* __restrict__ O) {
   const long long total = (long long)rows * np;
   for (long long e = blockIdx.x * 256LL + threadIdx.x; e < total; e += 256LL * gridDim.x) {
     const int row = (int)(e / np), n = (int)(e - (long long)row * np);
-    const IntPair pq = rowtab[row], ij = ntab[n];
+    const LadderPair pq = rowtab[row], ij = ntab[n];
     const long long p = pq.a, q = pq.b;
     const double v = c * Xp[e];
     O[((p * nP + q) * nH + ij.a) * nH + ij.b] += v;
@@ -838,29 +848,60 @@ __global__ __launch_bounds__(256) void ladder_unpack_kernel(const double* __rest
   }
 }
 
+__global__ __launch_bounds__(256) void ladder_unpack_sym_kernel(const double* __restrict__ Xs,
+                                                                const double* __restrict__ Xa, int rows, int np,
+                                                                int npa, int m0,
+                                                                const LadderPair* __restrict__ rowtab,
+                                                                const LadderPair* __restrict__ ntab, int nP,
+                                                                int nH, double c, double* __restrict__ O) {
+  const long long total = (long long)rows * np;
+  for (long long e = blockIdx.x * 256LL + threadIdx.x; e < total; e += 256LL * gridDim.x) {
+    const int row = (int)(e / np), n = (int)(e - (long long)row * np);
+    const LadderPair pq = rowtab[row], ij = ntab[n];
+    const double S = Xs[e];
+    const double A = (pq.m >= 0 && ij.m >= 0) ? Xa[(long long)(pq.m - m0) * npa + ij.m] : 0.0;
+    const long long p = pq.a, q = pq.b;
+    O[((p * nP + q) * nH + ij.a) * nH + ij.b] += c * (S + A);
+    if (ij.a != ij.b) O[((p * nP + q) * nH + ij.b) * nH + ij.a] += c * (S - A);
+    if (p != q) {
+      O[((q * nP + p) * nH + ij.a) * nH + ij.b] += c * (S - A);
+      if (ij.a != ij.b) O[((q * nP + p) * nH + ij.b) * nH + ij.a] += c * (S + A);
+    }
+  }
+}
+
 static unsigned grid_for(long long n) {
   return (unsigned)std::max<long long>(1, std::min<long long>((n + 255) / 256, 16384));
 }
 
-void launch_ladder_pack_v(const double* jb, int nP, int b0, const IntPair* rowtab, int rows,
-                          const IntPair* ktab, int kp, double* Vp, hipStream_t st) {
+void launch_ladder_pack_v(const double* jb, int nP, int b0, int qoff, int nq, const LadderPair* rowtab,
+                          int rows, const LadderPair* ktab, int kp, int sym, double* Vp, hipStream_t st) {
   if (rows <= 0 || kp <= 0) return;
   hipLaunchKernelGGL(ladder_pack_v_kernel, dim3(grid_for((long long)rows * kp)), dim3(256), 0, st, jb, nP, b0,
-                     rowtab, rows, ktab, kp, Vp);
+                     qoff, nq, rowtab, rows, ktab, kp, sym, Vp);
 }
 
-void launch_ladder_pack_t(const double* T, int nP, int nH, const IntPair* ktab, int kp,
-                          const IntPair* ntab, int np, double* Tp, hipStream_t st) {
+void launch_ladder_pack_t(const double* T, int nP, int nH, const LadderPair* ktab, int kp,
+                          const LadderPair* ntab, int np, int mode, double* Tp, hipStream_t st) {
   if (kp <= 0 || np <= 0) return;
   hipLaunchKernelGGL(ladder_pack_t_kernel, dim3(grid_for((long long)kp * np)), dim3(256), 0, st, T, nP, nH,
-                     ktab, kp, ntab, np, Tp);
+                     ktab, kp, ntab, np, mode, Tp);
 }
 
-void launch_ladder_unpack(const double* Xp, int rows, int np, const IntPair* rowtab,
-                          const IntPair* ntab, int nP, int nH, double c, double* O, hipStream_t st) {
+void launch_ladder_unpack_anti(const double* Xp, int rows, int np, const LadderPair* rowtab,
+                               const LadderPair* ntab, int nP, int nH, double c, double* O,
+                               hipStream_t st) {
   if (rows <= 0 || np <= 0) return;
-  hipLaunchKernelGGL(ladder_unpack_kernel, dim3(grid_for((long long)rows * np)), dim3(256), 0, st, Xp, rows,
-                     np, rowtab, ntab, nP, nH, c, O);
+  hipLaunchKernelGGL(ladder_unpack_anti_kernel, dim3(grid_for((long long)rows * np)), dim3(256), 0, st, Xp,
+                     rows, np, rowtab, ntab, nP, nH, c, O);
+}
+
+void launch_ladder_unpack_sym(const double* Xs, const double* Xa, int rows, int np, int npa, int m0,
+                              const LadderPair* rowtab, const LadderPair* ntab, int nP, int nH, double c,
+                              double* O, hipStream_t st) {
+  if (rows <= 0 || np <= 0) return;
+  hipLaunchKernelGGL(ladder_unpack_sym_kernel, dim3(grid_for((long long)rows * np)), dim3(256), 0, st, Xs, Xa,
+                     rows, np, npa, m0, rowtab, ntab, nP, nH, c, O);
 }
 
 // ---------------------------------------------------------------------------

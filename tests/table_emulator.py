@@ -101,6 +101,43 @@ def run_use(prods, d, B, tens, outs):
     return E
 
 
+def merge_equal(prods, ident, sym):
+    """The library's merge of products that compute the same value: factors keyed by the
+    array they read (ident[(tensor, block)]) with letters in a canonical order under that
+    array's symmetry (sym: 1 antisymmetric in each pair, 2 T[x,y,i,j] = T[y,x,j,i]), Coulomb
+    factors under the real pair symmetries, plus the letter spaces and the result order.
+    Later products of an equal key add their scatters, times the relative sign, to the
+    first."""
+    out, seen = [], {}
+    for facs, sp, res, scat in prods:
+        sign, keys = 1, []
+        for tn, blk, ls in facs:
+            if tn == "J":
+                a, b = "".join(sorted(ls[:2])), "".join(sorted(ls[2:]))
+                keys.append("J:" + min(a + b, b + a))
+                continue
+            idn = ident.get((tn, blk), (tn, blk))
+            sy = sym.get(idn, 0)
+            L = ls
+            if sy and len(ls) == 4:
+                forms = [(ls, 1), (ls[1] + ls[0] + ls[2:], -1), (ls[:2] + ls[3] + ls[2], -1),
+                         (ls[1] + ls[0] + ls[3] + ls[2], 1)]
+                if sy == 2:
+                    forms = [forms[0], forms[3]]
+                L, sg = min(forms, key=lambda f: f[0])
+                if sy == 1:
+                    sign *= sg
+            keys.append("%s.%s:%s" % (idn[0], idn[1], L))
+        key = ("|".join(sorted(keys)), tuple(sorted(sp.items())), res)
+        if key in seen:
+            k, s0 = seen[key]
+            out[k][3].extend((c * sign * s0, *rest) for c, *rest in scat)
+        else:
+            seen[key] = (len(out), sign)
+            out.append([facs, sp, res, list(scat)])
+    return out
+
+
 def regulariser(s, D):
     out = np.zeros_like(D)
     nz = D != 0

@@ -179,16 +179,19 @@ def test_small_batched_pppp_matches_unbatched():
     say("small batched")
     a = _lib.dsrg_pt3_energy(p, grouping=False)
     nP = p.n_active + p.n_virtual
-    b = _lib.dsrg_pt3_energy(p, workspace_cap=7 * nP ** 3 * 8, grouping=False)
+    # per value of the batch index: nP^3 integrals and nP^3 packed pair rows
+    b = _lib.dsrg_pt3_energy(p, workspace_cap=14 * nP ** 3 * 8, grouping=False)
     assert b["ladder_batch"] == 7
     assert _close(b["e2"], a["e2"], 1e-13) and _close(b["e3"], a["e3"], 1e-13)
 
 
 @pytest.mark.parametrize("name", ["micro", "onehole", "tiny", "small"])
 def test_unique_pair_ladder_matches_full(name):
-    """The same-spin (PP|PP) ladder on unique index pairs (default) and over every ordered
-    pair give the same intermediates and energies to summation order; also with the
-    integral block in ragged batches."""
+    """The (PP|PP) ladder on unique index pairs (default: antisymmetric same-spin amplitudes,
+    opposite-spin ones split into parts symmetric and antisymmetric in the particle pair,
+    integral batches holding only the rows q >= p) and over every ordered pair give the same
+    intermediates and energies to summation order; also with the integrals in ragged
+    batches."""
     if name == "micro":
         p = make_problem(2, 2, 4, 9, seed=5, s=1.3)
     elif name == "onehole":
@@ -209,8 +212,12 @@ def test_unique_pair_ladder_matches_full(name):
         assert _close(b[k], a[k], 1e-12), (k, a[k], b[k])
     if name == "small":
         nP = p.n_active + p.n_virtual
-        c = _lib.dsrg_pt3_energy(p, workspace_cap=7 * nP ** 3 * 8, grouping=False)
+        c = _lib.dsrg_pt3_energy(p, workspace_cap=7 * nP ** 3 * 8, grouping=False,
+                                 unique_ladder=False)
         assert c["ladder_batch"] == 7
+        d = _lib.dsrg_pt3_energy(p, workspace_cap=9 * nP ** 3 * 8, grouping=False)
+        assert d["ladder_batch"] == 4
+        assert _close(d["e2"], b["e2"], 1e-12) and _close(d["e3"], b["e3"], 1e-12)
         assert _close(c["e2"], b["e2"], 1e-12) and _close(c["e3"], b["e3"], 1e-12)
 
 

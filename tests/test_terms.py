@@ -15,6 +15,7 @@ from paper_1701_02011_amd.synth import make_problem, make_config
 from oracle import dsrg, gno
 from oracle.spaces import Spaces, build_densities
 
+import table_emulator
 from table_emulator import load_table, pipeline
 
 ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
@@ -113,3 +114,24 @@ def test_pair_use_matches_oracle(shape, seed, s):
     for k, v in pairs.items():
         assert abs(e["pairs"][k] - v) <= 1e-12 * scale, k
     assert abs(e["pair_rest"] - rest) <= 1e-12 * max(1.0, abs(rest))
+
+
+def test_merged_products_give_the_same_commutators():
+    """Products that read the same arrays (the beta doubles are the alpha ones in the first
+    order; the first-order doubles are antisymmetric (same spin) or symmetric under the
+    exchange of both pairs (opposite spin)) are computed once for all their scatters: the
+    commutators W and Z, and so E(3), are unchanged."""
+    p = make_problem(2, 2, 4, 9, seed=5, s=1.3)
+    uses = table_emulator.load_table()
+    ident = {("T2", "bb"): ("T2", "aa"), ("E2", "bb"): ("E2", "aa"), ("Y2", "bb"): ("Y2", "aa"),
+             ("E1", "a"): ("Y1", "a"), ("E1", "b"): ("Y1", "b")}
+    sym = {("T2", "aa"): 1, ("T2", "ab"): 2}
+    merged = dict(uses)
+    for name in ("W", "Z"):
+        merged[name] = table_emulator.merge_equal(uses[name], ident, sym)
+    assert len(merged["W"]) <= len(uses["W"]) - 30
+    a = table_emulator.pipeline(p, uses)
+    b = table_emulator.pipeline(p, merged)
+    for k in ("aa", "ab", "bb"):
+        assert np.abs(a["O2"][k] - b["O2"][k]).max() <= 1e-12 * max(1.0, np.abs(a["O2"][k]).max()), k
+    assert abs(a["e3"] - b["e3"]) <= 1e-12 * max(1.0, abs(a["e3"]))
