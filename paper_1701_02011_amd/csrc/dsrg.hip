@@ -321,6 +321,9 @@ struct Exec {
     int M, N, K, nm, nn, nk;
     int product;
     double bytes = 0;   // algorithmic bytes: operands read once, result written once
+    // layout after preparation, for the per-launch dump
+    int kin = 0, ksteps = 0, akf = 0, bkf = 0, pa = 0, pb = 0, splits = 1;
+    long long ai = 0, bi = 0, am = 0, bn = 0;
   };
   int cur_product = -1;
   std::vector<Rec> recs;
@@ -362,22 +365,32 @@ struct Exec {
 
   void gett(const GettDesc& g0, const double* A, const double* Bp, double* C, int role) {
     GettDesc g = g0;
-    const bool pa = !unit_fast(g.a_kfast, g.nm, g.am, g.ak[g.nk - 1]) && g.N >= kPackMin &&
-                    (long long)g.M * g.K <= kPackCap;
-    const bool pb = !unit_fast(g.b_kfast, g.nn, g.bn, g.bk[g.nk - 1]) && g.M >= kPackMin &&
-                    (long long)g.N * g.K <= kPackCap;
+    // A short inner k component wastes most of each zero-padded k step: packing both
+    // operands makes the whole k range one contiguous component (steps of kGettBK).
+    const int kin = g.kd[g.nk - 1];
+    const bool padk = g.nk > 1 && (long long)g.ksteps * kGettBK * 8 > 9LL * kin && g.M >= kPackMin &&
+                      g.N >= kPackMin && (long long)g.M * g.K <= kPackCap && (long long)g.N * g.K <= kPackCap;
+    const bool pa = padk || (!unit_fast(g.a_kfast, g.nm, g.am, g.ak[g.nk - 1]) && g.N >= kPackMin &&
+                             (long long)g.M * g.K <= kPackCap);
+    const bool pb = padk || (!unit_fast(g.b_kfast, g.nn, g.bn, g.bk[g.nk - 1]) && g.M >= kPackMin &&
+                             (long long)g.N * g.K <= kPackCap);
     if (pa) A = pack_operand(0, g, A);
     if (pb) Bp = pack_operand(1, g, Bp);
     if (pa || pb) gett_prepare(g);
     double fl = 2.0 * g.M * (double)g.N * g.K;
     Rec r{nullptr, nullptr, role, fl, g.M, g.N, g.K, g.nm, g.nn, g.nk, cur_product};
     r.bytes = 8.0 * ((double)g.M * g.K + (double)g.K * g.N + (double)g.M * g.N * (g.beta ? 2 : 1));
+    r.kin = g.kd[g.nk - 1]; r.ksteps = g.ksteps; r.akf = g.a_kfast; r.bkf = g.b_kfast;
+    r.pa = pa; r.pb = pb;
+    r.ai = g.ak[g.nk - 1]; r.bi = g.bk[g.nk - 1];
+    r.am = g.nm ? g.am[g.nm - 1] : 0; r.bn = g.nn ? g.bn[g.nn - 1] : 0;
     if (profile) {
       HIPCHECK(hipEventCreate(&r.a));
       HIPCHECK(hipEventCreate(&r.b));
       HIPCHECK(hipEventRecord(r.a, st));
     }
     const int ns = gett_splits(g, kSplitCap);
+    r.splits = ns;
     const long long wse = ns > 1 ? (long long)ns * g.M * g.N : 0;
     double* ws = splitk_buffer(wse);
     const bool lo = f32;
@@ -402,8 +415,9 @@ struct Exec {
       float ms = 0;
       HIPCHECK(hipEventElapsedTime(&ms, r.a, r.b));
       if (fd)
-        fprintf(fd, "%d,%d,%d,%d,%d,%d,%d,%d,%.6f\n", r.product, r.role, r.M, r.N, r.K, r.nm, r.nn,
-                r.nk, ms);
+        fprintf(fd, "%d,%d,%d,%d,%d,%d,%d,%d,%.6f,%d,%d,%d,%d,%d,%d,%d,%lld,%lld,%lld,%lld\n", r.product,
+                r.role, r.M, r.N, r.K, r.nm, r.nn, r.nk, ms, r.kin, r.ksteps, r.akf, r.bkf, r.pa, r.pb,
+                r.splits, r.ai, r.bi, r.am, r.bn);
       role_sec[r.role] += ms * 1e-3;
       role_flops[r.role] += r.flops;
       role_bytes[r.role] += r.bytes;
