@@ -1098,6 +1098,7 @@ struct Exec {
         it.B = at(fx.b, it.B);
         it.C = tbase + fx.c;
         it.g.part = it.splits > 1 ? pbase + poff[L][oi] : nullptr;
+        gett_magic(it.g);
         it.tile0 = R.tiles;
         long long t = (long long)it.tiles_m * it.tiles_n * it.splits;
         if (R.tiles + t >= (1LL << 31)) throw Error(DSRG_E_UNSUPPORTED, "grouped launch too large");
@@ -1645,14 +1646,14 @@ struct Exec {
           const int npi = (int)np, np1i = (int)np1, m0 = (int)r0;
           const bool anti_part = na > 0 && kp > 0 && np > 0;
           if (anti_part) {
-            op([jb, nPl, b0, qoff, nq, ra, nai, kt0, kpi, Va](hipStream_t s) {
-              launch_ladder_pack_v(jb, nPl, b0, qoff, nq, ra, nai, kt0, kpi, 0, Va, s);
+            op([jb, nPl, b0, qoff, nq, ra, nai, Va](hipStream_t s) {
+              launch_ladder_pack_v(jb, nPl, b0, qoff, nq, ra, nai, 0, Va, s);
             });
             ++n_launch;
           }
           if (ns > 0) {
-            op([jb, nPl, b0, qoff, nq, rsy, nsi, kt1, kp1i, Vs](hipStream_t s) {
-              launch_ladder_pack_v(jb, nPl, b0, qoff, nq, rsy, nsi, kt1, kp1i, 1, Vs, s);
+            op([jb, nPl, b0, qoff, nq, rsy, nsi, Vs](hipStream_t s) {
+              launch_ladder_pack_v(jb, nPl, b0, qoff, nq, rsy, nsi, 1, Vs, s);
             });
             ++n_launch;
           }

@@ -33,8 +33,15 @@ struct GettDesc {
   long long steps = 1;   // total k steps: K / kd[nk - 1] * ksteps
   long long kchunk = 1;  // k steps per split (split-K), set by the launcher
   double* part = nullptr;  // split-K partial tiles [split][M][N], set by the launcher
+  // division by md[c] (nd[c]) as a multiply and shift: q = (idx * mmag[c]) >> msh[c] for
+  // 0 <= idx < 2^31 (set by gett_magic)
+  unsigned mmag[kMaxComp] = {}, nmag[kMaxComp] = {};
+  int msh[kMaxComp] = {}, nsh[kMaxComp] = {};
 };
+// merges and orders components, chooses the inner k component, and sets the magic numbers
 void gett_prepare(GettDesc& g);
+// the magic numbers of md and nd alone (after any later change of them)
+void gett_magic(GettDesc& g);
 
 // sum_k A[k] B[k] over a strided multi-index k (deterministic two-pass reduction).
 struct DotDesc {
@@ -145,9 +152,10 @@ struct LadderPair {
 };
 // Vp[row][k] = (p x|q y) - (p y|q x)              (sym = 0: strict pairs x < y)
 // Vp[row][k] = ((p x|q y) + (p y|q x)) w_xy      (sym = 1: pairs x <= y, w = 1/2 on x == y)
-// with (p, q) = rowtab[row], (x, y) = ktab[k]; every q of the rows lies in [qoff, qoff + nq)
+// with (p, q) = rowtab[row] and k the position of (x, y) in x-major order of the pairs; every
+// q of the rows lies in [qoff, qoff + nq)
 void launch_ladder_pack_v(const double* jb, int nP, int b0, int qoff, int nq, const LadderPair* rowtab,
-                          int rows, const LadderPair* ktab, int kp, int sym, double* Vp, hipStream_t st);
+                          int rows, int sym, double* Vp, hipStream_t st);
 // Tp[n][k] from T [P][P][H][H], (x, y) = ktab[k], (I, J) = ntab[n]:
 // mode 0: T[x][y][I][J];  mode 1: (T[x][y][I][J] + T[y][x][I][J]) / 2;
 // mode 2: (T[x][y][I][J] - T[y][x][I][J]) / 2

@@ -15,13 +15,18 @@ typedef double double4_t __attribute__((ext_vector_type(4)));
 // ---------------------------------------------------------------------------
 // Offset of the row-major multi-index idx over components d[0..n) with strides s.  The
 // outermost component takes what is left of idx (idx < prod d), so it needs no division.
-__device__ __forceinline__ long long decode(int idx, int n, const int* d, const long long* s) {
+// Multi-index decode with each division a multiply-high and shift: for 1 <= d < 2^31 and
+// l = ceil(log2 d), m = floor(2^(31+l) / d) + 1 < 2^32 gives floor(n / d) = (n m) >> (31 + l)
+// for every 0 <= n < 2^31 (the error term n (m d - 2^(31+l)) / (d 2^(31+l)) < 2^-l <= 1/d
+// cannot carry past the next multiple of d; Granlund and Montgomery, PLDI 1994).
+__device__ __forceinline__ long long decode_fast(int idx, int n, const int* d, const unsigned* mag,
+                                                 const int* sh, const long long* s) {
   long long off = 0;
 #pragma unroll
   for (int c = kMaxComp - 1; c >= 1; --c) {
     if (c < n) {
-      int q = idx / d[c];
-      int r = idx - q * d[c];
+      const int q = (int)(((unsigned long long)(unsigned)idx * mag[c]) >> sh[c]);
+      const int r = idx - q * d[c];
       off += (long long)r * s[c];
       idx = q;
     }
@@ -29,6 +34,7 @@ __device__ __forceinline__ long long decode(int idx, int n, const int* d, const 
   if (n > 0) off += (long long)idx * s[0];
   return off;
 }
+
 
 // ---------------------------------------------------------------------------
 // GETT: a workgroup of 256 threads (4 waves, 2x2) computes a BM x BN output tile; each
@@ -119,12 +125,12 @@ __device__ __forceinline__ void gett_tile(const GettDesc& g, const double* __res
 #pragma unroll
   for (int i = 0; i < NA; ++i) {
     const int m = tile_m + a_m(i);
-    aoff[i] = m < g.M ? decode(m, g.nm, g.md, g.am) + a_k(i) * a_in : 0;
+    aoff[i] = m < g.M ? decode_fast(m, g.nm, g.md, g.mmag, g.msh, g.am) + a_k(i) * a_in : 0;
   }
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
     const int n = tile_n + b_n(i);
-    boff[i] = n < g.N ? decode(n, g.nn, g.nd, g.bn) + b_k(i) * b_in : 0;
+    boff[i] = n < g.N ? decode_fast(n, g.nn, g.nd, g.nmag, g.nsh, g.bn) + b_k(i) * b_in : 0;
   }
 
   // uniform k state: inner step c, outer counters and the outer base offsets
@@ -231,12 +237,12 @@ __device__ __forceinline__ void gett_tile(const GettDesc& g, const double* __res
           }
           continue;
         }
-        long long cmo = decode(m, g.nm, g.md, g.cm);
+        long long cmo = decode_fast(m, g.nm, g.md, g.mmag, g.msh, g.cm);
 #pragma unroll
         for (int b = 0; b < WN; ++b) {
           int n = tn0 + wn + b * 16 + li;
           if (n >= g.N) continue;
-          long long o = cmo + decode(n, g.nn, g.nd, g.cn);
+          long long o = cmo + decode_fast(n, g.nn, g.nd, g.nmag, g.nsh, g.cn);
           double v = g.alpha * (double)acc[a][b][r];
           if (g.beta || !first) v += C[o];
           C[o] = v;
@@ -347,7 +353,7 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(GettDesc g, const do
     int m = (int)(i / g.N), n = (int)(i - (long long)m * g.N);
     double s = 0.0;
     for (int z = 0; z < nsplit; ++z) s += part[(long long)z * total + i];
-    long long o = decode(m, g.nm, g.md, g.cm) + decode(n, g.nn, g.nd, g.cn);
+    long long o = decode_fast(m, g.nm, g.md, g.mmag, g.msh, g.cm) + decode_fast(n, g.nn, g.nd, g.nmag, g.nsh, g.cn);
     double v = g.alpha * s;
     if (g.beta) v += C[o];
     C[o] = v;
@@ -378,6 +384,20 @@ static void merge_free(int& n, int* d, long long* so, long long* sc) {
         merged = true;
       }
     }
+  }
+}
+
+static void magic_of(int d, unsigned& m, int& sh) {
+  int l = 0;
+  while (l < 31 && (1LL << l) < (long long)d) ++l;
+  sh = 31 + l;
+  m = (unsigned)((1ULL << sh) / (unsigned long long)std::max(d, 1) + 1);
+}
+
+void gett_magic(GettDesc& g) {
+  for (int c = 0; c < kMaxComp; ++c) {
+    magic_of(c < g.nm ? g.md[c] : 1, g.mmag[c], g.msh[c]);
+    magic_of(c < g.nn ? g.nd[c] : 1, g.nmag[c], g.nsh[c]);
   }
 }
 
@@ -432,6 +452,7 @@ void gett_prepare(GettDesc& g) {
   const long long ai = std::llabs(g.ak[g.nk - 1]), bi = std::llabs(g.bk[g.nk - 1]);
   g.a_kfast = g.nm == 0 || ai < std::llabs(g.am[g.nm - 1]);
   g.b_kfast = g.nn == 0 || bi < std::llabs(g.bn[g.nn - 1]);
+  gett_magic(g);
 }
 
 // Large tiles (128 x 128) when they still give enough workgroups, else 64 x 64.
@@ -487,6 +508,7 @@ void launch_gett(const GettDesc& g0, const double* A, const double* B, double* C
                  int role, double* ws, long long ws_elems, bool f32) {
   if (g0.M <= 0 || g0.N <= 0) return;
   GettDesc g = g0;
+  gett_magic(g);
   const bool big = big_tiles(g);
   const int bm = big ? 128 : 64, bn = bm;
   int ns = ws ? gett_splits(g, ws_elems) : 1;
@@ -589,7 +611,8 @@ __global__ __launch_bounds__(256) void group_reduce_kernel(const GroupItem* __re
     const int m = (int)(i / g.N), nn = (int)(i - (long long)m * g.N);
     double s = 0.0;
     for (int z = 0; z < it.splits; ++z) s += g.part[(long long)z * mn + i];
-    const long long o = decode(m, g.nm, g.md, g.cm) + decode(nn, g.nn, g.nd, g.cn);
+    const long long o = decode_fast(m, g.nm, g.md, g.mmag, g.msh, g.cm) +
+                        decode_fast(nn, g.nn, g.nd, g.nmag, g.nsh, g.cn);
     double v = g.alpha * s;
     if (g.beta) v += it.C[o];
     it.C[o] = v;
@@ -795,19 +818,50 @@ void launch_pack(const PackDesc& d, const double* src, double* dst, hipStream_t 
 // Same-spin ladder on unique pairs: packing of the antisymmetrised integrals and of the
 // amplitudes, and the antisymmetric fill of the result
 // ---------------------------------------------------------------------------
+// One workgroup per (row, pair of 32-wide tiles X <= Y of the x and y ranges): the tile
+// M[X][Y] of M[x][y] = jb[p - b0][x][q - qoff][y] and its mirror M[Y][X] are read with y
+// fastest into LDS, and V is written in packed order (y fastest inside each x).
+constexpr int kPackTile = 32;
 __global__ __launch_bounds__(256) void ladder_pack_v_kernel(const double* __restrict__ jb, int nP, int b0,
                                                             int qoff, int nq,
                                                             const LadderPair* __restrict__ rowtab, int rows,
-                                                            const LadderPair* __restrict__ ktab, int kp, int sym,
+                                                            int ntp, int sym, long long kpx,
                                                             double* __restrict__ Vp) {
-  const long long total = (long long)rows * kp;
+  __shared__ double A[kPackTile][kPackTile + 1], Bm[kPackTile][kPackTile + 1];
+  const int nT = (nP + kPackTile - 1) / kPackTile;
   const long long sq = nP, sx = (long long)nq * nP, sp = sx * nP;
-  for (long long e = blockIdx.x * 256LL + threadIdx.x; e < total; e += 256LL * gridDim.x) {
-    const int row = (int)(e / kp), k = (int)(e - (long long)row * kp);
-    const LadderPair pq = rowtab[row], xy = ktab[k];
-    const long long base = (pq.a - b0) * sp + (long long)(pq.b - qoff) * sq;
-    const double u = jb[base + xy.a * sx + xy.b], w = jb[base + xy.b * sx + xy.a];
-    Vp[e] = sym ? (xy.a == xy.b ? u : u + w) : u - w;
+  for (long long w = blockIdx.x; w < (long long)rows * ntp; w += gridDim.x) {
+    const int row = (int)(w / ntp);
+    int t = (int)(w - (long long)row * ntp);
+    // tile pair t -> (tx, ty), tx <= ty, tx-major
+    int tx = 0;
+    while (t >= nT - tx) {
+      t -= nT - tx;
+      ++tx;
+    }
+    const int ty = tx + t;
+    const LadderPair pq = rowtab[row];
+    const double* M = jb + (pq.a - b0) * sp + (long long)(pq.b - qoff) * sq;
+    const int X0 = tx * kPackTile, Y0 = ty * kPackTile;
+    __syncthreads();
+    for (int e = threadIdx.x; e < kPackTile * kPackTile; e += 256) {
+      const int i = e / kPackTile, j = e % kPackTile;
+      const int x = X0 + i, y = Y0 + j;
+      A[i][j] = (x < nP && y < nP) ? M[x * sx + y] : 0.0;
+      const int x2 = Y0 + i, y2 = X0 + j;
+      Bm[i][j] = (x2 < nP && y2 < nP) ? M[x2 * sx + y2] : 0.0;
+    }
+    __syncthreads();
+    double* out = Vp + (long long)row * kpx;
+    for (int e = threadIdx.x; e < kPackTile * kPackTile; e += 256) {
+      const int i = e / kPackTile, j = e % kPackTile;
+      const int x = X0 + i, y = Y0 + j;
+      if (x >= nP || y >= nP || (sym ? y < x : y <= x)) continue;
+      const double u = A[i][j], v = Bm[j][i];   // M[x][y], M[y][x]
+      const long long xl = x;
+      const long long k = sym ? xl * nP - xl * (xl - 1) / 2 + (y - x) : xl * nP - xl * (xl + 1) / 2 + (y - x - 1);
+      out[k] = sym ? (x == y ? u : u + v) : u - v;
+    }
   }
 }
 
@@ -875,10 +929,14 @@ static unsigned grid_for(long long n) {
 }
 
 void launch_ladder_pack_v(const double* jb, int nP, int b0, int qoff, int nq, const LadderPair* rowtab,
-                          int rows, const LadderPair* ktab, int kp, int sym, double* Vp, hipStream_t st) {
-  if (rows <= 0 || kp <= 0) return;
-  hipLaunchKernelGGL(ladder_pack_v_kernel, dim3(grid_for((long long)rows * kp)), dim3(256), 0, st, jb, nP, b0,
-                     qoff, nq, rowtab, rows, ktab, kp, sym, Vp);
+                          int rows, int sym, double* Vp, hipStream_t st) {
+  const long long kpx = sym ? (long long)nP * (nP + 1) / 2 : (long long)nP * (nP - 1) / 2;
+  if (rows <= 0 || kpx <= 0) return;
+  const int nT = (nP + kPackTile - 1) / kPackTile, ntp = nT * (nT + 1) / 2;
+  const long long work = (long long)rows * ntp;
+  const unsigned grid = (unsigned)std::min<long long>(work, 1LL << 20);
+  hipLaunchKernelGGL(ladder_pack_v_kernel, dim3(grid), dim3(256), 0, st, jb, nP, b0, qoff, nq, rowtab, rows, ntp,
+                     sym, kpx, Vp);
 }
 
 void launch_ladder_pack_t(const double* T, int nP, int nH, const LadderPair* ktab, int kp,
