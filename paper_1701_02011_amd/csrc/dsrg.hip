@@ -1018,7 +1018,8 @@ struct Exec {
       }
     }
 
-    // split-K for items with few tiles and a long k range; budget check
+    // split-K for items with few tiles and a k range long against the level's work per
+    // workgroup slot; budget check
     long long part_elems = 0;
     std::vector<std::vector<long long>> poff(lev.size());
     for (size_t L = 0; L < lev.size(); ++L) {
@@ -1048,10 +1049,19 @@ struct Exec {
             it.tiles_n = (int)tn;
           }
         }
+      }
+      // k steps per workgroup slot of the level (four small workgroups per CU): chunks
+      // shorter than that only add partial tiles to reduce
+      double level_steps = 0;
+      for (auto& it : lev[L]) level_steps += (double)it.tiles_m * it.tiles_n * it.g.steps;
+      const long long target = std::max<long long>(16, (long long)(level_steps / (4.0 * 256)));
+      for (auto& it : lev[L]) {
+        GettDesc& g = it.g;
         long long tiles = (long long)it.tiles_m * it.tiles_n;
         int ns = 1;
-        if (g.steps >= 64 && tiles < 64) {
-          long long want = std::min<long long>((g.steps + 15) / 16, std::max<long long>(1, 256 / tiles));
+        if (g.steps >= 64 && g.steps > 2 * target && tiles < 64) {
+          long long want = std::min<long long>((g.steps + target - 1) / target,
+                                               std::max<long long>(1, 256 / tiles));
           long long chunk = (g.steps + want - 1) / want;
           ns = (int)((g.steps + chunk - 1) / chunk);
           g.kchunk = chunk;
@@ -1072,7 +1082,7 @@ struct Exec {
 
     // flatten the levels (longest tiles first inside a level) and patch the addresses
     std::vector<GroupItem> items;
-    std::vector<int> split_idx;
+    std::vector<ReduceBlock> rblocks;
     struct LevelRange {
       int i0, n, tiles, s0, ns;
       long long red;
@@ -1090,7 +1100,7 @@ struct Exec {
       std::stable_sort(order.begin(), order.end(), [&](int x, int y) {
         return lev[L][x].g.kchunk > lev[L][y].g.kchunk;
       });
-      LevelRange R{(int)items.size(), (int)order.size(), 0, (int)split_idx.size(), 0, 0, 0.0, big == 1, 0.0};
+      LevelRange R{(int)items.size(), (int)order.size(), 0, (int)rblocks.size(), 0, 0, 0.0, big == 1, 0.0};
       for (int oi : order) {
         GroupItem it = lev[L][oi];
         const Fix& fx = levfix[L][oi];
@@ -1104,10 +1114,13 @@ struct Exec {
         if (R.tiles + t >= (1LL << 31)) throw Error(DSRG_E_UNSUPPORTED, "grouped launch too large");
         R.tiles += (int)t;
         if (it.splits > 1) {
-          it.red0 = R.red;
-          R.red += (long long)it.g.M * it.g.N;
-          split_idx.push_back((int)items.size() - R.i0);
-          ++R.ns;
+          const long long mn = (long long)it.g.M * it.g.N;
+          if (mn >= (1LL << 31)) throw Error(DSRG_E_UNSUPPORTED, "split-K tile too large");
+          for (long long e0 = 0; e0 < mn; e0 += 256) {
+            rblocks.push_back({(int)items.size() - R.i0, (int)e0});
+            ++R.ns;
+          }
+          R.red += mn;
         }
         R.flops += 2.0 * it.g.M * (double)it.g.N * it.g.K;
         R.bytes += 8.0 * ((double)it.g.M * it.g.K + (double)it.g.K * it.g.N + (double)it.g.M * it.g.N);
@@ -1139,19 +1152,19 @@ struct Exec {
       }
     }
     GroupItem* d_items = upload(items);
-    int* d_split = upload(split_idx);
+    ReduceBlock* d_rblk = upload(rblocks);
     int* d_map = upload(tile_item);
     for (size_t ri = 0; ri < ranges.size(); ++ri) {
       const LevelRange& R = ranges[ri];
       const GroupItem* it = d_items + R.i0;
-      const int* sp = d_split + R.s0;
+      const ReduceBlock* rb = d_rblk + R.s0;
       const int* tm = d_map + map0[ri];
       const bool lo = f32;
       group_launch(R.flops, [it, tm, R, lo](hipStream_t s) {
         launch_gett_group(it, tm, R.n, R.tiles, R.big, lo, s);
       }, true, R.n, R.tiles, R.bytes);
       if (R.ns > 0)
-        group_launch(0.0, [it, sp, R](hipStream_t s) { launch_group_reduce(it, sp, R.ns, R.red, s); });
+        group_launch(0.0, [it, rb, R](hipStream_t s) { launch_group_reduce(it, rb, R.ns, s); });
     }
 
     if (scalar_out) {

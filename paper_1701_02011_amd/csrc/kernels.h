@@ -90,14 +90,16 @@ struct GroupItem {
   int shape = 0;
   int tiles_m = 0, tiles_n = 0, splits = 1;
   int tile0 = 0;          // first workgroup of this item
-  long long red0 = 0;     // prefix of M N over the split items of the reduction launch
 };
 // tile_item[b] (b < tiles): index of the item that owns workgroup tile b of the launch.
 void launch_gett_group(const GroupItem* items, const int* tile_item, int n, int tiles, bool big,
                        bool f32, hipStream_t st);
-// split_idx: indices of the items with splits > 1, in increasing red0
-void launch_group_reduce(const GroupItem* items, const int* split_idx, int nsplit, long long total,
-                         hipStream_t st);
+// Block b of the split-K reduction sums the partial tiles of elements [e0, e0 + 256) of
+// item `item` (an index into the launch's items).
+struct ReduceBlock {
+  int item, e0;
+};
+void launch_group_reduce(const GroupItem* items, const ReduceBlock* blocks, int nblocks, hipStream_t st);
 
 // Grouped dot products: workgroups [blk0, blk0 + nblk) of the launch sum item i; one
 // partial per workgroup.

@@ -593,30 +593,34 @@ __global__ __launch_bounds__(256) void gett_group_big_kernel(const GroupItem* __
   gett_tile<4, 4, 2, kF32>(it.g, it.A, it.B, it.C, tm * Lds::BM, tn * Lds::BN, kz, lds);
 }
 
-// split-K items: C = alpha * sum_z part[z] (+ C), fixed order of z
+// split-K items: C = alpha * sum_z part[z] (+ C), fixed order of z; the loads of eight
+// partial tiles are issued together, the sum runs in z order
 __global__ __launch_bounds__(256) void group_reduce_kernel(const GroupItem* __restrict__ items,
-                                                           const int* __restrict__ idx, int nsplit,
-                                                           long long total) {
-  for (long long q = blockIdx.x * 256LL + threadIdx.x; q < total; q += 256LL * gridDim.x) {
-    int lo = 0, hi = nsplit - 1;
-    while (lo < hi) {
-      int mid = (lo + hi + 1) >> 1;
-      if (items[idx[mid]].red0 <= q) lo = mid;
-      else hi = mid - 1;
-    }
-    const GroupItem& it = items[idx[lo]];
-    const GettDesc& g = it.g;
-    const long long i = q - it.red0;
-    const long long mn = (long long)g.M * g.N;
-    const int m = (int)(i / g.N), nn = (int)(i - (long long)m * g.N);
-    double s = 0.0;
-    for (int z = 0; z < it.splits; ++z) s += g.part[(long long)z * mn + i];
-    const long long o = decode_fast(m, g.nm, g.md, g.mmag, g.msh, g.cm) +
-                        decode_fast(nn, g.nn, g.nd, g.nmag, g.nsh, g.cn);
-    double v = g.alpha * s;
-    if (g.beta) v += it.C[o];
-    it.C[o] = v;
+                                                           const ReduceBlock* __restrict__ blocks) {
+  const ReduceBlock rb = blocks[blockIdx.x];
+  const GroupItem& it = items[rb.item];
+  const GettDesc& g = it.g;
+  const long long mn = (long long)g.M * g.N;
+  const long long i = (long long)rb.e0 + threadIdx.x;
+  if (i >= mn) return;
+  const double* part = g.part + i;
+  const int ns = it.splits;
+  double s = 0.0;
+  int z = 0;
+  for (; z + 8 <= ns; z += 8) {
+    double v[8];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) v[u] = part[(long long)(z + u) * mn];
+#pragma unroll
+    for (int u = 0; u < 8; ++u) s += v[u];
   }
+  for (; z < ns; ++z) s += part[(long long)z * mn];
+  const int m = (int)(i / g.N), nn = (int)(i - (long long)m * g.N);
+  const long long o = decode_fast(m, g.nm, g.md, g.mmag, g.msh, g.cm) +
+                      decode_fast(nn, g.nn, g.nd, g.nmag, g.nsh, g.cn);
+  double v = g.alpha * s;
+  if (g.beta) v += it.C[o];
+  it.C[o] = v;
 }
 
 void launch_gett_group(const GroupItem* items, const int* tile_item, int n, int tiles, bool big,
@@ -633,12 +637,9 @@ void launch_gett_group(const GroupItem* items, const int* tile_item, int n, int 
     hipLaunchKernelGGL(gett_group_kernel<false>, grid, block, 0, st, items, tile_item);
 }
 
-void launch_group_reduce(const GroupItem* items, const int* split_idx, int nsplit, long long total,
-                         hipStream_t st) {
-  if (nsplit <= 0 || total <= 0) return;
-  long long blocks = std::min<long long>((total + 255) / 256, 4096);
-  hipLaunchKernelGGL(group_reduce_kernel, dim3((unsigned)blocks), dim3(256), 0, st, items, split_idx,
-                     nsplit, total);
+void launch_group_reduce(const GroupItem* items, const ReduceBlock* blocks, int nblocks, hipStream_t st) {
+  if (nblocks <= 0) return;
+  hipLaunchKernelGGL(group_reduce_kernel, dim3((unsigned)nblocks), dim3(256), 0, st, items, blocks);
 }
 
 // ---------------------------------------------------------------------------
