@@ -1203,6 +1203,8 @@ struct Exec {
       const TensorRef& o = outs.at(kv.first);
       GatherDesc gd;
       gd.rank = (int)o.axes.size();
+      if (gd.rank > 4 || o.lim >= (1LL << 38))
+        throw Error(DSRG_E_UNSUPPORTED, "gathered output too large");
       std::vector<GatherEntry> ent;
       for (int k = 0; k < gd.rank; ++k) {
         gd.dim[k] = d.len(o.axes[k]);

@@ -125,6 +125,7 @@ struct GatherDesc {
   int dim[4] = {1, 1, 1, 1};
   int split[4] = {};
   int cls[17] = {};
+  int blk[17] = {};   // workgroups of each class (prefix), set by launch_gather
 };
 void launch_gather(const GatherDesc& g, const GatherEntry* entries, double* out, hipStream_t st);
 

@@ -690,49 +690,75 @@ void launch_dot_group(const DotItem* items, int n, int blocks, double* partial, 
 // class given by which sub-space each index falls in; every entry of that class adds
 // coef * src[base + sum_k x_k ss_k], in entry order.
 // ---------------------------------------------------------------------------
-// tpe consecutive lanes share one output element: lane j of the group sums entries j,
-// j + tpe, ... of the element's class, and a fixed butterfly over the group adds the
-// partial sums (deterministic for a given tpe).  Small outputs with long entry lists use
-// wide groups, large outputs one lane per element.
+// Each workgroup covers 256 elements of one class (the box of index ranges the class
+// stands for, last index fastest), so the entry list it walks is the same for every lane:
+// entries load through the scalar cache and four source values are in flight at a time,
+// summed in entry order.
 __global__ __launch_bounds__(256) void gather_kernel(GatherDesc g, const GatherEntry* __restrict__ ent,
-                                                     double* __restrict__ out, long long total, int tpe) {
-  const long long gt = blockIdx.x * 256LL + threadIdx.x;
-  const int sub = (int)(gt % tpe);
-  for (long long e = gt / tpe; e < total; e += 256LL * gridDim.x / tpe) {
-    int x[4] = {0, 0, 0, 0};
-    long long idx = e;
-    int cls = 0;
+                                                     double* __restrict__ out) {
+  const int b = blockIdx.x;
+  const int ncls = 1 << g.rank;
+  int c = 0;
+  while (c + 1 < ncls && b >= g.blk[c + 1]) ++c;
+  int lo[4] = {0, 0, 0, 0}, len[4] = {1, 1, 1, 1};
+  long long cnt = 1;
 #pragma unroll
-    for (int k = 3; k >= 0; --k) {
-      if (k < g.rank) {
-        long long q = idx / g.dim[k];
-        x[k] = (int)(idx - q * g.dim[k]);
-        idx = q;
-        cls |= (x[k] >= g.split[k]) << k;
-      }
+  for (int k = 0; k < 4; ++k)
+    if (k < g.rank) {
+      const bool hi = (c >> k) & 1;
+      lo[k] = hi ? g.split[k] : 0;
+      len[k] = hi ? g.dim[k] - g.split[k] : g.split[k];
+      cnt *= len[k];
     }
-    double acc = 0.0;
-    for (int i = g.cls[cls] + sub; i < g.cls[cls + 1]; i += tpe) {
-      const GatherEntry& en = ent[i];
-      long long o = en.base + (long long)x[0] * en.ss[0] + (long long)x[1] * en.ss[1] +
-                    (long long)x[2] * en.ss[2] + (long long)x[3] * en.ss[3];
-      acc += en.coef * en.src[o];
+  long long e = (long long)(b - g.blk[c]) * 256 + threadIdx.x;
+  if (e >= cnt) return;
+  int x[4] = {0, 0, 0, 0};
+#pragma unroll
+  for (int k = 3; k >= 0; --k)
+    if (k < g.rank) {
+      const long long q = e / len[k];
+      x[k] = lo[k] + (int)(e - q * len[k]);
+      e = q;
     }
-    for (int w = tpe >> 1; w > 0; w >>= 1) acc += __shfl_xor(acc, w, 64);
-    if (sub == 0 && g.cls[cls + 1] > g.cls[cls]) out[e] += acc;
+  long long o = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k)
+    if (k < g.rank) o = o * g.dim[k] + x[k];
+  double acc = 0.0;
+  int i = g.cls[c];
+  const int end = g.cls[c + 1];
+  auto off = [&](const GatherEntry& en) {
+    return en.base + (long long)x[0] * en.ss[0] + (long long)x[1] * en.ss[1] + (long long)x[2] * en.ss[2] +
+           (long long)x[3] * en.ss[3];
+  };
+  for (; i + 4 <= end; i += 4) {
+    double v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = ent[i + u].src[off(ent[i + u])];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc = fma(ent[i + u].coef, v[u], acc);
   }
+  for (; i < end; ++i) acc = fma(ent[i].coef, ent[i].src[off(ent[i])], acc);
+  out[o] += acc;
 }
 
-void launch_gather(const GatherDesc& g, const GatherEntry* entries, double* out, hipStream_t st) {
-  long long total = 1;
-  for (int k = 0; k < g.rank; ++k) total *= g.dim[k];
-  if (total <= 0 || g.cls[1 << g.rank] == 0) return;
-  // lanes per element: enough threads to fill the chip (>= 2^18), at most a wave
-  int tpe = 1;
-  while (tpe < 64 && total * tpe < (1LL << 18)) tpe <<= 1;
-  long long threads = total * tpe;
-  long long blocks = std::min<long long>((threads + 255) / 256, 8192);
-  hipLaunchKernelGGL(gather_kernel, dim3((unsigned)blocks), dim3(256), 0, st, g, entries, out, total, tpe);
+void launch_gather(const GatherDesc& g0, const GatherEntry* entries, double* out, hipStream_t st) {
+  GatherDesc g = g0;
+  const int ncls = 1 << g.rank;
+  long long blocks = 0;
+  for (int c = 0; c < ncls; ++c) {
+    g.blk[c] = (int)blocks;
+    if (g.cls[c + 1] == g.cls[c]) continue;
+    long long cnt = 1;
+    for (int k = 0; k < g.rank; ++k) {
+      const bool hi = (c >> k) & 1;
+      cnt *= hi ? g.dim[k] - g.split[k] : g.split[k];
+    }
+    blocks += (cnt + 255) / 256;
+  }
+  for (int c = ncls; c <= 16; ++c) g.blk[c] = (int)blocks;
+  if (blocks <= 0) return;
+  hipLaunchKernelGGL(gather_kernel, dim3((unsigned)blocks), dim3(256), 0, st, g, entries, out);
 }
 
 // ---------------------------------------------------------------------------
