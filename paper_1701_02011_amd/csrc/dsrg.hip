@@ -1025,22 +1025,32 @@ struct Exec {
     for (size_t L = 0; L < lev.size(); ++L) {
       for (auto& it : lev[L]) {
         GettDesc& g = it.g;
-        // tile shape with the least padded work (ties: the first, square one); 128 x 128
-        // when it pads at most 10 % more than the best small shape (four times the work
-        // per loaded element) and the k range is long (short ones ran slower that way)
-        long long bestw = -1;
+        // tile shape: the square 64 x 64 one unless it pads more than 1.8 times the work
+        // of the thinnest fit (a 16 x 128 or 128 x 16 workgroup step costs about as long
+        // as a 64 x 64 one in these latency-bound launches but covers half the outputs);
+        // 128 x 128 when it pads at most 10 % more than the chosen small shape (four
+        // times the work per loaded element) and the k range is long (short ones ran
+        // slower that way)
+        long long bestw = -1, w0 = -1;
+        int best = 0;
         for (int sh = 0; sh < kGroupShapes; ++sh) {
           if (sh == kGroupBigShape) continue;
           const long long tm = (g.M + kGroupTiles[sh][0] - 1) / kGroupTiles[sh][0];
           const long long tn = (g.N + kGroupTiles[sh][1] - 1) / kGroupTiles[sh][1];
           const long long w = tm * kGroupTiles[sh][0] * tn * kGroupTiles[sh][1];
+          if (sh == 0) w0 = w;
           if (bestw < 0 || w < bestw) {
             bestw = w;
-            it.shape = sh;
-            it.tiles_m = (int)tm;
-            it.tiles_n = (int)tn;
+            best = sh;
           }
         }
+        if (w0 * 5 <= bestw * 9) {
+          best = 0;
+          bestw = w0;
+        }
+        it.shape = best;
+        it.tiles_m = (g.M + kGroupTiles[best][0] - 1) / kGroupTiles[best][0];
+        it.tiles_n = (g.N + kGroupTiles[best][1] - 1) / kGroupTiles[best][1];
         if (g.M >= 128 && g.N >= 128 && g.steps >= 128) {
           const long long tm = (g.M + 127) / 128, tn = (g.N + 127) / 128;
           if (tm * tn * 128 * 128 * 10 <= bestw * 11) {
