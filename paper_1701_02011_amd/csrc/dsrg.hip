@@ -1139,13 +1139,14 @@ struct Exec {
       ranges.push_back(R);
      }
     if (const char* path = getenv("DSRG_GROUP_DUMP")) {
-      // planning record for tuning: use, level, M, N, K, splits, k chunk
+      // planning record for tuning: use, level, M, N, K, splits, k chunk, shape, inner k,
+      // steps per inner range, steps
       if (FILE* f = fopen(path, "a")) {
         for (size_t L = 0; L < ranges.size(); ++L)
           for (int i = 0; i < ranges[L].n; ++i) {
             const GroupItem& it = items[ranges[L].i0 + i];
-            fprintf(f, "%d,%d,%d,%d,%d,%d,%lld,%d\n", use_id, (int)L, it.g.M, it.g.N, it.g.K, it.splits,
-                    it.g.kchunk, it.shape);
+            fprintf(f, "%d,%d,%d,%d,%d,%d,%lld,%d,%d,%d,%lld\n", use_id, (int)L, it.g.M, it.g.N, it.g.K,
+                    it.splits, it.g.kchunk, it.shape, it.g.kd[it.g.nk - 1], it.g.ksteps, it.g.steps);
           }
         fclose(f);
       }
