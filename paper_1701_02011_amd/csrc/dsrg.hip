@@ -367,9 +367,8 @@ struct Exec {
     GettDesc g = g0;
     // A short inner k component wastes most of each zero-padded k step: packing both
     // operands makes the whole k range one contiguous component (steps of kGettBK).
-    const int kin = g.kd[g.nk - 1];
-    const bool padk = g.nk > 1 && (long long)g.ksteps * kGettBK * 8 > 9LL * kin && g.M >= kPackMin &&
-                      g.N >= kPackMin && (long long)g.M * g.K <= kPackCap && (long long)g.N * g.K <= kPackCap;
+    const bool padk = g.nk > 1 && gett_k_fill(g) * 9 < 8 && g.M >= kPackMin && g.N >= kPackMin &&
+                      (long long)g.M * g.K <= kPackCap && (long long)g.N * g.K <= kPackCap;
     const bool pa = padk || (!unit_fast(g.a_kfast, g.nm, g.am, g.ak[g.nk - 1]) && g.N >= kPackMin &&
                              (long long)g.M * g.K <= kPackCap);
     const bool pb = padk || (!unit_fast(g.b_kfast, g.nn, g.bn, g.bk[g.nk - 1]) && g.M >= kPackMin &&
@@ -1057,6 +1056,7 @@ struct Exec {
             it.shape = kGroupBigShape;
             it.tiles_m = (int)tm;
             it.tiles_n = (int)tn;
+            gett_unpack_k(g);   // the 128 x 128 group tile walks plain k steps
           }
         }
       }

@@ -30,7 +30,11 @@ struct GettDesc {
   int a_kfast = 1;     // A tile loads walk k fastest (else m fastest)
   int b_kfast = 0;     // B tile loads walk k fastest (else n fastest)
   int ksteps = 1;      // k steps per value of the outer k components
-  long long steps = 1;   // total k steps: K / kd[nk - 1] * ksteps
+  long long steps = 1;   // total k steps: K / kd[nk - 1] * ksteps (K / (kd[nk-1] kd[nk-2]) * ksteps with kpack)
+  // kpack > 1: a step covers kpack consecutive values of component nk - 2 times the whole
+  // inner component (kpack * kd[nk - 1] <= kGettBK), for inner components of at most
+  // kGettBK / 2 values; ksteps is then the steps per sweep of component nk - 2
+  int kpack = 1;
   long long kchunk = 1;  // k steps per split (split-K), set by the launcher
   double* part = nullptr;  // split-K partial tiles [split][M][N], set by the launcher
   // division by md[c] (nd[c]) as a multiply and shift: q = (idx * mmag[c]) >> msh[c] for
@@ -40,6 +44,10 @@ struct GettDesc {
 };
 // merges and orders components, chooses the inner k component, and sets the magic numbers
 void gett_prepare(GettDesc& g);
+// back to plain k steps (for tiles without packed steps)
+void gett_unpack_k(GettDesc& g);
+// fraction of the k values of all steps that are real (not zero padding)
+inline double gett_k_fill(const GettDesc& g) { return (double)g.K / ((double)g.steps * kGettBK); }
 // the magic numbers of md and nd alone (after any later change of them)
 void gett_magic(GettDesc& g);
 

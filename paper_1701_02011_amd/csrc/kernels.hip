@@ -90,8 +90,10 @@ struct Mfma<true> {
 };
 constexpr int kF32FlushSteps = 64;
 
-// One BM x BN output tile at (tile_m, tile_n) for chunk kz of the k steps of g.
-template <int WM, int WN, int WGM = 2, bool kF32 = false>
+// One BM x BN output tile at (tile_m, tile_n) for chunk kz of the k steps of g.  kPackK:
+// the tile supports packed k steps (g.kpack > 1); the 128 x 128 tiles leave it out (their
+// launches are prepared without it) to keep their registers.
+template <int WM, int WN, int WGM = 2, bool kF32 = false, bool kPackK = (WM * WN < 16)>
 __device__ __forceinline__ void gett_tile(const GettDesc& g, const double* __restrict__ A,
                                           const double* __restrict__ B, double* __restrict__ C,
                                           int tile_m, int tile_n, int kz,
@@ -111,6 +113,14 @@ __device__ __forceinline__ void gett_tile(const GettDesc& g, const double* __res
   const int kin = g.kd[nk - 1];
   const long long a_in = g.ak[nk - 1], b_in = g.bk[nk - 1];
   const int ksteps = g.ksteps;
+  // a step walks U values of component kw (the inner one, or with kpack the one before it,
+  // whole inner ranges packed into the step); components below no advance between sweeps
+  const int kp = kPackK ? g.kpack : 1;
+  const int kw = kp > 1 ? nk - 2 : nk - 1;
+  const int U = kp > 1 ? kp : BK;
+  const int kdw = g.kd[kw];
+  const long long a_st = g.ak[kw], b_st = g.bk[kw];
+  const int no = kw;
   const long long s_lo = (long long)kz * g.kchunk;
   const long long s_hi = min(g.steps, s_lo + g.kchunk);
   const bool akf = g.a_kfast, bkf = g.b_kfast;
@@ -121,17 +131,40 @@ __device__ __forceinline__ void gett_tile(const GettDesc& g, const double* __res
   auto a_m = [&](int i) { return akf ? (tid / BK) + (256 / BK) * i : (tid & (BM - 1)); };
   auto b_k = [&](int i) { return bkf ? (tid & (BK - 1)) : tid / BN + (256 / BN) * i; };
   auto b_n = [&](int i) { return bkf ? (tid / BK) + (256 / BK) * i : (tid & (BN - 1)); };
+  // k slot j of a step: value j of the inner component (plain steps), or value j % kin of
+  // the inner and j / kin of the walked component (packed steps).  Each slot keeps a 4-bit
+  // code v (j; or j / kin, 15 past the packed ranges) and is real in a step while v < L
+  // with L = kin - c BK (plain) or min(8, kd[kw] - c kpack) (packed), so no per-slot
+  // limits stay in registers.
+  static_assert(NA <= 8 && NB <= 8, "slot codes");
+  auto slot_off = [&](int j, long long s_in, long long s_w) -> long long {
+    return kp > 1 ? (long long)(j % kin) * s_in + (long long)(j / kin) * s_w : (long long)j * s_in;
+  };
+  auto slot_code = [&](int j) -> unsigned { return kp > 1 ? (j < kp * kin ? (unsigned)(j / kin) : 15u) : (unsigned)j; };
   long long aoff[NA], boff[NB];
+  unsigned acode = 0, bcode = 0;
 #pragma unroll
   for (int i = 0; i < NA; ++i) {
     const int m = tile_m + a_m(i);
-    aoff[i] = m < g.M ? decode_fast(m, g.nm, g.md, g.mmag, g.msh, g.am) + a_k(i) * a_in : 0;
+    aoff[i] = m < g.M ? decode_fast(m, g.nm, g.md, g.mmag, g.msh, g.am) + slot_off(a_k(i), a_in, a_st) : 0;
+    if constexpr (kPackK) acode |= slot_code(a_k(i)) << (4 * i);
   }
 #pragma unroll
   for (int i = 0; i < NB; ++i) {
     const int n = tile_n + b_n(i);
-    boff[i] = n < g.N ? decode_fast(n, g.nn, g.nd, g.nmag, g.nsh, g.bn) + b_k(i) * b_in : 0;
+    boff[i] = n < g.N ? decode_fast(n, g.nn, g.nd, g.nmag, g.nsh, g.bn) + slot_off(b_k(i), b_in, b_st) : 0;
+    if constexpr (kPackK) bcode |= slot_code(b_k(i)) << (4 * i);
   }
+  // slot i of A (B) is real in the current step (L = real_slots()); without packed steps
+  // the code is the slot itself
+  auto real_a = [&](int i, int L) -> bool {
+    if constexpr (kPackK) return (int)((acode >> (4 * i)) & 15u) < L;
+    else return a_k(i) < L;
+  };
+  auto real_b = [&](int i, int L) -> bool {
+    if constexpr (kPackK) return (int)((bcode >> (4 * i)) & 15u) < L;
+    else return b_k(i) < L;
+  };
 
   // uniform k state: inner step c, outer counters and the outer base offsets
   int c;
@@ -143,7 +176,7 @@ __device__ __forceinline__ void gett_tile(const GettDesc& g, const double* __res
 #pragma unroll
     for (int j = kMaxComp - 2; j >= 0; --j) {
       cnt[j] = 0;
-      if (j <= nk - 2) {
+      if (j < no) {
         const long long q = o / g.kd[j];
         cnt[j] = (int)(o - q * g.kd[j]);
         o = q;
@@ -158,7 +191,7 @@ __device__ __forceinline__ void gett_tile(const GettDesc& g, const double* __res
     bool carry = true;
 #pragma unroll
     for (int j = kMaxComp - 2; j >= 0; --j) {
-      if (carry && j <= nk - 2) {
+      if (carry && j < no) {
         ++cnt[j];
         abo += g.ak[j];
         bbo += g.bk[j];
@@ -173,33 +206,35 @@ __device__ __forceinline__ void gett_tile(const GettDesc& g, const double* __res
     }
   };
 
+  auto real_slots = [&]() -> int { return kp > 1 ? min(8, kdw - c * kp) : kin - c * BK; };
   double ra[NA], rb[NB];
   // loads of the step (c): out-of-range slots read the step's first element (valid) and
   // are zeroed by the select in stash, which runs after the MFMAs so the loads overlap them
   auto fetch = [&]() {
-    const int k0 = c * BK;
-    const long long ab = abo + k0 * a_in, bb = bbo + k0 * b_in;
+    const int k0 = c * U;
+    const int L = real_slots();
+    const long long ab = abo + k0 * a_st, bb = bbo + k0 * b_st;
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
-      const bool ok = k0 + a_k(i) < kin;
+      const bool ok = real_a(i, L);
       ra[i] = A[ab + (ok ? aoff[i] : 0)];
     }
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
-      const bool ok = k0 + b_k(i) < kin;
+      const bool ok = real_b(i, L);
       rb[i] = B[bb + (ok ? boff[i] : 0)];
     }
   };
   auto stash = [&](int buf) {
-    const int k0 = c * BK;
+    const int L = real_slots();
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
-      const bool ok = k0 + a_k(i) < kin && tile_m + a_m(i) < g.M;
+      const bool ok = real_a(i, L) && tile_m + a_m(i) < g.M;
       As[buf][a_k(i) * LDA + a_m(i)] = ok ? (T)ra[i] : (T)0;
     }
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
-      const bool ok = k0 + b_k(i) < kin && tile_n + b_n(i) < g.N;
+      const bool ok = real_b(i, L) && tile_n + b_n(i) < g.N;
       Bs[buf][b_k(i) * LDB + b_n(i)] = ok ? (T)rb[i] : (T)0;
     }
   };
@@ -401,6 +436,17 @@ void gett_magic(GettDesc& g) {
   }
 }
 
+static bool big_tiles(const GettDesc& g);
+
+void gett_unpack_k(GettDesc& g) {
+  if (g.kpack <= 1) return;
+  const int kin = g.kd[g.nk - 1];
+  g.kpack = 1;
+  g.ksteps = (kin + BK - 1) / BK;
+  g.steps = (long long)(g.K / kin) * g.ksteps;
+  g.kchunk = g.steps;
+}
+
 void gett_prepare(GettDesc& g) {
   merge_free(g.nm, g.md, g.am, g.cm);
   merge_free(g.nn, g.nd, g.bn, g.cn);
@@ -445,8 +491,29 @@ void gett_prepare(GettDesc& g) {
   std::swap(g.ak[best], g.ak[g.nk - 1]);
   std::swap(g.bk[best], g.bk[g.nk - 1]);
   const int kin = g.kd[g.nk - 1];
+  g.kpack = 1;
   g.ksteps = (kin + BK - 1) / BK;
   g.steps = (long long)(g.K / kin) * g.ksteps;
+  if (g.nk >= 2 && 2 * kin <= BK) {
+    // pack whole inner ranges into a step along the outer component that pads least
+    // (ties: the larger); keep it only if it saves steps
+    const int R = BK / kin;
+    int o = 0;
+    auto pad = [&](int j) { return (double)((g.kd[j] + R - 1) / R * R) / g.kd[j]; };
+    for (int j = 1; j < g.nk - 1; ++j)
+      if (pad(j) < pad(o) - 1e-12 || (pad(j) <= pad(o) + 1e-12 && g.kd[j] > g.kd[o])) o = j;
+    const long long ksp = (g.kd[o] + R - 1) / R;
+    const long long stp = (long long)(g.K / ((long long)kin * g.kd[o])) * ksp;
+    if (stp < g.steps) {
+      std::swap(g.kd[o], g.kd[g.nk - 2]);
+      std::swap(g.ak[o], g.ak[g.nk - 2]);
+      std::swap(g.bk[o], g.bk[g.nk - 2]);
+      g.kpack = R;
+      g.ksteps = (int)ksp;
+      g.steps = stp;
+    }
+  }
+  if (big_tiles(g)) gett_unpack_k(g);   // 128 x 128 launches walk plain steps
   g.kchunk = g.steps;
   g.part = nullptr;
   const long long ai = std::llabs(g.ak[g.nk - 1]), bi = std::llabs(g.bk[g.nk - 1]);
@@ -510,6 +577,7 @@ void launch_gett(const GettDesc& g0, const double* A, const double* B, double* C
   GettDesc g = g0;
   gett_magic(g);
   const bool big = big_tiles(g);
+  if (big) gett_unpack_k(g);
   const int bm = big ? 128 : 64, bn = bm;
   int ns = ws ? gett_splits(g, ws_elems) : 1;
   g.part = nullptr;

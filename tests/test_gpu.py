@@ -34,7 +34,7 @@ def _close(x, ref, rel=1e-10):
 # ---------------------------------------------------------------------------
 # contraction kernel
 # ---------------------------------------------------------------------------
-GETT_CASES = ["gemm", "ragged", "strided", "multi", "vec", "accum", "splitk", "longk"]
+GETT_CASES = ["gemm", "ragged", "strided", "multi", "vec", "accum", "splitk", "longk", "packk"]
 
 
 @pytest.mark.parametrize("precision", [0, 1])
@@ -91,6 +91,16 @@ def test_gett_kernel(case, precision):
         A = rng.standard_normal((M, K)); B = rng.standard_normal((K, N)); C = rng.standard_normal((M, N))
         out = gett(A, B, C, m=[(M, K, N)], n=[(N, 1, 1)], k=[(K, 1, N)], alpha=1.5, beta=1)
         ref = C + 1.5 * (A @ B)
+    elif case == "packk":
+        # a 6-value inner k component unit-stride in both operands and two outer ones that
+        # do not merge: whole inner ranges are packed two to a k step along the 55-value one
+        M, N, f, e, u = 40, 70, 3, 55, 6
+        A = rng.standard_normal((M, f, e, u)); B = rng.standard_normal((e, f, N, u))
+        C = rng.standard_normal((M, N))
+        out = gett(A, B, C, m=[(M, f * e * u, N)], n=[(N, u, 1)],
+                   k=[(f, e * u, N * u), (e, u, f * N * u), (u, 1, 1)], alpha=0.5, beta=1)
+        ref = C + 0.5 * np.einsum("mfeu,efnu->mn", A, B)
+        K = f * e * u
     else:
         M, N, K = 65, 130, 17
         A = rng.standard_normal((M, K)); B = rng.standard_normal((K, N)); C = rng.standard_normal((M, N))
