@@ -56,7 +56,11 @@ constexpr int BK = kGettBK;
 template <int WM, int WN, int WGM, class T = double>
 struct TileLds {
   static constexpr int BM = 16 * WM * WGM, BN = 16 * WN * (4 / WGM);
-  static constexpr int LDA = BM + 2, LDB = BN + 2;
+  // row pitch: 16 lanes of a 64-bit access (one bank pass) with k = 0..15 and one m land on
+  // distinct banks when 2 pitch = 2 (mod 32 banks), i.e. an odd pitch of doubles; 32 lanes
+  // of a 32-bit access with k = 0..15 and two m need a pitch of 2 (mod 32) floats
+  static constexpr int PAD = sizeof(T) == 8 ? 1 : 2;
+  static constexpr int LDA = BM + PAD, LDB = BN + PAD;
   T As[2][BK * LDA];
   T Bs[2][BK * LDB];
 };
@@ -102,7 +106,7 @@ __device__ __forceinline__ void gett_tile(const GettDesc& g, const double* __res
   using T = typename MF::T;
   constexpr int BM = TileLds<WM, WN, WGM, T>::BM, BN = TileLds<WM, WN, WGM, T>::BN;
   static_assert(BM * BK % 256 == 0 && BN * BK % 256 == 0 && 256 % BM == 0 || BM >= 256, "tile");
-  constexpr int LDA = BM + 2, LDB = BN + 2;
+  constexpr int LDA = TileLds<WM, WN, WGM, T>::LDA, LDB = TileLds<WM, WN, WGM, T>::LDB;
   constexpr int NA = BM * BK / 256, NB = BN * BK / 256;   // loads per thread per step
   auto& As = lds.As;
   auto& Bs = lds.Bs;
