@@ -1467,8 +1467,83 @@ struct Exec {
   int grouped_uses = 0;
   bool grouped = true;
   long long group_cap = 0;   // bytes of temporaries one grouped use may hold
-  void run_use(const Use& U0, std::map<std::string, TensorRef>& outs, double* scalar_out) {
-    const Use U = merged_use(U0);
+  // Scatters of a product into a [P][P][H][H] output that form the four images of the
+  // pair antisymmetriser, X[pq ij] c, X[qp ij] -c, X[pq ji] -c, X[qp ji] c, become one
+  // scatter c X~[pq ij] into a zeroed pre-image X~ of the output, and X += A(X~) once at
+  // the end of the use (A: the same four images): a quarter of the scatter (gather)
+  // traffic of those products.
+  bool collapse_images = true;
+  void run_use(const Use& U0, std::map<std::string, TensorRef>& outs0, double* scalar_out) {
+    Use U = merged_use(U0);
+    std::map<std::string, TensorRef> outs = outs0;
+    std::vector<std::string> pre_names;
+    if (collapse_images && !scalar_out) {
+      const long long nP = d.len('P'), nH = d.len('H');
+      const std::vector<long long> dense{nP * nH * nH, nH * nH, nH, 1};
+      auto swap01 = [](std::string o) { std::swap(o[0], o[1]); return o; };
+      auto swap23 = [](std::string o) { std::swap(o[2], o[3]); return o; };
+      for (auto& P : U) {
+        std::vector<TScatter> kept;
+        std::vector<bool> used(P.s.size(), false);
+        for (size_t a = 0; a < P.s.size(); ++a) {
+          if (used[a]) continue;
+          const TScatter& S = P.s[a];
+          const std::string name = S.tensor + "." + S.block;
+          auto oi = outs0.find(name);
+          bool quad = false;
+          size_t idx[3] = {0, 0, 0};
+          if (oi != outs0.end() && S.letters.size() == 4 && oi->second.axes == "PPHH" &&
+              oi->second.stride == dense && S.letters[0] != S.letters[1] && S.letters[2] != S.letters[3]) {
+            const std::string img[3] = {swap01(S.letters), swap23(S.letters), swap23(swap01(S.letters))};
+            const double sg[3] = {-1.0, -1.0, 1.0};
+            quad = true;
+            for (int k = 0; k < 3 && quad; ++k) {
+              bool found = false;
+              for (size_t b = 0; b < P.s.size() && !found; ++b)
+                if (!used[b] && b != a && P.s[b].tensor == S.tensor && P.s[b].block == S.block &&
+                    P.s[b].letters == img[k] && P.s[b].coef == sg[k] * S.coef) {
+                  found = true;
+                  idx[k] = b;
+                }
+              quad = found;
+            }
+          }
+          if (!quad) {
+            kept.push_back(S);
+            used[a] = true;
+            continue;
+          }
+          used[a] = true;
+          for (int k = 0; k < 3; ++k) used[idx[k]] = true;
+          TScatter R = S;
+          R.block += "~";
+          kept.push_back(R);
+          const std::string pn = S.tensor + "." + R.block;
+          if (!outs.count(pn)) {
+            TensorRef t = oi->second;
+            t.p = pool.alloc((size_t)t.lim);
+            double* tp = t.p;
+            const long long n = t.lim;
+            op([tp, n](hipStream_t s) { launch_fill(tp, n, 0.0, s); });
+            ++n_launch;
+            outs[pn] = t;
+            pre_names.push_back(pn);
+          }
+        }
+        P.s = kept;
+      }
+    }
+    run_use_body(U, outs, scalar_out);
+    for (auto& pn : pre_names) {
+      const double* X = outs.at(pn).p;
+      double* O = outs0.at(pn.substr(0, pn.size() - 1)).p;
+      const int nPl = d.len('P'), nHl = d.len('H');
+      op([X, O, nPl, nHl](hipStream_t s) { launch_antisym_add(X, O, nPl, nHl, s); });
+      ++n_launch;
+    }
+  }
+
+  void run_use_body(const Use& U, std::map<std::string, TensorRef>& outs, double* scalar_out) {
     // products with the (PP|PP) block, grouped by the block's letters
     std::map<std::string, std::vector<const TProduct*>> pppp;
     std::vector<std::pair<int, const TProduct*>> plain;

@@ -228,5 +228,8 @@ void launch_pair_fold(int nC, const double* P2, const double* energies, double* 
 // out = sum_i coef[i] * vals[i] (fixed order)
 void launch_weighted_sum(int n, const double* vals, const double* coef, double* out, hipStream_t st);
 void launch_fill(double* p, long long n, double v, hipStream_t st);
+// O[p][q][i][j] += X[p][q][i][j] - X[q][p][i][j] - X[p][q][j][i] + X[q][p][j][i]
+// (both [P][P][H][H], dense, distinct arrays)
+void launch_antisym_add(const double* X, double* O, int nP, int nH, hipStream_t st);
 
 }  // namespace dsrg

@@ -914,6 +914,28 @@ void launch_pack(const PackDesc& d, const double* src, double* dst, hipStream_t 
 }
 
 // ---------------------------------------------------------------------------
+// Pair antisymmetriser of a pre-image added into a [P][P][H][H] tensor
+// ---------------------------------------------------------------------------
+__global__ __launch_bounds__(256) void antisym_add_kernel(const double* __restrict__ X, double* __restrict__ O,
+                                                          int nP, int nH, long long total) {
+  const long long hh = (long long)nH * nH, qs = hh, ps = (long long)nP * hh;
+  for (long long e = blockIdx.x * 256LL + threadIdx.x; e < total; e += 256LL * gridDim.x) {
+    const long long p = e / ps, r1 = e - p * ps;
+    const long long q = r1 / qs, r2 = r1 - q * qs;
+    const long long i = r2 / nH, j = r2 - i * nH;
+    const long long qp = q * ps + p * qs;
+    O[e] += X[e] - X[qp + r2] - X[p * ps + q * qs + j * nH + i] + X[qp + j * nH + i];
+  }
+}
+
+void launch_antisym_add(const double* X, double* O, int nP, int nH, hipStream_t st) {
+  const long long total = (long long)nP * nP * nH * nH;
+  if (total <= 0) return;
+  const unsigned grid = (unsigned)std::max<long long>(1, std::min<long long>((total + 255) / 256, 16384));
+  hipLaunchKernelGGL(antisym_add_kernel, dim3(grid), dim3(256), 0, st, X, O, nP, nH, total);
+}
+
+// ---------------------------------------------------------------------------
 // Same-spin ladder on unique pairs: packing of the antisymmetrised integrals and of the
 // amplitudes, and the antisymmetric fill of the result
 // ---------------------------------------------------------------------------

@@ -138,6 +138,43 @@ def merge_equal(prods, ident, sym):
     return out
 
 
+def collapse_images(prods, outs):
+    """The library's rewrite of antisymmetriser images: a product's four scatters
+    c X[pq ij], -c X[qp ij], -c X[pq ji], c X[qp ji] into a [P][P][H][H] output become one
+    scatter into the pre-image X~; the caller adds A(X~) to X afterwards."""
+    out = []
+    for facs, sp, res, scat in prods:
+        kept, used = [], [False] * len(scat)
+        for a, (c, tn, blk, ol) in enumerate(scat):
+            if used[a]:
+                continue
+            used[a] = True
+            quad = False
+            if tn in outs and len(ol) == 4 and ol[0] != ol[1] and ol[2] != ol[3]:
+                imgs = [(ol[1] + ol[0] + ol[2:], -c), (ol[:2] + ol[3] + ol[2], -c),
+                        (ol[1] + ol[0] + ol[3] + ol[2], c)]
+                idx = []
+                for il, ic in imgs:
+                    b = next((b for b, (c2, t2, b2, l2) in enumerate(scat)
+                              if not used[b] and b not in idx and (t2, b2, l2) == (tn, blk, il) and c2 == ic), None)
+                    if b is None:
+                        break
+                    idx.append(b)
+                quad = len(idx) == 3
+            if quad:
+                for b in idx:
+                    used[b] = True
+                kept.append((c, tn, blk + "~", ol))
+            else:
+                kept.append((c, tn, blk, ol))
+        out.append([facs, sp, res, kept])
+    return out
+
+
+def antisym(X):
+    return X - X.transpose(1, 0, 2, 3) - X.transpose(0, 1, 3, 2) + X.transpose(1, 0, 3, 2)
+
+
 def regulariser(s, D):
     out = np.zeros_like(D)
     nz = D != 0

@@ -135,3 +135,41 @@ def test_merged_products_give_the_same_commutators():
     for k in ("aa", "ab", "bb"):
         assert np.abs(a["O2"][k] - b["O2"][k]).max() <= 1e-12 * max(1.0, np.abs(a["O2"][k]).max()), k
     assert abs(a["e3"] - b["e3"]) <= 1e-12 * max(1.0, abs(a["e3"]))
+
+
+def test_collapsed_antisymmetriser_images_give_the_same_commutators():
+    """Four scatters forming the pair-antisymmetriser images of one product collapse into
+    one scatter into a pre-image, added as A(pre-image) afterwards: W and Z unchanged."""
+    p = make_problem(2, 2, 4, 9, seed=5, s=1.3)
+    uses = table_emulator.load_table()
+    a = table_emulator.pipeline(p, uses)
+    collapsed = {}
+    for name in ("W", "Z"):
+        prods = uses[name]
+        col = table_emulator.collapse_images(prods, {"O2"})
+        n_before = sum(len(x[3]) for x in prods)
+        n_after = sum(len(x[3]) for x in col)
+        assert n_after <= n_before - 3 * 30, (name, n_before, n_after)
+        collapsed[name] = col
+    # run with pre-images: the O2 outputs gain blocks "aa~", "ab~", "bb~" that are added
+    # into their blocks through the antisymmetriser after the use
+    orig_run_use = table_emulator.run_use
+
+    def run_use_collapsed(prods, dd, B, tens, outs):
+        if outs is None or not any(x[3] and any(bl.endswith("~") for _, _, bl, _ in x[3]) for x in prods):
+            return orig_run_use(prods, dd, B, tens, outs)
+        pre = {k + "~": np.zeros_like(v) for k, v in outs["O2"].items()}
+        outs["O2"].update(pre)
+        e = orig_run_use(prods, dd, B, tens, outs)
+        for k in list(pre):
+            outs["O2"][k[:-1]] += table_emulator.antisym(outs["O2"].pop(k))
+        return e
+
+    table_emulator.run_use = run_use_collapsed
+    try:
+        b = table_emulator.pipeline(p, dict(uses, W=collapsed["W"], Z=collapsed["Z"]))
+    finally:
+        table_emulator.run_use = orig_run_use
+    for k in ("aa", "ab", "bb"):
+        assert np.abs(a["O2"][k] - b["O2"][k]).max() <= 1e-12 * max(1.0, np.abs(a["O2"][k]).max()), k
+    assert abs(a["e3"] - b["e3"]) <= 1e-12 * max(1.0, abs(a["e3"]))
