@@ -376,9 +376,10 @@ struct Exec {
     if (pa) A = pack_operand(0, g, A);
     if (pb) Bp = pack_operand(1, g, Bp);
     if (pa || pb) gett_prepare(g);
-    double fl = 2.0 * g.M * (double)g.N * g.K;
+    const double frac = gett_tile_fraction(g);
+    double fl = 2.0 * g.M * (double)g.N * g.K * frac;
     Rec r{nullptr, nullptr, role, fl, g.M, g.N, g.K, g.nm, g.nn, g.nk, cur_product};
-    r.bytes = 8.0 * ((double)g.M * g.K + (double)g.K * g.N + (double)g.M * g.N * (g.beta ? 2 : 1));
+    r.bytes = 8.0 * ((double)g.M * g.K + (double)g.K * g.N + (double)g.M * g.N * frac * (g.beta ? 2 : 1));
     r.kin = g.kd[g.nk - 1]; r.ksteps = g.ksteps; r.akf = g.a_kfast; r.bkf = g.b_kfast;
     r.pa = pa; r.pb = pb;
     r.ai = g.ak[g.nk - 1]; r.bi = g.bk[g.nk - 1];
@@ -452,7 +453,7 @@ struct Exec {
   // (optionally the first index in [off1, off1 + n1) and the third in [off3, off3 + n3) of
   // their spaces)
   void build_j(char s1, char s2, char s3, char s4, int off1, int n1, double* out, int off3 = 0,
-               int n3 = -1) {
+               int n3 = -1, int tri = 0) {
     int N = d.nC + d.nA + d.nV;
     GettDesc g;
     g.nm = 2; g.nn = 2; g.nk = 1;
@@ -473,6 +474,7 @@ struct Exec {
     check_view("B (first pair)", nB - (A0 - B), {g.am[0], g.am[1], g.ak[0]}, {g.md[0], g.md[1], M});
     check_view("B (second pair)", nB - (B0 - B), {g.bn[0], g.bn[1], g.bk[0]}, {g.nd[0], g.nd[1], M});
     gett_prepare(g);   // may merge components: the checks above use the unmerged ones
+    g.tri = tri;
     gett(g, A0, B0, out, kRoleIntegrals);
   }
   double* jblock(const std::string& key) {
@@ -854,8 +856,8 @@ struct Exec {
   // bracketed by events and counted under the grouped role (items in M, workgroups in N of
   // the profile record); helper launches are not.
   void group_launch(double flops, DevOp launch, bool timed = false, int items = 0, int tiles = 0,
-                    double bytes = 0) {
-    Rec r{nullptr, nullptr, kRoleGrouped, flops, 0, 0, 0, 0, 0, 0, -2};
+                    double bytes = 0, int role = kRoleGrouped) {
+    Rec r{nullptr, nullptr, role, flops, 0, 0, 0, 0, 0, 0, -2};
     r.bytes = bytes;
     timed = timed && profile;
     r.M = items;
@@ -873,6 +875,121 @@ struct Exec {
     }
     gett_flops += flops;
     ++n_launch;
+  }
+
+  // Tile shape of a grouped item: the square 64 x 64 one unless it pads more than 1.8
+  // times the work of the thinnest fit (a 16 x 128 or 128 x 16 workgroup step costs about
+  // as long as a 64 x 64 one in these latency-bound launches but covers half the
+  // outputs); 128 x 128 when it pads at most 10 % more than the chosen small shape (four
+  // times the work per loaded element) and the k range is long (short ones ran slower
+  // that way).
+  static void group_shape(GroupItem& it) {
+    GettDesc& g = it.g;
+    long long bestw = -1, w0 = -1;
+    int best = 0;
+    for (int sh = 0; sh < kGroupShapes; ++sh) {
+      if (sh == kGroupBigShape) continue;
+      const long long tm = (g.M + kGroupTiles[sh][0] - 1) / kGroupTiles[sh][0];
+      const long long tn = (g.N + kGroupTiles[sh][1] - 1) / kGroupTiles[sh][1];
+      const long long w = tm * kGroupTiles[sh][0] * tn * kGroupTiles[sh][1];
+      if (sh == 0) w0 = w;
+      if (bestw < 0 || w < bestw) {
+        bestw = w;
+        best = sh;
+      }
+    }
+    if (w0 * 5 <= bestw * 9) {
+      best = 0;
+      bestw = w0;
+    }
+    it.shape = best;
+    it.tiles_m = (g.M + kGroupTiles[best][0] - 1) / kGroupTiles[best][0];
+    it.tiles_n = (g.N + kGroupTiles[best][1] - 1) / kGroupTiles[best][1];
+    if (g.M >= 128 && g.N >= 128 && g.steps >= 128) {
+      const long long tm = (g.M + 127) / 128, tn = (g.N + 127) / 128;
+      if (tm * tn * 128 * 128 * 10 <= bestw * 11) {
+        it.shape = kGroupBigShape;
+        it.tiles_m = (int)tm;
+        it.tiles_n = (int)tn;
+        gett_unpack_k(g);   // the 128 x 128 group tile walks plain k steps
+      }
+    }
+  }
+
+  // The Coulomb blocks (except (PP|PP)) of a call, in one grouped launch when they are all
+  // small (each at most 2^22 elements), else one launch each.
+  void prebuild_j(const std::vector<std::string>& keys) {
+    std::vector<std::string> todo;
+    bool small = grouped;
+    for (auto& k : keys)
+      if (!jblocks.count(k) && std::find(todo.begin(), todo.end(), k) == todo.end()) {
+        todo.push_back(k);
+        if ((long long)d.len(k[0]) * d.len(k[1]) * d.len(k[2]) * d.len(k[3]) > (1LL << 22)) small = false;
+      }
+    if (todo.empty()) return;
+    if (!small || todo.size() < 2) {
+      for (auto& k : todo) jblock(k);
+      return;
+    }
+    const int N = d.nC + d.nA + d.nV;
+    const long long nB = (long long)M * N * N;
+    std::vector<GroupItem> items;
+    std::vector<int> tile_item;
+    double fl = 0, bytes = 0;
+    int tiles = 0;
+    for (auto& k : todo) {
+      GettDesc g;
+      g.nm = 2; g.nn = 2; g.nk = 1;
+      g.md[0] = d.len(k[0]); g.md[1] = d.len(k[1]);
+      g.nd[0] = d.len(k[2]); g.nd[1] = d.len(k[3]);
+      g.kd[0] = M;
+      g.M = g.md[0] * g.md[1];
+      g.N = g.nd[0] * g.nd[1];
+      g.K = M;
+      g.am[0] = N; g.am[1] = 1; g.ak[0] = (long long)N * N;
+      g.bk[0] = (long long)N * N; g.bn[0] = N; g.bn[1] = 1;
+      g.cm[0] = (long long)g.md[1] * g.N; g.cm[1] = g.N;
+      g.cn[0] = g.nd[1]; g.cn[1] = 1;
+      g.alpha = 1.0; g.beta = 0;
+      const double* A0 = B + (long long)d.off(k[0]) * N + d.off(k[1]);
+      const double* B0 = B + (long long)d.off(k[2]) * N + d.off(k[3]);
+      check_view("B (first pair)", nB - (A0 - B), {g.am[0], g.am[1], g.ak[0]}, {g.md[0], g.md[1], M});
+      check_view("B (second pair)", nB - (B0 - B), {g.bn[0], g.bn[1], g.bk[0]}, {g.nd[0], g.nd[1], M});
+      gett_prepare(g);
+      double* out = pool.alloc((size_t)g.M * g.N);
+      jblocks[k] = out;
+      GroupItem it;
+      it.g = g;
+      it.A = A0;
+      it.B = B0;
+      it.C = out;
+      group_shape(it);
+      it.g.kchunk = it.g.steps;
+      it.g.part = nullptr;
+      it.splits = 1;
+      gett_magic(it.g);
+      if (it.shape == kGroupBigShape) {   // not with K = n_aux < 128 k steps; kept general
+        for (auto& kk : todo)
+          if (kk != k) jblocks.erase(kk);
+        jblocks.erase(k);
+        for (auto& kk : todo) jblock(kk);
+        return;
+      }
+      it.tile0 = tiles;
+      const int t = it.tiles_m * it.tiles_n;
+      for (int q = 0; q < t; ++q) tile_item.push_back((int)items.size());
+      tiles += t;
+      items.push_back(it);
+      fl += 2.0 * g.M * (double)g.N * g.K;
+      bytes += 8.0 * ((double)g.M * g.K + (double)g.K * g.N + (double)g.M * g.N);
+    }
+    GroupItem* d_items = upload(items);
+    int* d_map = upload(tile_item);
+    const int n = (int)items.size();
+    const bool lo = f32;
+    group_launch(fl, [d_items, d_map, n, tiles, lo](hipStream_t s) {
+      launch_gett_group(d_items, d_map, n, tiles, false, lo, s);
+    }, true, n, tiles, bytes, kRoleIntegrals);
   }
 
   // Sub-spaces of an output axis covered by a letter's space: bit 0 is the lower part of
@@ -1024,41 +1141,7 @@ struct Exec {
     for (size_t L = 0; L < lev.size(); ++L) {
       for (auto& it : lev[L]) {
         GettDesc& g = it.g;
-        // tile shape: the square 64 x 64 one unless it pads more than 1.8 times the work
-        // of the thinnest fit (a 16 x 128 or 128 x 16 workgroup step costs about as long
-        // as a 64 x 64 one in these latency-bound launches but covers half the outputs);
-        // 128 x 128 when it pads at most 10 % more than the chosen small shape (four
-        // times the work per loaded element) and the k range is long (short ones ran
-        // slower that way)
-        long long bestw = -1, w0 = -1;
-        int best = 0;
-        for (int sh = 0; sh < kGroupShapes; ++sh) {
-          if (sh == kGroupBigShape) continue;
-          const long long tm = (g.M + kGroupTiles[sh][0] - 1) / kGroupTiles[sh][0];
-          const long long tn = (g.N + kGroupTiles[sh][1] - 1) / kGroupTiles[sh][1];
-          const long long w = tm * kGroupTiles[sh][0] * tn * kGroupTiles[sh][1];
-          if (sh == 0) w0 = w;
-          if (bestw < 0 || w < bestw) {
-            bestw = w;
-            best = sh;
-          }
-        }
-        if (w0 * 5 <= bestw * 9) {
-          best = 0;
-          bestw = w0;
-        }
-        it.shape = best;
-        it.tiles_m = (g.M + kGroupTiles[best][0] - 1) / kGroupTiles[best][0];
-        it.tiles_n = (g.N + kGroupTiles[best][1] - 1) / kGroupTiles[best][1];
-        if (g.M >= 128 && g.N >= 128 && g.steps >= 128) {
-          const long long tm = (g.M + 127) / 128, tn = (g.N + 127) / 128;
-          if (tm * tn * 128 * 128 * 10 <= bestw * 11) {
-            it.shape = kGroupBigShape;
-            it.tiles_m = (int)tm;
-            it.tiles_n = (int)tn;
-            gett_unpack_k(g);   // the 128 x 128 group tile walks plain k steps
-          }
-        }
+        group_shape(it);
       }
       // k steps per workgroup slot of the level (four small workgroups per CU): chunks
       // shorter than that only add partial tiles to reduce
@@ -1658,11 +1741,18 @@ struct Exec {
       std::vector<long long> rs0, rs1;
       LadderPair *rows0 = nullptr, *rows1 = nullptr, *kt0 = nullptr, *kt1 = nullptr, *nt0 = nullptr,
                  *nt1 = nullptr;
-      std::vector<double*> tpk[3], tmk;   // packed amplitudes per distinct array (T-: tmk)
+      // packed amplitudes: the parts that multiply the antisymmetrised rows (same-spin
+      // amplitudes, then the antisymmetric parts of the opposite-spin ones) side by side in
+      // one [na_t * np][kp] operand, so one contraction serves them all; the symmetric
+      // parts [np1][kp1] each
+      std::vector<double*> tpk2;
+      double* Tanti = nullptr;
+      const long long na_t = (long long)pt[1].size() + (long long)pt[2].size();
+      const long long ldx = na_t * np;
       double *Va = nullptr, *Vs = nullptr, *Xa = nullptr, *Xs = nullptr;
       auto pack_t = [&](const double* Tt, const LadderPair* kt, long long k, const LadderPair* nt, long long n,
-                        int mode) {
-        double* tp = pool.alloc((size_t)std::max(1LL, k * n));
+                        int mode, double* into) {
+        double* tp = into ? into : pool.alloc((size_t)std::max(1LL, k * n));
         const int nPl = nP, nHl = nH, ki = (int)k, ni = (int)n;
         op([Tt, nPl, nHl, kt, ki, nt, ni, mode, tp](hipStream_t s) {
           launch_ladder_pack_t(Tt, nPl, nHl, kt, ki, nt, ni, mode, tp, s);
@@ -1696,17 +1786,18 @@ struct Exec {
           if (sym) mr1 = std::max(mr1, rs1[b1] - rs1[b0]);
         }
         Va = pool.alloc((size_t)std::max(1LL, mr0 * kp));
-        Xa = pool.alloc((size_t)std::max(1LL, mr0 * np));
+        Xa = pool.alloc((size_t)std::max(1LL, mr0 * ldx));
         if (sym) {
           Vs = pool.alloc((size_t)std::max(1LL, mr1 * kp1));
           Xs = pool.alloc((size_t)std::max(1LL, mr1 * np1));
         }
-        if (kp > 0 && np > 0)
-          for (const double* Tt : pt[1]) tpk[1].push_back(pack_t(Tt, kt0, kp, nt0, np, 0));
-        for (const double* Tt : pt[2]) {
-          tpk[2].push_back(pack_t(Tt, kt1, kp1, nt1, np1, 1));
-          tmk.push_back(kp > 0 && np > 0 ? pack_t(Tt, kt0, kp, nt0, np, 2) : nullptr);
+        if (kp > 0 && np > 0) {
+          Tanti = pool.alloc((size_t)std::max(1LL, ldx * kp));
+          long long j = 0;
+          for (const double* Tt : pt[1]) pack_t(Tt, kt0, kp, nt0, np, 0, Tanti + (j++) * np * kp);
+          for (const double* Tt : pt[2]) pack_t(Tt, kt0, kp, nt0, np, 2, Tanti + (j++) * np * kp);
         }
+        for (const double* Tt : pt[2]) tpk2.push_back(pack_t(Tt, kt1, kp1, nt1, np1, 1, nullptr));
       }
       // C[row][n] = sum_k A[row][k] B[n][k]
       auto pair_gemm = [&](const double* A, const double* Bm, double* C, long long rows, long long n,
@@ -1737,14 +1828,16 @@ struct Exec {
         int off1 = d.off(P0.space.at(bl)) - d.off('P') + b0;
         const int qoff = tri_build ? b0 : 0, nq = nP - qoff;
         double fb = gett_flops;
-        build_j('P', 'P', 'P', 'P', off1, n1, jb, qoff, nq);
+        // with rows q >= b0 only, the blocks of rows p and columns q < p stay unbuilt (the
+        // packs read q >= p)
+        build_j('P', 'P', 'P', 'P', off1, n1, jb, qoff, nq, tri_build ? nP : 0);
         if (pairs) {
           const long long r0 = rs0[b0], na = rs0[b0 + n1] - r0;
           const long long s0 = sym ? rs1[b0] : 0, ns = sym ? rs1[b0 + n1] - s0 : 0;
           const LadderPair* ra = rows0 + r0;
           const LadderPair* rsy = sym ? rows1 + s0 : nullptr;
-          const int nPl = nP, nHl = nH, nai = (int)na, nsi = (int)ns, kpi = (int)kp, kp1i = (int)kp1;
-          const int npi = (int)np, np1i = (int)np1, m0 = (int)r0;
+          const int nPl = nP, nHl = nH, nai = (int)na, nsi = (int)ns;
+          const int npi = (int)np, np1i = (int)np1, m0 = (int)r0, ldxi = (int)ldx;
           const bool anti_part = na > 0 && kp > 0 && np > 0;
           if (anti_part) {
             op([jb, nPl, b0, qoff, nq, ra, nai, Va](hipStream_t s) {
@@ -1759,27 +1852,29 @@ struct Exec {
             ++n_launch;
           }
           role_now = kRoleLadder;
+          // Xa[row][j np + n]: block j of every antisymmetric part in one contraction
+          if (anti_part) pair_gemm(Va, Tanti, Xa, na, ldx, kp);
           if (anti_part)
             for (size_t k = 0; k < pt[1].size(); ++k) {
-              pair_gemm(Va, tpk[1][k], Xa, na, np, kp);
+              const double* Xk = Xa + (long long)k * np;
               for (auto& tg : po[1][k]) {
                 double* Ot = tg.O;
                 const double c = tg.c;
-                op([Xa, nai, npi, ra, nt0, nPl, nHl, c, Ot](hipStream_t s) {
-                  launch_ladder_unpack_anti(Xa, nai, npi, ra, nt0, nPl, nHl, c, Ot, s);
+                op([Xk, nai, npi, ldxi, ra, nt0, nPl, nHl, c, Ot](hipStream_t s) {
+                  launch_ladder_unpack_anti(Xk, nai, npi, ldxi, ra, nt0, nPl, nHl, c, Ot, s);
                 });
                 ++n_launch;
               }
             }
           if (ns > 0)
             for (size_t k = 0; k < pt[2].size(); ++k) {
-              if (anti_part) pair_gemm(Va, tmk[k], Xa, na, np, kp);
-              pair_gemm(Vs, tpk[2][k], Xs, ns, np1, kp1);
+              const double* Xk = Xa + (long long)(pt[1].size() + k) * np;
+              pair_gemm(Vs, tpk2[k], Xs, ns, np1, kp1);
               for (auto& tg : po[2][k]) {
                 double* Ot = tg.O;
                 const double c = tg.c;
-                op([Xs, Xa, nsi, np1i, npi, m0, rsy, nt1, nPl, nHl, c, Ot](hipStream_t s) {
-                  launch_ladder_unpack_sym(Xs, Xa, nsi, np1i, npi, m0, rsy, nt1, nPl, nHl, c, Ot, s);
+                op([Xs, Xk, nsi, np1i, ldxi, m0, rsy, nt1, nPl, nHl, c, Ot](hipStream_t s) {
+                  launch_ladder_unpack_sym(Xs, Xk, nsi, np1i, ldxi, m0, rsy, nt1, nPl, nHl, c, Ot, s);
                 });
                 ++n_launch;
               }
@@ -1976,6 +2071,19 @@ static BodyOut body(Exec& X, OpLog& op, Pool& pool, const Shape& sh, const Input
     X.set_view("L3.bbb", L3 + off({1, 1, 1, 1, 1, 1}, st6), "AAAAAA", st6, s6 * n2 - off({1, 1, 1, 1, 1, 1}, st6));
   }
   // Coulomb blocks used by the first-order amplitudes
+  {
+    // every Coulomb block the tables read, except the batched (PP|PP) one
+    std::vector<std::string> keys{"HPHP"};
+    for (const char* u : {"C0", "W", "Z"})
+      for (const TProduct& P : table().at(u))
+        for (auto& f : P.f)
+          if (f.tensor == "J") {
+            std::string L, key;
+            Exec::canon_j(f.letters, P.space, L, key);
+            if (key != "PPPP") keys.push_back(key);
+          }
+    X.prebuild_j(keys);
+  }
   double* Jhphp = X.jblock("HPHP");
   HIPCHECK(hipEventRecord(ev[1], st));
 

@@ -35,6 +35,10 @@ struct GettDesc {
   // inner component (kpack * kd[nk - 1] <= kGettBK), for inner components of at most
   // kGettBK / 2 values; ksteps is then the steps per sweep of component nk - 2
   int kpack = 1;
+  // tri > 0: output tiles whose last column block (column / tri) lies before their first
+  // row block (row / tri) are skipped (left unwritten): blocks of a matrix needed only on and
+  // above its block diagonal.  Plain launches only.
+  int tri = 0;
   long long kchunk = 1;  // k steps per split (split-K), set by the launcher
   double* part = nullptr;  // split-K partial tiles [split][M][N], set by the launcher
   // division by md[c] (nd[c]) as a multiply and shift: q = (idx * mmag[c]) >> msh[c] for
@@ -44,6 +48,8 @@ struct GettDesc {
 };
 // merges and orders components, chooses the inner k component, and sets the magic numbers
 void gett_prepare(GettDesc& g);
+// fraction of the M x N outputs a plain launch computes (1 unless tri skips tiles)
+double gett_tile_fraction(const GettDesc& g);
 // back to plain k steps (for tiles without packed steps)
 void gett_unpack_k(GettDesc& g);
 // fraction of the k values of all steps that are real (not zero padding)
@@ -172,10 +178,11 @@ void launch_ladder_pack_v(const double* jb, int nP, int b0, int qoff, int nq, co
 // mode 2: (T[x][y][I][J] - T[y][x][I][J]) / 2
 void launch_ladder_pack_t(const double* T, int nP, int nH, const LadderPair* ktab, int kp,
                           const LadderPair* ntab, int np, int mode, double* Tp, hipStream_t st);
-// Antisymmetric fill, X = Xp[row][n] over strict pairs (p, q) = rowtab[row], (I, J) = ntab[n]:
+// Antisymmetric fill, X = Xp[row * ldx + n] over strict pairs (p, q) = rowtab[row],
+// (I, J) = ntab[n], n < np:
 // O[p][q][I][J] += c X, O[q][p][I][J] -= c X, O[p][q][J][I] -= c X, O[q][p][J][I] += c X.
 // O is [P][P][H][H]; the four elements of distinct (row, n) are distinct.
-void launch_ladder_unpack_anti(const double* Xp, int rows, int np, const LadderPair* rowtab,
+void launch_ladder_unpack_anti(const double* Xp, int rows, int np, int ldx, const LadderPair* rowtab,
                                const LadderPair* ntab, int nP, int nH, double c, double* O,
                                hipStream_t st);
 // Fill from a symmetric part S = Xs[row][n] over pairs p <= q, I <= J (tables rowtab, ntab)

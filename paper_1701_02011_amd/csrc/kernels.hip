@@ -364,6 +364,7 @@ __device__ __forceinline__ void gett_grid_tile(const GettDesc& g, const double* 
   const int L = xcd_tile(b, total);
   const int tm = L % gx, rest = L / gx;
   const int tn = rest % gy, kz = rest / gy;
+  if (g.tri > 0 && (tn * (32 * WN) + 32 * WN - 1) / g.tri < (tm * (32 * WM)) / g.tri) return;
   gett_tile<WM, WN, 2, kF32>(g, A, B, C, tm * (32 * WM), tn * (32 * WN), kz, lds);
 }
 
@@ -441,6 +442,17 @@ void gett_magic(GettDesc& g) {
 }
 
 static bool big_tiles(const GettDesc& g);
+
+double gett_tile_fraction(const GettDesc& g) {
+  if (g.tri <= 0 || g.M <= 0 || g.N <= 0) return 1.0;
+  const int b = big_tiles(g) ? 128 : 64;
+  double done = 0;
+  for (int tm = 0; tm < g.M; tm += b)
+    for (int tn = 0; tn < g.N; tn += b)
+      if ((tn + b - 1) / g.tri >= tm / g.tri)
+        done += (double)std::min(b, g.M - tm) * std::min(b, g.N - tn);
+  return done / ((double)g.M * g.N);
+}
 
 void gett_unpack_k(GettDesc& g) {
   if (g.kpack <= 1) return;
@@ -1007,7 +1019,7 @@ __global__ __launch_bounds__(256) void ladder_pack_t_kernel(const double* __rest
 }
 
 __global__ __launch_bounds__(256) void ladder_unpack_anti_kernel(const double* __restrict__ Xp, int rows, int np,
-                                                                 const LadderPair* __restrict__ rowtab,
+                                                                 int ldx, const LadderPair* __restrict__ rowtab,
                                                                  const LadderPair* __restrict__ ntab, int nP,
                                                                  int nH, double c, double* __restrict__ O) {
   const long long total = (long long)rows * np;
@@ -1015,7 +1027,7 @@ __global__ __launch_bounds__(256) void ladder_unpack_anti_kernel(const double* _
     const int row = (int)(e / np), n = (int)(e - (long long)row * np);
     const LadderPair pq = rowtab[row], ij = ntab[n];
     const long long p = pq.a, q = pq.b;
-    const double v = c * Xp[e];
+    const double v = c * Xp[(long long)row * ldx + n];
     O[((p * nP + q) * nH + ij.a) * nH + ij.b] += v;
     O[((q * nP + p) * nH + ij.a) * nH + ij.b] -= v;
     O[((p * nP + q) * nH + ij.b) * nH + ij.a] -= v;
@@ -1067,12 +1079,12 @@ void launch_ladder_pack_t(const double* T, int nP, int nH, const LadderPair* kta
                      ktab, kp, ntab, np, mode, Tp);
 }
 
-void launch_ladder_unpack_anti(const double* Xp, int rows, int np, const LadderPair* rowtab,
+void launch_ladder_unpack_anti(const double* Xp, int rows, int np, int ldx, const LadderPair* rowtab,
                                const LadderPair* ntab, int nP, int nH, double c, double* O,
                                hipStream_t st) {
   if (rows <= 0 || np <= 0) return;
   hipLaunchKernelGGL(ladder_unpack_anti_kernel, dim3(grid_for((long long)rows * np)), dim3(256), 0, st, Xp,
-                     rows, np, rowtab, ntab, nP, nH, c, O);
+                     rows, np, ldx, rowtab, ntab, nP, nH, c, O);
 }
 
 void launch_ladder_unpack_sym(const double* Xs, const double* Xa, int rows, int np, int npa, int m0,

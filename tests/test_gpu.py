@@ -41,7 +41,7 @@ GETT_CASES = ["gemm", "ragged", "strided", "multi", "vec", "accum", "splitk", "l
 @pytest.mark.parametrize("case", GETT_CASES)
 def test_gett_kernel(case, precision):
     say("gett case", case, "precision", precision)
-    rng = np.random.default_rng(hash(case) % 1000)
+    rng = np.random.default_rng(1000 + GETT_CASES.index(case))
     gett = lambda *a, **k: _lib.test_gett(*a, precision=precision, **k)
     if case == "gemm":
         M, N, K = 128, 64, 48
@@ -108,7 +108,10 @@ def test_gett_kernel(case, precision):
         ref = C - 0.5 * (A @ B)
     out = out.reshape(ref.shape)
     if precision == 0:
-        np.testing.assert_allclose(out, ref, rtol=1e-13, atol=1e-12)
+        # FP64 sums of K products in another order: |error| <= K eps max|A| max|B| per element
+        bound = 2 * (K + 16) * 2.0 ** -53 * np.abs(A).max() * np.abs(B).max() + 1e-14 * np.abs(ref).max()
+        err = np.abs(out - ref).max()
+        assert err <= bound, (err, bound)
         return
     # FP32 products: operands rounded to FP32 (relative 2^-24 each) and FP32 sums over at
     # most 1024 terms before FP64 accumulation; a worst-case bound per element
