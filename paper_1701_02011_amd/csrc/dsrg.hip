@@ -1040,6 +1040,7 @@ struct Exec {
     std::vector<DotItem> dots;
     std::vector<std::pair<long long, long long>> dfix;
     std::vector<double> dcoef;
+    std::vector<int> dslot;   // scalar slot of each dot (scalar_slots), 0 without slots
     struct GEnt {
       GatherEntry e;
       long long sfix;
@@ -1099,6 +1100,7 @@ struct Exec {
         double c = 0;
         for (auto& sc : P.s) c += sc.coef;
         dcoef.push_back(c);
+        dslot.push_back(scalar_slots.empty() ? 0 : scalar_slot(P));
       } else {
         const Opnd& r = ops[0];
         check_operand("gather source", r, lr);
@@ -1262,32 +1264,38 @@ struct Exec {
     }
 
     if (scalar_out) {
+      // one weighted sum per scalar slot over all dot partials (other slots' weights 0)
+      const std::vector<double*> outs_s = scalar_slots.empty() ? std::vector<double*>{scalar_out} : scalar_slots;
       int blocks = 0;
-      std::vector<double> bcoef;
+      std::vector<std::vector<double>> bcoef(outs_s.size());
       for (size_t i = 0; i < dots.size(); ++i) {
         dots[i].A = at(dfix[i].first, dots[i].A);
         dots[i].B = at(dfix[i].second, dots[i].B);
         dots[i].blk0 = blocks;
         blocks += dots[i].nblk;
-        for (int b = 0; b < dots[i].nblk; ++b) bcoef.push_back(dcoef[i]);
+        for (size_t k = 0; k < outs_s.size(); ++k)
+          for (int b = 0; b < dots[i].nblk; ++b) bcoef[k].push_back(dslot[i] == (int)k ? dcoef[i] : 0.0);
       }
       if (blocks == 0) {
-        op([scalar_out](hipStream_t s) { launch_fill(scalar_out, 1, 0.0, s); });
-        ++n_launch;
+        for (double* so : outs_s) {
+          op([so](hipStream_t s) { launch_fill(so, 1, 0.0, s); });
+          ++n_launch;
+        }
       } else {
         double* part = pool.alloc((size_t)blocks);
         DotItem* d_dots = upload(dots);
-        double* d_coef = upload(bcoef);
         double fl = 0;
         for (auto& di : dots) fl += 2.0 * di.d.K;
         const int nd = (int)dots.size();
         group_launch(fl, [d_dots, nd, blocks, part](hipStream_t s) {
           launch_dot_group(d_dots, nd, blocks, part, s);
         });
-        op([blocks, part, d_coef, scalar_out](hipStream_t s) {
-          launch_weighted_sum(blocks, part, d_coef, scalar_out, s);
-        });
-        ++n_launch;
+        for (size_t k = 0; k < outs_s.size(); ++k) {
+          double* d_coef = upload(bcoef[k]);
+          double* so = outs_s[k];
+          op([blocks, part, d_coef, so](hipStream_t s) { launch_weighted_sum(blocks, part, d_coef, so, s); });
+          ++n_launch;
+        }
       }
     } else if (!dots.empty()) {
       throw Error(DSRG_E_HIP, "internal: scalar products in a tensor use");
@@ -1541,6 +1549,36 @@ struct Exec {
       }
     }
     return out;
+  }
+
+  // Several scalar uses in one grouped run: each product's scalar scatter names its slot
+  // in its block ("0", "1", ...), scalar_slots holds the outputs.  Empty: one scalar.
+  std::vector<double*> scalar_slots;
+  static int scalar_slot(const TProduct& P) {
+    return (P.s.empty() || P.s[0].block.empty()) ? 0 : std::atoi(P.s[0].block.c_str());
+  }
+  // The scalar uses U[k] into out[k] as one grouped run; false (nothing run) when their
+  // temporaries do not fit the grouping budget together.
+  bool run_scalars_fused(const std::vector<Use>& uses, const std::vector<double*>& out) {
+    if (!grouped || uses.size() != out.size() || uses.empty()) return false;
+    Use all;
+    for (size_t k = 0; k < uses.size(); ++k)
+      for (const TProduct& P : merged_use(uses[k])) {
+        TProduct Q = P;
+        for (auto& sc : Q.s) sc.block = std::to_string(k);
+        all.push_back(Q);
+      }
+    std::vector<std::pair<int, const TProduct*>> plain;
+    for (size_t i = 0; i < all.size(); ++i) {
+      if (is_pppp(all[i], nullptr)) return false;
+      plain.push_back({(int)i, &all[i]});
+    }
+    std::map<std::string, TensorRef> none;
+    scalar_slots = out;
+    const bool ok = run_grouped(plain, none, out[0]);
+    scalar_slots.clear();
+    if (ok) ++grouped_uses;
+    return ok;
   }
 
   // Run a use of the table into tensor outputs, or (scalar uses) into *scalar_out.
@@ -2187,7 +2225,31 @@ static BodyOut body(Exec& X, OpLog& op, Pool& pool, const Shape& sh, const Input
     for (int sidx = 0; sidx < 2; ++sidx)
       launch_second_order_h1(ad, W1 + sidx * n1, Z1 + sidx * n1, S2 + sidx * n1, H1 + sidx * n1, s);
   });
-  // E(3)_a = <[H~(1), T(2)]>
+  // E(3)_a = <[H~(1), T(2)]> and E(3)_b = <[H~(2)_{1,2}, T(1)]>: without the pair
+  // decomposition both scalars run as one grouped use when their temporaries fit (the
+  // second-order tensors under their own names), else one after the other
+  if (!want_pairs) {
+    X.set("U1.a", U1, "PH"); X.set("U1.b", U1 + n1, "PH");
+    X.set("U2.aa", U2, "PPHH", 1); X.set("U2.ab", U2 + n4, "PPHH"); X.set("U2.bb", U2 + 2 * n4, "PPHH", 1);
+    X.set("H1.a", H1, "PH"); X.set("H1.b", H1 + n1, "PH");
+    X.set("H2.aa", H2, "PPHH"); X.set("H2.ab", H2 + n4, "PPHH"); X.set("H2.bb", H2 + 2 * n4, "PPHH");
+    auto renamed = [&](const char* from1, const char* to1, const char* from2, const char* to2) {
+      Use u = C0;
+      for (auto& P : u)
+        for (auto& f : P.f) {
+          if (f.tensor == from1) f.tensor = to1;
+          else if (f.tensor == from2) f.tensor = to2;
+        }
+      return u;
+    };
+    X.use_id = 0;
+    if (X.run_scalars_fused({renamed("T1", "U1", "T2", "U2"), renamed("E1", "H1", "E2", "H2")},
+                            {energies + 1, energies + 2})) {
+      HIPCHECK(hipEventRecord(ev[6], st));
+      bo.W1 = W1; bo.W2 = W2; bo.Z1 = Z1; bo.Z2 = Z2; bo.U1 = U1; bo.U2 = U2;
+      return bo;
+    }
+  }
   X.set("T1.a", U1, "PH"); X.set("T1.b", U1 + n1, "PH");
   X.set("T2.aa", U2, "PPHH", 1); X.set("T2.ab", U2 + n4, "PPHH"); X.set("T2.bb", U2 + 2 * n4, "PPHH", 1);
   scalar(energies + 1);
