@@ -112,8 +112,9 @@ typedef struct {
   double e3_b;            /* <[H~(2)_{1,2}, T(1)]> */
   double t_seconds[8];    /* device time: [0] densities+integrals, [1] first order, [2] E(2),
                              [3] [V,A] (ladders, rings), [4] [Y,A], [5] second order + E(3),
-                             [6] unused, [7] whole pipeline.  A call that replays a plan
-                             fills [7] only. */
+                             [6] unused, [7] whole pipeline.  Small problems run E(2), [V,A]
+                             and [Y,A] as one grouped sequence: its time is in [2] and [3],
+                             [4] are 0.  A call that replays a plan fills [7] only. */
   double gett_flops;      /* floating-point operations issued by the contraction kernels */
   double ladder_flops;    /* of which the (PP|PP) particle-particle ladder (Sec. III) */
   double ladder_seconds;  /* with DSRG_F_PROFILE: device time of the (PP|PP) ladder groups */

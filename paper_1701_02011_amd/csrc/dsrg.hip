@@ -1557,30 +1557,6 @@ struct Exec {
   static int scalar_slot(const TProduct& P) {
     return (P.s.empty() || P.s[0].block.empty()) ? 0 : std::atoi(P.s[0].block.c_str());
   }
-  // The scalar uses U[k] into out[k] as one grouped run; false (nothing run) when their
-  // temporaries do not fit the grouping budget together.
-  bool run_scalars_fused(const std::vector<Use>& uses, const std::vector<double*>& out) {
-    if (!grouped || uses.size() != out.size() || uses.empty()) return false;
-    Use all;
-    for (size_t k = 0; k < uses.size(); ++k)
-      for (const TProduct& P : merged_use(uses[k])) {
-        TProduct Q = P;
-        for (auto& sc : Q.s) sc.block = std::to_string(k);
-        all.push_back(Q);
-      }
-    std::vector<std::pair<int, const TProduct*>> plain;
-    for (size_t i = 0; i < all.size(); ++i) {
-      if (is_pppp(all[i], nullptr)) return false;
-      plain.push_back({(int)i, &all[i]});
-    }
-    std::map<std::string, TensorRef> none;
-    scalar_slots = out;
-    const bool ok = run_grouped(plain, none, out[0]);
-    scalar_slots.clear();
-    if (ok) ++grouped_uses;
-    return ok;
-  }
-
   // Run a use of the table into tensor outputs, or (scalar uses) into *scalar_out.
   int use_id = 0;
   bool f32 = false;   // FP32 products in every contraction
@@ -1594,11 +1570,20 @@ struct Exec {
   // the end of the use (A: the same four images): a quarter of the scatter (gather)
   // traffic of those products.
   bool collapse_images = true;
-  void run_use(const Use& U0, std::map<std::string, TensorRef>& outs0, double* scalar_out) {
-    Use U = merged_use(U0);
-    std::map<std::string, TensorRef> outs = outs0;
-    std::vector<std::string> pre_names;
-    if (collapse_images && !scalar_out) {
+  struct PreparedUse {
+    Use U;
+    std::map<std::string, TensorRef> outs;   // the use's outputs plus its pre-images
+    std::vector<std::string> pre;            // names of the pre-images
+  };
+  // products merged, antisymmetriser images collapsed (pre-images allocated and zeroed)
+  PreparedUse prepare_use(const Use& U0, const std::map<std::string, TensorRef>& outs0, bool scalar) {
+    PreparedUse pu;
+    pu.U = merged_use(U0);
+    pu.outs = outs0;
+    Use& U = pu.U;
+    std::map<std::string, TensorRef>& outs = pu.outs;
+    std::vector<std::string>& pre_names = pu.pre;
+    if (collapse_images && !scalar) {
       const long long nP = d.len('P'), nH = d.len('H');
       const std::vector<long long> dense{nP * nH * nH, nH * nH, nH, 1};
       auto swap01 = [](std::string o) { std::swap(o[0], o[1]); return o; };
@@ -1654,14 +1639,79 @@ struct Exec {
         P.s = kept;
       }
     }
-    run_use_body(U, outs, scalar_out);
-    for (auto& pn : pre_names) {
-      const double* X = outs.at(pn).p;
+    return pu;
+  }
+  // the pre-images added into their outputs through the pair antisymmetriser
+  void finish_use(const PreparedUse& pu, const std::map<std::string, TensorRef>& outs0) {
+    for (auto& pn : pu.pre) {
+      const double* X = pu.outs.at(pn).p;
       double* O = outs0.at(pn.substr(0, pn.size() - 1)).p;
       const int nPl = d.len('P'), nHl = d.len('H');
       op([X, O, nPl, nHl](hipStream_t s) { launch_antisym_add(X, O, nPl, nHl, s); });
       ++n_launch;
     }
+  }
+  void run_use(const Use& U0, std::map<std::string, TensorRef>& outs0, double* scalar_out) {
+    PreparedUse pu = prepare_use(U0, outs0, scalar_out != nullptr);
+    run_use_body(pu.U, pu.outs, scalar_out);
+    finish_use(pu, outs0);
+  }
+
+  // Several uses whose products are independent in one grouped run of their plain
+  // products (their contractions of equal depth share launches); each use's (PP|PP)
+  // products and pre-images follow.  scalars[k] is the output of a scalar use (its outs
+  // empty).  False, with nothing run but pre-image fills, when the temporaries do not fit
+  // the grouping budget together.
+  bool run_fused(const std::vector<const Use*>& uses, const std::vector<std::map<std::string, TensorRef>*>& outs,
+                 const std::vector<double*>& scalars) {
+    if (!grouped || uses.size() != outs.size() || uses.size() != scalars.size()) return false;
+    std::vector<PreparedUse> pus;
+    for (size_t k = 0; k < uses.size(); ++k) pus.push_back(prepare_use(*uses[k], *outs[k], scalars[k] != nullptr));
+    Use all;
+    std::vector<Use> pp(uses.size());
+    std::map<std::string, TensorRef> all_outs;
+    std::vector<double*> slots;
+    for (size_t k = 0; k < pus.size(); ++k) {
+      const std::string tag = "#" + std::to_string(k);
+      int slot = -1;
+      if (scalars[k]) {
+        slot = (int)slots.size();
+        slots.push_back(scalars[k]);
+      }
+      for (const TProduct& P : pus[k].U) {
+        if (is_pppp(P, nullptr)) {
+          if (scalars[k]) return false;
+          pp[k].push_back(P);
+          continue;
+        }
+        TProduct Q = P;
+        for (auto& sc : Q.s) {
+          if (Q.res.empty()) {
+            if (slot < 0) return false;
+            sc.block = std::to_string(slot);
+          } else {
+            sc.tensor += tag;
+          }
+        }
+        all.push_back(Q);
+      }
+      for (auto& kv : pus[k].outs) {
+        const size_t dot = kv.first.find('.');
+        all_outs[kv.first.substr(0, dot) + tag + kv.first.substr(dot)] = kv.second;
+      }
+    }
+    std::vector<std::pair<int, const TProduct*>> plain;
+    for (size_t i = 0; i < all.size(); ++i) plain.push_back({(int)i, &all[i]});
+    scalar_slots = slots;
+    const bool ok = run_grouped(plain, all_outs, slots.empty() ? nullptr : slots[0]);
+    scalar_slots.clear();
+    if (!ok) return false;
+    ++grouped_uses;
+    for (size_t k = 0; k < pus.size(); ++k) {
+      if (!pp[k].empty()) run_use_body(pp[k], pus[k].outs, nullptr);
+      finish_use(pus[k], *outs[k]);
+    }
+    return true;
   }
 
   void run_use_body(const Use& U, std::map<std::string, TensorRef>& outs, double* scalar_out) {
@@ -1682,7 +1732,9 @@ struct Exec {
       }
       plain.push_back({pidx, &P});
     }
-    if (grouped && run_grouped(plain, outs, scalar_out)) {
+    if (plain.empty()) {
+      // only (PP|PP) products
+    } else if (grouped && run_grouped(plain, outs, scalar_out)) {
       ++grouped_uses;
     } else if (grouped) {
       // too large to group as a whole: the small products run grouped in waves whose
@@ -2165,20 +2217,22 @@ static BodyOut body(Exec& X, OpLog& op, Pool& pool, const Shape& sh, const Input
     X.use_id = 0;
     X.run_use(C0, none, outp);
   };
-  // step a3: E(2) = <[H~(1), T(1)]>
-  scalar(energies + 0);
-  HIPCHECK(hipEventRecord(ev[3], st));
   if (!sh.pt3) {
-    for (int k = 4; k < 7; ++k) HIPCHECK(hipEventRecord(ev[k], st));
+    // step a3: E(2) = <[H~(1), T(1)]>
+    scalar(energies + 0);
+    for (int k = 3; k < 7; ++k) HIPCHECK(hipEventRecord(ev[k], st));
     return bo;
   }
-
-  // steps a4-a5: W = [V, A(1)]_{1,2}, excitation block
+  // W = [V, A(1)]_{1,2} and Z = [Y, A(1)]_{1,2}, excitation blocks
   double* W1 = pool.alloc(2 * n1);
   double* W2 = pool.alloc(3 * n4);
-  op([W1, W2, n1, n4](hipStream_t s) {
+  double* Z1 = pool.alloc(2 * n1);
+  double* Z2 = pool.alloc(3 * n4);
+  op([W1, W2, Z1, Z2, n1, n4](hipStream_t s) {
     launch_fill(W1, 2 * n1, 0.0, s);
     launch_fill(W2, 3 * n4, 0.0, s);
+    launch_fill(Z1, 2 * n1, 0.0, s);
+    launch_fill(Z2, 3 * n4, 0.0, s);
   });
   auto bind_out = [&](std::map<std::string, TensorRef>& o, double* p1, double* p2) {
     auto mk = [&](double* p, const char* ax) {
@@ -2192,23 +2246,27 @@ static BodyOut body(Exec& X, OpLog& op, Pool& pool, const Shape& sh, const Input
     o["O1.a"] = mk(p1, "PH"); o["O1.b"] = mk(p1 + n1, "PH");
     o["O2.aa"] = mk(p2, "PPHH"); o["O2.ab"] = mk(p2 + n4, "PPHH"); o["O2.bb"] = mk(p2 + 2 * n4, "PPHH");
   };
-  std::map<std::string, TensorRef> wout;
+  std::map<std::string, TensorRef> wout, zout;
   bind_out(wout, W1, W2);
-  X.use_id = 1;
-  X.run_use(T.at("W"), wout, nullptr);
-  HIPCHECK(hipEventRecord(ev[4], st));
-  // step a6: Z = [Y, A(1)]_{1,2}
-  double* Z1 = pool.alloc(2 * n1);
-  double* Z2 = pool.alloc(3 * n4);
-  op([Z1, Z2, n1, n4](hipStream_t s) {
-    launch_fill(Z1, 2 * n1, 0.0, s);
-    launch_fill(Z2, 3 * n4, 0.0, s);
-  });
-  std::map<std::string, TensorRef> zout;
   bind_out(zout, Z1, Z2);
-  X.use_id = 2;
-  X.run_use(T.at("Z"), zout, nullptr);
-  HIPCHECK(hipEventRecord(ev[5], st));
+  // E(2), W and Z read only first-order quantities: for small problems (a doubles block of
+  // at most 2^22 elements) one grouped run covers all three, with the stage time reported
+  // under E(2); else step a3, steps a4-a5 and step a6 in turn
+  std::map<std::string, TensorRef> none_e;
+  X.use_id = 0;
+  if ((long long)n4 <= (1LL << 22) &&
+      X.run_fused({&C0, &T.at("W"), &T.at("Z")}, {&none_e, &wout, &zout}, {energies + 0, nullptr, nullptr})) {
+    for (int k = 3; k < 6; ++k) HIPCHECK(hipEventRecord(ev[k], st));
+  } else {
+    scalar(energies + 0);
+    HIPCHECK(hipEventRecord(ev[3], st));
+    X.use_id = 1;
+    X.run_use(T.at("W"), wout, nullptr);
+    HIPCHECK(hipEventRecord(ev[4], st));
+    X.use_id = 2;
+    X.run_use(T.at("Z"), zout, nullptr);
+    HIPCHECK(hipEventRecord(ev[5], st));
+  }
   // second-order amplitudes and H~(2)_{1,2}
   double* U2 = pool.alloc(3 * n4);
   double* H2 = pool.alloc(3 * n4);
@@ -2243,8 +2301,9 @@ static BodyOut body(Exec& X, OpLog& op, Pool& pool, const Shape& sh, const Input
       return u;
     };
     X.use_id = 0;
-    if (X.run_scalars_fused({renamed("T1", "U1", "T2", "U2"), renamed("E1", "H1", "E2", "H2")},
-                            {energies + 1, energies + 2})) {
+    const Use ua = renamed("T1", "U1", "T2", "U2"), ub = renamed("E1", "H1", "E2", "H2");
+    std::map<std::string, TensorRef> none_a, none_b;
+    if (X.run_fused({&ua, &ub}, {&none_a, &none_b}, {energies + 1, energies + 2})) {
       HIPCHECK(hipEventRecord(ev[6], st));
       bo.W1 = W1; bo.W2 = W2; bo.Z1 = Z1; bo.Z2 = Z2; bo.U1 = U1; bo.U2 = U2;
       return bo;
