@@ -988,7 +988,7 @@ struct Exec {
     const int n = (int)items.size();
     const bool lo = f32;
     group_launch(fl, [d_items, d_map, n, tiles, lo](hipStream_t s) {
-      launch_gett_group(d_items, d_map, n, tiles, false, lo, s);
+      launch_gett_group(d_items, d_map, n, tiles, false, lo, s, true);
     }, true, n, tiles, bytes, kRoleIntegrals);
   }
 

@@ -106,8 +106,9 @@ struct GroupItem {
   int tile0 = 0;          // first workgroup of this item
 };
 // tile_item[b] (b < tiles): index of the item that owns workgroup tile b of the launch.
+// (coulomb: the same launch under the symbol coulomb_group_kernel, small tiles only)
 void launch_gett_group(const GroupItem* items, const int* tile_item, int n, int tiles, bool big,
-                       bool f32, hipStream_t st);
+                       bool f32, hipStream_t st, bool coulomb = false);
 // Block b of the split-K reduction sums the partial tiles of elements [e0, e0 + 256) of
 // item `item` (an index into the launch's items).
 struct ReduceBlock {

@@ -626,8 +626,7 @@ void launch_gett(const GettDesc& g0, const double* A, const double* B, double* C
 // depend on scheduling.
 // ---------------------------------------------------------------------------
 template <bool kF32>
-__global__ __launch_bounds__(256) void gett_group_kernel(const GroupItem* __restrict__ items,
-                                                         const int* __restrict__ tile_item) {
+__device__ __forceinline__ void group_tile(const GroupItem* __restrict__ items, const int* __restrict__ tile_item) {
   using T = typename Mfma<kF32>::T;
   using GroupLds0 = TileLds<2, 2, 2, T>;
   using GroupLds1 = TileLds<1, 2, 1, T>;
@@ -658,6 +657,19 @@ __global__ __launch_bounds__(256) void gett_group_kernel(const GroupItem* __rest
     default:
       gett_tile<2, 2, 2, kF32>(it.g, it.A, it.B, it.C, tm * GroupLds0::BM, tn * GroupLds0::BN, kz, lds.t0);
   }
+}
+
+template <bool kF32>
+__global__ __launch_bounds__(256) void gett_group_kernel(const GroupItem* __restrict__ items,
+                                                         const int* __restrict__ tile_item) {
+  group_tile<kF32>(items, tile_item);
+}
+
+// the same for the Coulomb blocks of a call built together (a symbol of its own in profiles)
+template <bool kF32>
+__global__ __launch_bounds__(256) void coulomb_group_kernel(const GroupItem* __restrict__ items,
+                                                            const int* __restrict__ tile_item) {
+  group_tile<kF32>(items, tile_item);
 }
 
 // items of the big shape (128 x 128)
@@ -708,9 +720,16 @@ __global__ __launch_bounds__(256) void group_reduce_kernel(const GroupItem* __re
 }
 
 void launch_gett_group(const GroupItem* items, const int* tile_item, int n, int tiles, bool big,
-                       bool f32, hipStream_t st) {
+                       bool f32, hipStream_t st, bool coulomb) {
   if (n <= 0 || tiles <= 0) return;
   const dim3 grid((unsigned)tiles), block(256);
+  if (coulomb && !big) {
+    if (f32)
+      hipLaunchKernelGGL(coulomb_group_kernel<true>, grid, block, 0, st, items, tile_item);
+    else
+      hipLaunchKernelGGL(coulomb_group_kernel<false>, grid, block, 0, st, items, tile_item);
+    return;
+  }
   if (big && f32)
     hipLaunchKernelGGL(gett_group_big_kernel<true>, grid, block, 0, st, items, tile_item);
   else if (big)
