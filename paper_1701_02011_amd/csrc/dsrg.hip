@@ -1092,6 +1092,7 @@ struct Exec {
         check_operand("dot B", ops[1], lr);
         DotItem di;
         di.d = dot_desc(ops[0], ops[1], lr);
+        div_magic(di.d.kd, di.d.nk, di.d.dm);
         di.A = ops[0].p;
         di.B = ops[1].p;
         di.nblk = (int)std::max<long long>(1, std::min<long long>(64, (di.d.K + 4095) / 4096));

@@ -58,11 +58,20 @@ inline double gett_k_fill(const GettDesc& g) { return (double)g.K / ((double)g.s
 void gett_magic(GettDesc& g);
 
 // sum_k A[k] B[k] over a strided multi-index k (deterministic two-pass reduction).
+// Divisions of a multi-index decode as multiply and shift (see gett_magic), valid for
+// indices below 2^31; set on the host (div_magic) before a launch.
+struct DivMagic {
+  unsigned mag[2 * kMaxComp] = {};
+  int sh[2 * kMaxComp] = {};
+};
+void div_magic(const int* d, int n, DivMagic& m);
+
 struct DotDesc {
   long long K = 0;
   int nk = 0;
   int kd[2 * kMaxComp] = {};
   long long as[2 * kMaxComp] = {}, bs[2 * kMaxComp] = {};
+  DivMagic dm;   // of kd (set by the launchers, or by the caller for grouped dots)
 };
 
 // out[o] += coef * src[s] over a strided multi-index (rank <= 6).
@@ -72,6 +81,7 @@ struct ScatterDesc {
   int d[kMaxComp] = {};
   long long ss[kMaxComp] = {}, so[kMaxComp] = {};
   double coef = 1.0;
+  DivMagic dm;   // of d (set by launch_scatter)
 };
 
 // Launch roles (same kernel, distinct symbols): contraction-table products, the (PP|PP)
@@ -157,6 +167,7 @@ struct PackDesc {
   int rank = 0;
   int d[2 * kMaxComp] = {};
   long long ss[2 * kMaxComp] = {};
+  DivMagic dm;   // of d (set by launch_pack)
 };
 void launch_pack(const PackDesc& d, const double* src, double* dst, hipStream_t st);
 

@@ -35,6 +35,35 @@ __device__ __forceinline__ long long decode_fast(int idx, int n, const int* d, c
   return off;
 }
 
+__device__ __forceinline__ void decode2(long long idx, int n, const int* d, const long long* sa,
+                                        const long long* sb, long long& oa, long long& ob) {
+  oa = 0;
+  ob = 0;
+  for (int c = n - 1; c >= 0; --c) {
+    long long q = idx / d[c];
+    long long r = idx - q * d[c];
+    oa += r * sa[c];
+    ob += r * sb[c];
+    idx = q;
+  }
+}
+
+// the same for idx < 2^31 with the divisions as multiply and shift
+__device__ __forceinline__ void decode2_fast(unsigned idx, int n, const int* d, const DivMagic& m,
+                                             const long long* sa, const long long* sb, long long& oa,
+                                             long long& ob) {
+  oa = 0;
+  ob = 0;
+  for (int c = n - 1; c >= 0; --c) {
+    const unsigned q = (unsigned)(((unsigned long long)idx * m.mag[c]) >> m.sh[c]);
+    const long long r = (long long)(idx - q * (unsigned)d[c]);
+    oa += r * sa[c];
+    if (sb) ob += r * sb[c];
+    idx = q;
+  }
+}
+
+
 
 // ---------------------------------------------------------------------------
 // GETT: a workgroup of 256 threads (4 waves, 2x2) computes a BM x BN output tile; each
@@ -762,16 +791,11 @@ __global__ __launch_bounds__(256) void dot_group_kernel(const DotItem* __restric
   const DotItem& it = items[lo];
   const int j = b - it.blk0;
   double sum = 0.0;
+  const bool fast = it.d.K < (1LL << 31);
   for (long long i = j * 256LL + threadIdx.x; i < it.d.K; i += 256LL * it.nblk) {
-    long long oa = 0, ob = 0;
-    long long idx = i;
-    for (int c = it.d.nk - 1; c >= 0; --c) {
-      long long q = idx / it.d.kd[c];
-      long long r = idx - q * it.d.kd[c];
-      oa += r * it.d.as[c];
-      ob += r * it.d.bs[c];
-      idx = q;
-    }
+    long long oa, ob;
+    if (fast) decode2_fast((unsigned)i, it.d.nk, it.d.kd, it.d.dm, it.d.as, it.d.bs, oa, ob);
+    else decode2(i, it.d.nk, it.d.kd, it.d.as, it.d.bs, oa, ob);
     sum += it.A[oa] * it.B[ob];
   }
   red[threadIdx.x] = sum;
@@ -870,27 +894,16 @@ void launch_gather(const GatherDesc& g0, const GatherEntry* entries, double* out
 constexpr int kDotBlocks = 512;
 int dot_partials() { return kDotBlocks; }
 
-__device__ __forceinline__ void decode2(long long idx, int n, const int* d, const long long* sa,
-                                        const long long* sb, long long& oa, long long& ob) {
-  oa = 0;
-  ob = 0;
-  for (int c = n - 1; c >= 0; --c) {
-    long long q = idx / d[c];
-    long long r = idx - q * d[c];
-    oa += r * sa[c];
-    ob += r * sb[c];
-    idx = q;
-  }
-}
-
 __global__ __launch_bounds__(256) void dot_kernel(DotDesc d, const double* __restrict__ A,
                                                   const double* __restrict__ B,
                                                   double* __restrict__ partial) {
   __shared__ double red[256];
   double sum = 0.0;
+  const bool fast = d.K < (1LL << 31);
   for (long long i = blockIdx.x * 256LL + threadIdx.x; i < d.K; i += 256LL * gridDim.x) {
     long long oa, ob;
-    decode2(i, d.nk, d.kd, d.as, d.bs, oa, ob);
+    if (fast) decode2_fast((unsigned)i, d.nk, d.kd, d.dm, d.as, d.bs, oa, ob);
+    else decode2(i, d.nk, d.kd, d.as, d.bs, oa, ob);
     sum += A[oa] * B[ob];
   }
   red[threadIdx.x] = sum;
@@ -916,8 +929,20 @@ __global__ __launch_bounds__(256) void sum_partials_kernel(const double* __restr
   if (threadIdx.x == 0) out[0] = red[0];
 }
 
-void launch_dot(const DotDesc& d, const double* A, const double* B, double* partial, double* out,
+void div_magic(const int* d, int n, DivMagic& m) {
+  for (int c = 0; c < 2 * kMaxComp; ++c) {
+    unsigned mg;
+    int sh;
+    magic_of(c < n ? std::max(1, d[c]) : 1, mg, sh);
+    m.mag[c] = mg;
+    m.sh[c] = sh;
+  }
+}
+
+void launch_dot(const DotDesc& d0, const double* A, const double* B, double* partial, double* out,
                 hipStream_t st) {
+  DotDesc d = d0;
+  div_magic(d.kd, d.nk, d.dm);
   hipLaunchKernelGGL(dot_kernel, dim3(kDotBlocks), dim3(256), 0, st, d, A, B, partial);
   hipLaunchKernelGGL(sum_partials_kernel, dim3(1), dim3(256), 0, st, partial, kDotBlocks, out);
 }
@@ -927,19 +952,27 @@ void launch_dot(const DotDesc& d, const double* A, const double* B, double* part
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void pack_kernel(PackDesc d, const double* __restrict__ src,
                                                    double* __restrict__ dst) {
+  const bool fast = d.n < (1LL << 31);
   for (long long e = blockIdx.x * 256LL + threadIdx.x; e < d.n; e += 256LL * gridDim.x) {
-    long long idx = e, off = 0;
-    for (int c = d.rank - 1; c >= 0; --c) {
-      const long long q = idx / d.d[c];
-      off += (idx - q * d.d[c]) * d.ss[c];
-      idx = q;
+    long long off = 0, unused;
+    if (fast) {
+      decode2_fast((unsigned)e, d.rank, d.d, d.dm, d.ss, nullptr, off, unused);
+    } else {
+      long long idx = e;
+      for (int c = d.rank - 1; c >= 0; --c) {
+        const long long q = idx / d.d[c];
+        off += (idx - q * d.d[c]) * d.ss[c];
+        idx = q;
+      }
     }
     dst[e] = src[off];
   }
 }
 
-void launch_pack(const PackDesc& d, const double* src, double* dst, hipStream_t st) {
-  if (d.n <= 0) return;
+void launch_pack(const PackDesc& d0, const double* src, double* dst, hipStream_t st) {
+  if (d0.n <= 0) return;
+  PackDesc d = d0;
+  div_magic(d.d, d.rank, d.dm);
   const long long blocks = std::min<long long>((d.n + 255) / 256, 16384);
   hipLaunchKernelGGL(pack_kernel, dim3((unsigned)blocks), dim3(256), 0, st, d, src, dst);
 }
@@ -1119,15 +1152,19 @@ void launch_ladder_unpack_sym(const double* Xs, const double* Xa, int rows, int 
 // ---------------------------------------------------------------------------
 __global__ __launch_bounds__(256) void scatter_kernel(ScatterDesc d, const double* __restrict__ src,
                                                       double* __restrict__ out) {
+  const bool fast = d.n < (1LL << 31);
   for (long long i = blockIdx.x * 256LL + threadIdx.x; i < d.n; i += 256LL * gridDim.x) {
     long long os, oo;
-    decode2(i, d.rank, d.d, d.ss, d.so, os, oo);
+    if (fast) decode2_fast((unsigned)i, d.rank, d.d, d.dm, d.ss, d.so, os, oo);
+    else decode2(i, d.rank, d.d, d.ss, d.so, os, oo);
     out[oo] += d.coef * src[os];
   }
 }
 
-void launch_scatter(const ScatterDesc& d, const double* src, double* out, hipStream_t st) {
-  if (d.n <= 0) return;
+void launch_scatter(const ScatterDesc& d0, const double* src, double* out, hipStream_t st) {
+  if (d0.n <= 0) return;
+  ScatterDesc d = d0;
+  div_magic(d.d, d.rank, d.dm);
   long long blocks = (d.n + 255) / 256;
   if (blocks > 8192) blocks = 8192;
   hipLaunchKernelGGL(scatter_kernel, dim3((unsigned)blocks), dim3(256), 0, st, d, src, out);
