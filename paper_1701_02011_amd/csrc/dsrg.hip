@@ -2070,8 +2070,10 @@ static Inputs alloc_inputs(Pool& pool, const Shape& sh) {
 // Copy the inputs into the device buffers (host or device sources) and s from s_host,
 // which must stay valid until the stream is synchronised.  Device inputs are checked for
 // non-finite values on the copies (one synchronisation).
+// With defer_bad (pinned host memory) the non-finite count of device inputs is only copied
+// there, and the caller checks it after its own synchronisation (no wait here).
 static void load_inputs(const dsrg_problem* P, bool devptr, const Shape& sh, const Inputs& in,
-                        const double* s_host, hipStream_t st) {
+                        const double* s_host, hipStream_t st, int* defer_bad = nullptr) {
   const hipMemcpyKind kind = devptr ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
   auto cp = [&](double* dst, const double* src, long long n) {
     if (n > 0) HIPCHECK(hipMemcpyAsync(dst, src, n * sizeof(double), kind, st));
@@ -2098,6 +2100,10 @@ static void load_inputs(const dsrg_problem* P, bool devptr, const Shape& sh, con
     chk(in.g2, sh.g2n);
   }
   if (sh.has_g3) chk(in.g3, sh.g3n);
+  if (defer_bad) {
+    HIPCHECK(hipMemcpyAsync(defer_bad, in.bad, sizeof(int), hipMemcpyDeviceToHost, st));
+    return;
+  }
   int hbad = 0;
   HIPCHECK(hipMemcpyAsync(&hbad, in.bad, sizeof(int), hipMemcpyDeviceToHost, st));
   HIPCHECK(hipStreamSynchronize(st));
@@ -2366,7 +2372,7 @@ struct Plan {
   hipStream_t cap = nullptr;
   hipGraph_t graph = nullptr;
   hipGraphExec_t exec = nullptr;
-  double* pinned = nullptr;   // host [8]: s at [0], energies at [4..8)
+  double* pinned = nullptr;   // host [16]: s at [0], energies at [4..8), non-finite count at [8]
   bool busy = false;
   unsigned long long stamp = 0;
   double gett_flops = 0, ladder_flops = 0;
@@ -2530,13 +2536,17 @@ static int run(const dsrg_problem* P, const dsrg_options* O, dsrg_result* R,
       }
     } rel{plan};
     plan->pinned[0] = P->s;
-    load_inputs(P, devptr, sh, plan->in, plan->pinned, st);
+    // device inputs: the non-finite check runs ahead of the graph and is read after it
+    int* bad = reinterpret_cast<int*>(plan->pinned + 8);
+    *bad = 0;
+    load_inputs(P, devptr, sh, plan->in, plan->pinned, st, devptr ? bad : nullptr);
     HIPCHECK(hipEventRecord(ev[0], st));
     HIPCHECK(hipGraphLaunch(plan->exec, st));
     HIPCHECK(hipEventRecord(ev[7], st));
     HIPCHECK(hipMemcpyAsync(plan->pinned + 4, plan->in.energies, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHECK(hipStreamSynchronize(st));
     HIPCHECK(hipGetLastError());
+    if (*bad) throw Error(DSRG_E_NONFINITE, "non-finite value in eps, B or the densities");
     fill_result(&r, plan->pinned + 4, pt3);
     float ms = 0;
     HIPCHECK(hipEventElapsedTime(&ms, ev[0], ev[7]));
@@ -2557,7 +2567,7 @@ static int run(const dsrg_problem* P, const dsrg_options* O, dsrg_result* R,
   if (fresh) {
     fresh->pool = std::make_unique<Pool>(st, true);
     pool = fresh->pool.get();
-    HIPCHECK(hipHostMalloc((void**)&fresh->pinned, 8 * sizeof(double), hipHostMallocDefault));
+    HIPCHECK(hipHostMalloc((void**)&fresh->pinned, 16 * sizeof(double), hipHostMallocDefault));
     fresh->pinned[0] = P->s;
     s_src = fresh->pinned;
   } else {

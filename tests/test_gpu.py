@@ -437,3 +437,16 @@ def test_nonfinite_device_input():
     with pytest.raises(_lib.DsrgError) as e:
         _lib.dsrg_pt3_energy(d)
     assert e.value.code == _lib.DSRG_E_NONFINITE
+    # the same through a recorded plan: a clean call records it, a replay with a NaN input
+    # reports the error after the graph has run, and the next clean replay is unaffected
+    q = make_problem(1, 2, 3, 7, seed=2)
+    dq = _lib.to_device(q)
+    first = _lib.dsrg_pt3_energy(dq)
+    assert first["plan"] == 1
+    dq["eps"][0] = float("inf")
+    with pytest.raises(_lib.DsrgError) as e:
+        _lib.dsrg_pt3_energy(dq)
+    assert e.value.code == _lib.DSRG_E_NONFINITE
+    dq["eps"][0] = float(q.eps[0])
+    again = _lib.dsrg_pt3_energy(dq)
+    assert again["plan"] == 2 and again["e2"] == first["e2"] and again["e3"] == first["e3"]
