@@ -821,8 +821,11 @@ void launch_dot_group(const DotItem* items, int n, int blocks, double* partial, 
 // stands for, last index fastest), so the entry list it walks is the same for every lane:
 // entries load through the scalar cache and four source values are in flight at a time,
 // summed in entry order.
+// tpe > 1 (small outputs, long entry lists): tpe consecutive lanes share an element, lane j
+// of the group sums entries j, j + tpe, ... and a fixed butterfly adds the group's partial
+// sums (deterministic for a given tpe).
 __global__ __launch_bounds__(256) void gather_kernel(GatherDesc g, const GatherEntry* __restrict__ ent,
-                                                     double* __restrict__ out) {
+                                                     double* __restrict__ out, int tpe) {
   const int b = blockIdx.x;
   const int ncls = 1 << g.rank;
   int c = 0;
@@ -837,8 +840,9 @@ __global__ __launch_bounds__(256) void gather_kernel(GatherDesc g, const GatherE
       len[k] = hi ? g.dim[k] - g.split[k] : g.split[k];
       cnt *= len[k];
     }
-  long long e = (long long)(b - g.blk[c]) * 256 + threadIdx.x;
-  if (e >= cnt) return;
+  const int sub = threadIdx.x % tpe;
+  long long e = (long long)(b - g.blk[c]) * (256 / tpe) + threadIdx.x / tpe;
+  const bool live = e < cnt;   // whole groups of tpe lanes share e, so shuffles stay in a group
   int x[4] = {0, 0, 0, 0};
 #pragma unroll
   for (int k = 3; k >= 0; --k)
@@ -852,26 +856,37 @@ __global__ __launch_bounds__(256) void gather_kernel(GatherDesc g, const GatherE
   for (int k = 0; k < 4; ++k)
     if (k < g.rank) o = o * g.dim[k] + x[k];
   double acc = 0.0;
-  int i = g.cls[c];
-  const int end = g.cls[c + 1];
+  const int end = live ? g.cls[c + 1] : g.cls[c];
   auto off = [&](const GatherEntry& en) {
     return en.base + (long long)x[0] * en.ss[0] + (long long)x[1] * en.ss[1] + (long long)x[2] * en.ss[2] +
            (long long)x[3] * en.ss[3];
   };
-  for (; i + 4 <= end; i += 4) {
+  int i = g.cls[c] + sub;
+  for (; i + 3 * tpe < end; i += 4 * tpe) {
     double v[4];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) v[u] = ent[i + u].src[off(ent[i + u])];
+    for (int u = 0; u < 4; ++u) v[u] = ent[i + u * tpe].src[off(ent[i + u * tpe])];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) acc = fma(ent[i + u].coef, v[u], acc);
+    for (int u = 0; u < 4; ++u) acc = fma(ent[i + u * tpe].coef, v[u], acc);
   }
-  for (; i < end; ++i) acc = fma(ent[i].coef, ent[i].src[off(ent[i])], acc);
-  out[o] += acc;
+  for (; i < end; i += tpe) acc = fma(ent[i].coef, ent[i].src[off(ent[i])], acc);
+  for (int w = tpe >> 1; w > 0; w >>= 1) acc += __shfl_xor(acc, w, 64);
+  if (live && sub == 0) out[o] += acc;
 }
 
 void launch_gather(const GatherDesc& g0, const GatherEntry* entries, double* out, hipStream_t st) {
   GatherDesc g = g0;
   const int ncls = 1 << g.rank;
+  long long total = 0;
+  for (int c = 0; c < ncls; ++c) {
+    if (g.cls[c + 1] == g.cls[c]) continue;
+    long long cnt = 1;
+    for (int k = 0; k < g.rank; ++k) cnt *= ((c >> k) & 1) ? g.dim[k] - g.split[k] : g.split[k];
+    total += cnt;
+  }
+  // lanes per element: enough lanes to fill the chip (>= 2^18) for small outputs, at most 64
+  int tpe = 1;
+  while (tpe < 64 && total * tpe < (1LL << 18)) tpe <<= 1;
   long long blocks = 0;
   for (int c = 0; c < ncls; ++c) {
     g.blk[c] = (int)blocks;
@@ -881,11 +896,11 @@ void launch_gather(const GatherDesc& g0, const GatherEntry* entries, double* out
       const bool hi = (c >> k) & 1;
       cnt *= hi ? g.dim[k] - g.split[k] : g.split[k];
     }
-    blocks += (cnt + 255) / 256;
+    blocks += (cnt * tpe + 255) / 256;
   }
   for (int c = ncls; c <= 16; ++c) g.blk[c] = (int)blocks;
   if (blocks <= 0) return;
-  hipLaunchKernelGGL(gather_kernel, dim3((unsigned)blocks), dim3(256), 0, st, g, entries, out);
+  hipLaunchKernelGGL(gather_kernel, dim3((unsigned)blocks), dim3(256), 0, st, g, entries, out, tpe);
 }
 
 // ---------------------------------------------------------------------------
