@@ -1627,17 +1627,24 @@ struct Exec {
           kept.push_back(R);
           const std::string pn = S.tensor + "." + R.block;
           if (!outs.count(pn)) {
-            TensorRef t = oi->second;
-            t.p = pool.alloc((size_t)t.lim);
-            double* tp = t.p;
-            const long long n = t.lim;
-            op([tp, n](hipStream_t s) { launch_fill(tp, n, 0.0, s); });
-            ++n_launch;
-            outs[pn] = t;
+            outs[pn] = oi->second;   // storage assigned below
             pre_names.push_back(pn);
           }
         }
         P.s = kept;
+      }
+      // the pre-images of the use in one zeroed block
+      long long total = 0;
+      for (auto& pn : pre_names) total += outs[pn].lim;
+      if (total > 0) {
+        double* blk = pool.alloc((size_t)total);
+        long long at = 0;
+        for (auto& pn : pre_names) {
+          outs[pn].p = blk + at;
+          at += outs[pn].lim;
+        }
+        op([blk, total](hipStream_t s) { launch_fill(blk, total, 0.0, s); });
+        ++n_launch;
       }
     }
     return pu;
@@ -2231,16 +2238,13 @@ static BodyOut body(Exec& X, OpLog& op, Pool& pool, const Shape& sh, const Input
     return bo;
   }
   // W = [V, A(1)]_{1,2} and Z = [Y, A(1)]_{1,2}, excitation blocks
-  double* W1 = pool.alloc(2 * n1);
-  double* W2 = pool.alloc(3 * n4);
-  double* Z1 = pool.alloc(2 * n1);
-  double* Z2 = pool.alloc(3 * n4);
-  op([W1, W2, Z1, Z2, n1, n4](hipStream_t s) {
-    launch_fill(W1, 2 * n1, 0.0, s);
-    launch_fill(W2, 3 * n4, 0.0, s);
-    launch_fill(Z1, 2 * n1, 0.0, s);
-    launch_fill(Z2, 3 * n4, 0.0, s);
-  });
+  // one zeroed block: W one-body, W two-body, Z one-body, Z two-body
+  const long long wz = 2 * (2 * (long long)n1 + 3 * (long long)n4);
+  double* W1 = pool.alloc((size_t)wz);
+  double* W2 = W1 + 2 * n1;
+  double* Z1 = W2 + 3 * n4;
+  double* Z2 = Z1 + 2 * n1;
+  op([W1, wz](hipStream_t s) { launch_fill(W1, wz, 0.0, s); });
   auto bind_out = [&](std::map<std::string, TensorRef>& o, double* p1, double* p2) {
     auto mk = [&](double* p, const char* ax) {
       TensorRef t{p, ax, {}};
