@@ -1302,6 +1302,10 @@ struct Exec {
       throw Error(DSRG_E_HIP, "internal: scalar products in a tensor use");
     }
 
+    // every output's gather in one launch (outputs are distinct arrays)
+    std::vector<GatherDesc> gds;
+    std::vector<std::vector<GatherEntry>> gent;
+    long long gblocks = 0;
     for (auto& kv : gents) {
       const TensorRef& o = outs.at(kv.first);
       GatherDesc gd;
@@ -1325,9 +1329,21 @@ struct Exec {
           }
       }
       gd.cls[1 << gd.rank] = (int)ent.size();
-      GatherEntry* d_ent = upload(ent);
-      double* dst = o.p;
-      op([gd, d_ent, dst](hipStream_t s) { launch_gather(gd, d_ent, dst, s); });
+      gd.out = o.p;
+      const long long nb = gather_prepare(gd);
+      if (nb <= 0) continue;
+      gd.blk0 = (int)gblocks;
+      gblocks += nb;
+      if (gblocks >= (1LL << 31)) throw Error(DSRG_E_UNSUPPORTED, "gather launch too large");
+      gds.push_back(gd);
+      gent.push_back(std::move(ent));
+    }
+    if (!gds.empty()) {
+      for (size_t i = 0; i < gds.size(); ++i) gds[i].ent = upload(gent[i]);
+      GatherDesc* d_gd = upload(gds);
+      const int ng = (int)gds.size();
+      const long long nbk = gblocks;
+      op([d_gd, ng, nbk](hipStream_t s) { launch_gather_multi(d_gd, ng, nbk, s); });
       ++n_launch;
     }
     return true;

@@ -150,9 +150,17 @@ struct GatherDesc {
   int dim[4] = {1, 1, 1, 1};
   int split[4] = {};
   int cls[17] = {};
-  int blk[17] = {};   // workgroups of each class (prefix), set by launch_gather
+  int blk[17] = {};   // workgroups of each class (prefix), set by gather_prepare
+  const GatherEntry* ent = nullptr;   // this output's entries (classes in order)
+  double* out = nullptr;              // contiguous output
+  int tpe = 1;                        // lanes per element, set by gather_prepare
+  int blk0 = 0;                       // first workgroup of this output in a multi-output launch
 };
-void launch_gather(const GatherDesc& g, const GatherEntry* entries, double* out, hipStream_t st);
+// lanes per element and class workgroups of one output; returns its workgroup count
+long long gather_prepare(GatherDesc& g);
+// several outputs (prepared, blk0 their workgroup prefix, the array in device memory) in
+// one launch of `blocks` workgroups
+void launch_gather_multi(const GatherDesc* descs, int n, long long blocks, hipStream_t st);
 
 // partial: scratch of at least dot_partials() doubles; writes the sum into out[0]
 int dot_partials();

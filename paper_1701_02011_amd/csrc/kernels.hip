@@ -824,9 +824,19 @@ void launch_dot_group(const DotItem* items, int n, int blocks, double* partial, 
 // tpe > 1 (small outputs, long entry lists): tpe consecutive lanes share an element, lane j
 // of the group sums entries j, j + tpe, ... and a fixed butterfly adds the group's partial
 // sums (deterministic for a given tpe).
-__global__ __launch_bounds__(256) void gather_kernel(GatherDesc g, const GatherEntry* __restrict__ ent,
-                                                     double* __restrict__ out, int tpe) {
-  const int b = blockIdx.x;
+__global__ __launch_bounds__(256) void gather_kernel(const GatherDesc* __restrict__ descs, int nd) {
+  // output of this workgroup: the last with blk0 <= blockIdx.x
+  int dl = 0, dh = nd - 1;
+  while (dl < dh) {
+    const int mid = (dl + dh + 1) >> 1;
+    if (descs[mid].blk0 <= (int)blockIdx.x) dl = mid;
+    else dh = mid - 1;
+  }
+  const GatherDesc& g = descs[dl];
+  const GatherEntry* __restrict__ ent = g.ent;
+  double* __restrict__ out = g.out;
+  const int tpe = g.tpe;
+  const int b = (int)blockIdx.x - g.blk0;
   const int ncls = 1 << g.rank;
   int c = 0;
   while (c + 1 < ncls && b >= g.blk[c + 1]) ++c;
@@ -874,8 +884,7 @@ __global__ __launch_bounds__(256) void gather_kernel(GatherDesc g, const GatherE
   if (live && sub == 0) out[o] += acc;
 }
 
-void launch_gather(const GatherDesc& g0, const GatherEntry* entries, double* out, hipStream_t st) {
-  GatherDesc g = g0;
+long long gather_prepare(GatherDesc& g) {
   const int ncls = 1 << g.rank;
   long long total = 0;
   for (int c = 0; c < ncls; ++c) {
@@ -887,20 +896,22 @@ void launch_gather(const GatherDesc& g0, const GatherEntry* entries, double* out
   // lanes per element: enough lanes to fill the chip (>= 2^18) for small outputs, at most 64
   int tpe = 1;
   while (tpe < 64 && total * tpe < (1LL << 18)) tpe <<= 1;
+  g.tpe = tpe;
   long long blocks = 0;
   for (int c = 0; c < ncls; ++c) {
     g.blk[c] = (int)blocks;
     if (g.cls[c + 1] == g.cls[c]) continue;
     long long cnt = 1;
-    for (int k = 0; k < g.rank; ++k) {
-      const bool hi = (c >> k) & 1;
-      cnt *= hi ? g.dim[k] - g.split[k] : g.split[k];
-    }
+    for (int k = 0; k < g.rank; ++k) cnt *= ((c >> k) & 1) ? g.dim[k] - g.split[k] : g.split[k];
     blocks += (cnt * tpe + 255) / 256;
   }
   for (int c = ncls; c <= 16; ++c) g.blk[c] = (int)blocks;
-  if (blocks <= 0) return;
-  hipLaunchKernelGGL(gather_kernel, dim3((unsigned)blocks), dim3(256), 0, st, g, entries, out, tpe);
+  return blocks;
+}
+
+void launch_gather_multi(const GatherDesc* descs, int n, long long blocks, hipStream_t st) {
+  if (n <= 0 || blocks <= 0) return;
+  hipLaunchKernelGGL(gather_kernel, dim3((unsigned)blocks), dim3(256), 0, st, descs, n);
 }
 
 // ---------------------------------------------------------------------------
