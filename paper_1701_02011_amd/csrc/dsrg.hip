@@ -2054,9 +2054,26 @@ static bool finite_host(const double* p, size_t n) {
   return true;
 }
 
-__global__ void count_nonfinite_kernel(const double* __restrict__ p, long long n, int* __restrict__ bad) {
-  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += 256LL * gridDim.x)
-    if (!isfinite(p[i])) atomicAdd(bad, 1);
+// Device inputs: every array copied into the library's buffers by one launch, which also
+// counts non-finite values (one launch instead of a copy and a check per array).
+struct CopyList {
+  const double* src[6];
+  double* dst[6];
+  long long end[6];   // prefix sums of the array lengths
+  int n;
+};
+__global__ __launch_bounds__(256) void copy_check_kernel(CopyList L, int* __restrict__ bad) {
+  const long long total = L.end[L.n - 1];
+  int nbad = 0;
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < total; i += 256LL * gridDim.x) {
+    int k = 0;
+    while (k + 1 < L.n && i >= L.end[k]) ++k;
+    const long long j = i - (k ? L.end[k - 1] : 0);
+    const double v = L.src[k][j];
+    L.dst[k][j] = v;
+    nbad += !isfinite(v);
+  }
+  if (nbad) atomicAdd(bad, nbad);
 }
 
 // Shape of a call and the device copies of its inputs.  The pipeline reads only these
@@ -2097,32 +2114,43 @@ static Inputs alloc_inputs(Pool& pool, const Shape& sh) {
 // there, and the caller checks it after its own synchronisation (no wait here).
 static void load_inputs(const dsrg_problem* P, bool devptr, const Shape& sh, const Inputs& in,
                         const double* s_host, hipStream_t st, int* defer_bad = nullptr) {
-  const hipMemcpyKind kind = devptr ? hipMemcpyDeviceToDevice : hipMemcpyHostToDevice;
-  auto cp = [&](double* dst, const double* src, long long n) {
-    if (n > 0) HIPCHECK(hipMemcpyAsync(dst, src, n * sizeof(double), kind, st));
-  };
-  cp(in.eps, P->eps, sh.N);
-  cp(in.B, P->B, sh.nB);
-  if (sh.nA > 0) {
-    cp(in.g1, P->gamma1, sh.g1n);
-    cp(in.g2, P->gamma2, sh.g2n);
-  }
-  if (sh.has_g3) cp(in.g3, P->gamma3, sh.g3n);
   HIPCHECK(hipMemcpyAsync(in.s, s_host, sizeof(double), hipMemcpyHostToDevice, st));
-  if (!devptr) return;
-  HIPCHECK(hipMemsetAsync(in.bad, 0, sizeof(int), st));
-  auto chk = [&](const double* p, long long n) {
-    if (!p || n == 0) return;
-    long long blocks = std::min<long long>((n + 255) / 256, 4096);
-    hipLaunchKernelGGL(count_nonfinite_kernel, dim3((unsigned)blocks), dim3(256), 0, st, p, n, in.bad);
-  };
-  chk(in.eps, sh.N);
-  chk(in.B, sh.nB);
-  if (sh.nA > 0) {
-    chk(in.g1, sh.g1n);
-    chk(in.g2, sh.g2n);
+  if (!devptr) {
+    auto cp = [&](double* dst, const double* src, long long n) {
+      if (n > 0) HIPCHECK(hipMemcpyAsync(dst, src, n * sizeof(double), hipMemcpyHostToDevice, st));
+    };
+    cp(in.eps, P->eps, sh.N);
+    cp(in.B, P->B, sh.nB);
+    if (sh.nA > 0) {
+      cp(in.g1, P->gamma1, sh.g1n);
+      cp(in.g2, P->gamma2, sh.g2n);
+    }
+    if (sh.has_g3) cp(in.g3, P->gamma3, sh.g3n);
+    return;
   }
-  if (sh.has_g3) chk(in.g3, sh.g3n);
+  HIPCHECK(hipMemsetAsync(in.bad, 0, sizeof(int), st));
+  CopyList L{};
+  long long total = 0;
+  auto add = [&](double* dst, const double* src, long long n) {
+    if (n <= 0) return;
+    L.src[L.n] = src;
+    L.dst[L.n] = dst;
+    total += n;
+    L.end[L.n] = total;
+    ++L.n;
+  };
+  add(in.eps, P->eps, sh.N);
+  add(in.B, P->B, sh.nB);
+  if (sh.nA > 0) {
+    add(in.g1, P->gamma1, sh.g1n);
+    add(in.g2, P->gamma2, sh.g2n);
+  }
+  if (sh.has_g3) add(in.g3, P->gamma3, sh.g3n);
+  if (L.n > 0) {
+    const long long blocks = std::min<long long>((total + 255) / 256, 8192);
+    hipLaunchKernelGGL(copy_check_kernel, dim3((unsigned)blocks), dim3(256), 0, st, L, in.bad);
+    HIPCHECK(hipGetLastError());
+  }
   if (defer_bad) {
     HIPCHECK(hipMemcpyAsync(defer_bad, in.bad, sizeof(int), hipMemcpyDeviceToHost, st));
     return;
