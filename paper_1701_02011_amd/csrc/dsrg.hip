@@ -883,8 +883,30 @@ struct Exec {
   // outputs); 128 x 128 when it pads at most 10 % more than the chosen small shape (four
   // times the work per loaded element) and the k range is long (short ones ran slower
   // that way).
+  // C^T = B^T A^T: the same contraction with the roles of m and n (and of A and B) swapped
+  static void transpose_item(GroupItem& it) {
+    GettDesc& g = it.g;
+    std::swap(g.M, g.N);
+    std::swap(g.nm, g.nn);
+    for (int c = 0; c < kMaxComp; ++c) {
+      std::swap(g.md[c], g.nd[c]);
+      std::swap(g.am[c], g.bn[c]);
+      std::swap(g.ak[c], g.bk[c]);
+      std::swap(g.cm[c], g.cn[c]);
+    }
+    std::swap(g.a_kfast, g.b_kfast);
+    std::swap(it.A, it.B);
+  }
   static void group_shape(GroupItem& it) {
     GettDesc& g = it.g;
+    if (g.K <= kGettBK && std::min(g.M, g.N) <= kGettBK) {
+      // one output row per thread along the long free dimension (operands swapped later
+      // when that is N)
+      it.shape = kGroupRowShape;
+      it.tiles_m = (std::max(g.M, g.N) + kGroupRows - 1) / kGroupRows;
+      it.tiles_n = 1;
+      return;
+    }
     long long bestw = -1, w0 = -1;
     int best = 0;
     for (int sh = 0; sh < kGroupShapes; ++sh) {
@@ -967,6 +989,7 @@ struct Exec {
       it.g.kchunk = it.g.steps;
       it.g.part = nullptr;
       it.splits = 1;
+      if (it.shape == kGroupRowShape && it.g.N > kGettBK) transpose_item(it);
       gett_magic(it.g);
       if (it.shape == kGroupBigShape) {   // not with K = n_aux < 128 k steps; kept general
         for (auto& kk : todo)
@@ -1137,38 +1160,56 @@ struct Exec {
       }
     }
 
-    // split-K for items with few tiles and a k range long against the level's work per
-    // workgroup slot; budget check
+    // split-K: a tile's k steps run one after another at about the same time per step
+    // whether it has the CU to itself (load latency) or shares it (MFMA), so a level ends no
+    // sooner than its longest chain of steps.  Chains are cut to half the level's work per
+    // workgroup slot (64 x 64 step units, four such workgroups per CU; at least 8 steps);
+    // should the partial tiles not fit beside the temporaries, only items with few tiles and
+    // a chain over twice the work per slot are split.  Budget check.
+    for (auto& lv : lev)
+      for (auto& it : lv) group_shape(it);
     long long part_elems = 0;
     std::vector<std::vector<long long>> poff(lev.size());
-    for (size_t L = 0; L < lev.size(); ++L) {
-      for (auto& it : lev[L]) {
-        GettDesc& g = it.g;
-        group_shape(it);
-      }
-      // k steps per workgroup slot of the level (four small workgroups per CU): chunks
-      // shorter than that only add partial tiles to reduce
-      double level_steps = 0;
-      for (auto& it : lev[L]) level_steps += (double)it.tiles_m * it.tiles_n * it.g.steps;
-      const long long target = std::max<long long>(16, (long long)(level_steps / (4.0 * 256)));
-      for (auto& it : lev[L]) {
-        GettDesc& g = it.g;
-        long long tiles = (long long)it.tiles_m * it.tiles_n;
-        int ns = 1;
-        if (g.steps >= 64 && g.steps > 2 * target && tiles < 64) {
-          long long want = std::min<long long>((g.steps + target - 1) / target,
-                                               std::max<long long>(1, 256 / tiles));
-          long long chunk = (g.steps + want - 1) / want;
-          ns = (int)((g.steps + chunk - 1) / chunk);
-          g.kchunk = chunk;
-        } else {
+    auto plan_splits = [&](bool fine) {
+      part_elems = 0;
+      for (size_t L = 0; L < lev.size(); ++L) {
+        poff[L].clear();
+        auto weight = [](const GroupItem& it) {
+          return it.shape == kGroupBigShape ? 4LL : 1LL;
+        };
+        double level_steps = 0;
+        for (auto& it : lev[L])
+          level_steps += (double)it.tiles_m * it.tiles_n * it.g.steps * weight(it);
+        const long long target = std::max<long long>(16, (long long)(level_steps / (4.0 * 256)));
+        const long long cap = std::max<long long>(8, target / 2);
+        for (auto& it : lev[L]) {
+          GettDesc& g = it.g;
+          const long long tiles = (long long)it.tiles_m * it.tiles_n, w = weight(it);
+          int ns = 1;
           g.kchunk = g.steps;
+          if (it.shape == kGroupRowShape) {
+            // one pass over k per row, never split
+          } else if (fine && g.steps * w > cap + cap / 2) {
+            const long long cw = std::max<long long>(1, cap / w);
+            const long long want = std::min<long long>((g.steps + cw - 1) / cw, 64);
+            const long long chunk = (g.steps + want - 1) / want;
+            ns = (int)((g.steps + chunk - 1) / chunk);
+            g.kchunk = chunk;
+          } else if (!fine && g.steps >= 64 && g.steps > 2 * target && tiles < 64) {
+            const long long want = std::min<long long>((g.steps + target - 1) / target,
+                                                       std::max<long long>(1, 256 / tiles));
+            const long long chunk = (g.steps + want - 1) / want;
+            ns = (int)((g.steps + chunk - 1) / chunk);
+            g.kchunk = chunk;
+          }
+          it.splits = ns;
+          poff[L].push_back(ns > 1 ? part_elems : -1);
+          if (ns > 1) part_elems += (long long)ns * g.M * g.N;
         }
-        it.splits = ns;
-        poff[L].push_back(ns > 1 ? part_elems : -1);
-        if (ns > 1) part_elems += (long long)ns * g.M * g.N;
       }
-    }
+    };
+    plan_splits(true);
+    if (8 * (arena + part_elems) > group_cap) plan_splits(false);
     long long bytes = 8 * (arena + part_elems);
     if (bytes > group_cap) return false;
 
@@ -1204,6 +1245,7 @@ struct Exec {
         it.B = at(fx.b, it.B);
         it.C = tbase + fx.c;
         it.g.part = it.splits > 1 ? pbase + poff[L][oi] : nullptr;
+        if (it.shape == kGroupRowShape && it.g.N > kGettBK) transpose_item(it);
         gett_magic(it.g);
         it.tile0 = R.tiles;
         long long t = (long long)it.tiles_m * it.tiles_n * it.splits;
@@ -1332,6 +1374,23 @@ struct Exec {
       gd.out = o.p;
       const long long nb = gather_prepare(gd);
       if (nb <= 0) continue;
+      if (const char* path = getenv("DSRG_GROUP_DUMP")) {
+        // gather record: G, use, output, rank, tpe, workgroups, then per class: entries,
+        // elements, entries whose last index has unit stride
+        if (FILE* f = fopen(path, "a")) {
+          fprintf(f, "G,%d,%s,%d,%d,%lld", use_id, kv.first.c_str(), gd.rank, gd.tpe, nb);
+          for (int c = 0; c < (1 << gd.rank); ++c) {
+            long long cnt = 1;
+            for (int k = 0; k < gd.rank; ++k)
+              cnt *= ((c >> k) & 1) ? gd.dim[k] - gd.split[k] : gd.split[k];
+            int unit = 0;
+            for (int i = gd.cls[c]; i < gd.cls[c + 1]; ++i) unit += ent[i].ss[gd.rank - 1] == 1;
+            fprintf(f, ",%d,%lld,%d", gd.cls[c + 1] - gd.cls[c], cnt, unit);
+          }
+          fprintf(f, "\n");
+          fclose(f);
+        }
+      }
       gd.blk0 = (int)gblocks;
       gblocks += nb;
       if (gblocks >= (1LL << 31)) throw Error(DSRG_E_UNSUPPORTED, "gather launch too large");

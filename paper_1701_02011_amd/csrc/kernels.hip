@@ -390,7 +390,9 @@ __device__ __forceinline__ void gett_grid_tile(const GettDesc& g, const double* 
   const int gx = gridDim.x, gy = gridDim.y;
   const int total = gx * gy * gridDim.z;
   const int b = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
-  const int L = xcd_tile(b, total);
+  // with the triangle skip the live tiles crowd into the last columns: runs of 8 tiles
+  // spread over the XCDs keep their loads even
+  const int L = g.tri > 0 ? xcd_tile_windowed(b, total) : xcd_tile(b, total);
   const int tm = L % gx, rest = L / gx;
   const int tn = rest % gy, kz = rest / gy;
   if (g.tri > 0 && (tn * (32 * WN) + 32 * WN - 1) / g.tri < (tm * (32 * WM)) / g.tri) return;
@@ -575,15 +577,18 @@ static bool big_tiles(const GettDesc& g) {
 
 // Split-K factor: the number of k chunks that fills the resident workgroup slots in the
 // most nearly whole rounds (256 CUs; two 128 x 128 or four 64 x 64 workgroups per CU fit
-// the registers), keeping at least 16 k steps per chunk and the partial tiles within
-// ws_elems.  A larger split must gain at least 5 % of utilisation.
+// the registers), keeping at least 16 k steps per chunk (4 when the output has at most
+// 2^20 elements: there a few tiles with long k ranges would wait on load latency, and the
+// partial tiles stay small) and the partial tiles within ws_elems.  A larger split must
+// gain at least 5 % of utilisation.
 int gett_splits(const GettDesc& g, long long ws_elems) {
   const bool big = big_tiles(g);
   const int bm = big ? 128 : 64, bn = bm;
   const long long slots = 256LL * (big ? 2 : 4);
   const long long tiles = (long long)((g.M + bm - 1) / bm) * ((g.N + bn - 1) / bn);
   const long long mn = std::max<long long>(1, (long long)g.M * g.N);
-  const long long smax = std::min<long long>({g.steps / 16, ws_elems / mn, 4096});
+  const long long min_chunk = mn <= (1LL << 20) ? 4 : 16;
+  const long long smax = std::min<long long>({g.steps / min_chunk, ws_elems / mn, 4096});
   auto util = [&](long long s) {
     const long long w = tiles * s;
     return (double)w / (double)(slots * ((w + slots - 1) / slots));
@@ -654,6 +659,54 @@ void launch_gett(const GettDesc& g0, const double* A, const double* B, double* C
 // never share an output element, so the launch is race-free and its result does not
 // depend on scheduling.
 // ---------------------------------------------------------------------------
+// Shape-4 items (K <= 16, N <= 16): the k offsets and B (zero past K and N) are staged in
+// LDS, each thread loads the K values of its row of A and forms its N outputs in FP64
+// (k in order), so a workgroup covers 256 rows at the cost of a streaming pass.
+struct RowLds {
+  double Bs[BK][BK];
+  long long ka[BK], kb[BK];
+};
+__device__ __forceinline__ void group_rows(const GroupItem& it, int tm, RowLds& lds) {
+  const GettDesc& g = it.g;
+  const int t = threadIdx.x;
+  if (t < g.K) {
+    long long oa = 0, ob = 0;
+    int idx = t;
+    for (int c = g.nk - 1; c >= 0; --c) {
+      const int q = idx / g.kd[c];
+      const int r = idx - q * g.kd[c];
+      oa += (long long)r * g.ak[c];
+      ob += (long long)r * g.bk[c];
+      idx = q;
+    }
+    lds.ka[t] = oa;
+    lds.kb[t] = ob;
+  }
+  __syncthreads();
+  {
+    const int k = t / BK, n = t % BK;   // 256 threads = BK x BK entries
+    double v = 0.0;
+    if (k < g.K && n < g.N) v = it.B[lds.kb[k] + decode_fast(n, g.nn, g.nd, g.nmag, g.nsh, g.bn)];
+    lds.Bs[k][n] = v;
+  }
+  __syncthreads();
+  const int m = tm * kGroupRows + t;
+  if (m >= g.M) return;
+  const long long ao = decode_fast(m, g.nm, g.md, g.mmag, g.msh, g.am);
+  double a[BK];
+#pragma unroll
+  for (int k = 0; k < BK; ++k) a[k] = k < g.K ? it.A[ao + lds.ka[k]] : 0.0;
+  const long long co = decode_fast(m, g.nm, g.md, g.mmag, g.msh, g.cm);
+  for (int n = 0; n < g.N; ++n) {
+    double s = 0.0;
+#pragma unroll
+    for (int k = 0; k < BK; ++k) s = fma(a[k], lds.Bs[k][n], s);
+    double* c = it.C + co + decode_fast(n, g.nn, g.nd, g.nmag, g.nsh, g.cn);
+    const double v = g.alpha * s;
+    *c = g.beta ? *c + v : v;
+  }
+}
+
 template <bool kF32>
 __device__ __forceinline__ void group_tile(const GroupItem* __restrict__ items, const int* __restrict__ tile_item) {
   using T = typename Mfma<kF32>::T;
@@ -667,6 +720,7 @@ __device__ __forceinline__ void group_tile(const GroupItem* __restrict__ items, 
     GroupLds0 t0;
     GroupLds1 t1;
     GroupLds2 t2;
+    RowLds rows;
   } lds;
   const int b = xcd_tile_windowed(blockIdx.x, gridDim.x);
   const GroupItem& it = items[tile_item[b]];
@@ -677,6 +731,9 @@ __device__ __forceinline__ void group_tile(const GroupItem* __restrict__ items, 
   const int tm = r / it.tiles_n;
   const int tn = r - tm * it.tiles_n;
   switch (it.shape) {
+    case kGroupRowShape:
+      group_rows(it, tm, lds.rows);
+      break;
     case 1:
       gett_tile<1, 2, 1, kF32>(it.g, it.A, it.B, it.C, tm * GroupLds1::BM, tn * GroupLds1::BN, kz, lds.t1);
       break;
@@ -791,12 +848,33 @@ __global__ __launch_bounds__(256) void dot_group_kernel(const DotItem* __restric
   const DotItem& it = items[lo];
   const int j = b - it.blk0;
   double sum = 0.0;
-  const bool fast = it.d.K < (1LL << 31);
-  for (long long i = j * 256LL + threadIdx.x; i < it.d.K; i += 256LL * it.nblk) {
-    long long oa, ob;
-    if (fast) decode2_fast((unsigned)i, it.d.nk, it.d.kd, it.d.dm, it.d.as, it.d.bs, oa, ob);
-    else decode2(i, it.d.nk, it.d.kd, it.d.as, it.d.bs, oa, ob);
-    sum += it.A[oa] * it.B[ob];
+  if (it.d.K < (1LL << 31)) {
+    // four index pairs decoded and loaded before they are summed (same order as one at a time)
+    const unsigned K = (unsigned)it.d.K, stride = 256u * (unsigned)it.nblk;
+    unsigned i = (unsigned)j * 256u + threadIdx.x;
+    for (; i < K && K - i > 3u * stride; i += 4u * stride) {
+      double a[4], bv[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        long long oa, ob;
+        decode2_fast(i + u * stride, it.d.nk, it.d.kd, it.d.dm, it.d.as, it.d.bs, oa, ob);
+        a[u] = it.A[oa];
+        bv[u] = it.B[ob];
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) sum += a[u] * bv[u];
+    }
+    for (; i < K; i += stride) {
+      long long oa, ob;
+      decode2_fast(i, it.d.nk, it.d.kd, it.d.dm, it.d.as, it.d.bs, oa, ob);
+      sum += it.A[oa] * it.B[ob];
+    }
+  } else {
+    for (long long i = j * 256LL + threadIdx.x; i < it.d.K; i += 256LL * it.nblk) {
+      long long oa, ob;
+      decode2(i, it.d.nk, it.d.kd, it.d.as, it.d.bs, oa, ob);
+      sum += it.A[oa] * it.B[ob];
+    }
   }
   red[threadIdx.x] = sum;
   __syncthreads();
@@ -819,7 +897,7 @@ void launch_dot_group(const DotItem* items, int n, int blocks, double* partial, 
 // ---------------------------------------------------------------------------
 // Each workgroup covers 256 elements of one class (the box of index ranges the class
 // stands for, last index fastest), so the entry list it walks is the same for every lane:
-// entries load through the scalar cache and four source values are in flight at a time,
+// entries load through the scalar cache and eight source values are in flight at a time,
 // summed in entry order.
 // tpe > 1 (small outputs, long entry lists): tpe consecutive lanes share an element, lane j
 // of the group sums entries j, j + tpe, ... and a fixed butterfly adds the group's partial
@@ -872,12 +950,12 @@ __global__ __launch_bounds__(256) void gather_kernel(const GatherDesc* __restric
            (long long)x[3] * en.ss[3];
   };
   int i = g.cls[c] + sub;
-  for (; i + 3 * tpe < end; i += 4 * tpe) {
-    double v[4];
+  for (; i + 7 * tpe < end; i += 8 * tpe) {
+    double v[8];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) v[u] = ent[i + u * tpe].src[off(ent[i + u * tpe])];
+    for (int u = 0; u < 8; ++u) v[u] = ent[i + u * tpe].src[off(ent[i + u * tpe])];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) acc = fma(ent[i + u * tpe].coef, v[u], acc);
+    for (int u = 0; u < 8; ++u) acc = fma(ent[i + u * tpe].coef, v[u], acc);
   }
   for (; i < end; i += tpe) acc = fma(ent[i].coef, ent[i].src[off(ent[i])], acc);
   for (int w = tpe >> 1; w > 0; w >>= 1) acc += __shfl_xor(acc, w, 64);
@@ -1201,16 +1279,18 @@ void launch_scatter(const ScatterDesc& d0, const double* src, double* out, hipSt
 // orbitals [alpha | beta]; other spin patterns follow from the canonical (alpha-first)
 // block by permuting upper and lower indices with the parity sign.
 // ---------------------------------------------------------------------------
+// 32-bit index arithmetic: (2 nA)^6 < 2^31 for nA <= 8 (larger active spaces are rejected)
 __global__ void expand_rdm_kernel(int nA, int rank, const double* __restrict__ blocks,
-                                  double* __restrict__ so, long long total) {
-  long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+                                  double* __restrict__ so, unsigned total) {
+  const unsigned i = blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= total) return;
-  const int n2 = 2 * nA;
+  const unsigned n2 = 2 * nA;
   int idx[6];
-  long long t = i;
+  unsigned t = i;
   for (int c = 2 * rank - 1; c >= 0; --c) {
-    idx[c] = (int)(t % n2);
-    t /= n2;
+    const unsigned q = t / n2;
+    idx[c] = (int)(t - q * n2);
+    t = q;
   }
   int spin[6], sp[6];
   int nbu = 0, nbl = 0;
@@ -1234,9 +1314,9 @@ __global__ void expand_rdm_kernel(int nA, int rank, const double* __restrict__ b
       par += pu[a] > pu[b];
       par += pl[a] > pl[b];
     }
-  long long bsz = 1;
+  int bsz = 1;
   for (int c = 0; c < 2 * rank; ++c) bsz *= nA;
-  long long off = 0;
+  int off = 0;
   for (int c = 0; c < rank; ++c) off = off * nA + sp[pu[c]];
   for (int c = 0; c < rank; ++c) off = off * nA + sp[rank + pl[c]];
   double v = blocks[nbu * bsz + off];
@@ -1248,28 +1328,32 @@ void launch_expand_rdm(int nA, int rank, const double* blocks, double* so, hipSt
   for (int c = 0; c < 2 * rank; ++c) total *= 2 * nA;
   if (total == 0) return;
   hipLaunchKernelGGL(expand_rdm_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, nA,
-                     rank, blocks, so, total);
+                     rank, blocks, so, (unsigned)total);
 }
 
 // lambda2[p,q,r,s] = G2 - (g_pr g_qs - g_ps g_qr);  C-convention over spin orbitals.
 __global__ void cumulant2_kernel(int n, const double* __restrict__ G1, const double* __restrict__ G2,
                                  double* __restrict__ L2) {
-  long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  long long total = (long long)n * n * n * n;
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int total = n * n * n * n;
   if (i >= total) return;
-  int s = i % n, r = (i / n) % n, q = (i / n / n) % n, p = i / n / n / n;
+  const int s = i % n, r = (i / n) % n, q = (i / n / n) % n, p = i / n / n / n;
   L2[i] = G2[i] - (G1[p * n + r] * G1[q * n + s] - G1[p * n + s] * G1[q * n + r]);
 }
 
 // lambda3 = G3 - det(g g g) - sum_{ij} (-1)^(i+j) g[P_i, S_j] lambda2[P\i, S\j]
 __global__ void cumulant3_kernel(int n, const double* __restrict__ G1, const double* __restrict__ L2,
                                  const double* __restrict__ G3, double* __restrict__ L3) {
-  long long i = blockIdx.x * (long long)blockDim.x + threadIdx.x;
-  long long total = (long long)n * n * n * n * n * n;
+  const unsigned i = blockIdx.x * blockDim.x + threadIdx.x;
+  const unsigned un = n, total = un * un * un * un * un * un;
   if (i >= total) return;
   int idx[6];
-  long long t = i;
-  for (int c = 5; c >= 0; --c) { idx[c] = (int)(t % n); t /= n; }
+  unsigned t = i;
+  for (int c = 5; c >= 0; --c) {
+    const unsigned q = t / un;
+    idx[c] = (int)(t - q * un);
+    t = q;
+  }
   const int* P = idx;
   const int* S = idx + 3;
   auto g = [&](int a, int b) { return G1[a * n + b]; };
@@ -1285,7 +1369,7 @@ __global__ void cumulant3_kernel(int n, const double* __restrict__ G1, const dou
       int l0 = S[(b + 1) % 3 < (b + 2) % 3 ? (b + 1) % 3 : (b + 2) % 3];
       int l1 = S[(b + 1) % 3 < (b + 2) % 3 ? (b + 2) % 3 : (b + 1) % 3];
       double sgn = ((a + b) & 1) ? -1.0 : 1.0;
-      gl += sgn * g(P[a], S[b]) * L2[((long long)(u0 * n + u1) * n + l0) * n + l1];
+      gl += sgn * g(P[a], S[b]) * L2[((u0 * n + u1) * n + l0) * n + l1];
     }
   }
   L3[i] = G3[i] - det - gl;
