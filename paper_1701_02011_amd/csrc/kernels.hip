@@ -1279,56 +1279,74 @@ void launch_scatter(const ScatterDesc& d0, const double* src, double* out, hipSt
 // orbitals [alpha | beta]; other spin patterns follow from the canonical (alpha-first)
 // block by permuting upper and lower indices with the parity sign.
 // ---------------------------------------------------------------------------
-// 32-bit index arithmetic: (2 nA)^6 < 2^31 for nA <= 8 (larger active spaces are rejected)
-__global__ void expand_rdm_kernel(int nA, int rank, const double* __restrict__ blocks,
-                                  double* __restrict__ so, unsigned total) {
-  const unsigned i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= total) return;
-  const unsigned n2 = 2 * nA;
-  int idx[6];
-  unsigned t = i;
-  for (int c = 2 * rank - 1; c >= 0; --c) {
-    const unsigned q = t / n2;
-    idx[c] = (int)(t - q * n2);
-    t = q;
+// Workgroup row blockIdx.x is one upper (creation) tuple, so its spins and block offset are
+// uniform; threads take the lower tuples.  The parity of the stable alpha-first sort of a
+// tuple is its number of (beta, alpha) pairs in that order.  Indices fit 32 bits:
+// (2 nA)^6 < 2^31 for nA <= 8 (larger active spaces are rejected).
+template <int R>
+__global__ void expand_rdm_kernel(int nA, const double* __restrict__ blocks, double* __restrict__ so) {
+  const int n2 = 2 * nA;
+  int nt = 1, bsz = 1;
+#pragma unroll
+  for (int c = 0; c < R; ++c) {
+    nt *= n2;
+    bsz *= nA * nA;
   }
-  int spin[6], sp[6];
-  int nbu = 0, nbl = 0;
-  for (int c = 0; c < 2 * rank; ++c) {
-    spin[c] = idx[c] >= nA;
-    sp[c] = idx[c] - spin[c] * nA;
+  const int l = blockIdx.y * blockDim.x + threadIdx.x;
+  if (l >= nt) return;
+  int su[R], pu[R], sl[R], pl[R];
+  int tu = blockIdx.x, tl = l;
+#pragma unroll
+  for (int c = R - 1; c >= 0; --c) {
+    const int xu = tu % n2, xl = tl % n2;
+    tu /= n2;
+    tl /= n2;
+    su[c] = xu >= nA;
+    pu[c] = xu - su[c] * nA;
+    sl[c] = xl >= nA;
+    pl[c] = xl - sl[c] * nA;
   }
-  for (int c = 0; c < rank; ++c) { nbu += spin[c]; nbl += spin[rank + c]; }
-  if (nbu != nbl) { so[i] = 0.0; return; }
-  // stable sort of upper and lower slots by spin; parity of each permutation
-  int pu[3], pl[3], k = 0, par = 0;
-  for (int s = 0; s < 2; ++s)
-    for (int c = 0; c < rank; ++c)
-      if (spin[c] == s) pu[k++] = c;
-  k = 0;
-  for (int s = 0; s < 2; ++s)
-    for (int c = 0; c < rank; ++c)
-      if (spin[rank + c] == s) pl[k++] = c;
-  for (int a = 0; a < rank; ++a)
-    for (int b = a + 1; b < rank; ++b) {
-      par += pu[a] > pu[b];
-      par += pl[a] > pl[b];
-    }
-  int bsz = 1;
-  for (int c = 0; c < 2 * rank; ++c) bsz *= nA;
+  int nbu = 0, nbl = 0, par = 0;
+#pragma unroll
+  for (int c = 0; c < R; ++c) {
+    nbu += su[c];
+    nbl += sl[c];
+  }
+  const long long o = (long long)blockIdx.x * nt + l;
+  if (nbu != nbl) {
+    so[o] = 0.0;
+    return;
+  }
+#pragma unroll
+  for (int a = 0; a < R; ++a)
+#pragma unroll
+    for (int b = a + 1; b < R; ++b) par += (su[a] > su[b]) + (sl[a] > sl[b]);
   int off = 0;
-  for (int c = 0; c < rank; ++c) off = off * nA + sp[pu[c]];
-  for (int c = 0; c < rank; ++c) off = off * nA + sp[rank + pl[c]];
-  double v = blocks[nbu * bsz + off];
-  so[i] = (par & 1) ? -v : v;
+#pragma unroll
+  for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+    for (int c = 0; c < R; ++c)
+      if (su[c] == sp) off = off * nA + pu[c];
+#pragma unroll
+  for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+    for (int c = 0; c < R; ++c)
+      if (sl[c] == sp) off = off * nA + pl[c];
+  const double v = blocks[(long long)nbu * bsz + off];
+  so[o] = (par & 1) ? -v : v;
 }
 
 void launch_expand_rdm(int nA, int rank, const double* blocks, double* so, hipStream_t st) {
-  long long total = 1;
-  for (int c = 0; c < 2 * rank; ++c) total *= 2 * nA;
-  if (total == 0) return;
-  hipLaunchKernelGGL(expand_rdm_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0, st, nA,
-                     rank, blocks, so, (unsigned)total);
+  int nt = 1;
+  for (int c = 0; c < rank; ++c) nt *= 2 * nA;
+  if (nt == 0) return;
+  const dim3 grid((unsigned)nt, (unsigned)((nt + 255) / 256));
+  if (rank == 1)
+    hipLaunchKernelGGL(expand_rdm_kernel<1>, grid, dim3(256), 0, st, nA, blocks, so);
+  else if (rank == 2)
+    hipLaunchKernelGGL(expand_rdm_kernel<2>, grid, dim3(256), 0, st, nA, blocks, so);
+  else
+    hipLaunchKernelGGL(expand_rdm_kernel<3>, grid, dim3(256), 0, st, nA, blocks, so);
 }
 
 // lambda2[p,q,r,s] = G2 - (g_pr g_qs - g_ps g_qr);  C-convention over spin orbitals.
@@ -1342,20 +1360,16 @@ __global__ void cumulant2_kernel(int n, const double* __restrict__ G1, const dou
 }
 
 // lambda3 = G3 - det(g g g) - sum_{ij} (-1)^(i+j) g[P_i, S_j] lambda2[P\i, S\j]
+// Workgroup row blockIdx.x is the upper triple P (uniform), threads take the lower triples S.
 __global__ void cumulant3_kernel(int n, const double* __restrict__ G1, const double* __restrict__ L2,
                                  const double* __restrict__ G3, double* __restrict__ L3) {
-  const unsigned i = blockIdx.x * blockDim.x + threadIdx.x;
-  const unsigned un = n, total = un * un * un * un * un * un;
-  if (i >= total) return;
-  int idx[6];
-  unsigned t = i;
-  for (int c = 5; c >= 0; --c) {
-    const unsigned q = t / un;
-    idx[c] = (int)(t - q * un);
-    t = q;
-  }
-  const int* P = idx;
-  const int* S = idx + 3;
+  const int n3 = n * n * n;
+  const int l = blockIdx.y * blockDim.x + threadIdx.x;
+  if (l >= n3) return;
+  const int u = blockIdx.x;
+  const int P[3] = {u / (n * n), (u / n) % n, u % n};
+  const int S[3] = {l / (n * n), (l / n) % n, l % n};
+  const long long i = (long long)u * n3 + l;
   auto g = [&](int a, int b) { return G1[a * n + b]; };
   // determinant part
   double det = g(P[0], S[0]) * (g(P[1], S[1]) * g(P[2], S[2]) - g(P[1], S[2]) * g(P[2], S[1]))
@@ -1389,9 +1403,9 @@ void launch_cumulants(int nA, const double* G1, const double* G2, const double* 
   hipLaunchKernelGGL(cumulant2_kernel, dim3((unsigned)((t2 + 255) / 256)), dim3(256), 0, st, n, G1,
                      G2, L2);
   if (G3 && L3) {
-    long long t3 = t2 * n * n;
-    hipLaunchKernelGGL(cumulant3_kernel, dim3((unsigned)((t3 + 255) / 256)), dim3(256), 0, st, n, G1,
-                       L2, G3, L3);
+    const int n3 = n * n * n;
+    hipLaunchKernelGGL(cumulant3_kernel, dim3((unsigned)n3, (unsigned)((n3 + 255) / 256)), dim3(256), 0, st,
+                       n, G1, L2, G3, L3);
   }
   hipLaunchKernelGGL(eta_kernel, dim3((n * n + 255) / 256), dim3(256), 0, st, n, G1, eta);
 }
@@ -1457,26 +1471,30 @@ __global__ void singles_kernel(AmpDims d, const double* __restrict__ Taa, const 
                                double* __restrict__ srca, double* __restrict__ srcb) {
   const double s = *sp;
   const int nH = d.nC + d.nA, nP = d.nA + d.nV, nA = d.nA, nC = d.nC;
-  int idx = blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= 2 * nP * nH) return;
+  // one wave per element, lane u * nA + x takes one term of the active sum (nA^2 <= 64),
+  // summed by a fixed butterfly
+  const int lane = threadIdx.x & 63;
+  const int idx = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+  if (idx >= 2 * nP * nH) return;   // the whole wave
   int spin = idx / (nP * nH);
   int e = idx - spin * nP * nH;
   int a = e / nH, i = e % nH;
   double c = 0.0;
   const long long sH = 1, sH2 = nH, sP = (long long)nH * nH, sP2 = (long long)nP * nH * nH;
-  for (int u = 0; u < nA; ++u) {
-    for (int x = 0; x < nA; ++x) {
-      double D = eps[nC + x] - eps[nC + u];
-      // t[a, x, i, u]: a (P), x (P, active at offset 0), i (H), u (H, active at offset nC)
-      long long o_axiu = a * sP2 + x * sP + i * sH2 + (nC + u) * sH;
-      if (spin == 0) {
-        c += D * (Taa[o_axiu] * ga[x * nA + u] + Tab[o_axiu] * gb[x * nA + u]);
-      } else {
-        long long o_xaui = x * sP2 + a * sP + (nC + u) * sH2 + i * sH;
-        c += D * (Tbb[o_axiu] * gb[x * nA + u] + Tab[o_xaui] * ga[x * nA + u]);
-      }
+  if (lane < nA * nA) {
+    const int u = lane / nA, x = lane - u * nA;
+    double D = eps[nC + x] - eps[nC + u];
+    // t[a, x, i, u]: a (P), x (P, active at offset 0), i (H), u (H, active at offset nC)
+    long long o_axiu = a * sP2 + x * sP + i * sH2 + (nC + u) * sH;
+    if (spin == 0) {
+      c = D * (Taa[o_axiu] * ga[x * nA + u] + Tab[o_axiu] * gb[x * nA + u]);
+    } else {
+      long long o_xaui = x * sP2 + a * sP + (nC + u) * sH2 + i * sH;
+      c = D * (Tbb[o_axiu] * gb[x * nA + u] + Tab[o_xaui] * ga[x * nA + u]);
     }
   }
+  for (int w = 32; w > 0; w >>= 1) c += __shfl_xor(c, w, 64);
+  if (lane != 0) return;
   double f = 0.0;
   const double* fp = spin ? fb : fa;
   if (fp) f = fp[e];
@@ -1493,9 +1511,9 @@ void launch_singles(AmpDims d, const double* T2aa, const double* T2ab, const dou
                     const double* fa, const double* fb, double* t1a, double* t1b, double* srca,
                     double* srcb, hipStream_t st) {
   int nH = d.nC + d.nA, nP = d.nA + d.nV;
-  int total = 2 * nP * nH;
+  int total = 2 * nP * nH;   // elements, one wave each
   if (total == 0) return;
-  hipLaunchKernelGGL(singles_kernel, dim3((total + 255) / 256), dim3(256), 0, st, d, T2aa, T2ab, T2bb,
+  hipLaunchKernelGGL(singles_kernel, dim3((total + 3) / 4), dim3(256), 0, st, d, T2aa, T2ab, T2bb,
                      g1a, g1b, eps, s, fa, fb, t1a, t1b, srca, srcb);
 }
 
