@@ -895,10 +895,10 @@ void launch_dot_group(const DotItem* items, int n, int blocks, double* partial, 
 // class given by which sub-space each index falls in; every entry of that class adds
 // coef * src[base + sum_k x_k ss_k], in entry order.
 // ---------------------------------------------------------------------------
-// Each workgroup covers 256 elements of one class (the box of index ranges the class
-// stands for, last index fastest), so the entry list it walks is the same for every lane:
-// entries load through the scalar cache and eight source values are in flight at a time,
-// summed in entry order.
+// Each workgroup covers 512 elements of one class (the box of index ranges the class
+// stands for, last index fastest; two per lane), so the entry list it walks is the same for
+// every lane: entries load through the scalar cache and four entries (eight source values)
+// are in flight at a time, summed in entry order.
 // tpe > 1 (small outputs, long entry lists): tpe consecutive lanes share an element, lane j
 // of the group sums entries j, j + tpe, ... and a fixed butterfly adds the group's partial
 // sums (deterministic for a given tpe).
@@ -928,36 +928,72 @@ __global__ __launch_bounds__(256) void gather_kernel(const GatherDesc* __restric
       len[k] = hi ? g.dim[k] - g.split[k] : g.split[k];
       cnt *= len[k];
     }
-  const int sub = threadIdx.x % tpe;
-  long long e = (long long)(b - g.blk[c]) * (256 / tpe) + threadIdx.x / tpe;
-  const bool live = e < cnt;   // whole groups of tpe lanes share e, so shuffles stay in a group
-  int x[4] = {0, 0, 0, 0};
+  // element e of the class -> its multi-index x and output offset
+  auto decode = [&](long long e, int* x) {
+    long long o = 0;
 #pragma unroll
-  for (int k = 3; k >= 0; --k)
-    if (k < g.rank) {
-      const long long q = e / len[k];
-      x[k] = lo[k] + (int)(e - q * len[k]);
-      e = q;
-    }
-  long long o = 0;
+    for (int k = 3; k >= 0; --k)
+      if (k < g.rank) {
+        const long long q = e / len[k];
+        x[k] = lo[k] + (int)(e - q * len[k]);
+        e = q;
+      }
 #pragma unroll
-  for (int k = 0; k < 4; ++k)
-    if (k < g.rank) o = o * g.dim[k] + x[k];
-  double acc = 0.0;
-  const int end = live ? g.cls[c + 1] : g.cls[c];
-  auto off = [&](const GatherEntry& en) {
+    for (int k = 0; k < 4; ++k)
+      if (k < g.rank) o = o * g.dim[k] + x[k];
+    return o;
+  };
+  auto off = [&](const GatherEntry& en, const int* x) {
     return en.base + (long long)x[0] * en.ss[0] + (long long)x[1] * en.ss[1] + (long long)x[2] * en.ss[2] +
            (long long)x[3] * en.ss[3];
   };
-  int i = g.cls[c] + sub;
-  for (; i + 7 * tpe < end; i += 8 * tpe) {
-    double v[8];
+  if (tpe == 1) {
+    // two elements per lane (e and e + 256): each entry's scalar loads serve both
+    const long long e0 = (long long)(b - g.blk[c]) * 512 + threadIdx.x;
+    const bool live0 = e0 < cnt, live1 = e0 + 256 < cnt;
+    int x0[4] = {0, 0, 0, 0}, x1[4] = {0, 0, 0, 0};
+    const long long o0 = decode(e0, x0);
+    const long long o1 = decode(live1 ? e0 + 256 : e0, x1);
+    double acc0 = 0.0, acc1 = 0.0;
+    const int end = live0 ? g.cls[c + 1] : g.cls[c];
+    int i = g.cls[c];
+    for (; i + 3 < end; i += 4) {
+      double v0[4], v1[4];
 #pragma unroll
-    for (int u = 0; u < 8; ++u) v[u] = ent[i + u * tpe].src[off(ent[i + u * tpe])];
+      for (int u = 0; u < 4; ++u) {
+        v0[u] = ent[i + u].src[off(ent[i + u], x0)];
+        v1[u] = ent[i + u].src[off(ent[i + u], x1)];
+      }
 #pragma unroll
-    for (int u = 0; u < 8; ++u) acc = fma(ent[i + u * tpe].coef, v[u], acc);
+      for (int u = 0; u < 4; ++u) {
+        acc0 = fma(ent[i + u].coef, v0[u], acc0);
+        acc1 = fma(ent[i + u].coef, v1[u], acc1);
+      }
+    }
+    for (; i < end; ++i) {
+      acc0 = fma(ent[i].coef, ent[i].src[off(ent[i], x0)], acc0);
+      acc1 = fma(ent[i].coef, ent[i].src[off(ent[i], x1)], acc1);
+    }
+    if (live0) out[o0] += acc0;
+    if (live1) out[o1] += acc1;
+    return;
   }
-  for (; i < end; i += tpe) acc = fma(ent[i].coef, ent[i].src[off(ent[i])], acc);
+  const int sub = threadIdx.x % tpe;
+  const long long e = (long long)(b - g.blk[c]) * (256 / tpe) + threadIdx.x / tpe;
+  const bool live = e < cnt;   // whole groups of tpe lanes share e, so shuffles stay in a group
+  int x[4] = {0, 0, 0, 0};
+  const long long o = decode(e, x);
+  double acc = 0.0;
+  const int end = live ? g.cls[c + 1] : g.cls[c];
+  int i = g.cls[c] + sub;
+  for (; i + 3 * tpe < end; i += 4 * tpe) {
+    double v[4];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) v[u] = ent[i + u * tpe].src[off(ent[i + u * tpe], x)];
+#pragma unroll
+    for (int u = 0; u < 4; ++u) acc = fma(ent[i + u * tpe].coef, v[u], acc);
+  }
+  for (; i < end; i += tpe) acc = fma(ent[i].coef, ent[i].src[off(ent[i], x)], acc);
   for (int w = tpe >> 1; w > 0; w >>= 1) acc += __shfl_xor(acc, w, 64);
   if (live && sub == 0) out[o] += acc;
 }
@@ -981,7 +1017,7 @@ long long gather_prepare(GatherDesc& g) {
     if (g.cls[c + 1] == g.cls[c]) continue;
     long long cnt = 1;
     for (int k = 0; k < g.rank; ++k) cnt *= ((c >> k) & 1) ? g.dim[k] - g.split[k] : g.split[k];
-    blocks += (cnt * tpe + 255) / 256;
+    blocks += tpe == 1 ? (cnt + 511) / 512 : (cnt * tpe + 255) / 256;
   }
   for (int c = ncls; c <= 16; ++c) g.blk[c] = (int)blocks;
   return blocks;
