@@ -1030,20 +1030,33 @@ struct Exec {
     throw Error(DSRG_E_HIP, "internal: output axis/letter space pair");
   }
 
+  // Components in the order of a's strides, largest first, so that the index the dot
+  // walks fastest is a's contiguous one (ties: b's strides).
   static DotDesc dot_desc(const Opnd& a, const Opnd& b, const LetterRange& lr) {
     DotDesc dd;
     dd.nk = (int)a.letters.size();
     if (dd.nk > 2 * kMaxComp || a.letters.size() != b.letters.size())
       throw Error(DSRG_E_HIP, "internal: scalar product shape");
+    std::vector<int> ord(dd.nk);
+    for (int i = 0; i < dd.nk; ++i) ord[i] = i;
+    auto bstride = [&](int i) {
+      const size_t j = b.letters.find(a.letters[i]);
+      return j == std::string::npos ? 0LL : std::llabs(b.stride[j]);
+    };
+    std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) {
+      const long long sx = std::llabs(a.stride[x]), sy = std::llabs(a.stride[y]);
+      return sx != sy ? sx > sy : bstride(x) > bstride(y);
+    });
     dd.K = 1;
-    for (int i = 0; i < dd.nk; ++i) {
+    for (int oi = 0; oi < dd.nk; ++oi) {
+      const int i = ord[oi];
       char l = a.letters[i];
       size_t j = b.letters.find(l);
       if (j == std::string::npos) throw Error(DSRG_E_HIP, "internal: scalar product letters");
-      dd.kd[i] = lr.len.at(l);
-      dd.as[i] = a.stride[i];
-      dd.bs[i] = b.stride[j];
-      dd.K *= dd.kd[i];
+      dd.kd[oi] = lr.len.at(l);
+      dd.as[oi] = a.stride[i];
+      dd.bs[oi] = b.stride[j];
+      dd.K *= dd.kd[oi];
     }
     return dd;
   }
@@ -1093,7 +1106,25 @@ struct Exec {
         // the final result of a tensor product is laid out like its first output, so the
         // gather reads that entry with unit stride
         const bool last = ops.size() == 2 && !P.res.empty();
-        Opnd r = result_operand(g, ml, nl, lr, last ? P.s[0].letters : std::string());
+        // the operand a scalar product's final dot pairs with this result, if any: the
+        // result takes its memory order so the dot reads both contiguously
+        std::string lay = last ? P.s[0].letters : std::string();
+        if (P.res.empty() && ops.size() == 3) {
+          const Opnd& o = ops[3 - bi - bj];
+          std::string mine = ml + nl, other = o.letters;
+          std::string s1 = mine, s2 = other;
+          std::sort(s1.begin(), s1.end());
+          std::sort(s2.begin(), s2.end());
+          if (s1 == s2) {
+            std::vector<int> ord(other.size());
+            for (size_t i = 0; i < ord.size(); ++i) ord[i] = (int)i;
+            std::stable_sort(ord.begin(), ord.end(), [&](int x, int y) {
+              return std::llabs(o.stride[x]) > std::llabs(o.stride[y]);
+            });
+            for (int i : ord) lay += other[i];
+          }
+        }
+        Opnd r = result_operand(g, ml, nl, lr, lay);
         r.toff = take(r.lim);
         if (lev.size() <= level) {
           lev.resize(level + 1);

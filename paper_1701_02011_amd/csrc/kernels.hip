@@ -49,17 +49,23 @@ __device__ __forceinline__ void decode2(long long idx, int n, const int* d, cons
 }
 
 // the same for idx < 2^31 with the divisions as multiply and shift
+// (the component loop is unrolled over the arrays' bound NC so the descriptor fields stay in
+// registers across a caller's loop instead of being reloaded)
+template <int NC>
 __device__ __forceinline__ void decode2_fast(unsigned idx, int n, const int* d, const DivMagic& m,
                                              const long long* sa, const long long* sb, long long& oa,
                                              long long& ob) {
   oa = 0;
   ob = 0;
-  for (int c = n - 1; c >= 0; --c) {
-    const unsigned q = (unsigned)(((unsigned long long)idx * m.mag[c]) >> m.sh[c]);
-    const long long r = (long long)(idx - q * (unsigned)d[c]);
-    oa += r * sa[c];
-    if (sb) ob += r * sb[c];
-    idx = q;
+#pragma unroll
+  for (int c = NC - 1; c >= 0; --c) {
+    if (c < n) {
+      const unsigned q = (unsigned)(((unsigned long long)idx * m.mag[c]) >> m.sh[c]);
+      const long long r = (long long)(idx - q * (unsigned)d[c]);
+      oa += r * sa[c];
+      if (sb) ob += r * sb[c];
+      idx = q;
+    }
   }
 }
 
@@ -849,7 +855,38 @@ __global__ __launch_bounds__(256) void dot_group_kernel(const DotItem* __restric
   const int j = b - it.blk0;
   double sum = 0.0;
   if (it.d.K < (1LL << 31)) {
+    // the decode tables copied to registers once (constant indices after unrolling), then
     // four index pairs decoded and loaded before they are summed (same order as one at a time)
+    constexpr int NC = 2 * kMaxComp;
+    const int nk = it.d.nk;
+    unsigned kd[NC], mag[NC];
+    int sh[NC];
+    long long as[NC], bs[NC];
+#pragma unroll
+    for (int c = 0; c < NC; ++c) {
+      const bool on = c < nk;
+      kd[c] = on ? (unsigned)it.d.kd[c] : 1u;
+      mag[c] = on ? it.d.dm.mag[c] : 0u;
+      sh[c] = on ? it.d.dm.sh[c] : 0;
+      as[c] = on ? it.d.as[c] : 0;
+      bs[c] = on ? it.d.bs[c] : 0;
+    }
+    auto dec = [&](unsigned idx, long long& oa, long long& ob) {
+      oa = 0;
+      ob = 0;
+#pragma unroll
+      for (int c = NC - 1; c >= 0; --c) {
+        if (c < nk) {
+          const unsigned q = (unsigned)(((unsigned long long)idx * mag[c]) >> sh[c]);
+          const long long r = (long long)(idx - q * kd[c]);
+          oa += r * as[c];
+          ob += r * bs[c];
+          idx = q;
+        }
+      }
+    };
+    const double* __restrict__ A = it.A;
+    const double* __restrict__ B = it.B;
     const unsigned K = (unsigned)it.d.K, stride = 256u * (unsigned)it.nblk;
     unsigned i = (unsigned)j * 256u + threadIdx.x;
     for (; i < K && K - i > 3u * stride; i += 4u * stride) {
@@ -857,17 +894,17 @@ __global__ __launch_bounds__(256) void dot_group_kernel(const DotItem* __restric
 #pragma unroll
       for (int u = 0; u < 4; ++u) {
         long long oa, ob;
-        decode2_fast(i + u * stride, it.d.nk, it.d.kd, it.d.dm, it.d.as, it.d.bs, oa, ob);
-        a[u] = it.A[oa];
-        bv[u] = it.B[ob];
+        dec(i + u * stride, oa, ob);
+        a[u] = A[oa];
+        bv[u] = B[ob];
       }
 #pragma unroll
       for (int u = 0; u < 4; ++u) sum += a[u] * bv[u];
     }
     for (; i < K; i += stride) {
       long long oa, ob;
-      decode2_fast(i, it.d.nk, it.d.kd, it.d.dm, it.d.as, it.d.bs, oa, ob);
-      sum += it.A[oa] * it.B[ob];
+      dec(i, oa, ob);
+      sum += A[oa] * B[ob];
     }
   } else {
     for (long long i = j * 256LL + threadIdx.x; i < it.d.K; i += 256LL * it.nblk) {
@@ -897,11 +934,13 @@ void launch_dot_group(const DotItem* items, int n, int blocks, double* partial, 
 // ---------------------------------------------------------------------------
 // Each workgroup covers 512 elements of one class (the box of index ranges the class
 // stands for, last index fastest; two per lane), so the entry list it walks is the same for
-// every lane: entries load through the scalar cache and four entries (eight source values)
-// are in flight at a time, summed in entry order.
+// every lane: entries load through the scalar cache and four entries (eight source values
+// per lane) are in flight at a time, summed in entry order.
 // tpe > 1 (small outputs, long entry lists): tpe consecutive lanes share an element, lane j
 // of the group sums entries j, j + tpe, ... and a fixed butterfly adds the group's partial
 // sums (deterministic for a given tpe).
+constexpr int kGatherEpl = 2;   // output elements per lane when lanes do not share one
+constexpr int kGatherEif = 8 / kGatherEpl;   // entries in flight (eight loads per lane)
 __global__ __launch_bounds__(256) void gather_kernel(const GatherDesc* __restrict__ descs, int nd) {
   // output of this workgroup: the last with blk0 <= blockIdx.x
   int dl = 0, dh = nd - 1;
@@ -948,34 +987,40 @@ __global__ __launch_bounds__(256) void gather_kernel(const GatherDesc* __restric
            (long long)x[3] * en.ss[3];
   };
   if (tpe == 1) {
-    // two elements per lane (e and e + 256): each entry's scalar loads serve both
-    const long long e0 = (long long)(b - g.blk[c]) * 512 + threadIdx.x;
-    const bool live0 = e0 < cnt, live1 = e0 + 256 < cnt;
-    int x0[4] = {0, 0, 0, 0}, x1[4] = {0, 0, 0, 0};
-    const long long o0 = decode(e0, x0);
-    const long long o1 = decode(live1 ? e0 + 256 : e0, x1);
-    double acc0 = 0.0, acc1 = 0.0;
-    const int end = live0 ? g.cls[c + 1] : g.cls[c];
+    // kGatherEpl elements per lane (e, e + 256, ...): each entry's scalar loads serve all
+    const long long e0 = (long long)(b - g.blk[c]) * (256 * kGatherEpl) + threadIdx.x;
+    int x[kGatherEpl][4];
+    long long o[kGatherEpl];
+    bool live[kGatherEpl];
+#pragma unroll
+    for (int j = 0; j < kGatherEpl; ++j) {
+      live[j] = e0 + 256 * j < cnt;
+#pragma unroll
+      for (int k = 0; k < 4; ++k) x[j][k] = 0;
+      o[j] = decode(live[j] ? e0 + 256 * j : e0, x[j]);   // dead slots repeat element e0
+    }
+    double acc[kGatherEpl];
+#pragma unroll
+    for (int j = 0; j < kGatherEpl; ++j) acc[j] = 0.0;
+    const int end = live[0] ? g.cls[c + 1] : g.cls[c];
     int i = g.cls[c];
-    for (; i + 3 < end; i += 4) {
-      double v0[4], v1[4];
+    for (; i + kGatherEif - 1 < end; i += kGatherEif) {
+      double v[kGatherEif][kGatherEpl];
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        v0[u] = ent[i + u].src[off(ent[i + u], x0)];
-        v1[u] = ent[i + u].src[off(ent[i + u], x1)];
-      }
+      for (int u = 0; u < kGatherEif; ++u)
 #pragma unroll
-      for (int u = 0; u < 4; ++u) {
-        acc0 = fma(ent[i + u].coef, v0[u], acc0);
-        acc1 = fma(ent[i + u].coef, v1[u], acc1);
-      }
+        for (int j = 0; j < kGatherEpl; ++j) v[u][j] = ent[i + u].src[off(ent[i + u], x[j])];
+#pragma unroll
+      for (int u = 0; u < kGatherEif; ++u)
+#pragma unroll
+        for (int j = 0; j < kGatherEpl; ++j) acc[j] = fma(ent[i + u].coef, v[u][j], acc[j]);
     }
-    for (; i < end; ++i) {
-      acc0 = fma(ent[i].coef, ent[i].src[off(ent[i], x0)], acc0);
-      acc1 = fma(ent[i].coef, ent[i].src[off(ent[i], x1)], acc1);
-    }
-    if (live0) out[o0] += acc0;
-    if (live1) out[o1] += acc1;
+    for (; i < end; ++i)
+#pragma unroll
+      for (int j = 0; j < kGatherEpl; ++j) acc[j] = fma(ent[i].coef, ent[i].src[off(ent[i], x[j])], acc[j]);
+#pragma unroll
+    for (int j = 0; j < kGatherEpl; ++j)
+      if (live[j]) out[o[j]] += acc[j];
     return;
   }
   const int sub = threadIdx.x % tpe;
@@ -1017,7 +1062,7 @@ long long gather_prepare(GatherDesc& g) {
     if (g.cls[c + 1] == g.cls[c]) continue;
     long long cnt = 1;
     for (int k = 0; k < g.rank; ++k) cnt *= ((c >> k) & 1) ? g.dim[k] - g.split[k] : g.split[k];
-    blocks += tpe == 1 ? (cnt + 511) / 512 : (cnt * tpe + 255) / 256;
+    blocks += tpe == 1 ? (cnt + 256 * kGatherEpl - 1) / (256 * kGatherEpl) : (cnt * tpe + 255) / 256;
   }
   for (int c = ncls; c <= 16; ++c) g.blk[c] = (int)blocks;
   return blocks;
@@ -1042,7 +1087,7 @@ __global__ __launch_bounds__(256) void dot_kernel(DotDesc d, const double* __res
   const bool fast = d.K < (1LL << 31);
   for (long long i = blockIdx.x * 256LL + threadIdx.x; i < d.K; i += 256LL * gridDim.x) {
     long long oa, ob;
-    if (fast) decode2_fast((unsigned)i, d.nk, d.kd, d.dm, d.as, d.bs, oa, ob);
+    if (fast) decode2_fast<2 * kMaxComp>((unsigned)i, d.nk, d.kd, d.dm, d.as, d.bs, oa, ob);
     else decode2(i, d.nk, d.kd, d.as, d.bs, oa, ob);
     sum += A[oa] * B[ob];
   }
@@ -1096,7 +1141,7 @@ __global__ __launch_bounds__(256) void pack_kernel(PackDesc d, const double* __r
   for (long long e = blockIdx.x * 256LL + threadIdx.x; e < d.n; e += 256LL * gridDim.x) {
     long long off = 0, unused;
     if (fast) {
-      decode2_fast((unsigned)e, d.rank, d.d, d.dm, d.ss, nullptr, off, unused);
+      decode2_fast<2 * kMaxComp>((unsigned)e, d.rank, d.d, d.dm, d.ss, nullptr, off, unused);
     } else {
       long long idx = e;
       for (int c = d.rank - 1; c >= 0; --c) {
@@ -1295,7 +1340,7 @@ __global__ __launch_bounds__(256) void scatter_kernel(ScatterDesc d, const doubl
   const bool fast = d.n < (1LL << 31);
   for (long long i = blockIdx.x * 256LL + threadIdx.x; i < d.n; i += 256LL * gridDim.x) {
     long long os, oo;
-    if (fast) decode2_fast((unsigned)i, d.rank, d.d, d.dm, d.ss, d.so, os, oo);
+    if (fast) decode2_fast<kMaxComp>((unsigned)i, d.rank, d.d, d.dm, d.ss, d.so, os, oo);
     else decode2(i, d.rank, d.d, d.ss, d.so, os, oo);
     out[oo] += d.coef * src[os];
   }
