@@ -2043,17 +2043,26 @@ struct Exec {
           const int nPl = nP, nHl = nH, nai = (int)na, nsi = (int)ns;
           const int npi = (int)np, np1i = (int)np1, m0 = (int)r0, ldxi = (int)ldx;
           const bool anti_part = na > 0 && kp > 0 && np > 0;
-          if (anti_part) {
-            op([jb, nPl, b0, qoff, nq, ra, nai, Va](hipStream_t s) {
-              launch_ladder_pack_v(jb, nPl, b0, qoff, nq, ra, nai, 0, Va, s);
+          if (anti_part && ns > 0) {
+            // both parts from one read of the batch: the rows p <= q carry the strict ones
+            const long long r0l = r0;
+            op([jb, nPl, b0, qoff, nq, rsy, nsi, Vs, Va, r0l](hipStream_t s) {
+              launch_ladder_pack_v(jb, nPl, b0, qoff, nq, rsy, nsi, 1, Vs, s, Va, r0l);
             });
             ++n_launch;
-          }
-          if (ns > 0) {
-            op([jb, nPl, b0, qoff, nq, rsy, nsi, Vs](hipStream_t s) {
-              launch_ladder_pack_v(jb, nPl, b0, qoff, nq, rsy, nsi, 1, Vs, s);
-            });
-            ++n_launch;
+          } else {
+            if (anti_part) {
+              op([jb, nPl, b0, qoff, nq, ra, nai, Va](hipStream_t s) {
+                launch_ladder_pack_v(jb, nPl, b0, qoff, nq, ra, nai, 0, Va, s);
+              });
+              ++n_launch;
+            }
+            if (ns > 0) {
+              op([jb, nPl, b0, qoff, nq, rsy, nsi, Vs](hipStream_t s) {
+                launch_ladder_pack_v(jb, nPl, b0, qoff, nq, rsy, nsi, 1, Vs, s);
+              });
+              ++n_launch;
+            }
           }
           role_now = kRoleLadder;
           // Xa[row][j np + n]: block j of every antisymmetric part in one contraction

@@ -194,9 +194,12 @@ struct LadderPair {
 // Vp[row][k] = (p x|q y) - (p y|q x)              (sym = 0: strict pairs x < y)
 // Vp[row][k] = ((p x|q y) + (p y|q x)) w_xy      (sym = 1: pairs x <= y, w = 1/2 on x == y)
 // with (p, q) = rowtab[row] and k the position of (x, y) in x-major order of the pairs; every
-// q of the rows lies in [qoff, qoff + nq)
+// q of the rows lies in [qoff, qoff + nq).  With sym = 1 and Va given, the same pass also
+// writes the sym = 0 row of every strict pair (m >= 0) into Va[m - m0] (one read of the
+// integrals for both parts).
 void launch_ladder_pack_v(const double* jb, int nP, int b0, int qoff, int nq, const LadderPair* rowtab,
-                          int rows, int sym, double* Vp, hipStream_t st);
+                          int rows, int sym, double* Vp, hipStream_t st, double* Va = nullptr,
+                          long long m0 = 0);
 // Tp[n][k] from T [P][P][H][H], (x, y) = ktab[k], (I, J) = ntab[n]:
 // mode 0: T[x][y][I][J];  mode 1: (T[x][y][I][J] + T[y][x][I][J]) / 2;
 // mode 2: (T[x][y][I][J] - T[y][x][I][J]) / 2

@@ -1196,7 +1196,8 @@ __global__ __launch_bounds__(256) void ladder_pack_v_kernel(const double* __rest
                                                             int qoff, int nq,
                                                             const LadderPair* __restrict__ rowtab, int rows,
                                                             int ntp, int sym, long long kpx,
-                                                            double* __restrict__ Vp) {
+                                                            double* __restrict__ Vp, double* __restrict__ Va,
+                                                            long long m0) {
   __shared__ double A[kPackTile][kPackTile + 1], Bm[kPackTile][kPackTile + 1];
   const int nT = (nP + kPackTile - 1) / kPackTile;
   const long long sq = nP, sx = (long long)nq * nP, sp = sx * nP;
@@ -1223,14 +1224,18 @@ __global__ __launch_bounds__(256) void ladder_pack_v_kernel(const double* __rest
     }
     __syncthreads();
     double* out = Vp + (long long)row * kpx;
+    // strict pairs' antisymmetric row in the same pass (sym mode with Va)
+    double* outa = (Va && pq.m >= 0) ? Va + (pq.m - m0) * ((long long)nP * (nP - 1) / 2) : nullptr;
     for (int e = threadIdx.x; e < kPackTile * kPackTile; e += 256) {
       const int i = e / kPackTile, j = e % kPackTile;
       const int x = X0 + i, y = Y0 + j;
       if (x >= nP || y >= nP || (sym ? y < x : y <= x)) continue;
       const double u = A[i][j], v = Bm[j][i];   // M[x][y], M[y][x]
       const long long xl = x;
-      const long long k = sym ? xl * nP - xl * (xl - 1) / 2 + (y - x) : xl * nP - xl * (xl + 1) / 2 + (y - x - 1);
+      const long long ka = xl * nP - xl * (xl + 1) / 2 + (y - x - 1);
+      const long long k = sym ? xl * nP - xl * (xl - 1) / 2 + (y - x) : ka;
       out[k] = sym ? (x == y ? u : u + v) : u - v;
+      if (outa && y > x) outa[ka] = u - v;
     }
   }
 }
@@ -1299,14 +1304,14 @@ static unsigned grid_for(long long n) {
 }
 
 void launch_ladder_pack_v(const double* jb, int nP, int b0, int qoff, int nq, const LadderPair* rowtab,
-                          int rows, int sym, double* Vp, hipStream_t st) {
+                          int rows, int sym, double* Vp, hipStream_t st, double* Va, long long m0) {
   const long long kpx = sym ? (long long)nP * (nP + 1) / 2 : (long long)nP * (nP - 1) / 2;
   if (rows <= 0 || kpx <= 0) return;
   const int nT = (nP + kPackTile - 1) / kPackTile, ntp = nT * (nT + 1) / 2;
   const long long work = (long long)rows * ntp;
   const unsigned grid = (unsigned)std::min<long long>(work, 1LL << 20);
   hipLaunchKernelGGL(ladder_pack_v_kernel, dim3(grid), dim3(256), 0, st, jb, nP, b0, qoff, nq, rowtab, rows, ntp,
-                     sym, kpx, Vp);
+                     sym, kpx, Vp, sym ? Va : nullptr, m0);
 }
 
 void launch_ladder_pack_t(const double* T, int nP, int nH, const LadderPair* ktab, int kp,
