@@ -1446,32 +1446,51 @@ __global__ void cumulant2_kernel(int n, const double* __restrict__ G1, const dou
 }
 
 // lambda3 = G3 - det(g g g) - sum_{ij} (-1)^(i+j) g[P_i, S_j] lambda2[P\i, S\j]
-// Workgroup row blockIdx.x is the upper triple P (uniform), threads take the lower triples S.
-__global__ void cumulant3_kernel(int n, const double* __restrict__ G1, const double* __restrict__ L2,
-                                 const double* __restrict__ G3, double* __restrict__ L3) {
-  const int n3 = n * n * n;
+// Workgroup row blockIdx.x is the upper triple P (uniform), threads take the lower triples S;
+// the three rows g[P_a][*] and the three slices lambda2[P\a][*][*] the row needs are staged
+// in LDS first (n <= 16).
+__global__ __launch_bounds__(256) void cumulant3_kernel(int n, const double* __restrict__ G1,
+                                                        const double* __restrict__ L2,
+                                                        const double* __restrict__ G3,
+                                                        double* __restrict__ L3) {
+  __shared__ double gs[3][16], ls[3][16 * 16];
+  const int n2 = n * n, n3 = n2 * n;
+  const int u = blockIdx.x;
+  const int P[3] = {u / n2, (u / n) % n, u % n};
+  // P without its a-th member, in order
+  const int U0[3] = {P[1], P[0], P[0]}, U1[3] = {P[2], P[2], P[1]};
+  for (int t = threadIdx.x; t < 3 * n; t += blockDim.x) {
+    const int a = t / n, c = t - a * n;
+    gs[a][c] = G1[P[a] * n + c];
+  }
+  for (int t = threadIdx.x; t < 3 * n2; t += blockDim.x) {
+    const int a = t / n2, c = t - a * n2;
+    ls[a][c] = L2[(long long)(U0[a] * n + U1[a]) * n2 + c];
+  }
+  __syncthreads();
   const int l = blockIdx.y * blockDim.x + threadIdx.x;
   if (l >= n3) return;
-  const int u = blockIdx.x;
-  const int P[3] = {u / (n * n), (u / n) % n, u % n};
-  const int S[3] = {l / (n * n), (l / n) % n, l % n};
+  const int S[3] = {l / n2, (l / n) % n, l % n};
   const long long i = (long long)u * n3 + l;
-  auto g = [&](int a, int b) { return G1[a * n + b]; };
+  double g[3][3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
+    for (int b = 0; b < 3; ++b) g[a][b] = gs[a][S[b]];
   // determinant part
-  double det = g(P[0], S[0]) * (g(P[1], S[1]) * g(P[2], S[2]) - g(P[1], S[2]) * g(P[2], S[1]))
-             - g(P[0], S[1]) * (g(P[1], S[0]) * g(P[2], S[2]) - g(P[1], S[2]) * g(P[2], S[0]))
-             + g(P[0], S[2]) * (g(P[1], S[0]) * g(P[2], S[1]) - g(P[1], S[1]) * g(P[2], S[0]));
+  const double det = g[0][0] * (g[1][1] * g[2][2] - g[1][2] * g[2][1])
+                   - g[0][1] * (g[1][0] * g[2][2] - g[1][2] * g[2][0])
+                   + g[0][2] * (g[1][0] * g[2][1] - g[1][1] * g[2][0]);
+  // S without its b-th member, in order
+  const int V0[3] = {S[1], S[0], S[0]}, V1[3] = {S[2], S[2], S[1]};
   double gl = 0.0;
-  for (int a = 0; a < 3; ++a) {
-    int u0 = P[(a + 1) % 3 < (a + 2) % 3 ? (a + 1) % 3 : (a + 2) % 3];
-    int u1 = P[(a + 1) % 3 < (a + 2) % 3 ? (a + 2) % 3 : (a + 1) % 3];
+#pragma unroll
+  for (int a = 0; a < 3; ++a)
+#pragma unroll
     for (int b = 0; b < 3; ++b) {
-      int l0 = S[(b + 1) % 3 < (b + 2) % 3 ? (b + 1) % 3 : (b + 2) % 3];
-      int l1 = S[(b + 1) % 3 < (b + 2) % 3 ? (b + 2) % 3 : (b + 1) % 3];
-      double sgn = ((a + b) & 1) ? -1.0 : 1.0;
-      gl += sgn * g(P[a], S[b]) * L2[((u0 * n + u1) * n + l0) * n + l1];
+      const double sgn = ((a + b) & 1) ? -1.0 : 1.0;
+      gl += sgn * g[a][b] * ls[a][V0[b] * n + V1[b]];
     }
-  }
   L3[i] = G3[i] - det - gl;
 }
 
