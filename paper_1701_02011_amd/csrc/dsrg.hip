@@ -238,7 +238,14 @@ using DevOp = std::function<void(hipStream_t)>;
 struct OpLog {
   hipStream_t st;
   std::vector<DevOp>* rec = nullptr;
+  hipStream_t side = nullptr;   // set: ops of a forked branch, run on this stream
   void operator()(DevOp f) {
+    if (side) {
+      DevOp g = [f = std::move(f), sd = side](hipStream_t) { f(sd); };
+      g(st);
+      if (rec) rec->push_back(std::move(g));
+      return;
+    }
     f(st);
     if (rec) rec->push_back(std::move(f));
   }
@@ -364,6 +371,9 @@ struct Exec {
   }
 
   void gett(const GettDesc& g0, const double* A, const double* Bp, double* C, int role) {
+    // the split-K and packing buffers are shared by every serial contraction: one on the
+    // main stream waits for an open side branch
+    if (side_pending && !op.side) join_side();
     GettDesc g = g0;
     // A short inner k component wastes most of each zero-padded k step: packing both
     // operands makes the whole k range one contiguous component (steps of kGettBK).
@@ -433,6 +443,53 @@ struct Exec {
       (void)hipEventDestroy(r.a);
       (void)hipEventDestroy(r.b);
     }
+    for (auto e : side_ev) (void)hipEventDestroy(e);
+    if (side_st) (void)hipStreamDestroy(side_st);
+  }
+
+  // A branch beside the main sequence (the (PP|PP) ladder beside the grouped launches of
+  // the same commutators): fork_side() orders it after everything recorded so far, the ops
+  // recorded until end_side() run on a second stream (default priority), and join_side()
+  // orders the main sequence after them.  A capture records the same fork and join as
+  // graph dependencies.  The events and the stream live until the executor ends.
+  hipStream_t side_st = nullptr, main_st = nullptr;
+  std::vector<hipEvent_t> side_ev;
+  bool side_pending = false;
+  hipEvent_t side_event() {
+    hipEvent_t e = nullptr;
+    HIPCHECK(hipEventCreateWithFlags(&e, hipEventDisableTiming));
+    side_ev.push_back(e);
+    return e;
+  }
+  void fork_side() {
+    if (op.side || side_pending) throw Error(DSRG_E_HIP, "internal: nested side branch");
+    if (!side_st) HIPCHECK(hipStreamCreateWithFlags(&side_st, hipStreamNonBlocking));
+    hipEvent_t e = side_event();
+    hipStream_t sd = side_st;
+    op([e, sd](hipStream_t s) {
+      HIPCHECK(hipEventRecord(e, s));
+      HIPCHECK(hipStreamWaitEvent(sd, e, 0));
+    });
+    main_st = st;
+    st = sd;   // uploads of the branch go in its order
+    op.side = sd;
+    side_pending = true;
+  }
+  void end_side() {
+    if (!op.side) return;
+    op.side = nullptr;
+    st = main_st;
+  }
+  void join_side() {
+    if (!side_pending) return;
+    end_side();
+    hipEvent_t e = side_event();
+    hipStream_t sd = side_st;
+    op([e, sd](hipStream_t s) {
+      HIPCHECK(hipEventRecord(e, sd));
+      HIPCHECK(hipStreamWaitEvent(s, e, 0));
+    });
+    side_pending = false;
   }
 
   void set(const std::string& name, double* p, const char* axes, int sym = 0) {
@@ -1067,7 +1124,8 @@ struct Exec {
   // gather per output tensor (fixed entry order, so the sums are deterministic).  Returns
   // false, having launched nothing, when the temporaries would exceed group_cap bytes.
   bool run_grouped(const std::vector<std::pair<int, const TProduct*>>& prods,
-                   std::map<std::string, TensorRef>& outs, double* scalar_out) {
+                   std::map<std::string, TensorRef>& outs, double* scalar_out,
+                   const std::function<void()>& on_start = nullptr) {
     struct Fix {
       long long a, b, c;   // arena offsets of A, B, C (-1: not a temporary)
     };
@@ -1243,6 +1301,7 @@ struct Exec {
     if (8 * (arena + part_elems) > group_cap) plan_splits(false);
     long long bytes = 8 * (arena + part_elems);
     if (bytes > group_cap) return false;
+    if (on_start) on_start();   // e.g. a side branch that overlaps the launches below
 
     double* tbase = arena > 0 ? pool.alloc((size_t)arena) : nullptr;
     double* pbase = part_elems > 0 ? pool.alloc((size_t)part_elems) : nullptr;
@@ -1433,6 +1492,7 @@ struct Exec {
       GatherDesc* d_gd = upload(gds);
       const int ng = (int)gds.size();
       const long long nbk = gblocks;
+      join_side();   // a side branch adds into the same outputs: it ends first
       op([d_gd, ng, nbk](hipStream_t s) { launch_gather_multi(d_gd, ng, nbk, s); });
       ++n_launch;
     }
@@ -1816,13 +1876,32 @@ struct Exec {
     }
     std::vector<std::pair<int, const TProduct*>> plain;
     for (size_t i = 0; i < all.size(); ++i) plain.push_back({(int)i, &all[i]});
+    // the (PP|PP) products (own buffers, serial contractions) run on the side stream while
+    // the grouped launches run; the gather, which adds into the same outputs, waits for them
+    // (not when profiling, whose events time each stream's launches in order)
+    bool any_pp = false;
+    for (auto& u : pp) any_pp = any_pp || !u.empty();
+    const bool overlap = any_pp && !profile;
+    auto side = [&] {
+      fork_side();
+      try {
+        for (size_t k = 0; k < pus.size(); ++k)
+          if (!pp[k].empty()) run_use_body(pp[k], pus[k].outs, nullptr);
+      } catch (...) {
+        end_side();
+        throw;
+      }
+      end_side();
+    };
     scalar_slots = slots;
-    const bool ok = run_grouped(plain, all_outs, slots.empty() ? nullptr : slots[0]);
+    const bool ok = run_grouped(plain, all_outs, slots.empty() ? nullptr : slots[0],
+                                overlap ? std::function<void()>(side) : nullptr);
     scalar_slots.clear();
     if (!ok) return false;
+    join_side();
     ++grouped_uses;
     for (size_t k = 0; k < pus.size(); ++k) {
-      if (!pp[k].empty()) run_use_body(pp[k], pus[k].outs, nullptr);
+      if (!overlap && !pp[k].empty()) run_use_body(pp[k], pus[k].outs, nullptr);
       finish_use(pus[k], *outs[k]);
     }
     return true;
