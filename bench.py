@@ -117,11 +117,11 @@ def main():
     prec = 1 if args.precision == "fp32" else 0
 
     def step():
-        if args.workload == "curve":
-            res, codes = _lib.dsrg_pt3_energy_batch(dev, precision=prec)
-            assert all(c == 0 for c in codes), codes
-            return res
-        return [_lib.dsrg_pt3_energy(d, precision=prec) for d in dev]
+        # the batch entry point: up to three problems of a step run at once, each on its
+        # own stream and plan (a single problem runs as one call)
+        res, codes = _lib.dsrg_pt3_energy_batch(dev, precision=prec)
+        assert all(c == 0 for c in codes), codes
+        return res
 
     for _ in range(args.warmup):
         step()

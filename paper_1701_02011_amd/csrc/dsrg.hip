@@ -2673,10 +2673,21 @@ static void fill_result(dsrg_result* R, const double* e, bool pt3) {
   R->e3 = R->e3_a + R->e3_b;
 }
 
-static int run(const dsrg_problem* P, const dsrg_options* O, dsrg_result* R,
-               const dsrg_intermediates* I, bool pt3, double* e3_pairs = nullptr,
-               double* e3_rest = nullptr) {
-  if (!P || !R) throw Error(DSRG_E_ARG, "null problem or result");
+// Checked arguments of a call and the key of its plan.  slot > 0 keys a separate plan of
+// the same shape (concurrent members of a batch).
+struct Setup {
+  Shape sh;
+  bool f32 = false, devptr = false, profile = false, grouped = true, unique_ladder = true;
+  bool want_pairs = false, cacheable = false;
+  long long cap = 0;
+  hipStream_t st = nullptr;
+  int dev = 0;
+  std::string key;
+};
+
+static Setup setup(const dsrg_problem* P, const dsrg_options* O, const dsrg_intermediates* I, bool pt3,
+                   double* e3_pairs, double* e3_rest, int slot) {
+  if (!P) throw Error(DSRG_E_ARG, "null problem or result");
   const int nC = P->n_core, nA = P->n_active, nV = P->n_virtual, M = P->n_aux;
   if (nC < 0 || nA < 0 || nV < 0) throw Error(DSRG_E_ARG, "negative orbital count");
   if (M < 1) throw Error(DSRG_E_ARG, "n_aux must be >= 1");
@@ -2687,11 +2698,12 @@ static int run(const dsrg_problem* P, const dsrg_options* O, dsrg_result* R,
   if (nA > 8) throw Error(DSRG_E_UNSUPPORTED, "active spaces above 8 orbitals are not built");
   if (O && O->precision != DSRG_PRECISION_FP64 && O->precision != DSRG_PRECISION_FP32)
     throw Error(DSRG_E_UNSUPPORTED, "unknown precision");
-  const bool f32 = O && O->precision == DSRG_PRECISION_FP32;
+  Setup S;
+  S.f32 = O && O->precision == DSRG_PRECISION_FP32;
   const int flags = O ? O->flags : 0;
-  const bool devptr = flags & DSRG_F_DEVICE_PTRS;
-  const bool profile = flags & DSRG_F_PROFILE;
-  Shape sh;
+  S.devptr = flags & DSRG_F_DEVICE_PTRS;
+  S.profile = flags & DSRG_F_PROFILE;
+  Shape& sh = S.sh;
   sh.nC = nC; sh.nA = nA; sh.nV = nV; sh.M = M;
   sh.N = nC + nA + nV;
   sh.nB = (long long)M * sh.N * sh.N;
@@ -2700,43 +2712,116 @@ static int run(const dsrg_problem* P, const dsrg_options* O, dsrg_result* R,
   sh.g3n = 4LL * nA * nA * nA * nA * nA * nA;
   sh.has_g3 = nA > 0 && P->gamma3;
   sh.pt3 = pt3;
-  if (!devptr) {
+  if (!S.devptr) {
     if (!finite_host(P->eps, sh.N) || !finite_host(P->B, sh.nB) ||
         (nA > 0 && (!finite_host(P->gamma1, sh.g1n) || !finite_host(P->gamma2, sh.g2n))) ||
         (sh.has_g3 && !finite_host(P->gamma3, sh.g3n)))
       throw Error(DSRG_E_NONFINITE, "non-finite value in eps, B or the densities");
   }
-  hipStream_t st = (O && O->stream) ? (hipStream_t)O->stream : (hipStream_t)0;
-  const long long cap = (O && O->workspace_cap > 0) ? O->workspace_cap : (8LL << 30);
-  const bool grouped = !(flags & DSRG_F_NO_GROUPING);
-  const bool unique_ladder = !(flags & DSRG_F_FULL_LADDER);
-  const bool want_pairs = e3_rest != nullptr;
-  if (want_pairs && nC > 0 && !e3_pairs) throw Error(DSRG_E_ARG, "null e3_pairs with n_core > 0");
-  const bool cacheable = !profile && !I && !want_pairs && !(flags & DSRG_F_NO_PLAN_CACHE);
+  S.st = (O && O->stream) ? (hipStream_t)O->stream : (hipStream_t)0;
+  S.cap = (O && O->workspace_cap > 0) ? O->workspace_cap : (8LL << 30);
+  S.grouped = !(flags & DSRG_F_NO_GROUPING);
+  S.unique_ladder = !(flags & DSRG_F_FULL_LADDER);
+  S.want_pairs = e3_rest != nullptr;
+  if (S.want_pairs && nC > 0 && !e3_pairs) throw Error(DSRG_E_ARG, "null e3_pairs with n_core > 0");
+  S.cacheable = !S.profile && !I && !S.want_pairs && !(flags & DSRG_F_NO_PLAN_CACHE);
+  HIPCHECK(hipGetDevice(&S.dev));
+  char kbuf[192];
+  snprintf(kbuf, sizeof(kbuf), "%d:%d:%d:%d:%d:%d:%d:%d:%d:%d:%lld:%d", S.dev, nC, nA, nV, M, (int)sh.has_g3,
+           (int)pt3, (int)S.grouped, (int)S.unique_ladder, (int)S.f32, S.cap, slot);
+  S.key = kbuf;
+  return S;
+}
 
-  int dev = 0;
-  HIPCHECK(hipGetDevice(&dev));
-  char kbuf[160];
-  snprintf(kbuf, sizeof(kbuf), "%d:%d:%d:%d:%d:%d:%d:%d:%d:%d:%lld", dev, nC, nA, nV, M, (int)sh.has_g3,
-           (int)pt3, (int)grouped, (int)unique_ladder, (int)f32, cap);
-  const std::string key(kbuf);
+// An idle cached plan of this key, marked busy (null if there is none); seen tells whether
+// one exists at all.
+static Plan* acquire_plan(const std::string& key, bool& seen) {
+  std::lock_guard<std::mutex> lk(g_plan_mu);
+  seen = false;
+  for (auto& p : plans())
+    if (p->key == key) {
+      seen = true;
+      if (!p->busy) {
+        p->busy = true;
+        p->stamp = ++g_plan_clock;
+        return p.get();
+      }
+    }
+  return nullptr;
+}
+
+static void release_plan(Plan* p) {
+  std::lock_guard<std::mutex> lk(g_plan_mu);
+  p->busy = false;
+}
+
+// Library streams for the concurrent members of a batch (per device, default priority,
+// created on first use and kept for the process).
+constexpr int kBatchStreams = 2;
+static hipStream_t* batch_streams(int dev) {
+  static std::mutex mu;
+  static std::map<int, std::vector<hipStream_t>> m;
+  std::lock_guard<std::mutex> lk(mu);
+  auto& v = m[dev];
+  if (v.empty()) {
+    v.assign(kBatchStreams, nullptr);
+    for (auto& x : v)
+      if (hipStreamCreateWithFlags(&x, hipStreamNonBlocking) != hipSuccess) {
+        (void)hipGetLastError();
+        for (auto& y : v)
+          if (y) (void)hipStreamDestroy(y);
+        v.clear();
+        return nullptr;
+      }
+  }
+  return v.data();
+}
+
+// Launches the replay of a cached plan on S.st without waiting: inputs (s read from s_src,
+// non-finite count to bad for device inputs), the graph, the energies to e_dst (host,
+// pinned).  The host buffers must stay untouched until the stream has passed the launch.
+static void replay_launch(Plan* plan, const dsrg_problem* P, const Setup& S, const double* s_src,
+                          double* e_dst, int* bad) {
+  *bad = 0;
+  load_inputs(P, S.devptr, S.sh, plan->in, s_src, S.st, S.devptr ? bad : nullptr);
+  HIPCHECK(hipGraphLaunch(plan->exec, S.st));
+  HIPCHECK(hipMemcpyAsync(e_dst, plan->in.energies, 4 * sizeof(double), hipMemcpyDeviceToHost, S.st));
+}
+
+static void replay_result(const Plan* plan, const double* e, bool pt3, dsrg_result* R) {
+  dsrg_result r;
+  memset(&r, 0, sizeof(r));
+  fill_result(&r, e, pt3);
+  r.gett_flops = plan->gett_flops;
+  r.ladder_flops = plan->ladder_flops;
+  r.ladder_batch = plan->ladder_batch;
+  r.n_launch = plan->n_launch;
+  r.grouped_uses = plan->grouped_uses;
+  r.plan = 2;
+  *R = r;
+}
+
+static int run(const dsrg_problem* P, const dsrg_options* O, dsrg_result* R,
+               const dsrg_intermediates* I, bool pt3, double* e3_pairs = nullptr,
+               double* e3_rest = nullptr, int slot = 0) {
+  if (!P || !R) throw Error(DSRG_E_ARG, "null problem or result");
+  const Setup S = setup(P, O, I, pt3, e3_pairs, e3_rest, slot);
+  const Shape& sh = S.sh;
+  const int nC = sh.nC, nA = sh.nA, nV = sh.nV, M = sh.M;
+  const bool f32 = S.f32, devptr = S.devptr, profile = S.profile, grouped = S.grouped;
+  const bool unique_ladder = S.unique_ladder, want_pairs = S.want_pairs, cacheable = S.cacheable;
+  hipStream_t st = S.st;
+  const long long cap = S.cap;
+  const int dev = S.dev;
+  const std::string& key = S.key;
   Plan* plan = nullptr;
   std::unique_ptr<Plan> fresh;
   if (cacheable) {
-    std::lock_guard<std::mutex> lk(g_plan_mu);
     bool seen = false;
-    for (auto& p : plans())
-      if (p->key == key) {
-        seen = true;
-        if (!p->busy) {
-          plan = p.get();
-          plan->busy = true;
-          plan->stamp = ++g_plan_clock;
-          break;
-        }
-      }
+    plan = acquire_plan(key, seen);
     // a plan of this shape in use by another thread: run without one
     if (!seen) {
+      std::lock_guard<std::mutex> lk(g_plan_mu);
       fresh = std::make_unique<Plan>();
       fresh->key = key;
       fresh->device = dev;
@@ -2756,10 +2841,7 @@ static int run(const dsrg_problem* P, const dsrg_options* O, dsrg_result* R,
   if (plan) {
     struct Release {
       Plan* p;
-      ~Release() {
-        std::lock_guard<std::mutex> lk(g_plan_mu);
-        p->busy = false;
-      }
+      ~Release() { release_plan(p); }
     } rel{plan};
     plan->pinned[0] = P->s;
     // device inputs: the non-finite check runs ahead of the graph and is read after it
@@ -2917,13 +2999,85 @@ int dsrg_pt3_energy_batch(const dsrg_problem* probs, int32_t n, const dsrg_optio
     dsrg::g_last_error = "null arrays or n < 1";
     return DSRG_E_ARG;
   }
+  // Members run in rounds of kBatchStreams: member k on library stream k % kBatchStreams
+  // (ordered after the caller's stream) with a plan of its own slot, so the members of a
+  // round overlap on the GPU.  Each member's s, energies and non-finite count go through its
+  // own pinned slot.  A member without a cached plan runs to completion in turn (that call
+  // records its plan).
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess) {
+    dsrg::g_last_error = "no HIP device";
+    return DSRG_E_HIP;
+  }
+  hipStream_t caller = (opt && opt->stream) ? (hipStream_t)opt->stream : (hipStream_t)0;
+  hipStream_t* ss = dsrg::batch_streams(dev);
+  hipEvent_t ready = nullptr;
+  double* stage = nullptr;   // per member: s, 4 energies, non-finite count
+  constexpr int kStage = 8;
+  if (!ss || hipEventCreateWithFlags(&ready, hipEventDisableTiming) != hipSuccess ||
+      hipHostMalloc((void**)&stage, (size_t)n * kStage * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+    (void)hipGetLastError();
+    if (ready) (void)hipEventDestroy(ready);
+    dsrg::g_last_error = "batch streams, event or pinned staging";
+    return DSRG_E_HIP;
+  }
+  const int K = std::min<int>(n, dsrg::kBatchStreams);
+  (void)hipEventRecord(ready, caller);
+  for (int j = 0; j < K; ++j) (void)hipStreamWaitEvent(ss[j], ready, 0);
+  std::map<std::string, dsrg::Plan*> held;   // plans this batch holds (busy) until its end
+  std::vector<dsrg::Plan*> used(n, nullptr);
+  std::vector<char> pt3v(n, 1);
+  for (int32_t k = 0; k < n; ++k) {
+    const int j = k % K;
+    // rounds of K members: more graphs in flight than the hardware queues serve (each
+    // replay has a side branch) ran slower than two at a time
+    if (j == 0 && k > 0)
+      for (int i = 0; i < K; ++i) (void)hipStreamSynchronize(ss[i]);
+    dsrg_options oj;
+    memset(&oj, 0, sizeof(oj));
+    if (opt) oj = *opt;
+    oj.stream = ss[j];
+    status[k] = dsrg::guarded([&] {
+      const dsrg::Setup S = dsrg::setup(probs + k, &oj, nullptr, true, nullptr, nullptr, j);
+      dsrg::Plan* plan = nullptr;
+      if (S.cacheable) {
+        auto it = held.find(S.key);
+        if (it != held.end()) {
+          plan = it->second;
+        } else {
+          bool seen = false;
+          plan = dsrg::acquire_plan(S.key, seen);
+          if (plan) held[S.key] = plan;
+        }
+      }
+      if (!plan) return dsrg::run(probs + k, &oj, outs + k, nullptr, true, nullptr, nullptr, j);
+      double* st_k = stage + (size_t)k * kStage;
+      st_k[0] = probs[k].s;
+      dsrg::replay_launch(plan, probs + k, S, st_k, st_k + 1, reinterpret_cast<int*>(st_k + 5));
+      used[k] = plan;
+      return DSRG_OK;
+    });
+  }
+  int sync_rc = DSRG_OK;
+  for (int j = 0; j < K; ++j)
+    if (hipStreamSynchronize(ss[j]) != hipSuccess) sync_rc = DSRG_E_HIP;
+  if (hipGetLastError() != hipSuccess) sync_rc = DSRG_E_HIP;
   int first_error = DSRG_OK;
   bool any_ok = false;
   for (int32_t k = 0; k < n; ++k) {
-    status[k] = dsrg::guarded([&] { return dsrg::run(probs + k, opt, outs + k, nullptr, true); });
+    if (status[k] == DSRG_OK && used[k]) {
+      const double* st_k = stage + (size_t)k * kStage;
+      if (sync_rc != DSRG_OK) status[k] = sync_rc;
+      else if (*reinterpret_cast<const int*>(st_k + 5)) status[k] = DSRG_E_NONFINITE;
+      else dsrg::replay_result(used[k], st_k + 1, pt3v[k], outs + k);
+    }
     if (status[k] == DSRG_OK) any_ok = true;
     else if (first_error == DSRG_OK) first_error = status[k];
   }
+  if (sync_rc != DSRG_OK) dsrg::g_last_error = "a batch stream failed";
+  for (auto& kv : held) dsrg::release_plan(kv.second);
+  (void)hipHostFree(stage);
+  (void)hipEventDestroy(ready);
   return any_ok ? DSRG_OK : first_error;
 }
 

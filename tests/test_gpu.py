@@ -363,6 +363,26 @@ def test_batch_of_uneven_problems():
     assert [x["e3"] for x in dres] == [res[k]["e3"] for k in range(len(probs)) if k != 2]
 
 
+def test_batch_rounds_run_concurrently_and_match_single_calls():
+    """Members of a batch round run at once on separate streams and plans: the replays of a
+    second batch (every member has its plan by then) equal the single calls bit for bit,
+    for host and device problems, with more members than one round holds."""
+    base = make_config("tiny")
+    probs = [base.with_s(s) for s in (0.1, 0.5, 1.0, 2.0)]
+    say("concurrent batch rounds", len(probs))
+    first, c1 = _lib.dsrg_pt3_energy_batch(probs)
+    again, c2 = _lib.dsrg_pt3_energy_batch(probs)
+    assert all(c == _lib.DSRG_OK for c in c1 + c2)
+    assert all(r["plan"] == 2 for r in again)
+    d = [_lib.to_device(p) for p in probs]
+    dev, c3 = _lib.dsrg_pt3_energy_batch(d)
+    assert all(c == _lib.DSRG_OK for c in c3)
+    for k, p in enumerate(probs):
+        single = _lib.dsrg_pt3_energy(p)
+        for r in (first[k], again[k], dev[k]):
+            assert r["e2"] == single["e2"] and r["e3_a"] == single["e3_a"] and r["e3_b"] == single["e3_b"], k
+
+
 @pytest.mark.parametrize("shape,seed,s", [((2, 2, 10, 40), 101, 0.5), ((3, 1, 5, 12), 23, 0.5),
                                           ((2, 0, 4, 9), 17, 0.4), ((0, 3, 3, 7), 19, 0.8)])
 def test_pair_energies_against_oracle(shape, seed, s):
