@@ -3005,21 +3005,26 @@ int dsrg_pt3_energy_batch(const dsrg_problem* probs, int32_t n, const dsrg_optio
   // own pinned slot.  A member without a cached plan runs to completion in turn (that call
   // records its plan).
   int dev = 0;
-  if (hipGetDevice(&dev) != hipSuccess) {
-    dsrg::g_last_error = "no HIP device";
-    return DSRG_E_HIP;
-  }
   hipStream_t caller = (opt && opt->stream) ? (hipStream_t)opt->stream : (hipStream_t)0;
-  hipStream_t* ss = dsrg::batch_streams(dev);
+  hipStream_t* ss = nullptr;
   hipEvent_t ready = nullptr;
   double* stage = nullptr;   // per member: s, 4 energies, non-finite count
   constexpr int kStage = 8;
-  if (!ss || hipEventCreateWithFlags(&ready, hipEventDisableTiming) != hipSuccess ||
+  if (hipGetDevice(&dev) != hipSuccess || !(ss = dsrg::batch_streams(dev)) ||
+      hipEventCreateWithFlags(&ready, hipEventDisableTiming) != hipSuccess ||
       hipHostMalloc((void**)&stage, (size_t)n * kStage * sizeof(double), hipHostMallocDefault) != hipSuccess) {
+    // no streams or staging (e.g. no device): the members one call after another, each
+    // with its own checks and error
     (void)hipGetLastError();
     if (ready) (void)hipEventDestroy(ready);
-    dsrg::g_last_error = "batch streams, event or pinned staging";
-    return DSRG_E_HIP;
+    int first_error = DSRG_OK;
+    bool any_ok = false;
+    for (int32_t k = 0; k < n; ++k) {
+      status[k] = dsrg::guarded([&] { return dsrg::run(probs + k, opt, outs + k, nullptr, true); });
+      if (status[k] == DSRG_OK) any_ok = true;
+      else if (first_error == DSRG_OK) first_error = status[k];
+    }
+    return any_ok ? DSRG_OK : first_error;
   }
   const int K = std::min<int>(n, dsrg::kBatchStreams);
   (void)hipEventRecord(ready, caller);
