@@ -155,11 +155,15 @@ int dsrg_pt2_energy(const dsrg_problem* prob, const dsrg_options* opt, dsrg_resu
 /* E(2) and E(3) (Eqs. E(2), E(3)).  Same conventions as dsrg_pt2_energy. */
 int dsrg_pt3_energy(const dsrg_problem* prob, const dsrg_options* opt, dsrg_result* out);
 
-/* E(2) and E(3) of n independent problems (e.g. geometries along a dissociation curve),
-   one after another on one stream; problems of equal shape share one plan.  outs[k] and
-   status[k] receive item k's result and return code; an item that fails (bad arguments,
-   non-finite input) is skipped and leaves outs[k] untouched.  Returns DSRG_OK if at least
-   one item succeeded, else the first item's code (DSRG_E_ARG for n < 1 or null arrays). */
+/* E(2) and E(3) of n independent problems (e.g. geometries along a dissociation curve, or
+   one geometry at several s).  Items run in rounds of two on streams of the library, ordered
+   after opt->stream, each with a plan of its own slot (item k uses slot k % 2), so the two
+   items of a round overlap on the GPU; the call returns when all have finished.  An item
+   whose slot has no cached plan yet runs to completion first (recording that plan).
+   outs[k] and status[k] receive item k's result and return code; an item that fails (bad
+   arguments, non-finite input) is skipped and leaves outs[k] untouched.  Returns DSRG_OK if
+   at least one item succeeded, else the first item's code (DSRG_E_ARG for n < 1 or null
+   arrays).  Results equal those of single calls bit for bit. */
 int dsrg_pt3_energy_batch(const dsrg_problem* probs, int32_t n, const dsrg_options* opt,
                           dsrg_result* outs, int32_t* status);
 
