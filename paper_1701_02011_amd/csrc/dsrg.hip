@@ -1816,14 +1816,23 @@ struct Exec {
     return pu;
   }
   // the pre-images added into their outputs through the pair antisymmetriser
+  // adds the use's pre-images into their outputs, in launches of up to kAntisymList pairs
   void finish_use(const PreparedUse& pu, const std::map<std::string, TensorRef>& outs0) {
-    for (auto& pn : pu.pre) {
-      const double* X = pu.outs.at(pn).p;
-      double* O = outs0.at(pn.substr(0, pn.size() - 1)).p;
-      const int nPl = d.len('P'), nHl = d.len('H');
-      op([X, O, nPl, nHl](hipStream_t s) { launch_antisym_add(X, O, nPl, nHl, s); });
+    const int nPl = d.len('P'), nHl = d.len('H');
+    AntisymList l;
+    auto flush = [&] {
+      if (l.n == 0) return;
+      const AntisymList lc = l;
+      op([lc, nPl, nHl](hipStream_t s) { launch_antisym_add_list(lc, nPl, nHl, s); });
       ++n_launch;
+      l = AntisymList();
+    };
+    for (auto& pn : pu.pre) {
+      l.X[l.n] = pu.outs.at(pn).p;
+      l.O[l.n] = outs0.at(pn.substr(0, pn.size() - 1)).p;
+      if (++l.n == kAntisymList) flush();
     }
+    flush();
   }
   void run_use(const Use& U0, std::map<std::string, TensorRef>& outs0, double* scalar_out) {
     PreparedUse pu = prepare_use(U0, outs0, scalar_out != nullptr);
@@ -2367,10 +2376,8 @@ static BodyOut body(Exec& X, OpLog& op, Pool& pool, const Shape& sh, const Input
     op([nA, g1, G1](hipStream_t s) { launch_expand_rdm(nA, 1, g1, G1, s); });
     op([nA, g2, G2](hipStream_t s) { launch_expand_rdm(nA, 2, g2, G2, s); });
     if (g3) {
-      double* G3 = pool.alloc((size_t)e6n);
-      op([nA, g3, G3](hipStream_t s) { launch_expand_rdm(nA, 3, g3, G3, s); });
-      op([nA, G1, G2, G3, L2, L3, eta](hipStream_t s) { launch_cumulants(nA, G1, G2, G3, L2, L3, eta, s); });
-      pool.release(G3);
+      // the spin blocks of gamma3 go straight into the three-body cumulant
+      op([nA, g3, G1, G2, L2, L3, eta](hipStream_t s) { launch_cumulants(nA, G1, G2, g3, L2, L3, eta, s); });
     } else {
       op([nA, G1, G2, L2, eta](hipStream_t s) { launch_cumulants(nA, G1, G2, nullptr, L2, nullptr, eta, s); });
       op([L3, e6n](hipStream_t s) { launch_fill(L3, e6n, 0.0, s); });

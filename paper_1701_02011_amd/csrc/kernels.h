@@ -220,9 +220,10 @@ void launch_ladder_unpack_sym(const double* Xs, const double* Xa, int rows, int 
                               const LadderPair* rowtab, const LadderPair* ntab, int nP, int nH, double c,
                               double* O, hipStream_t st);
 
-// Spin-orbital active densities [2nA]^k from the spin-block inputs, and cumulants.
+// Spin-orbital active densities [2nA]^k from the spin-block inputs, and cumulants.  The
+// three-body density enters the cumulant as its spin blocks g3 (expanded on the fly).
 void launch_expand_rdm(int nA, int rank, const double* blocks, double* so, hipStream_t st);
-void launch_cumulants(int nA, const double* G1, const double* G2, const double* G3, double* L2,
+void launch_cumulants(int nA, const double* G1, const double* G2, const double* g3, double* L2,
                       double* L3, double* eta, hipStream_t st);
 
 // The flow parameter s is read from device memory (s points at one double), so a captured
@@ -265,5 +266,14 @@ void launch_fill(double* p, long long n, double v, hipStream_t st);
 // O[p][q][i][j] += X[p][q][i][j] - X[q][p][i][j] - X[p][q][j][i] + X[q][p][j][i]
 // (both [P][P][H][H], dense, distinct arrays)
 void launch_antisym_add(const double* X, double* O, int nP, int nH, hipStream_t st);
+// the same for up to kAntisymList pairs (X[k], O[k]) of one shape in one launch (the O
+// arrays distinct)
+constexpr int kAntisymList = 8;
+struct AntisymList {
+  const double* X[kAntisymList] = {};
+  double* O[kAntisymList] = {};
+  int n = 0;
+};
+void launch_antisym_add_list(const AntisymList& l, int nP, int nH, hipStream_t st);
 
 }  // namespace dsrg

@@ -1184,6 +1184,32 @@ void launch_antisym_add(const double* X, double* O, int nP, int nH, hipStream_t 
   hipLaunchKernelGGL(antisym_add_kernel, dim3(grid), dim3(256), 0, st, X, O, nP, nH, total);
 }
 
+// Pair blockIdx.y of the list; 32-bit index arithmetic (the launcher checks the size).
+__global__ __launch_bounds__(256) void antisym_add_list_kernel(AntisymList l, int nP, int nH, unsigned total) {
+  const double* __restrict__ X = l.X[blockIdx.y];
+  double* __restrict__ O = l.O[blockIdx.y];
+  const unsigned hh = (unsigned)nH * nH, ps = (unsigned)nP * hh;
+  for (unsigned e = blockIdx.x * 256u + threadIdx.x; e < total; e += 256u * gridDim.x) {
+    const unsigned p = e / ps, r1 = e - p * ps;
+    const unsigned q = r1 / hh, r2 = r1 - q * hh;
+    const unsigned i = r2 / nH, j = r2 - i * nH;
+    const unsigned qp = q * ps + p * hh;
+    O[e] += X[e] - X[qp + r2] - X[p * ps + q * hh + j * nH + i] + X[qp + j * nH + i];
+  }
+}
+
+void launch_antisym_add_list(const AntisymList& l, int nP, int nH, hipStream_t st) {
+  const long long total = (long long)nP * nP * nH * nH;
+  if (total <= 0 || l.n <= 0) return;
+  if (total >= (1LL << 31)) {
+    for (int k = 0; k < l.n; ++k) launch_antisym_add(l.X[k], l.O[k], nP, nH, st);
+    return;
+  }
+  const unsigned gx = (unsigned)std::max<long long>(1, std::min<long long>((total + 255) / 256, 16384));
+  hipLaunchKernelGGL(antisym_add_list_kernel, dim3(gx, (unsigned)l.n), dim3(256), 0, st, l, nP, nH,
+                     (unsigned)total);
+}
+
 // ---------------------------------------------------------------------------
 // Same-spin ladder on unique pairs: packing of the antisymmetrised integrals and of the
 // amplitudes, and the antisymmetric fill of the result
@@ -1448,10 +1474,12 @@ __global__ void cumulant2_kernel(int n, const double* __restrict__ G1, const dou
 // lambda3 = G3 - det(g g g) - sum_{ij} (-1)^(i+j) g[P_i, S_j] lambda2[P\i, S\j]
 // Workgroup row blockIdx.x is the upper triple P (uniform), threads take the lower triples S;
 // the three rows g[P_a][*] and the three slices lambda2[P\a][*][*] the row needs are staged
-// in LDS first (n <= 16).
+// in LDS first (n <= 16).  G3[P][S] is read from the spin blocks g3 the way
+// expand_rdm_kernel<3> forms it (alpha-first block, parity sign, zero unless the numbers of
+// beta indices above and below agree), so the spin-orbital G3 is never stored.
 __global__ __launch_bounds__(256) void cumulant3_kernel(int n, const double* __restrict__ G1,
                                                         const double* __restrict__ L2,
-                                                        const double* __restrict__ G3,
+                                                        const double* __restrict__ g3,
                                                         double* __restrict__ L3) {
   __shared__ double gs[3][16], ls[3][16 * 16];
   const int n2 = n * n, n3 = n2 * n;
@@ -1491,7 +1519,40 @@ __global__ __launch_bounds__(256) void cumulant3_kernel(int n, const double* __r
       const double sgn = ((a + b) & 1) ? -1.0 : 1.0;
       gl += sgn * g[a][b] * ls[a][V0[b] * n + V1[b]];
     }
-  L3[i] = G3[i] - det - gl;
+  // G3[P][S] from the spin blocks
+  const int nA = n / 2;
+  int su[3], pu[3], sl[3], pl[3], nbu = 0, nbl = 0;
+#pragma unroll
+  for (int c = 0; c < 3; ++c) {
+    su[c] = P[c] >= nA;
+    pu[c] = P[c] - su[c] * nA;
+    sl[c] = S[c] >= nA;
+    pl[c] = S[c] - sl[c] * nA;
+    nbu += su[c];
+    nbl += sl[c];
+  }
+  double g3v = 0.0;
+  if (nbu == nbl) {
+    int par = 0, off = 0;
+#pragma unroll
+    for (int a = 0; a < 3; ++a)
+#pragma unroll
+      for (int b = a + 1; b < 3; ++b) par += (su[a] > su[b]) + (sl[a] > sl[b]);
+#pragma unroll
+    for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        if (su[c] == sp) off = off * nA + pu[c];
+#pragma unroll
+    for (int sp = 0; sp < 2; ++sp)
+#pragma unroll
+      for (int c = 0; c < 3; ++c)
+        if (sl[c] == sp) off = off * nA + pl[c];
+    const long long bsz = (long long)nA * nA * nA * nA * nA * nA;
+    const double v = g3[nbu * bsz + off];
+    g3v = (par & 1) ? -v : v;
+  }
+  L3[i] = g3v - det - gl;
 }
 
 __global__ void eta_kernel(int n, const double* __restrict__ G1, double* __restrict__ eta) {
@@ -1500,17 +1561,17 @@ __global__ void eta_kernel(int n, const double* __restrict__ G1, double* __restr
   eta[i] = ((i / n) == (i % n) ? 1.0 : 0.0) - G1[i];
 }
 
-void launch_cumulants(int nA, const double* G1, const double* G2, const double* G3, double* L2,
+void launch_cumulants(int nA, const double* G1, const double* G2, const double* g3, double* L2,
                       double* L3, double* eta, hipStream_t st) {
   int n = 2 * nA;
   if (n == 0) return;
   long long t2 = (long long)n * n * n * n;
   hipLaunchKernelGGL(cumulant2_kernel, dim3((unsigned)((t2 + 255) / 256)), dim3(256), 0, st, n, G1,
                      G2, L2);
-  if (G3 && L3) {
+  if (g3 && L3) {
     const int n3 = n * n * n;
     hipLaunchKernelGGL(cumulant3_kernel, dim3((unsigned)n3, (unsigned)((n3 + 255) / 256)), dim3(256), 0, st,
-                       n, G1, L2, G3, L3);
+                       n, G1, L2, g3, L3);
   }
   hipLaunchKernelGGL(eta_kernel, dim3((n * n + 255) / 256), dim3(256), 0, st, n, G1, eta);
 }
