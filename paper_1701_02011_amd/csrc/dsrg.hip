@@ -1493,7 +1493,10 @@ struct Exec {
       const int ng = (int)gds.size();
       const long long nbk = gblocks;
       join_side();   // a side branch adds into the same outputs: it ends first
-      op([d_gd, ng, nbk](hipStream_t s) { launch_gather_multi(d_gd, ng, nbk, s); });
+      // sources are temporaries of the arena; outputs are contiguous arrays
+      bool k32 = arena < (1LL << 31);
+      for (auto& kv : gents) k32 = k32 && outs.at(kv.first).lim < (1LL << 31);
+      op([d_gd, ng, nbk, k32](hipStream_t s) { launch_gather_multi(d_gd, ng, nbk, s, k32); });
       ++n_launch;
     }
     return true;

@@ -164,7 +164,8 @@ struct GatherDesc {
 long long gather_prepare(GatherDesc& g);
 // several outputs (prepared, blk0 their workgroup prefix, the array in device memory) in
 // one launch of `blocks` workgroups
-void launch_gather_multi(const GatherDesc* descs, int n, long long blocks, hipStream_t st);
+// k32: every output has fewer than 2^31 elements and every source offset is below 2^31
+void launch_gather_multi(const GatherDesc* descs, int n, long long blocks, hipStream_t st, bool k32 = false);
 
 // partial: scratch of at least dot_partials() doubles; writes the sum into out[0]
 int dot_partials();

@@ -5,6 +5,7 @@
 #include <cmath>
 #include <cstdio>
 #include <cstdlib>
+#include <type_traits>
 
 namespace dsrg {
 
@@ -941,7 +942,12 @@ void launch_dot_group(const DotItem* items, int n, int blocks, double* partial, 
 // sums (deterministic for a given tpe).
 constexpr int kGatherEpl = 2;   // output elements per lane when lanes do not share one
 constexpr int kGatherEif = 8 / kGatherEpl;   // entries in flight (eight loads per lane)
+// K32: every output and source offset of the launch is below 2^31 (the host checks), so
+// the element decode and the source offsets run in 32-bit arithmetic (unsigned, so partial
+// sums may wrap: the final offsets are in range).
+template <bool K32>
 __global__ __launch_bounds__(256) void gather_kernel(const GatherDesc* __restrict__ descs, int nd) {
+  using Idx = typename std::conditional<K32, unsigned, long long>::type;
   // output of this workgroup: the last with blk0 <= blockIdx.x
   int dl = 0, dh = nd - 1;
   while (dl < dh) {
@@ -968,23 +974,24 @@ __global__ __launch_bounds__(256) void gather_kernel(const GatherDesc* __restric
       cnt *= len[k];
     }
   // element e of the class -> its multi-index x and output offset
-  auto decode = [&](long long e, int* x) {
-    long long o = 0;
+  auto decode = [&](long long e64, int* x) {
+    Idx e = (Idx)e64, o = 0;
 #pragma unroll
     for (int k = 3; k >= 0; --k)
       if (k < g.rank) {
-        const long long q = e / len[k];
-        x[k] = lo[k] + (int)(e - q * len[k]);
+        const Idx q = e / (Idx)len[k];
+        x[k] = lo[k] + (int)(e - q * (Idx)len[k]);
         e = q;
       }
 #pragma unroll
     for (int k = 0; k < 4; ++k)
-      if (k < g.rank) o = o * g.dim[k] + x[k];
-    return o;
+      if (k < g.rank) o = o * (Idx)g.dim[k] + (Idx)x[k];
+    return (long long)o;
   };
   auto off = [&](const GatherEntry& en, const int* x) {
-    return en.base + (long long)x[0] * en.ss[0] + (long long)x[1] * en.ss[1] + (long long)x[2] * en.ss[2] +
-           (long long)x[3] * en.ss[3];
+    const Idx v = (Idx)en.base + (Idx)x[0] * (Idx)en.ss[0] + (Idx)x[1] * (Idx)en.ss[1] +
+                  (Idx)x[2] * (Idx)en.ss[2] + (Idx)x[3] * (Idx)en.ss[3];
+    return (long long)v;
   };
   if (tpe == 1) {
     // kGatherEpl elements per lane (e, e + 256, ...): each entry's scalar loads serve all
@@ -1068,9 +1075,12 @@ long long gather_prepare(GatherDesc& g) {
   return blocks;
 }
 
-void launch_gather_multi(const GatherDesc* descs, int n, long long blocks, hipStream_t st) {
+void launch_gather_multi(const GatherDesc* descs, int n, long long blocks, hipStream_t st, bool k32) {
   if (n <= 0 || blocks <= 0) return;
-  hipLaunchKernelGGL(gather_kernel, dim3((unsigned)blocks), dim3(256), 0, st, descs, n);
+  if (k32)
+    hipLaunchKernelGGL(gather_kernel<true>, dim3((unsigned)blocks), dim3(256), 0, st, descs, n);
+  else
+    hipLaunchKernelGGL(gather_kernel<false>, dim3((unsigned)blocks), dim3(256), 0, st, descs, n);
 }
 
 // ---------------------------------------------------------------------------
