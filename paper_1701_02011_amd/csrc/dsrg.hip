@@ -956,7 +956,7 @@ struct Exec {
   }
   static void group_shape(GroupItem& it) {
     GettDesc& g = it.g;
-    if (g.K <= kGettBK && std::min(g.M, g.N) <= kGettBK) {
+    if (g.K <= kGettBK && std::min(g.M, g.N) <= kGroupRowN) {
       // one output row per thread along the long free dimension (operands swapped later
       // when that is N)
       it.shape = kGroupRowShape;
@@ -1046,7 +1046,7 @@ struct Exec {
       it.g.kchunk = it.g.steps;
       it.g.part = nullptr;
       it.splits = 1;
-      if (it.shape == kGroupRowShape && it.g.N > kGettBK) transpose_item(it);
+      if (it.shape == kGroupRowShape && it.g.N > kGroupRowN) transpose_item(it);
       gett_magic(it.g);
       if (it.shape == kGroupBigShape) {   // not with K = n_aux < 128 k steps; kept general
         for (auto& kk : todo)
@@ -1335,7 +1335,7 @@ struct Exec {
         it.B = at(fx.b, it.B);
         it.C = tbase + fx.c;
         it.g.part = it.splits > 1 ? pbase + poff[L][oi] : nullptr;
-        if (it.shape == kGroupRowShape && it.g.N > kGettBK) transpose_item(it);
+        if (it.shape == kGroupRowShape && it.g.N > kGroupRowN) transpose_item(it);
         gett_magic(it.g);
         it.tile0 = R.tiles;
         long long t = (long long)it.tiles_m * it.tiles_n * it.splits;

@@ -106,10 +106,10 @@ int gett_splits(const GettDesc& g, long long ws_elems);
 // its own (launch_gett_group with big = true), since its register count halves occupancy.
 constexpr int kGroupShapes = 4, kGroupBigShape = 3;
 constexpr int kGroupTiles[kGroupShapes][2] = {{64, 64}, {16, 128}, {128, 16}, {128, 128}};
-// Shape 4 (in gett_group_kernel): items with K <= kGettBK and N <= kGettBK (the host swaps
-// the operands of an item whose short free dimension is M) run one output row per thread,
-// kGroupRows rows per workgroup (tiles_n = 1, no split), without LDS tiles or MFMA.
-constexpr int kGroupRowShape = 4, kGroupRows = 256;
+// Shape 4 (in gett_group_kernel): items with K <= kGettBK and N <= kGroupRowN (the host
+// swaps the operands of an item whose short free dimension is M) run one output row per
+// thread, kGroupRows rows per workgroup (tiles_n = 1, no split), without LDS tiles or MFMA.
+constexpr int kGroupRowShape = 4, kGroupRows = 256, kGroupRowN = 64;
 struct GroupItem {
   GettDesc g;
   const double* A = nullptr;

@@ -666,11 +666,11 @@ void launch_gett(const GettDesc& g0, const double* A, const double* B, double* C
 // never share an output element, so the launch is race-free and its result does not
 // depend on scheduling.
 // ---------------------------------------------------------------------------
-// Shape-4 items (K <= 16, N <= 16): the k offsets and B (zero past K and N) are staged in
+// Shape-4 items (K <= 16, N <= 64): the k offsets and B (zero past K and N) are staged in
 // LDS, each thread loads the K values of its row of A and forms its N outputs in FP64
 // (k in order), so a workgroup covers 256 rows at the cost of a streaming pass.
 struct RowLds {
-  double Bs[BK][BK];
+  double Bs[BK][kGroupRowN];
   long long ka[BK], kb[BK];
 };
 __device__ __forceinline__ void group_rows(const GroupItem& it, int tm, RowLds& lds) {
@@ -690,8 +690,8 @@ __device__ __forceinline__ void group_rows(const GroupItem& it, int tm, RowLds& 
     lds.kb[t] = ob;
   }
   __syncthreads();
-  {
-    const int k = t / BK, n = t % BK;   // 256 threads = BK x BK entries
+  for (int e = t; e < BK * kGroupRowN; e += 256) {
+    const int k = e / kGroupRowN, n = e % kGroupRowN;
     double v = 0.0;
     if (k < g.K && n < g.N) v = it.B[lds.kb[k] + decode_fast(n, g.nn, g.nd, g.nmag, g.nsh, g.bn)];
     lds.Bs[k][n] = v;
