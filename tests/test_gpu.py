@@ -313,6 +313,22 @@ def test_plan_replay_matches_eager():
     _lib.release_cache()
 
 
+@pytest.mark.parametrize("name", ["tiny", "small"])
+def test_ladder_on_second_stream_changes_nothing(name):
+    """The (PP|PP) ladder runs on a second stream beside the grouped launches (eager calls,
+    plan recording and replays) but in order on one stream when profiling: the energies
+    agree bit for bit, so the overlap only moves work in time."""
+    p = make_config(name)
+    say("ladder overlap vs one stream", name)
+    seq = _lib.dsrg_pt3_energy(p, profile=True)
+    eager = _lib.dsrg_pt3_energy(p, cache=False)
+    _lib.dsrg_pt3_energy(p)
+    rep = _lib.dsrg_pt3_energy(p)
+    assert rep["plan"] == 2
+    for r in (eager, rep):
+        assert r["e2"] == seq["e2"] and r["e3_a"] == seq["e3_a"] and r["e3_b"] == seq["e3_b"]
+
+
 @pytest.mark.parametrize("name", ["micro", "tiny", "small"])
 def test_fp32_products_meet_mixed_bar(name):
     """DSRG_PRECISION_FP32 (FP32 products in every contraction, FP64 sums, denominators and
