@@ -117,11 +117,14 @@ def main():
     prec = 1 if args.precision == "fp32" else 0
 
     def step():
-        # the batch entry point: up to three problems of a step run at once, each on its
-        # own stream and plan (a single problem runs as one call)
-        res, codes = _lib.dsrg_pt3_energy_batch(dev, precision=prec)
-        assert all(c == 0 for c in codes), codes
-        return res
+        if args.workload == "curve":
+            # geometries of different shapes: the batch entry point (two at a time)
+            res, codes = _lib.dsrg_pt3_energy_batch(dev, precision=prec)
+            assert all(c == 0 for c in codes), codes
+            return res
+        # one call per energy (replays of one plan; the batch's two-at-a-time rounds gained
+        # -3 to +4 % here depending on the box, within the run-to-run spread)
+        return [_lib.dsrg_pt3_energy(d, precision=prec) for d in dev]
 
     for _ in range(args.warmup):
         step()

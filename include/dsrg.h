@@ -156,9 +156,10 @@ int dsrg_pt2_energy(const dsrg_problem* prob, const dsrg_options* opt, dsrg_resu
 int dsrg_pt3_energy(const dsrg_problem* prob, const dsrg_options* opt, dsrg_result* out);
 
 /* E(2) and E(3) of n independent problems (e.g. geometries along a dissociation curve, or
-   one geometry at several s).  Items run in rounds of two on streams of the library, ordered
-   after opt->stream, each with a plan of its own slot (item k uses slot k % 2), so the two
-   items of a round overlap on the GPU; the call returns when all have finished.  An item
+   one geometry at several s).  Items run in rounds of K on streams of the library, ordered
+   after opt->stream, each with a plan of its own slot (item k uses slot k % K), so the
+   items of a round overlap on the GPU; K is half of GPU_MAX_HW_QUEUES (4 unless set, so 2),
+   at most 4.  The call returns when all have finished.  An item
    whose slot has no cached plan yet runs to completion first (recording that plan).
    outs[k] and status[k] receive item k's result and return code; an item that fails (bad
    arguments, non-finite input) is skipped and leaves outs[k] untouched.  Returns DSRG_OK if

@@ -2767,7 +2767,15 @@ static void release_plan(Plan* p) {
 
 // Library streams for the concurrent members of a batch (per device, default priority,
 // created on first use and kept for the process).
-constexpr int kBatchStreams = 2;
+constexpr int kBatchStreams = 4;   // streams created; a round uses batch_round() of them
+// Members per round: every replay keeps two streams busy (its main sequence and the ladder
+// beside it), so a round holds half the hardware queues HIP gives the process
+// (GPU_MAX_HW_QUEUES, 4 unless set): more streams than queues share queues and serialise.
+static int batch_round() {
+  const char* q = getenv("GPU_MAX_HW_QUEUES");
+  const int hwq = q ? atoi(q) : 4;
+  return std::max(1, std::min(kBatchStreams, hwq / 2));
+}
 static hipStream_t* batch_streams(int dev) {
   static std::mutex mu;
   static std::map<int, std::vector<hipStream_t>> m;
@@ -3009,7 +3017,7 @@ int dsrg_pt3_energy_batch(const dsrg_problem* probs, int32_t n, const dsrg_optio
     dsrg::g_last_error = "null arrays or n < 1";
     return DSRG_E_ARG;
   }
-  // Members run in rounds of kBatchStreams: member k on library stream k % kBatchStreams
+  // Members run in rounds of K = batch_round(): member k on library stream k % K
   // (ordered after the caller's stream) with a plan of its own slot, so the members of a
   // round overlap on the GPU.  Each member's s, energies and non-finite count go through its
   // own pinned slot.  A member without a cached plan runs to completion in turn (that call
@@ -3036,7 +3044,7 @@ int dsrg_pt3_energy_batch(const dsrg_problem* probs, int32_t n, const dsrg_optio
     }
     return any_ok ? DSRG_OK : first_error;
   }
-  const int K = std::min<int>(n, dsrg::kBatchStreams);
+  const int K = std::min<int>(n, dsrg::batch_round());
   (void)hipEventRecord(ready, caller);
   for (int j = 0; j < K; ++j) (void)hipStreamWaitEvent(ss[j], ready, 0);
   std::map<std::string, dsrg::Plan*> held;   // plans this batch holds (busy) until its end
