@@ -443,6 +443,8 @@ struct Exec {
       (void)hipEventDestroy(r.a);
       (void)hipEventDestroy(r.b);
     }
+    // a branch left open by an error may still run: it ends before its buffers can be freed
+    if (side_st) (void)hipStreamSynchronize(side_st);
     for (auto e : side_ev) (void)hipEventDestroy(e);
     if (side_st) (void)hipStreamDestroy(side_st);
   }
