@@ -103,7 +103,7 @@ def main():
                     help="fp32: FP32 products in the contractions (FP64 sums and reductions)")
     args = ap.parse_args()
     if args.gpus != 1:
-        sys.stderr.write("bench.py: this build runs on exactly one GPU; --gpus %d is not "
+        sys.stderr.write("bench.py: this benchmark runs on exactly one GPU; --gpus %d is not "
                          "supported (the multi-GPU sharding is a design note only)\n" % args.gpus)
         sys.exit(2)
 
@@ -123,7 +123,7 @@ def main():
             assert all(c == 0 for c in codes), codes
             return res
         # one call per energy (replays of one plan; the batch's two-at-a-time rounds gained
-        # -3 to +4 % here depending on the box, within the run-to-run spread)
+        # -3 to +4 % here depending on the machine, within the run-to-run spread)
         return [_lib.dsrg_pt3_energy(d, precision=prec) for d in dev]
 
     for _ in range(args.warmup):
