@@ -29,6 +29,11 @@
  * is bitwise the same as the recording run's would be for the same inputs.  At most 4
  * plans (16 GiB) are kept, least recently used first out; dsrg_release_cache() frees them.
  * Calls with DSRG_F_PROFILE, DSRG_F_NO_PLAN_CACHE or intermediates run without a plan.
+ * Part of a call's work (the (PP|PP) ladder beside the grouped contractions of E(3)'s
+ * first-order commutators) may run on a second, library-owned stream of default priority,
+ * ordered after the caller's stream and joined back into it before the call's last work
+ * there (in a plan, the same fork and join are edges of the graph); except with
+ * DSRG_F_PROFILE, which keeps every launch on the caller's stream.
  *
  * Thread safety: calls may run concurrently from different host threads on different
  * streams.  A call that finds the plan of its shape in use by another call runs without one.
