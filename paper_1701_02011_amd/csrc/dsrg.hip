@@ -2520,13 +2520,11 @@ static BodyOut body(Exec& X, OpLog& op, Pool& pool, const Shape& sh, const Input
   double* S2 = pool.alloc(2 * n1);
   double* H1 = pool.alloc(2 * n1);
   op([=](hipStream_t s) {
-    for (int b = 0; b < 3; ++b)
-      launch_second_order_doubles(ad, W2 + b * n4, Z2 + b * n4, eps, sdev, U2 + b * n4, H2 + b * n4, s);
+    launch_second_order_doubles(ad, W2, Z2, eps, sdev, U2, H2, 3, s);   // aa, ab, bb
     launch_combine_f2((int)(2 * n1), W1, Z1, f2, s);
     launch_singles(ad, U2, U2 + n4, U2 + 2 * n4, g1a, g1b, eps, sdev, f2, f2 + n1, U1, U1 + n1, S2,
                    S2 + n1, s);
-    for (int sidx = 0; sidx < 2; ++sidx)
-      launch_second_order_h1(ad, W1 + sidx * n1, Z1 + sidx * n1, S2 + sidx * n1, H1 + sidx * n1, s);
+    launch_second_order_h1(ad, W1, Z1, S2, H1, 2, s);   // alpha, beta
   });
   // E(3)_a = <[H~(1), T(2)]> and E(3)_b = <[H~(2)_{1,2}, T(1)]>: without the pair
   // decomposition both scalars run as one grouped use when their temporaries fit (the

@@ -246,12 +246,14 @@ void launch_singles(AmpDims d, const double* T2aa, const double* T2ab, const dou
                     double* srcb, hipStream_t st);
 // Second-order doubles and the H~(2) two-body excitation block:
 // O = 2 W + Z; u = (O/2) R_s(D) (0 on internal), H = (O/2) exp(-s D^2) - Z/6 (O/2 - Z/6 internal).
+// nblocks spin blocks at a stride of one [P][P][H][H] block, in one launch.
 void launch_second_order_doubles(AmpDims d, const double* W, const double* Z, const double* eps,
-                                 const double* s, double* U, double* H, hipStream_t st);
+                                 const double* s, double* U, double* H, int nblocks, hipStream_t st);
 // One-body counterpart: f2 = (2 W1 + Z1)/2; H1 = src - Z1/6 (f2 - Z1/6 on internal elements),
 // where src = (f2 + coup2) exp(-s D^2) comes from launch_singles.
+// nspins blocks at a stride of one [P][H] block, in one launch.
 void launch_second_order_h1(AmpDims d, const double* W1, const double* Z1, const double* src,
-                            double* H1, hipStream_t st);
+                            double* H1, int nspins, hipStream_t st);
 void launch_combine_f2(int n, const double* W1, const double* Z1, double* f2, hipStream_t st);
 // P2[i][j] += sum over the blocks aa, ab, bb and a, b in P of G2[blk][a][b][i][j] T[blk][a][b][i][j]
 // for core i, j (G2 and T are [P][P][H][H] per block; P2 is [nC][nC]); fixed-order sums.

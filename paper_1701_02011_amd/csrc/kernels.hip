@@ -1693,31 +1693,39 @@ void launch_singles(AmpDims d, const double* T2aa, const double* T2ab, const dou
                      g1a, g1b, eps, s, fa, fb, t1a, t1b, srca, srcb);
 }
 
+// Spin block blockIdx.y; the element index in 32-bit arithmetic when a block has fewer than
+// 2^31 elements (Idx = unsigned), else 64-bit.
+template <class Idx>
 __global__ void second_order_doubles_kernel(AmpDims d, const double* __restrict__ W,
                                             const double* __restrict__ Z,
                                             const double* __restrict__ eps, const double* __restrict__ sp,
                                             double* __restrict__ U, double* __restrict__ H) {
   const double s = *sp;
-  const int nH = d.nC + d.nA, nP = d.nA + d.nV;
-  long long total = (long long)nP * nP * nH * nH;
-  long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  const Idx nH = d.nC + d.nA, nP = d.nA + d.nV;
+  const Idx total = nP * nP * nH * nH;
+  const Idx idx = (Idx)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= total) return;
-  int j = idx % nH, i = (idx / nH) % nH, b = (idx / nH / nH) % nP, a = idx / nH / nH / nP;
-  bool internal = a < d.nA && b < d.nA && i >= d.nC && j >= d.nC;
-  double D = eps[i] + eps[j] - eps[d.nC + a] - eps[d.nC + b];
-  double z = Z[idx];
-  double v2 = W[idx] + 0.5 * z;  // (2 W + Z) / 2
-  U[idx] = internal ? 0.0 : v2 * regulariser(s, D);
-  H[idx] = (internal ? v2 : v2 * source_factor(s, D)) - z / 6.0;
+  const long long o = (long long)blockIdx.y * (long long)total + (long long)idx;
+  const Idx q1 = idx / nH, q2 = q1 / nH, q3 = q2 / nP;
+  const int j = (int)(idx - q1 * nH), i = (int)(q1 - q2 * nH), b = (int)(q2 - q3 * nP), a = (int)q3;
+  const bool internal = a < d.nA && b < d.nA && i >= d.nC && j >= d.nC;
+  const double D = eps[i] + eps[j] - eps[d.nC + a] - eps[d.nC + b];
+  const double z = Z[o];
+  const double v2 = W[o] + 0.5 * z;  // (2 W + Z) / 2
+  U[o] = internal ? 0.0 : v2 * regulariser(s, D);
+  H[o] = (internal ? v2 : v2 * source_factor(s, D)) - z / 6.0;
 }
 
 void launch_second_order_doubles(AmpDims d, const double* W, const double* Z, const double* eps,
-                                 const double* s, double* U, double* H, hipStream_t st) {
+                                 const double* s, double* U, double* H, int nblocks, hipStream_t st) {
   long long nH = d.nC + d.nA, nP = d.nA + d.nV;
   long long total = nP * nP * nH * nH;
-  if (total == 0) return;
-  hipLaunchKernelGGL(second_order_doubles_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0,
-                     st, d, W, Z, eps, s, U, H);
+  if (total == 0 || nblocks <= 0) return;
+  const dim3 grid((unsigned)((total + 255) / 256), (unsigned)nblocks);
+  if (total < (1LL << 31))
+    hipLaunchKernelGGL(second_order_doubles_kernel<unsigned>, grid, dim3(256), 0, st, d, W, Z, eps, s, U, H);
+  else
+    hipLaunchKernelGGL(second_order_doubles_kernel<long long>, grid, dim3(256), 0, st, d, W, Z, eps, s, U, H);
 }
 
 __global__ void combine_f2_kernel(int n, const double* __restrict__ W1, const double* __restrict__ Z1,
@@ -1731,6 +1739,7 @@ void launch_combine_f2(int n, const double* W1, const double* Z1, double* f2, hi
   hipLaunchKernelGGL(combine_f2_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, W1, Z1, f2);
 }
 
+// spin block blockIdx.y
 __global__ void second_order_h1_kernel(AmpDims d, const double* __restrict__ W1,
                                        const double* __restrict__ Z1,
                                        const double* __restrict__ src, double* __restrict__ H1) {
@@ -1738,18 +1747,19 @@ __global__ void second_order_h1_kernel(AmpDims d, const double* __restrict__ W1,
   int e = blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= nP * nH) return;
   int a = e / nH, i = e % nH;
+  const long long o = (long long)blockIdx.y * nP * nH + e;
   bool internal = a < d.nA && i >= d.nC;
-  double z = Z1[e];
-  double f2 = W1[e] + 0.5 * z;
-  H1[e] = (internal ? f2 : src[e]) - z / 6.0;
+  double z = Z1[o];
+  double f2 = W1[o] + 0.5 * z;
+  H1[o] = (internal ? f2 : src[o]) - z / 6.0;
 }
 
 void launch_second_order_h1(AmpDims d, const double* W1, const double* Z1, const double* src,
-                            double* H1, hipStream_t st) {
+                            double* H1, int nspins, hipStream_t st) {
   int n = (d.nA + d.nV) * (d.nC + d.nA);
-  if (n == 0) return;
-  hipLaunchKernelGGL(second_order_h1_kernel, dim3((n + 255) / 256), dim3(256), 0, st, d, W1, Z1, src,
-                     H1);
+  if (n == 0 || nspins <= 0) return;
+  hipLaunchKernelGGL(second_order_h1_kernel, dim3((n + 255) / 256, (unsigned)nspins), dim3(256), 0, st, d, W1,
+                     Z1, src, H1);
 }
 
 __global__ __launch_bounds__(256) void pair_dot_kernel(AmpDims d, const double* __restrict__ G2,
