@@ -1472,10 +1472,12 @@ void launch_expand_rdm(int nA, int rank, const double* blocks, double* so, hipSt
 }
 
 // lambda2[p,q,r,s] = G2 - (g_pr g_qs - g_ps g_qr);  C-convention over spin orbitals.
+// (the first n^2 threads also write eta = 1 - gamma1)
 __global__ void cumulant2_kernel(int n, const double* __restrict__ G1, const double* __restrict__ G2,
-                                 double* __restrict__ L2) {
+                                 double* __restrict__ L2, double* __restrict__ eta) {
   const int i = blockIdx.x * blockDim.x + threadIdx.x;
   const int total = n * n * n * n;
+  if (i < n * n) eta[i] = ((i / n) == (i % n) ? 1.0 : 0.0) - G1[i];
   if (i >= total) return;
   const int s = i % n, r = (i / n) % n, q = (i / n / n) % n, p = i / n / n / n;
   L2[i] = G2[i] - (G1[p * n + r] * G1[q * n + s] - G1[p * n + s] * G1[q * n + r]);
@@ -1565,11 +1567,6 @@ __global__ __launch_bounds__(256) void cumulant3_kernel(int n, const double* __r
   L3[i] = g3v - det - gl;
 }
 
-__global__ void eta_kernel(int n, const double* __restrict__ G1, double* __restrict__ eta) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= n * n) return;
-  eta[i] = ((i / n) == (i % n) ? 1.0 : 0.0) - G1[i];
-}
 
 void launch_cumulants(int nA, const double* G1, const double* G2, const double* g3, double* L2,
                       double* L3, double* eta, hipStream_t st) {
@@ -1577,13 +1574,12 @@ void launch_cumulants(int nA, const double* G1, const double* G2, const double* 
   if (n == 0) return;
   long long t2 = (long long)n * n * n * n;
   hipLaunchKernelGGL(cumulant2_kernel, dim3((unsigned)((t2 + 255) / 256)), dim3(256), 0, st, n, G1,
-                     G2, L2);
+                     G2, L2, eta);
   if (g3 && L3) {
     const int n3 = n * n * n;
     hipLaunchKernelGGL(cumulant3_kernel, dim3((unsigned)n3, (unsigned)((n3 + 255) / 256)), dim3(256), 0, st,
                        n, G1, L2, g3, L3);
   }
-  hipLaunchKernelGGL(eta_kernel, dim3((n * n + 255) / 256), dim3(256), 0, st, n, G1, eta);
 }
 
 // ---------------------------------------------------------------------------
