@@ -2378,8 +2378,7 @@ static BodyOut body(Exec& X, OpLog& op, Pool& pool, const Shape& sh, const Input
     double* L2 = pool.alloc((size_t)e4n);
     double* eta = pool.alloc((size_t)e2n);
     double* L3 = pool.alloc((size_t)e6n);
-    op([nA, g1, G1](hipStream_t s) { launch_expand_rdm(nA, 1, g1, G1, s); });
-    op([nA, g2, G2](hipStream_t s) { launch_expand_rdm(nA, 2, g2, G2, s); });
+    op([nA, g1, G1, g2, G2](hipStream_t s) { launch_expand_rdm12(nA, g1, G1, g2, G2, s); });
     if (g3) {
       // the spin blocks of gamma3 go straight into the three-body cumulant
       op([nA, g3, G1, G2, L2, L3, eta](hipStream_t s) { launch_cumulants(nA, G1, G2, g3, L2, L3, eta, s); });
@@ -2515,15 +2514,14 @@ static BodyOut body(Exec& X, OpLog& op, Pool& pool, const Shape& sh, const Input
   // second-order amplitudes and H~(2)_{1,2}
   double* U2 = pool.alloc(3 * n4);
   double* H2 = pool.alloc(3 * n4);
-  double* f2 = pool.alloc(2 * n1);
   double* U1 = pool.alloc(2 * n1);
   double* S2 = pool.alloc(2 * n1);
   double* H1 = pool.alloc(2 * n1);
   op([=](hipStream_t s) {
     launch_second_order_doubles(ad, W2, Z2, eps, sdev, U2, H2, 3, s);   // aa, ab, bb
-    launch_combine_f2((int)(2 * n1), W1, Z1, f2, s);
-    launch_singles(ad, U2, U2 + n4, U2 + 2 * n4, g1a, g1b, eps, sdev, f2, f2 + n1, U1, U1 + n1, S2,
-                   S2 + n1, s);
+    // f(2) = W1 + Z1 / 2 formed inside the singles launch
+    launch_singles(ad, U2, U2 + n4, U2 + 2 * n4, g1a, g1b, eps, sdev, W1, W1 + n1, U1, U1 + n1, S2,
+                   S2 + n1, s, Z1, Z1 + n1);
     launch_second_order_h1(ad, W1, Z1, S2, H1, 2, s);   // alpha, beta
   });
   // E(3)_a = <[H~(1), T(2)]> and E(3)_b = <[H~(2)_{1,2}, T(1)]>: without the pair

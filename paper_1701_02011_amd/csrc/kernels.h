@@ -224,6 +224,8 @@ void launch_ladder_unpack_sym(const double* Xs, const double* Xa, int rows, int 
 // Spin-orbital active densities [2nA]^k from the spin-block inputs, and cumulants.  The
 // three-body density enters the cumulant as its spin blocks g3 (expanded on the fly).
 void launch_expand_rdm(int nA, int rank, const double* blocks, double* so, hipStream_t st);
+// gamma1 (blocks g1 -> G1) and gamma2 (g2 -> G2) in one launch
+void launch_expand_rdm12(int nA, const double* g1, double* G1, const double* g2, double* G2, hipStream_t st);
 void launch_cumulants(int nA, const double* G1, const double* G2, const double* g3, double* L2,
                       double* L3, double* eta, hipStream_t st);
 
@@ -239,11 +241,12 @@ void launch_first_order_doubles(AmpDims d, const double* Jhphp, const double* ep
                                 double* E2aa, double* E2ab, hipStream_t st);
 // Singles: coup_s[a,i] = sum_{ux} (e_x - e_u) (t_ss[a,x,i,u] g_s[x,u] + t_{s s'}..[..] g_s'[x,u]);
 // t1 = (f + coup) R_s(D), and the non-diagonal one-body source (f + coup) exp(-s D^2).
-// f may be null (zero).  For a null g1 (nA = 0) coup = 0.
+// f may be null (zero); with za, zb given, f = fa + za / 2 (fb + zb / 2), the second-order
+// one-body source (2 W1 + Z1) / 2.  For a null g1 (nA = 0) coup = 0.
 void launch_singles(AmpDims d, const double* T2aa, const double* T2ab, const double* T2bb,
                     const double* g1a, const double* g1b, const double* eps, const double* s,
                     const double* fa, const double* fb, double* t1a, double* t1b, double* srca,
-                    double* srcb, hipStream_t st);
+                    double* srcb, hipStream_t st, const double* za = nullptr, const double* zb = nullptr);
 // Second-order doubles and the H~(2) two-body excitation block:
 // O = 2 W + Z; u = (O/2) R_s(D) (0 on internal), H = (O/2) exp(-s D^2) - Z/6 (O/2 - Z/6 internal).
 // nblocks spin blocks at a stride of one [P][P][H][H] block, in one launch.
@@ -254,7 +257,6 @@ void launch_second_order_doubles(AmpDims d, const double* W, const double* Z, co
 // nspins blocks at a stride of one [P][H] block, in one launch.
 void launch_second_order_h1(AmpDims d, const double* W1, const double* Z1, const double* src,
                             double* H1, int nspins, hipStream_t st);
-void launch_combine_f2(int n, const double* W1, const double* Z1, double* f2, hipStream_t st);
 // P2[i][j] += sum over the blocks aa, ab, bb and a, b in P of G2[blk][a][b][i][j] T[blk][a][b][i][j]
 // for core i, j (G2 and T are [P][P][H][H] per block; P2 is [nC][nC]); fixed-order sums.
 void launch_pair_dot(AmpDims d, const double* G2, const double* Taa, const double* Tab,

@@ -1406,7 +1406,8 @@ void launch_scatter(const ScatterDesc& d0, const double* src, double* out, hipSt
 // tuple is its number of (beta, alpha) pairs in that order.  Indices fit 32 bits:
 // (2 nA)^6 < 2^31 for nA <= 8 (larger active spaces are rejected).
 template <int R>
-__global__ void expand_rdm_kernel(int nA, const double* __restrict__ blocks, double* __restrict__ so) {
+__device__ __forceinline__ void expand_rdm_row(int nA, const double* __restrict__ blocks, double* __restrict__ so,
+                                               int row, int l) {
   const int n2 = 2 * nA;
   int nt = 1, bsz = 1;
 #pragma unroll
@@ -1414,10 +1415,9 @@ __global__ void expand_rdm_kernel(int nA, const double* __restrict__ blocks, dou
     nt *= n2;
     bsz *= nA * nA;
   }
-  const int l = blockIdx.y * blockDim.x + threadIdx.x;
   if (l >= nt) return;
   int su[R], pu[R], sl[R], pl[R];
-  int tu = blockIdx.x, tl = l;
+  int tu = row, tl = l;
 #pragma unroll
   for (int c = R - 1; c >= 0; --c) {
     const int xu = tu % n2, xl = tl % n2;
@@ -1434,7 +1434,7 @@ __global__ void expand_rdm_kernel(int nA, const double* __restrict__ blocks, dou
     nbu += su[c];
     nbl += sl[c];
   }
-  const long long o = (long long)blockIdx.x * nt + l;
+  const long long o = (long long)row * nt + l;
   if (nbu != nbl) {
     so[o] = 0.0;
     return;
@@ -1456,6 +1456,26 @@ __global__ void expand_rdm_kernel(int nA, const double* __restrict__ blocks, dou
       if (sl[c] == sp) off = off * nA + pl[c];
   const double v = blocks[(long long)nbu * bsz + off];
   so[o] = (par & 1) ? -v : v;
+}
+
+template <int R>
+__global__ void expand_rdm_kernel(int nA, const double* __restrict__ blocks, double* __restrict__ so) {
+  expand_rdm_row<R>(nA, blocks, so, blockIdx.x, blockIdx.y * blockDim.x + threadIdx.x);
+}
+
+// gamma1 and gamma2 in one launch: rows [0, 2 nA) are gamma1's, the next (2 nA)^2 gamma2's
+// (each row has at most (2 nA)^2 <= 256 lower tuples)
+__global__ void expand_rdm12_kernel(int nA, const double* __restrict__ g1, double* __restrict__ G1,
+                                    const double* __restrict__ g2, double* __restrict__ G2) {
+  const int n2 = 2 * nA;
+  if ((int)blockIdx.x < n2) expand_rdm_row<1>(nA, g1, G1, blockIdx.x, threadIdx.x);
+  else expand_rdm_row<2>(nA, g2, G2, blockIdx.x - n2, threadIdx.x);
+}
+
+void launch_expand_rdm12(int nA, const double* g1, double* G1, const double* g2, double* G2, hipStream_t st) {
+  const int n2 = 2 * nA;
+  if (n2 == 0) return;
+  hipLaunchKernelGGL(expand_rdm12_kernel, dim3((unsigned)(n2 + n2 * n2)), dim3(256), 0, st, nA, g1, G1, g2, G2);
 }
 
 void launch_expand_rdm(int nA, int rank, const double* blocks, double* so, hipStream_t st) {
@@ -1639,6 +1659,7 @@ __global__ void singles_kernel(AmpDims d, const double* __restrict__ Taa, const 
                                const double* __restrict__ Tbb, const double* __restrict__ ga,
                                const double* __restrict__ gb, const double* __restrict__ eps, const double* __restrict__ sp,
                                const double* __restrict__ fa, const double* __restrict__ fb,
+                               const double* __restrict__ za, const double* __restrict__ zb,
                                double* __restrict__ t1a, double* __restrict__ t1b,
                                double* __restrict__ srca, double* __restrict__ srcb) {
   const double s = *sp;
@@ -1669,7 +1690,8 @@ __global__ void singles_kernel(AmpDims d, const double* __restrict__ Taa, const 
   if (lane != 0) return;
   double f = 0.0;
   const double* fp = spin ? fb : fa;
-  if (fp) f = fp[e];
+  const double* zp = spin ? zb : za;
+  if (fp) f = zp ? fp[e] + 0.5 * zp[e] : fp[e];
   bool internal = a < nA && i >= nC;
   double D1 = eps[i] - eps[nC + a];
   double* t1 = spin ? t1b : t1a;
@@ -1681,12 +1703,12 @@ __global__ void singles_kernel(AmpDims d, const double* __restrict__ Taa, const 
 void launch_singles(AmpDims d, const double* T2aa, const double* T2ab, const double* T2bb,
                     const double* g1a, const double* g1b, const double* eps, const double* s,
                     const double* fa, const double* fb, double* t1a, double* t1b, double* srca,
-                    double* srcb, hipStream_t st) {
+                    double* srcb, hipStream_t st, const double* za, const double* zb) {
   int nH = d.nC + d.nA, nP = d.nA + d.nV;
   int total = 2 * nP * nH;   // elements, one wave each
   if (total == 0) return;
   hipLaunchKernelGGL(singles_kernel, dim3((total + 3) / 4), dim3(256), 0, st, d, T2aa, T2ab, T2bb,
-                     g1a, g1b, eps, s, fa, fb, t1a, t1b, srca, srcb);
+                     g1a, g1b, eps, s, fa, fb, za, zb, t1a, t1b, srca, srcb);
 }
 
 // Spin block blockIdx.y; the element index in 32-bit arithmetic when a block has fewer than
@@ -1724,16 +1746,6 @@ void launch_second_order_doubles(AmpDims d, const double* W, const double* Z, co
     hipLaunchKernelGGL(second_order_doubles_kernel<long long>, grid, dim3(256), 0, st, d, W, Z, eps, s, U, H);
 }
 
-__global__ void combine_f2_kernel(int n, const double* __restrict__ W1, const double* __restrict__ Z1,
-                                  double* __restrict__ f2) {
-  int i = blockIdx.x * blockDim.x + threadIdx.x;
-  if (i < n) f2[i] = W1[i] + 0.5 * Z1[i];
-}
-
-void launch_combine_f2(int n, const double* W1, const double* Z1, double* f2, hipStream_t st) {
-  if (n == 0) return;
-  hipLaunchKernelGGL(combine_f2_kernel, dim3((n + 255) / 256), dim3(256), 0, st, n, W1, Z1, f2);
-}
 
 // spin block blockIdx.y
 __global__ void second_order_h1_kernel(AmpDims d, const double* __restrict__ W1,
