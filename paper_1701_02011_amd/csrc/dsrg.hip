@@ -1425,10 +1425,17 @@ struct Exec {
         group_launch(fl, [d_dots, nd, blocks, part](hipStream_t s) {
           launch_dot_group(d_dots, nd, blocks, part, s);
         });
-        for (size_t k = 0; k < outs_s.size(); ++k) {
-          double* d_coef = upload(bcoef[k]);
-          double* so = outs_s[k];
-          op([blocks, part, d_coef, so](hipStream_t s) { launch_weighted_sum(blocks, part, d_coef, so, s); });
+        // every slot's weighted sum in one launch (workgroup k sums slot k in a fixed order)
+        for (size_t k0 = 0; k0 < outs_s.size(); k0 += 8) {
+          const size_t k1 = std::min(outs_s.size(), k0 + 8);
+          std::vector<double> coefs;
+          SumOuts so;
+          for (size_t k = k0; k < k1; ++k) {
+            coefs.insert(coefs.end(), bcoef[k].begin(), bcoef[k].end());
+            so.o[so.n++] = outs_s[k];
+          }
+          double* d_coef = upload(coefs);
+          op([blocks, part, d_coef, so](hipStream_t s) { launch_weighted_sums(blocks, part, d_coef, so, s); });
           ++n_launch;
         }
       }

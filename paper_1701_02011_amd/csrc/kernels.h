@@ -267,6 +267,12 @@ void launch_pair_dot(AmpDims d, const double* G2, const double* Taa, const doubl
 void launch_pair_fold(int nC, const double* P2, const double* energies, double* out, hipStream_t st);
 // out = sum_i coef[i] * vals[i] (fixed order)
 void launch_weighted_sum(int n, const double* vals, const double* coef, double* out, hipStream_t st);
+// out.o[k] = sum_i coef[k][i] vals[i] for k < out.n (<= 8), one launch
+struct SumOuts {
+  double* o[8] = {};
+  int n = 0;
+};
+void launch_weighted_sums(int n, const double* vals, const double* coef, const SumOuts& out, hipStream_t st);
 void launch_fill(double* p, long long n, double v, hipStream_t st);
 // O[p][q][i][j] += X[p][q][i][j] - X[q][p][i][j] - X[p][q][j][i] + X[q][p][j][i]
 // (both [P][P][H][H], dense, distinct arrays)

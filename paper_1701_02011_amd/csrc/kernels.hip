@@ -1616,6 +1616,9 @@ __device__ __forceinline__ double source_factor(double s, double D) {
   return exp(-s * D * D);
 }
 
+// element index in 32-bit arithmetic when the block has fewer than 2^31 elements (Idx =
+// unsigned), else 64-bit
+template <class Idx>
 __global__ void first_order_doubles_kernel(AmpDims d, const double* __restrict__ J,
                                            const double* __restrict__ eps, const double* __restrict__ sp,
                                            double* __restrict__ Taa, double* __restrict__ Tab,
@@ -1623,10 +1626,11 @@ __global__ void first_order_doubles_kernel(AmpDims d, const double* __restrict__
                                            double* __restrict__ Eaa, double* __restrict__ Eab) {
   const double s = *sp;
   const int nH = d.nC + d.nA, nP = d.nA + d.nV;
-  long long total = (long long)nP * nP * nH * nH;
-  long long idx = blockIdx.x * (long long)blockDim.x + threadIdx.x;
+  const Idx total = (Idx)nP * nP * nH * nH;
+  const Idx idx = (Idx)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx >= total) return;
-  int j = idx % nH, i = (idx / nH) % nH, b = (idx / nH / nH) % nP, a = idx / nH / nH / nP;
+  const Idx q1 = idx / nH, q2 = q1 / nH, q3 = q2 / nP;
+  const int j = (int)(idx - q1 * nH), i = (int)(q1 - q2 * nH), b = (int)(q2 - q3 * nP), a = (int)q3;
   // J(HP|HP)[i][a][j][b] = (ia|jb) = (ai|bj)
   double vab = J[(((long long)i * nP + a) * nH + j) * nP + b];
   double vx = J[(((long long)j * nP + a) * nH + i) * nP + b];  // (aj|bi)
@@ -1649,8 +1653,12 @@ void launch_first_order_doubles(AmpDims d, const double* J, const double* eps, c
   long long nH = d.nC + d.nA, nP = d.nA + d.nV;
   long long total = nP * nP * nH * nH;
   if (total == 0) return;
-  hipLaunchKernelGGL(first_order_doubles_kernel, dim3((unsigned)((total + 255) / 256)), dim3(256), 0,
-                     st, d, J, eps, s, T2aa, T2ab, Y2aa, Y2ab, E2aa, E2ab);
+  if (total < (1LL << 31))
+    hipLaunchKernelGGL(first_order_doubles_kernel<unsigned>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0,
+                       st, d, J, eps, s, T2aa, T2ab, Y2aa, Y2ab, E2aa, E2ab);
+  else
+    hipLaunchKernelGGL(first_order_doubles_kernel<long long>, dim3((unsigned)((total + 255) / 256)), dim3(256), 0,
+                       st, d, J, eps, s, T2aa, T2ab, Y2aa, Y2ab, E2aa, E2ab);
 }
 
 // coup_a[a,i] = sum_ux (e_x - e_u)(t_aa[a,x,i,u] g_a[x,u] + t_ab[a,x,i,u] g_b[x,u])
@@ -1835,9 +1843,9 @@ void launch_pair_fold(int nC, const double* P2, const double* energies, double* 
 }
 
 // one workgroup; thread t sums elements t, t + 256, ... and a fixed tree combines them
-__global__ __launch_bounds__(256) void weighted_sum_kernel(int n, const double* __restrict__ vals,
-                                                           const double* __restrict__ coef,
-                                                           double* __restrict__ out) {
+__device__ __forceinline__ void weighted_sum_kernel_body(int n, const double* __restrict__ vals,
+                                                         const double* __restrict__ coef,
+                                                         double* __restrict__ out) {
   __shared__ double red[256];
   double s = 0.0;
   for (int i = threadIdx.x; i < n; i += 256) s += coef[i] * vals[i];
@@ -1850,8 +1858,25 @@ __global__ __launch_bounds__(256) void weighted_sum_kernel(int n, const double* 
   if (threadIdx.x == 0) out[0] = red[0];
 }
 
+__global__ __launch_bounds__(256) void weighted_sum_kernel(int n, const double* __restrict__ vals,
+                                                           const double* __restrict__ coef,
+                                                           double* __restrict__ out) {
+  weighted_sum_kernel_body(n, vals, coef, out);
+}
+
 void launch_weighted_sum(int n, const double* vals, const double* coef, double* out, hipStream_t st) {
   hipLaunchKernelGGL(weighted_sum_kernel, dim3(1), dim3(256), 0, st, n, vals, coef, out);
+}
+
+// workgroup k: out.o[k] = sum_i coef[k n + i] vals[i], the same fixed order as above
+__global__ __launch_bounds__(256) void weighted_sums_kernel(int n, const double* __restrict__ vals,
+                                                            const double* __restrict__ coef, SumOuts out) {
+  weighted_sum_kernel_body(n, vals, coef + (long long)blockIdx.x * n, out.o[blockIdx.x]);
+}
+
+void launch_weighted_sums(int n, const double* vals, const double* coef, const SumOuts& out, hipStream_t st) {
+  if (out.n <= 0) return;
+  hipLaunchKernelGGL(weighted_sums_kernel, dim3((unsigned)out.n), dim3(256), 0, st, n, vals, coef, out);
 }
 
 __global__ void fill_kernel(double* __restrict__ p, long long n, double v) {
