@@ -462,3 +462,178 @@ def test_pair_energies_follow_core_permutation():
     for (i, j), v in b.items():
         key = tuple(sorted((int(perm[i]), int(perm[j]))))
         assert abs(v - a[key]) <= 1e-12 * max(1.0, abs(v)), ((i, j), key)
+
+
+# ---------------------------------------------------------------------------
+# The integral builder and the multireference projection, pinned in Fock space
+# ---------------------------------------------------------------------------
+def _so_map(nC, nA, nV):
+    """Spin-orbital index of (spatial p, spin sigma) in the space-major layout
+    [core a | core b | active a | active b | virtual a | virtual b], written out here
+    independently of the oracle's own layout helper."""
+    idx = {}
+    k = 0
+    for off, n in ((0, nC), (nC, nA), (nC + nA, nV)):
+        for sigma in (0, 1):
+            for p in range(off, off + n):
+                idx[(p, sigma)] = k
+                k += 1
+    return idx
+
+
+def test_so_integrals_against_chemists_operator():
+    """The two-electron operator written straight from the factorised chemists' integrals
+    (Eq. int_fact), 1/2 sum_{pqrs} sum_{sigma tau} (pq|rs) a+_{p sigma} a+_{r tau} a_{s tau}
+    a_{q sigma}, with explicit loops over spatial orbitals and spins, has the same Fock-space
+    matrix as 1/4 sum <pq||rs> a+_p a+_q a_s a_r built from the oracle's antisymmetrised
+    integrals.  A misplaced index in <pq||rs> (e.g. (pq|rs) - (pq|sr)) changes the matrix."""
+    nC, nA, nV, M = 1, 1, 2, 5
+    p = make_problem(nC, nA, nV, M, seed=61)
+    N = nC + nA + nV
+    eri = np.einsum("Qpq,Qrs->pqrs", p.B, p.B)       # (pq|rs), chemists' order
+    so = _so_map(nC, nA, nV)
+    n = 2 * N
+    fs = FockSpace(n)
+    rng = np.random.default_rng(62)
+    vecs = rng.standard_normal((3, fs.dim))
+    # explicit operator: accumulate its action on the test vectors
+    lhs = np.zeros_like(vecs)
+    for P_ in range(N):
+        for Q_ in range(N):
+            for R_ in range(N):
+                for S_ in range(N):
+                    g = 0.5 * eri[P_, Q_, R_, S_]
+                    for sig in (0, 1):
+                        for tau in (0, 1):
+                            cp, cr = fs.cre[so[(P_, sig)]], fs.cre[so[(R_, tau)]]
+                            as_, aq = fs.ann[so[(S_, tau)]], fs.ann[so[(Q_, sig)]]
+                            for k in range(len(vecs)):
+                                lhs[k] += g * (cp @ (cr @ (as_ @ (aq @ vecs[k]))))
+    sp = Spaces(nC, nA, nV)
+    v = so_integrals(sp, p.B)
+    # 1/4 v[p,q,r,s] a+p a+q a_s a_r in the plain order a+p a+q a_r' a_s' of FockSpace.apply
+    K2 = 0.25 * v.transpose(0, 1, 3, 2)
+    rhs = np.array([fs.apply((0.0, None, K2), x) for x in vecs])
+    assert np.abs(lhs).max() > 1e-3
+    assert np.abs(lhs - rhs).max() < 1e-13 * np.abs(lhs).max()
+
+
+def _fock_string(fs, cre, ann, vec):
+    """a+_{c1} .. a+_{ck} a_{d1} .. a_{dk} |vec> (bare plain-order string)."""
+    w = vec
+    for d in reversed(ann):
+        w = fs.ann[d] @ w
+    for c in reversed(cre):
+        w = fs.cre[c] @ w
+    return w
+
+
+def _normal_product_action(fs, psi0, cre, ann, vec, memo):
+    """{a+_{c1} .. a+_{ck} a_{d1} .. a_{dk}} |vec> for the multideterminantal reference psi0
+    (Mukherjee-Kutzelnigg generalised normal order, Sec. II.A), built recursively in the
+    full Fock space:
+        bare string = sum over equal-size subsets I of creators and J of annihilators of
+                      sign(I, J) <psi0| removed string |psi0> {remaining string},
+    where the I = J = {} term is the normal product itself and the expectation values are
+    brute-force matrix elements of psi0 (no cumulant or density code of the oracle)."""
+    key = (tuple(cre), tuple(ann))
+    if key in memo:
+        return memo[key]
+    k = len(cre)
+    out = _fock_string(fs, cre, ann, vec)
+    if k > 0:
+        ops = [("c", c) for c in cre] + [("a", d) for d in ann]
+        for m in range(1, k + 1):
+            for I in itertools.combinations(range(k), m):
+                for J in itertools.combinations(range(k), m):
+                    removed = [i for i in I] + [k + j for j in J]
+                    rest = [i for i in range(2 * k) if i not in removed]
+                    # sign of the permutation (removed block first, order kept in each block)
+                    perm = removed + rest
+                    sgn = perm_sign_local(perm)
+                    rc = [cre[i] for i in I]
+                    ra = [ann[j] for j in J]
+                    dens = psi0 @ _fock_string(fs, rc, ra, psi0)
+                    if dens == 0.0:
+                        continue
+                    kc = [cre[i] for i in range(k) if i not in I]
+                    ka = [ann[j] for j in range(k) if j not in J]
+                    out = out - sgn * dens * _normal_product_action(fs, psi0, kc, ka, vec, memo)
+    memo[key] = out
+    return out
+
+
+def perm_sign_local(perm):
+    inv = sum(1 for i in range(len(perm)) for j in range(i + 1, len(perm)) if perm[i] > perm[j])
+    return -1.0 if inv % 2 else 1.0
+
+
+@pytest.mark.parametrize("nC,nA,nV,seed", [(1, 3, 1, 71), (0, 4, 1, 72)])
+def test_multireference_projection_in_fock_space(nC, nA, nV, seed):
+    """The oracle's bare -> GNO projection of rank-3 and rank-2 bare operators (scalar,
+    one- and two-body parts; the "1,2" truncation of Sec. II.A) obeys the operator identity
+        R3 + R2 = c0 + {c1} + {c2} + {R3}
+    in the full Fock space of a correlated CAS reference (non-zero two- and three-body
+    cumulants), with every normal product built recursively from brute-force reference
+    expectation values; and <psi0|{R3}|psi0> = 0.  Weighting the two-index removals of the
+    rank-3 part by gamma ^ gamma instead of the full two-body density (dropping lambda2), or
+    a wrong sign in any branch, breaks the identity."""
+    p = make_problem(nC, nA, nV, 6, seed=seed)
+    sp = Spaces(nC, nA, nV)
+    n = 2 * sp.N
+    fs = FockSpace(n)
+    psi0 = reference_vector(sp, p.ci, p.n_alpha, p.n_beta, fs)
+    dens = build_densities(sp, p.gamma1, p.gamma2, p.gamma3)
+    assert np.abs(dens.L2).max() > 1e-2 and np.abs(dens.L3).max() > 1e-2
+    rng = np.random.default_rng(seed + 1)
+    # sparse random bare operators: rank-3 strings mostly over the hole space, where the
+    # reference densities are non-zero, and a few rank-2 strings
+    H = list(range(2 * sp.nH))
+    G_ = list(range(n))
+    K3 = np.zeros((n,) * 6)
+    strings3 = []
+    for _ in range(24):
+        pick = lambda: int(rng.choice(H)) if rng.random() < 0.8 else int(rng.choice(G_))
+        c = [pick() for _ in range(3)]
+        a = [pick() for _ in range(3)]
+        val = rng.standard_normal()
+        K3[tuple(c + a)] += val
+        strings3.append((c, a, val))
+    K2 = np.zeros((n,) * 4)
+    strings2 = []
+    for _ in range(8):
+        c = [int(rng.choice(H)) for _ in range(2)]
+        a = [int(rng.choice(H)) for _ in range(2)]
+        val = rng.standard_normal()
+        K2[tuple(c + a)] += val
+        strings2.append((c, a, val))
+    G, Hs = slice(0, n), slice(0, 2 * sp.nH)
+    c0, c1, c2 = _project([], [Term(1.0, [(K2, "abcd")], "abcd")],
+                          [Term(1.0, [(K3, "abcdef")], "abcdef")], dens, True,
+                          (G, G), (G, G, G, G), G, Hs)
+    # test vectors: the reference and random vectors in its particle-number sector
+    ne = 2 * nC + p.n_alpha + p.n_beta
+    sector = fs.number_sector(ne)
+    tests = [psi0]
+    for _ in range(2):
+        x = np.zeros(fs.dim)
+        x[sector] = rng.standard_normal(len(sector))
+        tests.append(x)
+    for x in tests:
+        memo = {}
+        lhs = np.zeros(fs.dim)
+        for c, a, val in strings3 + strings2:
+            lhs += val * _fock_string(fs, c, a, x)
+        rhs = c0 * x
+        for (i, j) in zip(*np.nonzero(np.abs(c1) > 0)):
+            rhs += c1[i, j] * _normal_product_action(fs, psi0, [i], [j], x, memo)
+        for idx in zip(*np.nonzero(np.abs(c2) > 0)):
+            rhs += c2[idx] * _normal_product_action(fs, psi0, list(idx[:2]), list(idx[2:]), x, memo)
+        r3 = np.zeros(fs.dim)
+        for c, a, val in strings3:
+            r3 += val * _normal_product_action(fs, psi0, c, a, x, memo)
+        rhs += r3
+        if x is psi0:
+            assert abs(psi0 @ r3) < 1e-12
+        assert np.abs(lhs).max() > 1e-3
+        assert np.abs(lhs - rhs).max() < 1e-11 * max(1.0, np.abs(lhs).max())
