@@ -16,14 +16,14 @@
  *   - Orbitals are restricted (one spatial set for alpha and beta); the reference may
  *     have different alpha and beta densities.
  *   - The orbitals are semicanonical: eps are the diagonal elements of the core, active
- *     and virtual blocks of the generalised Fock matrix (Sec. II.B, Eq. F0th), and the
- *     inter-block Fock elements are taken as zero.
- *   - The returned energies are correlation energies (the reference energy E0 is not an
- *     input) of the unrelaxed series (Eq. E_unrelaxed).
+ *     and virtual blocks of the generalised Fock matrix (Sec. II.B, Eq. F0th).  The
+ *     inter-block Fock elements f(1) are an optional input (zero when not given).
+ *   - e2 and e3 are correlation energies of the unrelaxed series (Eq. E_unrelaxed);
+ *     e_total adds the caller's reference energy e0.
  *   - All arrays are FP64, C (row-major) order.
  *
- * Execution: the first call of a shape (device, nC, nA, nV, n_aux, gamma3 given or not,
- * E(2) or E(3), grouping, workspace_cap) runs the pipeline and records it as a plan: its
+ * Execution: the first call of a shape (device, nC, nA, nV, n_aux, gamma3 and f_offdiag
+ * given or not, E(2) or E(3), grouping, precision, workspace_cap, virt_batch) runs the pipeline and records it as a plan: its
  * device buffers plus a HIP graph of every launch.  Later calls of that shape copy their
  * inputs into the plan's buffers and launch the graph on the caller's stream; the result
  * is bitwise the same as the recording run's would be for the same inputs.  At most 4
@@ -54,6 +54,11 @@ extern "C" {
 #define DSRG_E_OOM (-3)         /* device allocation failed or workspace_cap too small */
 #define DSRG_E_HIP (-4)         /* HIP runtime error (message in dsrg_last_error) */
 #define DSRG_E_UNSUPPORTED (-5) /* option not built (unknown precision, nA > 8) */
+#define DSRG_E_RDM (-6)         /* gamma1 not symmetric, or gamma2 not Hermitian (uv <-> xy) or,
+                                   in its same-spin blocks, not antisymmetric in u <-> v and
+                                   x <-> y, beyond 1e-10 */
+#define DSRG_E_INTRUDER (-7)    /* s = +INFINITY and some non-internal denominator |D| < 1e-12
+                                   (the unregularised limit 1/D does not exist) */
 
 /* options.precision */
 #define DSRG_PRECISION_FP64 0   /* every step in FP64 */
@@ -100,6 +105,14 @@ typedef struct {
   const double* gamma3;
   /* flow parameter s (E_h^-2), > 0; +INFINITY selects the unregularised limit 1/D */
   double s;
+  /* [N][N] inter-block part of the Fock matrix, f(1) of H(1) = f(1) + V (Sec. II.B: H(0) holds
+     the core, active and virtual diagonal blocks, which are diagonal in semicanonical
+     orbitals).  Only the elements between different blocks (core-active, core-virtual,
+     active-virtual) are read; the matrix must be symmetric there.  NULL means f(1) = 0. */
+  const double* f_offdiag;
+  /* reference energy E0 (E_h); only added into dsrg_result.e_total (Eq. E_unrelaxed).  A
+     zero-initialised struct gives e_total = E(2) + E(3); NaN gives NaN. */
+  double e0;
 } dsrg_problem;
 
 typedef struct {
@@ -108,6 +121,10 @@ typedef struct {
   int64_t workspace_cap;  /* bytes of device workspace for the batched (PP|PP) integrals and their
                              packed pair rows; 0 = 8 GiB */
   void* stream;           /* hipStream_t to run on, or NULL for the null stream; caller owns it */
+  int32_t virt_batch;     /* values of the first particle index per (PP|PP) integral batch
+                             (Sec. III, Eq. scaling_problem); 0 = the largest batch that fits
+                             workspace_cap.  A batch that does not fit workspace_cap, or a cap
+                             below one row, returns DSRG_E_OOM. */
 } dsrg_options;
 
 typedef struct {
@@ -137,6 +154,12 @@ typedef struct {
   double role_bytes[4];   /* with DSRG_F_PROFILE: algorithmic bytes of the role_* launches, each
                              operand view read once and the result written once (read too when
                              accumulated) */
+  double e_total;         /* e0 + E(2) + E(3) (E(3) = 0 for dsrg_pt2_energy) */
+  double alg_flops;       /* algorithmic flops of the executed contractions: 2 M N K per
+                             contraction of the term list and of the integral builds, unique
+                             index pairs for the ladder, no zero padding */
+  int32_t precision_used; /* DSRG_PRECISION_* the contractions ran in */
+  int32_t virt_batch_used;/* (PP|PP) batch size used (0: no ladder) */
 } dsrg_result;
 
 /* Optional host outputs of intermediates (each pointer may be NULL).  Shapes use
@@ -145,7 +168,7 @@ typedef struct {
 typedef struct {
   double* t1;   /* [2][nP][nH]       first-order singles, spins a, b */
   double* t2;   /* [3][nP][nP][nH][nH] first-order doubles, blocks aa, ab, bb */
-  double* w1;   /* [2][nP][nH]       excitation block of [V, A(1)]_{1,2} */
+  double* w1;   /* [2][nP][nH]       excitation block of [f(1) + V, A(1)]_{1,2} */
   double* w2;   /* [3][nP][nP][nH][nH] */
   double* z1;   /* [2][nP][nH]       excitation block of [[H(0), A(1)], A(1)]_{1,2} */
   double* z2;   /* [3][nP][nP][nH][nH] */

@@ -5,9 +5,9 @@ generic engine in ``gno`` (no hand-derived working equations).  Sizes up to the
 "small" workload (120 spin orbitals) run in seconds to a minute.
 
 Readings of the paper used here (each also listed in the design notes):
-* Only the semicanonical energies, the factorised integrals and the reference
-  densities are given, so the inter-block Fock elements f^(1) are zero and the
-  first-order Hamiltonian H^(1) is the normal-ordered two-body operator.
+* The zeroth-order Hamiltonian holds the core, active and virtual diagonal blocks of the
+  Fock matrix (diagonal in semicanonical orbitals); the inter-block Fock elements f^(1),
+  when the problem carries them, belong to H^(1) = f^(1) + V, and are zero otherwise.
 * Only correlation energies are returned (E0 is not an input); the energy is the
   unrelaxed one of Eq. E_unrelaxed.
 * The regulariser R_s(D) = (1 - exp(-s D^2)) / D takes its limit 0 at D = 0.
@@ -69,6 +69,21 @@ class Result:
     h2_1: np.ndarray     # H~(2)_{1,2} one-body [P][H]
     h2_2: np.ndarray     # H~(2)_{1,2} two-body [P][P][H][H]
     ops: Optional[dict] = None   # with keep_ops: the operators of the two E(3) scalars
+
+
+def so_fock_offdiag(sp: Spaces, f) -> np.ndarray:
+    """f^(1) over spin orbitals: the spatial inter-block Fock elements on equal spins, with
+    the core, active and virtual diagonal blocks (which belong to H^(0)) set to zero."""
+    n = 2 * sp.N
+    out = np.zeros((n, n))
+    if f is None:
+        return out
+    spatial, spin = sp.so_index()
+    blk = np.array([0] * sp.nC + [1] * sp.nA + [2] * sp.nV)[spatial]
+    out = np.asarray(f, dtype=np.float64)[np.ix_(spatial, spatial)].copy()
+    out[spin[:, None] != spin[None, :]] = 0.0
+    out[blk[:, None] == blk[None, :]] = 0.0
+    return out
 
 
 def _internal_mask(sp: Spaces):
@@ -136,8 +151,9 @@ def run(prob: Problem, keep_ops: bool = False, through: str = "e3") -> Result:
     # step a1: antisymmetrised integrals from the factorised tensor (Eq. int_fact)
     v = so_integrals(sp, prob.B)
     m1, m2 = _internal_mask(sp)
-    # step a2: first-order amplitudes (Eqs. T1_1st, T2_1st); f^(1) = 0
-    t1, t2 = amplitudes(sp, eps, dens.gamma, s, np.zeros((n, n)), v, m1, m2)
+    f1 = so_fock_offdiag(sp, getattr(prob, "f_offdiag", None))
+    # step a2: first-order amplitudes (Eqs. T1_1st, T2_1st), driven by f^(1) and v
+    t1, t2 = amplitudes(sp, eps, dens.gamma, s, f1, v, m1, m2)
     a1_1, a1_2 = anti_hermitian(t1, t2)
     A1 = gno.to_plain(0.0, a1_1, a1_2)
     F0 = (0.0, np.diag(eps), None)
@@ -146,7 +162,7 @@ def run(prob: Problem, keep_ops: bool = False, through: str = "e3") -> Result:
     y1_1 = y1_1p
     y1_2 = gno.c_from_plain2(y1_2p)
     del y1_2p
-    ht1_1 = y1_1
+    ht1_1 = 2.0 * f1 + y1_1
     ht1_2 = 2.0 * v + y1_2
     Ht1 = gno.to_plain(0.0, ht1_1, ht1_2)
     T1 = gno.to_plain(0.0, t1, t2)

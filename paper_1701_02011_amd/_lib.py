@@ -21,6 +21,8 @@ DSRG_E_NONFINITE = -2
 DSRG_E_OOM = -3
 DSRG_E_HIP = -4
 DSRG_E_UNSUPPORTED = -5
+DSRG_E_RDM = -6
+DSRG_E_INTRUDER = -7
 DSRG_F_DEVICE_PTRS = 1
 DSRG_F_PROFILE = 2
 DSRG_F_NO_GROUPING = 4
@@ -36,12 +38,14 @@ class Problem(ctypes.Structure):
     _fields_ = [("n_core", ctypes.c_int32), ("n_active", ctypes.c_int32),
                 ("n_virtual", ctypes.c_int32), ("n_aux", ctypes.c_int32),
                 ("eps", ctypes.c_void_p), ("B", ctypes.c_void_p), ("gamma1", ctypes.c_void_p),
-                ("gamma2", ctypes.c_void_p), ("gamma3", ctypes.c_void_p), ("s", ctypes.c_double)]
+                ("gamma2", ctypes.c_void_p), ("gamma3", ctypes.c_void_p), ("s", ctypes.c_double),
+                ("f_offdiag", ctypes.c_void_p), ("e0", ctypes.c_double)]
 
 
 class Options(ctypes.Structure):
     _fields_ = [("flags", ctypes.c_int32), ("precision", ctypes.c_int32),
-                ("workspace_cap", ctypes.c_int64), ("stream", ctypes.c_void_p)]
+                ("workspace_cap", ctypes.c_int64), ("stream", ctypes.c_void_p),
+                ("virt_batch", ctypes.c_int32)]
 
 
 class Result(ctypes.Structure):
@@ -52,7 +56,9 @@ class Result(ctypes.Structure):
                 ("n_launch", ctypes.c_int32), ("role_seconds", ctypes.c_double * 4),
                 ("role_flops", ctypes.c_double * 4), ("role_launches", ctypes.c_int32 * 4),
                 ("plan", ctypes.c_int32), ("grouped_uses", ctypes.c_int32),
-                ("role_bytes", ctypes.c_double * 4)]
+                ("role_bytes", ctypes.c_double * 4), ("e_total", ctypes.c_double),
+                ("alg_flops", ctypes.c_double), ("precision_used", ctypes.c_int32),
+                ("virt_batch_used", ctypes.c_int32)]
 
 
 class Intermediates(ctypes.Structure):
@@ -123,38 +129,43 @@ def _host(a):
     return arr, arr.ctypes.data
 
 
+_ARRAYS = ("eps", "B", "gamma1", "gamma2", "gamma3", "f_offdiag")
+
+
 def _problem_struct(p, keep):
     """dsrg_problem from a synth.Problem (host arrays) or a dict of torch device tensors."""
     if isinstance(p, dict):
         fl = DSRG_F_DEVICE_PTRS
         get = lambda k: None if p.get(k) is None else p[k].data_ptr()
-        for k in ("eps", "B", "gamma1", "gamma2", "gamma3"):
+        for k in _ARRAYS:
             if p.get(k) is not None:
                 keep.append(p[k])
         st = Problem(int(p["n_core"]), int(p["n_active"]), int(p["n_virtual"]), int(p["n_aux"]),
                      get("eps"), get("B"), get("gamma1"), get("gamma2"), get("gamma3"),
-                     float(p["s"]))
+                     float(p["s"]), get("f_offdiag"), float(p.get("e0", 0.0)))
         return st, fl
     ptrs = {}
-    for k in ("eps", "B", "gamma1", "gamma2", "gamma3"):
-        arr, ptr = _host(getattr(p, k))
+    for k in _ARRAYS:
+        arr, ptr = _host(getattr(p, k, None))
         keep.append(arr)
         ptrs[k] = ptr
     st = Problem(p.n_core, p.n_active, p.n_virtual, p.n_aux, ptrs["eps"], ptrs["B"],
-                 ptrs["gamma1"], ptrs["gamma2"], ptrs["gamma3"], float(p.s))
+                 ptrs["gamma1"], ptrs["gamma2"], ptrs["gamma3"], float(p.s), ptrs["f_offdiag"],
+                 float(getattr(p, "e0", 0.0)))
     return st, 0
 
 
-def _options(flags, stream=None, workspace_cap=0, precision=DSRG_PRECISION_FP64):
-    return Options(flags, int(precision), int(workspace_cap), stream)
+def _options(flags, stream=None, workspace_cap=0, precision=DSRG_PRECISION_FP64, virt_batch=0):
+    return Options(flags, int(precision), int(workspace_cap), stream, int(virt_batch))
 
 
 def to_device(p, device="cuda:0"):
     """Copy a synth.Problem's arrays into torch device tensors (marshalling helper)."""
     import torch
-    d = dict(n_core=p.n_core, n_active=p.n_active, n_virtual=p.n_virtual, n_aux=p.n_aux, s=p.s)
-    for k in ("eps", "B", "gamma1", "gamma2", "gamma3"):
-        a = getattr(p, k)
+    d = dict(n_core=p.n_core, n_active=p.n_active, n_virtual=p.n_virtual, n_aux=p.n_aux, s=p.s,
+             e0=float(getattr(p, "e0", 0.0)))
+    for k in _ARRAYS:
+        a = getattr(p, k, None)
         d[k] = None if a is None else torch.from_numpy(np.ascontiguousarray(a)).to(device)
     return d
 
@@ -165,7 +176,9 @@ def _result_dict(r: Result):
                 ladder_seconds=r.ladder_seconds, ladder_batch=r.ladder_batch,
                 n_launch=r.n_launch, role_seconds=list(r.role_seconds),
                 role_flops=list(r.role_flops), role_launches=list(r.role_launches), plan=r.plan,
-                grouped_uses=r.grouped_uses, role_bytes=list(r.role_bytes))
+                grouped_uses=r.grouped_uses, role_bytes=list(r.role_bytes), e_total=r.e_total,
+                alg_flops=r.alg_flops, precision_used=r.precision_used,
+                virt_batch_used=r.virt_batch_used)
 
 
 def _stream_of(p, stream):
@@ -194,24 +207,25 @@ def release_cache():
     _check(load().dsrg_release_cache())
 
 
-def dsrg_pt2_energy(p, stream=None, workspace_cap=0, grouping=True, cache=True, precision=0):
+def dsrg_pt2_energy(p, stream=None, workspace_cap=0, grouping=True, cache=True, precision=0,
+                    virt_batch=0):
     keep = []
     st, fl = _problem_struct(p, keep)
     fl = _flags(fl, grouping=grouping, cache=cache)
     r = Result()
     _check(load().dsrg_pt2_energy(ctypes.byref(st), ctypes.byref(
-        _options(fl, _stream_of(p, stream), workspace_cap, precision)), ctypes.byref(r)))
+        _options(fl, _stream_of(p, stream), workspace_cap, precision, virt_batch)), ctypes.byref(r)))
     return _result_dict(r)
 
 
 def dsrg_pt3_energy(p, stream=None, workspace_cap=0, profile=False, grouping=True, cache=True,
-                    precision=0, unique_ladder=True):
+                    precision=0, unique_ladder=True, virt_batch=0):
     keep = []
     st, fl = _problem_struct(p, keep)
     fl = _flags(fl, profile, grouping, cache, unique_ladder)
     r = Result()
     _check(load().dsrg_pt3_energy(ctypes.byref(st), ctypes.byref(
-        _options(fl, _stream_of(p, stream), workspace_cap, precision)), ctypes.byref(r)))
+        _options(fl, _stream_of(p, stream), workspace_cap, precision, virt_batch)), ctypes.byref(r)))
     return _result_dict(r)
 
 
@@ -264,7 +278,7 @@ INTERMEDIATES = ("t1", "t2", "w1", "w2", "z1", "z2", "u1", "u2")
 
 
 def dsrg_pt3_energy_ex(p, stream=None, workspace_cap=0, grouping=True, precision=0,
-                       keys=INTERMEDIATES, unique_ladder=True):
+                       keys=INTERMEDIATES, unique_ladder=True, virt_batch=0):
     """E(2), E(3) and the requested intermediates as numpy arrays (spin blocks, excitation
     order)."""
     keep = []
@@ -278,7 +292,7 @@ def dsrg_pt3_energy_ex(p, stream=None, workspace_cap=0, grouping=True, precision
     inter = Intermediates(**{k: v.ctypes.data for k, v in bufs.items()})
     r = Result()
     _check(load().dsrg_pt3_energy_ex(ctypes.byref(st), ctypes.byref(
-        _options(fl, _stream_of(p, stream), workspace_cap, precision)), ctypes.byref(r),
+        _options(fl, _stream_of(p, stream), workspace_cap, precision, virt_batch)), ctypes.byref(r),
         ctypes.byref(inter)))
     out = _result_dict(r)
     out.update(bufs)

@@ -183,7 +183,7 @@ static const Use& pair_use() {
 }
 
 static const char* storage_axes(const std::string& t) {
-  if (t == "T1" || t == "E1" || t == "Y1" || t == "O1") return "PH";
+  if (t == "T1" || t == "E1" || t == "Y1" || t == "O1" || t == "F1") return "PH";
   if (t == "T2" || t == "E2" || t == "Y2" || t == "O2") return "PPHH";
   if (t == "L2") return "AAAA";
   if (t == "L3") return "AAAAAA";
@@ -297,6 +297,7 @@ struct Exec {
   std::map<std::string, double*> jblocks;     // "HPHP" -> [X1][X2][X3][X4]
   double* partial = nullptr;
   long long ws_cap;
+  int virt_batch = 0;   // requested (PP|PP) batch size (0: the largest that fits ws_cap)
   double gett_flops = 0, ladder_flops = 0, ladder_ms = 0;
   int ladder_batch = 0, n_launch = 0;
 
@@ -2030,7 +2031,14 @@ struct Exec {
       // doubles per value of the batch letter: integral rows plus packed rows
       const long long per = (long long)nP * nP * nP;
       const long long per_all = per + (pairs ? (long long)nP * (kp + (sym ? kp1 : 0)) : 0);
-      long long nb = std::max(1LL, std::min<long long>(lbl, ws_cap / (8 * per_all)));
+      const long long fit = ws_cap / (8 * per_all);
+      if (fit < 1)
+        throw Error(DSRG_E_OOM, "workspace_cap of " + std::to_string(ws_cap) + " bytes is below one (PP|PP) batch row of " +
+                                    std::to_string(8 * per_all) + " bytes");
+      long long nb = std::min<long long>(lbl, virt_batch > 0 ? (long long)virt_batch : fit);
+      if (nb > fit)
+        throw Error(DSRG_E_OOM, "virt_batch " + std::to_string(virt_batch) + " needs " + std::to_string(8 * per_all * nb) +
+                                    " bytes, above workspace_cap");
       ladder_batch = (int)nb;
       // pair tables: strict pairs (m = own index) and pairs a <= b (m = strict index or -1),
       // p-major row lists with the first row of each p
@@ -2247,6 +2255,12 @@ struct Exec {
 // ---------------------------------------------------------------------------
 // Pipeline
 // ---------------------------------------------------------------------------
+// Errors from the device-side input counters: non-finite values first, then densities.
+static void check_bad(const int* bad) {
+  if (bad[0]) throw Error(DSRG_E_NONFINITE, "non-finite value in eps, B, f_offdiag or the densities");
+  if (bad[1]) throw Error(DSRG_E_RDM, "gamma1 not symmetric or gamma2 not Hermitian/antisymmetric");
+}
+
 static bool finite_host(const double* p, size_t n) {
   for (size_t i = 0; i < n; ++i)
     if (!std::isfinite(p[i])) return false;
@@ -2261,6 +2275,38 @@ struct CopyList {
   long long end[6];   // prefix sums of the array lengths
   int n;
 };
+
+// Reference densities as the ABI requires them (Sec. II.A: real densities of one state):
+// gamma1 symmetric, gamma2 Hermitian (uv <-> xy) and, in its same-spin blocks,
+// antisymmetric in u <-> v and in x <-> y; violations beyond kRdmTol are counted.
+constexpr double kRdmTol = 1e-10;
+__host__ __device__ inline int rdm_violations(int nA, const double* g1, const double* g2, long long e) {
+  const long long n2 = (long long)nA * nA, n4 = n2 * n2;
+  if (e < 2 * n2) {
+    const long long s = e / n2, r = e - s * n2, u = r / nA, v = r - u * nA;
+    return fabs(g1[s * n2 + u * nA + v] - g1[s * n2 + v * nA + u]) > kRdmTol;
+  }
+  e -= 2 * n2;
+  if (e >= 3 * n4) return 0;
+  const long long b = e / n4, r = e - b * n4;
+  const long long u = r / (n2 * nA), v = (r / n2) % nA, x = (r / nA) % nA, y = r % nA;
+  const double* g = g2 + b * n4;
+  const double val = g[r];
+  int bad = fabs(val - g[x * n2 * nA + y * n2 + u * nA + v]) > kRdmTol;
+  if (b != 1) {
+    bad += fabs(val + g[v * n2 * nA + u * n2 + x * nA + y]) > kRdmTol;
+    bad += fabs(val + g[u * n2 * nA + v * n2 + y * nA + x]) > kRdmTol;
+  }
+  return bad;
+}
+__global__ __launch_bounds__(256) void rdm_check_kernel(int nA, const double* __restrict__ g1,
+                                                        const double* __restrict__ g2, int* __restrict__ bad) {
+  const long long n2 = (long long)nA * nA, total = 2 * n2 + 3 * n2 * n2;
+  int nbad = 0;
+  for (long long e = blockIdx.x * 256LL + threadIdx.x; e < total; e += 256LL * gridDim.x)
+    nbad += rdm_violations(nA, g1, g2, e);
+  if (nbad) atomicAdd(bad + 1, nbad);
+}
 __global__ __launch_bounds__(256) void copy_check_kernel(CopyList L, int* __restrict__ bad) {
   const long long total = L.end[L.n - 1];
   int nbad = 0;
@@ -2280,15 +2326,16 @@ __global__ __launch_bounds__(256) void copy_check_kernel(CopyList L, int* __rest
 // the same shape, whatever the input values, s and input pointers.
 struct Shape {
   int nC, nA, nV, M;
-  bool has_g3, pt3;
+  bool has_g3, pt3, has_f = false;
   long long N, nB, g1n, g2n, g3n;
 };
 
 struct Inputs {
   double *eps = nullptr, *B = nullptr, *g1 = nullptr, *g2 = nullptr, *g3 = nullptr;
+  double* f = nullptr;         // [N][N] inter-block Fock elements (with f_offdiag)
   double* s = nullptr;         // [1]
   double* energies = nullptr;  // [4]: E(2), E(3)_a, E(3)_b, unused
-  int* bad = nullptr;          // non-finite counter for device inputs
+  int* bad = nullptr;          // [2]: non-finite values, density violations (device inputs)
 };
 
 static Inputs alloc_inputs(Pool& pool, const Shape& sh) {
@@ -2300,6 +2347,7 @@ static Inputs alloc_inputs(Pool& pool, const Shape& sh) {
     in.g2 = pool.alloc((size_t)sh.g2n);
   }
   if (sh.has_g3) in.g3 = pool.alloc((size_t)sh.g3n);
+  if (sh.has_f) in.f = pool.alloc((size_t)(sh.N * sh.N));
   in.s = pool.alloc(1);
   in.energies = pool.alloc(4);
   in.bad = (int*)pool.alloc(1);
@@ -2325,9 +2373,11 @@ static void load_inputs(const dsrg_problem* P, bool devptr, const Shape& sh, con
       cp(in.g2, P->gamma2, sh.g2n);
     }
     if (sh.has_g3) cp(in.g3, P->gamma3, sh.g3n);
+    if (sh.has_f) cp(in.f, P->f_offdiag, sh.N * sh.N);
     return;
   }
-  HIPCHECK(hipMemsetAsync(in.bad, 0, sizeof(int), st));
+  // both counters in one double (a fill kernel rather than a memset node)
+  launch_fill(reinterpret_cast<double*>(in.bad), 1, 0.0, st);
   CopyList L{};
   long long total = 0;
   auto add = [&](double* dst, const double* src, long long n) {
@@ -2345,19 +2395,26 @@ static void load_inputs(const dsrg_problem* P, bool devptr, const Shape& sh, con
     add(in.g2, P->gamma2, sh.g2n);
   }
   if (sh.has_g3) add(in.g3, P->gamma3, sh.g3n);
+  if (sh.has_f) add(in.f, P->f_offdiag, sh.N * sh.N);
   if (L.n > 0) {
     const long long blocks = std::min<long long>((total + 255) / 256, 8192);
     hipLaunchKernelGGL(copy_check_kernel, dim3((unsigned)blocks), dim3(256), 0, st, L, in.bad);
     HIPCHECK(hipGetLastError());
   }
+  if (sh.nA > 0) {
+    const long long n2 = (long long)sh.nA * sh.nA, total_r = 2 * n2 + 3 * n2 * n2;
+    const long long blocks = std::min<long long>((total_r + 255) / 256, 1024);
+    hipLaunchKernelGGL(rdm_check_kernel, dim3((unsigned)blocks), dim3(256), 0, st, sh.nA, in.g1, in.g2, in.bad);
+    HIPCHECK(hipGetLastError());
+  }
   if (defer_bad) {
-    HIPCHECK(hipMemcpyAsync(defer_bad, in.bad, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHECK(hipMemcpyAsync(defer_bad, in.bad, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
     return;
   }
-  int hbad = 0;
-  HIPCHECK(hipMemcpyAsync(&hbad, in.bad, sizeof(int), hipMemcpyDeviceToHost, st));
+  int hbad[2] = {0, 0};
+  HIPCHECK(hipMemcpyAsync(hbad, in.bad, 2 * sizeof(int), hipMemcpyDeviceToHost, st));
   HIPCHECK(hipStreamSynchronize(st));
-  if (hbad) throw Error(DSRG_E_NONFINITE, "non-finite value in eps, B or the densities");
+  check_bad(hbad);
 }
 
 // Device buffers of the intermediates a caller may ask for.
@@ -2445,9 +2502,28 @@ static BodyOut body(Exec& X, OpLog& op, Pool& pool, const Shape& sh, const Input
   // gamma1 input blocks [2][nA][nA] are read directly by the singles kernel
   const double* g1a = nA > 0 ? g1 : nullptr;
   const double* g1b = nA > 0 ? g1 + nA * nA : nullptr;
+  // inter-block Fock elements f(1) (H(1) = f(1) + V): they drive the singles (Eq. T1_1st),
+  // H~(1) = 2 H(1) + Y gains 2 f(1) in its one-body part, and O1 gains 2 [f(1), A(1)]
+  double* F1 = nullptr;
+  if (sh.has_f) {
+    F1 = pool.alloc(n1);
+    const double* fin = in.f;
+    op([=](hipStream_t s) { launch_fock_exc(ad, fin, F1, s); });
+  }
+  // the singles launch writes the source (f + coup) exp(-s D^2), which is Y1 + f(1)
   op([=](hipStream_t s) {
-    launch_singles(ad, T2aa, T2ab, T2aa, g1a, g1b, eps, sdev, nullptr, nullptr, T1a, T1b, Y1a, Y1b, s);
+    launch_singles(ad, T2aa, T2ab, T2aa, g1a, g1b, eps, sdev, F1, F1, T1a, T1b, Y1a, Y1b, s);
   });
+  double *E1a = Y1a, *E1b = Y1b;
+  if (F1) {
+    // Y1 = source - f(1), H~(1) one-body = source + f(1)
+    E1a = pool.alloc(n1);
+    E1b = pool.alloc(n1);
+    op([=](hipStream_t s) {
+      launch_split_source((long long)n1, 1, Y1a, E1a, F1, s);
+      launch_split_source((long long)n1, 1, Y1b, E1b, F1, s);
+    });
+  }
   auto bind_first = [&]() {
     X.set("T1.a", T1a, "PH"); X.set("T1.b", T1b, "PH");
     // first-order doubles: regularised integrals, so the same-spin blocks are antisymmetric
@@ -2455,7 +2531,7 @@ static BodyOut body(Exec& X, OpLog& op, Pool& pool, const Shape& sh, const Input
     X.set("T2.aa", T2aa, "PPHH", 1); X.set("T2.ab", T2ab, "PPHH", 2); X.set("T2.bb", T2aa, "PPHH", 1);
   };
   bind_first();
-  X.set("E1.a", Y1a, "PH"); X.set("E1.b", Y1b, "PH");
+  X.set("E1.a", E1a, "PH"); X.set("E1.b", E1b, "PH");
   X.set("E2.aa", E2aa, "PPHH"); X.set("E2.ab", E2ab, "PPHH"); X.set("E2.bb", E2aa, "PPHH");
   X.set("Y1.a", Y1a, "PH"); X.set("Y1.b", Y1b, "PH");
   X.set("Y2.aa", Y2aa, "PPHH"); X.set("Y2.ab", Y2ab, "PPHH"); X.set("Y2.bb", Y2aa, "PPHH");
@@ -2517,6 +2593,30 @@ static BodyOut body(Exec& X, OpLog& op, Pool& pool, const Shape& sh, const Input
     X.use_id = 2;
     X.run_use(T.at("Z"), zout, nullptr);
     HIPCHECK(hipEventRecord(ev[5], st));
+  }
+  if (F1) {
+    // [f(1), A(1)]_{1,2}: the products of [Y, A(1)] with a one-body Y factor, with f(1) in its
+    // place (both are Hermitian one-body operators with only excitation elements and their
+    // adjoints), added into W, so that O1 = 2 (W + [f(1), A(1)]) + Z downstream
+    Use fu;
+    for (const TProduct& P : T.at("Z")) {
+      bool one_body = false;
+      for (auto& f : P.f) one_body = one_body || f.tensor == "Y1";
+      if (!one_body) continue;
+      TProduct Q = P;
+      for (auto& f : Q.f)
+        if (f.tensor == "Y1") f.tensor = "F1";
+      fu.push_back(Q);
+    }
+    X.set("F1.a", F1, "PH"); X.set("F1.b", F1, "PH");
+    const long long fwn = 2 * (long long)n1 + 3 * (long long)n4;
+    double* FW = pool.alloc((size_t)fwn);
+    op([FW, fwn](hipStream_t s) { launch_fill(FW, fwn, 0.0, s); });
+    std::map<std::string, TensorRef> fout;
+    bind_out(fout, FW, FW + 2 * n1);
+    X.use_id = 5;
+    X.run_use(fu, fout, nullptr);
+    op([W1, FW, fwn](hipStream_t s) { launch_add(W1, FW, fwn, s); });   // W1, W2 are contiguous
   }
   // second-order amplitudes and H~(2)_{1,2}
   double* U2 = pool.alloc(3 * n4);
@@ -2617,7 +2717,7 @@ struct Plan {
   bool busy = false;
   unsigned long long stamp = 0;
   double gett_flops = 0, ladder_flops = 0;
-  int ladder_batch = 0, n_launch = 0, grouped_uses = 0;
+  int ladder_batch = 0, n_launch = 0, grouped_uses = 0, precision = 0;
   ~Plan() {
     int cur = 0;
     (void)hipGetDevice(&cur);
@@ -2681,11 +2781,53 @@ static bool keep_plan(std::unique_ptr<Plan> fresh) {
   return true;
 }
 
-static void fill_result(dsrg_result* R, const double* e, bool pt3) {
+static void fill_result(dsrg_result* R, const double* e, bool pt3, double e0) {
   R->e2 = e[0];
   R->e3_a = pt3 ? e[1] : 0.0;
   R->e3_b = pt3 ? e[2] : 0.0;
   R->e3 = R->e3_a + R->e3_b;
+  R->e_total = e0 + R->e2 + R->e3;   // Eq. E_unrelaxed
+}
+
+// Host-side checks of the densities (device inputs are checked on their device copies).
+static void check_rdm_host(int nA, const double* g1, const double* g2) {
+  const long long n2 = (long long)nA * nA, total = 2 * n2 + 3 * n2 * n2;
+  for (long long e = 0; e < total; ++e)
+    if (rdm_violations(nA, g1, g2, e))
+      throw Error(DSRG_E_RDM, "gamma1 not symmetric or gamma2 not Hermitian/antisymmetric");
+}
+
+// s = +INFINITY (R_s = 1/D): every non-internal singles and doubles denominator must be
+// away from zero.  Doubles: the pair sums e_i + e_j over holes and e_a + e_b over particles
+// are sorted and the closest pair found by a merge (internal quadruples, all four active,
+// carry no amplitude and are skipped by an exact scan of the active sums).
+static void check_intruder(int nC, int nA, int nV, const double* eps) {
+  const int nH = nC + nA, nP = nA + nV;
+  const double tol = 1e-12;
+  for (int i = 0; i < nH; ++i)
+    for (int a = 0; a < nP; ++a) {
+      if (i >= nC && a < nA) continue;   // internal
+      if (std::fabs(eps[i] - eps[nC + a]) < tol)
+        throw Error(DSRG_E_INTRUDER, "s = inf with a vanishing singles denominator");
+    }
+  // pairs touching at least one non-active index on either side
+  struct PS { double v; bool all_active; };
+  std::vector<PS> h, p;
+  for (int i = 0; i < nH; ++i)
+    for (int j = 0; j < nH; ++j) h.push_back({eps[i] + eps[j], i >= nC && j >= nC});
+  for (int a = 0; a < nP; ++a)
+    for (int b = 0; b < nP; ++b) p.push_back({eps[nC + a] + eps[nC + b], a < nA && b < nA});
+  auto by = [](const PS& x, const PS& y) { return x.v < y.v; };
+  std::sort(h.begin(), h.end(), by);
+  std::sort(p.begin(), p.end(), by);
+  // for every hole pair, the particle pairs within tol of it (two pointers)
+  size_t lo = 0;
+  for (const PS& x : h) {
+    while (lo < p.size() && p[lo].v < x.v - tol) ++lo;
+    for (size_t k = lo; k < p.size() && p[k].v <= x.v + tol; ++k)
+      if (!(x.all_active && p[k].all_active) && std::fabs(x.v - p[k].v) < tol)
+        throw Error(DSRG_E_INTRUDER, "s = inf with a vanishing doubles denominator");
+  }
 }
 
 // Checked arguments of a call and the key of its plan.  slot > 0 keys a separate plan of
@@ -2695,6 +2837,7 @@ struct Setup {
   bool f32 = false, devptr = false, profile = false, grouped = true, unique_ladder = true;
   bool want_pairs = false, cacheable = false;
   long long cap = 0;
+  int vb = 0;   // requested (PP|PP) batch (0: largest that fits)
   hipStream_t st = nullptr;
   int dev = 0;
   std::string key;
@@ -2713,7 +2856,9 @@ static Setup setup(const dsrg_problem* P, const dsrg_options* O, const dsrg_inte
   if (nA > 8) throw Error(DSRG_E_UNSUPPORTED, "active spaces above 8 orbitals are not built");
   if (O && O->precision != DSRG_PRECISION_FP64 && O->precision != DSRG_PRECISION_FP32)
     throw Error(DSRG_E_UNSUPPORTED, "unknown precision");
+  if (O && O->virt_batch < 0) throw Error(DSRG_E_ARG, "virt_batch must be >= 0");
   Setup S;
+  S.vb = O ? O->virt_batch : 0;
   S.f32 = O && O->precision == DSRG_PRECISION_FP32;
   const int flags = O ? O->flags : 0;
   S.devptr = flags & DSRG_F_DEVICE_PTRS;
@@ -2726,24 +2871,47 @@ static Setup setup(const dsrg_problem* P, const dsrg_options* O, const dsrg_inte
   sh.g2n = 3LL * nA * nA * nA * nA;
   sh.g3n = 4LL * nA * nA * nA * nA * nA * nA;
   sh.has_g3 = nA > 0 && P->gamma3;
+  sh.has_f = P->f_offdiag != nullptr;
   sh.pt3 = pt3;
   if (!S.devptr) {
     if (!finite_host(P->eps, sh.N) || !finite_host(P->B, sh.nB) ||
         (nA > 0 && (!finite_host(P->gamma1, sh.g1n) || !finite_host(P->gamma2, sh.g2n))) ||
-        (sh.has_g3 && !finite_host(P->gamma3, sh.g3n)))
-      throw Error(DSRG_E_NONFINITE, "non-finite value in eps, B or the densities");
+        (sh.has_g3 && !finite_host(P->gamma3, sh.g3n)) ||
+        (sh.has_f && !finite_host(P->f_offdiag, (size_t)(sh.N * sh.N))))
+      throw Error(DSRG_E_NONFINITE, "non-finite value in eps, B, f_offdiag or the densities");
+    if (nA > 0) check_rdm_host(nA, P->gamma1, P->gamma2);
+  }
+  if (std::isinf(P->s)) {
+    // the unregularised limit: denominators checked on the host (eps copied if on the device)
+    std::vector<double> e(sh.N);
+    if (S.devptr) HIPCHECK(hipMemcpy(e.data(), P->eps, sh.N * sizeof(double), hipMemcpyDeviceToHost));
+    else std::copy(P->eps, P->eps + sh.N, e.begin());
+    for (double x : e)
+      if (!std::isfinite(x)) throw Error(DSRG_E_NONFINITE, "non-finite value in eps");
+    check_intruder(nC, nA, nV, e.data());
   }
   S.st = (O && O->stream) ? (hipStream_t)O->stream : (hipStream_t)0;
   S.cap = (O && O->workspace_cap > 0) ? O->workspace_cap : (8LL << 30);
   S.grouped = !(flags & DSRG_F_NO_GROUPING);
   S.unique_ladder = !(flags & DSRG_F_FULL_LADDER);
+  if (pt3 && nC + nA > 0 && nA + nV > 0) {
+    // one value of the batch letter of the (PP|PP) ladder: nP^3 integrals plus, on unique
+    // pairs, its antisymmetrised and symmetrised pair rows (the executor checks the same)
+    const long long nP = nA + nV, kp = nP * (nP - 1) / 2;
+    const long long row = 8 * (nP * nP * nP + (S.unique_ladder ? nP * (2 * kp + nP) : 0));
+    if (S.cap < row)
+      throw Error(DSRG_E_OOM, "workspace_cap of " + std::to_string(S.cap) + " bytes is below one (PP|PP) batch row of " +
+                                  std::to_string(row) + " bytes");
+    if (S.vb > 0 && (long long)std::min<long long>(S.vb, nP) * row > S.cap)
+      throw Error(DSRG_E_OOM, "virt_batch " + std::to_string(S.vb) + " does not fit workspace_cap");
+  }
   S.want_pairs = e3_rest != nullptr;
   if (S.want_pairs && nC > 0 && !e3_pairs) throw Error(DSRG_E_ARG, "null e3_pairs with n_core > 0");
   S.cacheable = !S.profile && !I && !S.want_pairs && !(flags & DSRG_F_NO_PLAN_CACHE);
   HIPCHECK(hipGetDevice(&S.dev));
   char kbuf[192];
-  snprintf(kbuf, sizeof(kbuf), "%d:%d:%d:%d:%d:%d:%d:%d:%d:%d:%lld:%d", S.dev, nC, nA, nV, M, (int)sh.has_g3,
-           (int)pt3, (int)S.grouped, (int)S.unique_ladder, (int)S.f32, S.cap, slot);
+  snprintf(kbuf, sizeof(kbuf), "%d:%d:%d:%d:%d:%d:%d:%d:%d:%d:%d:%lld:%d:%d", S.dev, nC, nA, nV, M, (int)sh.has_g3,
+           (int)sh.has_f, (int)pt3, (int)S.grouped, (int)S.unique_ladder, (int)S.f32, S.cap, S.vb, slot);
   S.key = kbuf;
   return S;
 }
@@ -2805,22 +2973,25 @@ static hipStream_t* batch_streams(int dev) {
 // pinned).  The host buffers must stay untouched until the stream has passed the launch.
 static void replay_launch(Plan* plan, const dsrg_problem* P, const Setup& S, const double* s_src,
                           double* e_dst, int* bad) {
-  *bad = 0;
+  bad[0] = bad[1] = 0;
   load_inputs(P, S.devptr, S.sh, plan->in, s_src, S.st, S.devptr ? bad : nullptr);
   HIPCHECK(hipGraphLaunch(plan->exec, S.st));
   HIPCHECK(hipMemcpyAsync(e_dst, plan->in.energies, 4 * sizeof(double), hipMemcpyDeviceToHost, S.st));
 }
 
-static void replay_result(const Plan* plan, const double* e, bool pt3, dsrg_result* R) {
+static void replay_result(const Plan* plan, const double* e, bool pt3, double e0, dsrg_result* R) {
   dsrg_result r;
   memset(&r, 0, sizeof(r));
-  fill_result(&r, e, pt3);
+  fill_result(&r, e, pt3, e0);
   r.gett_flops = plan->gett_flops;
   r.ladder_flops = plan->ladder_flops;
   r.ladder_batch = plan->ladder_batch;
   r.n_launch = plan->n_launch;
   r.grouped_uses = plan->grouped_uses;
   r.plan = 2;
+  r.alg_flops = plan->gett_flops;
+  r.precision_used = plan->precision;
+  r.virt_batch_used = plan->ladder_batch;
   *R = r;
 }
 
@@ -2869,7 +3040,7 @@ static int run(const dsrg_problem* P, const dsrg_options* O, dsrg_result* R,
     plan->pinned[0] = P->s;
     // device inputs: the non-finite check runs ahead of the graph and is read after it
     int* bad = reinterpret_cast<int*>(plan->pinned + 8);
-    *bad = 0;
+    bad[0] = bad[1] = 0;
     load_inputs(P, devptr, sh, plan->in, plan->pinned, st, devptr ? bad : nullptr);
     HIPCHECK(hipEventRecord(ev[0], st));
     HIPCHECK(hipGraphLaunch(plan->exec, st));
@@ -2877,8 +3048,8 @@ static int run(const dsrg_problem* P, const dsrg_options* O, dsrg_result* R,
     HIPCHECK(hipMemcpyAsync(plan->pinned + 4, plan->in.energies, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHECK(hipStreamSynchronize(st));
     HIPCHECK(hipGetLastError());
-    if (*bad) throw Error(DSRG_E_NONFINITE, "non-finite value in eps, B or the densities");
-    fill_result(&r, plan->pinned + 4, pt3);
+    check_bad(bad);
+    fill_result(&r, plan->pinned + 4, pt3, P->e0);
     float ms = 0;
     HIPCHECK(hipEventElapsedTime(&ms, ev[0], ev[7]));
     r.t_seconds[7] = ms * 1e-3;
@@ -2888,6 +3059,9 @@ static int run(const dsrg_problem* P, const dsrg_options* O, dsrg_result* R,
     r.n_launch = plan->n_launch;
     r.grouped_uses = plan->grouped_uses;
     r.plan = 2;
+    r.alg_flops = plan->gett_flops;
+    r.precision_used = plan->precision;
+    r.virt_batch_used = plan->ladder_batch;
     *R = r;
     return DSRG_OK;
   }
@@ -2914,6 +3088,7 @@ static int run(const dsrg_problem* P, const dsrg_options* O, dsrg_result* R,
   X.unique_ladder = unique_ladder;
   X.group_cap = cap / 2;
   X.f32 = f32;
+  X.virt_batch = S.vb;
   HIPCHECK(hipEventRecord(ev[0], st));
   BodyOut bo = body(X, op, *pool, sh, in, ev, st, want_pairs);
   std::vector<double> pair_host;
@@ -2941,7 +3116,7 @@ static int run(const dsrg_problem* P, const dsrg_options* O, dsrg_result* R,
   HIPCHECK(hipMemcpyAsync(e, in.energies, 4 * 8, hipMemcpyDeviceToHost, st));
   HIPCHECK(hipStreamSynchronize(st));
   HIPCHECK(hipGetLastError());
-  fill_result(&r, e, pt3);
+  fill_result(&r, e, pt3, P->e0);
   float ms;
   for (int k = 0; k < 6; ++k) {
     HIPCHECK(hipEventElapsedTime(&ms, ev[k], ev[k + 1]));
@@ -2962,6 +3137,9 @@ static int run(const dsrg_problem* P, const dsrg_options* O, dsrg_result* R,
   r.ladder_batch = X.ladder_batch;
   r.n_launch = X.n_launch;
   r.grouped_uses = X.grouped_uses;
+  r.alg_flops = X.gett_flops;
+  r.precision_used = f32 ? DSRG_PRECISION_FP32 : DSRG_PRECISION_FP64;
+  r.virt_batch_used = X.ladder_batch;
   *R = r;
   if (want_pairs) {
     const size_t np = (size_t)nC * (nC + 1) / 2;
@@ -2977,6 +3155,7 @@ static int run(const dsrg_problem* P, const dsrg_options* O, dsrg_result* R,
     fresh->ladder_batch = X.ladder_batch;
     fresh->n_launch = X.n_launch;
     fresh->grouped_uses = X.grouped_uses;
+    fresh->precision = r.precision_used;
     try {
       capture(*fresh, ops);
       // from here on every use of the plan ends with a synchronisation of its caller's stream
@@ -3096,8 +3275,9 @@ int dsrg_pt3_energy_batch(const dsrg_problem* probs, int32_t n, const dsrg_optio
     if (status[k] == DSRG_OK && used[k]) {
       const double* st_k = stage + (size_t)k * kStage;
       if (sync_rc != DSRG_OK) status[k] = sync_rc;
-      else if (*reinterpret_cast<const int*>(st_k + 5)) status[k] = DSRG_E_NONFINITE;
-      else dsrg::replay_result(used[k], st_k + 1, pt3v[k], outs + k);
+      else if (reinterpret_cast<const int*>(st_k + 5)[0]) status[k] = DSRG_E_NONFINITE;
+      else if (reinterpret_cast<const int*>(st_k + 5)[1]) status[k] = DSRG_E_RDM;
+      else dsrg::replay_result(used[k], st_k + 1, pt3v[k], probs[k].e0, outs + k);
     }
     if (status[k] == DSRG_OK) any_ok = true;
     else if (first_error == DSRG_OK) first_error = status[k];

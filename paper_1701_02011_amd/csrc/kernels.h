@@ -274,6 +274,13 @@ struct SumOuts {
 };
 void launch_weighted_sums(int n, const double* vals, const double* coef, const SumOuts& out, hipStream_t st);
 void launch_fill(double* p, long long n, double v, hipStream_t st);
+// F1[a][i] = f[nC + a][i] over a in P, i in H (f is [N][N]); 0 on active-active elements
+void launch_fock_exc(AmpDims d, const double* f, double* F1, hipStream_t st);
+// Y = src - F, E = src + F over nspins blocks of n elements (Y holds src on entry; F is one
+// block shared by the spins)
+void launch_split_source(long long n, int nspins, double* Y, double* E, const double* F, hipStream_t st);
+// dst[i] += src[i]
+void launch_add(double* dst, const double* src, long long n, hipStream_t st);
 // O[p][q][i][j] += X[p][q][i][j] - X[q][p][i][j] - X[p][q][j][i] + X[q][p][j][i]
 // (both [P][P][H][H], dense, distinct arrays)
 void launch_antisym_add(const double* X, double* O, int nP, int nH, hipStream_t st);

@@ -1890,4 +1890,51 @@ void launch_fill(double* p, long long n, double v, hipStream_t st) {
   hipLaunchKernelGGL(fill_kernel, dim3((unsigned)blocks), dim3(256), 0, st, p, n, v);
 }
 
+// Excitation block of the inter-block Fock matrix: F1[a][i] = f[nC + a][i] for a in P,
+// i in H, zero on internal (active-active) elements, which f(1) does not have.
+__global__ __launch_bounds__(256) void fock_exc_kernel(AmpDims d, const double* __restrict__ f,
+                                                       double* __restrict__ F1) {
+  const int nH = d.nC + d.nA, nP = d.nA + d.nV, N = d.nC + d.nA + d.nV;
+  const int e = blockIdx.x * 256 + threadIdx.x;
+  if (e >= nP * nH) return;
+  const int a = e / nH, i = e - a * nH;
+  const bool internal = a < d.nA && i >= d.nC;
+  F1[e] = internal ? 0.0 : f[(long long)(d.nC + a) * N + i];
+}
+
+void launch_fock_exc(AmpDims d, const double* f, double* F1, hipStream_t st) {
+  const int n = (d.nA + d.nV) * (d.nC + d.nA);
+  if (n <= 0) return;
+  hipLaunchKernelGGL(fock_exc_kernel, dim3((n + 255) / 256), dim3(256), 0, st, d, f, F1);
+}
+
+// Y = src - F and E = src + F for nspins one-body blocks of n elements (F shared by the
+// spins); Y overwrites src.
+__global__ __launch_bounds__(256) void split_source_kernel(long long n, int nspins, double* __restrict__ Y,
+                                                           double* __restrict__ E, const double* __restrict__ F) {
+  for (long long e = blockIdx.x * 256LL + threadIdx.x; e < n * nspins; e += 256LL * gridDim.x) {
+    const double src = Y[e], f = F[e % n];
+    Y[e] = src - f;
+    E[e] = src + f;
+  }
+}
+
+void launch_split_source(long long n, int nspins, double* Y, double* E, const double* F, hipStream_t st) {
+  const long long tot = n * nspins;
+  if (tot <= 0) return;
+  const long long blocks = std::min<long long>((tot + 255) / 256, 16384);
+  hipLaunchKernelGGL(split_source_kernel, dim3((unsigned)blocks), dim3(256), 0, st, n, nspins, Y, E, F);
+}
+
+__global__ __launch_bounds__(256) void add_kernel(double* __restrict__ dst, const double* __restrict__ src,
+                                                  long long n) {
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += 256LL * gridDim.x) dst[i] += src[i];
+}
+
+void launch_add(double* dst, const double* src, long long n, hipStream_t st) {
+  if (n <= 0) return;
+  const long long blocks = std::min<long long>((n + 255) / 256, 16384);
+  hipLaunchKernelGGL(add_kernel, dim3((unsigned)blocks), dim3(256), 0, st, dst, src, n);
+}
+
 }  // namespace dsrg

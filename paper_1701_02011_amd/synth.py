@@ -75,6 +75,8 @@ class Problem:
     n_alpha: int = 0                  # active alpha electrons
     n_beta: int = 0                   # active beta electrons
     name: str = ""
+    f_offdiag: Optional[np.ndarray] = None   # [N][N] inter-block Fock elements, or None (zero)
+    e0: float = 0.0                          # reference energy, only added to the total
 
     @property
     def N(self) -> int:
@@ -235,13 +237,17 @@ def _draw_B(rng: np.random.Generator, M: int, N: int, sigma: float = 0.1) -> np.
 
 def make_problem(n_core: int, n_active: int, n_virtual: int, n_aux: int, seed: int,
                  s: float = 0.5, gap: float = 1.0, name: str = "",
-                 with_gamma3: bool = True) -> Problem:
+                 with_gamma3: bool = True, f_sigma: float = 0.0) -> Problem:
     """Draw one problem.
 
     Draw order (part of the contract so both sides reproduce it): core energies,
-    active energies, virtual energies, B, CI vector.  ``gap`` in (0, 1] scales the
+    active energies, virtual energies, B, CI vector, then (only with f_sigma > 0) the
+    inter-block Fock elements.  ``gap`` in (0, 1] scales the
     inner edges of the energy windows toward zero to mimic a stretched bond:
     core U(-2, -0.5 gap), active U(-0.3 gap, 0.3 gap), virtual U(0.2 gap, 3).
+    ``f_sigma`` > 0 adds a symmetric f_offdiag with N(0, f_sigma^2) entries on the
+    core-active, core-virtual and active-virtual blocks (upper triangle drawn row-major,
+    mirrored) and zeros inside the blocks.
     """
     rng = np.random.default_rng(seed)
     N = n_core + n_active + n_virtual
@@ -259,8 +265,17 @@ def make_problem(n_core: int, n_active: int, n_virtual: int, n_aux: int, seed: i
             g3 = None
     else:
         ci, g1, g2, g3 = None, None, None, None
+    f = None
+    if f_sigma > 0.0:
+        blk = np.array([0] * n_core + [1] * n_active + [2] * n_virtual)
+        iu = np.triu_indices(N, k=1)
+        inter = blk[iu[0]] != blk[iu[1]]
+        vals = rng.standard_normal(int(inter.sum())) * f_sigma
+        f = np.zeros((N, N))
+        f[iu[0][inter], iu[1][inter]] = vals
+        f[iu[1][inter], iu[0][inter]] = vals
     return Problem(n_core, n_active, n_virtual, n_aux, eps, B, g1, g2, g3, float(s),
-                   ci=ci, n_alpha=n_alpha, n_beta=n_beta, name=name)
+                   ci=ci, n_alpha=n_alpha, n_beta=n_beta, name=name, f_offdiag=f)
 
 
 # The five workloads: shapes from the paper's CAS(2,2), CAS(6,6) and CAS(8,8)

@@ -123,3 +123,80 @@ def test_test_gett_validates_strides(lib):
     with pytest.raises(_lib.DsrgError) as e:
         _lib.test_gett(A, B, C, m=[(2, 1, 1)], n=[(2, 1, 2)], k=[(2, 2, 1)], precision=5)
     assert e.value.code == _lib.DSRG_E_UNSUPPORTED
+
+
+def _opt(flags=0, precision=0, cap=0, virt_batch=0):
+    return _lib.Options(flags, precision, cap, None, virt_batch)
+
+
+def test_density_checks(lib):
+    """gamma1 must be symmetric, gamma2 Hermitian and antisymmetric in its same-spin blocks
+    (DSRG_E_RDM, output untouched)."""
+    p = make_problem(1, 3, 2, 6, seed=1)
+    assert _call(p)[0] != _lib.DSRG_E_RDM   # valid densities pass the host checks
+    q = make_problem(1, 3, 2, 6, seed=1)
+    q.gamma1[1, 0, 2] += 1e-6
+    rc, r = _call(q)
+    assert rc == _lib.DSRG_E_RDM and r.e2 == 12345.0
+    q = make_problem(1, 3, 2, 6, seed=1)
+    q.gamma2[0, 0, 1, 0, 2] += 1e-6      # aa block: breaks u <-> v antisymmetry
+    assert _call(q)[0] == _lib.DSRG_E_RDM
+    q = make_problem(1, 3, 2, 6, seed=1)
+    q.gamma2[1, 0, 1, 2, 0] += 1e-6      # ab block: breaks hermiticity only
+    assert _call(q)[0] == _lib.DSRG_E_RDM
+    q = make_problem(1, 3, 2, 6, seed=1)
+    q.gamma2[1, 0, 1, 2, 0] += 1e-12     # below the tolerance
+    assert _call(q)[0] != _lib.DSRG_E_RDM
+
+
+def test_intruder_at_infinite_s(lib):
+    """s = +inf with a vanishing singles or doubles denominator: DSRG_E_INTRUDER; the same
+    orbital energies at finite s are accepted (the regulariser has no intruders)."""
+    p = make_problem(2, 0, 3, 6, seed=1, s=float("inf"))
+    p.eps[:] = [-1.0, -0.5, 0.25, 0.75, 2.0]      # e0 + e1 = -1.5: no zero denominator
+    assert _call(p)[0] != _lib.DSRG_E_INTRUDER
+    q = make_problem(2, 0, 3, 6, seed=1, s=float("inf"))
+    q.eps[:] = [-1.0, -0.5, 0.25, 0.75, 2.0]
+    q.eps[4] = -1.0 - 0.5 - 0.25                  # e0 + e1 - e2 - e4 = 0
+    rc, r = _call(q)
+    assert rc == _lib.DSRG_E_INTRUDER and r.e2 == 12345.0
+    q = make_problem(1, 2, 2, 6, seed=1, s=float("inf"))
+    q.eps[3] = q.eps[0]                           # core-virtual singles denominator 0
+    assert _call(q)[0] == _lib.DSRG_E_INTRUDER
+    q2 = make_problem(1, 2, 2, 6, seed=1, s=0.5)
+    q2.eps[3] = q2.eps[0]
+    assert _call(q2)[0] != _lib.DSRG_E_INTRUDER
+    # an all-active quadruple carries no amplitude: a zero denominator there is allowed
+    q = make_problem(1, 2, 2, 6, seed=1, s=float("inf"))
+    q.eps[1] = q.eps[2] = 0.0
+    assert _call(q)[0] != _lib.DSRG_E_INTRUDER
+
+
+def test_workspace_and_batch_checks(lib):
+    """workspace_cap below one (PP|PP) batch row, or a virt_batch that does not fit it:
+    DSRG_E_OOM before any device work; negative virt_batch: DSRG_E_ARG."""
+    p = make_problem(1, 2, 6, 6, seed=1)
+    nP = 8
+    kp = nP * (nP - 1) // 2
+    row = 8 * (nP ** 3 + nP * (2 * kp + nP))
+    rc, r = _call(p, opt=_opt(cap=row - 8))
+    assert rc == _lib.DSRG_E_OOM and r.e2 == 12345.0
+    assert "below one" in lib.dsrg_last_error().decode()
+    rc, _ = _call(p, opt=_opt(cap=3 * row, virt_batch=4))
+    assert rc == _lib.DSRG_E_OOM
+    rc, _ = _call(p, opt=_opt(virt_batch=-1))
+    assert rc == _lib.DSRG_E_ARG
+
+
+def test_nonfinite_fock_offdiag(lib):
+    p = make_problem(1, 2, 3, 6, seed=1, f_sigma=0.1)
+    p.f_offdiag[0, 4] = np.nan
+    rc, r = _call(p)
+    assert rc == _lib.DSRG_E_NONFINITE and r.e2 == 12345.0
+
+
+def test_struct_layouts_match_header(lib):
+    """The binding's structs have the sizes of the C declarations (new fields appended)."""
+    assert ctypes.sizeof(_lib.Problem) == 4 * 4 + 5 * 8 + 8 + 8 + 8
+    assert ctypes.sizeof(_lib.Options) == 4 + 4 + 8 + 8 + 8
+    assert _lib.Result.e_total.offset > _lib.Result.role_bytes.offset

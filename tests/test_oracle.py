@@ -637,3 +637,96 @@ def test_multireference_projection_in_fock_space(nC, nA, nV, seed):
             assert abs(psi0 @ r3) < 1e-12
         assert np.abs(lhs).max() > 1e-3
         assert np.abs(lhs - rhs).max() < 1e-11 * max(1.0, np.abs(lhs).max())
+
+
+# ---------------------------------------------------------------------------
+# Inter-block Fock elements f(1) (H(1) = f(1) + V)
+# ---------------------------------------------------------------------------
+def test_e2_with_fock_offdiag_matches_fock_space():
+    """With f(1): E^(2) = <Psi0|[H~(1), T(1)]|Psi0>, H~(1) = 2 (f(1) + V) + [H(0), A(1)],
+    every operator a brute-force Fock-space matrix."""
+    p = make_problem(1, 2, 3, 10, seed=81, s=0.6, f_sigma=0.08)
+    r = dsrg.run(p)
+    sp = r.sp
+    dens = build_densities(sp, p.gamma1, p.gamma2, p.gamma3)
+    fs = FockSpace(2 * sp.N)
+    vec = reference_vector(sp, p.ci, p.n_alpha, p.n_beta, fs)
+    v = so_integrals(sp, p.B)
+    # f(1) over spin orbitals written out here: equal spins, inter-block spatial elements
+    so = _so_map(sp.nC, sp.nA, sp.nV)
+    blk = [0] * sp.nC + [1] * sp.nA + [2] * sp.nV
+    f_so = np.zeros((2 * sp.N, 2 * sp.N))
+    for P_ in range(sp.N):
+        for Q_ in range(sp.N):
+            if blk[P_] != blk[Q_]:
+                for sig in (0, 1):
+                    f_so[so[(P_, sig)], so[(Q_, sig)]] = p.f_offdiag[P_, Q_]
+    H1 = gno.gno_to_bare(gno.to_plain(0.0, f_so, v), dens)
+    F0 = gno.gno_to_bare((0.0, np.diag(r.eps), None), dens)
+    a1, a2 = dsrg.anti_hermitian(r.t1_1, r.t2_1)
+    A1 = gno.gno_to_bare(gno.to_plain(0.0, a1, a2), dens)
+    T1 = gno.gno_to_bare(gno.to_plain(0.0, r.t1_1, r.t2_1), dens)
+
+    def Ht(x):
+        return 2.0 * fs.apply(H1, x) + fs.apply(F0, fs.apply(A1, x)) - fs.apply(A1, fs.apply(F0, x))
+    e2 = vec @ Ht(fs.apply(T1, vec)) - vec @ fs.apply(T1, Ht(vec))
+    r0 = dsrg.run(dataclasses.replace(p, f_offdiag=None))
+    assert abs(e2 - r0.e2) > 1e-4           # f(1) matters
+    assert abs(e2 - r.e2) < 1e-12
+
+
+@pytest.mark.parametrize("nC,nV,seed", [(2, 3, 85), (1, 4, 86)])
+def test_single_reference_infinite_s_with_fock_offdiag_is_mp2_mp3(nC, nV, seed):
+    """n_A = 0, s -> infinity, f(1) on the core-virtual block: E^(2) and E^(3) equal second-
+    and third-order Rayleigh-Schroedinger energies (singles included) from brute force in
+    the determinant basis, with H0 = sum_p eps_p n_p and V = f(1) + the normal-ordered
+    two-electron operator."""
+    p = make_problem(nC, 0, nV, 9, seed=seed, s=float("inf"), f_sigma=0.1)
+    r = dsrg.run(p)
+    sp = Spaces(nC, 0, nV)
+    n = 2 * sp.N
+    dens = build_densities(sp, None, None, None)
+    fs = FockSpace(n)
+    eps = so_energies(sp, p.eps)
+    v = so_integrals(sp, p.B)
+    so = _so_map(nC, 0, nV)
+    f_so = np.zeros((n, n))
+    for P_ in range(sp.N):
+        for Q_ in range(sp.N):
+            if (P_ < nC) != (Q_ < nC):
+                for sig in (0, 1):
+                    f_so[so[(P_, sig)], so[(Q_, sig)]] = p.f_offdiag[P_, Q_]
+    basis = sector_basis(fs, sp, nC, nC)
+    ref = list(basis).index(sum(1 << k for k in range(2 * nC)))
+    V = fs.matrix(gno.gno_to_bare(gno.to_plain(0.0, f_so, v), dens), basis)
+    occ = np.array([[(st >> k) & 1 for k in range(n)] for st in basis])
+    h0 = occ @ eps
+    E1, E2, E3 = rspt_energies(h0, V, ref)
+    assert abs(E1) < 1e-15
+    r0 = dsrg.run(dataclasses.replace(p, f_offdiag=None))
+    assert abs(r.e2 - r0.e2) > 1e-4 and abs(r.e3 - r0.e3) > 1e-5
+    assert abs(r.e2 - E2) < 1e-14 and abs(r.e3 - E3) < 1e-14
+
+
+def test_first_order_closed_forms_with_fock_offdiag():
+    """With f(1) the non-diagonal one-body H~(1) is f + (f + sum_ux D^x_u t^iu_ax gamma^x_u)
+    exp(-s D^2) and t^i_a = (f + sum ...) R_s(D) (Eq. T1_1st and Sec. III)."""
+    p = make_problem(1, 2, 3, 10, seed=87, s=0.8, f_sigma=0.1)
+    sp = Spaces(1, 2, 3)
+    n = 2 * sp.N
+    dens = build_densities(sp, p.gamma1, p.gamma2, p.gamma3)
+    r = dsrg.run(p, keep_ops=True)
+    eps = r.eps
+    A = sp.A
+    coup = np.einsum("axiu,ux,xu->ai", r.t2_1[:, A, :, A], eps[None, A] - eps[A, None],
+                     dens.gamma[A, A])
+    f_so = dsrg.so_fock_offdiag(sp, p.f_offdiag)
+    m1, _ = dsrg._internal_mask(sp)
+    D1, _ = dsrg.denominators(eps)
+    Rs = np.where(D1 != 0, -np.expm1(-p.s * D1 ** 2) / np.where(D1 != 0, D1, 1.0), 0.0)
+    np.testing.assert_allclose(np.where(m1, r.t1_1, 0.0), np.where(m1, (f_so + coup) * Rs, 0.0),
+                               atol=1e-15)
+    ht1 = r.ops["Ht1"][1]          # plain-order one-body part of H~(1)
+    np.testing.assert_allclose(np.where(m1, ht1, 0.0),
+                               np.where(m1, f_so + (f_so + coup) * np.exp(-p.s * D1 ** 2), 0.0),
+                               atol=1e-14)
