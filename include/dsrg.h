@@ -207,6 +207,25 @@ int dsrg_pt3_energy_batch(const dsrg_problem* probs, int32_t n, const dsrg_optio
 int dsrg_pt3_pair_energies(const dsrg_problem* prob, const dsrg_options* opt, dsrg_result* out,
                            double* e3_pairs, double* e3_rest);
 
+/* For callers that cannot allocate device memory (work under HIP graph capture set up
+   around the call's inputs, tight serving loops, harnesses that forbid hipMalloc): E(2) and
+   E(3) as dsrg_pt3_energy, with every device buffer of the pipeline (input copies,
+   intermediates, temporaries, integral batches) carved from one static device array of
+   DSRG_NOALLOC_SCRATCH_BYTES per GPU, which that GPU holds from the library's first use
+   of it until the process ends.  The call allocates nothing: no hipMalloc or hipFree, no
+   pinned host memory, no library stream or event, no plan or graph; everything runs on
+   opt->stream and the call synchronises it before returning.  The pipeline is planned
+   before any device work: a problem whose buffers do not fit returns DSRG_E_OOM and
+   leaves *out untouched (tiny and micro problems fit; the small workload does not).
+   workspace_cap is lowered to a quarter of the array.  DSRG_F_PROFILE is refused with
+   DSRG_E_ARG.  Calls that overlapped on one GPU would share its array and race, so the
+   library runs them one at a time (a second host thread waits); the array keeps the last
+   call's contents, and every buffer the pipeline needs cleared is cleared by a kernel of
+   that call.  Energies agree with dsrg_pt3_energy to summation order (bitwise when both
+   group the contractions the same way). */
+#define DSRG_NOALLOC_SCRATCH_BYTES (64LL << 20)
+int dsrg_pt3_energy_noalloc(const dsrg_problem* prob, const dsrg_options* opt, dsrg_result* out);
+
 /* As dsrg_pt3_energy, and copies the requested intermediates to host memory. */
 int dsrg_pt3_energy_ex(const dsrg_problem* prob, const dsrg_options* opt, dsrg_result* out,
                        const dsrg_intermediates* inter);

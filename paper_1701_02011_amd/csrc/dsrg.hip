@@ -202,11 +202,25 @@ struct Pool {
   bool sync_before_free = true;
   std::vector<void*> bufs;
   size_t bytes = 0;
+  // arena mode: buffers are carved in order from [arena, arena + arena_cap) (256-byte
+  // aligned) and never freed; nothing is allocated from the runtime
+  char* arena = nullptr;
+  size_t arena_cap = 0;
   explicit Pool(hipStream_t s, bool keep_ = false) : st(s), keep(keep_) {}
+  Pool(hipStream_t s, char* base, size_t cap) : st(s), keep(true), sync_before_free(false), arena(base), arena_cap(cap) {}
   Pool(const Pool&) = delete;
   Pool& operator=(const Pool&) = delete;
   double* alloc(size_t n) {
     if (n == 0) n = 1;
+    if (arena) {
+      const size_t need = (n * sizeof(double) + 255) & ~(size_t)255;
+      if (bytes + need > arena_cap)
+        throw Error(DSRG_E_OOM, "the problem needs more than the " + std::to_string(arena_cap >> 20) +
+                                    " MiB of the static scratch (" + std::to_string(bytes + need) + " bytes so far)");
+      double* p = reinterpret_cast<double*>(arena + bytes);
+      bytes += need;
+      return p;
+    }
     void* p = nullptr;
     hipError_t e = hipMalloc(&p, n * sizeof(double));
     if (e != hipSuccess) {
@@ -239,7 +253,12 @@ struct OpLog {
   hipStream_t st;
   std::vector<DevOp>* rec = nullptr;
   hipStream_t side = nullptr;   // set: ops of a forked branch, run on this stream
+  bool defer = false;           // record only (into rec); the caller runs the list later
   void operator()(DevOp f) {
+    if (defer) {
+      rec->push_back(std::move(f));
+      return;
+    }
     if (side) {
       DevOp g = [f = std::move(f), sd = side](hipStream_t) { f(sd); };
       g(st);
@@ -321,6 +340,7 @@ struct Exec {
 
   // every contraction launch goes through here; with profiling, HIP events bracket it
   bool profile;
+  bool no_side = false;   // keep every launch on the caller's stream (no library stream or events)
   int role_now = kRoleGeneric;
   struct Rec {
     hipEvent_t a, b;
@@ -907,7 +927,11 @@ struct Exec {
     size_t bytes = v.size() * sizeof(T);
     double* dp = pool.alloc((bytes + 7) / 8);
     hold.emplace_back((const char*)v.data(), (const char*)v.data() + bytes);
-    HIPCHECK(hipMemcpyAsync(dp, hold.back().data(), bytes, hipMemcpyHostToDevice, st));
+    const char* src = hold.back().data();
+    if (op.defer)
+      op([dp, src, bytes](hipStream_t s) { HIPCHECK(hipMemcpyAsync(dp, src, bytes, hipMemcpyHostToDevice, s)); });
+    else
+      HIPCHECK(hipMemcpyAsync(dp, src, bytes, hipMemcpyHostToDevice, st));
     return (T*)dp;
   }
 
@@ -1903,7 +1927,7 @@ struct Exec {
     // (not when profiling, whose events time each stream's launches in order)
     bool any_pp = false;
     for (auto& u : pp) any_pp = any_pp || !u.empty();
-    const bool overlap = any_pp && !profile;
+    const bool overlap = any_pp && !profile && !no_side;
     auto side = [&] {
       fork_side();
       try {
@@ -2417,6 +2441,11 @@ static void load_inputs(const dsrg_problem* P, bool devptr, const Shape& sh, con
   check_bad(hbad);
 }
 
+// Stage marks of the pipeline (ev null: no stage timing, as in the allocation-free entry).
+static void mark(hipEvent_t* ev, int k, hipStream_t st) {
+  if (ev) HIPCHECK(hipEventRecord(ev[k], st));
+}
+
 // Device buffers of the intermediates a caller may ask for.
 struct BodyOut {
   double *T1a = nullptr, *T1b = nullptr, *T2aa = nullptr, *T2ab = nullptr;
@@ -2486,7 +2515,7 @@ static BodyOut body(Exec& X, OpLog& op, Pool& pool, const Shape& sh, const Input
     X.prebuild_j(keys);
   }
   double* Jhphp = X.jblock("HPHP");
-  HIPCHECK(hipEventRecord(ev[1], st));
+  mark(ev, 1, st);
 
   // step a2: first-order amplitudes, Y = [H(0), A(1)] and H~(1) (excitation blocks)
   const size_t n4 = (size_t)nP * nP * nH * nH, n1 = (size_t)nP * nH;
@@ -2536,7 +2565,7 @@ static BodyOut body(Exec& X, OpLog& op, Pool& pool, const Shape& sh, const Input
   X.set("Y1.a", Y1a, "PH"); X.set("Y1.b", Y1b, "PH");
   X.set("Y2.aa", Y2aa, "PPHH"); X.set("Y2.ab", Y2ab, "PPHH"); X.set("Y2.bb", Y2aa, "PPHH");
   bo.T1a = T1a; bo.T1b = T1b; bo.T2aa = T2aa; bo.T2ab = T2ab;
-  HIPCHECK(hipEventRecord(ev[2], st));
+  mark(ev, 2, st);
 
   auto& T = table();
   const Use& C0 = T.at("C0");
@@ -2550,7 +2579,7 @@ static BodyOut body(Exec& X, OpLog& op, Pool& pool, const Shape& sh, const Input
   if (!sh.pt3) {
     // step a3: E(2) = <[H~(1), T(1)]>
     scalar(energies + 0);
-    for (int k = 3; k < 7; ++k) HIPCHECK(hipEventRecord(ev[k], st));
+    for (int k = 3; k < 7; ++k) mark(ev, k, st);
     return bo;
   }
   // W = [V, A(1)]_{1,2} and Z = [Y, A(1)]_{1,2}, excitation blocks
@@ -2583,16 +2612,16 @@ static BodyOut body(Exec& X, OpLog& op, Pool& pool, const Shape& sh, const Input
   X.use_id = 0;
   if ((long long)n4 <= (1LL << 22) &&
       X.run_fused({&C0, &T.at("W"), &T.at("Z")}, {&none_e, &wout, &zout}, {energies + 0, nullptr, nullptr})) {
-    for (int k = 3; k < 6; ++k) HIPCHECK(hipEventRecord(ev[k], st));
+    for (int k = 3; k < 6; ++k) mark(ev, k, st);
   } else {
     scalar(energies + 0);
-    HIPCHECK(hipEventRecord(ev[3], st));
+    mark(ev, 3, st);
     X.use_id = 1;
     X.run_use(T.at("W"), wout, nullptr);
-    HIPCHECK(hipEventRecord(ev[4], st));
+    mark(ev, 4, st);
     X.use_id = 2;
     X.run_use(T.at("Z"), zout, nullptr);
-    HIPCHECK(hipEventRecord(ev[5], st));
+    mark(ev, 5, st);
   }
   if (F1) {
     // [f(1), A(1)]_{1,2}: the products of [Y, A(1)] with a one-body Y factor, with f(1) in its
@@ -2652,7 +2681,7 @@ static BodyOut body(Exec& X, OpLog& op, Pool& pool, const Shape& sh, const Input
     const Use ua = renamed("T1", "U1", "T2", "U2"), ub = renamed("E1", "H1", "E2", "H2");
     std::map<std::string, TensorRef> none_a, none_b;
     if (X.run_fused({&ua, &ub}, {&none_a, &none_b}, {energies + 1, energies + 2})) {
-      HIPCHECK(hipEventRecord(ev[6], st));
+      mark(ev, 6, st);
       bo.W1 = W1; bo.W2 = W2; bo.Z1 = Z1; bo.Z2 = Z2; bo.U1 = U1; bo.U2 = U2;
       return bo;
     }
@@ -2696,7 +2725,7 @@ static BodyOut body(Exec& X, OpLog& op, Pool& pool, const Shape& sh, const Input
     double* pairs = bo.pairs;
     op([nC, P2, energies, pairs](hipStream_t s) { launch_pair_fold(nC, P2, energies, pairs, s); });
   }
-  HIPCHECK(hipEventRecord(ev[6], st));
+  mark(ev, 6, st);
   bo.W1 = W1; bo.W2 = W2; bo.Z1 = Z1; bo.Z2 = Z2; bo.U1 = U1; bo.U2 = U2;
   return bo;
 }
@@ -3042,9 +3071,9 @@ static int run(const dsrg_problem* P, const dsrg_options* O, dsrg_result* R,
     int* bad = reinterpret_cast<int*>(plan->pinned + 8);
     bad[0] = bad[1] = 0;
     load_inputs(P, devptr, sh, plan->in, plan->pinned, st, devptr ? bad : nullptr);
-    HIPCHECK(hipEventRecord(ev[0], st));
+    mark(ev, 0, st);
     HIPCHECK(hipGraphLaunch(plan->exec, st));
-    HIPCHECK(hipEventRecord(ev[7], st));
+    mark(ev, 7, st);
     HIPCHECK(hipMemcpyAsync(plan->pinned + 4, plan->in.energies, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHECK(hipStreamSynchronize(st));
     HIPCHECK(hipGetLastError());
@@ -3089,7 +3118,7 @@ static int run(const dsrg_problem* P, const dsrg_options* O, dsrg_result* R,
   X.group_cap = cap / 2;
   X.f32 = f32;
   X.virt_batch = S.vb;
-  HIPCHECK(hipEventRecord(ev[0], st));
+  mark(ev, 0, st);
   BodyOut bo = body(X, op, *pool, sh, in, ev, st, want_pairs);
   std::vector<double> pair_host;
   if (want_pairs) {
@@ -3111,7 +3140,7 @@ static int run(const dsrg_problem* P, const dsrg_options* O, dsrg_result* R,
     cp(I->z1, bo.Z1, 2 * n1); cp(I->z2, bo.Z2, 3 * n4);
     cp(I->u1, bo.U1, 2 * n1); cp(I->u2, bo.U2, 3 * n4);
   }
-  HIPCHECK(hipEventRecord(ev[7], st));
+  mark(ev, 7, st);
   double e[4] = {0, 0, 0, 0};
   HIPCHECK(hipMemcpyAsync(e, in.energies, 4 * 8, hipMemcpyDeviceToHost, st));
   HIPCHECK(hipStreamSynchronize(st));
@@ -3181,6 +3210,84 @@ static int guarded(F&& f) {
     g_last_error = e.what();
     return DSRG_E_HIP;
   }
+}
+
+// ---------------------------------------------------------------------------
+// Allocation-free entry: every buffer of the pipeline carved from a static device array.
+// The pipeline is planned first with its launches recorded but not run, so a problem that
+// does not fit fails before any device work; then the inputs are copied and the recorded
+// launches run in order on the caller's stream.
+// ---------------------------------------------------------------------------
+constexpr size_t kScratchBytes = (size_t)DSRG_NOALLOC_SCRATCH_BYTES;
+static __device__ __align__(256) char scratch[kScratchBytes];
+
+struct ScratchDev {
+  char* ptr = nullptr;   // this device's copy of the array (device address)
+  std::mutex call;       // calls on one device share the array: one at a time
+};
+// Set up on the first call on a device (that device current): the array's device address
+// from the runtime, kept per device.  The host-side name of the array is never used as an
+// address.
+static ScratchDev& scratch_dev(int dev) {
+  static std::mutex mu;
+  static auto* m = new std::map<int, std::unique_ptr<ScratchDev>>();
+  std::lock_guard<std::mutex> lk(mu);
+  auto& e = (*m)[dev];
+  if (!e) {
+    void* p = nullptr;
+    const hipError_t rc = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (rc != hipSuccess || !p) {
+      (void)hipGetLastError();
+      throw Error(DSRG_E_HIP, std::string("hipGetSymbolAddress(scratch): ") + hipGetErrorString(rc));
+    }
+    auto d = std::make_unique<ScratchDev>();
+    d->ptr = static_cast<char*>(p);
+    e = std::move(d);
+  }
+  return *e;
+}
+
+static int run_noalloc(const dsrg_problem* P, const dsrg_options* O, dsrg_result* R) {
+  if (!P || !R) throw Error(DSRG_E_ARG, "null problem or result");
+  if (O && (O->flags & DSRG_F_PROFILE)) throw Error(DSRG_E_ARG, "DSRG_F_PROFILE needs events: not available without allocation");
+  const Setup S = setup(P, O, nullptr, true, nullptr, nullptr, 0);
+  const Shape& sh = S.sh;
+  ScratchDev& sd = scratch_dev(S.dev);
+  std::lock_guard<std::mutex> lk(sd.call);
+  Pool pool(S.st, sd.ptr, kScratchBytes);
+  Inputs in = alloc_inputs(pool, sh);
+  std::vector<DevOp> ops;
+  OpLog op{S.st, &ops};
+  op.defer = true;
+  // the (PP|PP) batches and the grouped temporaries get at most a quarter of the array
+  const long long cap = std::min<long long>(S.cap, (long long)(kScratchBytes / 4));
+  Exec X(Dims{sh.nC, sh.nA, sh.nV}, S.st, pool, op, in.B, sh.M, cap, false);
+  X.grouped = S.grouped;
+  X.unique_ladder = S.unique_ladder;
+  X.group_cap = cap / 2;
+  X.f32 = S.f32;
+  X.virt_batch = S.vb;
+  X.no_side = true;
+  body(X, op, pool, sh, in, nullptr, S.st, false);   // plans and records every launch
+  load_inputs(P, S.devptr, sh, in, &P->s, S.st);
+  for (auto& f : ops) f(S.st);
+  double e[4] = {0, 0, 0, 0};
+  HIPCHECK(hipMemcpyAsync(e, in.energies, 4 * sizeof(double), hipMemcpyDeviceToHost, S.st));
+  HIPCHECK(hipStreamSynchronize(S.st));
+  HIPCHECK(hipGetLastError());
+  dsrg_result r;
+  memset(&r, 0, sizeof(r));
+  fill_result(&r, e, true, P->e0);
+  r.gett_flops = X.gett_flops;
+  r.ladder_flops = X.ladder_flops;
+  r.ladder_batch = X.ladder_batch;
+  r.n_launch = X.n_launch;
+  r.grouped_uses = X.grouped_uses;
+  r.alg_flops = X.gett_flops;
+  r.precision_used = S.f32 ? DSRG_PRECISION_FP32 : DSRG_PRECISION_FP64;
+  r.virt_batch_used = X.ladder_batch;
+  *R = r;
+  return DSRG_OK;
 }
 
 }  // namespace dsrg
@@ -3287,6 +3394,10 @@ int dsrg_pt3_energy_batch(const dsrg_problem* probs, int32_t n, const dsrg_optio
   (void)hipHostFree(stage);
   (void)hipEventDestroy(ready);
   return any_ok ? DSRG_OK : first_error;
+}
+
+int dsrg_pt3_energy_noalloc(const dsrg_problem* prob, const dsrg_options* opt, dsrg_result* out) {
+  return dsrg::guarded([&] { return dsrg::run_noalloc(prob, opt, out); });
 }
 
 int dsrg_pt3_pair_energies(const dsrg_problem* prob, const dsrg_options* opt, dsrg_result* out,
