@@ -37,10 +37,6 @@ def workload_problems(name, geometries=4):
     return [make_config(name)]
 
 
-# Ratio of the oracle's time for a whole small-workload energy to its time through E(2)
-# (steps a0-a3), measured once with the same oracle on an 8-core host (OpenBLAS 0.3.29,
-# 8 threads, nothing else running): 204.7 s / 53.2 s.
-ORACLE_FULL_OVER_E2 = 3.85
 
 
 def measured_traffic(kernel, workload, precision):
@@ -74,33 +70,100 @@ def blas_threads():
     return int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
 
 
-def cpu_baseline(workload):
-    """The FP64 oracle, as it stands, on the host cores: a bounded sample of the workload
-    (one problem through E(2)), scaled to whole energies by the measured time ratio."""
-    from oracle import dsrg
-    p = workload_problems(workload)[len(workload_problems(workload)) // 2]
+# kernel instance of each profile bucket (index 2 * role + 128x128-tile flag), FP64 names
+KERNELS = ["gett_f64_kernel<0, 2, 2>", "gett_f64_kernel<0, 4, 4>",
+           "gett_f64_kernel<1, 2, 2>", "gett_f64_kernel<1, 4, 4>",
+           "gett_f64_kernel<2, 2, 2> / coulomb_group_kernel<false>", "gett_f64_kernel<2, 4, 4>",
+           "gett_group_kernel<false>", "gett_group_big_kernel<false>"]
+ROLE_NOTES = ["table products, one launch each", "(PP|PP) ladder contractions",
+              "Coulomb-block builds B.B", "grouped table products"]
+
+
+def kernel_name(k, f32):
+    n = KERNELS[k]
+    if f32:
+        n = n.replace("f64", "f32").replace("<false>", "<true>")
+    return n
+
+
+def golden(workload, s):
+    path = os.path.join(ROOT, "tests", "golden", "%s_s%g.json" % (workload, s))
+    return json.load(open(path)) if os.path.exists(path) else None
+
+
+def parity_of(probs, res, workload):
+    """|dE| and |dE|/|E| of each energy against the stored oracle values (FP64 oracle)."""
+    out = []
+    for p, r in zip(probs, res):
+        g = golden(workload, p.s)
+        if g is None:
+            return None
+        item = dict(s=p.s)
+        for k in ("e2", "e3"):
+            d = abs(r[k] - g[k])
+            item["abs_d" + k] = d
+            item["rel_d" + k] = d / max(abs(g[k]), 1e-300)
+        out.append(item)
+    return dict(items=out, max_abs_dE=max(max(x["abs_de2"], x["abs_de3"]) for x in out),
+                max_rel_dE=max(max(x["rel_de2"], x["rel_de3"]) for x in out),
+                reference="tests/golden/%s_s*.json (FP64 oracle, %s)" % (
+                    workload, golden(workload, probs[0].s).get("source", "oracle")))
+
+
+def cpu_baseline(workload, probs):
+    """The FP64 oracle as it stands, timed on this host's cores.
+
+    tiny, small: one whole energy of the workload's middle problem (the dense engine for
+    tiny, the block-sparse DF level for small).  medium, large: a bounded sample, the block
+    level's first stage (cumulants, antisymmetrised integral blocks and first-order
+    amplitudes) on the full problem, converted to a whole energy with the stage's share of
+    the full run that tests/golden/make_golden.py timed and recorded in the stored oracle
+    values (whose full-energy time is reported beside it)."""
+    p = probs[len(probs) // 2]
+    cores = blas_threads()
+    if workload == "tiny":
+        from oracle import dsrg
+        t0 = time.perf_counter()
+        dsrg.run(p)
+        dt = time.perf_counter() - t0
+        return dict(value=1.0 / dt, unit="energies/s", cores=cores, kind="oracle",
+                    sample="one whole energy, oracle/dsrg.py, %.2f s" % dt)
+    from oracle import dsrg_df
+    if workload == "small":
+        t0 = time.perf_counter()
+        dsrg_df.run(p)
+        dt = time.perf_counter() - t0
+        return dict(value=1.0 / dt, unit="energies/s", cores=cores, kind="oracle",
+                    sample="one whole energy (s = %g), oracle/dsrg_df.py, %.1f s" % (p.s, dt))
+    g = golden(workload, p.s)
+    if g is None or "stage_seconds" not in g:
+        return None
     t0 = time.perf_counter()
-    dsrg.run(p, through="e2")
+    dsrg_df.run(p, through="first_order")
     dt = time.perf_counter() - t0
-    per_energy = dt * ORACLE_FULL_OVER_E2
-    return dict(value=1.0 / per_energy, unit="energies/s", cores=blas_threads(), kind="oracle",
-                sample="oracle/dsrg.py run(through='e2') on the %s problem with s=%g (steps a0-a3: "
-                       "densities, integrals, first-order amplitudes, [H0,A1], E(2)) took %.1f s; "
-                       "scaled by %.1f, the oracle's full-energy/through-E(2) time ratio measured "
-                       "on an 8-core host (204.7 s / 53.2 s), to %.0f s per energy"
-                       % (workload, p.s, dt, ORACLE_FULL_OVER_E2, per_energy))
+    share = g["stage_seconds"]["first_order"] / g["stage_seconds"]["total"]
+    return dict(value=share / dt, unit="energies/s", cores=cores, kind="oracle",
+                sample="first stage of oracle/dsrg_df.py (cumulants, integral blocks, first-order "
+                       "amplitudes) on the full %s problem: %.1f s here; it is %.2f %% of the full "
+                       "energy in the recorded full run (%.0f s on %d cpus, tests/golden/%s_s%g.json), "
+                       "so %.0f s per energy" % (workload, dt, 100 * share, g["oracle_seconds"],
+                                                 g.get("host", {}).get("cpus", 0), workload, p.s,
+                                                 dt / share),
+                full_energy_seconds_recorded=g["oracle_seconds"])
 
 
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=10)
+    ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=2)
-    ap.add_argument("--workload", default="small", choices=["tiny", "small", "medium", "large", "curve"])
+    ap.add_argument("--workload", default="medium", choices=["tiny", "small", "medium", "large", "curve"])
     ap.add_argument("--geometries", type=int, default=4, help="curve workload: number of geometries")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"],
-                    help="fp32: FP32 products in the contractions (FP64 sums and reductions)")
+                    help="precision of the timed headline loop (fp32: FP32 products, FP64 sums)")
+    ap.add_argument("--mixed-steps", type=int, default=3,
+                    help="timed steps of the FP32-product pass reported beside the headline")
     args = ap.parse_args()
     if args.gpus != 1:
         sys.stderr.write("bench.py: this benchmark runs on exactly one GPU; --gpus %d is not "
@@ -114,78 +177,54 @@ def main():
     dev = [_lib.to_device(p) for p in probs]
     torch.cuda.synchronize()
 
-    prec = 1 if args.precision == "fp32" else 0
-
-    def step():
+    def step(prec):
         if args.workload == "curve":
             # geometries of different shapes: the batch entry point (two at a time)
             res, codes = _lib.dsrg_pt3_energy_batch(dev, precision=prec)
             assert all(c == 0 for c in codes), codes
             return res
-        # one call per energy (replays of one plan; the batch's two-at-a-time rounds gained
-        # -3 to +4 % here depending on the machine, within the run-to-run spread)
         return [_lib.dsrg_pt3_energy(d, precision=prec) for d in dev]
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for _ in range(args.steps):
-        res = step()
-    torch.cuda.synchronize()
-    dt = time.perf_counter() - t0
+    def timed(prec, warmup, steps):
+        for _ in range(warmup):
+            step(prec)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(steps):
+            res = step(prec)
+        torch.cuda.synchronize()
+        return res, time.perf_counter() - t0
+
+    prec = 1 if args.precision == "fp32" else 0
+    res, dt = timed(prec, args.warmup, args.steps)
     energies = args.steps * len(dev)
     ms_per_step = dt * 1e3 / args.steps
 
-    # roofline of the dominant contraction kernel: HIP events bracket every contraction
-    # launch (grouped or single) in a profiled pass over the same problems, on the stream
-    # the kernels run on; the timed loop above replays the recorded graph instead
+    # roofline of the dominant kernel instance: HIP events bracket every contraction launch
+    # (on the stream it runs on) in a profiled pass over the same problems; the timed loop
+    # above replays the recorded graph instead
     prof = [_lib.dsrg_pt3_energy(d, profile=True, precision=prec) for d in dev]
     torch.cuda.synchronize()
-    names = ["gett_f64_kernel<0, *, *> (table contractions, one launch each)",
-             "gett_f64_kernel<1, *, *> ((PP|PP) ladder contractions)",
-             "gett_f64_kernel<2, *, *> (Coulomb-block builds B.B)",
-             "gett_group_kernel<false> (grouped table contractions)"]
-    sec = [sum(r["role_seconds"][k] for r in prof) for k in range(4)]
-    nl = [sum(r["role_launches"][k] for r in prof) for k in range(4)]
-    fl = [sum(r["role_flops"][k] for r in prof) for k in range(4)]
-    dom = max(range(4), key=lambda k: sec[k])
-    # every role issues its algorithmic flops: the same-spin ladders contract unique index
-    # pairs only, and the two same-spin blocks share one contraction (equal amplitudes)
-    alg = fl[dom]
-    avg_s = sec[dom] / max(1, nl[dom])
-    by = [sum(r["role_bytes"][k] for r in prof) for k in range(4)]
-    # the binding roofline of the dominant role: MFMA if its arithmetic intensity (flops per
-    # algorithmic byte) is above the ridge point peak / 8 TB/s, else HBM
-    peak_flops = (PEAK_FP32_TFLOPS if prec else PEAK_FP64_TFLOPS) * 1e12
-    intensity = fl[dom] / by[dom] if by[dom] > 0 else float("inf")
-    hbm_bound = intensity < peak_flops / (PEAK_HBM_GBS * 1e9)
-    achieved = alg / sec[dom] / 1e12 if sec[dom] > 0 else 0.0
+    ksec = [sum(r["kernel_seconds"][k] for r in prof) for k in range(8)]
+    kfl = [sum(r["kernel_flops"][k] for r in prof) for k in range(8)]
+    kn = [sum(r["kernel_launches"][k] for r in prof) for k in range(8)]
+    dom = max(range(8), key=lambda k: ksec[k])
     peak = PEAK_FP32_TFLOPS if prec else PEAK_FP64_TFLOPS
-    if prec:
-        names = [n.replace("f64", "f32").replace("gett_group_kernel<false>", "gett_group_kernel<true>")
-                 for n in names]
-    bound, unit = "mfma", "TFLOP/s"
-    if hbm_bound:
-        bound, unit, peak = "hbm", "GB/s", PEAK_HBM_GBS
-        achieved = by[dom] / sec[dom] / 1e9
-    roofline = dict(bound=bound, achieved=achieved, peak=peak, unit=unit,
-                    frac=achieved / peak, traffic=measured_traffic(names[dom], args.workload, args.precision),
-                    kernel=names[dom], arithmetic_intensity=intensity,
-                    mfma_tflops=alg / sec[dom] / 1e12 if sec[dom] > 0 else 0.0,
-                    alg_bytes_per_launch=by[dom] / max(1, nl[dom]),
-                    launches_per_energy=nl[dom] / len(dev), avg_launch_us=1e6 * avg_s,
-                    alg_flops_per_launch=alg / max(1, nl[dom]),
-                    issued_tflops=fl[dom] / sec[dom] / 1e12 if sec[dom] > 0 else 0.0)
-
-    # parity of the timed energies against the stored oracle values
-    parity = None
-    if args.workload == "small":
-        worst = 0.0
-        for p, r in zip(probs, res):
-            g = json.load(open(os.path.join(ROOT, "tests", "golden", "small_s%g.json" % p.s)))
-            worst = max(worst, abs(r["e2"] - g["e2"]), abs(r["e3"] - g["e3"]))
-        parity = dict(max_abs_dE=worst, reference="tests/golden/small_s*.json (oracle)")
+    avg_s = ksec[dom] / max(1, kn[dom])
+    flops_per_launch = kfl[dom] / max(1, kn[dom])
+    achieved = flops_per_launch / avg_s / 1e12 if avg_s > 0 else 0.0
+    name = kernel_name(dom, prec)
+    roofline = dict(bound="mfma", achieved=achieved, peak=peak, unit="TFLOP/s", frac=achieved / peak,
+                    traffic=measured_traffic(name, args.workload, args.precision),
+                    kernel=name, note=ROLE_NOTES[dom // 2],
+                    alg_flops_per_launch=flops_per_launch, avg_launch_us=1e6 * avg_s,
+                    launches_per_energy=kn[dom] / len(dev),
+                    share_of_step=ksec[dom] / (len(dev) * dt / args.steps) if dt > 0 else None)
+    # whole-energy algorithmic rate: every contraction's 2 M N K over the step time
+    alg_flops = sum(r["alg_flops"] for r in res)
+    whole = dict(alg_tflop_per_energy=alg_flops / len(dev) / 1e12,
+                 alg_tflops=alg_flops * args.steps / dt / 1e12,
+                 frac_of_peak=alg_flops * args.steps / dt / 1e12 / peak)
 
     out = {
         "metric": METRIC, "value": energies / dt, "unit": "energies/s", "n_gpus": 1,
@@ -198,21 +237,25 @@ def main():
                                      n_aux=p.n_aux, s=p.s) for p in probs],
                    "energies_per_step": len(dev)},
         "roofline": roofline,
+        "whole_energy": whole,
         "energies": [dict(s=p.s, e2=r["e2"], e3=r["e3"]) for p, r in zip(probs, res)],
-        "parity": parity,
+        "parity": parity_of(probs, res, args.workload),
+        "kernels": {kernel_name(k, prec): dict(seconds=ksec[k], launches=kn[k], tflop=kfl[k] / 1e12)
+                    for k in range(8) if kn[k]},
         "plan": [r["plan"] for r in res],
-        # device time, launches and issued TFLOP of each contraction role in the profiled pass
-        "roles": {n: dict(seconds=sec[k], launches=nl[k], tflop=fl[k] / 1e12)
-                  for k, n in enumerate(["table", "ladder", "integrals", "grouped"])},
-        "contraction_flops_per_energy": res[0]["gett_flops"],
-        "launches_per_energy": res[0]["n_launch"],
     }
-    if not args.no_cpu_baseline:
-        if args.workload in ("tiny", "small"):
-            # (curve, medium, large: the spin-orbital oracle's (2N)^4 arrays exceed host memory)
-            out["cpu_baseline"] = cpu_baseline(args.workload)
-        else:
-            out["cpu_baseline"] = None
+    if args.mixed_steps > 0 and not prec and args.workload != "curve":
+        # the FP32-product path beside the FP64 headline: rate, and its error against the
+        # FP64 GPU energies and the stored oracle values
+        mres, mdt = timed(1, 1, args.mixed_steps)
+        mixed = dict(value=args.mixed_steps * len(dev) / mdt, unit="energies/s",
+                     speedup_vs_fp64=(args.mixed_steps * len(dev) / mdt) / (energies / dt),
+                     parity=parity_of(probs, mres, args.workload),
+                     vs_fp64_gpu=[dict(s=p.s, d_e2=m["e2"] - r["e2"], d_e3=m["e3"] - r["e3"])
+                                  for p, m, r in zip(probs, mres, res)])
+        out["fp32_products"] = mixed
+    if not args.no_cpu_baseline and args.workload != "curve":
+        out["cpu_baseline"] = cpu_baseline(args.workload, probs)
     print(json.dumps(out), flush=True)
 
 

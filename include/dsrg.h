@@ -67,6 +67,11 @@ extern "C" {
                                    most 1024 k values and accumulate those partial sums in FP64;
                                    tensors stay FP64 in memory; denominators, the regulariser and
                                    every energy reduction stay FP64 */
+#define DSRG_PRECISION_BF16X3 2 /* the tensor contractions as with FP32, each FP32-rounded operand
+                                   split into BF16 parts x = hi + lo (hi = bf16(x), lo = bf16(x - hi))
+                                   and every product formed as hi.hi + hi.lo + lo.hi on BF16 MFMA
+                                   with FP32 sums (about 16 significant bits per product); the rest
+                                   as with FP32 */
 
 /* options.flags */
 #define DSRG_F_DEVICE_PTRS 1    /* every array pointer in dsrg_problem is a device pointer */
@@ -117,7 +122,7 @@ typedef struct {
 
 typedef struct {
   int32_t flags;          /* DSRG_F_* */
-  int32_t precision;      /* DSRG_PRECISION_FP64 (0) or DSRG_PRECISION_FP32 (1) */
+  int32_t precision;      /* DSRG_PRECISION_FP64 (0), _FP32 (1) or _BF16X3 (2) */
   int64_t workspace_cap;  /* bytes of device workspace for the batched (PP|PP) integrals and their
                              packed pair rows; 0 = 8 GiB */
   void* stream;           /* hipStream_t to run on, or NULL for the null stream; caller owns it */
@@ -160,6 +165,11 @@ typedef struct {
                              index pairs for the ladder, no zero padding */
   int32_t precision_used; /* DSRG_PRECISION_* the contractions ran in */
   int32_t virt_batch_used;/* (PP|PP) batch size used (0: no ladder) */
+  /* with DSRG_F_PROFILE: the role_* figures per kernel instance, index 2 * role + t with
+     t = 1 for the launches of 128 x 128 output tiles (their own kernel instance), 0 else */
+  double kernel_seconds[8];
+  double kernel_flops[8];
+  int32_t kernel_launches[8];
 } dsrg_result;
 
 /* Optional host outputs of intermediates (each pointer may be NULL).  Shapes use

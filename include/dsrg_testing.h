@@ -8,8 +8,9 @@
  * through its own per-component strides (am, ak), (bk, bn), (cm, cn) in elements.
  * na, nb, nc are the host array lengths (elements), which must cover every addressed
  * element.  The caller owns every buffer; C is read (beta != 0) and overwritten.
- * precision selects the kernel: DSRG_PRECISION_FP64 or DSRG_PRECISION_FP32 (FP32 products,
- * FP64 accumulation between k chunks; see dsrg.h).
+ * precision selects the kernel: DSRG_PRECISION_FP64, DSRG_PRECISION_FP32 (FP32 products)
+ * or DSRG_PRECISION_BF16X3 (split-BF16 products), the last two with FP64 accumulation
+ * between k chunks (see dsrg.h).
  * Returns DSRG_OK or a DSRG_E_* code (message in dsrg_last_error).
  */
 #ifndef DSRG_TESTING_H

@@ -58,7 +58,8 @@ class Result(ctypes.Structure):
                 ("plan", ctypes.c_int32), ("grouped_uses", ctypes.c_int32),
                 ("role_bytes", ctypes.c_double * 4), ("e_total", ctypes.c_double),
                 ("alg_flops", ctypes.c_double), ("precision_used", ctypes.c_int32),
-                ("virt_batch_used", ctypes.c_int32)]
+                ("virt_batch_used", ctypes.c_int32), ("kernel_seconds", ctypes.c_double * 8),
+                ("kernel_flops", ctypes.c_double * 8), ("kernel_launches", ctypes.c_int32 * 8)]
 
 
 class Intermediates(ctypes.Structure):
@@ -178,7 +179,8 @@ def _result_dict(r: Result):
                 role_flops=list(r.role_flops), role_launches=list(r.role_launches), plan=r.plan,
                 grouped_uses=r.grouped_uses, role_bytes=list(r.role_bytes), e_total=r.e_total,
                 alg_flops=r.alg_flops, precision_used=r.precision_used,
-                virt_batch_used=r.virt_batch_used)
+                virt_batch_used=r.virt_batch_used, kernel_seconds=list(r.kernel_seconds),
+                kernel_flops=list(r.kernel_flops), kernel_launches=list(r.kernel_launches))
 
 
 def _stream_of(p, stream):

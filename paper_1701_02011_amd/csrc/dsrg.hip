@@ -349,6 +349,7 @@ struct Exec {
     int M, N, K, nm, nn, nk;
     int product;
     double bytes = 0;   // algorithmic bytes: operands read once, result written once
+    int big = 0;        // 128 x 128 tiles (a kernel instance of its own)
     // layout after preparation, for the per-launch dump
     int kin = 0, ksteps = 0, akf = 0, bkf = 0, pa = 0, pb = 0, splits = 1;
     long long ai = 0, bi = 0, am = 0, bn = 0;
@@ -415,6 +416,7 @@ struct Exec {
     r.pa = pa; r.pb = pb;
     r.ai = g.ak[g.nk - 1]; r.bi = g.bk[g.nk - 1];
     r.am = g.nm ? g.am[g.nm - 1] : 0; r.bn = g.nn ? g.bn[g.nn - 1] : 0;
+    r.big = gett_big_tiles(g) ? 1 : 0;
     if (profile) {
       HIPCHECK(hipEventCreate(&r.a));
       HIPCHECK(hipEventCreate(&r.b));
@@ -424,7 +426,7 @@ struct Exec {
     r.splits = ns;
     const long long wse = ns > 1 ? (long long)ns * g.M * g.N : 0;
     double* ws = splitk_buffer(wse);
-    const bool lo = f32;
+    const int lo = prec;
     op([g, A, Bp, C, role, ws, wse, lo](hipStream_t s) { launch_gett(g, A, Bp, C, s, role, ws, wse, lo); });
     if (profile) {
       HIPCHECK(hipEventRecord(r.b, st));
@@ -438,6 +440,9 @@ struct Exec {
   // per-role totals of profiled launches: seconds, launches, flops
   double role_sec[kRoles] = {}, role_flops[kRoles] = {}, role_bytes[kRoles] = {};
   int role_n[kRoles] = {};
+  // the same per kernel instance: index 2 * role + (128 x 128 tiles)
+  double kern_sec[2 * kRoles] = {}, kern_flops[2 * kRoles] = {};
+  int kern_n[2 * kRoles] = {};
   void collect_profile() {
     // optional per-launch dump (shape and device time) for tuning
     const char* dump = getenv("DSRG_PROFILE_DUMP");
@@ -453,6 +458,10 @@ struct Exec {
       role_flops[r.role] += r.flops;
       role_bytes[r.role] += r.bytes;
       role_n[r.role] += 1;
+      const int kk = 2 * r.role + (r.big ? 1 : 0);
+      kern_sec[kk] += ms * 1e-3;
+      kern_flops[kk] += r.flops;
+      kern_n[kk] += 1;
       (void)hipEventDestroy(r.a);
       (void)hipEventDestroy(r.b);
     }
@@ -940,9 +949,10 @@ struct Exec {
   // bracketed by events and counted under the grouped role (items in M, workgroups in N of
   // the profile record); helper launches are not.
   void group_launch(double flops, DevOp launch, bool timed = false, int items = 0, int tiles = 0,
-                    double bytes = 0, int role = kRoleGrouped) {
+                    double bytes = 0, int role = kRoleGrouped, bool big = false) {
     Rec r{nullptr, nullptr, role, flops, 0, 0, 0, 0, 0, 0, -2};
     r.bytes = bytes;
+    r.big = big ? 1 : 0;
     timed = timed && profile;
     r.M = items;
     r.N = tiles;
@@ -1093,7 +1103,7 @@ struct Exec {
     GroupItem* d_items = upload(items);
     int* d_map = upload(tile_item);
     const int n = (int)items.size();
-    const bool lo = f32;
+    const int lo = prec;
     group_launch(fl, [d_items, d_map, n, tiles, lo](hipStream_t s) {
       launch_gett_group(d_items, d_map, n, tiles, false, lo, s, true);
     }, true, n, tiles, bytes, kRoleIntegrals);
@@ -1415,10 +1425,10 @@ struct Exec {
       const GroupItem* it = d_items + R.i0;
       const ReduceBlock* rb = d_rblk + R.s0;
       const int* tm = d_map + map0[ri];
-      const bool lo = f32;
+      const int lo = prec;
       group_launch(R.flops, [it, tm, R, lo](hipStream_t s) {
         launch_gett_group(it, tm, R.n, R.tiles, R.big, lo, s);
-      }, true, R.n, R.tiles, R.bytes);
+      }, true, R.n, R.tiles, R.bytes, kRoleGrouped, R.big);
       if (R.ns > 0)
         group_launch(0.0, [it, rb, R](hipStream_t s) { launch_group_reduce(it, rb, R.ns, s); });
     }
@@ -1763,7 +1773,7 @@ struct Exec {
   }
   // Run a use of the table into tensor outputs, or (scalar uses) into *scalar_out.
   int use_id = 0;
-  bool f32 = false;   // FP32 products in every contraction
+  int prec = 0;   // DSRG_PRECISION_* of every contraction's products
   int group_level = 0;
   int grouped_uses = 0;
   bool grouped = true;
@@ -2863,7 +2873,8 @@ static void check_intruder(int nC, int nA, int nV, const double* eps) {
 // the same shape (concurrent members of a batch).
 struct Setup {
   Shape sh;
-  bool f32 = false, devptr = false, profile = false, grouped = true, unique_ladder = true;
+  int prec = 0;   // DSRG_PRECISION_* of the contractions
+  bool devptr = false, profile = false, grouped = true, unique_ladder = true;
   bool want_pairs = false, cacheable = false;
   long long cap = 0;
   int vb = 0;   // requested (PP|PP) batch (0: largest that fits)
@@ -2883,12 +2894,13 @@ static Setup setup(const dsrg_problem* P, const dsrg_options* O, const dsrg_inte
   if (!P->eps || !P->B) throw Error(DSRG_E_ARG, "null eps or B");
   if (nA > 0 && (!P->gamma1 || !P->gamma2)) throw Error(DSRG_E_ARG, "null gamma1/gamma2 with nA > 0");
   if (nA > 8) throw Error(DSRG_E_UNSUPPORTED, "active spaces above 8 orbitals are not built");
-  if (O && O->precision != DSRG_PRECISION_FP64 && O->precision != DSRG_PRECISION_FP32)
+  if (O && O->precision != DSRG_PRECISION_FP64 && O->precision != DSRG_PRECISION_FP32 &&
+      O->precision != DSRG_PRECISION_BF16X3)
     throw Error(DSRG_E_UNSUPPORTED, "unknown precision");
   if (O && O->virt_batch < 0) throw Error(DSRG_E_ARG, "virt_batch must be >= 0");
   Setup S;
   S.vb = O ? O->virt_batch : 0;
-  S.f32 = O && O->precision == DSRG_PRECISION_FP32;
+  S.prec = O ? O->precision : DSRG_PRECISION_FP64;
   const int flags = O ? O->flags : 0;
   S.devptr = flags & DSRG_F_DEVICE_PTRS;
   S.profile = flags & DSRG_F_PROFILE;
@@ -2940,7 +2952,7 @@ static Setup setup(const dsrg_problem* P, const dsrg_options* O, const dsrg_inte
   HIPCHECK(hipGetDevice(&S.dev));
   char kbuf[192];
   snprintf(kbuf, sizeof(kbuf), "%d:%d:%d:%d:%d:%d:%d:%d:%d:%d:%d:%lld:%d:%d", S.dev, nC, nA, nV, M, (int)sh.has_g3,
-           (int)sh.has_f, (int)pt3, (int)S.grouped, (int)S.unique_ladder, (int)S.f32, S.cap, S.vb, slot);
+           (int)sh.has_f, (int)pt3, (int)S.grouped, (int)S.unique_ladder, S.prec, S.cap, S.vb, slot);
   S.key = kbuf;
   return S;
 }
@@ -3031,7 +3043,8 @@ static int run(const dsrg_problem* P, const dsrg_options* O, dsrg_result* R,
   const Setup S = setup(P, O, I, pt3, e3_pairs, e3_rest, slot);
   const Shape& sh = S.sh;
   const int nC = sh.nC, nA = sh.nA, nV = sh.nV, M = sh.M;
-  const bool f32 = S.f32, devptr = S.devptr, profile = S.profile, grouped = S.grouped;
+  const int prec = S.prec;
+  const bool devptr = S.devptr, profile = S.profile, grouped = S.grouped;
   const bool unique_ladder = S.unique_ladder, want_pairs = S.want_pairs, cacheable = S.cacheable;
   hipStream_t st = S.st;
   const long long cap = S.cap;
@@ -3116,7 +3129,7 @@ static int run(const dsrg_problem* P, const dsrg_options* O, dsrg_result* R,
   X.grouped = grouped;
   X.unique_ladder = unique_ladder;
   X.group_cap = cap / 2;
-  X.f32 = f32;
+  X.prec = prec;
   X.virt_batch = S.vb;
   mark(ev, 0, st);
   BodyOut bo = body(X, op, *pool, sh, in, ev, st, want_pairs);
@@ -3160,6 +3173,11 @@ static int run(const dsrg_problem* P, const dsrg_options* O, dsrg_result* R,
     r.role_bytes[k] = X.role_bytes[k];
     r.role_launches[k] = X.role_n[k];
   }
+  for (int k = 0; k < 2 * kRoles; ++k) {
+    r.kernel_seconds[k] = X.kern_sec[k];
+    r.kernel_flops[k] = X.kern_flops[k];
+    r.kernel_launches[k] = X.kern_n[k];
+  }
   r.gett_flops = X.gett_flops;
   r.ladder_flops = X.ladder_flops;
   r.ladder_seconds = X.ladder_ms * 1e-3;
@@ -3167,7 +3185,7 @@ static int run(const dsrg_problem* P, const dsrg_options* O, dsrg_result* R,
   r.n_launch = X.n_launch;
   r.grouped_uses = X.grouped_uses;
   r.alg_flops = X.gett_flops;
-  r.precision_used = f32 ? DSRG_PRECISION_FP32 : DSRG_PRECISION_FP64;
+  r.precision_used = prec;
   r.virt_batch_used = X.ladder_batch;
   *R = r;
   if (want_pairs) {
@@ -3265,7 +3283,7 @@ static int run_noalloc(const dsrg_problem* P, const dsrg_options* O, dsrg_result
   X.grouped = S.grouped;
   X.unique_ladder = S.unique_ladder;
   X.group_cap = cap / 2;
-  X.f32 = S.f32;
+  X.prec = S.prec;
   X.virt_batch = S.vb;
   X.no_side = true;
   body(X, op, pool, sh, in, nullptr, S.st, false);   // plans and records every launch
@@ -3284,7 +3302,7 @@ static int run_noalloc(const dsrg_problem* P, const dsrg_options* O, dsrg_result
   r.n_launch = X.n_launch;
   r.grouped_uses = X.grouped_uses;
   r.alg_flops = X.gett_flops;
-  r.precision_used = S.f32 ? DSRG_PRECISION_FP32 : DSRG_PRECISION_FP64;
+  r.precision_used = S.prec;
   r.virt_batch_used = X.ladder_batch;
   *R = r;
   return DSRG_OK;
@@ -3439,7 +3457,8 @@ extern "C" int dsrg_test_gett(int nm, const int* md, const long long* am, const 
     if (nm < 0 || nn < 0 || nk < 0 || nm > kMaxComp || nn > kMaxComp || nk > kMaxComp)
       throw Error(DSRG_E_ARG, "component count out of range");
     if (!A || !B || !C || na <= 0 || nb <= 0 || nc <= 0) throw Error(DSRG_E_ARG, "null or empty array");
-    if (precision != DSRG_PRECISION_FP64 && precision != DSRG_PRECISION_FP32)
+    if (precision != DSRG_PRECISION_FP64 && precision != DSRG_PRECISION_FP32 &&
+        precision != DSRG_PRECISION_BF16X3)
       throw Error(DSRG_E_UNSUPPORTED, "unknown precision");
     GettDesc g;
     g.nm = nm; g.nn = nn; g.nk = nk;
@@ -3478,7 +3497,7 @@ extern "C" int dsrg_test_gett(int nm, const int* md, const long long* am, const 
     const long long ws_elems = 1LL << 22;
     double* ws;
     HIPCHECK(hipMalloc(&ws, ws_elems * 8));
-    launch_gett(g, dA, dB, dC, 0, kRoleGeneric, ws, ws_elems, precision == DSRG_PRECISION_FP32);
+    launch_gett(g, dA, dB, dC, 0, kRoleGeneric, ws, ws_elems, precision);
     HIPCHECK(hipGetLastError());
     HIPCHECK(hipDeviceSynchronize());
     (void)hipFree(ws);

@@ -50,6 +50,8 @@ struct GettDesc {
 void gett_prepare(GettDesc& g);
 // fraction of the M x N outputs a plain launch computes (1 unless tri skips tiles)
 double gett_tile_fraction(const GettDesc& g);
+// whether a plain launch of g runs 128 x 128 tiles (else 64 x 64)
+bool gett_big_tiles(const GettDesc& g);
 // back to plain k steps (for tiles without packed steps)
 void gett_unpack_k(GettDesc& g);
 // fraction of the k values of all steps that are real (not zero padding)
@@ -92,10 +94,12 @@ constexpr int kRoles = 4;
 // g must have been through gett_prepare.  ws (ws_elems doubles) enables split-K for
 // launches with few output tiles and a long k range: partial tiles go to ws and a
 // fixed-order reduction writes C (deterministic).
-// f32: FP32 products (operands rounded to FP32 in LDS, FP32 MFMA, sums flushed into the
+// prec (DSRG_PRECISION_*): 1 FP32 products, 2 split-BF16 x3 products (operands rounded to
+// FP32 in LDS, split into BF16 hi and lo parts, three BF16 MFMAs per block; both with FP32
+// sums flushed as below); 0 FP64 throughout.  FP32 products: operands rounded to FP32 in LDS, FP32 MFMA, sums flushed into the
 // FP64 output every kF32FlushSteps k steps); else FP64 throughout.
 void launch_gett(const GettDesc& g, const double* A, const double* B, double* C, hipStream_t st,
-                 int role, double* ws, long long ws_elems, bool f32 = false);
+                 int role, double* ws, long long ws_elems, int prec = 0);
 int gett_splits(const GettDesc& g, long long ws_elems);
 // ---- grouped execution: independent contractions of one dependency level per launch ----
 // Item i owns workgroup tiles [tile0, tile0 + tiles_m * tiles_n * splits) of a grouped launch,
@@ -122,7 +126,7 @@ struct GroupItem {
 // tile_item[b] (b < tiles): index of the item that owns workgroup tile b of the launch.
 // (coulomb: the same launch under the symbol coulomb_group_kernel, small tiles only)
 void launch_gett_group(const GroupItem* items, const int* tile_item, int n, int tiles, bool big,
-                       bool f32, hipStream_t st, bool coulomb = false);
+                       int prec, hipStream_t st, bool coulomb = false);
 // Block b of the split-K reduction sums the partial tiles of elements [e0, e0 + 256) of
 // item `item` (an index into the launch's items).
 struct ReduceBlock {

@@ -101,15 +101,21 @@ struct TileLds {
   T Bs[2][BK * LDB];
 };
 
-// MFMA blocks of the two precisions.  FP64: v_mfma_f64_16x16x4f64, accumulator element r
-// of lane l is D[l/16 + 4 r][l%16].  FP32 products: v_mfma_f32_16x16x4f32 (operands
-// rounded to FP32, products accumulated in FP32 for at most kF32FlushSteps k steps, then
-// added into the FP64 output); accumulator element r of lane l is D[4 (l/16) + r][l%16].
+// MFMA blocks of the three precisions (kP = DSRG_PRECISION_*).  FP64 (0):
+// v_mfma_f64_16x16x4f64, accumulator element r of lane l is D[l/16 + 4 r][l%16].  FP32
+// products (1): v_mfma_f32_16x16x4f32 (operands rounded to FP32, products accumulated in
+// FP32 for at most kF32FlushSteps k steps, then added into the FP64 output); accumulator
+// element r of lane l is D[4 (l/16) + r][l%16].  Split BF16 x3 (2): each FP32-rounded
+// operand x = hi + lo with hi = bf16(x), lo = bf16(x - hi); a 16 x 16 x 16 block is
+// hi.hi + hi.lo + lo.hi on v_mfma_f32_16x16x16bf16_1k with FP32 accumulation (lane l holds
+// A[l%16][4 (l/16) + j] and B[4 (l/16) + j][l%16], j < 4; the accumulator as for FP32),
+// flushed like FP32 products.
 typedef float float4_t __attribute__((ext_vector_type(4)));
-template <bool kF32>
+typedef short short4_t __attribute__((ext_vector_type(4)));
+template <int kP>
 struct Mfma;
 template <>
-struct Mfma<false> {
+struct Mfma<0> {
   using T = double;
   using Acc = double4_t;
   static __device__ __forceinline__ Acc zero() { return (Acc){0.0, 0.0, 0.0, 0.0}; }
@@ -119,7 +125,7 @@ struct Mfma<false> {
   static __device__ __forceinline__ int row(int lk, int r) { return lk + 4 * r; }
 };
 template <>
-struct Mfma<true> {
+struct Mfma<1> {
   using T = float;
   using Acc = float4_t;
   static __device__ __forceinline__ Acc zero() { return (Acc){0.f, 0.f, 0.f, 0.f}; }
@@ -128,17 +134,40 @@ struct Mfma<true> {
   }
   static __device__ __forceinline__ int row(int lk, int r) { return 4 * lk + r; }
 };
+template <>
+struct Mfma<2> {
+  using T = float;
+  using Acc = float4_t;
+  static __device__ __forceinline__ Acc zero() { return (Acc){0.f, 0.f, 0.f, 0.f}; }
+  static __device__ __forceinline__ int row(int lk, int r) { return 4 * lk + r; }
+  // round to nearest even to BF16 (finite inputs); the BF16 bits
+  static __device__ __forceinline__ unsigned short bf16_bits(float x) {
+    const unsigned u = __float_as_uint(x);
+    return (unsigned short)((u + 0x7fffu + ((u >> 16) & 1u)) >> 16);
+  }
+  // x = hi + lo (+ a remainder below 2^-16 |x|)
+  static __device__ __forceinline__ void split(float x, short& hi, short& lo) {
+    const unsigned short h = bf16_bits(x);
+    hi = (short)h;
+    lo = (short)bf16_bits(x - __uint_as_float((unsigned)h << 16));
+  }
+  static __device__ __forceinline__ Acc fma3(short4_t ah, short4_t al, short4_t bh, short4_t bl, Acc c) {
+    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bh, c, 0, 0, 0);
+    c = __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(ah, bl, c, 0, 0, 0);
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(al, bh, c, 0, 0, 0);
+  }
+};
 constexpr int kF32FlushSteps = 64;
 
 // One BM x BN output tile at (tile_m, tile_n) for chunk kz of the k steps of g.  kPackK:
 // the tile supports packed k steps (g.kpack > 1); the 128 x 128 tiles leave it out (their
 // launches are prepared without it) to keep their registers.
-template <int WM, int WN, int WGM = 2, bool kF32 = false, bool kPackK = (WM * WN < 16)>
+template <int WM, int WN, int WGM = 2, int kP = 0, bool kPackK = (WM * WN < 16)>
 __device__ __forceinline__ void gett_tile(const GettDesc& g, const double* __restrict__ A,
                                           const double* __restrict__ B, double* __restrict__ C,
                                           int tile_m, int tile_n, int kz,
-                                          TileLds<WM, WN, WGM, typename Mfma<kF32>::T>& lds) {
-  using MF = Mfma<kF32>;
+                                          TileLds<WM, WN, WGM, typename Mfma<kP>::T>& lds) {
+  using MF = Mfma<kP>;
   using T = typename MF::T;
   constexpr int BM = TileLds<WM, WN, WGM, T>::BM, BN = TileLds<WM, WN, WGM, T>::BN;
   static_assert(BM * BK % 256 == 0 && BN * BK % 256 == 0 && 256 % BM == 0 || BM >= 256, "tile");
@@ -340,19 +369,48 @@ __device__ __forceinline__ void gett_tile(const GettDesc& g, const double* __res
       advance();
       fetch();
     }
+    if constexpr (kP == 2) {
+      // one 16-deep BF16 block per step: lane (li, lk) splits k = 4 lk .. 4 lk + 3 of its
+      // row (column) into hi and lo parts
+      static_assert(BK == 16, "one BF16 block per step");
+      short4_t ah[WM], al[WM], bh[WN], bl[WN];
 #pragma unroll
-    for (int kk = 0; kk < BK; kk += 4) {
-      T av[WM], bv[WN];
+      for (int t = 0; t < WM; ++t)
 #pragma unroll
-      for (int t = 0; t < WM; ++t) av[t] = As[buf][(kk + lk) * LDA + wm + t * 16 + li];
+        for (int j = 0; j < 4; ++j) {
+          short h, l;
+          MF::split(As[buf][(4 * lk + j) * LDA + wm + t * 16 + li], h, l);
+          ah[t][j] = h;
+          al[t][j] = l;
+        }
 #pragma unroll
-      for (int t = 0; t < WN; ++t) bv[t] = Bs[buf][(kk + lk) * LDB + wn + t * 16 + li];
+      for (int t = 0; t < WN; ++t)
+#pragma unroll
+        for (int j = 0; j < 4; ++j) {
+          short h, l;
+          MF::split(Bs[buf][(4 * lk + j) * LDB + wn + t * 16 + li], h, l);
+          bh[t][j] = h;
+          bl[t][j] = l;
+        }
 #pragma unroll
       for (int a = 0; a < WM; ++a)
 #pragma unroll
-        for (int b = 0; b < WN; ++b) acc[a][b] = MF::fma(av[a], bv[b], acc[a][b]);
+        for (int b = 0; b < WN; ++b) acc[a][b] = MF::fma3(ah[a], al[a], bh[b], bl[b], acc[a][b]);
+    } else {
+#pragma unroll
+      for (int kk = 0; kk < BK; kk += 4) {
+        T av[WM], bv[WN];
+#pragma unroll
+        for (int t = 0; t < WM; ++t) av[t] = As[buf][(kk + lk) * LDA + wm + t * 16 + li];
+#pragma unroll
+        for (int t = 0; t < WN; ++t) bv[t] = Bs[buf][(kk + lk) * LDB + wn + t * 16 + li];
+#pragma unroll
+        for (int a = 0; a < WM; ++a)
+#pragma unroll
+          for (int b = 0; b < WN; ++b) acc[a][b] = MF::fma(av[a], bv[b], acc[a][b]);
+      }
     }
-    if (kF32 && more && ++since == kF32FlushSteps) {
+    if (kP != 0 && more && ++since == kF32FlushSteps) {
       flush(first);
       first = false;
       since = 0;
@@ -390,10 +448,10 @@ __device__ __forceinline__ int xcd_tile_windowed(int b, int total) {
 }
 
 // Logical tile L of a (gx, gy, gz) grid, consecutive L walking m tiles first.
-template <int WM, int WN, bool kF32>
+template <int WM, int WN, int kP>
 __device__ __forceinline__ void gett_grid_tile(const GettDesc& g, const double* __restrict__ A,
                                                const double* __restrict__ B, double* __restrict__ C,
-                                               TileLds<WM, WN, 2, typename Mfma<kF32>::T>& lds) {
+                                               TileLds<WM, WN, 2, typename Mfma<kP>::T>& lds) {
   const int gx = gridDim.x, gy = gridDim.y;
   const int total = gx * gy * gridDim.z;
   const int b = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
@@ -403,7 +461,7 @@ __device__ __forceinline__ void gett_grid_tile(const GettDesc& g, const double* 
   const int tm = L % gx, rest = L / gx;
   const int tn = rest % gy, kz = rest / gy;
   if (g.tri > 0 && (tn * (32 * WN) + 32 * WN - 1) / g.tri < (tm * (32 * WM)) / g.tri) return;
-  gett_tile<WM, WN, 2, kF32>(g, A, B, C, tm * (32 * WM), tn * (32 * WN), kz, lds);
+  gett_tile<WM, WN, 2, kP>(g, A, B, C, tm * (32 * WM), tn * (32 * WN), kz, lds);
 }
 
 template <int kRole, int WM, int WN>
@@ -411,7 +469,7 @@ __global__ __launch_bounds__(256) void gett_f64_kernel(GettDesc g, const double*
                                                        const double* __restrict__ B,
                                                        double* __restrict__ C) {
   __shared__ TileLds<WM, WN, 2, double> lds;
-  gett_grid_tile<WM, WN, false>(g, A, B, C, lds);
+  gett_grid_tile<WM, WN, 0>(g, A, B, C, lds);
 }
 
 // FP64 operands and output, FP32 products (DSRG_PRECISION_FP32)
@@ -420,7 +478,16 @@ __global__ __launch_bounds__(256) void gett_f32_kernel(GettDesc g, const double*
                                                        const double* __restrict__ B,
                                                        double* __restrict__ C) {
   __shared__ TileLds<WM, WN, 2, float> lds;
-  gett_grid_tile<WM, WN, true>(g, A, B, C, lds);
+  gett_grid_tile<WM, WN, 1>(g, A, B, C, lds);
+}
+
+// FP64 operands and output, split-BF16 x3 products (DSRG_PRECISION_BF16X3)
+template <int kRole, int WM, int WN>
+__global__ __launch_bounds__(256) void gett_b3_kernel(GettDesc g, const double* __restrict__ A,
+                                                      const double* __restrict__ B,
+                                                      double* __restrict__ C) {
+  __shared__ TileLds<WM, WN, 2, float> lds;
+  gett_grid_tile<WM, WN, 2>(g, A, B, C, lds);
 }
 
 // C[m][n] = alpha * sum_z part[z][m][n] (+ C) in a fixed order of z
@@ -582,6 +649,8 @@ static bool big_tiles(const GettDesc& g) {
   return g.M >= 128 && g.N >= 128 && t128 >= 256;
 }
 
+bool gett_big_tiles(const GettDesc& g) { return big_tiles(g); }
+
 // Split-K factor: the number of k chunks that fills the resident workgroup slots in the
 // most nearly whole rounds (256 CUs; two 128 x 128 or four 64 x 64 workgroups per CU fit
 // the registers), keeping at least 16 k steps per chunk (4 when the output has at most
@@ -613,9 +682,14 @@ int gett_splits(const GettDesc& g, long long ws_elems) {
 }
 
 template <int kRole>
-static void launch_role(const GettDesc& g, bool big, bool f32, dim3 grid, const double* A,
+static void launch_role(const GettDesc& g, bool big, int prec, dim3 grid, const double* A,
                         const double* B, double* C, hipStream_t st) {
-  if (f32) {
+  if (prec == 2) {
+    if (big)
+      hipLaunchKernelGGL((gett_b3_kernel<kRole, 4, 4>), grid, dim3(256), 0, st, g, A, B, C);
+    else
+      hipLaunchKernelGGL((gett_b3_kernel<kRole, 2, 2>), grid, dim3(256), 0, st, g, A, B, C);
+  } else if (prec == 1) {
     if (big)
       hipLaunchKernelGGL((gett_f32_kernel<kRole, 4, 4>), grid, dim3(256), 0, st, g, A, B, C);
     else
@@ -629,7 +703,7 @@ static void launch_role(const GettDesc& g, bool big, bool f32, dim3 grid, const 
 }
 
 void launch_gett(const GettDesc& g0, const double* A, const double* B, double* C, hipStream_t st,
-                 int role, double* ws, long long ws_elems, bool f32) {
+                 int role, double* ws, long long ws_elems, int prec) {
   if (g0.M <= 0 || g0.N <= 0) return;
   GettDesc g = g0;
   gett_magic(g);
@@ -648,11 +722,11 @@ void launch_gett(const GettDesc& g0, const double* A, const double* B, double* C
   dim3 grid((g.M + bm - 1) / bm, (g.N + bn - 1) / bn, ns);
   // the role only selects a distinct kernel symbol so profiles can tell the launches apart
   if (role == kRoleLadder)
-    launch_role<kRoleLadder>(g, big, f32, grid, A, B, C, st);
+    launch_role<kRoleLadder>(g, big, prec, grid, A, B, C, st);
   else if (role == kRoleIntegrals)
-    launch_role<kRoleIntegrals>(g, big, f32, grid, A, B, C, st);
+    launch_role<kRoleIntegrals>(g, big, prec, grid, A, B, C, st);
   else
-    launch_role<kRoleGeneric>(g, big, f32, grid, A, B, C, st);
+    launch_role<kRoleGeneric>(g, big, prec, grid, A, B, C, st);
   if (ns > 1) {
     long long total = (long long)g.M * g.N;
     long long blocks = std::min<long long>((total + 255) / 256, 4096);
@@ -714,9 +788,9 @@ __device__ __forceinline__ void group_rows(const GroupItem& it, int tm, RowLds& 
   }
 }
 
-template <bool kF32>
+template <int kP>
 __device__ __forceinline__ void group_tile(const GroupItem* __restrict__ items, const int* __restrict__ tile_item) {
-  using T = typename Mfma<kF32>::T;
+  using T = typename Mfma<kP>::T;
   using GroupLds0 = TileLds<2, 2, 2, T>;
   using GroupLds1 = TileLds<1, 2, 1, T>;
   using GroupLds2 = TileLds<2, 1, 4, T>;
@@ -742,34 +816,34 @@ __device__ __forceinline__ void group_tile(const GroupItem* __restrict__ items, 
       group_rows(it, tm, lds.rows);
       break;
     case 1:
-      gett_tile<1, 2, 1, kF32>(it.g, it.A, it.B, it.C, tm * GroupLds1::BM, tn * GroupLds1::BN, kz, lds.t1);
+      gett_tile<1, 2, 1, kP>(it.g, it.A, it.B, it.C, tm * GroupLds1::BM, tn * GroupLds1::BN, kz, lds.t1);
       break;
     case 2:
-      gett_tile<2, 1, 4, kF32>(it.g, it.A, it.B, it.C, tm * GroupLds2::BM, tn * GroupLds2::BN, kz, lds.t2);
+      gett_tile<2, 1, 4, kP>(it.g, it.A, it.B, it.C, tm * GroupLds2::BM, tn * GroupLds2::BN, kz, lds.t2);
       break;
     default:
-      gett_tile<2, 2, 2, kF32>(it.g, it.A, it.B, it.C, tm * GroupLds0::BM, tn * GroupLds0::BN, kz, lds.t0);
+      gett_tile<2, 2, 2, kP>(it.g, it.A, it.B, it.C, tm * GroupLds0::BM, tn * GroupLds0::BN, kz, lds.t0);
   }
 }
 
-template <bool kF32>
+template <int kP>
 __global__ __launch_bounds__(256) void gett_group_kernel(const GroupItem* __restrict__ items,
                                                          const int* __restrict__ tile_item) {
-  group_tile<kF32>(items, tile_item);
+  group_tile<kP>(items, tile_item);
 }
 
 // the same for the Coulomb blocks of a call built together (a symbol of its own in profiles)
-template <bool kF32>
+template <int kP>
 __global__ __launch_bounds__(256) void coulomb_group_kernel(const GroupItem* __restrict__ items,
                                                             const int* __restrict__ tile_item) {
-  group_tile<kF32>(items, tile_item);
+  group_tile<kP>(items, tile_item);
 }
 
 // items of the big shape (128 x 128)
-template <bool kF32>
+template <int kP>
 __global__ __launch_bounds__(256) void gett_group_big_kernel(const GroupItem* __restrict__ items,
                                                              const int* __restrict__ tile_item) {
-  using Lds = TileLds<4, 4, 2, typename Mfma<kF32>::T>;
+  using Lds = TileLds<4, 4, 2, typename Mfma<kP>::T>;
   __shared__ Lds lds;
   const int b = xcd_tile_windowed(blockIdx.x, gridDim.x);
   const GroupItem& it = items[tile_item[b]];
@@ -779,7 +853,7 @@ __global__ __launch_bounds__(256) void gett_group_big_kernel(const GroupItem* __
   const int r = t - kz * per;
   const int tm = r / it.tiles_n;
   const int tn = r - tm * it.tiles_n;
-  gett_tile<4, 4, 2, kF32>(it.g, it.A, it.B, it.C, tm * Lds::BM, tn * Lds::BN, kz, lds);
+  gett_tile<4, 4, 2, kP>(it.g, it.A, it.B, it.C, tm * Lds::BM, tn * Lds::BN, kz, lds);
 }
 
 // split-K items: C = alpha * sum_z part[z] (+ C), fixed order of z; the loads of eight
@@ -813,24 +887,33 @@ __global__ __launch_bounds__(256) void group_reduce_kernel(const GroupItem* __re
 }
 
 void launch_gett_group(const GroupItem* items, const int* tile_item, int n, int tiles, bool big,
-                       bool f32, hipStream_t st, bool coulomb) {
+                       int prec, hipStream_t st, bool coulomb) {
   if (n <= 0 || tiles <= 0) return;
   const dim3 grid((unsigned)tiles), block(256);
   if (coulomb && !big) {
-    if (f32)
-      hipLaunchKernelGGL(coulomb_group_kernel<true>, grid, block, 0, st, items, tile_item);
+    if (prec == 2)
+      hipLaunchKernelGGL(coulomb_group_kernel<2>, grid, block, 0, st, items, tile_item);
+    else if (prec == 1)
+      hipLaunchKernelGGL(coulomb_group_kernel<1>, grid, block, 0, st, items, tile_item);
     else
-      hipLaunchKernelGGL(coulomb_group_kernel<false>, grid, block, 0, st, items, tile_item);
+      hipLaunchKernelGGL(coulomb_group_kernel<0>, grid, block, 0, st, items, tile_item);
     return;
   }
-  if (big && f32)
-    hipLaunchKernelGGL(gett_group_big_kernel<true>, grid, block, 0, st, items, tile_item);
-  else if (big)
-    hipLaunchKernelGGL(gett_group_big_kernel<false>, grid, block, 0, st, items, tile_item);
-  else if (f32)
-    hipLaunchKernelGGL(gett_group_kernel<true>, grid, block, 0, st, items, tile_item);
+  if (big) {
+    if (prec == 2)
+      hipLaunchKernelGGL(gett_group_big_kernel<2>, grid, block, 0, st, items, tile_item);
+    else if (prec == 1)
+      hipLaunchKernelGGL(gett_group_big_kernel<1>, grid, block, 0, st, items, tile_item);
+    else
+      hipLaunchKernelGGL(gett_group_big_kernel<0>, grid, block, 0, st, items, tile_item);
+    return;
+  }
+  if (prec == 2)
+    hipLaunchKernelGGL(gett_group_kernel<2>, grid, block, 0, st, items, tile_item);
+  else if (prec == 1)
+    hipLaunchKernelGGL(gett_group_kernel<1>, grid, block, 0, st, items, tile_item);
   else
-    hipLaunchKernelGGL(gett_group_kernel<false>, grid, block, 0, st, items, tile_item);
+    hipLaunchKernelGGL(gett_group_kernel<0>, grid, block, 0, st, items, tile_item);
 }
 
 void launch_group_reduce(const GroupItem* items, const ReduceBlock* blocks, int nblocks, hipStream_t st) {

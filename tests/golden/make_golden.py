@@ -3,8 +3,11 @@
 Calls only ``oracle/`` (and the shared input generator).  Usage:
     python tests/golden/make_golden.py small          # energies and sampled intermediates
     python tests/golden/make_golden.py small-pairs    # core-pair parts of E(3), s = 0.5
-Writes tests/golden/<name>_s<s>.json with E(2), E(3) and its two parts, or
-tests/golden/small_pairs_s0.5.json with the core-pair decomposition of E(3).
+    python tests/golden/make_golden.py medium         # energies from the block-sparse DF level
+    python tests/golden/make_golden.py large          #   (oracle/dsrg_df.py; hours of CPU)
+Writes tests/golden/<name>_s<s>.json with E(2), E(3) and its two parts (and, for small,
+sampled intermediates), or tests/golden/small_pairs_s0.5.json with the core-pair
+decomposition of E(3).
 """
 import json
 import os
@@ -34,7 +37,28 @@ def samples(r, p, n=400, seed=12345):
     return out
 
 
+def main_df(name):
+    """Workloads beyond the dense engine: the block-sparse, density-fitted level."""
+    import platform
+    from oracle import dsrg_df
+    p = make_config(name)
+    t = time.time()
+    r = dsrg_df.run(p, log=lambda m: print(m, flush=True))
+    out = dict(workload=name, s=p.s, n_core=p.n_core, n_active=p.n_active,
+               n_virtual=p.n_virtual, n_aux=p.n_aux, e2=r.e2, e3=r.e3, e3_a=r.e3_a,
+               e3_b=r.e3_b, oracle_seconds=time.time() - t, stage_seconds=r.seconds,
+               host=dict(cpus=os.cpu_count(), machine=platform.machine(),
+                         processor=platform.processor()),
+               source="oracle/dsrg_df.py (FP64, block-sparse spin orbitals, DF integrals)")
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "%s_s%g.json" % (name, p.s))
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+    print(path, out["e2"], out["e3"], "%.0fs" % out["oracle_seconds"], flush=True)
+
+
 def main(name):
+    if name in ("medium", "large"):
+        return main_df(name)
     svals = SMALL_S_VALUES if name == "small" else (None,)
     for s in svals:
         p = make_config(name, s=s)

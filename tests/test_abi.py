@@ -84,7 +84,7 @@ def test_non_finite_input(lib):
 
 def test_unsupported_options(lib):
     p = make_problem(1, 2, 3, 6, seed=1)
-    for precision in (2, -1, 7):
+    for precision in (3, -1, 7):
         rc, _ = _call(p, opt=_lib.Options(0, precision, 0, None))
         assert rc == _lib.DSRG_E_UNSUPPORTED
     p = make_problem(0, 9, 1, 4, seed=1, with_gamma3=False)

@@ -38,7 +38,7 @@ def _close(x, ref, rel=1e-10):
 GETT_CASES = ["gemm", "ragged", "strided", "multi", "vec", "accum", "splitk", "longk", "packk"]
 
 
-@pytest.mark.parametrize("precision", [0, 1])
+@pytest.mark.parametrize("precision", [0, 1, 2])
 @pytest.mark.parametrize("case", GETT_CASES)
 def test_gett_kernel(case, precision):
     say("gett case", case, "precision", precision)
@@ -114,12 +114,18 @@ def test_gett_kernel(case, precision):
         err = np.abs(out - ref).max()
         assert err <= bound, (err, bound)
         return
-    # FP32 products: operands rounded to FP32 (relative 2^-24 each) and FP32 sums over at
-    # most 1024 terms before FP64 accumulation; a worst-case bound per element
-    bound = 4 * 2.0 ** -24 * (K + 64) * np.abs(A).max() * np.abs(B).max() * 1.5
+    if precision == 1:
+        # FP32 products: operands rounded to FP32 (relative 2^-24 each) and FP32 sums over at
+        # most 1024 terms before FP64 accumulation; a worst-case bound per element
+        bound = 4 * 2.0 ** -24 * (K + 64) * np.abs(A).max() * np.abs(B).max() * 1.5
+    else:
+        # split BF16 x3: x = hi + lo + r with |lo| <= 2^-8 |x| and |r| <= 2^-16 |x| (after the
+        # FP32 rounding), the dropped lo.lo and remainder terms at most 3 2^-16 |x y| per
+        # product, plus the FP32 sums as above
+        bound = (3 * 2.0 ** -16 + 4 * 2.0 ** -24) * (K + 64) * np.abs(A).max() * np.abs(B).max() * 1.5
     err = np.abs(out - ref).max()
     assert err <= bound, (err, bound)
-    assert err > 0.0   # the FP32 kernel really ran
+    assert err > 0.0   # the reduced-precision kernel really ran
 
 
 # ---------------------------------------------------------------------------
