@@ -236,6 +236,45 @@ int dsrg_pt3_pair_energies(const dsrg_problem* prob, const dsrg_options* opt, ds
 #define DSRG_NOALLOC_SCRATCH_BYTES (64LL << 20)
 int dsrg_pt3_energy_noalloc(const dsrg_problem* prob, const dsrg_options* opt, dsrg_result* out);
 
+/* ---- learned part: a network for the core-pair parts of E(3) ----
+   The core-pair decomposition of E(3) (see dsrg_pt3_pair_energies) is predicted pair by
+   pair from 16 features of first order (dsrg_pair_features).  Network: 16 -> 128 -> 128 ->
+   128 -> 1 with exact-erf GELU, BF16-rounded weights, FP32 activations and sums; it
+   predicts y_ij = e3_ij / |E2_ij|^{3/2} (E2_ij: the pair's second-order proxy), which B ->
+   kappa B leaves unchanged.  The weights blob (DSRG_MLP_WEIGHTS_BYTES, caller-owned) holds
+   a header, the feature and target standardisation and the FP32 parameters. */
+#define DSRG_MLP_FEATURES 16
+#define DSRG_MLP_WEIGHTS_BYTES 141572
+
+/* Features of the core pairs i <= j (row-major over the upper triangle), [nC(nC+1)/2][16]
+   FP32, and E2_ij [nC(nC+1)/2] FP64, from the first-order quantities of the problem: orbital
+   energies, min |D| and mean R_s(D) over the pair's doubles, 1/(1+s), logs of |E2_ij|, of its
+   s -> infinity value, of the squared norm and largest element of the pair's amplitudes
+   and of its mean squared integral, the same-spin share of E2_ij, log nV, log n_aux,
+   [i == j], log (ii|jj), log (ij|ij).  Runs the first-order steps only.  Arrays may be NULL
+   when n_core is 0. */
+int dsrg_pair_features(const dsrg_problem* prob, const dsrg_options* opt, float* features, double* e2_pairs);
+
+/* Train the network on n rows (X [n][16] features, y [n] targets y_ij) on the GPU: full
+   batch Adam (learning rate 1e-3) for `epochs` steps on the mean squared error of the
+   standardised targets, uniform initial weights from a counter-based generator of `seed`.
+   Writes the trained blob to weights_out.  Host arrays; deterministic. */
+int dsrg_mlp_train(const float* X, const double* y, int64_t n, int32_t epochs, uint64_t seed, void* weights_out);
+
+/* y [n] = the network's predictions for X [n][16] (host arrays), on the GPU. */
+int dsrg_mlp_predict(const void* weights, const float* X, int64_t n, double* y);
+
+/* E(2) exactly and E(3) = rest + sum of the core-pair parts, with the rest computed exactly
+   (the commutators' two-body outputs restricted to hole pairs with an active index, the
+   first-order doubles without their core-core pairs) and the pair parts predicted by the
+   network; a pair is computed exactly instead (one exact decomposition run for all of
+   them) when its predicted part exceeds rel_threshold times the summed magnitude of the
+   predictions or a feature lies more than 8 standard deviations from the training mean.
+   out->e3_a holds the rest of <[H~(1), T(2)]>, out->e3_b the rest of <[H~(2), T(1)]> plus
+   the pair parts; *n_exact_pairs (may be NULL) the number of pairs computed exactly. */
+int dsrg_pt3_energy_surrogate(const dsrg_problem* prob, const dsrg_options* opt, const void* weights,
+                              double rel_threshold, dsrg_result* out, int32_t* n_exact_pairs);
+
 /* As dsrg_pt3_energy, and copies the requested intermediates to host memory. */
 int dsrg_pt3_energy_ex(const dsrg_problem* prob, const dsrg_options* opt, dsrg_result* out,
                        const dsrg_intermediates* inter);

@@ -24,6 +24,12 @@ int dsrg_test_gett(int nm, const int* md, const long long* am, const long long* 
                    int nk, const int* kd, const long long* ak, const long long* bk,
                    const double* A, long long na, const double* B, long long nb,
                    double* C, long long nc, double alpha, int beta, int precision);
+/* Loss (mean squared error of the standardised targets) and its gradient with respect to
+   every parameter (grad: DSRG_MLP_WEIGHTS_BYTES / 4 - 64 floats, in the blob's parameter
+   order) of the pair-energy network at the given weights, computed by the training
+   kernels (forward, backward) on the GPU.  Host arrays. */
+int dsrg_test_mlp_grad(const void* weights, const float* X, const double* y, int64_t n, double* loss,
+                       float* grad);
 #ifdef __cplusplus
 }
 #endif

@@ -30,6 +30,9 @@ DSRG_F_NO_PLAN_CACHE = 8
 DSRG_F_FULL_LADDER = 16
 DSRG_PRECISION_FP64 = 0
 DSRG_PRECISION_FP32 = 1
+DSRG_PRECISION_BF16X3 = 2
+MLP_FEATURES = 16
+MLP_WEIGHTS_BYTES = 141572
 
 _dp = ctypes.POINTER(ctypes.c_double)
 
@@ -114,6 +117,22 @@ def load() -> ctypes.CDLL:
                                        ctypes.c_longlong, _dp, ctypes.c_longlong, ctypes.c_double,
                                        ctypes.c_int, ctypes.c_int]
         lib.dsrg_test_gett.restype = ctypes.c_int
+        fp = ctypes.POINTER(ctypes.c_float)
+        lib.dsrg_pair_features.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(Options), fp, _dp]
+        lib.dsrg_pair_features.restype = ctypes.c_int
+        lib.dsrg_mlp_train.argtypes = [fp, _dp, ctypes.c_int64, ctypes.c_int32, ctypes.c_uint64, ctypes.c_void_p]
+        lib.dsrg_mlp_train.restype = ctypes.c_int
+        lib.dsrg_mlp_predict.argtypes = [ctypes.c_void_p, fp, ctypes.c_int64, _dp]
+        lib.dsrg_mlp_predict.restype = ctypes.c_int
+        lib.dsrg_pt3_energy_surrogate.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(Options),
+                                                  ctypes.c_void_p, ctypes.c_double,
+                                                  ctypes.POINTER(Result), ctypes.POINTER(ctypes.c_int32)]
+        lib.dsrg_pt3_energy_surrogate.restype = ctypes.c_int
+        lib.dsrg_test_mlp_grad.argtypes = [ctypes.c_void_p, fp, _dp, ctypes.c_int64, _dp, fp]
+        lib.dsrg_test_mlp_grad.restype = ctypes.c_int
+        lib.dsrg_pt3_energy_noalloc.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(Options),
+                                                ctypes.POINTER(Result)]
+        lib.dsrg_pt3_energy_noalloc.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -318,3 +337,75 @@ def test_gett(A, B, C, m, n, k, alpha=1.0, beta=0, precision=0):
                                int(precision))
     _check(rc)
     return C
+
+
+# ---------------------------------------------------------------------------
+# the pair-energy network
+# ---------------------------------------------------------------------------
+def _f32(a, cols=None):
+    arr = np.ascontiguousarray(a, dtype=np.float32)
+    if cols is not None:
+        arr = arr.reshape(-1, cols)
+    return arr
+
+
+def dsrg_pair_features(p, stream=None):
+    """(features [nC(nC+1)/2][16] float32, E2_ij proxies [nC(nC+1)/2]) of the core pairs."""
+    keep = []
+    st, fl = _problem_struct(p, keep)
+    nC = int(st.n_core)
+    np_ = max(1, nC * (nC + 1) // 2)
+    X = np.zeros((np_, MLP_FEATURES), dtype=np.float32)
+    e2 = np.zeros(np_)
+    _check(load().dsrg_pair_features(ctypes.byref(st), ctypes.byref(_options(fl, _stream_of(p, stream))),
+                                     X.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), e2.ctypes.data_as(_dp)))
+    n = nC * (nC + 1) // 2
+    return X[:n], e2[:n]
+
+
+def dsrg_mlp_train(X, y, epochs=2000, seed=1):
+    """Train the network on the GPU; returns the weights blob (bytes)."""
+    X = _f32(X, MLP_FEATURES)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    out = ctypes.create_string_buffer(MLP_WEIGHTS_BYTES)
+    _check(load().dsrg_mlp_train(X.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), y.ctypes.data_as(_dp),
+                                 len(y), int(epochs), int(seed), out))
+    return out.raw
+
+
+def dsrg_mlp_predict(weights, X):
+    X = _f32(X, MLP_FEATURES)
+    y = np.zeros(len(X))
+    buf = ctypes.create_string_buffer(bytes(weights), MLP_WEIGHTS_BYTES)
+    _check(load().dsrg_mlp_predict(buf, X.ctypes.data_as(ctypes.POINTER(ctypes.c_float)), len(X),
+                                   y.ctypes.data_as(_dp)))
+    return y
+
+
+def test_mlp_grad(weights, X, y):
+    """(loss, gradient) of the network at the given weights, from the training kernels."""
+    X = _f32(X, MLP_FEATURES)
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    g = np.zeros(MLP_WEIGHTS_BYTES // 4 - 64, dtype=np.float32)
+    loss = ctypes.c_double(0.0)
+    buf = ctypes.create_string_buffer(bytes(weights), MLP_WEIGHTS_BYTES)
+    _check(load().dsrg_test_mlp_grad(buf, X.ctypes.data_as(ctypes.POINTER(ctypes.c_float)),
+                                     y.ctypes.data_as(_dp), len(y), ctypes.byref(loss),
+                                     g.ctypes.data_as(ctypes.POINTER(ctypes.c_float))))
+    return loss.value, g
+
+
+def dsrg_pt3_energy_surrogate(p, weights, rel_threshold=1.0, stream=None, workspace_cap=0, precision=0):
+    """E(2) and E(3) with the core-pair parts of E(3) from the network (exact fallback per
+    rel_threshold); the result dict gains 'n_exact_pairs'."""
+    keep = []
+    st, fl = _problem_struct(p, keep)
+    r = Result()
+    nex = ctypes.c_int32(0)
+    buf = ctypes.create_string_buffer(bytes(weights), MLP_WEIGHTS_BYTES)
+    _check(load().dsrg_pt3_energy_surrogate(ctypes.byref(st), ctypes.byref(
+        _options(fl, _stream_of(p, stream), workspace_cap, precision)), buf, float(rel_threshold),
+        ctypes.byref(r), ctypes.byref(nex)))
+    out = _result_dict(r)
+    out["n_exact_pairs"] = nex.value
+    return out

@@ -182,6 +182,48 @@ static const Use& pair_use() {
   return u;
 }
 
+// A commutator use restricted to the two-body outputs whose hole pair has at least one
+// active index (and all one-body outputs): in every product that writes the two-body
+// excitation block, each hole letter of the output (third and fourth output letters of its
+// scatters) that runs over all holes is split into its core and active parts, and the
+// core-core combination is dropped.  With these uses the second-order amplitudes vanish on
+// core-core hole pairs, which is what the rest of the core-pair decomposition of E(3)
+// needs (the scalars pair the hole indices of the two operators within one space).
+static Use rest_use(const Use& U) {
+  Use out;
+  for (const TProduct& P : U) {
+    std::string holes;
+    for (auto& sc : P.s)
+      if (sc.letters.size() == 4)
+        for (int k = 2; k < 4; ++k)
+          if (holes.find(sc.letters[k]) == std::string::npos) holes += sc.letters[k];
+    if (holes.empty()) {
+      out.push_back(P);
+      continue;
+    }
+    std::vector<std::vector<char>> opt;
+    for (char l : holes) {
+      const char sp = P.space.at(l);
+      if (sp == 'H') opt.push_back({'C', 'A'});
+      else opt.push_back({sp});
+    }
+    std::vector<size_t> pick(opt.size(), 0);
+    while (true) {
+      bool all_core = true;
+      TProduct Q = P;
+      for (size_t k = 0; k < opt.size(); ++k) {
+        Q.space[holes[k]] = opt[k][pick[k]];
+        all_core = all_core && opt[k][pick[k]] == 'C';
+      }
+      if (!all_core) out.push_back(Q);
+      size_t k = 0;
+      while (k < opt.size() && ++pick[k] == opt[k].size()) pick[k++] = 0;
+      if (k == opt.size()) break;
+    }
+  }
+  return out;
+}
+
 static const char* storage_axes(const std::string& t) {
   if (t == "T1" || t == "E1" || t == "Y1" || t == "O1" || t == "F1") return "PH";
   if (t == "T2" || t == "E2" || t == "Y2" || t == "O2") return "PPHH";
@@ -2465,8 +2507,19 @@ struct BodyOut {
 
 // The pipeline: every device operation goes through op (and so into a plan being built);
 // ev[1..6] mark the stages on st.
+// The pipeline modes: PairsMode runs the core-pair decomposition of E(3) beside the plain
+// energies; RestMode computes E(2) and only the rest of E(3) (the parts of the
+// decomposition outside the core pairs, from the restricted uses of [V, A(1)] and
+// [Y, A(1)] and first-order doubles without their core-core pairs) plus the features of
+// the core pairs.
+enum BodyMode { PlainMode = 0, PairsMode = 1, RestMode = 2 };
+struct RestOut {
+  float* feat = nullptr;   // [nC (nC + 1) / 2][16] device
+  double* e2 = nullptr;    // [nC (nC + 1) / 2] device
+};
+
 static BodyOut body(Exec& X, OpLog& op, Pool& pool, const Shape& sh, const Inputs& in, hipEvent_t* ev,
-                    hipStream_t st, bool want_pairs = false) {
+                    hipStream_t st, bool want_pairs = false, RestOut* rest = nullptr) {
   const int nC = sh.nC, nA = sh.nA, nV = sh.nV;
   const int nH = nC + nA, nP = nA + nV;
   const Dims d{nC, nA, nV};
@@ -2576,6 +2629,16 @@ static BodyOut body(Exec& X, OpLog& op, Pool& pool, const Shape& sh, const Input
   X.set("Y2.aa", Y2aa, "PPHH"); X.set("Y2.ab", Y2ab, "PPHH"); X.set("Y2.bb", Y2aa, "PPHH");
   bo.T1a = T1a; bo.T1b = T1b; bo.T2aa = T2aa; bo.T2ab = T2ab;
   mark(ev, 2, st);
+  if (rest && nC > 0) {
+    const int npairs = nC * (nC + 1) / 2;
+    rest->feat = reinterpret_cast<float*>(pool.alloc((size_t)npairs * 8));   // 16 floats per pair
+    rest->e2 = pool.alloc((size_t)npairs);
+    float* feat = rest->feat;
+    double* e2p = rest->e2;
+    const double* Bd = in.B;
+    const int Maux = sh.M;
+    op([=](hipStream_t s) { launch_pair_features(ad, Jhphp, eps, sdev, Bd, Maux, feat, e2p, s); });
+  }
 
   auto& T = table();
   const Use& C0 = T.at("C0");
@@ -2620,17 +2683,20 @@ static BodyOut body(Exec& X, OpLog& op, Pool& pool, const Shape& sh, const Input
   // under E(2); else step a3, steps a4-a5 and step a6 in turn
   std::map<std::string, TensorRef> none_e;
   X.use_id = 0;
+  static const Use rest_w = rest_use(T.at("W")), rest_z = rest_use(T.at("Z"));
+  const Use& Wu = rest ? rest_w : T.at("W");
+  const Use& Zu = rest ? rest_z : T.at("Z");
   if ((long long)n4 <= (1LL << 22) &&
-      X.run_fused({&C0, &T.at("W"), &T.at("Z")}, {&none_e, &wout, &zout}, {energies + 0, nullptr, nullptr})) {
+      X.run_fused({&C0, &Wu, &Zu}, {&none_e, &wout, &zout}, {energies + 0, nullptr, nullptr})) {
     for (int k = 3; k < 6; ++k) mark(ev, k, st);
   } else {
     scalar(energies + 0);
     mark(ev, 3, st);
     X.use_id = 1;
-    X.run_use(T.at("W"), wout, nullptr);
+    X.run_use(Wu, wout, nullptr);
     mark(ev, 4, st);
     X.use_id = 2;
-    X.run_use(T.at("Z"), zout, nullptr);
+    X.run_use(Zu, zout, nullptr);
     mark(ev, 5, st);
   }
   if (F1) {
@@ -2638,7 +2704,7 @@ static BodyOut body(Exec& X, OpLog& op, Pool& pool, const Shape& sh, const Input
     // place (both are Hermitian one-body operators with only excitation elements and their
     // adjoints), added into W, so that O1 = 2 (W + [f(1), A(1)]) + Z downstream
     Use fu;
-    for (const TProduct& P : T.at("Z")) {
+    for (const TProduct& P : Zu) {
       bool one_body = false;
       for (auto& f : P.f) one_body = one_body || f.tensor == "Y1";
       if (!one_body) continue;
@@ -2673,7 +2739,7 @@ static BodyOut body(Exec& X, OpLog& op, Pool& pool, const Shape& sh, const Input
   // E(3)_a = <[H~(1), T(2)]> and E(3)_b = <[H~(2)_{1,2}, T(1)]>: without the pair
   // decomposition both scalars run as one grouped use when their temporaries fit (the
   // second-order tensors under their own names), else one after the other
-  if (!want_pairs) {
+  if (!want_pairs && !rest) {
     X.set("U1.a", U1, "PH"); X.set("U1.b", U1 + n1, "PH");
     X.set("U2.aa", U2, "PPHH", 1); X.set("U2.ab", U2 + n4, "PPHH"); X.set("U2.bb", U2 + 2 * n4, "PPHH", 1);
     X.set("H1.a", H1, "PH"); X.set("H1.b", H1 + n1, "PH");
@@ -2725,6 +2791,15 @@ static BodyOut body(Exec& X, OpLog& op, Pool& pool, const Shape& sh, const Input
   }
   // E(3)_b = <[H~(2)_{1,2}, T(1)]>
   bind_first();
+  if (rest) {
+    // the rest of E(3)_b: first-order doubles without their core-core hole pairs
+    double* Tm = pool.alloc(2 * n4);
+    op([=](hipStream_t s) {
+      launch_mask_core_pairs(ad, T2aa, Tm, 1, s);
+      launch_mask_core_pairs(ad, T2ab, Tm + n4, 1, s);
+    });
+    X.set("T2.aa", Tm, "PPHH", 1); X.set("T2.ab", Tm + n4, "PPHH", 2); X.set("T2.bb", Tm, "PPHH", 1);
+  }
   X.set("E1.a", H1, "PH"); X.set("E1.b", H1 + n1, "PH");
   X.set("E2.aa", H2, "PPHH"); X.set("E2.ab", H2 + n4, "PPHH"); X.set("E2.bb", H2 + 2 * n4, "PPHH");
   scalar(energies + 2);
@@ -3036,11 +3111,16 @@ static void replay_result(const Plan* plan, const double* e, bool pt3, double e0
   *R = r;
 }
 
+// feat_host / e2p_host (both or neither): the rest-only mode (RestMode) with the core-pair
+// features and second-order pair proxies copied to these host arrays
 static int run(const dsrg_problem* P, const dsrg_options* O, dsrg_result* R,
                const dsrg_intermediates* I, bool pt3, double* e3_pairs = nullptr,
-               double* e3_rest = nullptr, int slot = 0) {
+               double* e3_rest = nullptr, int slot = 0, float* feat_host = nullptr,
+               double* e2p_host = nullptr) {
   if (!P || !R) throw Error(DSRG_E_ARG, "null problem or result");
-  const Setup S = setup(P, O, I, pt3, e3_pairs, e3_rest, slot);
+  Setup S = setup(P, O, I, pt3, e3_pairs, e3_rest, slot);
+  const bool rest_mode = feat_host != nullptr;
+  if (rest_mode) S.cacheable = false;
   const Shape& sh = S.sh;
   const int nC = sh.nC, nA = sh.nA, nV = sh.nV, M = sh.M;
   const int prec = S.prec;
@@ -3132,7 +3212,13 @@ static int run(const dsrg_problem* P, const dsrg_options* O, dsrg_result* R,
   X.prec = prec;
   X.virt_batch = S.vb;
   mark(ev, 0, st);
-  BodyOut bo = body(X, op, *pool, sh, in, ev, st, want_pairs);
+  RestOut ro;
+  BodyOut bo = body(X, op, *pool, sh, in, ev, st, want_pairs, rest_mode ? &ro : nullptr);
+  if (rest_mode && nC > 0) {
+    const size_t np = (size_t)nC * (nC + 1) / 2;
+    HIPCHECK(hipMemcpyAsync(feat_host, ro.feat, np * 16 * sizeof(float), hipMemcpyDeviceToHost, st));
+    HIPCHECK(hipMemcpyAsync(e2p_host, ro.e2, np * sizeof(double), hipMemcpyDeviceToHost, st));
+  }
   std::vector<double> pair_host;
   if (want_pairs) {
     const size_t np = (size_t)nC * (nC + 1) / 2 + 1;
@@ -3214,6 +3300,9 @@ static int run(const dsrg_problem* P, const dsrg_options* O, dsrg_result* R,
   }
   return DSRG_OK;
 }
+
+// the pair-energy network's entry points report errors through the same message
+void set_last_error(const char* m) { g_last_error = m; }
 
 template <class F>
 static int guarded(F&& f) {
@@ -3412,6 +3501,71 @@ int dsrg_pt3_energy_batch(const dsrg_problem* probs, int32_t n, const dsrg_optio
   (void)hipHostFree(stage);
   (void)hipEventDestroy(ready);
   return any_ok ? DSRG_OK : first_error;
+}
+
+int dsrg_pair_features(const dsrg_problem* prob, const dsrg_options* opt, float* features, double* e2_pairs) {
+  return dsrg::guarded([&] {
+    if (!prob) throw dsrg::Error(DSRG_E_ARG, "null problem");
+    if (prob->n_core > 0 && (!features || !e2_pairs)) throw dsrg::Error(DSRG_E_ARG, "null features or e2_pairs");
+    float dummy_f[16];
+    double dummy_e;
+    dsrg_result r;
+    return dsrg::run(prob, opt, &r, nullptr, false, nullptr, nullptr, 0, features ? features : dummy_f,
+                     e2_pairs ? e2_pairs : &dummy_e);
+  });
+}
+
+int dsrg_pt3_energy_surrogate(const dsrg_problem* prob, const dsrg_options* opt, const void* weights,
+                              double rel_threshold, dsrg_result* out, int32_t* n_exact_pairs) {
+  return dsrg::guarded([&] {
+    if (!prob || !out || !weights) throw dsrg::Error(DSRG_E_ARG, "null problem, result or weights");
+    if (!(rel_threshold >= 0.0)) throw dsrg::Error(DSRG_E_ARG, "rel_threshold must be >= 0");
+    const int nC = prob->n_core;
+    const size_t np = nC > 0 ? (size_t)nC * (nC + 1) / 2 : 0;
+    std::vector<float> feat(std::max<size_t>(1, np) * 16);
+    std::vector<double> e2p(std::max<size_t>(1, np)), pred(std::max<size_t>(1, np));
+    dsrg_result r;
+    dsrg::run(prob, opt, &r, nullptr, true, nullptr, nullptr, 0, feat.data(), e2p.data());
+    // predicted core-pair parts: y = e3_ij / |E2_ij|^{3/2}, invariant under B -> kappa B
+    int rc = np ? dsrg_mlp_predict(weights, feat.data(), (int64_t)np, pred.data()) : DSRG_OK;
+    if (rc != DSRG_OK) throw dsrg::Error(rc, std::string("pair-energy network: ") + dsrg::g_last_error);
+    std::vector<double> e3p(np);
+    double mag = 0.0;
+    for (size_t k = 0; k < np; ++k) {
+      e3p[k] = pred[k] * std::pow(std::fabs(e2p[k]), 1.5);
+      mag += std::fabs(e3p[k]);
+    }
+    // exact fallback: pairs predicted above rel_threshold of the summed magnitude, or whose
+    // features lie far outside the training distribution (|z| > 8)
+    const float* blob = static_cast<const float*>(weights);
+    std::vector<char> exact(np, 0);
+    int nexact = 0;
+    for (size_t k = 0; k < np; ++k) {
+      bool ood = false;
+      for (int f = 0; f < 16; ++f)
+        ood = ood || std::fabs((feat[k * 16 + f] - blob[8 + f]) / blob[24 + f]) > 8.0f;
+      if (ood || std::fabs(e3p[k]) > rel_threshold * mag) {
+        exact[k] = 1;
+        ++nexact;
+      }
+    }
+    if (nexact) {
+      std::vector<double> pairs(np);
+      double restv = 0;
+      dsrg_result rf;
+      dsrg::run(prob, opt, &rf, nullptr, true, pairs.data(), &restv);
+      for (size_t k = 0; k < np; ++k)
+        if (exact[k]) e3p[k] = pairs[k];
+    }
+    double sum = 0.0;
+    for (size_t k = 0; k < np; ++k) sum += e3p[k];
+    r.e3_b += sum;
+    r.e3 = r.e3_a + r.e3_b;
+    r.e_total = prob->e0 + r.e2 + r.e3;
+    *out = r;
+    if (n_exact_pairs) *n_exact_pairs = nexact;
+    return DSRG_OK;
+  });
 }
 
 int dsrg_pt3_energy_noalloc(const dsrg_problem* prob, const dsrg_options* opt, dsrg_result* out) {

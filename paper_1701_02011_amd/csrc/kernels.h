@@ -283,6 +283,13 @@ void launch_fock_exc(AmpDims d, const double* f, double* F1, hipStream_t st);
 // Y = src - F, E = src + F over nspins blocks of n elements (Y holds src on entry; F is one
 // block shared by the spins)
 void launch_split_source(long long n, int nspins, double* Y, double* E, const double* F, hipStream_t st);
+// dst = src with the core-core hole pairs (i, j < nC) zeroed, nblocks [P][P][H][H] blocks
+void launch_mask_core_pairs(AmpDims d, const double* src, double* dst, int nblocks, hipStream_t st);
+// Features of the core pairs i <= j for the pair-energy network (16 per pair, see the
+// kernel) from the Coulomb block J(HP|HP)[i][a][j][b] = (ai|bj), eps, s and B; e2[k]: the
+// pair's second-order proxy E2_ij
+void launch_pair_features(AmpDims d, const double* J, const double* eps, const double* s, const double* B, int M,
+                          float* feat, double* e2, hipStream_t st);
 // dst[i] += src[i]
 void launch_add(double* dst, const double* src, long long n, hipStream_t st);
 // O[p][q][i][j] += X[p][q][i][j] - X[q][p][i][j] - X[p][q][j][i] + X[q][p][j][i]

@@ -2009,6 +2009,123 @@ void launch_split_source(long long n, int nspins, double* Y, double* E, const do
   hipLaunchKernelGGL(split_source_kernel, dim3((unsigned)blocks), dim3(256), 0, st, n, nspins, Y, E, F);
 }
 
+// dst = src with the elements of core-core hole pairs (i < nC and j < nC) set to zero, over
+// nblocks [P][P][H][H] blocks
+__global__ __launch_bounds__(256) void mask_core_pairs_kernel(const double* __restrict__ src, double* __restrict__ dst,
+                                                              long long total, int nH, int nC) {
+  for (long long e = blockIdx.x * 256LL + threadIdx.x; e < total; e += 256LL * gridDim.x) {
+    const long long q = e / nH;
+    const int j = (int)(e - q * nH), i = (int)(q % nH);
+    dst[e] = (i < nC && j < nC) ? 0.0 : src[e];
+  }
+}
+
+void launch_mask_core_pairs(AmpDims d, const double* src, double* dst, int nblocks, hipStream_t st) {
+  const long long nH = d.nC + d.nA, nP = d.nA + d.nV;
+  const long long total = nP * nP * nH * nH * nblocks;
+  if (total <= 0) return;
+  const long long blocks = std::min<long long>((total + 255) / 256, 16384);
+  hipLaunchKernelGGL(mask_core_pairs_kernel, dim3((unsigned)blocks), dim3(256), 0, st, src, dst, total, (int)nH, d.nC);
+}
+
+// Features of the core pairs i <= j (row-major over the upper triangle), one workgroup per
+// pair, from V[a][b] = (ai|bj) and X[a][b] = (bi|aj) over particles a, b (the Coulomb block
+// J[i][a][j][b] = (ai|bj)), D = e_i + e_j - e_a - e_b, R = R_s(D), f = exp(-s D^2):
+//  0 e_i, 1 e_j, 2 min |D|, 3 mean R, 4 1/(1 + s), 5 log|E2_ij|, 6 log|E2inf_ij|,
+//  7 log sum t^2, 8 log (sum V^2 / nP^2), 9 log max|t|, 10 same-spin share of E2_ij,
+//  11 log nV, 12 log M, 13 [i == j], 14 log (ii|jj), 15 log (ij|ij)
+// with t = V R, E2_ij = c (2 sum V^2 (1 + f) R + sum (V - X)^2 (1 + f) R [i < j]) (c = 1 for
+// i < j, 1/2 for i == j), E2inf_ij the same with (1 + f) R -> 1/D.  e2_out[k] = E2_ij.
+// Sums in FP64 in a fixed order (a tree over the workgroup).
+constexpr int kPairFeatures = 16;
+__global__ __launch_bounds__(256) void pair_features_kernel(AmpDims d, const double* __restrict__ J,
+                                                            const double* __restrict__ eps, const double* __restrict__ sp,
+                                                            const double* __restrict__ B, int M,
+                                                            float* __restrict__ feat, double* __restrict__ e2_out) {
+  const double s = *sp;
+  const int nC = d.nC, nH = d.nC + d.nA, nP = d.nA + d.nV, N = nH + d.nV;
+  // pair k -> (i, j), i <= j
+  int k = blockIdx.x, i = 0;
+  while (k >= nC - i) {
+    k -= nC - i;
+    ++i;
+  }
+  const int j = i + k;
+  const bool diag = i == j;
+  __shared__ double red[8][256];
+  double os = 0, ss = 0, osi = 0, ssi = 0, tn = 0, vn = 0, tmax = 0, rs = 0, dmin = 1e300;
+  const long long sH = (long long)nP * nH * nP;   // J[i][a][j][b]
+  for (long long e = threadIdx.x; e < (long long)nP * nP; e += 256) {
+    const int a = (int)(e / nP), b = (int)(e - (long long)a * nP);
+    const double V = J[i * sH + (long long)a * nH * nP + (long long)j * nP + b];
+    const double X = J[i * sH + (long long)b * nH * nP + (long long)j * nP + a];
+    const double D = eps[i] + eps[j] - eps[nC + a] - eps[nC + b];
+    const double R = regulariser(s, D), f = source_factor(s, D);
+    const double inv = D != 0.0 ? 1.0 / D : 0.0;
+    os += V * V * (1.0 + f) * R;
+    osi += V * V * inv;
+    if (!diag) {
+      ss += (V - X) * (V - X) * (1.0 + f) * R;
+      ssi += (V - X) * (V - X) * inv;
+      tn += 0.5 * (V - X) * (V - X) * R * R;
+    }
+    tn += V * V * R * R;
+    vn += V * V;
+    tmax = fmax(tmax, fabs(V * R));
+    rs += R;
+    dmin = fmin(dmin, fabs(D));
+  }
+  double v[8] = {os, ss, osi, ssi, tn, vn, rs, tmax};
+  for (int q = 0; q < 8; ++q) red[q][threadIdx.x] = v[q];
+  __shared__ double dm[256];
+  dm[threadIdx.x] = dmin;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if ((int)threadIdx.x < w) {
+      for (int q = 0; q < 7; ++q) red[q][threadIdx.x] += red[q][threadIdx.x + w];
+      red[7][threadIdx.x] = fmax(red[7][threadIdx.x], red[7][threadIdx.x + w]);
+      dm[threadIdx.x] = fmin(dm[threadIdx.x], dm[threadIdx.x + w]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  const double c = diag ? 0.5 : 1.0;
+  const double e2 = c * (2.0 * red[0][0] + red[1][0]);
+  const double e2i = c * (2.0 * red[2][0] + red[3][0]);
+  double iijj = 0, ijij = 0;
+  for (int Q = 0; Q < M; ++Q) {
+    const double* BQ = B + (long long)Q * N * N;
+    iijj += BQ[(long long)i * N + i] * BQ[(long long)j * N + j];
+    ijij += BQ[(long long)i * N + j] * BQ[(long long)i * N + j];
+  }
+  const double tiny = 1e-300;
+  float* o = feat + (long long)blockIdx.x * kPairFeatures;
+  o[0] = (float)eps[i];
+  o[1] = (float)eps[j];
+  o[2] = (float)dm[0];
+  o[3] = (float)(red[6][0] / ((double)nP * nP));
+  o[4] = (float)(1.0 / (1.0 + s));
+  o[5] = (float)log(fabs(e2) + tiny);
+  o[6] = (float)log(fabs(e2i) + tiny);
+  o[7] = (float)log(red[4][0] + tiny);
+  o[8] = (float)log(red[5][0] / ((double)nP * nP) + tiny);
+  o[9] = (float)log(red[7][0] + tiny);
+  o[10] = (float)(fabs(e2) > 0 ? c * red[1][0] / e2 : 0.0);
+  o[11] = (float)log((double)d.nV + 1.0);
+  o[12] = (float)log((double)M);
+  o[13] = diag ? 1.f : 0.f;
+  o[14] = (float)log(fabs(iijj) + tiny);
+  o[15] = (float)log(ijij + tiny);
+  e2_out[blockIdx.x] = e2;
+}
+
+void launch_pair_features(AmpDims d, const double* J, const double* eps, const double* s, const double* B, int M,
+                          float* feat, double* e2, hipStream_t st) {
+  const int np = d.nC * (d.nC + 1) / 2;
+  if (np <= 0) return;
+  hipLaunchKernelGGL(pair_features_kernel, dim3(np), dim3(256), 0, st, d, J, eps, s, B, M, feat, e2);
+}
+
 __global__ __launch_bounds__(256) void add_kernel(double* __restrict__ dst, const double* __restrict__ src,
                                                   long long n) {
   for (long long i = blockIdx.x * 256LL + threadIdx.x; i < n; i += 256LL * gridDim.x) dst[i] += src[i];
