@@ -275,6 +275,20 @@ int dsrg_mlp_predict(const void* weights, const float* X, int64_t n, double* y);
 int dsrg_pt3_energy_surrogate(const dsrg_problem* prob, const dsrg_options* opt, const void* weights,
                               double rel_threshold, dsrg_result* out, int32_t* n_exact_pairs);
 
+/* Reference densities from a CAS vector, the step before the path (Sec. II.A: the method
+   takes the reference through its densities).  ci [C(nA, n_alpha)][C(nA, n_beta)]: the
+   coefficients over alpha strings x beta strings (all subsets of the nA active orbitals in
+   lexicographic order of their sorted index lists; a determinant is the alpha creators and
+   then the beta creators in ascending order on the vacuum).  Writes gamma1 [2][nA]^2,
+   gamma2 [3][nA]^4 and, unless NULL, gamma3 [4][nA]^6 in the layout of dsrg_problem.  Each
+   spin block is the Gram matrix of the vectors a_{t_k}..a_{t_1}|Psi> over ordered index
+   tuples (an FP64 contraction on the library's contraction kernel), spread over all index
+   orders.  With DSRG_F_DEVICE_PTRS in opt->flags every array is a device pointer, else a
+   host pointer; runs on opt->stream and synchronises it.  1 <= nA <= 16 (DSRG_E_UNSUPPORTED
+   otherwise); DSRG_E_OOM when one spin block's vectors exceed 2^30 doubles. */
+int dsrg_active_rdms(const double* ci, int32_t n_active, int32_t n_alpha, int32_t n_beta,
+                     const dsrg_options* opt, double* gamma1, double* gamma2, double* gamma3);
+
 /* As dsrg_pt3_energy, and copies the requested intermediates to host memory. */
 int dsrg_pt3_energy_ex(const dsrg_problem* prob, const dsrg_options* opt, dsrg_result* out,
                        const dsrg_intermediates* inter);

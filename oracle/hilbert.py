@@ -157,3 +157,23 @@ def rspt_energies(Hmat0_diag: np.ndarray, Vmat: np.ndarray, ref: int):
     Vkl = Vmat[np.ix_(others, others)] - E1 * np.eye(len(others))
     E3 = float((V0k / d) @ Vkl @ (V0k / d))
     return E1, E2, E3
+
+
+def active_rdm_blocks(ci, nA: int, n_alpha: int, n_beta: int):
+    """The reference densities of a CAS vector in the library's spin-block input layout,
+    from brute-force expectation values in the full Fock space of the 2 nA active spin
+    orbitals (nA <= 7): gamma1[s][u][v] = <a+_{us} a_{vs}>, gamma2[b][u][v][x][y] =
+    <a+_u a+_v a_y a_x> (blocks aa, ab, bb), gamma3[b][u][v][w][x][y][z] =
+    <a+_u a+_v a+_w a_z a_y a_x> (blocks aaa, aab, abb, bbb)."""
+    sp = Spaces(0, nA, 0)
+    fs = FockSpace(2 * nA)
+    vec = reference_vector(sp, ci, n_alpha, n_beta, fs)
+    idx = list(range(2 * nA))
+    D1 = rdm(fs, vec, 1, idx)
+    D2 = rdm(fs, vec, 2, idx).transpose(0, 1, 3, 2)          # -> <a+p a+q a_s a_r> at [p,q,r,s]
+    D3 = rdm(fs, vec, 3, idx).transpose(0, 1, 2, 5, 4, 3)    # -> <a+p a+q a+r a_u a_t a_s>
+    a, b = slice(0, nA), slice(nA, 2 * nA)
+    g1 = np.stack([D1[a, a], D1[b, b]])
+    g2 = np.stack([D2[a, a, a, a], D2[a, b, a, b], D2[b, b, b, b]])
+    g3 = np.stack([D3[a, a, a, a, a, a], D3[a, a, b, a, a, b], D3[a, b, b, a, b, b], D3[b, b, b, b, b, b]])
+    return g1, g2, g3

@@ -133,6 +133,10 @@ def load() -> ctypes.CDLL:
         lib.dsrg_pt3_energy_noalloc.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(Options),
                                                 ctypes.POINTER(Result)]
         lib.dsrg_pt3_energy_noalloc.restype = ctypes.c_int
+        lib.dsrg_active_rdms.argtypes = [ctypes.c_void_p, ctypes.c_int32, ctypes.c_int32, ctypes.c_int32,
+                                         ctypes.POINTER(Options), ctypes.c_void_p, ctypes.c_void_p,
+                                         ctypes.c_void_p]
+        lib.dsrg_active_rdms.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -409,3 +413,17 @@ def dsrg_pt3_energy_surrogate(p, weights, rel_threshold=1.0, stream=None, worksp
     out = _result_dict(r)
     out["n_exact_pairs"] = nex.value
     return out
+
+
+def dsrg_active_rdms(ci, n_active, n_alpha, n_beta, with_gamma3=True):
+    """gamma1 [2][nA]^2, gamma2 [3][nA]^4, gamma3 [4][nA]^6 (or None) of a CAS vector, on the
+    GPU (host arrays in and out)."""
+    c = np.ascontiguousarray(ci, dtype=np.float64)
+    nA = int(n_active)
+    g1 = np.zeros((2,) + (nA,) * 2)
+    g2 = np.zeros((3,) + (nA,) * 4)
+    g3 = np.zeros((4,) + (nA,) * 6) if with_gamma3 else None
+    _check(load().dsrg_active_rdms(c.ctypes.data, nA, int(n_alpha), int(n_beta),
+                                   ctypes.byref(_options(0)), g1.ctypes.data, g2.ctypes.data,
+                                   None if g3 is None else g3.ctypes.data))
+    return g1, g2, g3

@@ -200,3 +200,14 @@ def test_struct_layouts_match_header(lib):
     assert ctypes.sizeof(_lib.Problem) == 4 * 4 + 5 * 8 + 8 + 8 + 8
     assert ctypes.sizeof(_lib.Options) == 4 + 4 + 8 + 8 + 8
     assert _lib.Result.e_total.offset > _lib.Result.role_bytes.offset
+
+
+def test_active_rdms_argument_checks(lib):
+    ci = np.ones((3, 3)) / 3.0
+    assert _lib.load().dsrg_active_rdms(ci.ctypes.data, 0, 0, 0, None, None, None, None) == _lib.DSRG_E_UNSUPPORTED
+    assert _lib.load().dsrg_active_rdms(ci.ctypes.data, 17, 1, 1, None, None, None, None) == _lib.DSRG_E_UNSUPPORTED
+    g1, g2 = np.zeros(2 * 9), np.zeros(3 * 81)
+    assert _lib.load().dsrg_active_rdms(ci.ctypes.data, 3, 4, 1, None, g1.ctypes.data, g2.ctypes.data,
+                                        None) == _lib.DSRG_E_ARG
+    assert _lib.load().dsrg_active_rdms(None, 3, 1, 1, None, g1.ctypes.data, g2.ctypes.data,
+                                        None) == _lib.DSRG_E_ARG

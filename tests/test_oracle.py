@@ -730,3 +730,17 @@ def test_first_order_closed_forms_with_fock_offdiag():
     np.testing.assert_allclose(np.where(m1, ht1, 0.0),
                                np.where(m1, f_so + (f_so + coup) * np.exp(-p.s * D1 ** 2), 0.0),
                                atol=1e-14)
+
+
+@pytest.mark.parametrize("nA,na,nb,seed", [(3, 2, 1, 1), (4, 2, 2, 2), (5, 3, 2, 3)])
+def test_active_rdm_blocks_match_generator(nA, na, nb, seed):
+    """The oracle's CAS densities (brute force in the Fock space of the active spin orbitals)
+    equal the input generator's (Gram matrices of annihilated vectors): two constructions of
+    the same expectation values, and the layout of the spin blocks."""
+    rng = np.random.default_rng(seed)
+    ci = synth.random_ci(rng, nA, na, nb)
+    from oracle.hilbert import active_rdm_blocks
+    a = active_rdm_blocks(ci, nA, na, nb)
+    b = synth.active_rdms(ci, nA, na, nb)
+    for x, y in zip(a, b):
+        assert np.abs(x - y).max() < 1e-14
