@@ -289,6 +289,54 @@ int dsrg_pt3_energy_surrogate(const dsrg_problem* prob, const dsrg_options* opt,
 int dsrg_active_rdms(const double* ci, int32_t n_active, int32_t n_alpha, int32_t n_beta,
                      const dsrg_options* opt, double* gamma1, double* gamma2, double* gamma3);
 
+/* ---- one-step relaxed DSRG-MRPT3 (Sec. II.B Eqs. energy_relaxed, E_relaxed; App. A) ----
+   E^[3] is the lowest eigenvalue of the summed third-order transformed Hamiltonian
+   Hbar^[3]_{1,2} = sum_{n=0..3} Hbar^(n)_{1,2} (Eqs. Hbar_0th - Hbar_3rd) within the CAS
+   determinant space of n_alpha and n_beta active electrons.  After the unrelaxed pipeline
+   the library forms the active blocks of Hbar^[3]_{1,2} (the one- and two-body elements
+   with active indices only: H(0) and the integrals <uv||xy>, plus the active blocks of
+   1/2 [H~(1), A(1)] + 1/2 [H~(1), A(2)] + 1/2 [H~(2)_{1,2}, A(1)]; [H(0), A] has no active
+   element), writes the operator in true-vacuum order with the core folded in (Eqs.
+   Hbar_DNO, c0_cas):
+     H_CAS = const + sum_uv c^u_v a+_u a_v + 1/4 sum_uvxy Hbar^uv_xy a+_u a+_v a_y a_x,
+     const = Hbar_0 - sum Hbar^u_v g^u_v - sum Hbar^uv_xy (g^uv_xy / 4 - g^u_x g^v_y),
+     c^u_v = Hbar^u_v - sum_xy Hbar^ux_vy g^x_y   (spin-orbital sums, Hbar_0 = E(2) + E(3)),
+   builds its matrix over the determinants (Slater-Condon rules) and finds the lowest
+   eigenpair by Davidson iterations, all on the GPU.  The determinants and the CI layout
+   are those of dsrg_active_rdms.  The densities of prob must be those of a state with
+   n_alpha and n_beta electrons. */
+typedef struct {
+  double e_relaxed;    /* e0 + lowest eigenvalue of H_CAS (Eq. E_relaxed) */
+  double e_unrelaxed;  /* e0 + E(2) + E(3): the reference's expectation value of the same operator */
+  double cas_const;    /* const of H_CAS (without e0) */
+  double residual;     /* norm of H_CAS x - E x for the returned eigenvector x at exit */
+  int32_t n_det;       /* C(nA, n_alpha) C(nA, n_beta) */
+  int32_t iterations;  /* Davidson iterations */
+  int32_t converged;   /* 1 when residual <= 1e-9 (or the subspace spans the whole space) */
+  int32_t reserved;
+} dsrg_relaxed_result;
+
+/* Optional host outputs of the relaxation (each pointer may be NULL). */
+typedef struct {
+  double* ci;      /* [C(nA, n_alpha)][C(nA, n_beta)] the eigenvector, unit norm, sign chosen for a
+                      non-negative overlap with ci_guess (else a positive largest element) */
+  double* hbar1;   /* [2][nA][nA] Hbar^u_v, spins a, b */
+  double* hbar2;   /* [3][nA]^4 Hbar^uv_xy, blocks aa, ab, bb in the layout of gamma2 (coefficient
+                      of 1/4 {a+_u a+_v a_y a_x}) */
+  double* cas_c;   /* [2][nA][nA] c^u_v */
+} dsrg_relaxed_outputs;
+
+/* E(2), E(3) (into *out, as dsrg_pt3_energy) and the relaxed energy (into *rel).  ci_guess
+   (host, may be NULL): a start vector for the Davidson iterations, normally the reference's
+   CI vector; unit vectors on the lowest diagonal elements are always added.  Returns
+   DSRG_E_ARG for n_alpha or n_beta outside [0, nA] or null out/rel, DSRG_E_RDM when the
+   traces of gamma1 differ from n_alpha, n_beta by more than 1e-8, DSRG_E_NONFINITE for a
+   non-finite ci_guess, else as dsrg_pt3_energy.  Runs without a plan; ci_guess and the
+   outputs are host memory whatever opt->flags says. */
+int dsrg_pt3_energy_relaxed(const dsrg_problem* prob, int32_t n_alpha, int32_t n_beta, const double* ci_guess,
+                            const dsrg_options* opt, dsrg_result* out, dsrg_relaxed_result* rel,
+                            const dsrg_relaxed_outputs* outs);
+
 /* As dsrg_pt3_energy, and copies the requested intermediates to host memory. */
 int dsrg_pt3_energy_ex(const dsrg_problem* prob, const dsrg_options* opt, dsrg_result* out,
                        const dsrg_intermediates* inter);

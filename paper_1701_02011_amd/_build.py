@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdsrg.so")
-SOURCES = ["dsrg.hip", "kernels.hip", "mlp.hip", "rdm.hip"]
+SOURCES = ["dsrg.hip", "kernels.hip", "mlp.hip", "rdm.hip", "cas.hip"]
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          # MFMA accumulators in ordinary VGPRs: with the AGPR form the compiler copied every
@@ -24,13 +24,33 @@ def hipcc():
 
 
 def build(verbose: bool = False) -> str:
-    cmd = [hipcc()] + FLAGS + [os.path.join(CSRC, s) for s in SOURCES] + ["-o", LIB + ".tmp"]
+    """Compile every source to an object in parallel, then link the shared library."""
+    from concurrent.futures import ThreadPoolExecutor
+    odir = os.path.join(HERE, "_objs")
+    os.makedirs(odir, exist_ok=True)
+    cflags = [f for f in FLAGS if f != "-shared"]
+
+    def compile_one(src):
+        obj = os.path.join(odir, os.path.splitext(src)[0] + ".o")
+        cmd = [hipcc()] + cflags + ["-c", os.path.join(CSRC, src), "-o", obj]
+        if verbose:
+            print(" ".join(cmd), flush=True)
+        r = subprocess.run(cmd, capture_output=True, text=True)
+        return obj, r
+
+    with ThreadPoolExecutor(max_workers=min(len(SOURCES), os.cpu_count() or 1)) as ex:
+        results = list(ex.map(compile_one, SOURCES))
+    for obj, r in results:
+        if r.returncode != 0:
+            sys.stderr.write(r.stdout + r.stderr)
+            raise RuntimeError("hipcc failed on %s with exit code %d" % (obj, r.returncode))
+    cmd = [hipcc(), "--offload-arch=gfx950", "-fPIC", "-shared"] + [o for o, _ in results] + ["-o", LIB + ".tmp"]
     if verbose:
         print(" ".join(cmd), flush=True)
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         sys.stderr.write(r.stdout + r.stderr)
-        raise RuntimeError("hipcc failed with exit code %d" % r.returncode)
+        raise RuntimeError("link failed with exit code %d" % r.returncode)
     os.replace(LIB + ".tmp", LIB)
     return LIB
 

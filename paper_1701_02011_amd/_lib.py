@@ -69,6 +69,18 @@ class Intermediates(ctypes.Structure):
     _fields_ = [(n, ctypes.c_void_p) for n in ("t1", "t2", "w1", "w2", "z1", "z2", "u1", "u2")]
 
 
+class RelaxedResult(ctypes.Structure):
+    _fields_ = [("e_relaxed", ctypes.c_double), ("e_unrelaxed", ctypes.c_double),
+                ("cas_const", ctypes.c_double), ("residual", ctypes.c_double),
+                ("n_det", ctypes.c_int32), ("iterations", ctypes.c_int32),
+                ("converged", ctypes.c_int32), ("reserved", ctypes.c_int32)]
+
+
+class RelaxedOutputs(ctypes.Structure):
+    _fields_ = [("ci", ctypes.c_void_p), ("hbar1", ctypes.c_void_p), ("hbar2", ctypes.c_void_p),
+                ("cas_c", ctypes.c_void_p)]
+
+
 class DsrgError(RuntimeError):
     def __init__(self, code: int, msg: str):
         super().__init__("dsrg error %d: %s" % (code, msg))
@@ -137,6 +149,11 @@ def load() -> ctypes.CDLL:
                                          ctypes.POINTER(Options), ctypes.c_void_p, ctypes.c_void_p,
                                          ctypes.c_void_p]
         lib.dsrg_active_rdms.restype = ctypes.c_int
+        lib.dsrg_pt3_energy_relaxed.argtypes = [ctypes.POINTER(Problem), ctypes.c_int32, ctypes.c_int32,
+                                                ctypes.c_void_p, ctypes.POINTER(Options),
+                                                ctypes.POINTER(Result), ctypes.POINTER(RelaxedResult),
+                                                ctypes.POINTER(RelaxedOutputs)]
+        lib.dsrg_pt3_energy_relaxed.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -427,3 +444,41 @@ def dsrg_active_rdms(ci, n_active, n_alpha, n_beta, with_gamma3=True):
                                    ctypes.byref(_options(0)), g1.ctypes.data, g2.ctypes.data,
                                    None if g3 is None else g3.ctypes.data))
     return g1, g2, g3
+
+
+def dsrg_pt3_energy_relaxed(p, n_alpha=None, n_beta=None, ci_guess="reference", stream=None,
+                            workspace_cap=0, precision=0, outputs=True):
+    """E(2), E(3) and the one-step relaxed energy.  n_alpha/n_beta default to the problem's;
+    ci_guess "reference" passes the problem's CI vector (None: no guess).  With outputs the
+    dict gains 'ci', 'hbar1', 'hbar2', 'cas_c' (numpy arrays)."""
+    keep = []
+    st, fl = _problem_struct(p, keep)
+    nA = st.n_active
+    na = int(p.n_alpha if n_alpha is None else n_alpha)
+    nb = int(p.n_beta if n_beta is None else n_beta)
+    guess = None
+    if isinstance(ci_guess, str):
+        if getattr(p, "ci", None) is not None:
+            guess = np.ascontiguousarray(np.asarray(p.ci), dtype=np.float64)
+    elif ci_guess is not None:
+        guess = np.ascontiguousarray(ci_guess, dtype=np.float64)
+    ndet = math.comb(nA, na) * math.comb(nA, nb) if 0 <= na <= nA and 0 <= nb <= nA else 0
+    bufs = {}
+    if outputs:
+        bufs = dict(ci=np.zeros(max(ndet, 1)), hbar1=np.zeros((2, nA, nA)), hbar2=np.zeros((3,) + (nA,) * 4),
+                    cas_c=np.zeros((2, nA, nA)))
+    o = RelaxedOutputs(**{k: v.ctypes.data for k, v in bufs.items()})
+    r = Result()
+    x = RelaxedResult()
+    _check(load().dsrg_pt3_energy_relaxed(ctypes.byref(st), na, nb,
+                                          None if guess is None else guess.ctypes.data,
+                                          ctypes.byref(_options(fl, _stream_of(p, stream), workspace_cap,
+                                                                precision)),
+                                          ctypes.byref(r), ctypes.byref(x), ctypes.byref(o)))
+    out = _result_dict(r)
+    out.update(e_relaxed=x.e_relaxed, e_unrelaxed=x.e_unrelaxed, cas_const=x.cas_const,
+               residual=x.residual, n_det=x.n_det, iterations=x.iterations, converged=bool(x.converged))
+    if outputs:
+        bufs["ci"] = bufs["ci"][:ndet]
+        out.update(bufs)
+    return out

@@ -8,6 +8,7 @@
 // generated table in dsrg_terms.inc; every contraction in it runs on the GETT kernel.
 #include "../../include/dsrg.h"
 #include "../../include/dsrg_testing.h"
+#include "cas.h"
 #include "kernels.h"
 
 #include <hip/hip_runtime.h>
@@ -1152,8 +1153,9 @@ struct Exec {
   }
 
   // Sub-spaces of an output axis covered by a letter's space: bit 0 is the lower part of
-  // the axis (A of P, C of H), bit 1 the upper part (V of P, A of H).
+  // the axis (A of P, C of H, all of A), bit 1 the upper part (V of P, A of H).
   static unsigned covers(char axis, char letter_space) {
+    if (axis == 'A' && letter_space == 'A') return 1;
     if (axis == 'P') {
       if (letter_space == 'P') return 3;
       if (letter_space == 'A') return 1;
@@ -1533,7 +1535,7 @@ struct Exec {
       std::vector<GatherEntry> ent;
       for (int k = 0; k < gd.rank; ++k) {
         gd.dim[k] = d.len(o.axes[k]);
-        gd.split[k] = o.axes[k] == 'P' ? d.nA : d.nC;
+        gd.split[k] = o.axes[k] == 'P' ? d.nA : o.axes[k] == 'H' ? d.nC : gd.dim[k];
         if (o.stride[k] != (k + 1 < gd.rank ? o.stride[k + 1] * d.len(o.axes[k + 1]) : 1))
           throw Error(DSRG_E_HIP, "internal: gather output must be contiguous");
       }
@@ -2503,7 +2505,21 @@ struct BodyOut {
   double *T1a = nullptr, *T1b = nullptr, *T2aa = nullptr, *T2ab = nullptr;
   double *W1 = nullptr, *W2 = nullptr, *Z1 = nullptr, *Z2 = nullptr, *U1 = nullptr, *U2 = nullptr;
   double* pairs = nullptr;   // [nC (nC + 1) / 2 + 1]: core-pair parts of E(3), then the rest
+  // with relax: active blocks R1 [2][nA][nA], R2 [3][nA]^4 of [H~(1), A(1)] + [H~(2)_{1,2}, A(1)]
+  // + [H~(1), A(2)] (twice the active blocks of Hbar^(2) + Hbar^(3), Eqs. Hbar_2nd, Hbar_3rd)
+  double* R = nullptr;
 };
+
+// A use with its factor tensors renamed (the same products on other arrays).
+static Use rename_use(const Use& U, const char* from1, const char* to1, const char* from2, const char* to2) {
+  Use u = U;
+  for (auto& P : u)
+    for (auto& f : P.f) {
+      if (f.tensor == from1) f.tensor = to1;
+      else if (f.tensor == from2) f.tensor = to2;
+    }
+  return u;
+}
 
 // The pipeline: every device operation goes through op (and so into a plan being built);
 // ev[1..6] mark the stages on st.
@@ -2519,7 +2535,7 @@ struct RestOut {
 };
 
 static BodyOut body(Exec& X, OpLog& op, Pool& pool, const Shape& sh, const Inputs& in, hipEvent_t* ev,
-                    hipStream_t st, bool want_pairs = false, RestOut* rest = nullptr) {
+                    hipStream_t st, bool want_pairs = false, RestOut* rest = nullptr, bool relax = false) {
   const int nC = sh.nC, nA = sh.nA, nV = sh.nV;
   const int nH = nC + nA, nP = nA + nV;
   const Dims d{nC, nA, nV};
@@ -2736,6 +2752,43 @@ static BodyOut body(Exec& X, OpLog& op, Pool& pool, const Shape& sh, const Input
                    S2 + n1, s, Z1, Z1 + n1);
     launch_second_order_h1(ad, W1, Z1, S2, H1, 2, s);   // alpha, beta
   });
+  // One-step relaxation (Sec. II.B Eq. E_relaxed): the active blocks of the second- and
+  // third-order transformed Hamiltonian, R = [H~(1), A(1)] + [H~(2)_{1,2}, A(1)] + [H~(1), A(2)]
+  // (use R of the table on H~(1) or H~(2)_{1,2} as the de-excitation operator and either
+  // order of amplitudes; Hbar^(2) + Hbar^(3) = R / 2 on the active blocks)
+  auto relax_stage = [&]() {
+    if (!relax || nA == 0) return;
+    const long long n2 = (long long)nA * nA, nr = 2 * n2 + 3 * n2 * n2;
+    double* R = pool.alloc((size_t)nr);
+    op([R, nr](hipStream_t s) { launch_fill(R, nr, 0.0, s); });
+    X.set("E1.a", E1a, "PH"); X.set("E1.b", E1b, "PH");
+    X.set("E2.aa", E2aa, "PPHH"); X.set("E2.ab", E2ab, "PPHH"); X.set("E2.bb", E2aa, "PPHH");
+    bind_first();
+    X.set("U1.a", U1, "PH"); X.set("U1.b", U1 + n1, "PH");
+    X.set("U2.aa", U2, "PPHH", 1); X.set("U2.ab", U2 + n4, "PPHH"); X.set("U2.bb", U2 + 2 * n4, "PPHH", 1);
+    X.set("H1.a", H1, "PH"); X.set("H1.b", H1 + n1, "PH");
+    X.set("H2.aa", H2, "PPHH"); X.set("H2.ab", H2 + n4, "PPHH"); X.set("H2.bb", H2 + 2 * n4, "PPHH");
+    std::map<std::string, TensorRef> rout;
+    auto mk = [&](double* p, const char* ax) {
+      const int r = (int)strlen(ax);
+      TensorRef t{p, ax, std::vector<long long>(r, 1)};
+      for (int k = r - 2; k >= 0; --k) t.stride[k] = t.stride[k + 1] * nA;
+      t.lim = t.stride[0] * nA;
+      return t;
+    };
+    rout["R1.a"] = mk(R, "AA"); rout["R1.b"] = mk(R + n2, "AA");
+    rout["R2.aa"] = mk(R + 2 * n2, "AAAA"); rout["R2.ab"] = mk(R + 2 * n2 + n2 * n2, "AAAA");
+    rout["R2.bb"] = mk(R + 2 * n2 + 2 * n2 * n2, "AAAA");
+    static const Use r_h2 = rename_use(T.at("R"), "E1", "H1", "E2", "H2");
+    static const Use r_u = rename_use(T.at("R"), "T1", "U1", "T2", "U2");
+    X.use_id = 6;
+    X.run_use(T.at("R"), rout, nullptr);
+    X.use_id = 7;
+    X.run_use(r_h2, rout, nullptr);
+    X.use_id = 8;
+    X.run_use(r_u, rout, nullptr);
+    bo.R = R;
+  };
   // E(3)_a = <[H~(1), T(2)]> and E(3)_b = <[H~(2)_{1,2}, T(1)]>: without the pair
   // decomposition both scalars run as one grouped use when their temporaries fit (the
   // second-order tensors under their own names), else one after the other
@@ -2744,19 +2797,11 @@ static BodyOut body(Exec& X, OpLog& op, Pool& pool, const Shape& sh, const Input
     X.set("U2.aa", U2, "PPHH", 1); X.set("U2.ab", U2 + n4, "PPHH"); X.set("U2.bb", U2 + 2 * n4, "PPHH", 1);
     X.set("H1.a", H1, "PH"); X.set("H1.b", H1 + n1, "PH");
     X.set("H2.aa", H2, "PPHH"); X.set("H2.ab", H2 + n4, "PPHH"); X.set("H2.bb", H2 + 2 * n4, "PPHH");
-    auto renamed = [&](const char* from1, const char* to1, const char* from2, const char* to2) {
-      Use u = C0;
-      for (auto& P : u)
-        for (auto& f : P.f) {
-          if (f.tensor == from1) f.tensor = to1;
-          else if (f.tensor == from2) f.tensor = to2;
-        }
-      return u;
-    };
     X.use_id = 0;
-    const Use ua = renamed("T1", "U1", "T2", "U2"), ub = renamed("E1", "H1", "E2", "H2");
+    const Use ua = rename_use(C0, "T1", "U1", "T2", "U2"), ub = rename_use(C0, "E1", "H1", "E2", "H2");
     std::map<std::string, TensorRef> none_a, none_b;
     if (X.run_fused({&ua, &ub}, {&none_a, &none_b}, {energies + 1, energies + 2})) {
+      relax_stage();
       mark(ev, 6, st);
       bo.W1 = W1; bo.W2 = W2; bo.Z1 = Z1; bo.Z2 = Z2; bo.U1 = U1; bo.U2 = U2;
       return bo;
@@ -2810,6 +2855,7 @@ static BodyOut body(Exec& X, OpLog& op, Pool& pool, const Shape& sh, const Input
     double* pairs = bo.pairs;
     op([nC, P2, energies, pairs](hipStream_t s) { launch_pair_fold(nC, P2, energies, pairs, s); });
   }
+  relax_stage();
   mark(ev, 6, st);
   bo.W1 = W1; bo.W2 = W2; bo.Z1 = Z1; bo.Z2 = Z2; bo.U1 = U1; bo.U2 = U2;
   return bo;
@@ -3113,14 +3159,22 @@ static void replay_result(const Plan* plan, const double* e, bool pt3, double e0
 
 // feat_host / e2p_host (both or neither): the rest-only mode (RestMode) with the core-pair
 // features and second-order pair proxies copied to these host arrays
+// One-step relaxation request: the CAS determinant space and what to copy back.
+struct RelaxReq {
+  int n_alpha = 0, n_beta = 0;
+  const double* ci_guess = nullptr;
+  bool want_ci = false, want_blocks = false;
+  dsrg_cas::Out out;
+};
+
 static int run(const dsrg_problem* P, const dsrg_options* O, dsrg_result* R,
                const dsrg_intermediates* I, bool pt3, double* e3_pairs = nullptr,
                double* e3_rest = nullptr, int slot = 0, float* feat_host = nullptr,
-               double* e2p_host = nullptr) {
+               double* e2p_host = nullptr, RelaxReq* rq = nullptr) {
   if (!P || !R) throw Error(DSRG_E_ARG, "null problem or result");
   Setup S = setup(P, O, I, pt3, e3_pairs, e3_rest, slot);
   const bool rest_mode = feat_host != nullptr;
-  if (rest_mode) S.cacheable = false;
+  if (rest_mode || rq) S.cacheable = false;
   const Shape& sh = S.sh;
   const int nC = sh.nC, nA = sh.nA, nV = sh.nV, M = sh.M;
   const int prec = S.prec;
@@ -3213,7 +3267,7 @@ static int run(const dsrg_problem* P, const dsrg_options* O, dsrg_result* R,
   X.virt_batch = S.vb;
   mark(ev, 0, st);
   RestOut ro;
-  BodyOut bo = body(X, op, *pool, sh, in, ev, st, want_pairs, rest_mode ? &ro : nullptr);
+  BodyOut bo = body(X, op, *pool, sh, in, ev, st, want_pairs, rest_mode ? &ro : nullptr, rq != nullptr);
   if (rest_mode && nC > 0) {
     const size_t np = (size_t)nC * (nC + 1) / 2;
     HIPCHECK(hipMemcpyAsync(feat_host, ro.feat, np * 16 * sizeof(float), hipMemcpyDeviceToHost, st));
@@ -3278,6 +3332,18 @@ static int run(const dsrg_problem* P, const dsrg_options* O, dsrg_result* R,
     const size_t np = (size_t)nC * (nC + 1) / 2;
     if (np) memcpy(e3_pairs, pair_host.data(), np * sizeof(double));
     *e3_rest = pair_host[np];
+  }
+  if (rq) {
+    // the CAS eigenproblem of Hbar^[3]_{1,2} after the pipeline (its own host-driven loop)
+    dsrg_cas::In ci;
+    ci.nC = nC; ci.nA = nA; ci.nV = nV; ci.M = M;
+    ci.eps = in.eps; ci.B = in.B; ci.g1 = in.g1; ci.g2 = in.g2; ci.energies = in.energies; ci.R = bo.R;
+    ci.n_alpha = rq->n_alpha; ci.n_beta = rq->n_beta; ci.ci_guess = rq->ci_guess;
+    try {
+      dsrg_cas::relax(ci, st, rq->want_ci, rq->want_blocks, rq->out);
+    } catch (const dsrg_cas::Err& e) {
+      throw Error(e.code, e.what());
+    }
   }
 
   if (fresh && pool->bytes <= kMaxPlanBytes) {
@@ -3583,6 +3649,70 @@ int dsrg_pt3_pair_energies(const dsrg_problem* prob, const dsrg_options* opt, ds
 int dsrg_pt3_energy_ex(const dsrg_problem* prob, const dsrg_options* opt, dsrg_result* out,
                        const dsrg_intermediates* inter) {
   return dsrg::guarded([&] { return dsrg::run(prob, opt, out, inter, true); });
+}
+
+int dsrg_pt3_energy_relaxed(const dsrg_problem* prob, int32_t n_alpha, int32_t n_beta, const double* ci_guess,
+                            const dsrg_options* opt, dsrg_result* out, dsrg_relaxed_result* rel,
+                            const dsrg_relaxed_outputs* outs) {
+  return dsrg::guarded([&] {
+    using dsrg::Error;
+    if (!prob || !out || !rel) throw Error(DSRG_E_ARG, "null problem, result or relaxed result");
+    const int nA = prob->n_active;
+    if (nA < 0 || n_alpha < 0 || n_beta < 0 || n_alpha > nA || n_beta > nA)
+      throw Error(DSRG_E_ARG, "n_alpha and n_beta must lie in [0, n_active]");
+    auto binom = [](int n, int k) {
+      long long r = 1;
+      for (int i = 1; i <= k; ++i) r = r * (n - k + i) / i;
+      return r;
+    };
+    const long long ndet = binom(nA, n_alpha) * binom(nA, n_beta);
+    if (nA > 0 && prob->gamma1) {
+      std::vector<double> g((size_t)2 * nA * nA);
+      if (opt && (opt->flags & DSRG_F_DEVICE_PTRS))
+        HIPCHECK(hipMemcpy(g.data(), prob->gamma1, g.size() * sizeof(double), hipMemcpyDeviceToHost));
+      else
+        std::copy(prob->gamma1, prob->gamma1 + g.size(), g.begin());
+      double ta = 0, tb = 0;
+      for (int u = 0; u < nA; ++u) {
+        ta += g[(size_t)u * nA + u];
+        tb += g[(size_t)nA * nA + (size_t)u * nA + u];
+      }
+      // a non-finite gamma1 is left to the input checks of the pipeline
+      if (std::isfinite(ta) && std::isfinite(tb) &&
+          (std::fabs(ta - n_alpha) > 1e-8 || std::fabs(tb - n_beta) > 1e-8))
+        throw Error(DSRG_E_RDM, "the traces of gamma1 differ from n_alpha, n_beta");
+    }
+    if (ci_guess && nA > 0 && !dsrg::finite_host(ci_guess, (size_t)ndet))
+      throw Error(DSRG_E_NONFINITE, "non-finite value in ci_guess");
+    dsrg::RelaxReq rq;
+    rq.n_alpha = n_alpha;
+    rq.n_beta = n_beta;
+    rq.ci_guess = nA > 0 ? ci_guess : nullptr;
+    rq.want_ci = outs && outs->ci;
+    rq.want_blocks = outs && (outs->hbar1 || outs->hbar2 || outs->cas_c);
+    dsrg_result r;
+    const int rc = dsrg::run(prob, opt, &r, nullptr, true, nullptr, nullptr, 0, nullptr, nullptr, &rq);
+    dsrg_relaxed_result x;
+    memset(&x, 0, sizeof(x));
+    x.e_relaxed = prob->e0 + rq.out.lambda;
+    x.e_unrelaxed = r.e_total;
+    x.cas_const = rq.out.cconst;
+    x.residual = rq.out.residual;
+    x.n_det = rq.out.n_det;
+    x.iterations = rq.out.iterations;
+    x.converged = rq.out.converged;
+    if (outs) {
+      if (outs->ci && !rq.out.ci.empty()) std::copy(rq.out.ci.begin(), rq.out.ci.end(), outs->ci);
+      if (nA > 0) {
+        if (outs->hbar1) std::copy(rq.out.h1.begin(), rq.out.h1.end(), outs->hbar1);
+        if (outs->hbar2) std::copy(rq.out.h2.begin(), rq.out.h2.end(), outs->hbar2);
+        if (outs->cas_c) std::copy(rq.out.c.begin(), rq.out.c.end(), outs->cas_c);
+      }
+    }
+    *out = r;
+    *rel = x;
+    return rc;
+  });
 }
 
 const char* dsrg_last_error(void) { return dsrg::g_last_error.c_str(); }

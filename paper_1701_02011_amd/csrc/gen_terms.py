@@ -26,10 +26,15 @@ theorem and does not reprint the term list (Sec. III); this script re-derives it
 4. Products with identical factors are computed once and scattered to every output
    position (common-subexpression grouping).
 
-Three uses are emitted:
+Four uses are emitted:
   C0  the scalar <[X, T]> for X given by its de-excitation block (tensors E1, E2);
   W   the excitation block of [V, A]_{1,2} = [V,T] + [V,T]^+ for the two-body Hamiltonian V;
-  Z   the excitation block of [Y, A]_{1,2} for the non-diagonal operator Y (Y1, Y2).
+  Z   the excitation block of [Y, A]_{1,2} for the non-diagonal operator Y (Y1, Y2);
+  R   the active block of [X, A]_{1,2} = [X,T] + [X,T]^+ for a Hermitian X given, as in C0,
+      by its de-excitation block (outputs R1 [A][A], R2 [A]^4).  Every amplitude has a
+      non-active index, which a contraction must remove when all output indices are
+      active: a virtual one meets an annihilator of X, a core one a creator, so only the
+      de-excitation block of X (creators in H, annihilators in P) enters.
 Index spaces: C core, A active, V virtual, H = C+A, P = A+V, G all (orbital order
 [C|A|V] makes each a contiguous range).  Storage (C-convention, excitation order):
 T1/E1/Y1/O1 [P][H], T2/E2/Y2/O2 [P][P][H][H], gA/eA [A][A], L2 [A]^4, L3 [A]^6.
@@ -249,7 +254,7 @@ SETS = {"C": {"C"}, "A": {"A"}, "V": {"V"}, "H": {"C", "A"}, "P": {"A", "V"}, "G
 CODE = {frozenset(v): k for k, v in SETS.items()}
 STORAGE = {"T1": "PH", "T2": "PPHH", "E1": "PH", "E2": "PPHH", "Y1": "PH", "Y2": "PPHH",
            "L2": "AAAA", "L3": "AAAAAA", "gA": "AA", "eA": "AA", "v": "GGGG", "J": "GGGG",
-           "O1": "PH", "O2": "PPHH"}
+           "O1": "PH", "O2": "PPHH", "R1": "AA", "R2": "AAAA"}
 
 
 def _inter(a, b):
@@ -293,7 +298,7 @@ def _spin_terms(coef, facs, ospins):
 
 
 def _xpieces(use):
-    if use == "C0":
+    if use in ("C0", "R"):
         return {1: [lambda L: _Fac("E1", L[1] + L[0], 1)],
                 2: [lambda L: _Fac("E2", L[2] + L[3] + L[0] + L[1], 2)]}
     if use == "W":
@@ -314,17 +319,21 @@ def _conv(nm, ls):
     return _Fac(nm, ls, 1)
 
 
-def _out_entries(out, rank, blk):
+def _out_entries(out, rank, blk, active=False):
+    """Output positions of a term's plain-order output letters: the term itself ("exc") or
+    its adjoint ("dex"), over the excitation block (creators P, annihilators H) or, with
+    active=True, over the active block (every letter A)."""
     if rank == 0:
         return [("", 1.0, {})]
+    up, lo = ("A", "A") if active else ("P", "H")
     if rank == 1:
         c, a = out
-        return [(c + a, 1.0, {c: "P", a: "H"})] if blk == "exc" else [(a + c, 1.0, {c: "H", a: "P"})]
+        return [(c + a, 1.0, {c: up, a: lo})] if blk == "exc" else [(a + c, 1.0, {c: lo, a: up})]
     c1, c2, a1, a2 = out
     if blk == "exc":
-        req, (x1, x2, y1, y2) = {c1: "P", c2: "P", a1: "H", a2: "H"}, (c1, c2, a2, a1)
+        req, (x1, x2, y1, y2) = {c1: up, c2: up, a1: lo, a2: lo}, (c1, c2, a2, a1)
     else:
-        req, (x1, x2, y1, y2) = {c1: "H", c2: "H", a1: "P", a2: "P"}, (a2, a1, c1, c2)
+        req, (x1, x2, y1, y2) = {c1: lo, c2: lo, a1: up, a2: up}, (a2, a1, c1, c2)
     return [(x1 + x2 + y1 + y2, 1.0, req), (x2 + x1 + y1 + y2, -1.0, req),
             (x1 + x2 + y2 + y1, -1.0, req), (x2 + x1 + y2 + y1, 1.0, req)]
 
@@ -337,6 +346,8 @@ def spatial_entries(so_terms, use, ranks):
     """(coef, out_tensor, out_block, out_letters, [(tensor, block, letters)], spaces)."""
     ents = []
     xp = _xpieces(use)
+    active = use == "R"
+    otn = "R" if active else "O"
     for (rx, rt), terms in so_terms.items():
         for coef, fac, out in terms:
             rank = len(out) // 2
@@ -344,7 +355,7 @@ def spatial_entries(so_terms, use, ranks):
                 continue
             for xb in xp[rx]:
                 for blk in (("exc", "dex") if rank else ("exc",)):
-                    for olets, osign, req in _out_entries(out, rank, blk):
+                    for olets, osign, req in _out_entries(out, rank, blk, active):
                         facs = [xb(ls) if nm in ("X", "X1") else _conv(nm, ls) for nm, ls in fac]
                         sp = dict(req)
                         ok = True
@@ -357,7 +368,7 @@ def spatial_entries(so_terms, use, ranks):
                         if not ok:
                             continue
                         if rank:
-                            for ax, l in zip(STORAGE["O%d" % rank], olets):
+                            for ax, l in zip(STORAGE["%s%d" % (otn, rank)], olets):
                                 new = _inter(sp[l], ax)
                                 if new is None:
                                     ok = False
@@ -379,8 +390,8 @@ def spatial_entries(so_terms, use, ranks):
                                         pieces = ([(cc, fs + [("J", "", p + r + q + s)]) for cc, fs in pieces]
                                                   + [(-cc, fs + [("J", "", p + s + q + r)]) for cc, fs in pieces])
                                 for cc, fs in pieces:
-                                    ents.append((cc, "O%d" % rank if rank else "E", bname, olets, fs,
-                                                 dict(sp)))
+                                    ents.append((cc, "%s%d" % (otn, rank) if rank else "E", bname,
+                                                 olets, fs, dict(sp)))
     return ents
 
 
@@ -511,7 +522,7 @@ def emit(tables, path):
 def build_tables():
     so = spin_orbital_terms()
     tables = {}
-    for use, ranks in (("C0", (0,)), ("W", (1, 2)), ("Z", (1, 2))):
+    for use, ranks in (("C0", (0,)), ("W", (1, 2)), ("Z", (1, 2)), ("R", (1, 2))):
         tables[use] = group_products(merge_spatial(spatial_entries(so, use, ranks)))
     return so, tables
 

@@ -5,6 +5,7 @@ Calls only ``oracle/`` (and the shared input generator).  Usage:
     python tests/golden/make_golden.py small-pairs    # core-pair parts of E(3), s = 0.5
     python tests/golden/make_golden.py medium         # energies from the block-sparse DF level
     python tests/golden/make_golden.py large          #   (oracle/dsrg_df.py; hours of CPU)
+    python tests/golden/make_golden.py relax          # one-step relaxed energies (oracle/relax.py)
 Writes tests/golden/<name>_s<s>.json with E(2), E(3) and its two parts (and, for small,
 sampled intermediates), or tests/golden/small_pairs_s0.5.json with the core-pair
 decomposition of E(3).
@@ -89,9 +90,56 @@ def main_pairs():
     print(path, len(pairs), rest, "%.0fs" % out["oracle_seconds"], flush=True)
 
 
+# relaxed-energy cases: (name, make_problem arguments or a workload name, s, f_sigma, e0)
+RELAX_CASES = [("cas77", dict(n_core=0, n_active=7, n_virtual=1, n_aux=6, seed=41), 0.5, 0.03, -1.5),
+               ("cas66", dict(n_core=1, n_active=6, n_virtual=2, n_aux=8, seed=42), 0.5, 0.03, -2.0),
+               ("small", "small", 0.5, 0.0, 0.0)]
+
+
+def relax_problem(case):
+    import dataclasses
+    from paper_1701_02011_amd.synth import make_problem
+    name, args, s, f_sigma, e0 = case
+    if isinstance(args, str):
+        p = make_config(args, s=s)
+    else:
+        p = make_problem(s=s, f_sigma=f_sigma, **args)
+    return dataclasses.replace(p, e0=e0)
+
+
+def main_relax():
+    """Relaxed energies (Sec. II.B Eq. E_relaxed), the CAS constant, the one-body active block
+    of Hbar^[3]_{1,2} and seeded samples of its two-body blocks, in the library's layout."""
+    from oracle import relax
+    cases = []
+    for case in RELAX_CASES:
+        p = relax_problem(case)
+        t = time.time()
+        r = relax.relaxed_energy(p)
+        nA = p.n_active
+        a, b = slice(0, nA), slice(nA, 2 * nA)
+        h1 = np.stack([r.hbar.h1[a, a], r.hbar.h1[b, b]])
+        h2 = np.stack([r.hbar.h2[a, a, a, a], r.hbar.h2[a, b, a, b], r.hbar.h2[b, b, b, b]])
+        rng = np.random.default_rng(777)
+        flat = rng.choice(h2.size, size=min(300, h2.size), replace=False)
+        idx = np.array(np.unravel_index(flat, h2.shape)).T
+        cases.append(dict(name=case[0], args=case[1], s=case[2], f_sigma=case[3], e0=case[4],
+                          e_relaxed=r.e_relaxed, e_unrelaxed=r.e_unrelaxed, cas_const=r.const,
+                          hbar1=h1.tolist(), hbar2_index=idx.tolist(),
+                          hbar2_value=h2[tuple(idx.T)].tolist(), oracle_seconds=time.time() - t))
+        print(case[0], r.e_relaxed, r.e_unrelaxed, "%.0fs" % cases[-1]["oracle_seconds"], flush=True)
+    out = dict(cases=cases, source="oracle/relax.py (FP64, spin-orbital, MK-GNO engine, Fock-space CAS)")
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "relax.json")
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+    print(path, flush=True)
+
+
 if __name__ == "__main__":
     arg = sys.argv[1] if len(sys.argv) > 1 else "small"
     if arg == "small-pairs":
         main_pairs()
+    elif arg == "relax":
+        main_relax()
     else:
         main(arg)

@@ -14,7 +14,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 INC = os.path.join(ROOT, "paper_1701_02011_amd", "csrc", "dsrg_terms.inc")
 STORAGE = {"T1": "PH", "T2": "PPHH", "E1": "PH", "E2": "PPHH", "Y1": "PH", "Y2": "PPHH",
            "L2": "AAAA", "L3": "AAAAAA", "gA": "AA", "eA": "AA", "O1": "PH", "O2": "PPHH",
-           "G2": "PPHH"}
+           "G2": "PPHH", "R1": "AA", "R2": "AAAA"}
 
 
 def pair_use(c0):
@@ -305,4 +305,115 @@ def pipeline(p, uses=None):
             pairs[(i, j)] = P2[i, i] if i == j else P2[i, j] + P2[j, i]
     return dict(e2=e2, e3=e3a + e3b, e3a=e3a, e3b=e3b, t1=t1, t2=t2, u1=u1, u2=u2,
                 O1=O1, O2=O2, Z=Z, H1=H1, H2=H2, pairs=pairs,
-                pair_rest=e3a + e3b - sum(pairs.values()))
+                pair_rest=e3a + e3b - sum(pairs.values()), tens=tens)
+
+
+def relaxation(p, e, uses=None):
+    """The library's relaxation steps after E(3): active blocks of Hbar^[3]_{1,2} from the
+    use R (H~(1) and H~(2)_{1,2} with the first-order amplitudes, H~(1) with the second
+    order), the spin-blocked CAS operator and the lowest eigenvalue of its determinant
+    matrix (Slater-Condon rules).  Returns dict(h1, h2, const, c, w, lam, M)."""
+    uses = uses or load_table()
+    nC, nA, nV = p.n_core, p.n_active, p.n_virtual
+    if nA == 0:
+        return dict(h1=None, h2=None, const=e["e2"] + e["e3"], c=None, w=None,
+                    lam=e["e2"] + e["e3"], M=np.full((1, 1), e["e2"] + e["e3"]))
+    d = Dims(nC, nA, nV)
+    tens = e["tens"]
+    R = {"R1": {k: np.zeros((nA, nA)) for k in "ab"},
+         "R2": {k: np.zeros((nA,) * 4) for k in ("aa", "ab", "bb")}}
+    run_use(uses["R"], d, p.B, tens, R)
+    run_use(uses["R"], d, p.B, dict(tens, E1=e["H1"], E2=e["H2"]), R)
+    run_use(uses["R"], d, p.B, dict(tens, T1=e["u1"], T2=e["u2"]), R)
+    A = slice(nC, nC + nA)
+    J = np.einsum("Qux,Qvy->uvxy", p.B[:, A, A], p.B[:, A, A])          # (ux|vy)
+    vaa = J - J.transpose(0, 1, 3, 2)
+    h1 = {k: np.diag(p.eps[A]) + 0.5 * R["R1"][k] for k in "ab"}
+    h2 = {"aa": vaa + 0.5 * R["R2"]["aa"], "ab": J + 0.5 * R["R2"]["ab"],
+          "bb": vaa + 0.5 * R["R2"]["bb"]}
+    g = {"a": p.gamma1[0], "b": p.gamma1[1]}
+    g2 = {"aa": p.gamma2[0], "ab": p.gamma2[1], "bb": p.gamma2[2]}
+    gg = lambda x, y: np.einsum("ux,vy->uvxy", x, y)
+    const = e["e2"] + e["e3"]
+    for sk, bk in (("a", "aa"), ("b", "bb")):
+        const -= np.sum(h1[sk] * g[sk])
+        const -= 0.25 * np.sum(h2[bk] * g2[bk]) - np.sum(h2[bk] * gg(g[sk], g[sk]))
+    const -= np.sum(h2["ab"] * g2["ab"]) - 2.0 * np.sum(h2["ab"] * gg(g["a"], g["b"]))
+    c = {"a": h1["a"] - np.einsum("uxvy,xy->uv", h2["aa"], g["a"])
+              - np.einsum("uxvy,xy->uv", h2["ab"], g["b"]),
+         "b": h1["b"] - np.einsum("uxvy,xy->uv", h2["bb"], g["b"])
+              - np.einsum("xuyv,xy->uv", h2["ab"], g["a"])}
+    M = cas_matrix(nA, p.n_alpha, p.n_beta, const, c, h2)
+    lam = float(np.linalg.eigvalsh(M)[0])
+    return dict(h1=h1, h2=h2, const=const, c=c, w=h2, lam=lam, M=M)
+
+
+def _w_so(w, nA, p, q, r, s):
+    """Spin-orbital <pq||rs>-type element (index = spin * nA + orbital) of the spin blocks."""
+    sp = [x // nA for x in (p, q, r, s)]
+    o = [x % nA for x in (p, q, r, s)]
+    if sp[0] == sp[1]:
+        if not (sp[2] == sp[0] and sp[3] == sp[0]):
+            return 0.0
+        return w["aa" if sp[0] == 0 else "bb"][o[0], o[1], o[2], o[3]]
+    if sp[0] == 0:     # p alpha, q beta
+        if sp[2] == 0 and sp[3] == 1:
+            return w["ab"][o[0], o[1], o[2], o[3]]
+        if sp[2] == 1 and sp[3] == 0:
+            return -w["ab"][o[0], o[1], o[3], o[2]]
+        return 0.0
+    if sp[2] == 1 and sp[3] == 0:  # p beta, q alpha
+        return w["ab"][o[1], o[0], o[3], o[2]]
+    if sp[2] == 0 and sp[3] == 1:
+        return -w["ab"][o[1], o[0], o[2], o[3]]
+    return 0.0
+
+
+def _apply(ops, det):
+    """Apply a string of (create?, spin orbital) from right to left to a bit string;
+    returns (sign, det) or (0, None)."""
+    sign = 1
+    for cre, k in reversed(ops):
+        occ = (det >> k) & 1
+        if cre == occ:
+            return 0, None
+        if bin(det & ((1 << k) - 1)).count("1") % 2:
+            sign = -sign
+        det ^= 1 << k
+    return sign, det
+
+
+def cas_matrix(nA, na, nb, const, c, w):
+    """Determinant matrix of const + sum c a+a + 1/4 sum w a+a+aa (Slater-Condon rules),
+    determinants |I_alpha J_beta> in lexicographic string order, alpha index slowest."""
+    import itertools
+    sa = [sum(1 << o for o in t) for t in itertools.combinations(range(nA), na)]
+    sb = [sum(1 << o for o in t) for t in itertools.combinations(range(nA), nb)]
+    dets = [a | (b << nA) for a in sa for b in sb]
+    n2 = 2 * nA
+    csp = np.zeros((n2, n2))
+    csp[:nA, :nA] = c["a"]
+    csp[nA:, nA:] = c["b"]
+    M = np.zeros((len(dets), len(dets)))
+    for j, D in enumerate(dets):
+        occ = [k for k in range(n2) if (D >> k) & 1]
+        for i, Dp in enumerate(dets):
+            diff = D ^ Dp
+            nd = bin(diff).count("1")
+            if nd == 0:
+                val = const + sum(csp[k, k] for k in occ)
+                val += 0.5 * sum(_w_so(w, nA, k, l, k, l) for k in occ for l in occ)
+            elif nd == 2:
+                q = [k for k in occ if not (Dp >> k) & 1][0]
+                pp = [k for k in range(n2) if (Dp >> k) & 1 and not (D >> k) & 1][0]
+                sg, _ = _apply([(1, pp), (0, q)], D)
+                val = sg * (csp[pp, q] + sum(_w_so(w, nA, pp, r, q, r) for r in occ))
+            elif nd == 4:
+                rs = [k for k in occ if not (Dp >> k) & 1]
+                pq = [k for k in range(n2) if (Dp >> k) & 1 and not (D >> k) & 1]
+                sg, _ = _apply([(1, pq[0]), (1, pq[1]), (0, rs[1]), (0, rs[0])], D)
+                val = sg * _w_so(w, nA, pq[0], pq[1], rs[0], rs[1])
+            else:
+                val = 0.0
+            M[i, j] = val
+    return M

@@ -211,3 +211,27 @@ def test_active_rdms_argument_checks(lib):
                                         None) == _lib.DSRG_E_ARG
     assert _lib.load().dsrg_active_rdms(None, 3, 1, 1, None, g1.ctypes.data, g2.ctypes.data,
                                         None) == _lib.DSRG_E_ARG
+
+
+def test_relaxed_argument_checks(lib):
+    """dsrg_pt3_energy_relaxed: electron numbers outside [0, nA] (DSRG_E_ARG), densities of
+    another electron count (DSRG_E_RDM), a non-finite start vector (DSRG_E_NONFINITE) and
+    null results (DSRG_E_ARG) are rejected before any device work."""
+    assert ctypes.sizeof(_lib.RelaxedResult) == 4 * 8 + 4 * 4
+    assert ctypes.sizeof(_lib.RelaxedOutputs) == 4 * 8
+    p = make_problem(1, 3, 2, 6, seed=1)
+    keep = []
+    st, fl = _lib._problem_struct(p, keep)
+    r, x, o = _lib.Result(), _lib.RelaxedResult(), _lib.RelaxedOutputs()
+    f = lib.dsrg_pt3_energy_relaxed
+    opt = ctypes.byref(_lib._options(fl))
+    assert f(ctypes.byref(st), 4, 1, None, opt, ctypes.byref(r), ctypes.byref(x), ctypes.byref(o)) == _lib.DSRG_E_ARG
+    assert f(ctypes.byref(st), -1, 1, None, opt, ctypes.byref(r), ctypes.byref(x), ctypes.byref(o)) == _lib.DSRG_E_ARG
+    assert f(ctypes.byref(st), p.n_alpha, p.n_beta, None, opt, ctypes.byref(r), None, None) == _lib.DSRG_E_ARG
+    # make_problem(nA = 3) has 2 alpha and 1 beta electrons
+    assert (p.n_alpha, p.n_beta) == (2, 1)
+    assert f(ctypes.byref(st), 1, 2, None, opt, ctypes.byref(r), ctypes.byref(x), ctypes.byref(o)) == _lib.DSRG_E_RDM
+    bad = np.array(p.ci, dtype=np.float64)
+    bad[0, 0] = np.nan
+    assert f(ctypes.byref(st), 2, 1, bad.ctypes.data, opt, ctypes.byref(r), ctypes.byref(x),
+             ctypes.byref(o)) == _lib.DSRG_E_NONFINITE

@@ -173,3 +173,29 @@ def test_collapsed_antisymmetriser_images_give_the_same_commutators():
     for k in ("aa", "ab", "bb"):
         assert np.abs(a["O2"][k] - b["O2"][k]).max() <= 1e-12 * max(1.0, np.abs(a["O2"][k]).max()), k
     assert abs(a["e3"] - b["e3"]) <= 1e-12 * max(1.0, abs(a["e3"]))
+
+
+@pytest.mark.parametrize("shape,seed,s", [((1, 2, 3, 10), 11, 0.6), ((1, 3, 2, 8), 7, 0.6),
+                                          ((2, 2, 4, 9), 5, 1.3), ((0, 3, 3, 7), 19, 0.8),
+                                          ((1, 4, 2, 8), 3, 0.5), ((2, 0, 4, 9), 17, 0.4)])
+def test_relaxation_steps_match_oracle(shape, seed, s):
+    """The library's relaxation steps (use R on H~(1), H~(2)_{1,2} and both orders of
+    amplitudes, spin-blocked de-normal ordering, Slater-Condon determinant matrix), run by
+    the emulator, give the oracle's active blocks of Hbar^[3]_{1,2}, CAS constant and
+    relaxed energy (Sec. II.B Eq. E_relaxed; App. A)."""
+    from oracle import relax
+    p = make_problem(*shape, seed=seed, s=s)
+    e = pipeline(p)
+    r = table_emulator.relaxation(p, e)
+    o = relax.relaxed_energy(p)
+    assert abs(r["lam"] - o.e_relaxed) < 1e-12 * max(1.0, abs(o.e_relaxed))
+    nA = p.n_active
+    if nA == 0:
+        return
+    a, b = slice(0, nA), slice(nA, 2 * nA)
+    hb = o.hbar
+    for k, sl in (("a", a), ("b", b)):
+        assert np.abs(r["h1"][k] - hb.h1[sl, sl]).max() < 1e-12
+    for k, (x, y) in (("aa", (a, a)), ("ab", (a, b)), ("bb", (b, b))):
+        assert np.abs(r["h2"][k] - hb.h2[x, y, x, y]).max() < 1e-12
+    assert abs(r["const"] - o.const) < 1e-12
