@@ -53,7 +53,7 @@ extern "C" {
 #define DSRG_E_NONFINITE (-2)   /* NaN or Inf in eps, B or the densities */
 #define DSRG_E_OOM (-3)         /* device allocation failed or workspace_cap too small */
 #define DSRG_E_HIP (-4)         /* HIP runtime error (message in dsrg_last_error) */
-#define DSRG_E_UNSUPPORTED (-5) /* option not built (unknown precision, nA > 8) */
+#define DSRG_E_UNSUPPORTED (-5) /* option not built (unknown precision, nA > 16) */
 #define DSRG_E_RDM (-6)         /* gamma1 not symmetric, or gamma2 not Hermitian (uv <-> xy) or,
                                    in its same-spin blocks, not antisymmetric in u <-> v and
                                    x <-> y, beyond 1e-10 */
@@ -329,13 +329,36 @@ typedef struct {
 /* E(2), E(3) (into *out, as dsrg_pt3_energy) and the relaxed energy (into *rel).  ci_guess
    (host, may be NULL): a start vector for the Davidson iterations, normally the reference's
    CI vector; unit vectors on the lowest diagonal elements are always added.  Returns
-   DSRG_E_ARG for n_alpha or n_beta outside [0, nA] or null out/rel, DSRG_E_RDM when the
+   DSRG_E_ARG for n_alpha or n_beta outside [0, nA] or null out/rel, DSRG_E_UNSUPPORTED for
+   more than 11585 determinants (the matrix is held densely), DSRG_E_RDM when the
    traces of gamma1 differ from n_alpha, n_beta by more than 1e-8, DSRG_E_NONFINITE for a
    non-finite ci_guess, else as dsrg_pt3_energy.  Runs without a plan; ci_guess and the
    outputs are host memory whatever opt->flags says. */
 int dsrg_pt3_energy_relaxed(const dsrg_problem* prob, int32_t n_alpha, int32_t n_beta, const double* ci_guess,
                             const dsrg_options* opt, dsrg_result* out, dsrg_relaxed_result* rel,
                             const dsrg_relaxed_outputs* outs);
+
+/* ---- Dyall's zeroth-order Hamiltonian: active-to-virtual doubles (App. B, Eq. t2_aavv) ----
+   With the two-body interaction among active orbitals moved into H(0) and s -> inf, the
+   first-order amplitudes t_{ef}^{uv} that move two electrons from active (u, v) to virtual
+   (e, f) orbitals solve, for each virtual pair, a linear system that couples all active
+   pairs of that virtual pair:
+     (e_u + e_v - e_e - e_f) t^{uv} + 1/2 sum_xy <xy||uv> t^{xy} - sum_xyz <xy||uv> t^{xz} gamma^y_z = <ef||uv>
+   (spin-orbital sums over active orbitals, gamma^y_z = <a+_y a_z>).  The library solves
+   every block exactly (Gaussian elimination with partial pivoting, FP64, one workgroup per
+   virtual pair and spin block) after building (eu|fv) and the active integrals from B on
+   the contraction kernel.  Reads eps, B, n_aux and gamma1 of prob (gamma2, gamma3,
+   f_offdiag, s and e0 are not used; s must still be > 0).
+   t_out [3][nV][nV][nA][nA]: spin blocks aa (e, f, u, v alpha), ab (e, u alpha; f, v beta),
+   bb, each t[e][f][u][v], antisymmetric in (e, f) and in (u, v) within aa and bb.
+   dmin (may be NULL): the smallest |shifted denominator| over all blocks, i.e. the smallest
+   magnitude of a diagonal element of the systems (App. B Eq. full_preconditioner, read as
+   that diagonal).  Host or device arrays as DSRG_F_DEVICE_PTRS in opt->flags says; runs on
+   opt->stream and synchronises it.  Returns DSRG_E_UNSUPPORTED unless 1 <= nA <= 9 (a block
+   of nA^2 unknowns is factorised in LDS), DSRG_E_INTRUDER when a block is singular (a
+   pivot below 1e-13 of its largest element; the outputs are then left untouched with host
+   arrays), else the checks and codes of dsrg_pt3_energy. */
+int dsrg_dyall_aavv(const dsrg_problem* prob, const dsrg_options* opt, double* t_out, double* dmin);
 
 /* As dsrg_pt3_energy, and copies the requested intermediates to host memory. */
 int dsrg_pt3_energy_ex(const dsrg_problem* prob, const dsrg_options* opt, dsrg_result* out,

@@ -9,6 +9,7 @@
 #include "../../include/dsrg.h"
 #include "../../include/dsrg_testing.h"
 #include "cas.h"
+#include "dyall.h"
 #include "kernels.h"
 
 #include <hip/hip_runtime.h>
@@ -3014,7 +3015,7 @@ static Setup setup(const dsrg_problem* P, const dsrg_options* O, const dsrg_inte
   if (!(P->s > 0.0)) throw Error(DSRG_E_ARG, "s must be > 0");
   if (!P->eps || !P->B) throw Error(DSRG_E_ARG, "null eps or B");
   if (nA > 0 && (!P->gamma1 || !P->gamma2)) throw Error(DSRG_E_ARG, "null gamma1/gamma2 with nA > 0");
-  if (nA > 8) throw Error(DSRG_E_UNSUPPORTED, "active spaces above 8 orbitals are not built");
+  if (nA > 16) throw Error(DSRG_E_UNSUPPORTED, "active spaces above 16 orbitals are not built");
   if (O && O->precision != DSRG_PRECISION_FP64 && O->precision != DSRG_PRECISION_FP32 &&
       O->precision != DSRG_PRECISION_BF16X3)
     throw Error(DSRG_E_UNSUPPORTED, "unknown precision");
@@ -3651,6 +3652,56 @@ int dsrg_pt3_energy_ex(const dsrg_problem* prob, const dsrg_options* opt, dsrg_r
   return dsrg::guarded([&] { return dsrg::run(prob, opt, out, inter, true); });
 }
 
+int dsrg_dyall_aavv(const dsrg_problem* prob, const dsrg_options* opt, double* t_out, double* dmin) {
+  return dsrg::guarded([&] {
+    using namespace dsrg;
+    if (!prob || !t_out) throw Error(DSRG_E_ARG, "null problem or t_out");
+    if (prob->n_active == 0 || prob->n_active > dsrg_dyall::kMaxActive)
+      throw Error(DSRG_E_UNSUPPORTED, "the Dyall active-to-virtual solve takes 1 to 9 active orbitals");
+    const Setup S = setup(prob, opt, nullptr, false, nullptr, nullptr, 0);
+    const Shape& sh = S.sh;
+    const int nC = sh.nC, nA = sh.nA, nV = sh.nV;
+    hipStream_t st = S.st;
+    Pool pool(st);
+    Inputs in = alloc_inputs(pool, sh);
+    load_inputs(prob, S.devptr, sh, in, &prob->s, st);
+    OpLog op{st, nullptr};
+    Exec X(Dims{nC, nA, nV}, st, pool, op, in.B, sh.M, S.cap, false);
+    double* Jvava = X.jblock("VAVA");   // [e][u][f][v] = (eu|fv)
+    double* Jaaaa = X.jblock("AAAA");   // [x][u][y][v] = (xu|yv)
+    const size_t np = (size_t)nA * (nA - 1) / 2, n2 = (size_t)nA * nA;
+    double* Kaa = pool.alloc(np * np);
+    double* Kbb = pool.alloc(np * np);
+    double* Kab = pool.alloc(n2 * n2);
+    const size_t nt = 3 * (size_t)nV * nV * n2;
+    double* t = S.devptr ? t_out : pool.alloc(nt);
+    const long long nsys = 3LL * nV * nV;
+    double* dm = pool.alloc((size_t)std::max<long long>(nsys, 1) + 2);
+    int* sing = reinterpret_cast<int*>(dm + std::max<long long>(nsys, 1) + 1);
+    launch_fill(dm + std::max<long long>(nsys, 1), 2, 0.0, st);
+    dsrg_dyall::launch_operator(nA, Jaaaa, in.g1, Kaa, Kbb, Kab, st);
+    HIPCHECK(hipGetLastError());
+    dsrg_dyall::launch_solve(nC, nA, nV, in.eps, Jvava, Kaa, Kbb, Kab, t, dm, sing, st);
+    HIPCHECK(hipGetLastError());
+    double* dres = dm + std::max<long long>(nsys, 1);   // the minimum over all blocks
+    int hsing = 0;
+    HIPCHECK(hipMemcpyAsync(&hsing, sing, sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHECK(hipStreamSynchronize(st));
+    if (hsing) throw Error(DSRG_E_INTRUDER, "a block of the active-to-virtual system is singular");
+    if (nsys > 0) dsrg_dyall::launch_min(dm, nsys, dres, st);
+    else launch_fill(dres, 1, INFINITY, st);
+    HIPCHECK(hipGetLastError());
+    double hmin = INFINITY;
+    HIPCHECK(hipMemcpyAsync(&hmin, dres, sizeof(double), hipMemcpyDeviceToHost, st));
+    if (!S.devptr) HIPCHECK(hipMemcpyAsync(t_out, t, nt * sizeof(double), hipMemcpyDeviceToHost, st));
+    else if (dmin) HIPCHECK(hipMemcpyAsync(dmin, dres, sizeof(double), hipMemcpyDeviceToDevice, st));
+    HIPCHECK(hipStreamSynchronize(st));
+    HIPCHECK(hipGetLastError());
+    if (dmin && !S.devptr) *dmin = hmin;
+    return DSRG_OK;
+  });
+}
+
 int dsrg_pt3_energy_relaxed(const dsrg_problem* prob, int32_t n_alpha, int32_t n_beta, const double* ci_guess,
                             const dsrg_options* opt, dsrg_result* out, dsrg_relaxed_result* rel,
                             const dsrg_relaxed_outputs* outs) {
@@ -3666,6 +3717,8 @@ int dsrg_pt3_energy_relaxed(const dsrg_problem* prob, int32_t n_alpha, int32_t n
       return r;
     };
     const long long ndet = binom(nA, n_alpha) * binom(nA, n_beta);
+    // the determinant matrix is held densely: at most 2^27 elements (1 GiB)
+    if (ndet > 11585) throw Error(DSRG_E_UNSUPPORTED, "CAS spaces above 11585 determinants are not built");
     if (nA > 0 && prob->gamma1) {
       std::vector<double> g((size_t)2 * nA * nA);
       if (opt && (opt->flags & DSRG_F_DEVICE_PTRS))

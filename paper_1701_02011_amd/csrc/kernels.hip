@@ -1486,8 +1486,8 @@ void launch_scatter(const ScatterDesc& d0, const double* src, double* out, hipSt
 // ---------------------------------------------------------------------------
 // Workgroup row blockIdx.x is one upper (creation) tuple, so its spins and block offset are
 // uniform; threads take the lower tuples.  The parity of the stable alpha-first sort of a
-// tuple is its number of (beta, alpha) pairs in that order.  Indices fit 32 bits:
-// (2 nA)^6 < 2^31 for nA <= 8 (larger active spaces are rejected).
+// tuple is its number of (beta, alpha) pairs in that order.  Row and column indices fit
+// 32 bits: (2 nA)^3 <= 2^15 for nA <= 16 (larger active spaces are rejected).
 template <int R>
 __device__ __forceinline__ void expand_rdm_row(int nA, const double* __restrict__ blocks, double* __restrict__ so,
                                                int row, int l) {
@@ -1547,12 +1547,15 @@ __global__ void expand_rdm_kernel(int nA, const double* __restrict__ blocks, dou
 }
 
 // gamma1 and gamma2 in one launch: rows [0, 2 nA) are gamma1's, the next (2 nA)^2 gamma2's
-// (each row has at most (2 nA)^2 <= 256 lower tuples)
+// (a row has at most (2 nA)^2 <= 1024 lower tuples, taken 256 at a time)
 __global__ void expand_rdm12_kernel(int nA, const double* __restrict__ g1, double* __restrict__ G1,
                                     const double* __restrict__ g2, double* __restrict__ G2) {
   const int n2 = 2 * nA;
-  if ((int)blockIdx.x < n2) expand_rdm_row<1>(nA, g1, G1, blockIdx.x, threadIdx.x);
-  else expand_rdm_row<2>(nA, g2, G2, blockIdx.x - n2, threadIdx.x);
+  if ((int)blockIdx.x < n2) {
+    expand_rdm_row<1>(nA, g1, G1, blockIdx.x, threadIdx.x);
+    return;
+  }
+  for (int l = threadIdx.x; l < n2 * n2; l += blockDim.x) expand_rdm_row<2>(nA, g2, G2, blockIdx.x - n2, l);
 }
 
 void launch_expand_rdm12(int nA, const double* g1, double* G1, const double* g2, double* G2, hipStream_t st) {
@@ -1589,14 +1592,14 @@ __global__ void cumulant2_kernel(int n, const double* __restrict__ G1, const dou
 // lambda3 = G3 - det(g g g) - sum_{ij} (-1)^(i+j) g[P_i, S_j] lambda2[P\i, S\j]
 // Workgroup row blockIdx.x is the upper triple P (uniform), threads take the lower triples S;
 // the three rows g[P_a][*] and the three slices lambda2[P\a][*][*] the row needs are staged
-// in LDS first (n <= 16).  G3[P][S] is read from the spin blocks g3 the way
+// in LDS first (n = 2 nA <= 32).  G3[P][S] is read from the spin blocks g3 the way
 // expand_rdm_kernel<3> forms it (alpha-first block, parity sign, zero unless the numbers of
 // beta indices above and below agree), so the spin-orbital G3 is never stored.
 __global__ __launch_bounds__(256) void cumulant3_kernel(int n, const double* __restrict__ G1,
                                                         const double* __restrict__ L2,
                                                         const double* __restrict__ g3,
                                                         double* __restrict__ L3) {
-  __shared__ double gs[3][16], ls[3][16 * 16];
+  __shared__ double gs[3][32], ls[3][32 * 32];
   const int n2 = n * n, n3 = n2 * n;
   const int u = blockIdx.x;
   const int P[3] = {u / n2, (u / n) % n, u % n};
@@ -1755,8 +1758,8 @@ __global__ void singles_kernel(AmpDims d, const double* __restrict__ Taa, const 
                                double* __restrict__ srca, double* __restrict__ srcb) {
   const double s = *sp;
   const int nH = d.nC + d.nA, nP = d.nA + d.nV, nA = d.nA, nC = d.nC;
-  // one wave per element, lane u * nA + x takes one term of the active sum (nA^2 <= 64),
-  // summed by a fixed butterfly
+  // one wave per element, lane l takes the terms l, l + 64, ... (u * nA + x) of the active
+  // sum (one term each for nA <= 8), summed by a fixed butterfly
   const int lane = threadIdx.x & 63;
   const int idx = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
   if (idx >= 2 * nP * nH) return;   // the whole wave
@@ -1765,16 +1768,16 @@ __global__ void singles_kernel(AmpDims d, const double* __restrict__ Taa, const 
   int a = e / nH, i = e % nH;
   double c = 0.0;
   const long long sH = 1, sH2 = nH, sP = (long long)nH * nH, sP2 = (long long)nP * nH * nH;
-  if (lane < nA * nA) {
-    const int u = lane / nA, x = lane - u * nA;
+  for (int l = lane; l < nA * nA; l += 64) {
+    const int u = l / nA, x = l - u * nA;
     double D = eps[nC + x] - eps[nC + u];
     // t[a, x, i, u]: a (P), x (P, active at offset 0), i (H), u (H, active at offset nC)
     long long o_axiu = a * sP2 + x * sP + i * sH2 + (nC + u) * sH;
     if (spin == 0) {
-      c = D * (Taa[o_axiu] * ga[x * nA + u] + Tab[o_axiu] * gb[x * nA + u]);
+      c += D * (Taa[o_axiu] * ga[x * nA + u] + Tab[o_axiu] * gb[x * nA + u]);
     } else {
       long long o_xaui = x * sP2 + a * sP + (nC + u) * sH2 + i * sH;
-      c = D * (Tbb[o_axiu] * gb[x * nA + u] + Tab[o_xaui] * ga[x * nA + u]);
+      c += D * (Tbb[o_axiu] * gb[x * nA + u] + Tab[o_xaui] * ga[x * nA + u]);
     }
   }
   for (int w = 32; w > 0; w >>= 1) c += __shfl_xor(c, w, 64);

@@ -201,24 +201,92 @@ def random_ci(rng: np.random.Generator, n_orb: int, n_alpha: int, n_beta: int) -
 
 
 def active_rdms(ci: np.ndarray, n_orb: int, n_alpha: int, n_beta: int):
-    """gamma1 [2][n]^2, gamma2 [3][n]^4, gamma3 [4][n]^6 of a CAS vector (spin-block layout)."""
+    """gamma1 [2][n]^2, gamma2 [3][n]^4, gamma3 [4][n]^6 of a CAS vector (spin-block layout).
+
+    Per spin block (k indices, m of them alpha): the vectors w_T = a_{t_k} .. a_{t_1}|psi>
+    of the index tuples T (m alpha then k - m beta orbitals, each part ascending) are
+    gathered from the CI matrix with the signs of the annihilations; the block of sorted
+    tuples is their Gram matrix, <w_P|w_Q> = <psi| a+_{p_1} .. a+_{p_k} a_{q_k} .. a_{q_1} |psi>,
+    spread over all index orders with the permutation signs.  Strings only (no Fock space),
+    so active spaces up to about 12 orbitals are generated in seconds."""
     n = n_orb
-    fock = _Fock(2 * n)
-    vec = _ci_to_fock(ci, n, n_alpha, n_beta, fock, 0, n)
-    g1 = fock_rdms(vec, fock, 1)
-    g2 = fock_rdms(vec, fock, 2)
-    g3 = fock_rdms(vec, fock, 3) if n > 0 else None
-    A, Bb = slice(0, n), slice(n, 2 * n)
-    gamma1 = np.stack([g1[A, A], g1[Bb, Bb]])
-    gamma2 = np.stack([g2[A, A, A, A], g2[A, Bb, A, Bb], g2[Bb, Bb, Bb, Bb]])
-    gamma3 = np.stack([
-        g3[A, A, A, A, A, A],
-        g3[A, A, Bb, A, A, Bb],
-        g3[A, Bb, Bb, A, Bb, Bb],
-        g3[Bb, Bb, Bb, Bb, Bb, Bb],
-    ])
-    return (np.ascontiguousarray(gamma1), np.ascontiguousarray(gamma2),
-            np.ascontiguousarray(gamma3))
+    c = np.asarray(ci, dtype=np.float64)
+    out = []
+    for k in (1, 2, 3):
+        blocks = []
+        for m in range(k, -1, -1):                       # alpha-first block order
+            blocks.append(_rdm_block(c, n, n_alpha, n_beta, k, m))
+        out.append(np.ascontiguousarray(np.stack(blocks)))
+    return out[0], out[1], out[2]
+
+
+def _annihilation_map(n: int, n_el: int, orbs):
+    """a_{o_last} .. a_{o_first} on the strings of n_el electrons: for every string of
+    n_el - len(orbs) electrons, the index of the source string (0 where none) and the sign
+    (0 where none)."""
+    src = {sum(1 << o for o in t): i for i, t in enumerate(itertools.combinations(range(n), n_el))}
+    tm = sum(1 << o for o in orbs)
+    tgt = list(itertools.combinations(range(n), n_el - len(orbs)))
+    idx = np.zeros(len(tgt), dtype=np.int64)
+    sgn = np.zeros(len(tgt))
+    for j, t in enumerate(tgt):
+        m = sum(1 << o for o in t)
+        if m & tm:
+            continue
+        cur, sign = m | tm, 1.0
+        for o in orbs:                                   # a_{orbs[0]} acts first
+            if bin(cur & ((1 << o) - 1)).count("1") & 1:
+                sign = -sign
+            cur ^= 1 << o
+        idx[j] = src[m | tm]
+        sgn[j] = sign
+    return idx, sgn
+
+
+def _tuple_positions(n: int, r: int):
+    """For every r-tuple of orbitals (row-major over [n]^r): its sorted combination's index
+    in lexicographic order (-1 if an orbital repeats) and the sign of the sorting."""
+    combos = {t: i for i, t in enumerate(itertools.combinations(range(n), r))}
+    pos = np.full(n ** r, -1, dtype=np.int64)
+    sgn = np.zeros(n ** r)
+    for flat, t in enumerate(itertools.product(range(n), repeat=r)):
+        if len(set(t)) < r:
+            continue
+        inv = sum(1 for i in range(r) for j in range(i + 1, r) if t[i] > t[j])
+        pos[flat] = combos[tuple(sorted(t))]
+        sgn[flat] = -1.0 if inv % 2 else 1.0
+    return pos, sgn
+
+
+def _rdm_block(c: np.ndarray, n: int, na: int, nb: int, k: int, m: int) -> np.ndarray:
+    """Spin block of the k-body density with m alpha indices, [n]^(2k)."""
+    shape = (n,) * (2 * k)
+    Ta = list(itertools.combinations(range(n), m))
+    Tb = list(itertools.combinations(range(n), k - m))
+    if na - m < 0 or nb - (k - m) < 0 or not Ta or not Tb:
+        return np.zeros(shape)
+    amaps = [_annihilation_map(n, na, t) for t in Ta]
+    bmaps = [_annihilation_map(n, nb, t) for t in Tb]
+    # each beta annihilation passes the na - m alpha electrons left
+    gsign = -1.0 if ((na - m) * (k - m)) % 2 else 1.0
+    nra, nrb = len(amaps[0][0]), len(bmaps[0][0])
+    W = np.empty((len(Ta), len(Tb), nra, nrb))
+    for ia, (ida, sga) in enumerate(amaps):
+        rows = c[ida] * sga[:, None]
+        for ib, (idb, sgb) in enumerate(bmaps):
+            W[ia, ib] = rows[:, idb] * (sgb * gsign)[None, :]
+    W = W.reshape(len(Ta) * len(Tb), nra * nrb)
+    G = W @ W.T                                          # sorted tuples (alpha part, beta part)
+    pa, sa = _tuple_positions(n, m)
+    pb, sb = _tuple_positions(n, k - m)
+    # full index tuple = (alpha part, beta part), row-major
+    pos = (pa[:, None] * len(Tb) + pb[None, :]).ravel()
+    sgn = (sa[:, None] * sb[None, :]).ravel()
+    valid = (pa[:, None] >= 0) & (pb[None, :] >= 0)
+    pos = np.where(valid.ravel(), pos, 0)
+    sgn = np.where(valid.ravel(), sgn, 0.0)
+    out = sgn[:, None] * sgn[None, :] * G[np.ix_(pos, pos)]
+    return out.reshape(shape)
 
 
 # ---------------------------------------------------------------------------
@@ -237,7 +305,8 @@ def _draw_B(rng: np.random.Generator, M: int, N: int, sigma: float = 0.1) -> np.
 
 def make_problem(n_core: int, n_active: int, n_virtual: int, n_aux: int, seed: int,
                  s: float = 0.5, gap: float = 1.0, name: str = "",
-                 with_gamma3: bool = True, f_sigma: float = 0.0) -> Problem:
+                 with_gamma3: bool = True, f_sigma: float = 0.0,
+                 n_alpha: Optional[int] = None, n_beta: Optional[int] = None) -> Problem:
     """Draw one problem.
 
     Draw order (part of the contract so both sides reproduce it): core energies,
@@ -247,7 +316,9 @@ def make_problem(n_core: int, n_active: int, n_virtual: int, n_aux: int, seed: i
     core U(-2, -0.5 gap), active U(-0.3 gap, 0.3 gap), virtual U(0.2 gap, 3).
     ``f_sigma`` > 0 adds a symmetric f_offdiag with N(0, f_sigma^2) entries on the
     core-active, core-virtual and active-virtual blocks (upper triangle drawn row-major,
-    mirrored) and zeros inside the blocks.
+    mirrored) and zeros inside the blocks.  ``n_alpha``, ``n_beta`` (default
+    ceil(nA/2), floor(nA/2)) set the electron numbers of the CAS vector, e.g. a few
+    electrons in a large active space whose half-filled vector would be too long to draw.
     """
     rng = np.random.default_rng(seed)
     N = n_core + n_active + n_virtual
@@ -256,8 +327,8 @@ def make_problem(n_core: int, n_active: int, n_virtual: int, n_aux: int, seed: i
     ev = np.sort(rng.uniform(0.2 * gap, 3.0, n_virtual))
     eps = np.concatenate([ec, ea, ev])
     B = _draw_B(rng, n_aux, N)
-    n_alpha = (n_active + 1) // 2
-    n_beta = n_active // 2
+    n_alpha = (n_active + 1) // 2 if n_alpha is None else int(n_alpha)
+    n_beta = n_active // 2 if n_beta is None else int(n_beta)
     if n_active > 0:
         ci = random_ci(rng, n_active, n_alpha, n_beta)
         g1, g2, g3 = active_rdms(ci, n_active, n_alpha, n_beta)

@@ -6,6 +6,8 @@ Calls only ``oracle/`` (and the shared input generator).  Usage:
     python tests/golden/make_golden.py medium         # energies from the block-sparse DF level
     python tests/golden/make_golden.py large          #   (oracle/dsrg_df.py; hours of CPU)
     python tests/golden/make_golden.py relax          # one-step relaxed energies (oracle/relax.py)
+    python tests/golden/make_golden.py cas88          # CAS(8,8) with 150 virtuals, block-sparse DF
+    python tests/golden/make_golden.py big-active     # active spaces of 9 to 16 orbitals
 Writes tests/golden/<name>_s<s>.json with E(2), E(3) and its two parts (and, for small,
 sampled intermediates), or tests/golden/small_pairs_s0.5.json with the core-pair
 decomposition of E(3).
@@ -38,11 +40,12 @@ def samples(r, p, n=400, seed=12345):
     return out
 
 
-def main_df(name):
+def main_df(name, shape=None):
     """Workloads beyond the dense engine: the block-sparse, density-fitted level."""
     import platform
     from oracle import dsrg_df
-    p = make_config(name)
+    from paper_1701_02011_amd.synth import make_problem
+    p = make_config(name) if shape is None else make_problem(name=name, **shape)
     t = time.time()
     r = dsrg_df.run(p, log=lambda m: print(m, flush=True))
     out = dict(workload=name, s=p.s, n_core=p.n_core, n_active=p.n_active,
@@ -57,9 +60,53 @@ def main_df(name):
     print(path, out["e2"], out["e3"], "%.0fs" % out["oracle_seconds"], flush=True)
 
 
+# CAS(8,8) at a size the block-sparse level finishes in minutes, large enough that the
+# library runs its large-problem paths (ungrouped commutators, batched (PP|PP) ladder when
+# asked for, 128 x 128 tiles)
+CAS88 = dict(n_core=12, n_active=8, n_virtual=150, n_aux=600, seed=404, s=0.5)
+
+
+# Active spaces beyond 8 orbitals: (name, make_problem arguments, oracle level).  The dense
+# engine takes up to 10 active orbitals at these sizes; the block-sparse level goes further.
+# The 16-orbital case holds three electrons (two alpha, one beta): a half-filled CAS(16,16)
+# vector has 1.7e8 determinants, too many to draw.
+BIG_ACTIVE = [("cas9", dict(n_core=0, n_active=9, n_virtual=1, n_aux=4, seed=91), "dense"),
+              ("cas10", dict(n_core=1, n_active=10, n_virtual=1, n_aux=6, seed=92), "dense"),
+              ("cas12", dict(n_core=1, n_active=12, n_virtual=1, n_aux=6, seed=93), "block"),
+              ("cas16_3e", dict(n_core=1, n_active=16, n_virtual=2, n_aux=8, seed=94,
+                                n_alpha=2, n_beta=1), "block")]
+
+
+def main_big_active(only=None):
+    """E(2), E(3) for active spaces of 9 to 16 orbitals (s = 0.5)."""
+    from oracle import dsrg_df
+    from paper_1701_02011_amd.synth import make_problem
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "big_active.json")
+    cases = {}
+    if os.path.exists(path):
+        with open(path) as f:
+            cases = {c["name"]: c for c in json.load(f)["cases"]}
+    for name, args, level in BIG_ACTIVE:
+        if only and name != only:
+            continue
+        p = make_problem(**args)
+        t = time.time()
+        r = dsrg.run(p) if level == "dense" else dsrg_df.run(p)
+        cases[name] = dict(name=name, args=args, s=p.s, level=level, e2=r.e2, e3=r.e3,
+                           e3_a=r.e3_a, e3_b=r.e3_b, oracle_seconds=time.time() - t)
+        print(name, r.e2, r.e3, "%.0fs" % cases[name]["oracle_seconds"], flush=True)
+        out = dict(cases=[cases[n] for n, _, _ in BIG_ACTIVE if n in cases],
+                   source="oracle/dsrg.py (dense) or oracle/dsrg_df.py (block), FP64")
+        with open(path, "w") as f:
+            json.dump(out, f, indent=1)
+    print(path, flush=True)
+
+
 def main(name):
     if name in ("medium", "large"):
         return main_df(name)
+    if name == "cas88":
+        return main_df(name, CAS88)
     svals = SMALL_S_VALUES if name == "small" else (None,)
     for s in svals:
         p = make_config(name, s=s)
@@ -141,5 +188,7 @@ if __name__ == "__main__":
         main_pairs()
     elif arg == "relax":
         main_relax()
+    elif arg == "big-active":
+        main_big_active(sys.argv[2] if len(sys.argv) > 2 else None)
     else:
         main(arg)

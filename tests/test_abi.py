@@ -87,7 +87,12 @@ def test_unsupported_options(lib):
     for precision in (3, -1, 7):
         rc, _ = _call(p, opt=_lib.Options(0, precision, 0, None))
         assert rc == _lib.DSRG_E_UNSUPPORTED
-    p = make_problem(0, 9, 1, 4, seed=1, with_gamma3=False)
+    # 17 active orbitals: above the largest active space built (16)
+    import dataclasses
+    n = 18
+    p = dataclasses.replace(make_problem(0, 2, 1, 4, seed=1), n_active=17, eps=np.zeros(n),
+                            B=np.zeros((4, n, n)), gamma1=np.zeros((2, 17, 17)),
+                            gamma2=np.zeros((3,) + (17,) * 4), gamma3=None, f_offdiag=None)
     rc, _ = _call(p)
     assert rc == _lib.DSRG_E_UNSUPPORTED
 
@@ -235,3 +240,29 @@ def test_relaxed_argument_checks(lib):
     bad[0, 0] = np.nan
     assert f(ctypes.byref(st), 2, 1, bad.ctypes.data, opt, ctypes.byref(r), ctypes.byref(x),
              ctypes.byref(o)) == _lib.DSRG_E_NONFINITE
+
+
+def test_dyall_argument_checks(lib):
+    """dsrg_dyall_aavv: null outputs (DSRG_E_ARG), active spaces outside 1..9
+    (DSRG_E_UNSUPPORTED), and the problem checks of the energy entry points (negative sizes,
+    non-finite integrals) before any device work."""
+    p = make_problem(1, 3, 2, 6, seed=1)
+    keep = []
+    st, fl = _lib._problem_struct(p, keep)
+    f = lib.dsrg_dyall_aavv
+    opt = ctypes.byref(_lib._options(fl))
+    t = np.full(3 * 2 * 2 * 3 * 3, 7.0)
+    assert f(ctypes.byref(st), opt, None, None) == _lib.DSRG_E_ARG
+    assert f(None, opt, t.ctypes.data, None) == _lib.DSRG_E_ARG
+    for nA in (0, 10):
+        q = make_problem(0, nA, 1, 4, seed=2, with_gamma3=False)
+        sq, _ = _lib._problem_struct(q, keep)
+        assert f(ctypes.byref(sq), opt, t.ctypes.data, None) == _lib.DSRG_E_UNSUPPORTED
+    st.n_virtual = -1
+    assert f(ctypes.byref(st), opt, t.ctypes.data, None) == _lib.DSRG_E_ARG
+    st.n_virtual = 2
+    bad = np.array(p.B)
+    bad[0, 0, 0] = np.inf
+    st.B = bad.ctypes.data
+    assert f(ctypes.byref(st), opt, t.ctypes.data, None) == _lib.DSRG_E_NONFINITE
+    assert np.all(t == 7.0)
