@@ -7,7 +7,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libdsrg.so")
-SOURCES = ["dsrg.hip", "kernels.hip", "mlp.hip", "rdm.hip", "cas.hip"]
+SOURCES = ["dsrg.hip", "kernels.hip", "mlp.hip", "rdm.hip", "cas.hip", "dyall.hip"]
 FLAGS = ["-O3", "-std=c++17", "--offload-arch=gfx950", "-fPIC", "-shared",
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          # MFMA accumulators in ordinary VGPRs: with the AGPR form the compiler copied every

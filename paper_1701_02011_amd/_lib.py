@@ -154,6 +154,9 @@ def load() -> ctypes.CDLL:
                                                 ctypes.POINTER(Result), ctypes.POINTER(RelaxedResult),
                                                 ctypes.POINTER(RelaxedOutputs)]
         lib.dsrg_pt3_energy_relaxed.restype = ctypes.c_int
+        lib.dsrg_dyall_aavv.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(Options), ctypes.c_void_p,
+                                        ctypes.c_void_p]
+        lib.dsrg_dyall_aavv.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -482,3 +485,16 @@ def dsrg_pt3_energy_relaxed(p, n_alpha=None, n_beta=None, ci_guess="reference", 
         bufs["ci"] = bufs["ci"][:ndet]
         out.update(bufs)
     return out
+
+
+def dsrg_dyall_aavv(p, stream=None):
+    """Active-to-virtual doubles under Dyall's H(0) (host problem in, host arrays out):
+    returns (t [3][nV][nV][nA][nA] with blocks aa, ab, bb, smallest |shifted denominator|)."""
+    keep = []
+    st, fl = _problem_struct(p, keep)
+    nA, nV = st.n_active, st.n_virtual
+    t = np.zeros((3, nV, nV, nA, nA))
+    dmin = ctypes.c_double(0.0)
+    _check(load().dsrg_dyall_aavv(ctypes.byref(st), ctypes.byref(_options(fl, stream)), t.ctypes.data,
+                                  ctypes.addressof(dmin)))
+    return t, dmin.value
