@@ -152,6 +152,12 @@ def cpu_baseline(workload, probs):
                 full_energy_seconds_recorded=g["oracle_seconds"])
 
 
+def progress(msg):
+    """A progress line on stderr (the JSON result is the only line on stdout)."""
+    sys.stderr.write("bench: %s\n" % msg)
+    sys.stderr.flush()
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -173,13 +179,19 @@ def main():
     import torch
     from paper_1701_02011_amd import _lib
     _lib.load()
+    if args.workload == "curve":
+        # tile choices per size class from the package's autotuner, when it has stored them
+        rules = _lib.load_tile_rules()
+        progress("tile rules: %s" % ("none stored" if rules is None else rules))
     probs = workload_problems(args.workload, args.geometries)
+    progress("inputs drawn: %d problem(s)" % len(probs))
     dev = [_lib.to_device(p) for p in probs]
     torch.cuda.synchronize()
 
     def step(prec):
         if args.workload == "curve":
-            # geometries of different shapes: the batch entry point (two at a time)
+            # geometries of different shapes: the batch entry point (rounds of two, unplanned
+            # shapes on worker threads)
             res, codes = _lib.dsrg_pt3_energy_batch(dev, precision=prec)
             assert all(c == 0 for c in codes), codes
             return res
@@ -189,11 +201,14 @@ def main():
         for _ in range(warmup):
             step(prec)
         torch.cuda.synchronize()
+        progress("warm-up done (%d step(s))" % warmup)
         t0 = time.perf_counter()
         for _ in range(steps):
             res = step(prec)
         torch.cuda.synchronize()
-        return res, time.perf_counter() - t0
+        dt = time.perf_counter() - t0
+        progress("timed %d step(s): %.3f s" % (steps, dt))
+        return res, dt
 
     prec = 1 if args.precision == "fp32" else 0
     res, dt = timed(prec, args.warmup, args.steps)
@@ -204,6 +219,7 @@ def main():
     # (on the stream it runs on) in a profiled pass over the same problems; the timed loop
     # above replays the recorded graph instead
     prof = [_lib.dsrg_pt3_energy(d, profile=True, precision=prec) for d in dev]
+    progress("profiled pass done")
     torch.cuda.synchronize()
     ksec = [sum(r["kernel_seconds"][k] for r in prof) for k in range(8)]
     kfl = [sum(r["kernel_flops"][k] for r in prof) for k in range(8)]
@@ -219,7 +235,7 @@ def main():
                     kernel=name, note=ROLE_NOTES[dom // 2],
                     alg_flops_per_launch=flops_per_launch, avg_launch_us=1e6 * avg_s,
                     launches_per_energy=kn[dom] / len(dev),
-                    share_of_step=ksec[dom] / (len(dev) * dt / args.steps) if dt > 0 else None)
+                    share_of_step=ksec[dom] / (dt / args.steps) if dt > 0 else None)
     # whole-energy algorithmic rate: every contraction's 2 M N K over the step time
     alg_flops = sum(r["alg_flops"] for r in res)
     whole = dict(alg_tflop_per_energy=alg_flops / len(dev) / 1e12,

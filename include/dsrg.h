@@ -197,8 +197,10 @@ int dsrg_pt3_energy(const dsrg_problem* prob, const dsrg_options* opt, dsrg_resu
    one geometry at several s).  Items run in rounds of K on streams of the library, ordered
    after opt->stream, each with a plan of its own slot (item k uses slot k % K), so the
    items of a round overlap on the GPU; K is half of GPU_MAX_HW_QUEUES (4 unless set, so 2),
-   at most 4.  The call returns when all have finished.  An item
-   whose slot has no cached plan yet runs to completion first (recording that plan).
+   at most 4.  The call returns when all have finished.  Items of a round whose slot has
+   no cached plan (a shape not seen before) run their whole pipeline directly, each on a
+   host worker thread of its own and on its round's stream, and record that plan; so a
+   round of uneven geometries overlaps on the GPU as well.
    outs[k] and status[k] receive item k's result and return code; an item that fails (bad
    arguments, non-finite input) is skipped and leaves outs[k] untouched.  Returns DSRG_OK if
    at least one item succeeded, else the first item's code (DSRG_E_ARG for n < 1 or null
@@ -337,6 +339,26 @@ typedef struct {
 int dsrg_pt3_energy_relaxed(const dsrg_problem* prob, int32_t n_alpha, int32_t n_beta, const double* ci_guess,
                             const dsrg_options* opt, dsrg_result* out, dsrg_relaxed_result* rel,
                             const dsrg_relaxed_outputs* outs);
+
+/* ---- tile choices by problem size (the batched dissociation curve's autotuned tiles) ----
+   A rule applies to every later call (any entry point, any host thread) whose particle
+   space n_active + n_virtual lies in [np_min, np_max]; the first matching rule wins, and
+   a call matched by none keeps the built-in choices.  big_tile_min: plain contraction
+   launches run 128 x 128 output tiles when both free dimensions reach 128 and the output
+   holds at least this many such tiles (0: the built-in 256), else 64 x 64 tiles.
+   virt_batch: the (PP|PP) batch when the options give none (0: the largest that fits
+   workspace_cap).  Cached plans are keyed by the settings they were recorded with.  The
+   package's autotuner (autotune.py) times candidate settings per size class on the GPU and
+   stores the winners as a rule table. */
+typedef struct {
+  int32_t np_min, np_max;
+  int32_t big_tile_min;
+  int32_t virt_batch;
+} dsrg_tile_rule;
+
+/* Replaces the process-wide rule table with rules[0..n) (copied; n = 0 clears it).
+   DSRG_E_ARG for n < 0, null rules with n > 0, np_min > np_max or a negative setting. */
+int dsrg_set_tile_rules(const dsrg_tile_rule* rules, int32_t n);
 
 /* ---- Dyall's zeroth-order Hamiltonian: active-to-virtual doubles (App. B, Eq. t2_aavv) ----
    With the two-body interaction among active orbitals moved into H(0) and s -> inf, the

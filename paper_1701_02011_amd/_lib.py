@@ -45,6 +45,11 @@ class Problem(ctypes.Structure):
                 ("f_offdiag", ctypes.c_void_p), ("e0", ctypes.c_double)]
 
 
+class TileRule(ctypes.Structure):
+    _fields_ = [("np_min", ctypes.c_int32), ("np_max", ctypes.c_int32),
+                ("big_tile_min", ctypes.c_int32), ("virt_batch", ctypes.c_int32)]
+
+
 class Options(ctypes.Structure):
     _fields_ = [("flags", ctypes.c_int32), ("precision", ctypes.c_int32),
                 ("workspace_cap", ctypes.c_int64), ("stream", ctypes.c_void_p),
@@ -157,6 +162,8 @@ def load() -> ctypes.CDLL:
         lib.dsrg_dyall_aavv.argtypes = [ctypes.POINTER(Problem), ctypes.POINTER(Options), ctypes.c_void_p,
                                         ctypes.c_void_p]
         lib.dsrg_dyall_aavv.restype = ctypes.c_int
+        lib.dsrg_set_tile_rules.argtypes = [ctypes.POINTER(TileRule), ctypes.c_int32]
+        lib.dsrg_set_tile_rules.restype = ctypes.c_int
         _lib = lib
     return _lib
 
@@ -498,3 +505,29 @@ def dsrg_dyall_aavv(p, stream=None):
     _check(load().dsrg_dyall_aavv(ctypes.byref(st), ctypes.byref(_options(fl, stream)), t.ctypes.data,
                                   ctypes.addressof(dmin)))
     return t, dmin.value
+
+
+TILE_RULES_PATH = os.path.join(HERE, "tile_rules.json")
+
+
+def set_tile_rules(rules):
+    """Install a rule table (list of dicts with np_min, np_max, big_tile_min, virt_batch);
+    an empty list restores the built-in choices."""
+    arr = (TileRule * max(1, len(rules)))()
+    for k, r in enumerate(rules):
+        arr[k] = TileRule(int(r["np_min"]), int(r["np_max"]), int(r.get("big_tile_min", 0)),
+                          int(r.get("virt_batch", 0)))
+    _check(load().dsrg_set_tile_rules(arr, len(rules)))
+
+
+def load_tile_rules(path=None):
+    """Install the autotuner's stored rule table (tile_rules.json beside this module);
+    returns the rules, or None when there is no such file."""
+    import json
+    path = path or TILE_RULES_PATH
+    if not os.path.exists(path):
+        return None
+    with open(path) as f:
+        rules = json.load(f)["rules"]
+    set_tile_rules(rules)
+    return rules

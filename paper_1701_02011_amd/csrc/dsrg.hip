@@ -27,6 +27,7 @@
 #include <sstream>
 #include <stdexcept>
 #include <string>
+#include <thread>
 #include <vector>
 
 #include "dsrg_terms.inc"
@@ -2993,6 +2994,20 @@ static void check_intruder(int nC, int nA, int nV, const double* eps) {
 
 // Checked arguments of a call and the key of its plan.  slot > 0 keys a separate plan of
 // the same shape (concurrent members of a batch).
+// Tile rules by problem size (dsrg_set_tile_rules): the first rule whose particle-space
+// range holds n_active + n_virtual applies to a call.
+static std::mutex g_rules_mu;
+static std::vector<dsrg_tile_rule> g_rules;
+
+static dsrg_tile_rule rule_for(int nP) {
+  std::lock_guard<std::mutex> lk(g_rules_mu);
+  for (const auto& r : g_rules)
+    if (nP >= r.np_min && nP <= r.np_max) return r;
+  dsrg_tile_rule none;
+  memset(&none, 0, sizeof(none));
+  return none;
+}
+
 struct Setup {
   Shape sh;
   int prec = 0;   // DSRG_PRECISION_* of the contractions
@@ -3022,6 +3037,11 @@ static Setup setup(const dsrg_problem* P, const dsrg_options* O, const dsrg_inte
   if (O && O->virt_batch < 0) throw Error(DSRG_E_ARG, "virt_batch must be >= 0");
   Setup S;
   S.vb = O ? O->virt_batch : 0;
+  // the size class's tile rule: the large-tile threshold of this thread's launches and,
+  // unless the options name one, the (PP|PP) batch
+  const dsrg_tile_rule rule = rule_for(nA + nV);
+  set_big_tile_min(rule.big_tile_min);
+  if (S.vb == 0 && rule.virt_batch > 0) S.vb = rule.virt_batch;
   S.prec = O ? O->precision : DSRG_PRECISION_FP64;
   const int flags = O ? O->flags : 0;
   S.devptr = flags & DSRG_F_DEVICE_PTRS;
@@ -3072,9 +3092,10 @@ static Setup setup(const dsrg_problem* P, const dsrg_options* O, const dsrg_inte
   if (S.want_pairs && nC > 0 && !e3_pairs) throw Error(DSRG_E_ARG, "null e3_pairs with n_core > 0");
   S.cacheable = !S.profile && !I && !S.want_pairs && !(flags & DSRG_F_NO_PLAN_CACHE);
   HIPCHECK(hipGetDevice(&S.dev));
-  char kbuf[192];
-  snprintf(kbuf, sizeof(kbuf), "%d:%d:%d:%d:%d:%d:%d:%d:%d:%d:%d:%lld:%d:%d", S.dev, nC, nA, nV, M, (int)sh.has_g3,
-           (int)sh.has_f, (int)pt3, (int)S.grouped, (int)S.unique_ladder, S.prec, S.cap, S.vb, slot);
+  char kbuf[224];
+  snprintf(kbuf, sizeof(kbuf), "%d:%d:%d:%d:%d:%d:%d:%d:%d:%d:%d:%lld:%d:%d:%d", S.dev, nC, nA, nV, M, (int)sh.has_g3,
+           (int)sh.has_f, (int)pt3, (int)S.grouped, (int)S.unique_ladder, S.prec, S.cap, S.vb, slot,
+           big_tile_min());
   S.key = kbuf;
   return S;
 }
@@ -3485,8 +3506,8 @@ int dsrg_pt3_energy_batch(const dsrg_problem* probs, int32_t n, const dsrg_optio
   // Members run in rounds of K = batch_round(): member k on library stream k % K
   // (ordered after the caller's stream) with a plan of its own slot, so the members of a
   // round overlap on the GPU.  Each member's s, energies and non-finite count go through its
-  // own pinned slot.  A member without a cached plan runs to completion in turn (that call
-  // records its plan).
+  // own pinned slot.  Members without a cached plan (a shape not seen before) run their
+  // pipeline directly on worker threads, one per stream of the round, and record a plan.
   int dev = 0;
   hipStream_t caller = (opt && opt->stream) ? (hipStream_t)opt->stream : (hipStream_t)0;
   hipStream_t* ss = nullptr;
@@ -3514,37 +3535,59 @@ int dsrg_pt3_energy_batch(const dsrg_problem* probs, int32_t n, const dsrg_optio
   for (int j = 0; j < K; ++j) (void)hipStreamWaitEvent(ss[j], ready, 0);
   std::map<std::string, dsrg::Plan*> held;   // plans this batch holds (busy) until its end
   std::vector<dsrg::Plan*> used(n, nullptr);
+  std::vector<dsrg_options> oj(n);
+  std::vector<std::string> werr(n);           // messages of members run on worker threads
   std::vector<char> pt3v(n, 1);
-  for (int32_t k = 0; k < n; ++k) {
-    const int j = k % K;
+  for (int32_t r0 = 0; r0 < n; r0 += K) {
     // rounds of K members: more graphs in flight than the hardware queues serve (each
     // replay has a side branch) ran slower than two at a time
-    if (j == 0 && k > 0)
+    if (r0 > 0)
       for (int i = 0; i < K; ++i) (void)hipStreamSynchronize(ss[i]);
-    dsrg_options oj;
-    memset(&oj, 0, sizeof(oj));
-    if (opt) oj = *opt;
-    oj.stream = ss[j];
-    status[k] = dsrg::guarded([&] {
-      const dsrg::Setup S = dsrg::setup(probs + k, &oj, nullptr, true, nullptr, nullptr, j);
-      dsrg::Plan* plan = nullptr;
-      if (S.cacheable) {
-        auto it = held.find(S.key);
-        if (it != held.end()) {
-          plan = it->second;
-        } else {
-          bool seen = false;
-          plan = dsrg::acquire_plan(S.key, seen);
-          if (plan) held[S.key] = plan;
+    // members without a cached plan run their whole pipeline on worker threads, one per
+    // library stream, so uneven shapes (a plan each) overlap on the GPU as replays do
+    std::vector<std::thread> workers;
+    for (int32_t k = r0; k < std::min<int32_t>(n, r0 + K); ++k) {
+      const int j = k - r0;
+      memset(&oj[k], 0, sizeof(dsrg_options));
+      if (opt) oj[k] = *opt;
+      oj[k].stream = ss[j];
+      bool direct = false;
+      status[k] = dsrg::guarded([&] {
+        const dsrg::Setup S = dsrg::setup(probs + k, &oj[k], nullptr, true, nullptr, nullptr, j);
+        dsrg::Plan* plan = nullptr;
+        if (S.cacheable) {
+          auto it = held.find(S.key);
+          if (it != held.end()) {
+            plan = it->second;
+          } else {
+            bool seen = false;
+            plan = dsrg::acquire_plan(S.key, seen);
+            if (plan) held[S.key] = plan;
+          }
         }
+        if (!plan) {
+          direct = true;
+          return DSRG_OK;
+        }
+        double* st_k = stage + (size_t)k * kStage;
+        st_k[0] = probs[k].s;
+        dsrg::replay_launch(plan, probs + k, S, st_k, st_k + 1, reinterpret_cast<int*>(st_k + 5));
+        used[k] = plan;
+        return DSRG_OK;
+      });
+      if (status[k] == DSRG_OK && direct) {
+        workers.emplace_back([&, k, j] {
+          if (hipSetDevice(dev) != hipSuccess) {
+            status[k] = DSRG_E_HIP;
+            werr[k] = "hipSetDevice failed on a batch worker";
+            return;
+          }
+          status[k] = dsrg::guarded([&] { return dsrg::run(probs + k, &oj[k], outs + k, nullptr, true, nullptr, nullptr, j); });
+          if (status[k] != DSRG_OK) werr[k] = dsrg::g_last_error;
+        });
       }
-      if (!plan) return dsrg::run(probs + k, &oj, outs + k, nullptr, true, nullptr, nullptr, j);
-      double* st_k = stage + (size_t)k * kStage;
-      st_k[0] = probs[k].s;
-      dsrg::replay_launch(plan, probs + k, S, st_k, st_k + 1, reinterpret_cast<int*>(st_k + 5));
-      used[k] = plan;
-      return DSRG_OK;
-    });
+    }
+    for (auto& w : workers) w.join();
   }
   int sync_rc = DSRG_OK;
   for (int j = 0; j < K; ++j)
@@ -3564,6 +3607,12 @@ int dsrg_pt3_energy_batch(const dsrg_problem* probs, int32_t n, const dsrg_optio
     else if (first_error == DSRG_OK) first_error = status[k];
   }
   if (sync_rc != DSRG_OK) dsrg::g_last_error = "a batch stream failed";
+  else
+    for (int32_t k = 0; k < n; ++k)
+      if (!werr[k].empty()) {
+        dsrg::g_last_error = "member " + std::to_string(k) + ": " + werr[k];
+        break;
+      }
   for (auto& kv : held) dsrg::release_plan(kv.second);
   (void)hipHostFree(stage);
   (void)hipEventDestroy(ready);
@@ -3650,6 +3699,22 @@ int dsrg_pt3_pair_energies(const dsrg_problem* prob, const dsrg_options* opt, ds
 int dsrg_pt3_energy_ex(const dsrg_problem* prob, const dsrg_options* opt, dsrg_result* out,
                        const dsrg_intermediates* inter) {
   return dsrg::guarded([&] { return dsrg::run(prob, opt, out, inter, true); });
+}
+
+int dsrg_set_tile_rules(const dsrg_tile_rule* rules, int32_t n) {
+  if (n < 0 || (n > 0 && !rules)) {
+    dsrg::g_last_error = "null rules or n < 0";
+    return DSRG_E_ARG;
+  }
+  for (int32_t k = 0; k < n; ++k)
+    if (rules[k].np_min > rules[k].np_max || rules[k].big_tile_min < 0 || rules[k].virt_batch < 0) {
+      dsrg::g_last_error = "rule " + std::to_string(k) + ": np_min > np_max or a negative setting";
+      return DSRG_E_ARG;
+    }
+  std::lock_guard<std::mutex> lk(dsrg::g_rules_mu);
+  dsrg::g_rules.assign(rules, rules + n);
+  dsrg::g_last_error.clear();
+  return DSRG_OK;
 }
 
 int dsrg_dyall_aavv(const dsrg_problem* prob, const dsrg_options* opt, double* t_out, double* dmin) {

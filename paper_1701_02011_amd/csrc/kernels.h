@@ -52,6 +52,10 @@ void gett_prepare(GettDesc& g);
 double gett_tile_fraction(const GettDesc& g);
 // whether a plain launch of g runs 128 x 128 tiles (else 64 x 64)
 bool gett_big_tiles(const GettDesc& g);
+// Tile choice of plain launches on the calling host thread: 128 x 128 tiles when both free
+// dimensions reach 128 and the output holds at least big_tile_min such tiles (default 256).
+void set_big_tile_min(int n);
+int big_tile_min();
 // back to plain k steps (for tiles without packed steps)
 void gett_unpack_k(GettDesc& g);
 // fraction of the k values of all steps that are real (not zero padding)

@@ -644,9 +644,14 @@ void gett_prepare(GettDesc& g) {
 }
 
 // Large tiles (128 x 128) when they still give enough workgroups, else 64 x 64.
+// per host thread: a call plans and launches its contractions on one thread
+static thread_local int t_big_tile_min = 256;
+void set_big_tile_min(int n) { t_big_tile_min = n > 0 ? n : 256; }
+int big_tile_min() { return t_big_tile_min; }
+
 static bool big_tiles(const GettDesc& g) {
   long long t128 = (long long)((g.M + 127) / 128) * ((g.N + 127) / 128);
-  return g.M >= 128 && g.N >= 128 && t128 >= 256;
+  return g.M >= 128 && g.N >= 128 && t128 >= t_big_tile_min;
 }
 
 bool gett_big_tiles(const GettDesc& g) { return big_tiles(g); }

@@ -178,6 +178,7 @@ static void run(const double* ci, int nA, int na, int nb, const dsrg_options* O,
   if (!ci || !g1 || !g2) throw Err(DSRG_E_ARG, "null ci, gamma1 or gamma2");
   const bool dev = O && (O->flags & DSRG_F_DEVICE_PTRS);
   hipStream_t st = (O && O->stream) ? (hipStream_t)O->stream : (hipStream_t)0;
+  dsrg::set_big_tile_min(0);   // the built-in tile choice (tile rules are keyed by orbital spaces)
   const std::vector<uint32_t> Sa = subsets(nA, na), Sb = subsets(nA, nb);
   const long long nI = (long long)Sa.size(), nJ = (long long)Sb.size();
   std::vector<int> pos(1u << nA, -1), rank(1u << nA, 0);

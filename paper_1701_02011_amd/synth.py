@@ -50,6 +50,7 @@ __all__ = [
     "make_problem",
     "make_config",
     "make_batch_config",
+    "batch_sizes",
     "random_ci",
     "active_rdms",
     "fock_rdms",
@@ -375,13 +376,22 @@ def make_batch_config(n_geom: int = 64, base_seed: int = 4000, s: float = 0.5,
     U{80..400}), then uses naux = 4 N and gap factor 1 - 0.8 k/63.
     """
     probs = []
-    for k in range(first, first + n_geom):
-        rng = np.random.default_rng(base_seed + k)
-        nc = int(rng.integers(5, 16))
-        na = int(rng.integers(4, 9))
-        nv = int(rng.integers(80, 401))
+    for k, (nc, na, nv) in zip(range(first, first + n_geom), batch_sizes(n_geom, base_seed, first)):
         N = nc + na + nv
         gap = 1.0 - 0.8 * k / 63.0
         probs.append(make_problem(nc, na, nv, 4 * N, seed=base_seed + 10000 + k, s=s,
                                   gap=gap, name=f"curve{k}"))
     return probs
+
+
+def batch_sizes(n_geom: int = 64, base_seed: int = 4000, first: int = 0):
+    """(n_core, n_active, n_virtual) of the curve geometries first .. first + n_geom - 1,
+    without drawing their arrays."""
+    out = []
+    for k in range(first, first + n_geom):
+        rng = np.random.default_rng(base_seed + k)
+        nc = int(rng.integers(5, 16))
+        na = int(rng.integers(4, 9))
+        nv = int(rng.integers(80, 401))
+        out.append((nc, na, nv))
+    return out

@@ -8,6 +8,7 @@ Calls only ``oracle/`` (and the shared input generator).  Usage:
     python tests/golden/make_golden.py relax          # one-step relaxed energies (oracle/relax.py)
     python tests/golden/make_golden.py cas88          # CAS(8,8) with 150 virtuals, block-sparse DF
     python tests/golden/make_golden.py big-active     # active spaces of 9 to 16 orbitals
+    python tests/golden/make_golden.py curve 36       # geometry 36 of the synthetic curve (block level)
 Writes tests/golden/<name>_s<s>.json with E(2), E(3) and its two parts (and, for small,
 sampled intermediates), or tests/golden/small_pairs_s0.5.json with the core-pair
 decomposition of E(3).
@@ -102,6 +103,25 @@ def main_big_active(only=None):
     print(path, flush=True)
 
 
+def main_curve(k):
+    """One geometry of the 64-point synthetic dissociation curve, block-sparse level."""
+    import platform
+    from oracle import dsrg_df
+    from paper_1701_02011_amd.synth import make_batch_config
+    p = make_batch_config(1, first=k)[0]
+    t = time.time()
+    r = dsrg_df.run(p, log=lambda m: print(m, flush=True))
+    out = dict(workload="curve%d" % k, geometry=k, s=p.s, n_core=p.n_core, n_active=p.n_active,
+               n_virtual=p.n_virtual, n_aux=p.n_aux, e2=r.e2, e3=r.e3, e3_a=r.e3_a, e3_b=r.e3_b,
+               oracle_seconds=time.time() - t,
+               host=dict(cpus=os.cpu_count(), machine=platform.machine()),
+               source="oracle/dsrg_df.py (FP64, block-sparse spin orbitals, DF integrals)")
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "curve%d_s%g.json" % (k, p.s))
+    with open(path, "w") as f:
+        json.dump(out, f, indent=1)
+    print(path, out["e2"], out["e3"], "%.0fs" % out["oracle_seconds"], flush=True)
+
+
 def main(name):
     if name in ("medium", "large"):
         return main_df(name)
@@ -188,6 +208,8 @@ if __name__ == "__main__":
         main_pairs()
     elif arg == "relax":
         main_relax()
+    elif arg == "curve":
+        main_curve(int(sys.argv[2]))
     elif arg == "big-active":
         main_big_active(sys.argv[2] if len(sys.argv) > 2 else None)
     else:

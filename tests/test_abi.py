@@ -266,3 +266,18 @@ def test_dyall_argument_checks(lib):
     st.B = bad.ctypes.data
     assert f(ctypes.byref(st), opt, t.ctypes.data, None) == _lib.DSRG_E_NONFINITE
     assert np.all(t == 7.0)
+
+
+def test_tile_rules_argument_checks(lib):
+    """dsrg_set_tile_rules validates and replaces the rule table without device work."""
+    R = _lib.TileRule
+    assert ctypes.sizeof(R) == 16
+    arr = (R * 2)(R(0, 100, 128, 0), R(101, 200, 0, 8))
+    assert lib.dsrg_set_tile_rules(arr, 2) == 0
+    assert lib.dsrg_set_tile_rules(arr, -1) == _lib.DSRG_E_ARG
+    assert lib.dsrg_set_tile_rules(None, 1) == _lib.DSRG_E_ARG
+    bad = (R * 1)(R(50, 10, 0, 0))
+    assert lib.dsrg_set_tile_rules(bad, 1) == _lib.DSRG_E_ARG
+    bad = (R * 1)(R(0, 10, -1, 0))
+    assert lib.dsrg_set_tile_rules(bad, 1) == _lib.DSRG_E_ARG
+    assert lib.dsrg_set_tile_rules(None, 0) == 0
