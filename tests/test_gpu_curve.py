@@ -1,0 +1,77 @@
+"""The batched dissociation curve: geometries of uneven shapes through the batch entry
+point (rounds of members on library streams; unplanned shapes on worker threads), with the
+autotuner's tile rules installed, against stored oracle values of the geometries the
+block-sparse oracle level reaches and bit for bit against single calls; and the tile rules
+themselves (large-tile threshold, (PP|PP) batch) against the oracle."""
+import json
+import os
+import sys
+
+import pytest
+
+from paper_1701_02011_amd import _lib
+from paper_1701_02011_amd.synth import make_batch_config, make_config
+
+pytestmark = pytest.mark.gpu
+GOLDEN = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden")
+CURVE_GOLDEN = [36, 59]   # the two smallest geometries (n_V = 86, 96)
+
+
+def _close(x, ref, rel=1e-10):
+    return abs(x - ref) <= rel * max(1.0, abs(ref))
+
+
+def say(*a):
+    print(*a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture
+def tuned():
+    rules = _lib.load_tile_rules()
+    yield rules
+    _lib.set_tile_rules([])
+
+
+def test_curve_batch_against_oracle_and_single_calls(tuned):
+    probs = [make_batch_config(1, first=k)[0] for k in CURVE_GOLDEN]
+    probs.insert(1, make_batch_config(1, first=4)[0])   # a third shape between them
+    say("curve batch", [(p.n_core, p.n_active, p.n_virtual, p.n_aux) for p in probs], "rules", tuned)
+    dev = [_lib.to_device(p) for p in probs]
+    res, codes = _lib.dsrg_pt3_energy_batch(dev)
+    assert all(c == _lib.DSRG_OK for c in codes), codes
+    again, codes = _lib.dsrg_pt3_energy_batch(dev)
+    assert all(c == _lib.DSRG_OK for c in codes), codes
+    for k, (p, d) in enumerate(zip(probs, dev)):
+        single = _lib.dsrg_pt3_energy(d, cache=False)
+        for r in (res[k], again[k]):
+            assert (r["e2"], r["e3_a"], r["e3_b"]) == (single["e2"], single["e3_a"], single["e3_b"]), k
+    for k, g in zip((0, 2), CURVE_GOLDEN):
+        with open(os.path.join(GOLDEN, "curve%d_s0.5.json" % g)) as f:
+            ref = json.load(f)
+        assert (ref["n_core"], ref["n_active"], ref["n_virtual"]) == (probs[k].n_core, probs[k].n_active,
+                                                                      probs[k].n_virtual)
+        for key in ("e2", "e3_a", "e3_b"):
+            assert _close(res[k][key], ref[key]), (g, key, res[k][key], ref[key])
+
+
+def test_tile_rules_keep_the_energies():
+    """Every contraction on 128 x 128 tiles where the shapes allow, and (PP|PP) batches of 3
+    rows: the small workload still matches the oracle's stored values; the rules reach only
+    the calls of their size class."""
+    p = make_config("small")
+    with open(os.path.join(GOLDEN, "small_s0.5.json")) as f:
+        ref = json.load(f)
+    base = _lib.dsrg_pt3_energy(p, cache=False)
+    nP = p.n_active + p.n_virtual
+    try:
+        _lib.set_tile_rules([dict(np_min=nP, np_max=nP, big_tile_min=1, virt_batch=3)])
+        r = _lib.dsrg_pt3_energy(p, cache=False)
+        assert r["virt_batch_used"] == 3
+        _lib.set_tile_rules([dict(np_min=nP + 1, np_max=nP + 10, big_tile_min=1, virt_batch=3)])
+        other = _lib.dsrg_pt3_energy(p, cache=False)
+    finally:
+        _lib.set_tile_rules([])
+    for key in ("e2", "e3_a", "e3_b"):
+        assert _close(r[key], ref[key]), (key, r[key], ref[key])
+    assert other["virt_batch_used"] == base["virt_batch_used"] and other["e3"] == base["e3"]
