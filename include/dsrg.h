@@ -123,8 +123,13 @@ typedef struct {
 typedef struct {
   int32_t flags;          /* DSRG_F_* */
   int32_t precision;      /* DSRG_PRECISION_FP64 (0), _FP32 (1) or _BF16X3 (2) */
-  int64_t workspace_cap;  /* bytes of device workspace for the batched (PP|PP) integrals and their
-                             packed pair rows; 0 = 8 GiB */
+  int64_t workspace_cap;  /* bytes of device workspace for the (PP|PP) integrals and their packed
+                             pair rows; 0 = 48 GiB.  When the whole block over particle pairs
+                             x <= y (8 (nP (nP + 1) / 2)^2 bytes, plus n_aux nP (nP + 1) / 2 for
+                             the packed B) fits beside one batch of packed rows, it is built
+                             once and kept resident; else it is built in batches of rows.  Half
+                             of an explicit cap (4 GiB by default) bounds the temporaries of a
+                             grouped commutator. */
   void* stream;           /* hipStream_t to run on, or NULL for the null stream; caller owns it */
   int32_t virt_batch;     /* values of the first particle index per (PP|PP) integral batch
                              (Sec. III, Eq. scaling_problem); 0 = the largest batch that fits
@@ -392,7 +397,9 @@ const char* dsrg_last_error(void);
 /* Library version: major * 10000 + minor * 100 + patch. */
 int dsrg_version(void);
 
-/* Free the cached plans (device buffers and graphs) that no call is using.  Returns
+/* Free the cached plans (device buffers and graphs) that no call is using, and the large
+   device buffers (64 MiB and up) the library keeps after a call for reuse by later calls on
+   the same device (at most 96 GiB are kept; a failed allocation frees them too).  Returns
    DSRG_OK. */
 int dsrg_release_cache(void);
 

@@ -241,11 +241,71 @@ static const char* storage_axes(const std::string& t) {
 // pool (keep = true) never frees before the plan is destroyed, because a captured graph
 // addresses every buffer of the pipeline.
 // ---------------------------------------------------------------------------
+// Large device buffers kept across calls.  Allocating and freeing tens of GB per call
+// (the resident (PP|PP) block, its packed rows) made later calls of the same process stall
+// for seconds inside the runtime; a buffer of at least kBigBytes goes back to this list
+// when its pool is destroyed (its work finished: the pool synchronises its stream, or a
+// plan's last use did) and serves a later request of the same device that it covers
+// within a factor of two.  At most kCachedBytes stay listed; dsrg_release_cache() and a
+// failed allocation empty the list.
+constexpr size_t kBigBytes = 64ULL << 20;
+constexpr size_t kCachedBytes = 96ULL << 30;
+struct BigCache {
+  std::mutex mu;
+  struct Buf {
+    int dev;
+    size_t bytes;
+    void* p;
+  };
+  std::vector<Buf> free_list;
+  size_t held = 0;
+  // a listed buffer of dev holding at least `bytes` (and at most twice that), or null;
+  // *got receives its size
+  void* take(int dev, size_t bytes, size_t* got) {
+    std::lock_guard<std::mutex> lk(mu);
+    int best = -1;
+    for (int i = 0; i < (int)free_list.size(); ++i) {
+      const Buf& b = free_list[i];
+      if (b.dev == dev && b.bytes >= bytes && b.bytes <= 2 * bytes &&
+          (best < 0 || b.bytes < free_list[best].bytes))
+        best = i;
+    }
+    if (best < 0) return nullptr;
+    void* p = free_list[best].p;
+    *got = free_list[best].bytes;
+    held -= free_list[best].bytes;
+    free_list.erase(free_list.begin() + best);
+    return p;
+  }
+  void give(int dev, size_t bytes, void* p) {
+    std::lock_guard<std::mutex> lk(mu);
+    free_list.push_back({dev, bytes, p});
+    held += bytes;
+    while (held > kCachedBytes && !free_list.empty()) {   // oldest first
+      held -= free_list.front().bytes;
+      (void)hipFree(free_list.front().p);
+      free_list.erase(free_list.begin());
+    }
+  }
+  void clear() {
+    std::lock_guard<std::mutex> lk(mu);
+    for (auto& b : free_list) (void)hipFree(b.p);
+    free_list.clear();
+    held = 0;
+  }
+};
+static BigCache& big_cache() {
+  static BigCache* c = new BigCache;   // never destroyed: buffers outlive static teardown
+  return *c;
+}
+
 struct Pool {
   hipStream_t st;     // synchronised before freeing while sync_before_free is set
   bool keep;
   bool sync_before_free = true;
   std::vector<void*> bufs;
+  std::vector<size_t> sizes;   // bytes of each buffer (cached big buffers may be larger)
+  int dev = -1;
   size_t bytes = 0;
   // arena mode: buffers are carved in order from [arena, arena + arena_cap) (256-byte
   // aligned) and never freed; nothing is allocated from the runtime
@@ -267,12 +327,28 @@ struct Pool {
       return p;
     }
     void* p = nullptr;
-    hipError_t e = hipMalloc(&p, n * sizeof(double));
-    if (e != hipSuccess) {
-      (void)hipGetLastError();
-      throw Error(DSRG_E_OOM, "device allocation of " + std::to_string(n * 8) + " bytes failed");
+    size_t got = n * sizeof(double);
+    if (got >= kBigBytes) {
+      if (dev < 0 && hipGetDevice(&dev) != hipSuccess) {
+        (void)hipGetLastError();
+        throw Error(DSRG_E_HIP, "hipGetDevice failed");
+      }
+      p = big_cache().take(dev, got, &got);
+    }
+    if (!p) {
+      hipError_t e = hipMalloc(&p, got);
+      if (e != hipSuccess && got >= kBigBytes) {
+        (void)hipGetLastError();
+        big_cache().clear();
+        e = hipMalloc(&p, got);
+      }
+      if (e != hipSuccess) {
+        (void)hipGetLastError();
+        throw Error(DSRG_E_OOM, "device allocation of " + std::to_string(n * 8) + " bytes failed");
+      }
     }
     bufs.push_back(p);
+    sizes.push_back(got);
     bytes += n * 8;
     return (double*)p;
   }
@@ -280,14 +356,17 @@ struct Pool {
     if (keep) return;
     for (auto& b : bufs)
       if (b == p) {
-        (void)hipFree(b);
+        (void)hipFree(b);   // synchronises with the work that may still read it
         b = nullptr;
       }
   }
   ~Pool() {
     if (sync_before_free) (void)hipStreamSynchronize(st);
-    for (void* p : bufs)
-      if (p) (void)hipFree(p);
+    for (size_t i = 0; i < bufs.size(); ++i) {
+      if (!bufs[i]) continue;
+      if (sizes[i] >= kBigBytes && dev >= 0) big_cache().give(dev, sizes[i], bufs[i]);
+      else (void)hipFree(bufs[i]);
+    }
   }
 };
 
@@ -406,6 +485,8 @@ struct Exec {
   // last, so both load with k fastest.  Only when the other free dimension is large
   // enough for the copy to cost a small fraction of the contraction.
   static constexpr long long kPackMin = 64, kPackCap = 1LL << 28;
+  // tile block of the triangular build of the resident (PP|PP) block (a multiple of 32)
+  static constexpr int kFullKBlock = 128;
   double* pack_buf[2] = {nullptr, nullptr};
   long long pack_elems[2] = {0, 0};
   static bool unit_fast(bool kfast, int nfree, const long long* free_stride, long long k_inner) {
@@ -2108,10 +2189,21 @@ struct Exec {
       const bool tri_build = pairs && full.empty();
       const long long kp = (long long)nP * (nP - 1) / 2, kp1 = kp + nP;
       const long long np = (long long)nH * (nH - 1) / 2, np1 = np + nH;
-      // doubles per value of the batch letter: integral rows plus packed rows
+      // The whole (PP|PP) block over particle pairs x <= y, K[pair(p, x)][pair(q, y)] =
+      // (p x|q y), resident when it fits the workspace beside one value's packed rows: one
+      // triangular contraction over the packed B builds it (the pair symmetries of real
+      // integrals leave a quarter of the batched build's work) and the pair packs read it.
+      const long long npk = (long long)nP * (nP + 1) / 2;
+      const long long per_rows = pairs ? (long long)nP * (kp + (sym ? kp1 : 0)) : 0;
+      const long long kbytes = 8 * (npk * npk + (long long)M * npk);   // K and the packed B
+      bool fullk = tri_build && per_rows > 0 && npk < (1LL << 31) && ws_cap - kbytes >= 8 * per_rows;
+      if (fullk && virt_batch > 0 &&
+          (ws_cap - kbytes) / (8 * per_rows) < std::min<long long>(virt_batch, lbl))
+        fullk = false;   // the requested batch needs the batched build's memory
+      // doubles per value of the batch letter: integral rows (batched build) plus packed rows
       const long long per = (long long)nP * nP * nP;
-      const long long per_all = per + (pairs ? (long long)nP * (kp + (sym ? kp1 : 0)) : 0);
-      const long long fit = ws_cap / (8 * per_all);
+      const long long per_all = (fullk ? 0 : per) + per_rows;
+      const long long fit = (ws_cap - (fullk ? kbytes : 0)) / (8 * per_all);
       if (fit < 1)
         throw Error(DSRG_E_OOM, "workspace_cap of " + std::to_string(ws_cap) + " bytes is below one (PP|PP) batch row of " +
                                     std::to_string(8 * per_all) + " bytes");
@@ -2206,7 +2298,33 @@ struct Exec {
         gett(g, A, Bm, C, kRoleLadder);
       };
       // products are written with the batch letter first in the J factor: rotate letters
-      double* jb = jbatch_buffer(nb * per);
+      double* jb = fullk ? nullptr : jbatch_buffer(nb * per);
+      double* Kfull = nullptr;
+      if (fullk) {
+        double* Bp = pool.alloc((size_t)M * npk);
+        const int Nl = d.nC + d.nA + d.nV, offP = d.off('P'), nPl = nP, Ml = M;
+        const double* Bl = B;
+        op([Bl, Nl, offP, nPl, Ml, Bp](hipStream_t s) { launch_pack_pairs(Bl, Nl, offP, nPl, Ml, Bp, s); });
+        ++n_launch;
+        Kfull = pool.alloc((size_t)(npk * npk));
+        GettDesc g;
+        g.nm = 1; g.nn = 1; g.nk = 1;
+        g.md[0] = (int)npk; g.nd[0] = (int)npk; g.kd[0] = M;
+        g.M = (int)npk; g.N = (int)npk; g.K = M;
+        g.am[0] = 1; g.ak[0] = npk;
+        g.bk[0] = npk; g.bn[0] = 1;
+        g.cm[0] = npk; g.cn[0] = 1;
+        g.alpha = 1.0; g.beta = 0;
+        gett_prepare(g);
+        g.tri = kFullKBlock;   // the blocks below the diagonal are mirrored instead
+        double fb0 = gett_flops;
+        gett(g, Bp, Bp, Kfull, kRoleIntegrals);
+        ladder_flops += gett_flops - fb0;
+        double* Kl = Kfull;
+        const long long nk = npk;
+        op([Kl, nk](hipStream_t s) { launch_mirror_lower(Kl, nk, kFullKBlock, s); });
+        ++n_launch;
+      }
       hipEvent_t e0 = nullptr, e1 = nullptr;
       if (profile) {
         HIPCHECK(hipEventCreate(&e0));
@@ -2222,7 +2340,8 @@ struct Exec {
         double fb = gett_flops;
         // with rows q >= b0 only, the blocks of rows p and columns q < p stay unbuilt (the
         // packs read q >= p)
-        build_j('P', 'P', 'P', 'P', off1, n1, jb, qoff, nq, tri_build ? nP : 0);
+        if (!fullk) build_j('P', 'P', 'P', 'P', off1, n1, jb, qoff, nq, tri_build ? nP : 0);
+        const double* Kl = Kfull;
         if (pairs) {
           const long long r0 = rs0[b0], na = rs0[b0 + n1] - r0;
           const long long s0 = sym ? rs1[b0] : 0, ns = sym ? rs1[b0 + n1] - s0 : 0;
@@ -2234,20 +2353,23 @@ struct Exec {
           if (anti_part && ns > 0) {
             // both parts from one read of the batch: the rows p <= q carry the strict ones
             const long long r0l = r0;
-            op([jb, nPl, b0, qoff, nq, rsy, nsi, Vs, Va, r0l](hipStream_t s) {
-              launch_ladder_pack_v(jb, nPl, b0, qoff, nq, rsy, nsi, 1, Vs, s, Va, r0l);
+            op([jb, Kl, nPl, b0, qoff, nq, rsy, nsi, Vs, Va, r0l](hipStream_t s) {
+              if (Kl) launch_ladder_pack_vk(Kl, nPl, rsy, nsi, 1, Vs, s, Va, r0l);
+              else launch_ladder_pack_v(jb, nPl, b0, qoff, nq, rsy, nsi, 1, Vs, s, Va, r0l);
             });
             ++n_launch;
           } else {
             if (anti_part) {
-              op([jb, nPl, b0, qoff, nq, ra, nai, Va](hipStream_t s) {
-                launch_ladder_pack_v(jb, nPl, b0, qoff, nq, ra, nai, 0, Va, s);
+              op([jb, Kl, nPl, b0, qoff, nq, ra, nai, Va](hipStream_t s) {
+                if (Kl) launch_ladder_pack_vk(Kl, nPl, ra, nai, 0, Va, s);
+                else launch_ladder_pack_v(jb, nPl, b0, qoff, nq, ra, nai, 0, Va, s);
               });
               ++n_launch;
             }
             if (ns > 0) {
-              op([jb, nPl, b0, qoff, nq, rsy, nsi, Vs](hipStream_t s) {
-                launch_ladder_pack_v(jb, nPl, b0, qoff, nq, rsy, nsi, 1, Vs, s);
+              op([jb, Kl, nPl, b0, qoff, nq, rsy, nsi, Vs](hipStream_t s) {
+                if (Kl) launch_ladder_pack_vk(Kl, nPl, rsy, nsi, 1, Vs, s);
+                else launch_ladder_pack_v(jb, nPl, b0, qoff, nq, rsy, nsi, 1, Vs, s);
               });
               ++n_launch;
             }
@@ -3014,6 +3136,7 @@ struct Setup {
   bool devptr = false, profile = false, grouped = true, unique_ladder = true;
   bool want_pairs = false, cacheable = false;
   long long cap = 0;
+  long long group_cap = 0;   // bytes of temporaries one grouped commutator may hold
   int vb = 0;   // requested (PP|PP) batch (0: largest that fits)
   hipStream_t st = nullptr;
   int dev = 0;
@@ -3074,7 +3197,8 @@ static Setup setup(const dsrg_problem* P, const dsrg_options* O, const dsrg_inte
     check_intruder(nC, nA, nV, e.data());
   }
   S.st = (O && O->stream) ? (hipStream_t)O->stream : (hipStream_t)0;
-  S.cap = (O && O->workspace_cap > 0) ? O->workspace_cap : (8LL << 30);
+  S.cap = (O && O->workspace_cap > 0) ? O->workspace_cap : (48LL << 30);
+  S.group_cap = (O && O->workspace_cap > 0) ? O->workspace_cap / 2 : (4LL << 30);
   S.grouped = !(flags & DSRG_F_NO_GROUPING);
   S.unique_ladder = !(flags & DSRG_F_FULL_LADDER);
   if (pt3 && nC + nA > 0 && nA + nV > 0) {
@@ -3284,7 +3408,7 @@ static int run(const dsrg_problem* P, const dsrg_options* O, dsrg_result* R,
   Exec X(Dims{nC, nA, nV}, st, *pool, op, in.B, M, cap, profile);
   X.grouped = grouped;
   X.unique_ladder = unique_ladder;
-  X.group_cap = cap / 2;
+  X.group_cap = S.group_cap;
   X.prec = prec;
   X.virt_batch = S.vb;
   mark(ev, 0, st);
@@ -3839,10 +3963,13 @@ int dsrg_version(void) { return 100; }
 
 int dsrg_release_cache(void) {
   return dsrg::guarded([&] {
-    std::lock_guard<std::mutex> lk(dsrg::g_plan_mu);
-    auto& v = dsrg::plans();
-    for (size_t i = v.size(); i-- > 0;)
-      if (!v[i]->busy) v.erase(v.begin() + i);
+    {
+      std::lock_guard<std::mutex> lk(dsrg::g_plan_mu);
+      auto& v = dsrg::plans();
+      for (size_t i = v.size(); i-- > 0;)
+        if (!v[i]->busy) v.erase(v.begin() + i);
+    }
+    dsrg::big_cache().clear();
     return DSRG_OK;
   });
 }

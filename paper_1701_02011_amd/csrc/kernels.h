@@ -209,6 +209,16 @@ struct LadderPair {
 void launch_ladder_pack_v(const double* jb, int nP, int b0, int qoff, int nq, const LadderPair* rowtab,
                           int rows, int sym, double* Vp, hipStream_t st, double* Va = nullptr,
                           long long m0 = 0);
+// As launch_ladder_pack_v, reading the integrals from the resident packed block
+// K[pair(p, x)][pair(q, y)] = (p x|q y) (pairs a <= b of the nP particle orbitals, a-major;
+// K is npk x npk with npk = nP (nP + 1) / 2, both triangles stored).
+void launch_ladder_pack_vk(const double* K, int nP, const LadderPair* rowtab, int rows, int sym, double* Vp,
+                           hipStream_t st, double* Va = nullptr, long long m0 = 0);
+// Bp[Q][pair(a, b)] = B[Q][off + a][off + b] for a <= b < nP (B is [M][N][N])
+void launch_pack_pairs(const double* B, int N, int off, int nP, int M, double* Bp, hipStream_t st);
+// Fill K[i][j] = K[j][i] (n x n, row-major) where i / blk > j / blk: the blocks a contraction
+// with tri = blk skips (blk a multiple of 32)
+void launch_mirror_lower(double* K, long long n, int blk, hipStream_t st);
 // Tp[n][k] from T [P][P][H][H], (x, y) = ktab[k], (I, J) = ntab[n]:
 // mode 0: T[x][y][I][J];  mode 1: (T[x][y][I][J] + T[y][x][I][J]) / 2;
 // mode 2: (T[x][y][I][J] - T[y][x][I][J]) / 2

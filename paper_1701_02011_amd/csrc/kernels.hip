@@ -1316,6 +1316,21 @@ void launch_antisym_add_list(const AntisymList& l, int nP, int nH, hipStream_t s
 // M[X][Y] of M[x][y] = jb[p - b0][x][q - qoff][y] and its mirror M[Y][X] are read with y
 // fastest into LDS, and V is written in packed order (y fastest inside each x).
 constexpr int kPackTile = 32;
+
+// position of the particle pair (a, b) among the pairs a <= b in a-major order
+__device__ __forceinline__ long long pair_pos(int nP, int a, int b) {
+  if (a > b) {
+    const int t = a;
+    a = b;
+    b = t;
+  }
+  const long long al = a;
+  return al * nP - al * (al - 1) / 2 + (b - a);
+}
+
+// Integral source of the packs: a batch jb[p - b0][x][q - qoff][y] = (p x|q y) (kFull =
+// false) or the resident packed block K[pair(p, x)][pair(q, y)] (kFull = true).
+template <bool kFull>
 __global__ __launch_bounds__(256) void ladder_pack_v_kernel(const double* __restrict__ jb, int nP, int b0,
                                                             int qoff, int nq,
                                                             const LadderPair* __restrict__ rowtab, int rows,
@@ -1325,6 +1340,7 @@ __global__ __launch_bounds__(256) void ladder_pack_v_kernel(const double* __rest
   __shared__ double A[kPackTile][kPackTile + 1], Bm[kPackTile][kPackTile + 1];
   const int nT = (nP + kPackTile - 1) / kPackTile;
   const long long sq = nP, sx = (long long)nq * nP, sp = sx * nP;
+  const long long npk = (long long)nP * (nP + 1) / 2;
   for (long long w = blockIdx.x; w < (long long)rows * ntp; w += gridDim.x) {
     const int row = (int)(w / ntp);
     int t = (int)(w - (long long)row * ntp);
@@ -1336,15 +1352,19 @@ __global__ __launch_bounds__(256) void ladder_pack_v_kernel(const double* __rest
     }
     const int ty = tx + t;
     const LadderPair pq = rowtab[row];
-    const double* M = jb + (pq.a - b0) * sp + (long long)(pq.b - qoff) * sq;
+    // (p x|q y) of this row's pair (p, q)
+    auto J = [&](int x, int y) -> double {
+      if constexpr (kFull) return jb[pair_pos(nP, pq.a, x) * npk + pair_pos(nP, pq.b, y)];
+      else return jb[(pq.a - b0) * sp + (long long)(pq.b - qoff) * sq + x * sx + y];
+    };
     const int X0 = tx * kPackTile, Y0 = ty * kPackTile;
     __syncthreads();
     for (int e = threadIdx.x; e < kPackTile * kPackTile; e += 256) {
       const int i = e / kPackTile, j = e % kPackTile;
       const int x = X0 + i, y = Y0 + j;
-      A[i][j] = (x < nP && y < nP) ? M[x * sx + y] : 0.0;
+      A[i][j] = (x < nP && y < nP) ? J(x, y) : 0.0;
       const int x2 = Y0 + i, y2 = X0 + j;
-      Bm[i][j] = (x2 < nP && y2 < nP) ? M[x2 * sx + y2] : 0.0;
+      Bm[i][j] = (x2 < nP && y2 < nP) ? J(x2, y2) : 0.0;
     }
     __syncthreads();
     double* out = Vp + (long long)row * kpx;
@@ -1354,7 +1374,7 @@ __global__ __launch_bounds__(256) void ladder_pack_v_kernel(const double* __rest
       const int i = e / kPackTile, j = e % kPackTile;
       const int x = X0 + i, y = Y0 + j;
       if (x >= nP || y >= nP || (sym ? y < x : y <= x)) continue;
-      const double u = A[i][j], v = Bm[j][i];   // M[x][y], M[y][x]
+      const double u = A[i][j], v = Bm[j][i];   // (p x|q y), (p y|q x)
       const long long xl = x;
       const long long ka = xl * nP - xl * (xl + 1) / 2 + (y - x - 1);
       const long long k = sym ? xl * nP - xl * (xl - 1) / 2 + (y - x) : ka;
@@ -1362,6 +1382,60 @@ __global__ __launch_bounds__(256) void ladder_pack_v_kernel(const double* __rest
       if (outa && y > x) outa[ka] = u - v;
     }
   }
+}
+
+// Bp[Q][pair(a, b)] = B[Q][off + a][off + b] over the pairs a <= b of nP orbitals from off
+__global__ __launch_bounds__(256) void pack_pairs_kernel(const double* __restrict__ B, int N, int off, int nP,
+                                                         long long total, double* __restrict__ Bp) {
+  const long long npk = (long long)nP * (nP + 1) / 2;
+  for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < total;
+       e += (long long)gridDim.x * blockDim.x) {
+    const long long Q = e / ((long long)nP * nP);
+    const int r = (int)(e - Q * nP * nP);
+    const int a = r / nP, b = r - a * nP;
+    if (a > b) continue;
+    Bp[Q * npk + pair_pos(nP, a, b)] = B[(Q * N + off + a) * N + off + b];
+  }
+}
+
+// K[i][j] = K[j][i] for the elements whose row block i / blk lies below the column block
+// j / blk (those a triangular contraction with tri = blk leaves unwritten); 32 x 32 tiles
+// through LDS, tile (ti, tj) of the lower part taken from the transposed tile.
+__global__ __launch_bounds__(256) void mirror_lower_kernel(double* __restrict__ K, long long n, int blk) {
+  __shared__ double T[32][33];
+  const long long nt = (n + 31) / 32;
+  const int per = blk / 32;   // 32-tiles per block
+  for (long long w = blockIdx.x; w < nt * nt; w += gridDim.x) {
+    const long long ti = w / nt, tj = w - (w / nt) * nt;
+    if (ti / per <= tj / per) continue;   // uniform over the workgroup
+    __syncthreads();
+    for (int e = threadIdx.x; e < 1024; e += 256) {
+      const int a = e / 32, b = e % 32;
+      const long long r = tj * 32 + a, c = ti * 32 + b;   // source: upper tile (tj, ti)
+      T[a][b] = (r < n && c < n) ? K[r * n + c] : 0.0;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 1024; e += 256) {
+      const int a = e / 32, b = e % 32;
+      const long long r = ti * 32 + a, c = tj * 32 + b;
+      if (r < n && c < n) K[r * n + c] = T[b][a];
+    }
+  }
+}
+
+static unsigned grid_for(long long n);
+
+void launch_pack_pairs(const double* B, int N, int off, int nP, int M, double* Bp, hipStream_t st) {
+  const long long total = (long long)M * nP * nP;
+  if (total <= 0) return;
+  hipLaunchKernelGGL(pack_pairs_kernel, dim3(grid_for(total)), dim3(256), 0, st, B, N, off, nP, total, Bp);
+}
+
+void launch_mirror_lower(double* K, long long n, int blk, hipStream_t st) {
+  const long long nt = (n + 31) / 32;
+  if (nt <= 1 || blk % 32 != 0) return;
+  const unsigned grid = (unsigned)std::min<long long>(nt * nt, 1LL << 20);
+  hipLaunchKernelGGL(mirror_lower_kernel, dim3(grid), dim3(256), 0, st, K, n, blk);
 }
 
 __global__ __launch_bounds__(256) void ladder_pack_t_kernel(const double* __restrict__ T, int nP, int nH,
@@ -1434,7 +1508,18 @@ void launch_ladder_pack_v(const double* jb, int nP, int b0, int qoff, int nq, co
   const int nT = (nP + kPackTile - 1) / kPackTile, ntp = nT * (nT + 1) / 2;
   const long long work = (long long)rows * ntp;
   const unsigned grid = (unsigned)std::min<long long>(work, 1LL << 20);
-  hipLaunchKernelGGL(ladder_pack_v_kernel, dim3(grid), dim3(256), 0, st, jb, nP, b0, qoff, nq, rowtab, rows, ntp,
+  hipLaunchKernelGGL(ladder_pack_v_kernel<false>, dim3(grid), dim3(256), 0, st, jb, nP, b0, qoff, nq, rowtab, rows,
+                     ntp, sym, kpx, Vp, sym ? Va : nullptr, m0);
+}
+
+void launch_ladder_pack_vk(const double* K, int nP, const LadderPair* rowtab, int rows, int sym, double* Vp,
+                           hipStream_t st, double* Va, long long m0) {
+  const long long kpx = sym ? (long long)nP * (nP + 1) / 2 : (long long)nP * (nP - 1) / 2;
+  if (rows <= 0 || kpx <= 0) return;
+  const int nT = (nP + kPackTile - 1) / kPackTile, ntp = nT * (nT + 1) / 2;
+  const long long work = (long long)rows * ntp;
+  const unsigned grid = (unsigned)std::min<long long>(work, 1LL << 20);
+  hipLaunchKernelGGL(ladder_pack_v_kernel<true>, dim3(grid), dim3(256), 0, st, K, nP, 0, 0, nP, rowtab, rows, ntp,
                      sym, kpx, Vp, sym ? Va : nullptr, m0);
 }
 

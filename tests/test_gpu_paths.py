@@ -190,3 +190,27 @@ def test_device_density_check():
     d["gamma1"][0, 0, 1] = float(p.gamma1[0, 0, 1])
     again = _lib.dsrg_pt3_energy(d)
     assert again["e2"] == first["e2"] and again["e3"] == first["e3"]
+
+
+@pytest.mark.parametrize("mode", ["resident", "batched"])
+def test_cas88_against_block_oracle(mode):
+    """CAS(8,8) with 150 virtual orbitals (nP = 158) against the stored block-level oracle
+    values: the (PP|PP) block either resident over particle pairs (the default) or built in
+    batches of 16 rows (a workspace_cap below the resident block), 128 x 128 tiles on the
+    large contractions."""
+    with open(os.path.join(GOLDEN, "cas88_s0.5.json")) as f:
+        gold = json.load(f)
+    # the shape and seed tests/golden/make_golden.py cas88 uses
+    p = make_problem(n_core=12, n_active=8, n_virtual=150, n_aux=600, seed=404, s=0.5, name="cas88")
+    assert (gold["n_core"], gold["n_active"], gold["n_virtual"], gold["n_aux"]) == (
+        p.n_core, p.n_active, p.n_virtual, p.n_aux)
+    nP = p.n_active + p.n_virtual
+    kp = nP * (nP - 1) // 2
+    row = 8 * (nP ** 3 + nP * (2 * kp + nP))
+    kw = dict(cache=False) if mode == "resident" else dict(cache=False, workspace_cap=16 * row)
+    say("cas88", mode)
+    g = _lib.dsrg_pt3_energy(p, **kw)
+    if mode == "batched":
+        assert g["virt_batch_used"] == 16
+    for k in ("e2", "e3_a", "e3_b"):
+        assert _close(g[k], gold[k]), (k, g[k], gold[k])
