@@ -1352,19 +1352,57 @@ __global__ __launch_bounds__(256) void ladder_pack_v_kernel(const double* __rest
     }
     const int ty = tx + t;
     const LadderPair pq = rowtab[row];
-    // (p x|q y) of this row's pair (p, q)
-    auto J = [&](int x, int y) -> double {
-      if constexpr (kFull) return jb[pair_pos(nP, pq.a, x) * npk + pair_pos(nP, pq.b, y)];
-      else return jb[(pq.a - b0) * sp + (long long)(pq.b - qoff) * sq + x * sx + y];
-    };
+    const int p = pq.a, q = pq.b;
     const int X0 = tx * kPackTile, Y0 = ty * kPackTile;
     __syncthreads();
-    for (int e = threadIdx.x; e < kPackTile * kPackTile; e += 256) {
-      const int i = e / kPackTile, j = e % kPackTile;
-      const int x = X0 + i, y = Y0 + j;
-      A[i][j] = (x < nP && y < nP) ? J(x, y) : 0.0;
-      const int x2 = Y0 + i, y2 = X0 + j;
-      Bm[i][j] = (x2 < nP && y2 < nP) ? J(x2, y2) : 0.0;
+    if constexpr (!kFull) {
+      const double* M = jb + (p - b0) * sp + (long long)(q - qoff) * sq;
+      for (int e = threadIdx.x; e < kPackTile * kPackTile; e += 256) {
+        const int i = e / kPackTile, j = e % kPackTile;
+        const int x = X0 + i, y = Y0 + j;
+        A[i][j] = (x < nP && y < nP) ? M[x * sx + y] : 0.0;
+        const int x2 = Y0 + i, y2 = X0 + j;
+        Bm[i][j] = (x2 < nP && y2 < nP) ? M[x2 * sx + y2] : 0.0;
+      }
+    } else {
+      // (p x|q y) from the symmetric K, read where consecutive lanes meet consecutive
+      // columns: row pair(p, x) along y while y >= q (columns pair(q, y) are contiguous),
+      // row pair(y, q) along x while y < q and x >= p (columns pair(p, x) contiguous, by the
+      // symmetry of K); the rest (x < p, y < q) element by element.  Pass 0 walks y
+      // fastest, pass 1 x.
+      auto J = [&](int x, int y) -> double {
+        if (y >= q) return jb[pair_pos(nP, p, x) * npk + pair_pos(nP, q, y)];
+        if (x >= p) return jb[pair_pos(nP, y, q) * npk + pair_pos(nP, p, x)];
+        return jb[pair_pos(nP, x, p) * npk + pair_pos(nP, y, q)];
+      };
+      // tile T (0: A holds S[X0 + i][Y0 + j]; 1: Bm holds S[Y0 + i][X0 + j]) over S[x][y] =
+      // (p x|q y)
+      for (int e = threadIdx.x; e < kPackTile * kPackTile; e += 256) {
+        const int i = e / kPackTile, j = e % kPackTile;   // j fastest
+        {
+          const int x = X0 + i, y = Y0 + j;
+          const bool in = x < nP && y < nP;
+          if (!in) A[i][j] = 0.0;
+          else if (y >= q || x < p) A[i][j] = J(x, y);
+        }
+        {
+          const int x = Y0 + i, y = X0 + j;
+          const bool in = x < nP && y < nP;
+          if (!in) Bm[i][j] = 0.0;
+          else if (y >= q || x < p) Bm[i][j] = J(x, y);
+        }
+      }
+      for (int e = threadIdx.x; e < kPackTile * kPackTile; e += 256) {
+        const int i = e % kPackTile, j = e / kPackTile;   // i fastest
+        {
+          const int x = X0 + i, y = Y0 + j;
+          if (x < nP && y < nP && y < q && x >= p) A[i][j] = J(x, y);
+        }
+        {
+          const int x = Y0 + i, y = X0 + j;
+          if (x < nP && y < nP && y < q && x >= p) Bm[i][j] = J(x, y);
+        }
+      }
     }
     __syncthreads();
     double* out = Vp + (long long)row * kpx;
@@ -1560,8 +1598,76 @@ __global__ __launch_bounds__(256) void scatter_kernel(ScatterDesc d, const doubl
   }
 }
 
+// Transposing variant for a source whose fastest dimension u differs from the target's
+// fastest dimension w: a workgroup takes a 32 x 32 tile of (u, w) at one index of the other
+// dimensions (ru: their row-major composition, up to kMaxComp - 2 of them), reads it along
+// u and writes it along w, both coalesced.  Same arithmetic as scatter_kernel per element.
+struct ScatterTile {
+  int nr = 0;                  // other dimensions
+  int rd[kMaxComp] = {};       // their extents (row-major)
+  long long rs[kMaxComp] = {}, ro[kMaxComp] = {};   // their source and target strides
+  int du = 1, dw = 1;
+  long long su = 0, ou = 0, sw = 0, ow = 0;        // strides of u and w (source, target)
+  long long rest = 1;          // product of rd
+  double coef = 1.0;
+};
+__global__ __launch_bounds__(256) void scatter_tiled_kernel(ScatterTile t, const double* __restrict__ src,
+                                                            double* __restrict__ out) {
+  __shared__ double T[32][33];
+  const int tu = (t.du + 31) / 32, tw = (t.dw + 31) / 32;
+  const long long work = t.rest * tu * tw;
+  for (long long w = blockIdx.x; w < work; w += gridDim.x) {
+    long long r = w / (tu * tw);
+    const int q = (int)(w - r * (tu * tw));
+    const int u0 = (q % tu) * 32, w0 = (q / tu) * 32;
+    long long sb = 0, ob = 0;
+    for (int c = t.nr - 1; c >= 0; --c) {
+      const long long x = r % t.rd[c];
+      r /= t.rd[c];
+      sb += x * t.rs[c];
+      ob += x * t.ro[c];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 1024; e += 256) {
+      const int b = e & 31, a = e >> 5;   // b along u (fastest in the source)
+      const int uu = u0 + b, ww = w0 + a;
+      T[a][b] = (uu < t.du && ww < t.dw) ? src[sb + uu * t.su + ww * t.sw] : 0.0;
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 1024; e += 256) {
+      const int a = e & 31, b = e >> 5;   // a along w (fastest in the target)
+      const int uu = u0 + b, ww = w0 + a;
+      if (uu < t.du && ww < t.dw) out[ob + uu * t.ou + ww * t.ow] += t.coef * T[a][b];
+    }
+  }
+}
+
 void launch_scatter(const ScatterDesc& d0, const double* src, double* out, hipStream_t st) {
   if (d0.n <= 0) return;
+  // the fastest dimension of the source and of the target
+  int u = 0, w = 0;
+  for (int k = 1; k < d0.rank; ++k) {
+    if (std::llabs(d0.ss[k]) < std::llabs(d0.ss[u])) u = k;
+    if (std::llabs(d0.so[k]) < std::llabs(d0.so[w])) w = k;
+  }
+  if (u != w && d0.d[u] >= 8 && d0.d[w] >= 8 && d0.ss[u] == 1 && d0.so[w] == 1) {
+    ScatterTile t;
+    for (int k = 0; k < d0.rank; ++k) {
+      if (k == u || k == w) continue;
+      t.rd[t.nr] = d0.d[k];
+      t.rs[t.nr] = d0.ss[k];
+      t.ro[t.nr] = d0.so[k];
+      t.rest *= d0.d[k];
+      ++t.nr;
+    }
+    t.du = d0.d[u]; t.su = d0.ss[u]; t.ou = d0.so[u];
+    t.dw = d0.d[w]; t.sw = d0.ss[w]; t.ow = d0.so[w];
+    t.coef = d0.coef;
+    const long long work = t.rest * ((t.du + 31) / 32) * ((t.dw + 31) / 32);
+    const unsigned grid = (unsigned)std::min<long long>(work, 1LL << 20);
+    hipLaunchKernelGGL(scatter_tiled_kernel, dim3(grid), dim3(256), 0, st, t, src, out);
+    return;
+  }
   ScatterDesc d = d0;
   div_magic(d.d, d.rank, d.dm);
   long long blocks = (d.n + 255) / 256;
