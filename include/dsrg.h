@@ -203,9 +203,11 @@ int dsrg_pt3_energy(const dsrg_problem* prob, const dsrg_options* opt, dsrg_resu
    after opt->stream, each with a plan of its own slot (item k uses slot k % K), so the
    items of a round overlap on the GPU; K is half of GPU_MAX_HW_QUEUES (4 unless set, so 2),
    at most 4.  The call returns when all have finished.  Items of a round whose slot has
-   no cached plan (a shape not seen before) run their whole pipeline directly, each on a
-   host worker thread of its own and on its round's stream, and record that plan; so a
-   round of uneven geometries overlaps on the GPU as well.
+   no cached plan (a shape not seen before) run their whole pipeline directly and record
+   that plan: items whose first-order doubles hold at most 2^22 elements per spin block
+   ((n_core + n_active)^2 (n_active + n_virtual)^2) each on a host worker thread of its own
+   and on its round's stream, so small uneven geometries overlap on the GPU too; larger
+   ones one after another on the calling thread (each fills the GPU alone).
    outs[k] and status[k] receive item k's result and return code; an item that fails (bad
    arguments, non-finite input) is skipped and leaves outs[k] untouched.  Returns DSRG_OK if
    at least one item succeeded, else the first item's code (DSRG_E_ARG for n < 1 or null

@@ -3631,7 +3631,8 @@ int dsrg_pt3_energy_batch(const dsrg_problem* probs, int32_t n, const dsrg_optio
   // (ordered after the caller's stream) with a plan of its own slot, so the members of a
   // round overlap on the GPU.  Each member's s, energies and non-finite count go through its
   // own pinned slot.  Members without a cached plan (a shape not seen before) run their
-  // pipeline directly on worker threads, one per stream of the round, and record a plan.
+  // pipeline directly and record a plan: small ones on worker threads, one per stream of
+  // the round, large ones alone on the calling thread.
   int dev = 0;
   hipStream_t caller = (opt && opt->stream) ? (hipStream_t)opt->stream : (hipStream_t)0;
   hipStream_t* ss = nullptr;
@@ -3699,7 +3700,15 @@ int dsrg_pt3_energy_batch(const dsrg_problem* probs, int32_t n, const dsrg_optio
         used[k] = plan;
         return DSRG_OK;
       });
-      if (status[k] == DSRG_OK && direct) {
+      // a member too large to gain from sharing the GPU (its first-order doubles above 2^22
+      // elements: two such members at once took longer than one after the other) runs
+      // alone on this thread; smaller ones overlap on worker threads
+      const long long nPm = (long long)probs[k].n_active + probs[k].n_virtual;
+      const long long nHm = (long long)probs[k].n_core + probs[k].n_active;
+      if (status[k] == DSRG_OK && direct && nPm * nPm * nHm * nHm > (1LL << 22)) {
+        status[k] = dsrg::guarded([&] { return dsrg::run(probs + k, &oj[k], outs + k, nullptr, true, nullptr, nullptr, j); });
+        if (status[k] != DSRG_OK) werr[k] = dsrg::g_last_error;
+      } else if (status[k] == DSRG_OK && direct) {
         workers.emplace_back([&, k, j] {
           if (hipSetDevice(dev) != hipSuccess) {
             status[k] = DSRG_E_HIP;
