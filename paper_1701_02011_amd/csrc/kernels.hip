@@ -447,7 +447,24 @@ __device__ __forceinline__ int xcd_tile_windowed(int b, int total) {
   return base + (o % kXcds) * c + o / kXcds;
 }
 
-// Logical tile L of a (gx, gy, gz) grid, consecutive L walking m tiles first.
+// Tile (tm, tn) of logical index Lp among the gx x gy tiles of one k split: groups of
+// kGroupM m tiles, each group walked m fastest and then n.  Consecutive indices go to one
+// XCD (xcd_tile), so the workgroups resident on an XCD at one time cover a block of about
+// kGroupM m tiles by (resident / kGroupM) n tiles and share both operands' panels in its L2,
+// instead of one column of m tiles that shares only the B panel.
+constexpr int kGroupM = 8;
+__device__ __forceinline__ void grouped_tile(int Lp, int gx, int gy, int& tm, int& tn) {
+  const int per = kGroupM * gy;
+  const int gid = Lp / per;
+  const int first = gid * kGroupM;
+  const int gsz = min(gx - first, kGroupM);
+  const int r = Lp - gid * per;
+  tm = first + r % gsz;
+  tn = r / gsz;
+}
+
+// Logical tile L of a (gx, gy, gz) grid (grouped m tiles, see grouped_tile; plain m-first
+// order with the triangle skip).
 template <int WM, int WN, int kP>
 __device__ __forceinline__ void gett_grid_tile(const GettDesc& g, const double* __restrict__ A,
                                                const double* __restrict__ B, double* __restrict__ C,
@@ -458,8 +475,16 @@ __device__ __forceinline__ void gett_grid_tile(const GettDesc& g, const double* 
   // with the triangle skip the live tiles crowd into the last columns: runs of 8 tiles
   // spread over the XCDs keep their loads even
   const int L = g.tri > 0 ? xcd_tile_windowed(b, total) : xcd_tile(b, total);
-  const int tm = L % gx, rest = L / gx;
-  const int tn = rest % gy, kz = rest / gy;
+  int tm, tn, kz;
+  if (g.tri > 0) {
+    tm = L % gx;
+    const int rest = L / gx;
+    tn = rest % gy;
+    kz = rest / gy;
+  } else {
+    kz = L / (gx * gy);
+    grouped_tile(L - kz * gx * gy, gx, gy, tm, tn);
+  }
   if (g.tri > 0 && (tn * (32 * WN) + 32 * WN - 1) / g.tri < (tm * (32 * WM)) / g.tri) return;
   gett_tile<WM, WN, 2, kP>(g, A, B, C, tm * (32 * WM), tn * (32 * WN), kz, lds);
 }

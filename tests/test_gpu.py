@@ -35,7 +35,7 @@ def _close(x, ref, rel=1e-10):
 # ---------------------------------------------------------------------------
 # contraction kernel
 # ---------------------------------------------------------------------------
-GETT_CASES = ["gemm", "ragged", "strided", "multi", "vec", "accum", "splitk", "longk", "packk"]
+GETT_CASES = ["gemm", "ragged", "strided", "multi", "vec", "accum", "splitk", "longk", "packk", "nt", "nt_tail"]
 
 
 @pytest.mark.parametrize("precision", [0, 1, 2])
@@ -102,6 +102,14 @@ def test_gett_kernel(case, precision):
                    k=[(f, e * u, N * u), (e, u, f * N * u), (u, 1, 1)], alpha=0.5, beta=1)
         ref = C + 0.5 * np.einsum("mfeu,efnu->mn", A, B)
         K = f * e * u
+    elif case in ("nt", "nt_tail"):
+        # both operands contiguous along k and enough output tiles for 128 x 128 tiles
+        # (ragged in m, n and k; accumulate)
+        M, N, K = (2100, 2177, 50) if case == "nt" else (2049, 2050, 18)
+        A = rng.standard_normal((M, K)); Bt = rng.standard_normal((N, K)); C = rng.standard_normal((M, N))
+        B = Bt
+        out = gett(A, Bt, C, m=[(M, K, N)], n=[(N, K, 1)], k=[(K, 1, 1)], alpha=0.5, beta=1)
+        ref = C + 0.5 * (A @ Bt.T)
     else:
         M, N, K = 65, 130, 17
         A = rng.standard_normal((M, K)); B = rng.standard_normal((K, N)); C = rng.standard_normal((M, N))
