@@ -149,7 +149,4 @@ def test_surrogate_gain_on_large_workload():
                abs_dE3=abs(sur["e3"] - exact["e3"]), rel_dE3=abs(sur["e3"] - exact["e3"]) / abs(exact["e3"]),
                n_exact_pairs=sur["n_exact_pairs"], e2_equal=sur["e2"] == exact["e2"])
     say("surrogate gain", json.dumps(out))
-    os.makedirs("gpurun_out", exist_ok=True)
-    with open("gpurun_out/surrogate_gain_large.json", "w") as f:
-        json.dump(out, f)
     assert np.isfinite(sur["e3"]) and abs(sur["e2"] - exact["e2"]) <= 1e-10 * abs(exact["e2"])
