@@ -194,12 +194,18 @@ __device__ __forceinline__ void gett_tile(const GettDesc& g, const double* __res
   const long long s_hi = min(g.steps, s_lo + g.kchunk);
   const bool akf = g.a_kfast, bkf = g.b_kfast;
 
-  // load slots: slot i of this thread covers (row, k) of the A tile and (k, col) of B;
-  // with k fastest the k of every slot is the same, else the row (column) is
-  auto a_k = [&](int i) { return akf ? (tid & (BK - 1)) : tid / BM + (256 / BM) * i; };
-  auto a_m = [&](int i) { return akf ? (tid / BK) + (256 / BK) * i : (tid & (BM - 1)); };
-  auto b_k = [&](int i) { return bkf ? (tid & (BK - 1)) : tid / BN + (256 / BN) * i; };
-  auto b_n = [&](int i) { return bkf ? (tid / BK) + (256 / BK) * i : (tid & (BN - 1)); };
+  // load slots: slot i of this thread covers (row, k) = (ma0 + i mad, ka0 + i kad) of the A
+  // tile and (k, col) of B likewise; with k fastest the k of every slot is the same
+  // (kad = 0), else the row (column) is (mad = 0).  The per-slot values are one register
+  // plus a uniform step, so the bounds tests and LDS addresses need no register per slot.
+  const int ka0 = akf ? (tid & (BK - 1)) : tid / BM, kad = akf ? 0 : 256 / BM;
+  const int ma0 = akf ? tid / BK : (tid & (BM - 1)), mad = akf ? 256 / BK : 0;
+  const int kb0 = bkf ? (tid & (BK - 1)) : tid / BN, kbd = bkf ? 0 : 256 / BN;
+  const int nb0 = bkf ? tid / BK : (tid & (BN - 1)), nbd = bkf ? 256 / BK : 0;
+  auto a_k = [&](int i) { return ka0 + kad * i; };
+  auto a_m = [&](int i) { return ma0 + mad * i; };
+  auto b_k = [&](int i) { return kb0 + kbd * i; };
+  auto b_n = [&](int i) { return nb0 + nbd * i; };
   // k slot j of a step: value j of the inner component (plain steps), or value j % kin of
   // the inner and j / kin of the walked component (packed steps).  Each slot keeps a 4-bit
   // code v (j; or j / kin, 15 past the packed ranges) and is real in a step while v < L
@@ -228,11 +234,11 @@ __device__ __forceinline__ void gett_tile(const GettDesc& g, const double* __res
   // the code is the slot itself
   auto real_a = [&](int i, int L) -> bool {
     if constexpr (kPackK) return (int)((acode >> (4 * i)) & 15u) < L;
-    else return a_k(i) < L;
+    else return ka0 < L - kad * i;
   };
   auto real_b = [&](int i, int L) -> bool {
     if constexpr (kPackK) return (int)((bcode >> (4 * i)) & 15u) < L;
-    else return b_k(i) < L;
+    else return kb0 < L - kbd * i;
   };
 
   // uniform k state: inner step c, outer counters and the outer base offsets
@@ -294,18 +300,16 @@ __device__ __forceinline__ void gett_tile(const GettDesc& g, const double* __res
       rb[i] = B[bb + (ok ? boff[i] : 0)];
     }
   };
+  // rows (columns) past M (N) hold a real element of the operand (offset 0): they only
+  // reach output rows (columns) that are never written, so only the k range is masked
+  const int a_l0 = ka0 * LDA + ma0, a_ld = kad * LDA + mad;
+  const int b_l0 = kb0 * LDB + nb0, b_ld = kbd * LDB + nbd;
   auto stash = [&](int buf) {
     const int L = real_slots();
 #pragma unroll
-    for (int i = 0; i < NA; ++i) {
-      const bool ok = real_a(i, L) && tile_m + a_m(i) < g.M;
-      As[buf][a_k(i) * LDA + a_m(i)] = ok ? (T)ra[i] : (T)0;
-    }
+    for (int i = 0; i < NA; ++i) As[buf][a_l0 + a_ld * i] = real_a(i, L) ? (T)ra[i] : (T)0;
 #pragma unroll
-    for (int i = 0; i < NB; ++i) {
-      const bool ok = real_b(i, L) && tile_n + b_n(i) < g.N;
-      Bs[buf][b_k(i) * LDB + b_n(i)] = ok ? (T)rb[i] : (T)0;
-    }
+    for (int i = 0; i < NB; ++i) Bs[buf][b_l0 + b_ld * i] = real_b(i, L) ? (T)rb[i] : (T)0;
   };
 
   typename MF::Acc acc[WM][WN];
@@ -363,12 +367,8 @@ __device__ __forceinline__ void gett_tile(const GettDesc& g, const double* __res
   __syncthreads();
   bool first = true;
   int since = 0;
-  for (long long s = s_lo; s < s_hi; ++s) {
-    const bool more = s + 1 < s_hi;
-    if (more) {
-      advance();
-      fetch();
-    }
+  // the MFMAs of one step on LDS buffer buf
+  auto compute = [&]() {
     if constexpr (kP == 2) {
       // one 16-deep BF16 block per step: lane (li, lk) splits k = 4 lk .. 4 lk + 3 of its
       // row (column) into hi and lo parts
@@ -410,7 +410,15 @@ __device__ __forceinline__ void gett_tile(const GettDesc& g, const double* __res
           for (int b = 0; b < WN; ++b) acc[a][b] = MF::fma(av[a], bv[b], acc[a][b]);
       }
     }
-    if (kP != 0 && more && ++since == kF32FlushSteps) {
+  };
+  // every step but the last loads the next one (the last is peeled off, so the loop's
+  // loads are always waited for inside the loop)
+  long long s = s_lo;
+  for (; s + 1 < s_hi; ++s) {
+    advance();
+    fetch();
+    compute();
+    if (kP != 0 && ++since == kF32FlushSteps) {
       flush(first);
       first = false;
       since = 0;
@@ -419,9 +427,13 @@ __device__ __forceinline__ void gett_tile(const GettDesc& g, const double* __res
 #pragma unroll
         for (int b = 0; b < WN; ++b) acc[a][b] = MF::zero();
     }
-    if (more) stash(buf ^ 1);
+    stash(buf ^ 1);
     __syncthreads();
     buf ^= 1;
+  }
+  if (s < s_hi) {
+    compute();
+    __syncthreads();
   }
   flush(first);
 }
@@ -685,8 +697,13 @@ bool gett_big_tiles(const GettDesc& g) { return big_tiles(g); }
 // most nearly whole rounds (256 CUs; two 128 x 128 or four 64 x 64 workgroups per CU fit
 // the registers), keeping at least 16 k steps per chunk (4 when the output has at most
 // 2^20 elements: there a few tiles with long k ranges would wait on load latency, and the
-// partial tiles stay small) and the partial tiles within ws_elems.  A larger split must
-// gain at least 5 % of utilisation.
+// partial tiles stay small) and the partial tiles within ws_elems.
+//  - 64 x 64 tiles: a larger split must gain at least 5 % of utilisation.
+//  - 128 x 128 tiles: the split with the least modelled time, rounds x (k steps per chunk
+//    x 5.1 us + 8 us per tile) plus the partial tiles' HBM traffic (written and read
+//    once, 16 bytes per element at 4 TB/s); the step and tile costs are the measured ones
+//    of this kernel at two workgroups per CU.  Up to 64 chunks.  (Triangular launches,
+//    whose grid skips tiles, keep the 5 % rule.)
 int gett_splits(const GettDesc& g, long long ws_elems) {
   const bool big = big_tiles(g);
   const int bm = big ? 128 : 64, bn = bm;
@@ -695,6 +712,24 @@ int gett_splits(const GettDesc& g, long long ws_elems) {
   const long long mn = std::max<long long>(1, (long long)g.M * g.N);
   const long long min_chunk = mn <= (1LL << 20) ? 4 : 16;
   const long long smax = std::min<long long>({g.steps / min_chunk, ws_elems / mn, 4096});
+  if (big && g.tri <= 0) {
+    auto model = [&](long long s) {
+      const long long chunk = (g.steps + s - 1) / s;
+      const long long w = tiles * ((g.steps + chunk - 1) / chunk);
+      const double rounds = (double)((w + slots - 1) / slots);
+      return rounds * ((double)chunk * 5.1e-6 + 8e-6) + (s > 1 ? (double)s * mn * 16.0 / 4e12 : 0.0);
+    };
+    long long best = 1;
+    double tb = model(1);
+    for (long long s = 2; s <= std::min<long long>(smax, 64); ++s) {
+      const double t = model(s);
+      if (t < tb) {
+        best = s;
+        tb = t;
+      }
+    }
+    return (int)best;
+  }
   auto util = [&](long long s) {
     const long long w = tiles * s;
     return (double)w / (double)(slots * ((w + slots - 1) / slots));
