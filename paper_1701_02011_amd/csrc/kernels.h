@@ -8,6 +8,7 @@ namespace dsrg {
 
 constexpr int kMaxComp = 6;   // index components per group (M, N or K)
 constexpr int kGettBK = 16;   // k step of the contraction kernel (split-K chunks are multiples)
+constexpr int kGettBigBK = 32;   // k step of the FP32 / BF16 x3 plain launches with 128 x 128 tiles
 
 // A strided tensor contraction C[m][n] (+)= alpha * sum_k A[m][k] B[k][n], where m, n and
 // k are multi-indices (row-major composition of up to kMaxComp components) and every

@@ -89,16 +89,17 @@ constexpr int BK = kGettBK;
 
 // Tile of WGM x (4 / WGM) waves, each wave WM x WN MFMA blocks of 16 x 16; T is the
 // element type staged in LDS (double, or float for the FP32-product precision).
-template <int WM, int WN, int WGM, class T = double>
+template <int WM, int WN, int WGM, class T = double, int kBK = BK>
 struct TileLds {
   static constexpr int BM = 16 * WM * WGM, BN = 16 * WN * (4 / WGM);
   // row pitch: 16 lanes of a 64-bit access (one bank pass) with k = 0..15 and one m land on
   // distinct banks when 2 pitch = 2 (mod 32 banks), i.e. an odd pitch of doubles; 32 lanes
-  // of a 32-bit access with k = 0..15 and two m need a pitch of 2 (mod 32) floats
+  // of a 32-bit access with k = 0..15 and two m need a pitch of 2 (mod 32) floats (with 32
+  // k values per step the slots still put k = 0..15 of two rows on 32 lanes)
   static constexpr int PAD = sizeof(T) == 8 ? 1 : 2;
   static constexpr int LDA = BM + PAD, LDB = BN + PAD;
-  T As[2][BK * LDA];
-  T Bs[2][BK * LDB];
+  T As[2][kBK * LDA];
+  T Bs[2][kBK * LDB];
 };
 
 // MFMA blocks of the three precisions (kP = DSRG_PRECISION_*).  FP64 (0):
@@ -162,17 +163,22 @@ constexpr int kF32FlushSteps = 64;
 // One BM x BN output tile at (tile_m, tile_n) for chunk kz of the k steps of g.  kPackK:
 // the tile supports packed k steps (g.kpack > 1); the 128 x 128 tiles leave it out (their
 // launches are prepared without it) to keep their registers.
-template <int WM, int WN, int WGM = 2, int kP = 0, bool kPackK = (WM * WN < 16)>
+template <int WM, int WN, int WGM = 2, int kP = 0, bool kPackK = (WM * WN < 16), int kBK = BK>
 __device__ __forceinline__ void gett_tile(const GettDesc& g, const double* __restrict__ A,
                                           const double* __restrict__ B, double* __restrict__ C,
                                           int tile_m, int tile_n, int kz,
-                                          TileLds<WM, WN, WGM, typename Mfma<kP>::T>& lds) {
+                                          TileLds<WM, WN, WGM, typename Mfma<kP>::T, kBK>& lds) {
   using MF = Mfma<kP>;
   using T = typename MF::T;
-  constexpr int BM = TileLds<WM, WN, WGM, T>::BM, BN = TileLds<WM, WN, WGM, T>::BN;
+  using Lds = TileLds<WM, WN, WGM, T, kBK>;
+  constexpr int BK = kBK;   // k values per step of this tile
+  constexpr int BM = Lds::BM, BN = Lds::BN;
   static_assert(BM * BK % 256 == 0 && BN * BK % 256 == 0 && 256 % BM == 0 || BM >= 256, "tile");
-  constexpr int LDA = TileLds<WM, WN, WGM, T>::LDA, LDB = TileLds<WM, WN, WGM, T>::LDB;
+  static_assert(!kPackK || BK == kGettBK, "packed steps are prepared for the default step");
+  constexpr int LDA = Lds::LDA, LDB = Lds::LDB;
   constexpr int NA = BM * BK / 256, NB = BN * BK / 256;   // loads per thread per step
+  // FP32 sums run over at most kF32FlushSteps default steps (1024 k values)
+  constexpr int kFlushSteps = kF32FlushSteps * kGettBK / BK;
   auto& As = lds.As;
   auto& Bs = lds.Bs;
   const int tid = threadIdx.x;
@@ -194,51 +200,67 @@ __device__ __forceinline__ void gett_tile(const GettDesc& g, const double* __res
   const long long s_hi = min(g.steps, s_lo + g.kchunk);
   const bool akf = g.a_kfast, bkf = g.b_kfast;
 
-  // load slots: slot i of this thread covers (row, k) = (ma0 + i mad, ka0 + i kad) of the A
-  // tile and (k, col) of B likewise; with k fastest the k of every slot is the same
-  // (kad = 0), else the row (column) is (mad = 0).  The per-slot values are one register
-  // plus a uniform step, so the bounds tests and LDS addresses need no register per slot.
-  const int ka0 = akf ? (tid & (BK - 1)) : tid / BM, kad = akf ? 0 : 256 / BM;
-  const int ma0 = akf ? tid / BK : (tid & (BM - 1)), mad = akf ? 256 / BK : 0;
-  const int kb0 = bkf ? (tid & (BK - 1)) : tid / BN, kbd = bkf ? 0 : 256 / BN;
-  const int nb0 = bkf ? tid / BK : (tid & (BN - 1)), nbd = bkf ? 256 / BK : 0;
-  auto a_k = [&](int i) { return ka0 + kad * i; };
-  auto a_m = [&](int i) { return ma0 + mad * i; };
-  auto b_k = [&](int i) { return kb0 + kbd * i; };
-  auto b_n = [&](int i) { return nb0 + nbd * i; };
+  // load slots: slot i of this thread covers (row, k) of the A tile and (k, col) of B.  With
+  // k fastest, 16 lanes cover k = 0..15 of a row, slot i in row ma0 + 16 (i / kPair) at
+  // k = ka0 + 16 (i % kPair) (kPair = BK / 16 slots per row); else every slot has the row
+  // ma0 and k = ka0 + i kad.  The per-slot values are one register plus uniform steps, so
+  // the bounds tests and LDS addresses need no register per slot, and the operand offsets
+  // one per row (kPair slots share it).
+  constexpr int kPair = BK / kGettBK;
+  static_assert(kPair * kGettBK == BK && 256 / kGettBK * kGettBK == 256, "slot rows");
+  const int ka0 = akf ? (tid & (kGettBK - 1)) : tid / BM, kad = akf ? 0 : 256 / BM;
+  const int ma0 = akf ? tid / kGettBK : (tid & (BM - 1));
+  const int kb0 = bkf ? (tid & (kGettBK - 1)) : tid / BN, kbd = bkf ? 0 : 256 / BN;
+  const int nb0 = bkf ? tid / kGettBK : (tid & (BN - 1));
+  auto a_dk = [&](int i) { return akf ? kGettBK * (i % kPair) : kad * i; };
+  auto b_dk = [&](int i) { return bkf ? kGettBK * (i % kPair) : kbd * i; };
+  auto a_k = [&](int i) { return ka0 + a_dk(i); };
+  auto a_m = [&](int i) { return ma0 + (akf ? 256 / kGettBK * (i / kPair) : 0); };
+  auto b_k = [&](int i) { return kb0 + b_dk(i); };
+  auto b_n = [&](int i) { return nb0 + (bkf ? 256 / kGettBK * (i / kPair) : 0); };
   // k slot j of a step: value j of the inner component (plain steps), or value j % kin of
   // the inner and j / kin of the walked component (packed steps).  Each slot keeps a 4-bit
   // code v (j; or j / kin, 15 past the packed ranges) and is real in a step while v < L
   // with L = kin - c BK (plain) or min(8, kd[kw] - c kpack) (packed), so no per-slot
   // limits stay in registers.
-  static_assert(NA <= 8 && NB <= 8, "slot codes");
+  static_assert(!kPackK || (NA <= 8 && NB <= 8), "slot codes");
   auto slot_off = [&](int j, long long s_in, long long s_w) -> long long {
     return kp > 1 ? (long long)(j % kin) * s_in + (long long)(j / kin) * s_w : (long long)j * s_in;
   };
   auto slot_code = [&](int j) -> unsigned { return kp > 1 ? (j < kp * kin ? (unsigned)(j / kin) : 15u) : (unsigned)j; };
-  long long aoff[NA], boff[NB];
+  // operand offset of the first slot of each row group of kPair slots (0 past M, N: such
+  // rows read a real element and reach only outputs that are never written); slot i adds
+  // (i % kPair) times the uniform a_pd (b_pd)
+  long long aoff[NA / kPair], boff[NB / kPair];
+  const long long a_pd = (long long)(akf ? kGettBK : kad) * a_in, b_pd = (long long)(bkf ? kGettBK : kbd) * b_in;
   unsigned acode = 0, bcode = 0;
 #pragma unroll
-  for (int i = 0; i < NA; ++i) {
+  for (int i = 0; i < NA; i += kPair) {
     const int m = tile_m + a_m(i);
-    aoff[i] = m < g.M ? decode_fast(m, g.nm, g.md, g.mmag, g.msh, g.am) + slot_off(a_k(i), a_in, a_st) : 0;
-    if constexpr (kPackK) acode |= slot_code(a_k(i)) << (4 * i);
+    aoff[i / kPair] = m < g.M ? decode_fast(m, g.nm, g.md, g.mmag, g.msh, g.am) + slot_off(a_k(i), a_in, a_st) : 0;
   }
 #pragma unroll
-  for (int i = 0; i < NB; ++i) {
+  for (int i = 0; i < NB; i += kPair) {
     const int n = tile_n + b_n(i);
-    boff[i] = n < g.N ? decode_fast(n, g.nn, g.nd, g.nmag, g.nsh, g.bn) + slot_off(b_k(i), b_in, b_st) : 0;
-    if constexpr (kPackK) bcode |= slot_code(b_k(i)) << (4 * i);
+    boff[i / kPair] = n < g.N ? decode_fast(n, g.nn, g.nd, g.nmag, g.nsh, g.bn) + slot_off(b_k(i), b_in, b_st) : 0;
   }
+  if constexpr (kPackK) {
+#pragma unroll
+    for (int i = 0; i < NA; ++i) acode |= slot_code(a_k(i)) << (4 * i);
+#pragma unroll
+    for (int i = 0; i < NB; ++i) bcode |= slot_code(b_k(i)) << (4 * i);
+  }
+  auto a_off = [&](int i) -> long long { return aoff[i / kPair] + (i % kPair ? a_pd : 0); };
+  auto b_off = [&](int i) -> long long { return boff[i / kPair] + (i % kPair ? b_pd : 0); };
   // slot i of A (B) is real in the current step (L = real_slots()); without packed steps
   // the code is the slot itself
   auto real_a = [&](int i, int L) -> bool {
     if constexpr (kPackK) return (int)((acode >> (4 * i)) & 15u) < L;
-    else return ka0 < L - kad * i;
+    else return ka0 < L - a_dk(i);
   };
   auto real_b = [&](int i, int L) -> bool {
     if constexpr (kPackK) return (int)((bcode >> (4 * i)) & 15u) < L;
-    else return kb0 < L - kbd * i;
+    else return kb0 < L - b_dk(i);
   };
 
   // uniform k state: inner step c, outer counters and the outer base offsets
@@ -292,24 +314,25 @@ __device__ __forceinline__ void gett_tile(const GettDesc& g, const double* __res
 #pragma unroll
     for (int i = 0; i < NA; ++i) {
       const bool ok = real_a(i, L);
-      ra[i] = A[ab + (ok ? aoff[i] : 0)];
+      ra[i] = A[ab + (ok ? a_off(i) : 0)];
     }
 #pragma unroll
     for (int i = 0; i < NB; ++i) {
       const bool ok = real_b(i, L);
-      rb[i] = B[bb + (ok ? boff[i] : 0)];
+      rb[i] = B[bb + (ok ? b_off(i) : 0)];
     }
   };
   // rows (columns) past M (N) hold a real element of the operand (offset 0): they only
   // reach output rows (columns) that are never written, so only the k range is masked
-  const int a_l0 = ka0 * LDA + ma0, a_ld = kad * LDA + mad;
-  const int b_l0 = kb0 * LDB + nb0, b_ld = kbd * LDB + nbd;
+  const int a_l0 = ka0 * LDA + ma0, b_l0 = kb0 * LDB + nb0;
   auto stash = [&](int buf) {
     const int L = real_slots();
 #pragma unroll
-    for (int i = 0; i < NA; ++i) As[buf][a_l0 + a_ld * i] = real_a(i, L) ? (T)ra[i] : (T)0;
+    for (int i = 0; i < NA; ++i)
+      As[buf][a_l0 + a_dk(i) * LDA + (a_m(i) - ma0)] = real_a(i, L) ? (T)ra[i] : (T)0;
 #pragma unroll
-    for (int i = 0; i < NB; ++i) Bs[buf][b_l0 + b_ld * i] = real_b(i, L) ? (T)rb[i] : (T)0;
+    for (int i = 0; i < NB; ++i)
+      Bs[buf][b_l0 + b_dk(i) * LDB + (b_n(i) - nb0)] = real_b(i, L) ? (T)rb[i] : (T)0;
   };
 
   typename MF::Acc acc[WM][WN];
@@ -370,32 +393,35 @@ __device__ __forceinline__ void gett_tile(const GettDesc& g, const double* __res
   // the MFMAs of one step on LDS buffer buf
   auto compute = [&]() {
     if constexpr (kP == 2) {
-      // one 16-deep BF16 block per step: lane (li, lk) splits k = 4 lk .. 4 lk + 3 of its
+      // 16-deep BF16 blocks: in block h lane (li, lk) splits k = 16 h + 4 lk .. + 3 of its
       // row (column) into hi and lo parts
-      static_assert(BK == 16, "one BF16 block per step");
-      short4_t ah[WM], al[WM], bh[WN], bl[WN];
+      static_assert(BK % 16 == 0, "whole BF16 blocks per step");
 #pragma unroll
-      for (int t = 0; t < WM; ++t)
+      for (int h16 = 0; h16 < BK; h16 += 16) {
+        short4_t ah[WM], al[WM], bh[WN], bl[WN];
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          short h, l;
-          MF::split(As[buf][(4 * lk + j) * LDA + wm + t * 16 + li], h, l);
-          ah[t][j] = h;
-          al[t][j] = l;
-        }
+        for (int t = 0; t < WM; ++t)
 #pragma unroll
-      for (int t = 0; t < WN; ++t)
+          for (int j = 0; j < 4; ++j) {
+            short h, l;
+            MF::split(As[buf][(h16 + 4 * lk + j) * LDA + wm + t * 16 + li], h, l);
+            ah[t][j] = h;
+            al[t][j] = l;
+          }
 #pragma unroll
-        for (int j = 0; j < 4; ++j) {
-          short h, l;
-          MF::split(Bs[buf][(4 * lk + j) * LDB + wn + t * 16 + li], h, l);
-          bh[t][j] = h;
-          bl[t][j] = l;
-        }
+        for (int t = 0; t < WN; ++t)
 #pragma unroll
-      for (int a = 0; a < WM; ++a)
+          for (int j = 0; j < 4; ++j) {
+            short h, l;
+            MF::split(Bs[buf][(h16 + 4 * lk + j) * LDB + wn + t * 16 + li], h, l);
+            bh[t][j] = h;
+            bl[t][j] = l;
+          }
 #pragma unroll
-        for (int b = 0; b < WN; ++b) acc[a][b] = MF::fma3(ah[a], al[a], bh[b], bl[b], acc[a][b]);
+        for (int a = 0; a < WM; ++a)
+#pragma unroll
+          for (int b = 0; b < WN; ++b) acc[a][b] = MF::fma3(ah[a], al[a], bh[b], bl[b], acc[a][b]);
+      }
     } else {
 #pragma unroll
       for (int kk = 0; kk < BK; kk += 4) {
@@ -418,7 +444,7 @@ __device__ __forceinline__ void gett_tile(const GettDesc& g, const double* __res
     advance();
     fetch();
     compute();
-    if (kP != 0 && ++since == kF32FlushSteps) {
+    if (kP != 0 && ++since == kFlushSteps) {
       flush(first);
       first = false;
       since = 0;
@@ -477,10 +503,10 @@ __device__ __forceinline__ void grouped_tile(int Lp, int gx, int gy, int& tm, in
 
 // Logical tile L of a (gx, gy, gz) grid (grouped m tiles, see grouped_tile; plain m-first
 // order with the triangle skip).
-template <int WM, int WN, int kP>
+template <int WM, int WN, int kP, int kBK>
 __device__ __forceinline__ void gett_grid_tile(const GettDesc& g, const double* __restrict__ A,
                                                const double* __restrict__ B, double* __restrict__ C,
-                                               TileLds<WM, WN, 2, typename Mfma<kP>::T>& lds) {
+                                               TileLds<WM, WN, 2, typename Mfma<kP>::T, kBK>& lds) {
   const int gx = gridDim.x, gy = gridDim.y;
   const int total = gx * gy * gridDim.z;
   const int b = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
@@ -498,33 +524,41 @@ __device__ __forceinline__ void gett_grid_tile(const GettDesc& g, const double* 
     grouped_tile(L - kz * gx * gy, gx, gy, tm, tn);
   }
   if (g.tri > 0 && (tn * (32 * WN) + 32 * WN - 1) / g.tri < (tm * (32 * WM)) / g.tri) return;
-  gett_tile<WM, WN, 2, kP>(g, A, B, C, tm * (32 * WM), tn * (32 * WN), kz, lds);
+  gett_tile<WM, WN, 2, kP, (WM * WN < 16), kBK>(g, A, B, C, tm * (32 * WM), tn * (32 * WN), kz, lds);
 }
+
+// k values per step of the plain launches: FP32 and BF16 x3 products on 128 x 128 tiles
+// walk 32 (the FP32 LDS tiles of two steps fit where one FP64 step does, and each barrier
+// and LDS write pass then feeds twice the MFMAs), everything else kGettBK
+template <int kP, int WM, int WN>
+constexpr int plain_bk() { return kP != 0 && WM * WN == 16 ? kGettBigBK : kGettBK; }
 
 template <int kRole, int WM, int WN>
 __global__ __launch_bounds__(256) void gett_f64_kernel(GettDesc g, const double* __restrict__ A,
                                                        const double* __restrict__ B,
                                                        double* __restrict__ C) {
-  __shared__ TileLds<WM, WN, 2, double> lds;
-  gett_grid_tile<WM, WN, 0>(g, A, B, C, lds);
+  __shared__ TileLds<WM, WN, 2, double, plain_bk<0, WM, WN>()> lds;
+  gett_grid_tile<WM, WN, 0, plain_bk<0, WM, WN>()>(g, A, B, C, lds);
 }
 
-// FP64 operands and output, FP32 products (DSRG_PRECISION_FP32)
+// FP64 operands and output, FP32 products (DSRG_PRECISION_FP32); two workgroups per CU
+// (the 32-deep steps of the 128 x 128 tiles would otherwise take every register)
 template <int kRole, int WM, int WN>
-__global__ __launch_bounds__(256) void gett_f32_kernel(GettDesc g, const double* __restrict__ A,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void gett_f32_kernel(GettDesc g, const double* __restrict__ A,
                                                        const double* __restrict__ B,
                                                        double* __restrict__ C) {
-  __shared__ TileLds<WM, WN, 2, float> lds;
-  gett_grid_tile<WM, WN, 1>(g, A, B, C, lds);
+  __shared__ TileLds<WM, WN, 2, float, plain_bk<1, WM, WN>()> lds;
+  gett_grid_tile<WM, WN, 1, plain_bk<1, WM, WN>()>(g, A, B, C, lds);
 }
 
-// FP64 operands and output, split-BF16 x3 products (DSRG_PRECISION_BF16X3)
+// FP64 operands and output, split-BF16 x3 products (DSRG_PRECISION_BF16X3); two
+// workgroups per CU as for FP32 products
 template <int kRole, int WM, int WN>
-__global__ __launch_bounds__(256) void gett_b3_kernel(GettDesc g, const double* __restrict__ A,
+__global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void gett_b3_kernel(GettDesc g, const double* __restrict__ A,
                                                       const double* __restrict__ B,
                                                       double* __restrict__ C) {
-  __shared__ TileLds<WM, WN, 2, float> lds;
-  gett_grid_tile<WM, WN, 2>(g, A, B, C, lds);
+  __shared__ TileLds<WM, WN, 2, float, plain_bk<2, WM, WN>()> lds;
+  gett_grid_tile<WM, WN, 2, plain_bk<2, WM, WN>()>(g, A, B, C, lds);
 }
 
 // C[m][n] = alpha * sum_z part[z][m][n] (+ C) in a fixed order of z
@@ -774,6 +808,13 @@ void launch_gett(const GettDesc& g0, const double* A, const double* B, double* C
   gett_magic(g);
   const bool big = big_tiles(g);
   if (big) gett_unpack_k(g);
+  if (big && prec != 0) {
+    // these kernels walk kGettBigBK k values per step
+    const int kin = g.kd[g.nk - 1];
+    g.ksteps = (kin + kGettBigBK - 1) / kGettBigBK;
+    g.steps = (long long)(g.K / kin) * g.ksteps;
+    g.kchunk = g.steps;
+  }
   const int bm = big ? 128 : 64, bn = bm;
   int ns = ws ? gett_splits(g, ws_elems) : 1;
   g.part = nullptr;
