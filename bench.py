@@ -268,7 +268,7 @@ def main():
                     for k in range(8) if kn[k]},
         "plan": [r["plan"] for r in res],
     }
-    if args.mixed_steps > 0 and not prec and args.workload != "curve":
+    if args.mixed_steps > 0 and not prec:
         # the FP32-product path beside the FP64 headline: rate, and its error against the
         # FP64 GPU energies and the stored oracle values
         mres, mdt = timed(1, 1, args.mixed_steps)
