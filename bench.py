@@ -22,6 +22,7 @@ sys.path.insert(0, ROOT)
 
 PEAK_FP64_TFLOPS = 78.6      # MI355X dense FP64 (matrix = vector)
 PEAK_FP32_TFLOPS = 157.3     # MI355X dense FP32 MFMA
+PEAK_BF16_TFLOPS = 2500.0    # MI355X dense BF16 MFMA
 PEAK_HBM_GBS = 8000.0        # MI355X HBM3E
 METRIC = "DSRG-MRPT3 energies/sec and MFMA TFLOP/s vs peak at |ΔE|≤1e-6 Eh"
 
@@ -73,17 +74,45 @@ def blas_threads():
 # kernel instance of each profile bucket (index 2 * role + 128x128-tile flag), FP64 names
 KERNELS = ["gett_f64_kernel<0, 2, 2>", "gett_f64_kernel<0, 4, 4>",
            "gett_f64_kernel<1, 2, 2>", "gett_f64_kernel<1, 4, 4>",
-           "gett_f64_kernel<2, 2, 2> / coulomb_group_kernel<false>", "gett_f64_kernel<2, 4, 4>",
-           "gett_group_kernel<false>", "gett_group_big_kernel<false>"]
+           "gett_f64_kernel<2, 2, 2> / coulomb_group_kernel<0>", "gett_f64_kernel<2, 4, 4>",
+           "gett_group_kernel<0>", "gett_group_big_kernel<0>"]
 ROLE_NOTES = ["table products, one launch each", "(PP|PP) ladder contractions",
               "Coulomb-block builds B.B", "grouped table products"]
 
 
-def kernel_name(k, f32):
+def kernel_name(k, prec):
+    """Kernel symbol of slot k of the library's per-kernel profile at precision prec
+    (0 FP64, 1 FP32 products, 2 split-BF16 x3 products)."""
     n = KERNELS[k]
-    if f32:
-        n = n.replace("f64", "f32").replace("<false>", "<true>")
+    if prec:
+        n = n.replace("gett_f64", "gett_f32" if prec == 1 else "gett_b3").replace("<0>", "<%d>" % prec)
     return n
+
+
+def dominant_kernel(prof, prec, step_s):
+    """The kernel instance with the most device time in a profiled pass: its algorithmic
+    rate (the library's 2 M N K flop count over the HIP-event time of its launches) against
+    the MFMA peak of the instruction it issues.  Split BF16 x3 issues three BF16 products
+    per product, so its executed rate is three times the algorithmic one."""
+    ksec = [sum(r["kernel_seconds"][k] for r in prof) for k in range(8)]
+    kfl = [sum(r["kernel_flops"][k] for r in prof) for k in range(8)]
+    kn = [sum(r["kernel_launches"][k] for r in prof) for k in range(8)]
+    dom = max(range(8), key=lambda k: ksec[k])
+    avg_s = ksec[dom] / max(1, kn[dom])
+    flops_per_launch = kfl[dom] / max(1, kn[dom])
+    achieved = flops_per_launch / avg_s / 1e12 if avg_s > 0 else 0.0
+    out = dict(kernel=kernel_name(dom, prec), note=ROLE_NOTES[dom // 2], alg_flops_per_launch=flops_per_launch,
+               avg_launch_us=1e6 * avg_s, launches_per_energy=kn[dom] / max(1, len(prof)),
+               share_of_step=ksec[dom] / len(prof) / step_s if step_s > 0 else None)
+    if prec == 2:
+        out.update(bound="mfma", achieved=3 * achieved, peak=PEAK_BF16_TFLOPS, unit="TFLOP/s",
+                   frac=3 * achieved / PEAK_BF16_TFLOPS, alg_tflops=achieved,
+                   instruction="v_mfma_f32_16x16x16bf16_1k, three per product")
+    else:
+        peak = PEAK_FP32_TFLOPS if prec else PEAK_FP64_TFLOPS
+        out.update(bound="mfma", achieved=achieved, peak=peak, unit="TFLOP/s", frac=achieved / peak,
+                   instruction="v_mfma_f32_16x16x4f32" if prec else "v_mfma_f64_16x16x4f64")
+    return out, (ksec, kfl, kn)
 
 
 def golden(workload, s):
@@ -174,8 +203,9 @@ def main():
     ap.add_argument("--workload", default="medium", choices=["tiny", "small", "medium", "large", "curve"])
     ap.add_argument("--geometries", type=int, default=4, help="curve workload: number of geometries")
     ap.add_argument("--no-cpu-baseline", action="store_true")
-    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32"],
-                    help="precision of the timed headline loop (fp32: FP32 products, FP64 sums)")
+    ap.add_argument("--precision", default="fp64", choices=["fp64", "fp32", "bf16x3"],
+                    help="precision of the timed headline loop (fp32: FP32 products, bf16x3: split "
+                         "BF16 x3 products; FP64 sums)")
     ap.add_argument("--mixed-steps", type=int, default=3,
                     help="timed steps of the FP32-product pass reported beside the headline")
     args = ap.parse_args()
@@ -218,7 +248,7 @@ def main():
         progress("timed %d step(s): %.3f s" % (steps, dt))
         return res, dt
 
-    prec = 1 if args.precision == "fp32" else 0
+    prec = {"fp64": 0, "fp32": 1, "bf16x3": 2}[args.precision]
     res, dt = timed(prec, args.warmup, args.steps)
     energies = args.steps * len(dev)
     ms_per_step = dt * 1e3 / args.steps
@@ -229,32 +259,20 @@ def main():
     prof = [_lib.dsrg_pt3_energy(d, profile=True, precision=prec) for d in dev]
     progress("profiled pass done")
     torch.cuda.synchronize()
-    ksec = [sum(r["kernel_seconds"][k] for r in prof) for k in range(8)]
-    kfl = [sum(r["kernel_flops"][k] for r in prof) for k in range(8)]
-    kn = [sum(r["kernel_launches"][k] for r in prof) for k in range(8)]
-    dom = max(range(8), key=lambda k: ksec[k])
-    peak = PEAK_FP32_TFLOPS if prec else PEAK_FP64_TFLOPS
-    avg_s = ksec[dom] / max(1, kn[dom])
-    flops_per_launch = kfl[dom] / max(1, kn[dom])
-    achieved = flops_per_launch / avg_s / 1e12 if avg_s > 0 else 0.0
-    name = kernel_name(dom, prec)
-    roofline = dict(bound="mfma", achieved=achieved, peak=peak, unit="TFLOP/s", frac=achieved / peak,
-                    traffic=measured_traffic(name, args.workload, args.precision),
-                    kernel=name, note=ROLE_NOTES[dom // 2],
-                    alg_flops_per_launch=flops_per_launch, avg_launch_us=1e6 * avg_s,
-                    launches_per_energy=kn[dom] / len(dev),
-                    share_of_step=ksec[dom] / (dt / args.steps) if dt > 0 else None)
+    roofline, (ksec, kfl, kn) = dominant_kernel(prof, prec, dt / args.steps / len(dev))
+    roofline["traffic"] = measured_traffic(roofline["kernel"], args.workload, args.precision)
+    peak = roofline["peak"]
     # whole-energy algorithmic rate: every contraction's 2 M N K over the step time
     alg_flops = sum(r["alg_flops"] for r in res)
     whole = dict(alg_tflop_per_energy=alg_flops / len(dev) / 1e12,
                  alg_tflops=alg_flops * args.steps / dt / 1e12,
-                 frac_of_peak=alg_flops * args.steps / dt / 1e12 / peak)
+                 frac_of_peak=alg_flops * args.steps / dt / 1e12 * (3 if prec == 2 else 1) / peak)
 
     out = {
         "metric": METRIC, "value": energies / dt, "unit": "energies/s", "n_gpus": 1,
         "steps": args.steps, "warmup": args.warmup, "ms_per_step": ms_per_step,
         "higher_is_better": True, "scaling": "weak", "vs_baseline": None,
-        "dtype": "f64" if not prec else "f64 (FP32 products)",
+        "dtype": ["f64", "f64 (FP32 products)", "f64 (split BF16 x3 products)"][prec],
         "data": "synthetic",
         "config": {"workload": args.workload,
                    "problems": [dict(n_core=p.n_core, n_active=p.n_active, n_virtual=p.n_virtual,
@@ -272,7 +290,9 @@ def main():
         # the FP32-product path beside the FP64 headline: rate, and its error against the
         # FP64 GPU energies and the stored oracle values
         mres, mdt = timed(1, 1, args.mixed_steps)
+        mprof = [_lib.dsrg_pt3_energy(d, profile=True, precision=1) for d in dev]
         mixed = dict(value=args.mixed_steps * len(dev) / mdt, unit="energies/s",
+                     roofline=dominant_kernel(mprof, 1, mdt / args.mixed_steps / len(dev))[0],
                      speedup_vs_fp64=(args.mixed_steps * len(dev) / mdt) / (energies / dt),
                      parity=parity_of(probs, mres, args.workload),
                      vs_fp64_gpu=[dict(s=p.s, d_e2=m["e2"] - r["e2"], d_e3=m["e3"] - r["e3"],
@@ -282,8 +302,10 @@ def main():
         out["fp32_products"] = mixed
         # split BF16 x3 products beside them (measured error, not a parity claim: R19)
         bres, bdt = timed(2, 1, args.mixed_steps)
+        bprof = [_lib.dsrg_pt3_energy(d, profile=True, precision=2) for d in dev]
         out["bf16x3_products"] = dict(
             value=args.mixed_steps * len(dev) / bdt, unit="energies/s",
+            roofline=dominant_kernel(bprof, 2, bdt / args.mixed_steps / len(dev))[0],
             speedup_vs_fp64=(args.mixed_steps * len(dev) / bdt) / (energies / dt),
             parity=parity_of(probs, bres, args.workload),
             vs_fp64_gpu=[dict(s=p.s, d_e2=b["e2"] - r["e2"], d_e3=b["e3"] - r["e3"],

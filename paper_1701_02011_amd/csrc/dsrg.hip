@@ -4031,8 +4031,9 @@ extern "C" int dsrg_test_gett(int nm, const int* md, const long long* am, const 
     HIPCHECK(hipMemcpy(dA, A, na * 8, hipMemcpyHostToDevice));
     HIPCHECK(hipMemcpy(dB, B, nb * 8, hipMemcpyHostToDevice));
     HIPCHECK(hipMemcpy(dC, C, nc * 8, hipMemcpyHostToDevice));
-    // with a workspace, shapes with few output tiles and a long k range use split-K
-    const long long ws_elems = 1LL << 22;
+    // with a workspace, shapes with few output tiles and a long k range use split-K (room
+    // for up to 8 partial outputs, at least 2^22 and at most 2^28 doubles)
+    const long long ws_elems = std::max<long long>(1LL << 22, std::min<long long>(8LL * M * N, 1LL << 28));
     double* ws;
     HIPCHECK(hipMalloc(&ws, ws_elems * 8));
     launch_gett(g, dA, dB, dC, 0, kRoleGeneric, ws, ws_elems, precision);

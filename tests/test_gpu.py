@@ -35,7 +35,8 @@ def _close(x, ref, rel=1e-10):
 # ---------------------------------------------------------------------------
 # contraction kernel
 # ---------------------------------------------------------------------------
-GETT_CASES = ["gemm", "ragged", "strided", "multi", "vec", "accum", "splitk", "longk", "packk", "nt", "nt_tail"]
+GETT_CASES = ["gemm", "ragged", "strided", "multi", "vec", "accum", "splitk", "longk", "packk", "nt", "nt_tail",
+              "big_splitk"]
 
 
 @pytest.mark.parametrize("precision", [0, 1, 2])
@@ -102,6 +103,14 @@ def test_gett_kernel(case, precision):
                    k=[(f, e * u, N * u), (e, u, f * N * u), (u, 1, 1)], alpha=0.5, beta=1)
         ref = C + 0.5 * np.einsum("mfeu,efnu->mn", A, B)
         K = f * e * u
+    elif case == "big_splitk":
+        # exactly 256 output tiles of 128 x 128 (ragged in m and n) and a long ragged k
+        # range contiguous in both operands: the 128 x 128 launch splits k in two
+        M, N, K = 2040, 2047, 16 * 200 + 13
+        A = rng.standard_normal((M, K)); Bt = rng.standard_normal((N, K)); C = rng.standard_normal((M, N))
+        B = Bt
+        out = gett(A, Bt, C, m=[(M, K, N)], n=[(N, K, 1)], k=[(K, 1, 1)], alpha=0.25, beta=1)
+        ref = C + 0.25 * (A @ Bt.T)
     elif case in ("nt", "nt_tail"):
         # both operands contiguous along k and enough output tiles for 128 x 128 tiles
         # (ragged in m, n and k; accumulate)
