@@ -99,10 +99,11 @@ constexpr int kRoles = 4;
 // g must have been through gett_prepare.  ws (ws_elems doubles) enables split-K for
 // launches with few output tiles and a long k range: partial tiles go to ws and a
 // fixed-order reduction writes C (deterministic).
-// prec (DSRG_PRECISION_*): 1 FP32 products, 2 split-BF16 x3 products (operands rounded to
-// FP32 in LDS, split into BF16 hi and lo parts, three BF16 MFMAs per block; both with FP32
-// sums flushed as below); 0 FP64 throughout.  FP32 products: operands rounded to FP32 in LDS, FP32 MFMA, sums flushed into the
-// FP64 output every kF32FlushSteps k steps); else FP64 throughout.
+// prec (DSRG_PRECISION_*): 0 FP64 throughout; 1 FP32 products (operands rounded to FP32 in
+// LDS, FP32 MFMA); 2 split-BF16 x3 products (operands rounded to FP32 in LDS, split into
+// BF16 hi and lo parts, three BF16 MFMAs per block).  With 1 and 2 the FP32 sums are added
+// into the FP64 output (or partial tile) every 1024 k values, and 128 x 128 tiles walk
+// kGettBigBK k values per step.
 void launch_gett(const GettDesc& g, const double* A, const double* B, double* C, hipStream_t st,
                  int role, double* ws, long long ws_elems, int prec = 0);
 int gett_splits(const GettDesc& g, long long ws_elems);
