@@ -75,3 +75,26 @@ def test_tile_rules_keep_the_energies():
     for key in ("e2", "e3_a", "e3_b"):
         assert _close(r[key], ref[key]), (key, r[key], ref[key])
     assert other["virt_batch_used"] == base["virt_batch_used"] and other["e3"] == base["e3"]
+
+
+@pytest.mark.parametrize("precision", [1, 2])
+def test_curve_batch_mixed_precision_against_oracle(tuned, precision):
+    """The curve's mixed precisions through the batch entry point: FP32 products meet the
+    mixed bar (1e-6 |E| relative) against the oracle's stored values, split BF16 x3 products
+    are reported against them with their measured bound (2e-5 relative; not a parity claim),
+    and both agree bit for bit with single calls at the same precision."""
+    probs = [make_batch_config(1, first=k)[0] for k in CURVE_GOLDEN]
+    dev = [_lib.to_device(p) for p in probs]
+    res, codes = _lib.dsrg_pt3_energy_batch(dev, precision=precision)
+    assert all(c == _lib.DSRG_OK for c in codes), codes
+    bar = 1e-6 if precision == 1 else 2e-5
+    for k, (g, d) in enumerate(zip(CURVE_GOLDEN, dev)):
+        assert res[k]["precision_used"] == precision
+        single = _lib.dsrg_pt3_energy(d, cache=False, precision=precision)
+        assert (res[k]["e2"], res[k]["e3"]) == (single["e2"], single["e3"]), k
+        with open(os.path.join(GOLDEN, "curve%d_s0.5.json" % g)) as f:
+            ref = json.load(f)
+        for key in ("e2", "e3"):
+            rel = abs(res[k][key] - ref[key]) / max(1.0, abs(ref[key]))
+            say("curve geometry", g, "precision", precision, key, res[k][key], "oracle", ref[key], "rel", rel)
+            assert rel <= bar, (g, key, rel)
