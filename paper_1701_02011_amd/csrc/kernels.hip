@@ -90,7 +90,7 @@ constexpr int BK = kGettBK;
 // Tile of WGM x (4 / WGM) waves, each wave WM x WN MFMA blocks of 16 x 16; T is the
 // element type staged in LDS (double, or float for the FP32-product precision).
 template <int WM, int WN, int WGM, class T = double, int kBK = BK>
-struct TileLds {
+struct alignas(16) TileLds {
   static constexpr int BM = 16 * WM * WGM, BN = 16 * WN * (4 / WGM);
   // row pitch: 16 lanes of a 64-bit access (one bank pass) with k = 0..15 and one m land on
   // distinct banks when 2 pitch = 2 (mod 32 banks), i.e. an odd pitch of doubles; 32 lanes
@@ -203,21 +203,41 @@ __device__ __forceinline__ void gett_tile(const GettDesc& g, const double* __res
   // load slots: slot i of this thread covers (row, k) of the A tile and (k, col) of B.  With
   // k fastest, 16 lanes cover k = 0..15 of a row, slot i in row ma0 + 16 (i / kPair) at
   // k = ka0 + 16 (i % kPair) (kPair = BK / 16 slots per row); else every slot has the row
-  // ma0 and k = ka0 + i kad.  The per-slot values are one register plus uniform steps, so
-  // the bounds tests and LDS addresses need no register per slot, and the operand offsets
-  // one per row (kPair slots share it).
+  // ma0 and k = ka0 + i kad.  The 128 x 128 FP32 / BF16 x3 tiles (32 k per step, kMPair)
+  // pair the rows instead: slots 2j and 2j + 1 hold rows m and m + 1 at one k, written to
+  // LDS as one 8-byte store (k fastest: rows 2 (tid / 16) + q + 32 (i / 4) at
+  // k = tid % 16 + 16 ((i / 2) % 2); else rows 2 (tid % 64) + q at k = tid / 64 + 4 (i / 2)).
+  // The per-slot values are one register plus uniform steps, so the bounds tests and LDS
+  // addresses need no register per slot, and the operand offsets one per row.
   constexpr int kPair = BK / kGettBK;
   static_assert(kPair * kGettBK == BK && 256 / kGettBK * kGettBK == 256, "slot rows");
-  const int ka0 = akf ? (tid & (kGettBK - 1)) : tid / BM, kad = akf ? 0 : 256 / BM;
-  const int ma0 = akf ? tid / kGettBK : (tid & (BM - 1));
-  const int kb0 = bkf ? (tid & (kGettBK - 1)) : tid / BN, kbd = bkf ? 0 : 256 / BN;
-  const int nb0 = bkf ? tid / kGettBK : (tid & (BN - 1));
-  auto a_dk = [&](int i) { return akf ? kGettBK * (i % kPair) : kad * i; };
-  auto b_dk = [&](int i) { return bkf ? kGettBK * (i % kPair) : kbd * i; };
+  constexpr bool kMPair = kP != 0 && BK == 2 * kGettBK && BM == 128 && BN == 128;
+  const int ka0 = kMPair ? (akf ? (tid & 15) : tid >> 6) : (akf ? (tid & (kGettBK - 1)) : tid / BM);
+  const int ma0 = kMPair ? (akf ? 2 * (tid >> 4) : 2 * (tid & 63)) : (akf ? tid / kGettBK : (tid & (BM - 1)));
+  const int kb0 = kMPair ? (bkf ? (tid & 15) : tid >> 6) : (bkf ? (tid & (kGettBK - 1)) : tid / BN);
+  const int nb0 = kMPair ? (bkf ? 2 * (tid >> 4) : 2 * (tid & 63)) : (bkf ? tid / kGettBK : (tid & (BN - 1)));
+  const int kad = akf ? 0 : 256 / BM, kbd = bkf ? 0 : 256 / BN;
+  // k and row (column) of slot i relative to (ka0, ma0)
+  auto dk = [&](bool kf, int kd_, int i) -> int {
+    if constexpr (kMPair) return kf ? 16 * ((i >> 1) & 1) : 4 * (i >> 1);
+    else return kf ? kGettBK * (i % kPair) : kd_ * i;
+  };
+  auto dm = [&](bool kf, int i) -> int {
+    if constexpr (kMPair) return (i & 1) + (kf ? 32 * (i >> 2) : 0);
+    else return kf ? 256 / kGettBK * (i / kPair) : 0;
+  };
+  // operand rows held per thread and the first slot of row r
+  constexpr int kRows = kMPair ? 8 : (BM >= BN ? NA : NB) / kPair;
+  auto first_of = [&](bool kf, int r) -> int {
+    if constexpr (kMPair) return kf ? ((r & 1) | ((r >> 1) << 2)) : (r & 1);
+    else return r * kPair;
+  };
+  auto a_dk = [&](int i) { return dk(akf, kad, i); };
+  auto b_dk = [&](int i) { return dk(bkf, kbd, i); };
   auto a_k = [&](int i) { return ka0 + a_dk(i); };
-  auto a_m = [&](int i) { return ma0 + (akf ? 256 / kGettBK * (i / kPair) : 0); };
+  auto a_m = [&](int i) { return ma0 + dm(akf, i); };
   auto b_k = [&](int i) { return kb0 + b_dk(i); };
-  auto b_n = [&](int i) { return nb0 + (bkf ? 256 / kGettBK * (i / kPair) : 0); };
+  auto b_n = [&](int i) { return nb0 + dm(bkf, i); };
   // k slot j of a step: value j of the inner component (plain steps), or value j % kin of
   // the inner and j / kin of the walked component (packed steps).  Each slot keeps a 4-bit
   // code v (j; or j / kin, 15 past the packed ranges) and is real in a step while v < L
@@ -228,21 +248,23 @@ __device__ __forceinline__ void gett_tile(const GettDesc& g, const double* __res
     return kp > 1 ? (long long)(j % kin) * s_in + (long long)(j / kin) * s_w : (long long)j * s_in;
   };
   auto slot_code = [&](int j) -> unsigned { return kp > 1 ? (j < kp * kin ? (unsigned)(j / kin) : 15u) : (unsigned)j; };
-  // operand offset of the first slot of each row group of kPair slots (0 past M, N: such
-  // rows read a real element and reach only outputs that are never written); slot i adds
-  // (i % kPair) times the uniform a_pd (b_pd)
-  long long aoff[NA / kPair], boff[NB / kPair];
-  const long long a_pd = (long long)(akf ? kGettBK : kad) * a_in, b_pd = (long long)(bkf ? kGettBK : kbd) * b_in;
+  // operand offset of the first slot of each row (0 past M, N: such rows read a real
+  // element and reach only outputs that are never written); slot i adds the uniform
+  // (k of i - k of its row's first slot) times the inner stride
+  static_assert(NA / kPair <= kRows && NB / kPair <= kRows, "rows");
+  long long aoff[kRows], boff[kRows];
   unsigned acode = 0, bcode = 0;
 #pragma unroll
-  for (int i = 0; i < NA; i += kPair) {
+  for (int r = 0; r < kRows; ++r) {
+    const int i = first_of(akf, r);
     const int m = tile_m + a_m(i);
-    aoff[i / kPair] = m < g.M ? decode_fast(m, g.nm, g.md, g.mmag, g.msh, g.am) + slot_off(a_k(i), a_in, a_st) : 0;
+    aoff[r] = i < NA && m < g.M ? decode_fast(m, g.nm, g.md, g.mmag, g.msh, g.am) + slot_off(a_k(i), a_in, a_st) : 0;
   }
 #pragma unroll
-  for (int i = 0; i < NB; i += kPair) {
+  for (int r = 0; r < kRows; ++r) {
+    const int i = first_of(bkf, r);
     const int n = tile_n + b_n(i);
-    boff[i / kPair] = n < g.N ? decode_fast(n, g.nn, g.nd, g.nmag, g.nsh, g.bn) + slot_off(b_k(i), b_in, b_st) : 0;
+    boff[r] = i < NB && n < g.N ? decode_fast(n, g.nn, g.nd, g.nmag, g.nsh, g.bn) + slot_off(b_k(i), b_in, b_st) : 0;
   }
   if constexpr (kPackK) {
 #pragma unroll
@@ -250,8 +272,21 @@ __device__ __forceinline__ void gett_tile(const GettDesc& g, const double* __res
 #pragma unroll
     for (int i = 0; i < NB; ++i) bcode |= slot_code(b_k(i)) << (4 * i);
   }
-  auto a_off = [&](int i) -> long long { return aoff[i / kPair] + (i % kPair ? a_pd : 0); };
-  auto b_off = [&](int i) -> long long { return boff[i / kPair] + (i % kPair ? b_pd : 0); };
+  // (constant indices: the two layouts of the paired tiles are chosen by a select)
+  auto a_off = [&](int i) -> long long {
+    if constexpr (kMPair)
+      return akf ? aoff[(i & 1) | ((i >> 2) << 1)] + (long long)(16 * ((i >> 1) & 1)) * a_in
+                 : aoff[i & 1] + (long long)(4 * (i >> 1)) * a_in;
+    else
+      return aoff[i / kPair] + (long long)(a_dk(i) - a_dk(i / kPair * kPair)) * a_in;
+  };
+  auto b_off = [&](int i) -> long long {
+    if constexpr (kMPair)
+      return bkf ? boff[(i & 1) | ((i >> 2) << 1)] + (long long)(16 * ((i >> 1) & 1)) * b_in
+                 : boff[i & 1] + (long long)(4 * (i >> 1)) * b_in;
+    else
+      return boff[i / kPair] + (long long)(b_dk(i) - b_dk(i / kPair * kPair)) * b_in;
+  };
   // slot i of A (B) is real in the current step (L = real_slots()); without packed steps
   // the code is the slot itself
   auto real_a = [&](int i, int L) -> bool {
@@ -327,12 +362,27 @@ __device__ __forceinline__ void gett_tile(const GettDesc& g, const double* __res
   const int a_l0 = ka0 * LDA + ma0, b_l0 = kb0 * LDB + nb0;
   auto stash = [&](int buf) {
     const int L = real_slots();
+    if constexpr (kMPair) {
+      // rows m, m + 1 (m even; even pitch) at one k: one 8-byte store per pair
+      typedef T T2 __attribute__((ext_vector_type(2)));
 #pragma unroll
-    for (int i = 0; i < NA; ++i)
-      As[buf][a_l0 + a_dk(i) * LDA + (a_m(i) - ma0)] = real_a(i, L) ? (T)ra[i] : (T)0;
+      for (int i = 0; i < NA; i += 2) {
+        const bool ok = real_a(i, L);
+        *(T2*)&As[buf][a_l0 + a_dk(i) * LDA + dm(akf, i)] = (T2){ok ? (T)ra[i] : (T)0, ok ? (T)ra[i + 1] : (T)0};
+      }
 #pragma unroll
-    for (int i = 0; i < NB; ++i)
-      Bs[buf][b_l0 + b_dk(i) * LDB + (b_n(i) - nb0)] = real_b(i, L) ? (T)rb[i] : (T)0;
+      for (int i = 0; i < NB; i += 2) {
+        const bool ok = real_b(i, L);
+        *(T2*)&Bs[buf][b_l0 + b_dk(i) * LDB + dm(bkf, i)] = (T2){ok ? (T)rb[i] : (T)0, ok ? (T)rb[i + 1] : (T)0};
+      }
+    } else {
+#pragma unroll
+      for (int i = 0; i < NA; ++i)
+        As[buf][a_l0 + a_dk(i) * LDA + dm(akf, i)] = real_a(i, L) ? (T)ra[i] : (T)0;
+#pragma unroll
+      for (int i = 0; i < NB; ++i)
+        Bs[buf][b_l0 + b_dk(i) * LDB + dm(bkf, i)] = real_b(i, L) ? (T)rb[i] : (T)0;
+    }
   };
 
   typename MF::Acc acc[WM][WN];
