@@ -95,8 +95,10 @@ struct alignas(16) TileLds {
   // row pitch: 16 lanes of a 64-bit access (one bank pass) with k = 0..15 and one m land on
   // distinct banks when 2 pitch = 2 (mod 32 banks), i.e. an odd pitch of doubles; 32 lanes
   // of a 32-bit access with k = 0..15 and two m need a pitch of 2 (mod 32) floats (with 32
-  // k values per step the slots still put k = 0..15 of two rows on 32 lanes)
-  static constexpr int PAD = sizeof(T) == 8 ? 1 : 2;
+  // k values per step the slots still put k = 0..15 of two rows on 32 lanes).  The 128 x 128
+  // FP64 tiles store rows m, m + 1 (m even) as one 16-byte access: 8 lanes per bank pass
+  // with k = 0..7 are distinct with a pitch of 2 (mod 4) doubles, which keeps them aligned.
+  static constexpr int PAD = sizeof(T) == 8 ? (BM == 128 && BN == 128 ? 2 : 1) : 2;
   static constexpr int LDA = BM + PAD, LDB = BN + PAD;
   T As[2][kBK * LDA];
   T Bs[2][kBK * LDB];
@@ -203,15 +205,17 @@ __device__ __forceinline__ void gett_tile(const GettDesc& g, const double* __res
   // load slots: slot i of this thread covers (row, k) of the A tile and (k, col) of B.  With
   // k fastest, 16 lanes cover k = 0..15 of a row, slot i in row ma0 + 16 (i / kPair) at
   // k = ka0 + 16 (i % kPair) (kPair = BK / 16 slots per row); else every slot has the row
-  // ma0 and k = ka0 + i kad.  The 128 x 128 FP32 / BF16 x3 tiles (32 k per step, kMPair)
-  // pair the rows instead: slots 2j and 2j + 1 hold rows m and m + 1 at one k, written to
-  // LDS as one 8-byte store (k fastest: rows 2 (tid / 16) + q + 32 (i / 4) at
-  // k = tid % 16 + 16 ((i / 2) % 2); else rows 2 (tid % 64) + q at k = tid / 64 + 4 (i / 2)).
-  // The per-slot values are one register plus uniform steps, so the bounds tests and LDS
-  // addresses need no register per slot, and the operand offsets one per row.
+  // ma0 and k = ka0 + i kad.  The 128 x 128 tiles of plain launches (16 k per step in
+  // FP64, 32 with FP32 / BF16 x3 products; kMPair) pair the rows instead: slots 2j and
+  // 2j + 1 hold rows m and m + 1 at one k, written to LDS as one 16-byte (FP64) or 8-byte
+  // store (k fastest: rows 2 (tid / 16) + q + 32 (i / (2 kPair)) at
+  // k = tid % 16 + 16 ((i / 2) % kPair); else rows 2 (tid % 64) + q at
+  // k = tid / 64 + 4 (i / 2)).  The per-slot values are one register plus uniform steps, so
+  // the bounds tests and LDS addresses need no register per slot, and the operand offsets
+  // one per row.
   constexpr int kPair = BK / kGettBK;
   static_assert(kPair * kGettBK == BK && 256 / kGettBK * kGettBK == 256, "slot rows");
-  constexpr bool kMPair = kP != 0 && BK == 2 * kGettBK && BM == 128 && BN == 128;
+  constexpr bool kMPair = BM == 128 && BN == 128 && !kPackK && BK == (kP != 0 ? 2 : 1) * kGettBK;
   const int ka0 = kMPair ? (akf ? (tid & 15) : tid >> 6) : (akf ? (tid & (kGettBK - 1)) : tid / BM);
   const int ma0 = kMPair ? (akf ? 2 * (tid >> 4) : 2 * (tid & 63)) : (akf ? tid / kGettBK : (tid & (BM - 1)));
   const int kb0 = kMPair ? (bkf ? (tid & 15) : tid >> 6) : (bkf ? (tid & (kGettBK - 1)) : tid / BN);
@@ -219,17 +223,18 @@ __device__ __forceinline__ void gett_tile(const GettDesc& g, const double* __res
   const int kad = akf ? 0 : 256 / BM, kbd = bkf ? 0 : 256 / BN;
   // k and row (column) of slot i relative to (ka0, ma0)
   auto dk = [&](bool kf, int kd_, int i) -> int {
-    if constexpr (kMPair) return kf ? 16 * ((i >> 1) & 1) : 4 * (i >> 1);
+    if constexpr (kMPair) return kf ? 16 * ((i >> 1) % kPair) : 4 * (i >> 1);
     else return kf ? kGettBK * (i % kPair) : kd_ * i;
   };
   auto dm = [&](bool kf, int i) -> int {
-    if constexpr (kMPair) return (i & 1) + (kf ? 32 * (i >> 2) : 0);
+    if constexpr (kMPair) return (i & 1) + (kf ? 32 * (i / (2 * kPair)) : 0);
     else return kf ? 256 / kGettBK * (i / kPair) : 0;
   };
-  // operand rows held per thread and the first slot of row r
+  // operand rows held per thread and the first slot of row r (paired tiles, k fastest:
+  // row r = 2 j + q holds slots 2 kPair j + q + 2 h)
   constexpr int kRows = kMPair ? 8 : (BM >= BN ? NA : NB) / kPair;
   auto first_of = [&](bool kf, int r) -> int {
-    if constexpr (kMPair) return kf ? ((r & 1) | ((r >> 1) << 2)) : (r & 1);
+    if constexpr (kMPair) return kf ? ((r & 1) | ((r >> 1) * 2 * kPair)) : (r & 1);
     else return r * kPair;
   };
   auto a_dk = [&](int i) { return dk(akf, kad, i); };
@@ -275,14 +280,14 @@ __device__ __forceinline__ void gett_tile(const GettDesc& g, const double* __res
   // (constant indices: the two layouts of the paired tiles are chosen by a select)
   auto a_off = [&](int i) -> long long {
     if constexpr (kMPair)
-      return akf ? aoff[(i & 1) | ((i >> 2) << 1)] + (long long)(16 * ((i >> 1) & 1)) * a_in
+      return akf ? aoff[(i & 1) | ((i / (2 * kPair)) << 1)] + (long long)(16 * ((i >> 1) % kPair)) * a_in
                  : aoff[i & 1] + (long long)(4 * (i >> 1)) * a_in;
     else
       return aoff[i / kPair] + (long long)(a_dk(i) - a_dk(i / kPair * kPair)) * a_in;
   };
   auto b_off = [&](int i) -> long long {
     if constexpr (kMPair)
-      return bkf ? boff[(i & 1) | ((i >> 2) << 1)] + (long long)(16 * ((i >> 1) & 1)) * b_in
+      return bkf ? boff[(i & 1) | ((i / (2 * kPair)) << 1)] + (long long)(16 * ((i >> 1) % kPair)) * b_in
                  : boff[i & 1] + (long long)(4 * (i >> 1)) * b_in;
     else
       return boff[i / kPair] + (long long)(b_dk(i) - b_dk(i / kPair * kPair)) * b_in;
@@ -363,7 +368,7 @@ __device__ __forceinline__ void gett_tile(const GettDesc& g, const double* __res
   auto stash = [&](int buf) {
     const int L = real_slots();
     if constexpr (kMPair) {
-      // rows m, m + 1 (m even; even pitch) at one k: one 8-byte store per pair
+      // rows m, m + 1 (m even; even pitch) at one k: one store per pair
       typedef T T2 __attribute__((ext_vector_type(2)));
 #pragma unroll
       for (int i = 0; i < NA; i += 2) {
