@@ -36,7 +36,7 @@ def _close(x, ref, rel=1e-10):
 # contraction kernel
 # ---------------------------------------------------------------------------
 GETT_CASES = ["gemm", "ragged", "strided", "multi", "vec", "accum", "splitk", "longk", "packk", "nt", "nt_tail",
-              "big_splitk"]
+              "big_splitk", "big_mfast"]
 
 
 @pytest.mark.parametrize("precision", [0, 1, 2])
@@ -111,6 +111,14 @@ def test_gett_kernel(case, precision):
         B = Bt
         out = gett(A, Bt, C, m=[(M, K, N)], n=[(N, K, 1)], k=[(K, 1, 1)], alpha=0.25, beta=1)
         ref = C + 0.25 * (A @ Bt.T)
+    elif case == "big_mfast":
+        # 128 x 128 tiles with both operands contiguous along the free index (the layout of
+        # the Coulomb builds: m and n fastest), ragged in m, n and k; accumulate
+        M, N, K = 2049, 2050, 37
+        At = rng.standard_normal((K, M)); B = rng.standard_normal((K, N)); C = rng.standard_normal((M, N))
+        A = At
+        out = gett(At, B, C, m=[(M, 1, N)], n=[(N, 1, 1)], k=[(K, M, N)], alpha=0.5, beta=1)
+        ref = C + 0.5 * (At.T @ B)
     elif case in ("nt", "nt_tail"):
         # both operands contiguous along k and enough output tiles for 128 x 128 tiles
         # (ragged in m, n and k; accumulate)
