@@ -558,10 +558,12 @@ __device__ __forceinline__ void grouped_tile(int Lp, int gx, int gy, int& tm, in
 
 // Logical tile L of a (gx, gy, gz) grid (grouped m tiles, see grouped_tile; plain m-first
 // order with the triangle skip).
-template <int WM, int WN, int kP, int kBK>
+template <int WM, int WN, int kP, int kBK, int WGM = 2>
 __device__ __forceinline__ void gett_grid_tile(const GettDesc& g, const double* __restrict__ A,
                                                const double* __restrict__ B, double* __restrict__ C,
-                                               TileLds<WM, WN, 2, typename Mfma<kP>::T, kBK>& lds) {
+                                               TileLds<WM, WN, WGM, typename Mfma<kP>::T, kBK>& lds) {
+  using Lds = TileLds<WM, WN, WGM, typename Mfma<kP>::T, kBK>;
+  constexpr int BM = Lds::BM, BN = Lds::BN;
   const int gx = gridDim.x, gy = gridDim.y;
   const int total = gx * gy * gridDim.z;
   const int b = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
@@ -578,8 +580,8 @@ __device__ __forceinline__ void gett_grid_tile(const GettDesc& g, const double* 
     kz = L / (gx * gy);
     grouped_tile(L - kz * gx * gy, gx, gy, tm, tn);
   }
-  if (g.tri > 0 && (tn * (32 * WN) + 32 * WN - 1) / g.tri < (tm * (32 * WM)) / g.tri) return;
-  gett_tile<WM, WN, 2, kP, (WM * WN < 16), kBK>(g, A, B, C, tm * (32 * WM), tn * (32 * WN), kz, lds);
+  if (g.tri > 0 && (tn * BN + BN - 1) / g.tri < (tm * BM) / g.tri) return;
+  gett_tile<WM, WN, WGM, kP, (WM * WN < 16), kBK>(g, A, B, C, tm * BM, tn * BN, kz, lds);
 }
 
 // k values per step of the plain launches: FP32 and BF16 x3 products on 128 x 128 tiles
@@ -588,32 +590,33 @@ __device__ __forceinline__ void gett_grid_tile(const GettDesc& g, const double* 
 template <int kP, int WM, int WN>
 constexpr int plain_bk() { return kP != 0 && WM * WN == 16 ? kGettBigBK : kGettBK; }
 
-template <int kRole, int WM, int WN>
+// WGM: waves along m (2: 64 x 64 and 128 x 128 tiles; 4: 128 x 32 tiles of skinny outputs)
+template <int kRole, int WM, int WN, int WGM = 2>
 __global__ __launch_bounds__(256) void gett_f64_kernel(GettDesc g, const double* __restrict__ A,
                                                        const double* __restrict__ B,
                                                        double* __restrict__ C) {
-  __shared__ TileLds<WM, WN, 2, double, plain_bk<0, WM, WN>()> lds;
-  gett_grid_tile<WM, WN, 0, plain_bk<0, WM, WN>()>(g, A, B, C, lds);
+  __shared__ TileLds<WM, WN, WGM, double, plain_bk<0, WM, WN>()> lds;
+  gett_grid_tile<WM, WN, 0, plain_bk<0, WM, WN>(), WGM>(g, A, B, C, lds);
 }
 
 // FP64 operands and output, FP32 products (DSRG_PRECISION_FP32); two workgroups per CU
 // (the 32-deep steps of the 128 x 128 tiles would otherwise take every register)
-template <int kRole, int WM, int WN>
+template <int kRole, int WM, int WN, int WGM = 2>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void gett_f32_kernel(GettDesc g, const double* __restrict__ A,
                                                        const double* __restrict__ B,
                                                        double* __restrict__ C) {
-  __shared__ TileLds<WM, WN, 2, float, plain_bk<1, WM, WN>()> lds;
-  gett_grid_tile<WM, WN, 1, plain_bk<1, WM, WN>()>(g, A, B, C, lds);
+  __shared__ TileLds<WM, WN, WGM, float, plain_bk<1, WM, WN>()> lds;
+  gett_grid_tile<WM, WN, 1, plain_bk<1, WM, WN>(), WGM>(g, A, B, C, lds);
 }
 
 // FP64 operands and output, split-BF16 x3 products (DSRG_PRECISION_BF16X3); two
 // workgroups per CU as for FP32 products
-template <int kRole, int WM, int WN>
+template <int kRole, int WM, int WN, int WGM = 2>
 __global__ __launch_bounds__(256) __attribute__((amdgpu_waves_per_eu(2))) void gett_b3_kernel(GettDesc g, const double* __restrict__ A,
                                                       const double* __restrict__ B,
                                                       double* __restrict__ C) {
-  __shared__ TileLds<WM, WN, 2, float, plain_bk<2, WM, WN>()> lds;
-  gett_grid_tile<WM, WN, 2, plain_bk<2, WM, WN>()>(g, A, B, C, lds);
+  __shared__ TileLds<WM, WN, WGM, float, plain_bk<2, WM, WN>()> lds;
+  gett_grid_tile<WM, WN, 2, plain_bk<2, WM, WN>(), WGM>(g, A, B, C, lds);
 }
 
 // C[m][n] = alpha * sum_z part[z][m][n] (+ C) in a fixed order of z
@@ -782,6 +785,10 @@ static bool big_tiles(const GettDesc& g) {
 
 bool gett_big_tiles(const GettDesc& g) { return big_tiles(g); }
 
+// 128 x 32 tiles (four waves along m) for plain launches with at most 32 output columns and
+// many rows: a 64 x 64 tile there computes more than half of its MFMA work on zero columns.
+static bool skinny_tiles(const GettDesc& g) { return !big_tiles(g) && g.tri <= 0 && g.N <= 32 && g.M >= 2048; }
+
 // Split-K factor: the number of k chunks that fills the resident workgroup slots in the
 // most nearly whole rounds (256 CUs; two 128 x 128 or four 64 x 64 workgroups per CU fit
 // the registers), keeping at least 16 k steps per chunk (4 when the output has at most
@@ -794,9 +801,10 @@ bool gett_big_tiles(const GettDesc& g) { return big_tiles(g); }
 //    of this kernel at two workgroups per CU.  Up to 64 chunks.  (Triangular launches,
 //    whose grid skips tiles, keep the 5 % rule.)
 int gett_splits(const GettDesc& g, long long ws_elems) {
-  const bool big = big_tiles(g);
-  const int bm = big ? 128 : 64, bn = bm;
-  const long long slots = 256LL * (big ? 2 : 4);
+  const bool big = big_tiles(g), skinny = skinny_tiles(g);
+  const int bm = big || skinny ? 128 : 64, bn = big ? 128 : skinny ? 32 : 64;
+  // resident workgroups per CU: registers (128 x 128), LDS (128 x 32: 41.5 KB), else 4
+  const long long slots = 256LL * (big ? 2 : skinny ? 3 : 4);
   const long long tiles = (long long)((g.M + bm - 1) / bm) * ((g.N + bn - 1) / bn);
   const long long mn = std::max<long long>(1, (long long)g.M * g.N);
   const long long min_chunk = mn <= (1LL << 20) ? 4 : 16;
@@ -835,22 +843,29 @@ int gett_splits(const GettDesc& g, long long ws_elems) {
   return (int)best;
 }
 
+// shape: 0 64 x 64, 1 128 x 128, 2 128 x 32 tiles
 template <int kRole>
-static void launch_role(const GettDesc& g, bool big, int prec, dim3 grid, const double* A,
+static void launch_role(const GettDesc& g, int shape, int prec, dim3 grid, const double* A,
                         const double* B, double* C, hipStream_t st) {
   if (prec == 2) {
-    if (big)
+    if (shape == 1)
       hipLaunchKernelGGL((gett_b3_kernel<kRole, 4, 4>), grid, dim3(256), 0, st, g, A, B, C);
+    else if (shape == 2)
+      hipLaunchKernelGGL((gett_b3_kernel<kRole, 2, 2, 4>), grid, dim3(256), 0, st, g, A, B, C);
     else
       hipLaunchKernelGGL((gett_b3_kernel<kRole, 2, 2>), grid, dim3(256), 0, st, g, A, B, C);
   } else if (prec == 1) {
-    if (big)
+    if (shape == 1)
       hipLaunchKernelGGL((gett_f32_kernel<kRole, 4, 4>), grid, dim3(256), 0, st, g, A, B, C);
+    else if (shape == 2)
+      hipLaunchKernelGGL((gett_f32_kernel<kRole, 2, 2, 4>), grid, dim3(256), 0, st, g, A, B, C);
     else
       hipLaunchKernelGGL((gett_f32_kernel<kRole, 2, 2>), grid, dim3(256), 0, st, g, A, B, C);
   } else {
-    if (big)
+    if (shape == 1)
       hipLaunchKernelGGL((gett_f64_kernel<kRole, 4, 4>), grid, dim3(256), 0, st, g, A, B, C);
+    else if (shape == 2)
+      hipLaunchKernelGGL((gett_f64_kernel<kRole, 2, 2, 4>), grid, dim3(256), 0, st, g, A, B, C);
     else
       hipLaunchKernelGGL((gett_f64_kernel<kRole, 2, 2>), grid, dim3(256), 0, st, g, A, B, C);
   }
@@ -870,7 +885,8 @@ void launch_gett(const GettDesc& g0, const double* A, const double* B, double* C
     g.steps = (long long)(g.K / kin) * g.ksteps;
     g.kchunk = g.steps;
   }
-  const int bm = big ? 128 : 64, bn = bm;
+  const int shape = big ? 1 : skinny_tiles(g) ? 2 : 0;
+  const int bm = shape ? 128 : 64, bn = shape == 1 ? 128 : shape == 2 ? 32 : 64;
   int ns = ws ? gett_splits(g, ws_elems) : 1;
   g.part = nullptr;
   g.kchunk = g.steps;
@@ -883,11 +899,11 @@ void launch_gett(const GettDesc& g0, const double* A, const double* B, double* C
   dim3 grid((g.M + bm - 1) / bm, (g.N + bn - 1) / bn, ns);
   // the role only selects a distinct kernel symbol so profiles can tell the launches apart
   if (role == kRoleLadder)
-    launch_role<kRoleLadder>(g, big, prec, grid, A, B, C, st);
+    launch_role<kRoleLadder>(g, shape, prec, grid, A, B, C, st);
   else if (role == kRoleIntegrals)
-    launch_role<kRoleIntegrals>(g, big, prec, grid, A, B, C, st);
+    launch_role<kRoleIntegrals>(g, shape, prec, grid, A, B, C, st);
   else
-    launch_role<kRoleGeneric>(g, big, prec, grid, A, B, C, st);
+    launch_role<kRoleGeneric>(g, shape, prec, grid, A, B, C, st);
   if (ns > 1) {
     long long total = (long long)g.M * g.N;
     long long blocks = std::min<long long>((total + 255) / 256, 4096);

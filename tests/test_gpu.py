@@ -36,7 +36,7 @@ def _close(x, ref, rel=1e-10):
 # contraction kernel
 # ---------------------------------------------------------------------------
 GETT_CASES = ["gemm", "ragged", "strided", "multi", "vec", "accum", "splitk", "longk", "packk", "nt", "nt_tail",
-              "big_splitk", "big_mfast"]
+              "big_splitk", "big_mfast", "skinny", "skinny_mfast", "skinny_splitk"]
 
 
 @pytest.mark.parametrize("precision", [0, 1, 2])
@@ -119,6 +119,21 @@ def test_gett_kernel(case, precision):
         A = At
         out = gett(At, B, C, m=[(M, 1, N)], n=[(N, 1, 1)], k=[(K, M, N)], alpha=0.5, beta=1)
         ref = C + 0.5 * (At.T @ B)
+    elif case in ("skinny", "skinny_splitk"):
+        # at most 32 output columns and many rows: 128 x 32 tiles, ragged in m, n and k,
+        # both operands contiguous along k; the long k range of the second case is split
+        M, N, K = (2100, 28, 309) if case == "skinny" else (2050, 17, 16 * 300 + 7)
+        A = rng.standard_normal((M, K)); Bt = rng.standard_normal((N, K)); C = rng.standard_normal((M, N))
+        B = Bt
+        out = gett(A, Bt, C, m=[(M, K, N)], n=[(N, K, 1)], k=[(K, 1, 1)], alpha=0.5, beta=1)
+        ref = C + 0.5 * (A @ Bt.T)
+    elif case == "skinny_mfast":
+        # 128 x 32 tiles with both operands contiguous along the free index, ragged
+        M, N, K = 4099, 31, 45
+        At = rng.standard_normal((K, M)); B = rng.standard_normal((K, N)); C = rng.standard_normal((M, N))
+        A = At
+        out = gett(At, B, C, m=[(M, 1, N)], n=[(N, 1, 1)], k=[(K, M, N)], alpha=-1.0, beta=1)
+        ref = C - (At.T @ B)
     elif case in ("nt", "nt_tail"):
         # both operands contiguous along k and enough output tiles for 128 x 128 tiles
         # (ragged in m, n and k; accumulate)
