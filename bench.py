@@ -71,10 +71,12 @@ def blas_threads():
     return int(os.environ.get("OMP_NUM_THREADS", os.cpu_count() or 1))
 
 
-# kernel instance of each profile bucket (index 2 * role + 128x128-tile flag), FP64 names
-KERNELS = ["gett_f64_kernel<0, 2, 2>", "gett_f64_kernel<0, 4, 4>",
-           "gett_f64_kernel<1, 2, 2>", "gett_f64_kernel<1, 4, 4>",
-           "gett_f64_kernel<2, 2, 2> / coulomb_group_kernel<0>", "gett_f64_kernel<2, 4, 4>",
+# kernel instance of each profile bucket (index 2 * role + 128x128-tile flag), FP64 names;
+# the last template argument is the waves along m (2: 64 x 64 and 128 x 128 tiles, 4:
+# 128 x 32 tiles, which share the bucket of the 64 x 64 ones)
+KERNELS = ["gett_f64_kernel<0, 2, 2, 2|4>", "gett_f64_kernel<0, 4, 4, 2>",
+           "gett_f64_kernel<1, 2, 2, 2|4>", "gett_f64_kernel<1, 4, 4, 2>",
+           "gett_f64_kernel<2, 2, 2, 2|4> / coulomb_group_kernel<0>", "gett_f64_kernel<2, 4, 4, 2>",
            "gett_group_kernel<0>", "gett_group_big_kernel<0>"]
 ROLE_NOTES = ["table products, one launch each", "(PP|PP) ladder contractions",
               "Coulomb-block builds B.B", "grouped table products"]

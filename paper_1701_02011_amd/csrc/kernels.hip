@@ -1488,6 +1488,7 @@ void launch_antisym_add_list(const AntisymList& l, int nP, int nH, hipStream_t s
 // M[X][Y] of M[x][y] = jb[p - b0][x][q - qoff][y] and its mirror M[Y][X] are read with y
 // fastest into LDS, and V is written in packed order (y fastest inside each x).
 constexpr int kPackTile = 32;
+constexpr int kPackRun = 16;   // rows per run of the resident-block packs (one 128-byte line of q)
 
 // position of the particle pair (a, b) among the pairs a <= b in a-major order
 __device__ __forceinline__ long long pair_pos(int nP, int a, int b) {
@@ -1513,9 +1514,19 @@ __global__ __launch_bounds__(256) void ladder_pack_v_kernel(const double* __rest
   const int nT = (nP + kPackTile - 1) / kPackTile;
   const long long sq = nP, sx = (long long)nq * nP, sp = sx * nP;
   const long long npk = (long long)nP * (nP + 1) / 2;
-  for (long long w = blockIdx.x; w < (long long)rows * ntp; w += gridDim.x) {
-    const int row = (int)(w / ntp);
-    int t = (int)(w - (long long)row * ntp);
+  const long long work = (long long)rows * ntp;
+  for (long long w = blockIdx.x; w < work; w += gridDim.x) {
+    // work order: runs of kPackRun consecutive rows (one p, consecutive q in the row table)
+    // with the rows fastest for each tile pair, the runs of one XCD contiguous when one
+    // pass of the grid covers the work.  The reads with x < p and y < q (K[pair(x, p)]
+    // [pair(y, q)], one element per cache line for a single row) are contiguous along q, so
+    // the run's workgroups, resident on one XCD at the same time, share those lines in L2.
+    const long long L = gridDim.x == work ? xcd_tile((int)w, (int)work) : w;
+    const long long run = L / ((long long)kPackRun * ntp);
+    const long long rem = L - run * kPackRun * ntp;
+    const int rr = (int)min((long long)kPackRun, rows - run * kPackRun);
+    int t = (int)(rem / rr);
+    const int row = (int)(run * kPackRun + (rem - (long long)t * rr));
     // tile pair t -> (tx, ty), tx <= ty, tx-major
     int tx = 0;
     while (t >= nT - tx) {
