@@ -36,7 +36,7 @@ def _close(x, ref, rel=1e-10):
 # contraction kernel
 # ---------------------------------------------------------------------------
 GETT_CASES = ["gemm", "ragged", "strided", "multi", "vec", "accum", "splitk", "longk", "packk", "nt", "nt_tail",
-              "big_splitk", "big_mfast", "skinny", "skinny_mfast", "skinny_splitk"]
+              "big_splitk", "big_mfast", "skinny", "skinny_mfast", "skinny_splitk", "skinny_k8"]
 
 
 @pytest.mark.parametrize("precision", [0, 1, 2])
@@ -127,6 +127,13 @@ def test_gett_kernel(case, precision):
         B = Bt
         out = gett(A, Bt, C, m=[(M, K, N)], n=[(N, K, 1)], k=[(K, 1, 1)], alpha=0.5, beta=1)
         ref = C + 0.5 * (A @ Bt.T)
+    elif case == "skinny_k8":
+        # 128 x 32 tiles over a k range shorter than one step (8 values contiguous in A, the
+        # shape of the active-index transforms of the large tensors); accumulate
+        M, N, K = 3001, 8, 8
+        A = rng.standard_normal((M, K)); B = rng.standard_normal((K, N)); C = rng.standard_normal((M, N))
+        out = gett(A, B, C, m=[(M, K, N)], n=[(N, 1, 1)], k=[(K, 1, N)], alpha=0.5, beta=1)
+        ref = C + 0.5 * (A @ B)
     elif case == "skinny_mfast":
         # 128 x 32 tiles with both operands contiguous along the free index, ragged
         M, N, K = 4099, 31, 45
