@@ -1424,8 +1424,80 @@ __global__ __launch_bounds__(256) void pack_kernel(PackDesc d, const double* __r
   }
 }
 
+// Transposing packs: the source's unit-stride dimension u is not the target's last one w.
+// A workgroup copies a 32 x 32 tile of (u, w) for one index of the other dimensions through
+// LDS, reading along u and writing along w, so both sides move whole cache lines.
+struct PackTile {
+  int nr = 0;                            // other dimensions
+  int rd[2 * kMaxComp] = {};             // their extents (row-major)
+  long long rs[2 * kMaxComp] = {}, ro[2 * kMaxComp] = {};   // their source and target strides
+  int du = 1, dw = 1;
+  long long su = 1, ou = 0, sw = 0, ow = 1;
+  long long rest = 1;                    // product of rd
+};
+__global__ __launch_bounds__(256) void pack_tiled_kernel(PackTile t, const double* __restrict__ src,
+                                                         double* __restrict__ dst) {
+  __shared__ double T[32][33];
+  const int tu = (t.du + 31) / 32, tw = (t.dw + 31) / 32;
+  const long long work = t.rest * tu * tw;
+  for (long long w = blockIdx.x; w < work; w += gridDim.x) {
+    long long r = w / (tu * tw);
+    const int q = (int)(w - r * (tu * tw));
+    const int u0 = (q % tu) * 32, w0 = (q / tu) * 32;
+    long long sb = 0, ob = 0;
+    for (int c = t.nr - 1; c >= 0; --c) {
+      const long long x = r % t.rd[c];
+      r /= t.rd[c];
+      sb += x * t.rs[c];
+      ob += x * t.ro[c];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 1024; e += 256) {
+      const int b = e & 31, a = e >> 5;   // b along u (unit stride in the source)
+      const int uu = u0 + b, ww = w0 + a;
+      if (uu < t.du && ww < t.dw) T[a][b] = src[sb + uu * t.su + ww * t.sw];
+    }
+    __syncthreads();
+    for (int e = threadIdx.x; e < 1024; e += 256) {
+      const int a = e & 31, b = e >> 5;   // a along w (unit stride in the target)
+      const int uu = u0 + b, ww = w0 + a;
+      if (uu < t.du && ww < t.dw) dst[ob + uu * t.ou + ww * t.ow] = T[a][b];
+    }
+  }
+}
+
 void launch_pack(const PackDesc& d0, const double* src, double* dst, hipStream_t st) {
   if (d0.n <= 0) return;
+  // the target is contiguous in the order of the dimensions (the last fastest)
+  long long os[2 * kMaxComp];
+  {
+    long long m = 1;
+    for (int k = d0.rank - 1; k >= 0; --k) {
+      os[k] = m;
+      m *= d0.d[k];
+    }
+  }
+  const int w = d0.rank - 1;
+  int u = -1;
+  for (int k = 0; k < d0.rank; ++k)
+    if (d0.ss[k] == 1 && d0.d[k] > 1) u = k;
+  if (u >= 0 && u != w && d0.d[u] >= 8 && d0.d[w] >= 8) {
+    PackTile t;
+    for (int k = 0; k < d0.rank; ++k) {
+      if (k == u || k == w) continue;
+      t.rd[t.nr] = d0.d[k];
+      t.rs[t.nr] = d0.ss[k];
+      t.ro[t.nr] = os[k];
+      t.rest *= d0.d[k];
+      ++t.nr;
+    }
+    t.du = d0.d[u]; t.su = d0.ss[u]; t.ou = os[u];
+    t.dw = d0.d[w]; t.sw = d0.ss[w]; t.ow = os[w];
+    const long long work = t.rest * ((t.du + 31) / 32) * ((t.dw + 31) / 32);
+    const unsigned grid = (unsigned)std::min<long long>(work, 1LL << 20);
+    hipLaunchKernelGGL(pack_tiled_kernel, dim3(grid), dim3(256), 0, st, t, src, dst);
+    return;
+  }
   PackDesc d = d0;
   div_magic(d.d, d.rank, d.dm);
   const long long blocks = std::min<long long>((d.n + 255) / 256, 16384);
