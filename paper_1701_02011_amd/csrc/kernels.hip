@@ -1692,27 +1692,46 @@ __global__ __launch_bounds__(256) void pack_pairs_kernel(const double* __restric
 }
 
 // K[i][j] = K[j][i] for the elements whose row block i / blk lies below the column block
-// j / blk (those a triangular contraction with tri = blk leaves unwritten); 32 x 32 tiles
-// through LDS, tile (ti, tj) of the lower part taken from the transposed tile.
+// j / blk (those a triangular contraction with tri = blk leaves unwritten), through LDS.
+// Work item w is a run of G 32 x 32 tiles (ti, tj0 .. tj0 + G - 1) of the lower part, taken
+// from the transposed upper tiles; only lower tiles are enumerated: row ti of tiles holds
+// (ti / per) (per / G) items (per = blk / 32, a multiple of G), so the items before row ti
+// number cum(ti) = (per / G) (per Q (Q - 1) / 2 + S Q) with Q = ti / per, S = ti % per, and
+// the row of w is the last ti with cum(ti) <= w.
+template <int G>
 __global__ __launch_bounds__(256) void mirror_lower_kernel(double* __restrict__ K, long long n, int blk) {
-  __shared__ double T[32][33];
+  __shared__ double T[G][32][33];
   const long long nt = (n + 31) / 32;
-  const int per = blk / 32;   // 32-tiles per block
-  for (long long w = blockIdx.x; w < nt * nt; w += gridDim.x) {
-    const long long ti = w / nt, tj = w - (w / nt) * nt;
-    if (ti / per <= tj / per) continue;   // uniform over the workgroup
-    __syncthreads();
-    for (int e = threadIdx.x; e < 1024; e += 256) {
-      const int a = e / 32, b = e % 32;
-      const long long r = tj * 32 + a, c = ti * 32 + b;   // source: upper tile (tj, ti)
-      T[a][b] = (r < n && c < n) ? K[r * n + c] : 0.0;
+  const long long per = blk / 32, cpg = per / G;
+  auto cum = [&](long long t) -> long long {
+    const long long Q = t / per, S = t - Q * per;
+    return cpg * (per * Q * (Q - 1) / 2 + S * Q);
+  };
+  const long long total = cum(nt);
+  for (long long w = blockIdx.x; w < total; w += gridDim.x) {
+    long long lo = 0, hi = nt - 1;
+    while (lo < hi) {
+      const long long mid = (lo + hi + 1) / 2;
+      if (cum(mid) <= w) lo = mid;
+      else hi = mid - 1;
     }
+    const long long ti = lo, tj0 = (w - cum(ti)) * G;
     __syncthreads();
-    for (int e = threadIdx.x; e < 1024; e += 256) {
-      const int a = e / 32, b = e % 32;
-      const long long r = ti * 32 + a, c = tj * 32 + b;
-      if (r < n && c < n) K[r * n + c] = T[b][a];
-    }
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+      for (int e = threadIdx.x; e < 1024; e += 256) {
+        const int a = e / 32, b = e % 32;
+        const long long r = (tj0 + g) * 32 + a, c = ti * 32 + b;   // source: upper tile (tj, ti)
+        T[g][a][b] = (r < n && c < n) ? K[r * n + c] : 0.0;
+      }
+    __syncthreads();
+#pragma unroll
+    for (int g = 0; g < G; ++g)
+      for (int e = threadIdx.x; e < 1024; e += 256) {
+        const int a = e / 32, b = e % 32;
+        const long long r = ti * 32 + a, c = (tj0 + g) * 32 + b;
+        if (r < n && c < n) K[r * n + c] = T[g][b][a];
+      }
   }
 }
 
@@ -1727,8 +1746,16 @@ void launch_pack_pairs(const double* B, int N, int off, int nP, int M, double* B
 void launch_mirror_lower(double* K, long long n, int blk, hipStream_t st) {
   const long long nt = (n + 31) / 32;
   if (nt <= 1 || blk % 32 != 0) return;
-  const unsigned grid = (unsigned)std::min<long long>(nt * nt, 1LL << 20);
-  hipLaunchKernelGGL(mirror_lower_kernel, dim3(grid), dim3(256), 0, st, K, n, blk);
+  // items of four tiles when a block holds a multiple of four tiles (one per tile else)
+  const long long per = blk / 32, Q = nt / per, S = nt - Q * per;
+  const int G = per % 4 == 0 ? 4 : 1;
+  const long long items = per / G * (per * Q * (Q - 1) / 2 + S * Q);
+  if (items <= 0) return;
+  const unsigned grid = (unsigned)std::min<long long>(items, 1LL << 20);
+  if (G == 4)
+    hipLaunchKernelGGL(mirror_lower_kernel<4>, dim3(grid), dim3(256), 0, st, K, n, blk);
+  else
+    hipLaunchKernelGGL(mirror_lower_kernel<1>, dim3(grid), dim3(256), 0, st, K, n, blk);
 }
 
 __global__ __launch_bounds__(256) void ladder_pack_t_kernel(const double* __restrict__ T, int nP, int nH,
