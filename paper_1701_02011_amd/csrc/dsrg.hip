@@ -550,7 +550,7 @@ struct Exec {
     }
     const int ns = gett_splits(g, kSplitCap);
     r.splits = ns;
-    const long long wse = ns > 1 ? (long long)ns * g.M * g.N : 0;
+    const long long wse = ns > 1 ? (long long)ns * g.M * g.N : gett_tail_ws(g);
     double* ws = splitk_buffer(wse);
     const int lo = prec;
     op([g, A, Bp, C, role, ws, wse, lo](hipStream_t s) { launch_gett(g, A, Bp, C, s, role, ws, wse, lo); });

@@ -42,6 +42,11 @@ struct GettDesc {
   int tri = 0;
   long long kchunk = 1;  // k steps per split (split-K), set by the launcher
   double* part = nullptr;  // split-K partial tiles [split][M][N], set by the launcher
+  // tail launches of 128 x 128 tiles (set by the launcher, zero otherwise): the launch covers
+  // logical tiles [t0, t0 + nl) of a gx x gy tile grid, and its partial tiles are stored
+  // [split][pM][pN] over the box of rows pm0 .. pm0 + pM - 1, columns pn0 .. pn0 + pN - 1
+  int gx = 0, gy = 0, t0 = 0, nl = 0;
+  int pm0 = 0, pn0 = 0, pM = 0, pN = 0;
   // division by md[c] (nd[c]) as a multiply and shift: q = (idx * mmag[c]) >> msh[c] for
   // 0 <= idx < 2^31 (set by gett_magic)
   unsigned mmag[kMaxComp] = {}, nmag[kMaxComp] = {};
@@ -107,6 +112,10 @@ constexpr int kRoles = 4;
 void launch_gett(const GettDesc& g, const double* A, const double* B, double* C, hipStream_t st,
                  int role, double* ws, long long ws_elems, int prec = 0);
 int gett_splits(const GettDesc& g, long long ws_elems);
+// workspace (doubles) for the k-split tail of a 128 x 128 launch without split-K (0 when
+// the launch has none): launch_gett splits the k range of the tiles past the last whole
+// round of resident workgroups when ws holds this many doubles
+long long gett_tail_ws(const GettDesc& g);
 // ---- grouped execution: independent contractions of one dependency level per launch ----
 // Item i owns workgroup tiles [tile0, tile0 + tiles_m * tiles_n * splits) of a grouped launch,
 // each an output tile of shape kGroupTiles[shape] and one chunk of k steps (g.kchunk).

@@ -415,7 +415,8 @@ __device__ __forceinline__ void gett_tile(const GettDesc& g, const double* __res
         int m = tm0 + wm + a * 16 + MF::row(lk, r);
         if (m >= g.M) continue;
         if (g.part) {
-          double* prow = g.part + ((long long)kz * g.M + m) * g.N;
+          const long long pM = g.pM ? g.pM : g.M, pN = g.pM ? g.pN : g.N;
+          double* prow = g.part + ((long long)kz * pM + (m - g.pm0)) * pN - g.pn0;
 #pragma unroll
           for (int b = 0; b < WN; ++b) {
             int n = tn0 + wn + b * 16 + li;
@@ -564,9 +565,12 @@ __device__ __forceinline__ void gett_grid_tile(const GettDesc& g, const double* 
                                                TileLds<WM, WN, WGM, typename Mfma<kP>::T, kBK>& lds) {
   using Lds = TileLds<WM, WN, WGM, typename Mfma<kP>::T, kBK>;
   constexpr int BM = Lds::BM, BN = Lds::BN;
-  const int gx = gridDim.x, gy = gridDim.y;
-  const int total = gx * gy * gridDim.z;
-  const int b = blockIdx.x + gx * (blockIdx.y + gy * blockIdx.z);
+  // a tail launch covers logical tiles [t0, t0 + nl) of the gx x gy grid in g
+  const bool sub = g.gx > 0;
+  const int gx = sub ? g.gx : gridDim.x, gy = sub ? g.gy : gridDim.y;
+  const int nl = sub ? g.nl : gx * gy;
+  const int total = gridDim.x * gridDim.y * gridDim.z;
+  const int b = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
   // with the triangle skip the live tiles crowd into the last columns: runs of 8 tiles
   // spread over the XCDs keep their loads even
   const int L = g.tri > 0 ? xcd_tile_windowed(b, total) : xcd_tile(b, total);
@@ -577,8 +581,8 @@ __device__ __forceinline__ void gett_grid_tile(const GettDesc& g, const double* 
     tn = rest % gy;
     kz = rest / gy;
   } else {
-    kz = L / (gx * gy);
-    grouped_tile(L - kz * gx * gy, gx, gy, tm, tn);
+    kz = L / nl;
+    grouped_tile(g.t0 + L - kz * nl, gx, gy, tm, tn);
   }
   if (g.tri > 0 && (tn * BN + BN - 1) / g.tri < (tm * BM) / g.tri) return;
   gett_tile<WM, WN, WGM, kP, (WM * WN < 16), kBK>(g, A, B, C, tm * BM, tn * BN, kz, lds);
@@ -628,6 +632,27 @@ __global__ __launch_bounds__(256) void splitk_reduce_kernel(GettDesc g, const do
     double s = 0.0;
     for (int z = 0; z < nsplit; ++z) s += part[(long long)z * total + i];
     long long o = decode_fast(m, g.nm, g.md, g.mmag, g.msh, g.cm) + decode_fast(n, g.nn, g.nd, g.nmag, g.nsh, g.cn);
+    double v = g.alpha * s;
+    if (g.beta) v += C[o];
+    C[o] = v;
+  }
+}
+
+// The k-split tail of a 128 x 128 launch: C[m][n] = alpha * sum_z part[z][m - pm0][n - pn0]
+// (+ C) in a fixed order of z, for the elements of the box whose tile is one of the tail's
+// (logical index >= t0: the inverse of grouped_tile); the others were written by the main
+// launch.
+__global__ __launch_bounds__(256) void splitk_tail_reduce_kernel(GettDesc g, const double* __restrict__ part,
+                                                                 int nsplit, double* __restrict__ C) {
+  const long long box = (long long)g.pM * g.pN;
+  for (long long i = blockIdx.x * 256LL + threadIdx.x; i < box; i += 256LL * gridDim.x) {
+    const int m = g.pm0 + (int)(i / g.pN), n = g.pn0 + (int)(i % g.pN);
+    const int tm = m / 128, tn = n / 128;
+    const int first = tm / kGroupM * kGroupM, gsz = min(g.gx - first, kGroupM);
+    if (first * g.gy + tn * gsz + (tm - first) < g.t0) continue;
+    double s = 0.0;
+    for (int z = 0; z < nsplit; ++z) s += part[(long long)z * box + i];
+    const long long o = decode_fast(m, g.nm, g.md, g.mmag, g.msh, g.cm) + decode_fast(n, g.nn, g.nd, g.nmag, g.nsh, g.cn);
     double v = g.alpha * s;
     if (g.beta) v += C[o];
     C[o] = v;
@@ -789,6 +814,42 @@ bool gett_big_tiles(const GettDesc& g) { return big_tiles(g); }
 // many rows: a 64 x 64 tile there computes more than half of its MFMA work on zero columns.
 static bool skinny_tiles(const GettDesc& g) { return !big_tiles(g) && g.tri <= 0 && g.N <= 32 && g.M >= 2048; }
 
+// k-split tail of a 128 x 128 launch with more tiles than the 512 resident workgroup slots
+// (two per CU) whose last round is at most half full: the last rem logical tiles would run
+// alone for a whole tile time, so their k range is split smax ways instead (rem x smax about
+// one round; the launcher lowers the split to keep 16 k steps per chunk).  Only tails inside
+// the last group of kGroupM m tiles (grouped_tile), whose partial tiles are kept over the
+// box of rows from that group's first and columns from the tail's first, at most
+// kTailCap doubles.
+constexpr long long kTailCap = 1LL << 24;
+struct TailPlan {
+  int gx = 0, gy = 0, t0 = 0, rem = 0, smax = 0;
+  int pm0 = 0, pn0 = 0, pM = 0, pN = 0;
+};
+static TailPlan tail_plan(const GettDesc& g) {
+  TailPlan t;
+  if (!big_tiles(g) || g.tri > 0) return t;
+  const int gx = (g.M + 127) / 128, gy = (g.N + 127) / 128;
+  const long long tiles = (long long)gx * gy, slots = 512;
+  const int rem = (int)(tiles % slots);
+  if (tiles <= slots || rem == 0 || rem > slots / 2 || tiles >= (1LL << 31)) return t;
+  const int first = (gx - 1) / kGroupM * kGroupM, gsz = gx - first;
+  if ((long long)rem > (long long)gsz * gy) return t;
+  const int tn_lo = (gsz * gy - rem) / gsz;
+  const int pm0 = first * 128, pn0 = tn_lo * 128, pM = g.M - pm0, pN = g.N - pn0;
+  long long s = std::min<long long>(32, slots / rem);
+  while (s >= 2 && s * pM * pN > kTailCap) --s;
+  if (s < 2) return t;
+  t.gx = gx; t.gy = gy; t.t0 = (int)(tiles - rem); t.rem = rem; t.smax = (int)s;
+  t.pm0 = pm0; t.pn0 = pn0; t.pM = pM; t.pN = pN;
+  return t;
+}
+
+long long gett_tail_ws(const GettDesc& g) {
+  const TailPlan t = tail_plan(g);
+  return t.rem ? (long long)t.smax * t.pM * t.pN : 0;
+}
+
 // Split-K factor: the number of k chunks that fills the resident workgroup slots in the
 // most nearly whole rounds (256 CUs; two 128 x 128 or four 64 x 64 workgroups per CU fit
 // the registers), keeping at least 16 k steps per chunk (4 when the output has at most
@@ -890,6 +951,37 @@ void launch_gett(const GettDesc& g0, const double* A, const double* B, double* C
   int ns = ws ? gett_splits(g, ws_elems) : 1;
   g.part = nullptr;
   g.kchunk = g.steps;
+  if (ns == 1 && ws && big) {
+    const TailPlan t = tail_plan(g);
+    long long s = std::min<long long>(t.smax, g.steps / 16);
+    if (t.rem > 0 && s >= 2 && s * t.pM * t.pN <= ws_elems) {
+      // the whole rounds in one launch, the tail's k chunks in another, then the tail's
+      // fixed-order reduction
+      GettDesc gm = g;
+      gm.gx = t.gx; gm.gy = t.gy; gm.t0 = 0; gm.nl = t.t0;
+      GettDesc gt = g;
+      gt.gx = t.gx; gt.gy = t.gy; gt.t0 = t.t0; gt.nl = t.rem;
+      const long long chunk = (g.steps + s - 1) / s;
+      const int nz = (int)((g.steps + chunk - 1) / chunk);
+      gt.kchunk = chunk;
+      gt.part = ws;
+      gt.pm0 = t.pm0; gt.pn0 = t.pn0; gt.pM = t.pM; gt.pN = t.pN;
+      auto go = [&](const GettDesc& d, dim3 grid) {
+        if (role == kRoleLadder)
+          launch_role<kRoleLadder>(d, shape, prec, grid, A, B, C, st);
+        else if (role == kRoleIntegrals)
+          launch_role<kRoleIntegrals>(d, shape, prec, grid, A, B, C, st);
+        else
+          launch_role<kRoleGeneric>(d, shape, prec, grid, A, B, C, st);
+      };
+      go(gm, dim3((unsigned)t.t0, 1, 1));
+      go(gt, dim3((unsigned)t.rem, 1, (unsigned)nz));
+      const long long box = (long long)t.pM * t.pN;
+      const long long blocks = std::min<long long>((box + 255) / 256, 4096);
+      hipLaunchKernelGGL(splitk_tail_reduce_kernel, dim3((unsigned)blocks), dim3(256), 0, st, gt, ws, nz, C);
+      return;
+    }
+  }
   if (ns > 1) {
     long long chunk = (g.steps + ns - 1) / ns;
     ns = (int)((g.steps + chunk - 1) / chunk);

@@ -36,7 +36,7 @@ def _close(x, ref, rel=1e-10):
 # contraction kernel
 # ---------------------------------------------------------------------------
 GETT_CASES = ["gemm", "ragged", "strided", "multi", "vec", "accum", "splitk", "longk", "packk", "nt", "nt_tail",
-              "big_splitk", "big_mfast", "skinny", "skinny_mfast", "skinny_splitk", "skinny_k8"]
+              "big_splitk", "big_mfast", "skinny", "skinny_mfast", "skinny_splitk", "skinny_k8", "big_tail"]
 
 
 @pytest.mark.parametrize("precision", [0, 1, 2])
@@ -111,6 +111,15 @@ def test_gett_kernel(case, precision):
         B = Bt
         out = gett(A, Bt, C, m=[(M, K, N)], n=[(N, K, 1)], k=[(K, 1, 1)], alpha=0.25, beta=1)
         ref = C + 0.25 * (A @ Bt.T)
+    elif case == "big_tail":
+        # 552 tiles of 128 x 128, 40 past the last whole round of 512 resident workgroups:
+        # the tail's k range is split (its partial tiles over a box ragged in m and n) and
+        # reduced after the main launch; accumulate
+        M, N, K = 2900, 2950, 16 * 70 + 9
+        A = rng.standard_normal((M, K)); Bt = rng.standard_normal((N, K)); C = rng.standard_normal((M, N))
+        B = Bt
+        out = gett(A, Bt, C, m=[(M, K, N)], n=[(N, K, 1)], k=[(K, 1, 1)], alpha=0.75, beta=1)
+        ref = C + 0.75 * (A @ Bt.T)
     elif case == "big_mfast":
         # 128 x 128 tiles with both operands contiguous along the free index (the layout of
         # the Coulomb builds: m and n fastest), ragged in m, n and k; accumulate
