@@ -78,7 +78,10 @@ KERNELS = ["gett_f64_kernel<0, 2, 2, 2|4>", "gett_f64_kernel<0, 4, 4, 2>",
            "gett_f64_kernel<1, 2, 2, 2|4>", "gett_f64_kernel<1, 4, 4, 2>",
            "gett_f64_kernel<2, 2, 2, 2|4> / coulomb_group_kernel<0>", "gett_f64_kernel<2, 4, 4, 2>",
            "gett_group_kernel<0>", "gett_group_big_kernel<0>"]
-ROLE_NOTES = ["table products, one launch each", "(PP|PP) ladder contractions",
+# a "launch" below is one contraction call of the library, timed by HIP events around all
+# of its dispatches: a 128 x 128 launch whose last round is mostly empty is the whole rounds
+# plus a k-split tail (two dispatches of the kernel and a reduction)
+ROLE_NOTES = ["table products, one contraction call each", "(PP|PP) ladder contractions",
               "Coulomb-block builds B.B", "grouped table products"]
 
 
