@@ -523,6 +523,8 @@ struct Exec {
     // main stream waits for an open side branch
     if (side_pending && !op.side) join_side();
     GettDesc g = g0;
+    // with FP32 or BF16 x3 products, 128 x 128 tiles only from 8 k steps
+    g.big_min_steps = prec != 0 ? 8 : 0;
     // A short inner k component wastes most of each zero-padded k step: packing both
     // operands makes the whole k range one contiguous component (steps of kGettBK).
     const bool padk = g.nk > 1 && gett_k_fill(g) * 9 < 8 && g.M >= kPackMin && g.N >= kPackMin &&

@@ -47,6 +47,9 @@ struct GettDesc {
   // [split][pM][pN] over the box of rows pm0 .. pm0 + pM - 1, columns pn0 .. pn0 + pN - 1
   int gx = 0, gy = 0, t0 = 0, nl = 0;
   int pm0 = 0, pn0 = 0, pM = 0, pN = 0;
+  // fewest k steps for 128 x 128 tiles (set by the caller; FP32 and BF16 x3 products walk
+  // 32 k values per step there, so short k ranges run faster on 64 x 64 tiles)
+  long long big_min_steps = 0;
   // division by md[c] (nd[c]) as a multiply and shift: q = (idx * mmag[c]) >> msh[c] for
   // 0 <= idx < 2^31 (set by gett_magic)
   unsigned mmag[kMaxComp] = {}, nmag[kMaxComp] = {};

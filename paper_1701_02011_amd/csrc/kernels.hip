@@ -805,7 +805,7 @@ int big_tile_min() { return t_big_tile_min; }
 
 static bool big_tiles(const GettDesc& g) {
   long long t128 = (long long)((g.M + 127) / 128) * ((g.N + 127) / 128);
-  return g.M >= 128 && g.N >= 128 && t128 >= t_big_tile_min;
+  return g.M >= 128 && g.N >= 128 && t128 >= t_big_tile_min && g.steps >= g.big_min_steps;
 }
 
 bool gett_big_tiles(const GettDesc& g) { return big_tiles(g); }
