@@ -812,7 +812,11 @@ bool gett_big_tiles(const GettDesc& g) { return big_tiles(g); }
 
 // 128 x 32 tiles (four waves along m) for plain launches with at most 32 output columns and
 // many rows: a 64 x 64 tile there computes more than half of its MFMA work on zero columns.
-static bool skinny_tiles(const GettDesc& g) { return !big_tiles(g) && g.tri <= 0 && g.N <= 32 && g.M >= 2048; }
+// Also for long k ranges over at least 256 rows (reductions such as 308 x 28 x 2.7e6):
+// fewer m tiles each stream the whole B operand.
+static bool skinny_tiles(const GettDesc& g) {
+  return !big_tiles(g) && g.tri <= 0 && g.N <= 32 && (g.M >= 2048 || (g.M >= 256 && g.steps >= 4096));
+}
 
 // k-split tail of a 128 x 128 launch with more tiles than the 512 resident workgroup slots
 // (two per CU) whose last round is at most half full: the last rem logical tiles would run

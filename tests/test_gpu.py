@@ -36,7 +36,7 @@ def _close(x, ref, rel=1e-10):
 # contraction kernel
 # ---------------------------------------------------------------------------
 GETT_CASES = ["gemm", "ragged", "strided", "multi", "vec", "accum", "splitk", "longk", "packk", "nt", "nt_tail",
-              "big_splitk", "big_mfast", "skinny", "skinny_mfast", "skinny_splitk", "skinny_k8", "big_tail"]
+              "big_splitk", "big_mfast", "skinny", "skinny_mfast", "skinny_splitk", "skinny_k8", "skinny_longk", "big_tail"]
 
 
 @pytest.mark.parametrize("precision", [0, 1, 2])
@@ -132,6 +132,14 @@ def test_gett_kernel(case, precision):
         # at most 32 output columns and many rows: 128 x 32 tiles, ragged in m, n and k,
         # both operands contiguous along k; the long k range of the second case is split
         M, N, K = (2100, 28, 309) if case == "skinny" else (2050, 17, 16 * 300 + 7)
+        A = rng.standard_normal((M, K)); Bt = rng.standard_normal((N, K)); C = rng.standard_normal((M, N))
+        B = Bt
+        out = gett(A, Bt, C, m=[(M, K, N)], n=[(N, K, 1)], k=[(K, 1, 1)], alpha=0.5, beta=1)
+        ref = C + 0.5 * (A @ Bt.T)
+    elif case == "skinny_longk":
+        # few rows, at most 32 columns and a k range of over 4096 steps: 128 x 32 tiles with
+        # the k range split; ragged in m, n and k; accumulate
+        M, N, K = 300, 20, 65536 + 37
         A = rng.standard_normal((M, K)); Bt = rng.standard_normal((N, K)); C = rng.standard_normal((M, N))
         B = Bt
         out = gett(A, Bt, C, m=[(M, K, N)], n=[(N, K, 1)], k=[(K, 1, 1)], alpha=0.5, beta=1)
